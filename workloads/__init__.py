@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs shared by the oracle side and the GPU side.
+
+This module only draws and samples inputs (grids, material maps, force
+patterns, envelopes, probe lists).  It holds none of the solver's arithmetic:
+no operator, no projection, no time step, no stability bound.  Where a
+workload states its time step as a fraction of the stability limit, it
+carries the fraction (``dt_factor``) and each side computes the limit itself.
+
+Coordinates: node (i, j, k) sits at x = (i - nx//2) hx, y = (j - ny//2) hy,
+z = (k - nz//2) hz, so the centre node of an even grid lies exactly at 0.
+Arrays are [nz][ny][nx] (x fastest); vector fields [3][nz][ny][nx].
+Seeds: numpy default_rng(1000 + workload index).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    name: str
+    grid: tuple                       # (nx, ny, nz, hx, hy, hz)
+    G: object                         # float or [nz][ny][nx] array, Pa
+    rho: object                       # kg/m^3
+    eta: object                       # Pa s
+    F: Optional[np.ndarray]           # [3][nz][ny][nx] body force pattern b0, N/m^3
+    env: np.ndarray                   # g[n], n < len(env); 0 afterwards
+    nsteps: int
+    probes: np.ndarray                # [n][3] (i, j, k)
+    comp: int = 2                     # recorded component (0..2) or 3 = all
+    dt: Optional[float] = None        # explicit time step, s
+    dt_factor: Optional[float] = None  # else dt = dt_factor * stable limit
+    push_time: float = 0.0            # s; envelope length derived from dt
+    sponge_cells: int = 8
+    tol: float = 1e-8
+    precision: str = "fp32"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.grid[:3]
+        return (nz, ny, nx)
+
+    @property
+    def ncells(self):
+        nx, ny, nz = self.grid[:3]
+        return nx * ny * nz
+
+    @property
+    def interior_cells(self):
+        nx, ny, nz = self.grid[:3]
+        return (nx - 2) * (ny - 2) * (nz - 2)
+
+    def envelope_for(self, dt):
+        """Step envelope: g = 1 for n < round(push_time / dt), counted in
+        whole steps."""
+        n_push = int(round(self.push_time / dt))
+        return np.ones(n_push)
+
+
+def coords(n, h):
+    return (np.arange(n) - n // 2) * h
+
+
+def gaussian_push(grid, sigma_l, sigma_a, F0, centre=(0.0, 0.0, 0.0), axis=2):
+    """F along `axis` = F0 exp(-(lateral^2)/(2 sigma_l^2) - (axial - c)^2/(2 sigma_a^2)).
+    Returns the [3][nz][ny][nx] force with only component `axis` non-zero."""
+    nx, ny, nz, hx, hy, hz = grid
+    x = coords(nx, hx) - centre[0]
+    y = coords(ny, hy) - centre[1]
+    z = coords(nz, hz) - centre[2]
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    pos = [X, Y, Z]
+    axial = pos[axis]
+    lat2 = sum(pos[a] ** 2 for a in range(3) if a != axis)
+    F = np.zeros((3, nz, ny, nx))
+    F[axis] = F0 * np.exp(-lat2 / (2.0 * sigma_l ** 2) - axial ** 2 / (2.0 * sigma_a ** 2))
+    return F
+
+
+def x_line_probes(grid, j=None, k=None):
+    nx, ny, nz = grid[:3]
+    j = ny // 2 if j is None else j
+    k = nz // 2 if k is None else k
+    return np.array([[i, j, k] for i in range(nx)], dtype=np.int64)
+
+
+def cfg1_homogeneous_fp64():
+    """48^3, dx = 0.5 mm, G = 3 kPa, rho = 1000, eta = 0, 8-cell sponge,
+    Gaussian F_z (1 mm lateral, 4 mm axial, F0 = 1e4) at the centre node,
+    100 us push, dt = 5e-5 s, 200 steps, u_z on the lateral x line, FP64,
+    projection tolerance 1e-10."""
+    h = 0.5e-3
+    grid = (48, 48, 48, h, h, h)
+    F = gaussian_push(grid, 1e-3, 4e-3, 1e4)
+    w = Workload(name="homogeneous 48^3 fp64", grid=grid, G=3e3, rho=1000.0, eta=0.0, F=F,
+                 env=None, nsteps=200, probes=x_line_probes(grid), comp=2, dt=5e-5,
+                 push_time=100e-6, sponge_cells=8, tol=1e-10, precision="fp64")
+    w.env = w.envelope_for(w.dt)
+    return w
+
+
+def spherical_inclusions(grid, rng, n_incl, background, radius_range, G_range, rho_range, eta_range,
+                         margin_cells):
+    """Background (G, rho, eta) with n_incl spheres; centres uniform over the
+    index box [margin, n-1-margin] on each axis, radius uniform in
+    radius_range; each property uniform in its range; a cell belongs to a
+    sphere when |x - c| <= r; later spheres overwrite earlier ones."""
+    nx, ny, nz, hx, hy, hz = grid
+    G = np.full((nz, ny, nx), float(background[0]))
+    rho = np.full((nz, ny, nx), float(background[1]))
+    eta = np.full((nz, ny, nx), float(background[2]))
+    x, y, z = coords(nx, hx), coords(ny, hy), coords(nz, hz)
+    spheres = []
+    for _ in range(n_incl):
+        ci = rng.uniform(margin_cells, nx - 1 - margin_cells)
+        cj = rng.uniform(margin_cells, ny - 1 - margin_cells)
+        ck = rng.uniform(margin_cells, nz - 1 - margin_cells)
+        c = ((ci - nx // 2) * hx, (cj - ny // 2) * hy, (ck - nz // 2) * hz)
+        r = rng.uniform(*radius_range)
+        g_, r_, e_ = rng.uniform(*G_range), rng.uniform(*rho_range), rng.uniform(*eta_range)
+        spheres.append((c, r, g_, r_, e_))
+    for (c, r, g_, r_, e_) in spheres:
+        dz2 = (z - c[2])[:, None, None] ** 2
+        dy2 = (y - c[1])[None, :, None] ** 2
+        dx2 = (x - c[0])[None, None, :] ** 2
+        m = (dz2 + dy2 + dx2) <= r * r
+        G[m], rho[m], eta[m] = g_, r_, e_
+    return G, rho, eta, spheres
+
+
+def cfg2_inclusions_fp32(n=256):
+    """256^3, dx = 0.25 mm, background (2 kPa, 1000, 0.5 Pa s), 12 seeded
+    spherical inclusions (radius 1.5-5 mm, G 1-10 kPa, rho 1000-1100,
+    eta 0-1.5), Gaussian F_z with the same physical widths as the 48^3 case,
+    100 us push, dt = 0.4 x stable limit, 4000 steps, FP32 state with FP64
+    projection to 1e-8.  `n` shrinks the grid for tests (same physics)."""
+    rng = np.random.default_rng(1002)
+    h = 0.25e-3
+    grid = (n, n, n, h, h, h)
+    G, rho, eta, spheres = spherical_inclusions(grid, rng, 12, (2e3, 1000.0, 0.5), (1.5e-3, 5e-3),
+                                                (1e3, 1e4), (1000.0, 1100.0), (0.0, 1.5), 8)
+    F = gaussian_push(grid, 1e-3, 4e-3, 1e4)
+    return Workload(name=f"inclusions {n}^3 fp32", grid=grid, G=G, rho=rho, eta=eta, F=F, env=None,
+                    nsteps=4000, probes=x_line_probes(grid), comp=2, dt_factor=0.4, push_time=100e-6,
+                    sponge_cells=8, tol=1e-8, precision="fp32", meta={"spheres": spheres})
+
+
+def cfg3_batch_draws(n_inst=64, edges=(96, 128, 160, 192)):
+    """64 homogeneous instances: edge from `edges`, G from 10 log-spaced
+    values in [1, 10] kPa, eta from 16 values 0, 0.1, ..., 1.5 Pa s,
+    rho = 1000, dx = 0.25 mm; returns a list of (edge, G, rho, eta)."""
+    rng = np.random.default_rng(1003)
+    Gs = 10.0 ** (3.0 + np.arange(10) / 9.0)
+    etas = 0.1 * np.arange(16)
+    out = []
+    for _ in range(n_inst):
+        e = int(rng.choice(edges))
+        out.append((e, float(rng.choice(Gs)), 1000.0, float(rng.choice(etas))))
+    return out
+
+
+def random_force(grid, rng, scale=1.0):
+    """Smooth-ish random 3-component force for operator tests."""
+    nx, ny, nz = grid[:3]
+    return scale * rng.standard_normal((3, nz, ny, nx))
