@@ -1,0 +1,180 @@
+"""Benchmark of the shear solver's hot path on one MI355X.
+
+One benchmark step is one whole simulation of the 256^3 heterogeneous
+inclusion workload (FP32 stencil state, FP64 projection): return the medium
+to rest, take the force pattern from device memory, project it (divergence,
+Jacobi-PCG to 1e-8, gradient subtraction), advance 4000 FDTD steps with the
+push envelope and the lateral-line probe traces, and read the traces back.
+The material, force pattern and probes are resident in HBM before timing.
+
+value = interior cell-updates of the timed steps / timed wall time
+        (whole job, projection included), in Gcell-updates/s.
+roofline: the FDTD step kernel, algorithmic bytes per interior cell-update
+          (48 B of FP32 u, w read + written, 12 B of G, eta, dt^2/rho, and
+          12 B of f_S on push steps) over its HIP-event-timed launches.
+cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "FDTD Gcell-updates/s (% HBM roofline); projection time, learned-FPCG vs PCG @1e-8"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=256, help="cubic grid edge of the inclusion workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, dt, smax, FS_host, nsteps):
+    """The FP64 oracle, as it stands, on `nsteps` FDTD steps of the workload
+    (from rest, push on), timed on the host cores."""
+    import numpy as np
+
+    import oracle
+    env = w.envelope_for(dt)
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.run(w.grid, w.G, w.rho, w.eta, dt, nsteps, FS=FS_host, env=env, probes=w.probes, comp=2,
+               sponge_cells=w.sponge_cells, sigma_max=smax)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": w.interior_cells * nsteps / el / 1e9, "unit": "Gcell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{nsteps} FDTD steps of the same {w.grid[0]}^3 workload from rest with the push on "
+                      f"(FP64 C oracle, OpenMP), {el:.1f} s; projection not included"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the solver has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2607_28414_amd import kvs
+    from workloads import cfg2_inclusions_fp32
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = args.grid
+    log(f"bench: building inclusion workload {n}^3")
+    w = cfg2_inclusions_fp32(n=n)
+    ctx = kvs.kvs_create(w.grid, precision=kvs.KVS_FP32, sponge_cells=w.sponge_cells, sponge_sigma_max=-1.0,
+                         stream=stream.cuda_stream)
+    try:
+        kvs.kvs_set_material(ctx, w.G, w.rho, w.eta)
+        dt = w.dt_factor * kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        env = w.envelope_for(dt)
+        kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_set_probes(ctx, w.probes, w.comp)
+        F_dev = torch.from_numpy(np.ascontiguousarray(w.F)).to("cuda")
+        torch.cuda.synchronize()
+        nsteps = w.nsteps
+        cells = w.interior_cells
+        n_push = min(len(env), nsteps)
+
+        def one_step():
+            kvs.kvs_reset_state(ctx)
+            kvs.kvs_set_force_device(ctx, F_dev.data_ptr(), 0)
+            rep = kvs.kvs_project(ctx, tol=w.tol, max_iter=20000, precond=kvs.KVS_PC_JACOBI)
+            kvs.kvs_step(ctx, nsteps)
+            tr = kvs.kvs_read_traces(ctx, len(w.probes), 1)
+            return rep, tr
+
+        for q in range(args.warmup):
+            log(f"bench: warmup step {q}")
+            rep, _ = one_step()
+        torch.cuda.synchronize()
+        kvs.kvs_enable_kernel_timing(ctx, True)
+        log(f"bench: timing {args.steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        proj_ms = []
+        for q in range(args.steps):
+            rep, tr = one_step()
+            proj_ms.append(rep["ms"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        k_ms, k_launches = kvs.kvs_kernel_time(ctx)
+        kvs.kvs_enable_kernel_timing(ctx, False)
+        assert np.all(np.isfinite(tr)), "non-finite traces"
+        FS_host = kvs.kvs_get_projected_force(ctx, w.shape) if not args.no_cpu_baseline else None
+        smax = kvs.kvs_sponge_sigma_max(ctx)
+    finally:
+        kvs.kvs_destroy(ctx)
+
+    total_updates = args.steps * nsteps * cells
+    value = total_updates / el / 1e9
+    # algorithmic bytes of the step kernel over the timed launches
+    bytes_total = args.steps * (nsteps * cells * 60 + n_push * cells * 12)
+    achieved = bytes_total / (k_ms * 1e-3) / 1e9
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"heterogeneous inclusions {n}^3, dx 0.25 mm, 12 spheres, Gaussian push 100 us, "
+                        f"dt 0.4 x stable limit, {nsteps} FDTD steps, FP32 state + FP64 Jacobi-PCG projection to 1e-8",
+            "grid": [n, n, n],
+            "fdtd_steps": nsteps,
+            "interior_cells": cells,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "step_kernel (FDTD step)",
+            "algorithmic_bytes_per_cell_update": "60 (+12 on push steps)",
+            "kernel_ms_avg": k_ms / max(k_launches, 1),
+            "launches": k_launches,
+        },
+        "fdtd_kernel_gcells": args.steps * nsteps * cells / (k_ms * 1e-3) / 1e9,
+        "projection": {"precond": "jacobi", "tol": w.tol, "iters": rep["iters"],
+                       "relres_true": rep["relres_true"], "ms": float(np.mean(proj_ms))},
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle sample ({args.cpu_sample_steps} steps)")
+        res["cpu_baseline"] = cpu_baseline(w, dt, smax, FS_host, args.cpu_sample_steps)
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

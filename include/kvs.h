@@ -1,0 +1,207 @@
+/*
+ * kvs.h -- C ABI of the MI355X (gfx950) reduced Kelvin-Voigt shear-wave
+ * solver.
+ *
+ * The library advances the reduced Kelvin-Voigt shear equation
+ *     rho u_tt = div(G grad u) + eta lap(u_t) + f_S                    (1)
+ * (the paper's reduced shear equation, Sec. 2.4, with spatially varying
+ * G = mu, rho and eta) by the explicit leapfrog of Sec. 3.1, and makes the
+ * body force solenoidal by the Helmholtz projection of Sec. 3.2:
+ *     lap phi = div f,   f_S = f - grad phi,                           (2)
+ * solved matrix-free by conjugate gradient (Sec. 3.2.3).  For a separable
+ * force f = b0(x) g(t) the projection is computed once and scaled per step
+ * (Sec. 3.3, eq. projected_separable).
+ *
+ * Discretisation (shared by every entry point):
+ *   - Grid of nx*ny*nz cell-centred nodes with spacings hx, hy, hz [m].
+ *     Scalar fields are laid out [nz][ny][nx] (x fastest, flat index
+ *     i + nx*(j + ny*k)); vector fields are [3][nz][ny][nx] (x, y, z
+ *     components, each a contiguous scalar field).
+ *   - The outer layer of nodes (i in {0, nx-1}, same for j, k) is the
+ *     Dirichlet layer of Sec. 3.5: u = 0 there at all times.
+ *   - 7-point Laplacian; div(G grad u) with the harmonic mean of G on each
+ *     face; viscous term eta * lap(w)/dt with w = u^n - u^{n-1} (backward
+ *     difference velocity of Sec. 3.1).
+ *   - State is kept in summed form (u^n, w^n = u^n - u^{n-1}):
+ *       w^{n+1} = [(1 - s) w^n + (dt^2/rho)(E(u^n) + eta lap(w^n)/dt
+ *                   + g_n f_S)] / (1 + s),   u^{n+1} = u^n + w^{n+1},
+ *     which is the leapfrog u^{n+1} = 2u^n - u^{n-1} + dt^2 a^n plus a
+ *     centred velocity damping s = sigma dt / 2 (sponge, see kvs_opts).
+ *   - Projection: b = centred divergence of F on interior nodes; CG on
+ *     A phi = -b with A = -lap_h (the paper's A, with the sign that makes
+ *     lap phi = div f hold); f_S,a = (F_a(-a) + 2 F_a + F_a(+a))/4
+ *     - (phi(+a) - phi(-a))/(2 h_a) on interior nodes, 0 on the outer layer
+ *     (the cell average of the face field avg(F) - D+ phi, whose face
+ *     divergence is the CG residual).
+ *
+ * Precision: KVS_FP64 keeps everything in double.  KVS_FP32 keeps the
+ * stencil state (u, w), material and f_S in float, and the projection (F,
+ * b, phi, CG vectors, inner products, residual norms, the phi-gradient
+ * subtraction) in double.
+ *
+ * Conventions for every function:
+ *   - Returns kvs_status; KVS_OK == 0.  No C++ exception crosses the ABI.
+ *     On error the context (when there is one) keeps a message readable by
+ *     kvs_last_error().
+ *   - Host pointers are borrowed for the duration of the call only; the
+ *     library copies what it needs and never frees them.
+ *   - "*_device" pointers are device memory owned by the caller, read
+ *     asynchronously on the context's stream; the caller keeps them alive
+ *     until kvs_synchronize() returns.
+ *   - The context owns every device buffer it allocates (hipMalloc) and
+ *     releases them in kvs_destroy().
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *     All GPU work of a context is ordered on its stream.
+ */
+#ifndef KVS_H
+#define KVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kvs_ctx kvs_ctx;
+
+typedef enum {
+    KVS_OK = 0,
+    KVS_EINVAL = 1,      /* bad argument: sizes, non-finite / non-positive G or rho, eta < 0, probe outside grid */
+    KVS_ENOMEM = 2,      /* device or host allocation failed */
+    KVS_EDEVICE = 3,     /* HIP runtime error, or no GPU / wrong architecture */
+    KVS_ENOTCONV = 4,    /* CG reached max_iter above tolerance (phi and f_S are still produced) */
+    KVS_EBREAKDOWN = 5,  /* CG guard fired: p.Ap <= 0 or a non-finite inner product (Sec. 3.2.3) */
+    KVS_EUNSTABLE = 6,   /* dt above the stability limit */
+    KVS_ESTATE = 7       /* call order: material, dt, or a current projection missing */
+} kvs_status;
+
+typedef enum { KVS_FP64 = 0, KVS_FP32 = 1 } kvs_precision;
+typedef enum { KVS_PC_NONE = 0, KVS_PC_JACOBI = 1, KVS_PC_UNET = 2 } kvs_precond;
+
+typedef struct {
+    int64_t nx, ny, nz; /* nodes per axis, each >= 3 */
+    double hx, hy, hz;  /* spacings [m], > 0 */
+} kvs_grid;
+
+typedef struct {
+    int32_t precision;       /* kvs_precision */
+    int32_t sponge_cells;    /* L >= 0: linear damping ramp over L cells from every face (0 = none) */
+    double sponge_sigma_max; /* ramp peak [1/s]; < 0 selects 6 ln(10) c_max / (L h_min), which makes
+                                the one-way amplitude factor through the ramp about 10^-1.5 */
+    int32_t device;          /* HIP device ordinal */
+    void* stream;            /* hipStream_t to run on, or NULL: the context creates its own */
+} kvs_opts;
+
+typedef struct {
+    double tol;          /* stop when sqrt(r.r / r0.r0) < tol (Sec. 3.2.3) */
+    int64_t max_iter;    /* > 0 */
+    int32_t precond;     /* kvs_precond: NONE = the paper's CG; JACOBI = z = r / diag(A) */
+    int64_t fixed_iters; /* > 0: run exactly this many iterations, ignore tol (parity mode) */
+    int32_t warm_start;  /* != 0: start from the previous phi instead of phi_0 = 0 */
+} kvs_solve_opts;
+
+typedef struct {
+    int64_t iters;           /* phi updates performed */
+    double relres_recursive; /* sqrt(r.r / r0.r0) at exit */
+    double relres_true;      /* ||-b - A phi|| / ||b|| recomputed from phi, FP64 */
+    double ms;               /* wall time of divergence + solve + gradient subtraction */
+    int32_t status;          /* kvs_status of the solve */
+} kvs_solve_report;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Create a solver for `grid` on opts->device (NULL opts: FP64, no sponge,
+ * device 0, own stream).  Allocates the state (zeroed: the medium starts at
+ * rest), force and projection buffers.  Fails with KVS_EDEVICE when the
+ * device is not a gfx950 GPU. */
+kvs_status kvs_create(const kvs_grid* grid, const kvs_opts* opts, kvs_ctx** out);
+void kvs_destroy(kvs_ctx* ctx);
+const char* kvs_status_string(kvs_status s);
+const char* kvs_last_error(const kvs_ctx* ctx);
+/* Block until all work queued on the context's stream is done. */
+kvs_status kvs_synchronize(kvs_ctx* ctx);
+/* The hipStream_t the context runs on. */
+void* kvs_stream(const kvs_ctx* ctx);
+
+/* ---- medium and time step (Sec. 2.4 coefficients, Sec. 3.1 bound) ------ */
+
+/* Heterogeneous medium: host arrays of N = nx*ny*nz doubles each, G > 0 [Pa],
+ * rho > 0 [kg/m^3], eta >= 0 [Pa s], all finite, else KVS_EINVAL.
+ * Recomputes the stability limit and the default sponge strength; a time
+ * step set earlier is re-checked against the new limit. */
+kvs_status kvs_set_material(kvs_ctx* ctx, const double* G, const double* rho, const double* eta);
+/* Homogeneous medium (no per-cell material traffic). */
+kvs_status kvs_set_material_uniform(kvs_ctx* ctx, double G, double rho, double eta);
+/* Largest dt with A + 2B <= 4 on every interior cell, where
+ * A = 4 dt^2 (Gmax_face / rho) S, B = 4 dt (eta / rho) S, S = sum 1/h_a^2
+ * and Gmax_face is the largest harmonic face modulus around the cell; for
+ * eta = 0 this is the CFL bound (1/c_s)(sum 1/h_a^2)^(-1/2) of Sec. 3.1. */
+kvs_status kvs_stable_dt(const kvs_ctx* ctx, double* dt_max);
+/* The sponge ramp peak in use [1/s] (resolved default after set_material). */
+kvs_status kvs_sponge_sigma_max(const kvs_ctx* ctx, double* sigma_max);
+/* Set dt [s]; dt > dt_max (1 + 1e-12) gives KVS_EUNSTABLE and keeps the
+ * previous dt. */
+kvs_status kvs_set_dt(kvs_ctx* ctx, double dt);
+
+/* ---- force and projection (Sec. 3.2, 3.3) ------------------------------ */
+
+/* Body-force pattern b0 (or the current general force f^n): host, 3*N
+ * doubles [3][nz][ny][nx] [N/m^3].  Marks the projected force stale. */
+kvs_status kvs_set_force(kvs_ctx* ctx, const double* F);
+/* Same from device memory: dtype 0 = double, 1 = float; copied on the
+ * context's stream. */
+kvs_status kvs_set_force_device(kvs_ctx* ctx, const void* F, int32_t dtype);
+/* Temporal envelope g[n] for steps n < n_env (absolute step index since the
+ * state was last reset); steps n >= n_env use g = 0. n_env may be 0. */
+kvs_status kvs_set_envelope(kvs_ctx* ctx, const double* g, int64_t n_env);
+/* Project the current force: b = div F, CG solve, f_S = F - grad phi.
+ * opts NULL: tol 1e-8, max_iter 10000, Jacobi-PCG.  ||b|| = 0 gives
+ * 0 iterations, phi = 0.  Returns the solve status (KVS_OK, KVS_ENOTCONV,
+ * KVS_EBREAKDOWN); f_S is produced in every case but EBREAKDOWN.  `report`
+ * may be NULL. */
+kvs_status kvs_project(kvs_ctx* ctx, const kvs_solve_opts* opts, kvs_solve_report* report);
+/* Inject / read back the projected force f_S (host, 3*N doubles).  Setting
+ * it marks it current (no projection needed before stepping). */
+kvs_status kvs_set_projected_force(kvs_ctx* ctx, const double* FS);
+kvs_status kvs_get_projected_force(const kvs_ctx* ctx, double* FS);
+/* Read back phi of the last projection (host, N doubles). */
+kvs_status kvs_get_phi(const kvs_ctx* ctx, double* phi);
+
+/* ---- time stepping and sensors (Sec. 3.1, 4.1) ------------------------- */
+
+/* Probe cells: ijk = n triples (i, j, k), 0 <= i < nx etc.; comp 0..2 records
+ * that displacement component, 3 records all three.  Clears recorded
+ * traces.  n = 0 disables probes. */
+kvs_status kvs_set_probes(kvs_ctx* ctx, const int64_t* ijk, int64_t n, int32_t comp);
+/* Advance nsteps >= 0 steps.  Needs material and dt; needs a current f_S
+ * when the envelope is non-zero on any of these steps (else KVS_ESTATE).
+ * After every step the probe values of u^{n+1} are appended to the traces. */
+kvs_status kvs_step(kvs_ctx* ctx, int64_t nsteps);
+/* Number of steps recorded in the traces. */
+kvs_status kvs_trace_count(const kvs_ctx* ctx, int64_t* nsteps_recorded);
+/* Copy the traces [step][probe][comp] (comp extent 1, or 3 for comp == 3)
+ * into out (host, cap doubles); n_written = doubles written.  Blocks. */
+kvs_status kvs_read_traces(const kvs_ctx* ctx, double* out, int64_t cap, int64_t* n_written);
+kvs_status kvs_clear_traces(kvs_ctx* ctx);
+/* State in doubles (host, 3*N each): u^n and w^n = u^n - u^{n-1}, and the
+ * absolute step index n.  get blocks; set resets the outer layer to 0. */
+kvs_status kvs_get_state(const kvs_ctx* ctx, double* u, double* w, int64_t* step);
+kvs_status kvs_set_state(kvs_ctx* ctx, const double* u, const double* w, int64_t step);
+/* Return the medium to rest (u = w = 0), reset the step index to 0 and clear
+ * the traces; material, dt, force, projection and probes are kept. */
+kvs_status kvs_reset_state(kvs_ctx* ctx);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* When on, kvs_step brackets every launch of the FDTD step kernel with HIP
+ * events on the context's stream; kvs_kernel_time returns the summed
+ * duration [ms] and the launch count since timing was switched on. */
+kvs_status kvs_enable_kernel_timing(kvs_ctx* ctx, int32_t on);
+kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KVS_H */

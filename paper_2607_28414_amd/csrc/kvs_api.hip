@@ -1,0 +1,641 @@
+// C ABI of the shear solver (declarations and contracts in include/kvs.h).
+// Host code only: argument checking, buffer ownership, call ordering, and
+// the launch sequence of the kernels in kvs_step.hip and kvs_cg.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kvs_internal.hpp"
+
+namespace {
+
+thread_local std::string g_create_err;
+
+kvs_status fail(kvs_ctx* c, kvs_status s, const std::string& msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_create_err = msg;
+    return s;
+}
+
+#define API_HIP(c, call)                                                                                 \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fail(c, KVS_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t tsize(const kvs_ctx* c) { return c->prec == KVS_FP32 ? sizeof(float) : sizeof(double); }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Closed-form stability bound of a homogeneous medium (every face modulus is G).
+double uniform_dt_max(const kvs_grid& g, double G, double rho, double eta) {
+    const double S = 1.0 / (g.hx * g.hx) + 1.0 / (g.hy * g.hy) + 1.0 / (g.hz * g.hz);
+    const double qa = G / rho * S, qb = 2.0 * eta / rho * S;
+    return (-qb + std::sqrt(qb * qb + 4.0 * qa)) / (2.0 * qa);
+}
+
+void resolve_sigma(kvs_ctx* c, double cmax) {
+    if (c->sponge_cells <= 0) {
+        c->sigma_max = 0.0;
+        return;
+    }
+    if (c->sigma_user >= 0.0) {
+        c->sigma_max = c->sigma_user;
+        return;
+    }
+    const double hmin = std::min(c->grid.hx, std::min(c->grid.hy, c->grid.hz));
+    c->sigma_max = 6.0 * std::log(10.0) * cmax / ((double)c->sponge_cells * hmin);
+}
+
+template <typename P>
+void dfree(P*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void release(kvs_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (int b = 0; b < 2; ++b) {
+        dfree(c->u[b]);
+        dfree(c->w[b]);
+        dfree(c->p[b]);
+    }
+    dfree(c->G);
+    dfree(c->eta);
+    dfree(c->rho_t);
+    dfree(c->crho);
+    dfree(c->F);
+    dfree(c->FS);
+    dfree(c->phi);
+    dfree(c->r);
+    dfree(c->Ap);
+    dfree(c->partials);
+    dfree(c->cgs);
+    dfree(c->probe_cells);
+    dfree(c->traces);
+    if (c->cgs_host) (void)hipHostFree(c->cgs_host);
+    c->cgs_host = nullptr;
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    c->ev_pool.clear();
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    c->stream = nullptr;
+}
+
+kvs_status need_material(kvs_ctx* c) {
+    if (!c) return KVS_EINVAL;
+    if (!c->have_material) return fail(c, KVS_ESTATE, "no material set");
+    return KVS_OK;
+}
+
+kvs_status ensure_trace_capacity(kvs_ctx* c, int64_t more) {
+    if (c->nprobes == 0) return KVS_OK;
+    const int64_t need = c->trace_steps + more;
+    if (need <= c->trace_cap) return KVS_OK;
+    int64_t cap = std::max<int64_t>(need, std::max<int64_t>(2 * c->trace_cap, 1024));
+    const int64_t per = c->nprobes * ncomp_of(c->probe_comp);
+    double* nb = nullptr;
+    API_HIP(c, hipMalloc(&nb, sizeof(double) * per * cap));
+    if (c->traces && c->trace_steps > 0)
+        API_HIP(c, hipMemcpyAsync(nb, c->traces, sizeof(double) * per * c->trace_steps, hipMemcpyDeviceToDevice,
+                                  c->stream));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    dfree(c->traces);
+    c->traces = nb;
+    c->trace_cap = cap;
+    return KVS_OK;
+}
+
+// Accumulate the durations of the recorded event pairs and recycle them.
+kvs_status flush_timing(kvs_ctx* c) {
+    if (c->ev_used == 0) return KVS_OK;
+    API_HIP(c, hipEventSynchronize(c->ev_pool[2 * c->ev_used - 1]));
+    for (int64_t q = 0; q < c->ev_used; ++q) {
+        float ms = 0.f;
+        API_HIP(c, hipEventElapsedTime(&ms, c->ev_pool[2 * q], c->ev_pool[2 * q + 1]));
+        c->timed_ms += ms;
+    }
+    c->timed_launches += c->ev_used;
+    c->ev_used = 0;
+    return KVS_OK;
+}
+
+kvs_status next_event_pair(kvs_ctx* c, hipEvent_t* a, hipEvent_t* b) {
+    const int64_t cap_pairs = 1 << 14;
+    if (c->ev_used >= cap_pairs) {
+        kvs_status s = flush_timing(c);
+        if (s != KVS_OK) return s;
+    }
+    while ((int64_t)c->ev_pool.size() < 2 * (c->ev_used + 1)) {
+        hipEvent_t e;
+        API_HIP(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    *a = c->ev_pool[2 * c->ev_used];
+    *b = c->ev_pool[2 * c->ev_used + 1];
+    c->ev_used += 1;
+    return KVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kvs_status_string(kvs_status s) {
+    switch (s) {
+        case KVS_OK: return "ok";
+        case KVS_EINVAL: return "invalid argument";
+        case KVS_ENOMEM: return "out of memory";
+        case KVS_EDEVICE: return "device error";
+        case KVS_ENOTCONV: return "not converged";
+        case KVS_EBREAKDOWN: return "CG breakdown";
+        case KVS_EUNSTABLE: return "time step above the stability limit";
+        case KVS_ESTATE: return "call order / missing state";
+    }
+    return "unknown status";
+}
+
+const char* kvs_last_error(const kvs_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+void* kvs_stream(const kvs_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+kvs_status kvs_create(const kvs_grid* grid, const kvs_opts* opts, kvs_ctx** out) {
+    if (!out) return fail(nullptr, KVS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grid) return fail(nullptr, KVS_EINVAL, "grid is NULL");
+    const kvs_grid g = *grid;
+    if (g.nx < 3 || g.ny < 3 || g.nz < 3) return fail(nullptr, KVS_EINVAL, "every axis needs >= 3 nodes");
+    if (!finite_pos(g.hx) || !finite_pos(g.hy) || !finite_pos(g.hz))
+        return fail(nullptr, KVS_EINVAL, "spacings must be finite and > 0");
+    const double Nd = (double)g.nx * (double)g.ny * (double)g.nz;
+    if (Nd > 2.0e9) return fail(nullptr, KVS_EINVAL, "grid above 2e9 nodes (32-bit in-plane indexing)");
+    kvs_opts o{};
+    o.precision = KVS_FP64;
+    o.sponge_cells = 0;
+    o.sponge_sigma_max = -1.0;
+    if (opts) o = *opts;
+    if (o.precision != KVS_FP64 && o.precision != KVS_FP32) return fail(nullptr, KVS_EINVAL, "unknown precision");
+    if (o.sponge_cells < 0) return fail(nullptr, KVS_EINVAL, "sponge_cells < 0");
+    if (std::isnan(o.sponge_sigma_max)) return fail(nullptr, KVS_EINVAL, "sponge_sigma_max is NaN");
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, KVS_EDEVICE, "no HIP device");
+    if (o.device < 0 || o.device >= ndev) return fail(nullptr, KVS_EINVAL, "device ordinal out of range");
+    if (hipSetDevice(o.device) != hipSuccess) return fail(nullptr, KVS_EDEVICE, "hipSetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, o.device) != hipSuccess)
+        return fail(nullptr, KVS_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, KVS_EDEVICE, std::string("library built for gfx950, device is ") + prop.gcnArchName);
+
+    kvs_ctx* c = new (std::nothrow) kvs_ctx();
+    if (!c) return fail(nullptr, KVS_ENOMEM, "host allocation failed");
+    c->grid = g;
+    c->N = g.nx * g.ny * g.nz;
+    c->prec = o.precision;
+    c->device = o.device;
+    c->sponge_cells = o.sponge_cells;
+    c->sigma_user = o.sponge_sigma_max;
+    if (o.stream) {
+        c->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(nullptr, KVS_EDEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    const size_t ts = tsize(c);
+    const size_t N = (size_t)c->N;
+    c->npart = kvs_cg_partials_needed(g);
+    bool ok = true;
+    for (int b = 0; b < 2 && ok; ++b) {
+        ok = ok && hipMalloc(&c->u[b], 3 * N * ts) == hipSuccess;
+        ok = ok && hipMalloc(&c->w[b], 3 * N * ts) == hipSuccess;
+        ok = ok && hipMalloc(&c->p[b], N * sizeof(double)) == hipSuccess;
+    }
+    ok = ok && hipMalloc(&c->F, 3 * N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&c->FS, 3 * N * ts) == hipSuccess;
+    ok = ok && hipMalloc(&c->phi, N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&c->r, N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&c->Ap, N * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&c->partials, 3 * (size_t)std::max<int64_t>(c->npart, 2048) * sizeof(double)) == hipSuccess;
+    ok = ok && hipMalloc(&c->cgs, sizeof(CgState)) == hipSuccess;
+    ok = ok && hipHostMalloc(&c->cgs_host, sizeof(CgState), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        release(c);
+        delete c;
+        return fail(nullptr, KVS_ENOMEM, "device allocation failed");
+    }
+    bool z = true;
+    for (int b = 0; b < 2; ++b) {
+        z = z && hipMemsetAsync(c->u[b], 0, 3 * N * ts, c->stream) == hipSuccess;
+        z = z && hipMemsetAsync(c->w[b], 0, 3 * N * ts, c->stream) == hipSuccess;
+        z = z && hipMemsetAsync(c->p[b], 0, N * sizeof(double), c->stream) == hipSuccess;
+    }
+    z = z && hipMemsetAsync(c->F, 0, 3 * N * sizeof(double), c->stream) == hipSuccess;
+    z = z && hipMemsetAsync(c->FS, 0, 3 * N * ts, c->stream) == hipSuccess;
+    z = z && hipMemsetAsync(c->phi, 0, N * sizeof(double), c->stream) == hipSuccess;
+    z = z && hipMemsetAsync(c->r, 0, N * sizeof(double), c->stream) == hipSuccess;
+    z = z && hipMemsetAsync(c->Ap, 0, N * sizeof(double), c->stream) == hipSuccess;
+    z = z && hipStreamSynchronize(c->stream) == hipSuccess;
+    if (!z) {
+        release(c);
+        delete c;
+        return fail(nullptr, KVS_EDEVICE, "initial zero fill failed");
+    }
+    *out = c;
+    return KVS_OK;
+}
+
+void kvs_destroy(kvs_ctx* c) {
+    if (!c) return;
+    release(c);
+    delete c;
+}
+
+kvs_status kvs_synchronize(kvs_ctx* c) {
+    if (!c) return KVS_EINVAL;
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    return KVS_OK;
+}
+
+kvs_status kvs_set_material(kvs_ctx* c, const double* G, const double* rho, const double* eta) {
+    if (!c) return KVS_EINVAL;
+    if (!G || !rho || !eta) return fail(c, KVS_EINVAL, "material pointer is NULL");
+    const int64_t N = c->N;
+    bool visc = false;
+    for (int64_t q = 0; q < N; ++q) {
+        if (!finite_pos(G[q]) || !finite_pos(rho[q]) || !std::isfinite(eta[q]) || eta[q] < 0.0)
+            return fail(c, KVS_EINVAL, "material must have finite G > 0, rho > 0, eta >= 0 (cell " +
+                                           std::to_string(q) + ")");
+        visc = visc || eta[q] > 0.0;
+    }
+    API_HIP(c, hipSetDevice(c->device));
+    const size_t ts = tsize(c);
+    if (!c->G) API_HIP(c, hipMalloc(&c->G, N * ts));
+    if (!c->eta) API_HIP(c, hipMalloc(&c->eta, N * ts));
+    if (!c->rho_t) API_HIP(c, hipMalloc(&c->rho_t, N * ts));
+    if (!c->crho) API_HIP(c, hipMalloc(&c->crho, N * ts));
+    double* tmp = nullptr;
+    const int64_t npart = 2 * 1024;
+    API_HIP(c, hipMalloc(&tmp, sizeof(double) * (3 * N + npart + 2)));
+    double* dG = tmp;
+    double* drho = tmp + N;
+    double* deta = tmp + 2 * N;
+    double* part = tmp + 3 * N;
+    double* res = part + npart;
+    kvs_status st = KVS_OK;
+    double host_res[2] = {0, 0};
+    do {
+        hipError_t e = hipMemcpyAsync(dG, G, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(drho, rho, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(deta, eta, sizeof(double) * N, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = kvs_launch_stable_dt(c, dG, drho, deta, part, npart, res);
+        if (e == hipSuccess) e = kvs_launch_cast_material(c, dG, drho, deta);
+        if (e == hipSuccess) e = hipMemcpyAsync(host_res, res, sizeof(host_res), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail(c, KVS_EDEVICE, std::string("set_material: ") + hipGetErrorString(e));
+    } while (false);
+    (void)hipFree(tmp);
+    if (st != KVS_OK) return st;
+    c->hetero = true;
+    c->viscous = visc;
+    c->have_material = true;
+    c->dt_max = host_res[0];
+    resolve_sigma(c, host_res[1]);
+    if (c->have_dt) {
+        if (c->dt > c->dt_max * (1.0 + 1e-12)) {
+            c->have_dt = false;
+        } else {
+            API_HIP(c, kvs_launch_crho(c));
+        }
+    }
+    return KVS_OK;
+}
+
+kvs_status kvs_set_material_uniform(kvs_ctx* c, double G, double rho, double eta) {
+    if (!c) return KVS_EINVAL;
+    if (!finite_pos(G) || !finite_pos(rho) || !std::isfinite(eta) || eta < 0.0)
+        return fail(c, KVS_EINVAL, "material must have finite G > 0, rho > 0, eta >= 0");
+    c->hetero = false;
+    c->viscous = eta > 0.0;
+    c->G0 = G;
+    c->rho0 = rho;
+    c->eta0 = eta;
+    c->have_material = true;
+    c->dt_max = uniform_dt_max(c->grid, G, rho, eta);
+    resolve_sigma(c, std::sqrt(G / rho));
+    if (c->have_dt && c->dt > c->dt_max * (1.0 + 1e-12)) c->have_dt = false;
+    return KVS_OK;
+}
+
+kvs_status kvs_stable_dt(const kvs_ctx* cc, double* dt_max) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    kvs_status s = need_material(c);
+    if (s != KVS_OK) return s;
+    if (!dt_max) return fail(c, KVS_EINVAL, "dt_max is NULL");
+    *dt_max = c->dt_max;
+    return KVS_OK;
+}
+
+kvs_status kvs_sponge_sigma_max(const kvs_ctx* cc, double* sigma_max) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    kvs_status s = need_material(c);
+    if (s != KVS_OK) return s;
+    if (!sigma_max) return fail(c, KVS_EINVAL, "sigma_max is NULL");
+    *sigma_max = c->sigma_max;
+    return KVS_OK;
+}
+
+kvs_status kvs_set_dt(kvs_ctx* c, double dt) {
+    kvs_status s = need_material(c);
+    if (s != KVS_OK) return s;
+    if (!finite_pos(dt)) return fail(c, KVS_EINVAL, "dt must be finite and > 0");
+    if (dt > c->dt_max * (1.0 + 1e-12))
+        return fail(c, KVS_EUNSTABLE, "dt " + std::to_string(dt) + " above the stability limit " +
+                                          std::to_string(c->dt_max));
+    c->dt = dt;
+    c->have_dt = true;
+    API_HIP(c, kvs_launch_crho(c));
+    return KVS_OK;
+}
+
+kvs_status kvs_set_force(kvs_ctx* c, const double* F) {
+    if (!c) return KVS_EINVAL;
+    if (!F) return fail(c, KVS_EINVAL, "F is NULL");
+    API_HIP(c, hipMemcpyAsync(c->F, F, sizeof(double) * 3 * c->N, hipMemcpyHostToDevice, c->stream));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    c->have_force = true;
+    c->fs_current = false;
+    return KVS_OK;
+}
+
+kvs_status kvs_set_force_device(kvs_ctx* c, const void* F, int32_t dtype) {
+    if (!c) return KVS_EINVAL;
+    if (!F) return fail(c, KVS_EINVAL, "F is NULL");
+    if (dtype == 0) {
+        API_HIP(c, hipMemcpyAsync(c->F, F, sizeof(double) * 3 * c->N, hipMemcpyDeviceToDevice, c->stream));
+    } else if (dtype == 1) {
+        API_HIP(c, kvs_launch_f32_to_f64(c, static_cast<const float*>(F), c->F, 3 * c->N));
+    } else {
+        return fail(c, KVS_EINVAL, "dtype must be 0 (double) or 1 (float)");
+    }
+    c->have_force = true;
+    c->fs_current = false;
+    return KVS_OK;
+}
+
+kvs_status kvs_set_envelope(kvs_ctx* c, const double* g, int64_t n) {
+    if (!c) return KVS_EINVAL;
+    if (n < 0 || (n > 0 && !g)) return fail(c, KVS_EINVAL, "bad envelope");
+    for (int64_t q = 0; q < n; ++q)
+        if (!std::isfinite(g[q])) return fail(c, KVS_EINVAL, "envelope value not finite");
+    c->env.assign(g, g + n);
+    return KVS_OK;
+}
+
+kvs_status kvs_project(kvs_ctx* c, const kvs_solve_opts* opts, kvs_solve_report* rep) {
+    if (!c) return KVS_EINVAL;
+    if (!c->have_force) return fail(c, KVS_ESTATE, "no force set");
+    kvs_solve_opts o{};
+    o.tol = 1e-8;
+    o.max_iter = 10000;
+    o.precond = KVS_PC_JACOBI;
+    if (opts) o = *opts;
+    if (o.fixed_iters < 0) return fail(c, KVS_EINVAL, "fixed_iters < 0");
+    if (o.fixed_iters == 0 && !(o.tol > 0.0 && std::isfinite(o.tol))) return fail(c, KVS_EINVAL, "tol must be > 0");
+    if (o.max_iter <= 0) return fail(c, KVS_EINVAL, "max_iter must be > 0");
+    if (o.precond != KVS_PC_NONE && o.precond != KVS_PC_JACOBI)
+        return fail(c, KVS_EINVAL, "preconditioner not available on this context");
+    API_HIP(c, hipSetDevice(c->device));
+    return kvs_run_projection(c, &o, rep);
+}
+
+kvs_status kvs_set_projected_force(kvs_ctx* c, const double* FS) {
+    if (!c) return KVS_EINVAL;
+    if (!FS) return fail(c, KVS_EINVAL, "FS is NULL");
+    const size_t bytes = sizeof(double) * 3 * c->N;
+    if (c->prec == KVS_FP64) {
+        API_HIP(c, hipMemcpyAsync(c->FS, FS, bytes, hipMemcpyHostToDevice, c->stream));
+        API_HIP(c, hipStreamSynchronize(c->stream));
+    } else {
+        double* tmp = nullptr;
+        API_HIP(c, hipMalloc(&tmp, bytes));
+        hipError_t e = hipMemcpyAsync(tmp, FS, bytes, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = kvs_launch_cast(c, tmp, c->FS, 3 * c->N);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("set_projected_force: ") + hipGetErrorString(e));
+    }
+    c->fs_current = true;
+    return KVS_OK;
+}
+
+kvs_status kvs_get_projected_force(const kvs_ctx* cc, double* FS) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    if (!FS) return fail(c, KVS_EINVAL, "FS is NULL");
+    const size_t bytes = sizeof(double) * 3 * c->N;
+    if (c->prec == KVS_FP64) {
+        API_HIP(c, hipMemcpyAsync(FS, c->FS, bytes, hipMemcpyDeviceToHost, c->stream));
+        API_HIP(c, hipStreamSynchronize(c->stream));
+        return KVS_OK;
+    }
+    double* tmp = nullptr;
+    API_HIP(c, hipMalloc(&tmp, bytes));
+    hipError_t e = kvs_launch_widen(c, c->FS, tmp, 3 * c->N);
+    if (e == hipSuccess) e = hipMemcpyAsync(FS, tmp, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("get_projected_force: ") + hipGetErrorString(e));
+    return KVS_OK;
+}
+
+kvs_status kvs_get_phi(const kvs_ctx* cc, double* phi) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    if (!phi) return fail(c, KVS_EINVAL, "phi is NULL");
+    API_HIP(c, hipMemcpyAsync(phi, c->phi, sizeof(double) * c->N, hipMemcpyDeviceToHost, c->stream));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    return KVS_OK;
+}
+
+kvs_status kvs_set_probes(kvs_ctx* c, const int64_t* ijk, int64_t n, int32_t comp) {
+    if (!c) return KVS_EINVAL;
+    if (n < 0 || (n > 0 && !ijk)) return fail(c, KVS_EINVAL, "bad probe list");
+    if (comp < 0 || comp > 3) return fail(c, KVS_EINVAL, "comp must be 0..3");
+    std::vector<int64_t> flat((size_t)n);
+    const kvs_grid& g = c->grid;
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t i = ijk[3 * p], j = ijk[3 * p + 1], k = ijk[3 * p + 2];
+        if (i < 0 || i >= g.nx || j < 0 || j >= g.ny || k < 0 || k >= g.nz)
+            return fail(c, KVS_EINVAL, "probe " + std::to_string(p) + " outside the grid");
+        flat[(size_t)p] = i + g.nx * (j + g.ny * k);
+    }
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    dfree(c->probe_cells);
+    dfree(c->traces);
+    c->trace_cap = 0;
+    c->trace_steps = 0;
+    c->nprobes = n;
+    c->probe_comp = comp;
+    if (n > 0) {
+        API_HIP(c, hipMalloc(&c->probe_cells, sizeof(int64_t) * n));
+        API_HIP(c, hipMemcpyAsync(c->probe_cells, flat.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
+        API_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return KVS_OK;
+}
+
+kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
+    kvs_status s = need_material(c);
+    if (s != KVS_OK) return s;
+    if (nsteps < 0) return fail(c, KVS_EINVAL, "nsteps < 0");
+    if (!c->have_dt) return fail(c, KVS_ESTATE, "no time step set");
+    const int64_t n_env = (int64_t)c->env.size();
+    for (int64_t n = c->step; n < std::min(c->step + nsteps, n_env); ++n)
+        if (c->env[(size_t)n] != 0.0 && !c->fs_current)
+            return fail(c, KVS_ESTATE, "the envelope is non-zero but the projected force is not current");
+    s = ensure_trace_capacity(c, nsteps);
+    if (s != KVS_OK) return s;
+    API_HIP(c, hipSetDevice(c->device));
+    for (int64_t q = 0; q < nsteps; ++q) {
+        const int64_t n = c->step;
+        const double gn = n < n_env ? c->env[(size_t)n] : 0.0;
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (c->timing) {
+            s = next_event_pair(c, &ea, &eb);
+            if (s != KVS_OK) return s;
+            API_HIP(c, hipEventRecord(ea, c->stream));
+        }
+        API_HIP(c, kvs_launch_step(c, gn));
+        if (c->timing) API_HIP(c, hipEventRecord(eb, c->stream));
+        c->cur = 1 - c->cur;
+        if (c->nprobes > 0) {
+            API_HIP(c, kvs_launch_probe_gather(c, c->u[c->cur], c->trace_steps));
+            c->trace_steps += 1;
+        }
+        c->step += 1;
+    }
+    return KVS_OK;
+}
+
+kvs_status kvs_trace_count(const kvs_ctx* c, int64_t* n) {
+    if (!c || !n) return KVS_EINVAL;
+    *n = c->trace_steps;
+    return KVS_OK;
+}
+
+kvs_status kvs_read_traces(const kvs_ctx* cc, double* out, int64_t cap, int64_t* n_written) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    if (cap < 0 || (cap > 0 && !out)) return fail(c, KVS_EINVAL, "bad output buffer");
+    const int64_t total = c->trace_steps * c->nprobes * ncomp_of(c->probe_comp);
+    const int64_t n = std::min(cap, total);
+    if (n > 0) {
+        API_HIP(c, hipMemcpyAsync(out, c->traces, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    }
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    if (n_written) *n_written = n;
+    return KVS_OK;
+}
+
+kvs_status kvs_clear_traces(kvs_ctx* c) {
+    if (!c) return KVS_EINVAL;
+    c->trace_steps = 0;
+    return KVS_OK;
+}
+
+kvs_status kvs_get_state(const kvs_ctx* cc, double* u, double* w, int64_t* step) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    const size_t bytes = sizeof(double) * 3 * c->N;
+    double* tmp = nullptr;
+    if (c->prec == KVS_FP32) API_HIP(c, hipMalloc(&tmp, bytes));
+    hipError_t e = hipSuccess;
+    void* src[2] = {c->u[c->cur], c->w[c->cur]};
+    double* dst[2] = {u, w};
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+        if (!dst[q]) continue;
+        if (c->prec == KVS_FP64) {
+            e = hipMemcpyAsync(dst[q], src[q], bytes, hipMemcpyDeviceToHost, c->stream);
+        } else {
+            e = kvs_launch_widen(c, src[q], tmp, 3 * c->N);
+            if (e == hipSuccess) e = hipMemcpyAsync(dst[q], tmp, bytes, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("get_state: ") + hipGetErrorString(e));
+    if (step) *step = c->step;
+    return KVS_OK;
+}
+
+kvs_status kvs_set_state(kvs_ctx* c, const double* u, const double* w, int64_t step) {
+    if (!c) return KVS_EINVAL;
+    if (!u || !w || step < 0) return fail(c, KVS_EINVAL, "bad state");
+    const size_t bytes = sizeof(double) * 3 * c->N;
+    double* tmp = nullptr;
+    API_HIP(c, hipMalloc(&tmp, bytes));
+    hipError_t e = hipSuccess;
+    const double* src[2] = {u, w};
+    void* dst[2] = {c->u[c->cur], c->w[c->cur]};
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+        e = hipMemcpyAsync(tmp, src[q], bytes, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = kvs_launch_cast(c, tmp, dst[q], 3 * c->N);
+        if (e == hipSuccess) e = kvs_launch_zero_boundary(c, dst[q]);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("set_state: ") + hipGetErrorString(e));
+    c->step = step;
+    return KVS_OK;
+}
+
+kvs_status kvs_reset_state(kvs_ctx* c) {
+    if (!c) return KVS_EINVAL;
+    const size_t bytes = 3 * (size_t)c->N * tsize(c);
+    for (int b = 0; b < 2; ++b) {
+        API_HIP(c, hipMemsetAsync(c->u[b], 0, bytes, c->stream));
+        API_HIP(c, hipMemsetAsync(c->w[b], 0, bytes, c->stream));
+    }
+    c->step = 0;
+    c->trace_steps = 0;
+    return KVS_OK;
+}
+
+kvs_status kvs_enable_kernel_timing(kvs_ctx* c, int32_t on) {
+    if (!c) return KVS_EINVAL;
+    if (on && !c->timing) {
+        c->timed_ms = 0.0;
+        c->timed_launches = 0;
+        c->ev_used = 0;
+    }
+    if (!on && c->timing) {
+        kvs_status s = flush_timing(c);
+        if (s != KVS_OK) return s;
+    }
+    c->timing = on != 0;
+    return KVS_OK;
+}
+
+kvs_status kvs_kernel_time(kvs_ctx* c, double* ms_total, int64_t* launches) {
+    if (!c) return KVS_EINVAL;
+    kvs_status s = flush_timing(c);
+    if (s != KVS_OK) return s;
+    if (ms_total) *ms_total = c->timed_ms;
+    if (launches) *launches = c->timed_launches;
+    return KVS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,429 @@
+// Helmholtz projection of the body force (Sec. 3.2) on gfx950, all in FP64:
+//   b = centred divergence of F on interior nodes,
+//   CG on A phi = -b, A = -lap_h (interior mask after every update, phi_0 = 0
+//   or a warm start, stop at sqrt(r.r / r0.r0) < tol, guards on p.Ap <= 0 and
+//   non-finite inner products: Sec. 3.2.3),
+//   f_S,a = (F_a(-a) + 2 F_a + F_a(+a))/4 - (phi(+a) - phi(-a))/(2 h_a).
+//
+// One CG iteration is two fused HBM sweeps plus two one-block finalize
+// kernels, with every scalar (alpha, beta, r.r, the stop flag) kept on the
+// device, so the host only polls a flag once per chunk of iterations:
+//   sweep 1: p' = z + beta p (z = r, or r / diag(A) for Jacobi), Ap' = -lap p',
+//            block partials of p'.Ap'            (reads r, p; writes p', Ap')
+//   finalize: alpha = r.z / p.Ap with the breakdown guard
+//   sweep 2: phi += alpha p', r -= alpha Ap', partials of r.r and r.z
+//   finalize: beta, the stop test, the iteration count
+// p is ping-ponged because sweep 1 reads p at neighbours while writing p'.
+// Reductions are deterministic: fixed-shape wavefront shuffles inside a
+// block, one partial per block, and a one-block fixed-order final sum.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "kvs_internal.hpp"
+
+namespace {
+
+constexpr int CBY = 4;    // rows per block
+constexpr int CKZ = 16;   // z planes per block
+
+struct CgGeom {
+    int nx, ny, nz, gx, gy, gz, kchunk;
+    long long N;
+    double ihx2, ihy2, ihz2;
+    double i2hx, i2hy, i2hz;  // 1/(2h)
+    double dinv;              // 1/diag(A)
+};
+
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3 };
+
+__device__ __forceinline__ int tile_of(int b, int B) {
+    const int xcd = b & 7, pos = b >> 3;
+    const int per = B >> 3, rem = B & 7;
+    return xcd * per + min(xcd, rem) + pos;
+}
+
+struct Tile {
+    int i, j, kb, ke;
+    bool act;
+    int col;
+};
+
+__device__ __forceinline__ Tile tile_coords(const CgGeom& g) {
+    const int B = g.gx * g.gy * g.gz;
+    const int t = tile_of(blockIdx.x, B);
+    const int bx = t % g.gx, by = (t / g.gx) % g.gy, bz = t / (g.gx * g.gy);
+    Tile T;
+    T.i = bx * 64 + threadIdx.x;
+    T.j = by * CBY + threadIdx.y;
+    T.kb = 1 + bz * g.kchunk;
+    T.ke = min(g.nz - 1, T.kb + g.kchunk);
+    T.act = T.i >= 1 && T.i <= g.nx - 2 && T.j >= 1 && T.j <= g.ny - 2;
+    T.col = T.act ? T.i + g.nx * T.j : 0;
+    return T;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum up to three values over the block; thread 0 writes them to partials
+// [which * npart + block].
+template <int NS>
+__device__ __forceinline__ void block_partials(double v0, double v1, double v2, double* partials, int npart) {
+    __shared__ double sh[3][CBY];
+    const int lane = threadIdx.x, wid = threadIdx.y;
+    v0 = wave_sum(v0);
+    if (NS > 1) v1 = wave_sum(v1);
+    if (NS > 2) v2 = wave_sum(v2);
+    if (lane == 0) {
+        sh[0][wid] = v0;
+        if (NS > 1) sh[1][wid] = v1;
+        if (NS > 2) sh[2][wid] = v2;
+    }
+    __syncthreads();
+    if (lane == 0 && wid == 0) {
+        double a = 0, b = 0, c = 0;
+        for (int w = 0; w < CBY; ++w) {
+            a += sh[0][w];
+            if (NS > 1) b += sh[1][w];
+            if (NS > 2) c += sh[2][w];
+        }
+        partials[blockIdx.x] = a;
+        if (NS > 1) partials[npart + blockIdx.x] = b;
+        if (NS > 2) partials[2 * npart + blockIdx.x] = c;
+    }
+}
+
+__device__ __forceinline__ double div_at(const CgGeom& g, const double* F, int idx) {
+    const int sy = g.nx, sz = g.nx * g.ny;
+    const double* Fx = F;
+    const double* Fy = F + g.N;
+    const double* Fz = F + 2 * g.N;
+    return (Fx[idx + 1] - Fx[idx - 1]) * g.i2hx + (Fy[idx + sy] - Fy[idx - sy]) * g.i2hy
+         + (Fz[idx + sz] - Fz[idx - sz]) * g.i2hz;
+}
+
+__device__ __forceinline__ double negative_lap_at(const CgGeom& g, const double* q, int idx) {
+    const int sy = g.nx, sz = g.nx * g.ny;
+    const double c2 = 2.0 * q[idx];
+    return -((q[idx + 1] + q[idx - 1] - c2) * g.ihx2 + (q[idx + sy] + q[idx - sy] - c2) * g.ihy2
+             + (q[idx + sz] + q[idx - sz] - c2) * g.ihz2);
+}
+
+// r0 = -b - A phi0 (warm) or -b; partials of r.r, r.z, b.b
+__global__ __launch_bounds__(64 * CBY) void cg_init_kernel(const CgGeom g, const double* F, const double* phi,
+                                                           double* r, int warm, double* partials, int npart) {
+    const Tile t = tile_coords(g);
+    const int sxy = g.nx * g.ny;
+    double s1 = 0, s2 = 0, s3 = 0;
+    if (t.act) {
+        for (int k = t.kb; k < t.ke; ++k) {
+            const int idx = k * sxy + t.col;
+            const double b = div_at(g, F, idx);
+            double rv = -b;
+            if (warm) rv -= negative_lap_at(g, phi, idx);
+            r[idx] = rv;
+            s1 += rv * rv;
+            s2 += rv * (rv * g.dinv);
+            s3 += b * b;
+        }
+    }
+    block_partials<3>(s1, s2, s3, partials, npart);
+}
+
+// p' = z + beta p, Ap' = -lap p', partial p'.Ap'
+__global__ __launch_bounds__(64 * CBY) void cg_matvec_kernel(const CgGeom g, const double* r, const double* p_old,
+                                                             double* p_new, double* Ap, const CgState* st,
+                                                             double* partials, int npart) {
+    if (st->done) return;
+    const Tile t = tile_coords(g);
+    const double beta = st->beta;
+    const double zs = st->jacobi ? g.dinv : 1.0;
+    const int sxy = g.nx * g.ny, sy = g.nx;
+    double s1 = 0;
+    if (t.act) {
+        auto pn = [&](int q) { return beta == 0.0 ? r[q] * zs : r[q] * zs + beta * p_old[q]; };
+        double pm = pn((t.kb - 1) * sxy + t.col);
+        double pc = pn(t.kb * sxy + t.col);
+        for (int k = t.kb; k < t.ke; ++k) {
+            const int idx = k * sxy + t.col;
+            const double pp = pn(idx + sxy);
+            const double c2 = 2.0 * pc;
+            const double ap = -((pn(idx + 1) + pn(idx - 1) - c2) * g.ihx2 + (pn(idx + sy) + pn(idx - sy) - c2) * g.ihy2
+                                + (pp + pm - c2) * g.ihz2);
+            p_new[idx] = pc;
+            Ap[idx] = ap;
+            s1 += pc * ap;
+            pm = pc;
+            pc = pp;
+        }
+    }
+    block_partials<1>(s1, 0, 0, partials, npart);
+}
+
+// phi += alpha p, r -= alpha Ap, partials of r.r and r.z
+__global__ __launch_bounds__(64 * CBY) void cg_update_kernel(const CgGeom g, double* phi, double* r, const double* p,
+                                                             const double* Ap, const CgState* st, double* partials,
+                                                             int npart) {
+    if (st->done) return;
+    const Tile t = tile_coords(g);
+    const double alpha = st->alpha;
+    const int sxy = g.nx * g.ny;
+    double s1 = 0, s2 = 0;
+    if (t.act) {
+        for (int k = t.kb; k < t.ke; ++k) {
+            const int idx = k * sxy + t.col;
+            phi[idx] += alpha * p[idx];
+            const double rv = r[idx] - alpha * Ap[idx];
+            r[idx] = rv;
+            s1 += rv * rv;
+            s2 += rv * (rv * g.dinv);
+        }
+    }
+    block_partials<2>(s1, s2, 0, partials, npart);
+}
+
+// partials of (-b - A phi)^2 and b^2
+__global__ __launch_bounds__(64 * CBY) void cg_true_residual_kernel(const CgGeom g, const double* F, const double* phi,
+                                                                    double* partials, int npart) {
+    const Tile t = tile_coords(g);
+    const int sxy = g.nx * g.ny;
+    double s1 = 0, s3 = 0;
+    if (t.act) {
+        for (int k = t.kb; k < t.ke; ++k) {
+            const int idx = k * sxy + t.col;
+            const double b = div_at(g, F, idx);
+            const double d = -b - negative_lap_at(g, phi, idx);
+            s1 += d * d;
+            s3 += b * b;
+        }
+    }
+    block_partials<3>(s1, 0.0, s3, partials, npart);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * CBY) void grad_subtract_kernel(const CgGeom g, const double* F, const double* phi,
+                                                                 T* FS) {
+    const Tile t = tile_coords(g);
+    if (!t.act) return;
+    const int sxy = g.nx * g.ny;
+    const int st[3] = {1, g.nx, sxy};
+    const double i2h[3] = {g.i2hx, g.i2hy, g.i2hz};
+    for (int k = t.kb; k < t.ke; ++k) {
+        const int idx = k * sxy + t.col;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double* Fa = F + a * g.N;
+            const double v = 0.25 * (Fa[idx - st[a]] + 2.0 * Fa[idx] + Fa[idx + st[a]])
+                           - (phi[idx + st[a]] - phi[idx - st[a]]) * i2h[a];
+            FS[a * g.N + idx] = (T)v;
+        }
+    }
+}
+
+// One block: fixed-order sums of the partials, then the scalar logic.
+__global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials, int npart, int nsum, int mode,
+                                                          CgState* st) {
+    if (mode != FIN_INIT && mode != FIN_TRUE && st->done) return;
+    __shared__ double sh[3][256];
+    for (int s = 0; s < nsum; ++s) {
+        double acc = 0.0;
+        for (int q = threadIdx.x; q < npart; q += 256) acc += partials[s * npart + q];
+        sh[s][threadIdx.x] = acc;
+    }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int s = 0; s < nsum; ++s) sh[s][threadIdx.x] += sh[s][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double s1 = sh[0][0];
+    const double s2 = nsum > 1 ? sh[1][0] : 0.0;
+    const double s3 = nsum > 2 ? sh[2][0] : 0.0;
+    st->s1 = s1;
+    st->s2 = s2;
+    st->s3 = s3;
+    if (mode == FIN_INIT) {
+        st->rr0 = s1;
+        st->rr = s1;
+        st->rz = st->jacobi ? s2 : s1;
+        st->bb = s3;
+        st->iters = 0;
+        st->beta = 0.0;
+        st->alpha = 0.0;
+        st->status = KVS_OK;
+        st->done = 0;
+        if (!isfinite(s1) || !isfinite(s3) || !isfinite(st->rz)) {
+            st->status = KVS_EBREAKDOWN;
+            st->done = 1;
+        } else if (s1 == 0.0) {
+            st->done = 1;
+        } else if (st->fixed_iters <= 0 && !(1.0 >= sqrt(st->tol2))) {
+            st->done = 1;  // tol > 1: the initial residual already satisfies the test
+        }
+    } else if (mode == FIN_ALPHA) {
+        st->pAp = s1;
+        if (!(s1 > 0.0) || !isfinite(s1)) {
+            st->status = KVS_EBREAKDOWN;
+            st->done = 1;
+        } else {
+            st->alpha = st->rz / s1;
+        }
+    } else if (mode == FIN_BETA) {
+        st->iters += 1;
+        if (!isfinite(s1) || s1 < 0.0 || !isfinite(s2)) {
+            st->status = KVS_EBREAKDOWN;
+            st->done = 1;
+            return;
+        }
+        const double rz_new = st->jacobi ? s2 : s1;
+        st->beta = rz_new / st->rz;
+        st->rz = rz_new;
+        st->rr = s1;
+        if (st->fixed_iters > 0) {
+            if (st->iters >= st->fixed_iters) st->done = 1;
+        } else if (sqrt(st->rr / st->rr0) < sqrt(st->tol2)) {
+            st->done = 1;
+        } else if (st->iters >= st->max_iter) {
+            st->status = KVS_ENOTCONV;
+            st->done = 1;
+        }
+    } else {  // FIN_TRUE
+        st->relres_true2 = s3 > 0.0 ? s1 / s3 : 0.0;
+    }
+}
+
+CgGeom make_geom(const kvs_grid& gr) {
+    CgGeom g{};
+    g.nx = (int)gr.nx;
+    g.ny = (int)gr.ny;
+    g.nz = (int)gr.nz;
+    g.kchunk = std::min<int>(CKZ, g.nz - 2);
+    g.gx = (g.nx + 63) / 64;
+    g.gy = (g.ny + CBY - 1) / CBY;
+    g.gz = (g.nz - 2 + g.kchunk - 1) / g.kchunk;
+    g.N = (long long)gr.nx * gr.ny * gr.nz;
+    g.ihx2 = 1.0 / (gr.hx * gr.hx);
+    g.ihy2 = 1.0 / (gr.hy * gr.hy);
+    g.ihz2 = 1.0 / (gr.hz * gr.hz);
+    g.i2hx = 1.0 / (2.0 * gr.hx);
+    g.i2hy = 1.0 / (2.0 * gr.hy);
+    g.i2hz = 1.0 / (2.0 * gr.hz);
+    g.dinv = 1.0 / (2.0 * g.ihx2 + 2.0 * g.ihy2 + 2.0 * g.ihz2);
+    return g;
+}
+
+int nblocks(const CgGeom& g) { return g.gx * g.gy * g.gz; }
+
+kvs_status fail(kvs_ctx* c, kvs_status s, const std::string& msg) {
+    c->err = msg;
+    return s;
+}
+
+}  // namespace
+
+int64_t kvs_cg_partials_needed(const kvs_grid& gr) {
+    CgGeom g = make_geom(gr);
+    return nblocks(g);
+}
+
+#define CG_HIP(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(c, KVS_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep) {
+    const CgGeom g = make_geom(c->grid);
+    const int nb = nblocks(g);
+    const dim3 blk(64, CBY);
+    double* part = c->partials;
+    const int npart = (int)c->npart;
+
+    hipEvent_t e0, e1;
+    CG_HIP(hipEventCreate(&e0));
+    CG_HIP(hipEventCreate(&e1));
+    CG_HIP(hipEventRecord(e0, c->stream));
+
+    CgState init{};
+    init.tol2 = o->tol * o->tol;
+    init.max_iter = o->max_iter;
+    init.fixed_iters = o->fixed_iters;
+    init.jacobi = o->precond == KVS_PC_JACOBI ? 1 : 0;
+    *c->cgs_host = init;
+    CG_HIP(hipMemcpyAsync(c->cgs, c->cgs_host, sizeof(CgState), hipMemcpyHostToDevice, c->stream));
+    const bool warm = o->warm_start && c->have_phi;
+    if (!warm) CG_HIP(hipMemsetAsync(c->phi, 0, sizeof(double) * c->N, c->stream));
+
+    hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, c->r, warm ? 1 : 0, part, npart);
+    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 3, (int)FIN_INIT, c->cgs);
+    CG_HIP(hipGetLastError());
+
+    int pi = 0;  // p[pi] holds the current search direction
+    int chunk = 4;
+    long long launched = 0;
+    const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
+    while (true) {
+        for (int m = 0; m < chunk; ++m) {
+            hipLaunchKernelGGL(cg_matvec_kernel, dim3(nb), blk, 0, c->stream, g, c->r, c->p[pi], c->p[1 - pi], c->Ap,
+                               c->cgs, part, npart);
+            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 1, (int)FIN_ALPHA,
+                               c->cgs);
+            hipLaunchKernelGGL(cg_update_kernel, dim3(nb), blk, 0, c->stream, g, c->phi, c->r, c->p[1 - pi], c->Ap,
+                               c->cgs, part, npart);
+            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 2, (int)FIN_BETA,
+                               c->cgs);
+            pi = 1 - pi;
+        }
+        CG_HIP(hipGetLastError());
+        launched += chunk;
+        CG_HIP(hipMemcpyAsync(c->cgs_host, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+        CG_HIP(hipStreamSynchronize(c->stream));
+        if (c->cgs_host->done) break;
+        if (launched > cap) return fail(c, KVS_EDEVICE, "CG driver: iteration cap passed without a stop flag");
+        chunk = std::min(chunk * 2, 64);
+    }
+    // Iterations that were launched after the stop flag returned early, so
+    // the direction buffers flipped once per performed iteration only for the
+    // performed ones; the buffers are rebuilt from r on the next solve.
+
+    hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, part, npart);
+    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 3, (int)FIN_TRUE, c->cgs);
+    const int status = c->cgs_host->status;
+    if (status != KVS_EBREAKDOWN) {
+        if (c->prec == KVS_FP32)
+            hipLaunchKernelGGL(grad_subtract_kernel<float>, dim3(nb), blk, 0, c->stream, g, c->F, c->phi,
+                               static_cast<float*>(c->FS));
+        else
+            hipLaunchKernelGGL(grad_subtract_kernel<double>, dim3(nb), blk, 0, c->stream, g, c->F, c->phi,
+                               static_cast<double*>(c->FS));
+    }
+    CG_HIP(hipGetLastError());
+    CG_HIP(hipEventRecord(e1, c->stream));
+    CG_HIP(hipMemcpyAsync(c->cgs_host, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+    CG_HIP(hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    CG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+
+    const CgState& s = *c->cgs_host;
+    c->have_phi = true;
+    if (s.status != KVS_EBREAKDOWN) c->fs_current = true;
+    if (rep) {
+        rep->iters = s.iters;
+        rep->relres_recursive = s.rr0 > 0 ? std::sqrt(s.rr / s.rr0) : 0.0;
+        rep->relres_true = std::sqrt(s.relres_true2);
+        rep->ms = ms;
+        rep->status = s.status;
+    }
+    if (s.status != KVS_OK)
+        c->err = s.status == KVS_ENOTCONV ? "projection: CG reached max_iter above tolerance"
+                                          : "projection: CG breakdown (p.Ap <= 0 or non-finite inner product)";
+    return (kvs_status)s.status;
+}

@@ -1,0 +1,114 @@
+// Internal declarations of the kvs library (host side + kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kvs.h"
+
+// Device-side control block of one projection solve.  Written only by the
+// single-block finalize kernels; read by every CG kernel (early exit once
+// `done` is set) and copied to the host once per chunk of iterations.
+struct CgState {
+    double s1, s2, s3;      // finalized sums of the last reduction
+    double rr, rr0, rz;     // r.r, r0.r0, r.z
+    double bb;              // ||b||^2
+    double pAp, alpha, beta;
+    double tol2;            // tol^2 (compared with rr / rr0)
+    double relres_true2;    // ||-b - A phi||^2 / ||b||^2
+    long long iters, max_iter, fixed_iters;
+    int done, status, jacobi, pad;
+};
+
+struct kvs_ctx {
+    kvs_grid grid{};
+    int64_t N = 0;
+    int prec = KVS_FP64;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    // sponge
+    int sponge_cells = 0;
+    double sigma_user = -1.0;
+    double sigma_max = 0.0;
+
+    // medium
+    bool have_material = false;
+    bool hetero = false;
+    bool viscous = false;
+    double G0 = 0, rho0 = 0, eta0 = 0;
+    void* G = nullptr;     // [N] T, hetero only
+    void* eta = nullptr;   // [N] T
+    void* rho_t = nullptr; // [N] T: rho
+    void* crho = nullptr;  // [N] T: dt^2/rho
+    double dt_max = 0.0;
+    double dt = 0.0;
+    bool have_dt = false;
+
+    // state: u[b], w[b] each 3N of T, b = cur or 1 - cur
+    void* u[2] = {nullptr, nullptr};
+    void* w[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t step = 0;
+
+    // force and projection
+    double* F = nullptr;  // [3N] double
+    bool have_force = false;
+    void* FS = nullptr;   // [3N] T
+    bool fs_current = false;
+    std::vector<double> env;  // host copy of g[n]
+
+    double* phi = nullptr;
+    double* r = nullptr;
+    double* p[2] = {nullptr, nullptr};
+    double* Ap = nullptr;
+    double* partials = nullptr;  // 3 * npart
+    int64_t npart = 0;
+    CgState* cgs = nullptr;       // device
+    CgState* cgs_host = nullptr;  // pinned host mirror
+    bool have_phi = false;
+
+    // probes: flat cell indices on device, traces [step][probe][ncomp] doubles
+    int64_t* probe_cells = nullptr;
+    int64_t nprobes = 0;
+    int probe_comp = 2;
+    double* traces = nullptr;
+    int64_t trace_cap = 0;    // steps of capacity
+    int64_t trace_steps = 0;  // steps recorded
+
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+
+    // tuning
+    int step_variant = 0;
+};
+
+inline int ncomp_of(int comp) { return comp == 3 ? 3 : 1; }
+
+// ---- launchers (kvs_step.hip) -------------------------------------------
+// One FDTD step from (u[cur], w[cur]) into (u[1-cur], w[1-cur]) with source
+// amplitude gn (0: no force read).  Returns the launch error.
+hipError_t kvs_launch_step(kvs_ctx* c, double gn);
+hipError_t kvs_launch_probe_gather(kvs_ctx* c, const void* u_new, int64_t slot);
+hipError_t kvs_launch_crho(kvs_ctx* c);
+hipError_t kvs_launch_cast_material(kvs_ctx* c, const double* dG, const double* drho, const double* deta);
+hipError_t kvs_launch_cast(kvs_ctx* c, const double* src, void* dst, int64_t n);
+hipError_t kvs_launch_widen(kvs_ctx* c, const void* src, double* dst, int64_t n);
+hipError_t kvs_launch_f32_to_f64(kvs_ctx* c, const float* src, double* dst, int64_t n);
+hipError_t kvs_launch_zero_boundary(kvs_ctx* c, void* field3);
+// stable dt: per-cell bound reduced to its minimum in *out (device double)
+hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho, const double* deta,
+                                double* partial, int64_t npartial, double* out);
+
+// ---- projection (kvs_cg.hip) ---------------------------------------------
+kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep);
+int64_t kvs_cg_partials_needed(const kvs_grid& g);

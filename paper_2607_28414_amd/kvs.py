@@ -1,0 +1,264 @@
+"""ctypes binding of libkvs.so (declared in include/kvs.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Functions keep the C names; a ``kvs_status`` other than KVS_OK
+raises :class:`KvsError` carrying the status and the context's last error.
+There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libkvs.so")
+
+KVS_OK, KVS_EINVAL, KVS_ENOMEM, KVS_EDEVICE, KVS_ENOTCONV, KVS_EBREAKDOWN, KVS_EUNSTABLE, KVS_ESTATE = range(8)
+KVS_FP64, KVS_FP32 = 0, 1
+KVS_PC_NONE, KVS_PC_JACOBI, KVS_PC_UNET = 0, 1, 2
+STATUS_NAMES = {0: "KVS_OK", 1: "KVS_EINVAL", 2: "KVS_ENOMEM", 3: "KVS_EDEVICE", 4: "KVS_ENOTCONV",
+                5: "KVS_EBREAKDOWN", 6: "KVS_EUNSTABLE", 7: "KVS_ESTATE"}
+
+
+class KvsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class kvs_grid(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double)]
+
+
+class kvs_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("sponge_cells", C.c_int32), ("sponge_sigma_max", C.c_double),
+                ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class kvs_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precond", C.c_int32),
+                ("fixed_iters", C.c_int64), ("warm_start", C.c_int32)]
+
+
+class kvs_solve_report(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("relres_recursive", C.c_double), ("relres_true", C.c_double),
+                ("ms", C.c_double), ("status", C.c_int32)]
+
+
+_lib = None
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I64 = C.POINTER(C.c_int64)
+
+# name -> (argtypes, restype)
+SIGNATURES = {
+    "kvs_create": ([C.POINTER(kvs_grid), C.POINTER(kvs_opts), C.POINTER(C.c_void_p)], C.c_int),
+    "kvs_destroy": ([_P], None),
+    "kvs_status_string": ([C.c_int], C.c_char_p),
+    "kvs_last_error": ([_P], C.c_char_p),
+    "kvs_synchronize": ([_P], C.c_int),
+    "kvs_stream": ([_P], C.c_void_p),
+    "kvs_set_material": ([_P, _D, _D, _D], C.c_int),
+    "kvs_set_material_uniform": ([_P, C.c_double, C.c_double, C.c_double], C.c_int),
+    "kvs_stable_dt": ([_P, _D], C.c_int),
+    "kvs_sponge_sigma_max": ([_P, _D], C.c_int),
+    "kvs_set_dt": ([_P, C.c_double], C.c_int),
+    "kvs_set_force": ([_P, _D], C.c_int),
+    "kvs_set_force_device": ([_P, C.c_void_p, C.c_int32], C.c_int),
+    "kvs_set_envelope": ([_P, _D, C.c_int64], C.c_int),
+    "kvs_project": ([_P, C.POINTER(kvs_solve_opts), C.POINTER(kvs_solve_report)], C.c_int),
+    "kvs_set_projected_force": ([_P, _D], C.c_int),
+    "kvs_get_projected_force": ([_P, _D], C.c_int),
+    "kvs_get_phi": ([_P, _D], C.c_int),
+    "kvs_set_probes": ([_P, _I64, C.c_int64, C.c_int32], C.c_int),
+    "kvs_step": ([_P, C.c_int64], C.c_int),
+    "kvs_trace_count": ([_P, _I64], C.c_int),
+    "kvs_read_traces": ([_P, _D, C.c_int64, _I64], C.c_int),
+    "kvs_clear_traces": ([_P], C.c_int),
+    "kvs_get_state": ([_P, _D, _D, _I64], C.c_int),
+    "kvs_set_state": ([_P, _D, _D, C.c_int64], C.c_int),
+    "kvs_reset_state": ([_P], C.c_int),
+    "kvs_enable_kernel_timing": ([_P, C.c_int32], C.c_int),
+    "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
+}
+
+
+def lib():
+    """Load libkvs.so from the package directory; raise when it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != KVS_OK:
+        msg = lib().kvs_last_error(ctx)
+        raise KvsError(status, msg.decode() if msg else "")
+    return status
+
+
+def _dptr(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---- thin wrappers with the C names ------------------------------------
+
+def kvs_create(grid, precision=KVS_FP64, sponge_cells=0, sponge_sigma_max=-1.0, device=0, stream=None):
+    nx, ny, nz, hx, hy, hz = grid
+    g = kvs_grid(int(nx), int(ny), int(nz), float(hx), float(hy), float(hz))
+    o = kvs_opts(int(precision), int(sponge_cells), float(sponge_sigma_max), int(device), stream or None)
+    out = C.c_void_p()
+    _check(lib().kvs_create(C.byref(g), C.byref(o), C.byref(out)))
+    return out
+
+
+def kvs_destroy(ctx):
+    lib().kvs_destroy(ctx)
+
+
+def kvs_synchronize(ctx):
+    _check(lib().kvs_synchronize(ctx), ctx)
+
+
+def kvs_stream(ctx):
+    return lib().kvs_stream(ctx)
+
+
+def kvs_set_material(ctx, G, rho, eta):
+    G, rho, eta = _f64(G), _f64(rho), _f64(eta)
+    _check(lib().kvs_set_material(ctx, _dptr(G), _dptr(rho), _dptr(eta)), ctx)
+
+
+def kvs_set_material_uniform(ctx, G, rho, eta):
+    _check(lib().kvs_set_material_uniform(ctx, float(G), float(rho), float(eta)), ctx)
+
+
+def kvs_stable_dt(ctx):
+    v = C.c_double()
+    _check(lib().kvs_stable_dt(ctx, C.byref(v)), ctx)
+    return v.value
+
+
+def kvs_sponge_sigma_max(ctx):
+    v = C.c_double()
+    _check(lib().kvs_sponge_sigma_max(ctx, C.byref(v)), ctx)
+    return v.value
+
+
+def kvs_set_dt(ctx, dt):
+    _check(lib().kvs_set_dt(ctx, float(dt)), ctx)
+
+
+def kvs_set_force(ctx, F):
+    F = _f64(F)
+    _check(lib().kvs_set_force(ctx, _dptr(F)), ctx)
+
+
+def kvs_set_force_device(ctx, ptr, dtype):
+    _check(lib().kvs_set_force_device(ctx, C.c_void_p(ptr), int(dtype)), ctx)
+
+
+def kvs_set_envelope(ctx, g):
+    g = _f64(g if g is not None else [])
+    _check(lib().kvs_set_envelope(ctx, _dptr(g) if len(g) else None, len(g)), ctx)
+
+
+def kvs_project(ctx, tol=1e-8, max_iter=10000, precond=KVS_PC_JACOBI, fixed_iters=0, warm_start=False,
+                raise_on_status=True):
+    o = kvs_solve_opts(float(tol), int(max_iter), int(precond), int(fixed_iters), int(bool(warm_start)))
+    rep = kvs_solve_report()
+    st = lib().kvs_project(ctx, C.byref(o), C.byref(rep))
+    if raise_on_status:
+        _check(st, ctx)
+    return dict(iters=rep.iters, relres_recursive=rep.relres_recursive, relres_true=rep.relres_true,
+                ms=rep.ms, status=rep.status, return_status=st)
+
+
+def kvs_set_projected_force(ctx, FS):
+    FS = _f64(FS)
+    _check(lib().kvs_set_projected_force(ctx, _dptr(FS)), ctx)
+
+
+def kvs_get_projected_force(ctx, shape):
+    out = np.empty((3,) + tuple(shape))
+    _check(lib().kvs_get_projected_force(ctx, _dptr(out)), ctx)
+    return out
+
+
+def kvs_get_phi(ctx, shape):
+    out = np.empty(tuple(shape))
+    _check(lib().kvs_get_phi(ctx, _dptr(out)), ctx)
+    return out
+
+
+def kvs_set_probes(ctx, ijk, comp):
+    a = np.ascontiguousarray(np.asarray(ijk, dtype=np.int64).reshape(-1, 3))
+    _check(lib().kvs_set_probes(ctx, a.ctypes.data_as(_I64) if len(a) else None, len(a), int(comp)), ctx)
+
+
+def kvs_step(ctx, nsteps):
+    _check(lib().kvs_step(ctx, int(nsteps)), ctx)
+
+
+def kvs_trace_count(ctx):
+    v = C.c_int64()
+    _check(lib().kvs_trace_count(ctx, C.byref(v)), ctx)
+    return v.value
+
+
+def kvs_read_traces(ctx, nprobes, ncomp):
+    n = kvs_trace_count(ctx)
+    out = np.empty((n, nprobes, ncomp))
+    nw = C.c_int64()
+    _check(lib().kvs_read_traces(ctx, _dptr(out), out.size, C.byref(nw)), ctx)
+    assert nw.value == out.size
+    return out
+
+
+def kvs_clear_traces(ctx):
+    _check(lib().kvs_clear_traces(ctx), ctx)
+
+
+def kvs_get_state(ctx, shape):
+    u = np.empty((3,) + tuple(shape))
+    w = np.empty((3,) + tuple(shape))
+    step = C.c_int64()
+    _check(lib().kvs_get_state(ctx, _dptr(u), _dptr(w), C.byref(step)), ctx)
+    return u, w, step.value
+
+
+def kvs_set_state(ctx, u, w, step):
+    u, w = _f64(u), _f64(w)
+    _check(lib().kvs_set_state(ctx, _dptr(u), _dptr(w), int(step)), ctx)
+
+
+def kvs_reset_state(ctx):
+    _check(lib().kvs_reset_state(ctx), ctx)
+
+
+def kvs_enable_kernel_timing(ctx, on):
+    _check(lib().kvs_enable_kernel_timing(ctx, int(bool(on))), ctx)
+
+
+def kvs_kernel_time(ctx):
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(lib().kvs_kernel_time(ctx, C.byref(ms), C.byref(n)), ctx)
+    return ms.value, n.value

@@ -1,0 +1,303 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: FP64 mode to 1e-12 relative, FP32 displacement traces to 2e-5
+relative L2 (FP32 state, FP64 projection).  CG parity runs pin the
+iteration count to the oracle's own count at the tolerance, so both sides
+perform the same number of updates.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.analysis import rel_l2
+from workloads import cfg1_homogeneous_fp64, cfg2_inclusions_fp32, gaussian_push, spherical_inclusions, x_line_probes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kvs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2607_28414_amd import kvs as k
+    k.lib()
+    return k
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_gpu(kvs, grid, G, rho, eta, dt, nsteps, F=None, env=None, probes=None, comp=2, precision=0,
+            sponge_cells=0, sigma_max=0.0, tol=1e-10, fixed_iters=0, precond=1, FS=None):
+    ctx = kvs.kvs_create(grid, precision=precision, sponge_cells=sponge_cells, sponge_sigma_max=sigma_max)
+    out = {}
+    try:
+        if np.isscalar(G):
+            kvs.kvs_set_material_uniform(ctx, G, rho, eta)
+        else:
+            kvs.kvs_set_material(ctx, G, rho, eta)
+        out["dt_max"] = kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        shp = (grid[2], grid[1], grid[0])
+        if F is not None:
+            kvs.kvs_set_force(ctx, F)
+            out["rep"] = kvs.kvs_project(ctx, tol=tol, fixed_iters=fixed_iters, precond=precond)
+            out["FS"] = kvs.kvs_get_projected_force(ctx, shp)
+            out["phi"] = kvs.kvs_get_phi(ctx, shp)
+        if FS is not None:
+            kvs.kvs_set_projected_force(ctx, FS)
+        if env is not None:
+            kvs.kvs_set_envelope(ctx, env)
+        if probes is not None:
+            kvs.kvs_set_probes(ctx, probes, comp)
+        kvs.kvs_step(ctx, nsteps)
+        if probes is not None:
+            out["traces"] = kvs.kvs_read_traces(ctx, len(probes), 3 if comp == 3 else 1)
+        out["u"], out["w"], out["step"] = kvs.kvs_get_state(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    return out
+
+
+def test_cfg1_homogeneous_fp64_end_to_end(kvs):
+    """48^3 homogeneous FP64 workload: Jacobi-PCG projection to 1e-10, 8-cell
+    sponge, 200 steps, u_z on the lateral line; everything to 1e-12."""
+    w = cfg1_homogeneous_fp64()
+    say("case cfg1 48^3 fp64")
+    smax = oracle.default_sigma_max(w.grid, w.G, w.rho, w.sponge_cells)
+    FS_o, phi_o, rep_o = oracle.project(w.grid, w.F, tol=w.tol, jacobi=True)
+    assert rep_o["status"] == 0
+    _, _, tr_o = oracle.run(w.grid, w.G, w.rho, w.eta, w.dt, w.nsteps, FS=FS_o, env=w.env, probes=w.probes,
+                            comp=w.comp, sponge_cells=w.sponge_cells, sigma_max=smax)
+    g = run_gpu(kvs, w.grid, w.G, w.rho, w.eta, w.dt, w.nsteps, F=w.F, env=w.env, probes=w.probes, comp=w.comp,
+                precision=kvs.KVS_FP64, sponge_cells=w.sponge_cells, sigma_max=smax, tol=w.tol,
+                fixed_iters=rep_o["iters"])
+    assert g["rep"]["iters"] == rep_o["iters"]
+    assert rel_l2(g["phi"], phi_o) < 1e-12
+    assert rel_l2(g["FS"], FS_o) < 1e-12
+    assert rel_l2(g["traces"], tr_o) < 1e-12
+    assert g["rep"]["relres_true"] == pytest.approx(rep_o["relres_true"], rel=1e-6)
+    assert g["dt_max"] == pytest.approx(oracle.stable_dt(w.grid, w.G, w.rho, w.eta), rel=1e-14)
+
+
+def test_tolerance_stop_matches_oracle_count(kvs):
+    """Without pinning, the device-side stop test lands on the oracle's
+    iteration count (or one off, from rounding of r.r at the threshold)."""
+    w = cfg1_homogeneous_fp64()
+    say("case tolerance stop 48^3")
+    _, _, rep_o = oracle.project(w.grid, w.F, tol=w.tol, jacobi=True)
+    ctx = kvs.kvs_create(w.grid)
+    try:
+        kvs.kvs_set_force(ctx, w.F)
+        rep = kvs.kvs_project(ctx, tol=w.tol, precond=kvs.KVS_PC_JACOBI)
+        rep_cg = kvs.kvs_project(ctx, tol=w.tol, precond=kvs.KVS_PC_NONE)
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert abs(rep["iters"] - rep_o["iters"]) <= 1
+    assert abs(rep_cg["iters"] - rep_o["iters"]) <= 1
+    assert rep["relres_recursive"] < w.tol and rep["relres_true"] < 10 * w.tol
+
+
+def hetero_case(shape, seed, n_incl=5):
+    nx, ny, nz = shape
+    h = 0.25e-3
+    grid = (nx, ny, nz, h, h * 1.1, h * 0.9)
+    rng = np.random.default_rng(seed)
+    G, rho, eta, _ = spherical_inclusions(grid, rng, n_incl, (2e3, 1000.0, 0.5), (0.8e-3, 2e-3),
+                                          (1e3, 1e4), (1000.0, 1100.0), (0.0, 1.5), 3)
+    F = gaussian_push(grid, 0.8e-3, 2e-3, 1e4) + 50.0 * rng.standard_normal((3, nz, ny, nx))
+    return grid, G, rho, eta, F
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 41), (70, 9, 35), (130, 6, 5), (3, 3, 3), (64, 8, 34)])
+def test_hetero_viscous_fp64_parity_ragged_tiles(kvs, shape):
+    """Heterogeneous G, rho, eta, sponge and force on grids whose sizes are
+    not multiples of the 64 x 4 x 32 tiles (and the 1-cell 3^3 grid)."""
+    say(f"case hetero fp64 {shape}")
+    grid, G, rho, eta, F = hetero_case(shape, 17)
+    L = 3 if min(shape) > 3 else 1
+    smax = oracle.default_sigma_max(grid, G, rho, L)
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    env = np.array([1.0, 0.5, 0.25, 1.0, 0.0, 2.0])
+    probes = np.array([[i, shape[1] // 2, shape[2] // 2] for i in range(shape[0])])
+    FS_o, phi_o, rep_o = oracle.project(grid, F, tol=1e-11)
+    _, _, tr_o = oracle.run(grid, G, rho, eta, dt, 80, FS=FS_o, env=env, probes=probes, comp=3,
+                            sponge_cells=L, sigma_max=smax)
+    g = run_gpu(kvs, grid, G, rho, eta, dt, 80, F=F, env=env, probes=probes, comp=3, precision=kvs.KVS_FP64,
+                sponge_cells=L, sigma_max=smax, fixed_iters=max(rep_o["iters"], 1), precond=kvs.KVS_PC_NONE)
+    assert g["dt_max"] == pytest.approx(oracle.stable_dt(grid, G, rho, eta), rel=1e-13)
+    if rep_o["iters"] > 0:
+        assert rel_l2(g["phi"], phi_o) < 1e-12
+    assert rel_l2(g["FS"], FS_o) < 1e-12
+    assert rel_l2(g["traces"], tr_o) < 1e-12
+    assert not g["u"][:, 0].any() and not g["u"][:, :, :, -1].any() and not g["w"][:, :, 0].any()
+
+
+def test_fp32_heterogeneous_traces_within_2e5(kvs):
+    """Inclusion workload physics at 64^3 (same h, push widths, dt rule and
+    tolerance as the 256^3 case): FP32 state with FP64 projection against
+    the FP64 oracle, 1500 steps."""
+    w = cfg2_inclusions_fp32(n=64)
+    say("case fp32 inclusions 64^3")
+    dt = w.dt_factor * oracle.stable_dt(w.grid, w.G, w.rho, w.eta)
+    env = w.envelope_for(dt)
+    smax = oracle.default_sigma_max(w.grid, w.G, w.rho, w.sponge_cells)
+    FS_o, _, rep_o = oracle.project(w.grid, w.F, tol=w.tol, jacobi=True)
+    nsteps = 1500
+    _, _, tr_o = oracle.run(w.grid, w.G, w.rho, w.eta, dt, nsteps, FS=FS_o, env=env, probes=w.probes, comp=2,
+                            sponge_cells=w.sponge_cells, sigma_max=smax)
+    g = run_gpu(kvs, w.grid, w.G, w.rho, w.eta, dt, nsteps, F=w.F, env=env, probes=w.probes, comp=2,
+                precision=kvs.KVS_FP32, sponge_cells=w.sponge_cells, sigma_max=smax, tol=w.tol,
+                fixed_iters=rep_o["iters"])
+    err = rel_l2(g["traces"], tr_o)
+    say(f"fp32 trace rel L2 {err:.3e}")
+    assert err <= 2e-5
+    assert rel_l2(g["FS"], FS_o) < 1e-6  # FS stored in float
+
+
+def test_fp32_homogeneous_viscous_traces_within_2e5(kvs):
+    h = 0.25e-3
+    grid = (72, 66, 60, h, h, h)
+    G, rho, eta = 5e3, 1000.0, 1.0
+    say("case fp32 homogeneous viscous 72x66x60")
+    F = gaussian_push(grid, 1e-3, 3e-3, 1e4)
+    dt = 0.4 * oracle.stable_dt(grid, G, rho, eta)
+    env = np.ones(int(round(100e-6 / dt)))
+    smax = oracle.default_sigma_max(grid, G, rho, 8)
+    probes = x_line_probes(grid)
+    FS_o, _, rep_o = oracle.project(grid, F, tol=1e-8, jacobi=True)
+    _, _, tr_o = oracle.run(grid, G, rho, eta, dt, 1200, FS=FS_o, env=env, probes=probes, comp=2,
+                            sponge_cells=8, sigma_max=smax)
+    g = run_gpu(kvs, grid, G, rho, eta, dt, 1200, F=F, env=env, probes=probes, precision=kvs.KVS_FP32,
+                sponge_cells=8, sigma_max=smax, tol=1e-8, fixed_iters=rep_o["iters"])
+    assert rel_l2(g["traces"], tr_o) <= 2e-5
+
+
+def test_state_roundtrip_resume_is_bitwise(kvs):
+    """Stopping, reading the state and resuming from it in a fresh context
+    reproduces an uninterrupted run exactly (FP64)."""
+    say("case resume")
+    grid, G, rho, eta, F = hetero_case((40, 24, 30), 5)
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    FS_o, _, _ = oracle.project(grid, F, tol=1e-10)
+    env = np.ones(10)
+    shp = (30, 24, 40)
+    a = kvs.kvs_create(grid, sponge_cells=2, sponge_sigma_max=1000.0)
+    b = kvs.kvs_create(grid, sponge_cells=2, sponge_sigma_max=1000.0)
+    try:
+        for ctx in (a, b):
+            kvs.kvs_set_material(ctx, G, rho, eta)
+            kvs.kvs_set_dt(ctx, dt)
+            kvs.kvs_set_projected_force(ctx, FS_o)
+            kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_step(a, 25)
+        u, w, step = kvs.kvs_get_state(a, shp)
+        assert step == 25
+        kvs.kvs_step(a, 15)
+        kvs.kvs_set_state(b, u, w, step)
+        kvs.kvs_step(b, 15)
+        ua, wa, _ = kvs.kvs_get_state(a, shp)
+        ub, wb, sb = kvs.kvs_get_state(b, shp)
+    finally:
+        kvs.kvs_destroy(a)
+        kvs.kvs_destroy(b)
+    assert sb == 40
+    assert np.array_equal(ua, ub) and np.array_equal(wa, wb)
+
+
+def test_error_paths(kvs):
+    say("case error paths")
+    grid = (16, 16, 16, 0.5e-3, 0.5e-3, 0.5e-3)
+    shp = (16, 16, 16)
+    ctx = kvs.kvs_create(grid)
+    try:
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_step(ctx, 1)
+        assert e.value.status == kvs.KVS_ESTATE
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_set_material_uniform(ctx, -1.0, 1000.0, 0.0)
+        assert e.value.status == kvs.KVS_EINVAL
+        kvs.kvs_set_material_uniform(ctx, 3e3, 1000.0, 0.2)
+        dtm = kvs.kvs_stable_dt(ctx)
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_set_dt(ctx, 1.01 * dtm)
+        assert e.value.status == kvs.KVS_EUNSTABLE
+        kvs.kvs_set_dt(ctx, 0.5 * dtm)
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_project(ctx)
+        assert e.value.status == kvs.KVS_ESTATE
+        kvs.kvs_set_envelope(ctx, [1.0])
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_step(ctx, 1)  # envelope on, no current projection
+        assert e.value.status == kvs.KVS_ESTATE
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_set_probes(ctx, [[16, 0, 0]], 0)
+        assert e.value.status == kvs.KVS_EINVAL
+        # zero force: no iteration, FS = 0
+        kvs.kvs_set_force(ctx, np.zeros((3,) + shp))
+        rep = kvs.kvs_project(ctx, tol=1e-8)
+        assert rep["iters"] == 0 and not kvs.kvs_get_projected_force(ctx, shp).any()
+        # max_iter reached -> not converged, FS still produced
+        F = gaussian_push(grid, 1e-3, 2e-3, 1e4)
+        kvs.kvs_set_force(ctx, F)
+        rep = kvs.kvs_project(ctx, tol=1e-12, max_iter=2, raise_on_status=False)
+        assert rep["status"] == kvs.KVS_ENOTCONV and rep["iters"] == 2
+        kvs.kvs_step(ctx, 2)  # FS is current after a not-converged solve
+        # non-finite force -> breakdown
+        bad = F.copy()
+        bad[2, 8, 8, 8] = np.nan
+        kvs.kvs_set_force(ctx, bad)
+        rep = kvs.kvs_project(ctx, tol=1e-8, raise_on_status=False)
+        assert rep["status"] == kvs.KVS_EBREAKDOWN
+    finally:
+        kvs.kvs_destroy(ctx)
+
+
+def test_cfg2_full_size_sampled_parity(kvs):
+    """256^3 inclusion workload in the benchmark's launch configuration:
+    projection judged by the FP64 true residual and by the oracle's
+    gradient subtraction on the GPU's phi; the step judged on 4096 sampled
+    cells by the oracle's one-step update from the GPU state."""
+    w = cfg2_inclusions_fp32(n=256)
+    say("case cfg2 256^3 sampled")
+    dt_o = w.dt_factor * oracle.stable_dt(w.grid, w.G, w.rho, w.eta)
+    smax = oracle.default_sigma_max(w.grid, w.G, w.rho, w.sponge_cells)
+    env = w.envelope_for(dt_o)
+    shp = w.shape
+    ctx = kvs.kvs_create(w.grid, precision=kvs.KVS_FP32, sponge_cells=w.sponge_cells, sponge_sigma_max=-1.0)
+    try:
+        kvs.kvs_set_material(ctx, w.G, w.rho, w.eta)
+        assert kvs.kvs_stable_dt(ctx) * w.dt_factor == pytest.approx(dt_o, rel=1e-13)
+        assert kvs.kvs_sponge_sigma_max(ctx) == pytest.approx(smax, rel=1e-13)
+        kvs.kvs_set_dt(ctx, dt_o)
+        kvs.kvs_set_force(ctx, w.F)
+        kvs.kvs_set_envelope(ctx, env)
+        rep = kvs.kvs_project(ctx, tol=w.tol, precond=kvs.KVS_PC_JACOBI)
+        say(f"projection: {rep}")
+        assert rep["status"] == 0 and rep["relres_true"] < 1e-8 * 1.5
+        phi = kvs.kvs_get_phi(ctx, shp)
+        b = oracle.divergence(w.grid, w.F)
+        assert oracle.true_relres(w.grid, b, phi) == pytest.approx(rep["relres_true"], rel=1e-6)
+        FS_g = kvs.kvs_get_projected_force(ctx, shp)
+        FS_ref = oracle.grad_subtract(w.grid, w.F, phi)
+        assert rel_l2(FS_g, FS_ref) < 1e-7
+        kvs.kvs_step(ctx, 30)  # through part of the push
+        u0, w0, s0 = kvs.kvs_get_state(ctx, shp)
+        kvs.kvs_step(ctx, 1)
+        u1, w1, s1 = kvs.kvs_get_state(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    rng = np.random.default_rng(99)
+    n = 256
+    ii = rng.integers(1, n - 1, size=(4096, 3))
+    ii[:2048] = np.column_stack([rng.integers(1, n - 1, 2048), np.full(2048, n // 2), rng.integers(100, 156, 2048)])
+    cells = ii[:, 0] + n * (ii[:, 1] + n * ii[:, 2])
+    gn = env[s0] if s0 < len(env) else 0.0
+    uo, wo = oracle.step_cells(w.grid, w.G, w.rho, w.eta, dt_o, u0, w0, cells, FS=FS_g, gn=gn,
+                               sponge_cells=w.sponge_cells, sigma_max=smax)
+    ug = u1.reshape(3, -1)[:, cells].T
+    wg = w1.reshape(3, -1)[:, cells].T
+    assert np.max(np.abs(wg - wo)) <= 1e-5 * np.max(np.abs(w1))
+    assert np.max(np.abs(ug - uo)) <= 1e-6 * np.max(np.abs(u1))

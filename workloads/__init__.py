@@ -115,10 +115,12 @@ def spherical_inclusions(grid, rng, n_incl, background, radius_range, G_range, r
     eta = np.full((nz, ny, nx), float(background[2]))
     x, y, z = coords(nx, hx), coords(ny, hy), coords(nz, hz)
     spheres = []
+    def centre(n):
+        m = min(margin_cells, (n - 1) / 2.0)  # small grids: the box shrinks to the middle
+        return rng.uniform(m, n - 1 - m)
+
     for _ in range(n_incl):
-        ci = rng.uniform(margin_cells, nx - 1 - margin_cells)
-        cj = rng.uniform(margin_cells, ny - 1 - margin_cells)
-        ck = rng.uniform(margin_cells, nz - 1 - margin_cells)
+        ci, cj, ck = centre(nx), centre(ny), centre(nz)
         c = ((ci - nx // 2) * hx, (cj - ny // 2) * hy, (ck - nz // 2) * hz)
         r = rng.uniform(*radius_range)
         g_, r_, e_ = rng.uniform(*G_range), rng.uniform(*rho_range), rng.uniform(*eta_range)
