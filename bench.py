@@ -91,6 +91,8 @@ def main():
         kvs.kvs_set_envelope(ctx, env)
         kvs.kvs_set_probes(ctx, w.probes, w.comp)
         F_dev = torch.from_numpy(np.ascontiguousarray(w.F)).to("cuda")
+        variant, variant_ms = kvs.kvs_autotune_step(ctx, 20)
+        log(f"bench: step-kernel variant {variant} ({', '.join(f'{m * 1e3:.1f}' for m in variant_ms)} us)")
         torch.cuda.synchronize()
         nsteps = w.nsteps
         cells = w.interior_cells
@@ -163,6 +165,7 @@ def main():
             "algorithmic_bytes_per_cell_update": "60 (+12 on push steps)",
             "kernel_ms_avg": k_ms / max(k_launches, 1),
             "launches": k_launches,
+            "variant": variant,
         },
         "fdtd_kernel_gcells": args.steps * nsteps * cells / (k_ms * 1e-3) / 1e9,
         "projection": {"precond": "jacobi", "tol": w.tol, "iters": rep["iters"],

@@ -200,6 +200,26 @@ kvs_status kvs_reset_state(kvs_ctx* ctx);
 kvs_status kvs_enable_kernel_timing(kvs_ctx* ctx, int32_t on);
 kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* launches);
 
+/* ---- tuning --------------------------------------------------------------- */
+
+/* Number of FDTD step-kernel variants (tile rows x cells per lane). */
+int32_t kvs_num_step_variants(void);
+/* Use variant v (0 <= v < kvs_num_step_variants()) for kvs_step.  Every
+ * variant computes the same update; they differ in tile shape only. */
+kvs_status kvs_set_step_variant(kvs_ctx* ctx, int32_t v);
+/* Full step-kernel tuning: variant v, z planes per block zchunk (0 = split
+ * z so that the blocks fill whole rounds of resident blocks), remap != 0
+ * issues tiles XCD by XCD in contiguous ranges (y-adjacent tiles share L2). */
+kvs_status kvs_set_step_tuning(kvs_ctx* ctx, int32_t v, int32_t zchunk, int32_t remap);
+/* Time every variant on this context's grid, precision and medium, each with
+ * the automatic z split and with 32-plane z segments (trial_steps >= 1
+ * launches each, after one untimed launch), and keep the fastest.
+ * ms_per_launch[v] is the better of the two for variant v.  The state is not advanced: trial launches only write the
+ * buffers the next real step overwrites.  Needs material and dt.  chosen and
+ * ms_per_launch (cap entries, one per variant) may be NULL. */
+kvs_status kvs_autotune_step(kvs_ctx* ctx, int32_t trial_steps, int32_t* chosen, double* ms_per_launch,
+                             int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

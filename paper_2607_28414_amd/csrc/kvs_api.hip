@@ -638,4 +638,75 @@ kvs_status kvs_kernel_time(kvs_ctx* c, double* ms_total, int64_t* launches) {
     return KVS_OK;
 }
 
+int32_t kvs_num_step_variants(void) { return kvs_step_variant_count(); }
+
+kvs_status kvs_set_step_variant(kvs_ctx* c, int32_t v) {
+    if (!c) return KVS_EINVAL;
+    if (v < 0 || v >= kvs_step_variant_count()) return fail(c, KVS_EINVAL, "no such step variant");
+    c->step_variant = v;
+    return KVS_OK;
+}
+
+kvs_status kvs_set_step_tuning(kvs_ctx* c, int32_t v, int32_t zchunk, int32_t remap) {
+    if (!c) return KVS_EINVAL;
+    if (v < 0 || v >= kvs_step_variant_count()) return fail(c, KVS_EINVAL, "no such step variant");
+    if (zchunk < 0) return fail(c, KVS_EINVAL, "zchunk < 0");
+    c->step_variant = v;
+    c->step_zchunk = zchunk;
+    c->step_remap = remap != 0;
+    return KVS_OK;
+}
+
+kvs_status kvs_autotune_step(kvs_ctx* c, int32_t trial_steps, int32_t* chosen, double* ms_per_launch,
+                             int32_t cap) {
+    kvs_status s = need_material(c);
+    if (s != KVS_OK) return s;
+    if (!c->have_dt) return fail(c, KVS_ESTATE, "no time step set");
+    if (trial_steps < 1) return fail(c, KVS_EINVAL, "trial_steps < 1");
+    API_HIP(c, hipSetDevice(c->device));
+    hipEvent_t e0, e1;
+    API_HIP(c, hipEventCreate(&e0));
+    API_HIP(c, hipEventCreate(&e1));
+    const int nv = kvs_step_variant_count();
+    const int zchunks[2] = {0, 32};  // auto split, and 32-plane segments
+    int best = 0, best_z = 0;
+    double best_ms = 1e300;
+    const int saved_z = c->step_zchunk;
+    for (int v = 0; v < nv; ++v) {
+        double v_best = 1e300;
+        for (int zi = 0; zi < 2; ++zi) {
+            c->step_zchunk = zchunks[zi];
+            // warm-up launch, then timed launches; cur is not flipped, so every
+            // launch recomputes the same next state from the same current state
+            hipError_t e = kvs_launch_step_variant(c, 0.0, v);
+            if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+            for (int q = 0; q < trial_steps && e == hipSuccess; ++q) e = kvs_launch_step_variant(c, 0.0, v);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                c->step_zchunk = saved_z;
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return fail(c, KVS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            }
+            const double per = ms / trial_steps;
+            v_best = std::min(v_best, per);
+            if (per < best_ms) {
+                best_ms = per;
+                best = v;
+                best_z = zchunks[zi];
+            }
+        }
+        if (ms_per_launch && v < cap) ms_per_launch[v] = v_best;
+    }
+    c->step_zchunk = best_z;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->step_variant = best;
+    if (chosen) *chosen = best;
+    return KVS_OK;
+}
+
 }  // extern "C"

@@ -88,8 +88,11 @@ struct kvs_ctx {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
 
-    // tuning
+    // tuning of the step kernel: shape variant, z planes per block (0: fill
+    // whole rounds of resident blocks), XCD-contiguous tile order
     int step_variant = 0;
+    int step_zchunk = 0;
+    int step_remap = 1;
 };
 
 inline int ncomp_of(int comp) { return comp == 3 ? 3 : 1; }
@@ -98,6 +101,9 @@ inline int ncomp_of(int comp) { return comp == 3 ? 3 : 1; }
 // One FDTD step from (u[cur], w[cur]) into (u[1-cur], w[1-cur]) with source
 // amplitude gn (0: no force read).  Returns the launch error.
 hipError_t kvs_launch_step(kvs_ctx* c, double gn);
+hipError_t kvs_launch_step_variant(kvs_ctx* c, double gn, int variant);
+int kvs_step_variant_count();
+void kvs_step_variant_shape(int variant, int* by, int* vec);
 hipError_t kvs_launch_probe_gather(kvs_ctx* c, const void* u_new, int64_t slot);
 hipError_t kvs_launch_crho(kvs_ctx* c);
 hipError_t kvs_launch_cast_material(kvs_ctx* c, const double* dG, const double* drho, const double* deta);

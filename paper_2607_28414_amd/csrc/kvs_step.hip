@@ -43,6 +43,7 @@ struct StepArgs {
     T inv_dt;
     T gn;
     T half_dt_smax;  // sigma_max * dt / 2
+    int remap;       // 1: XCD-contiguous tile order
 };
 
 template <typename T>
@@ -57,20 +58,18 @@ __device__ __forceinline__ double harm<double>(double a, double b) {
 }
 
 template <typename T>
-__device__ __forceinline__ T recip(T x);
-template <>
-__device__ __forceinline__ float recip<float>(float x) {
-    return 1.0f / x;
-}
-template <>
-__device__ __forceinline__ double recip<double>(double x) {
-    return 1.0 / x;
-}
-
-template <typename T>
 __device__ __forceinline__ T ramp(int idx, int n, int L, T invL) {
     const int d = min(idx, n - 1 - idx);
     return d < L ? T(L - d) * invL : T(0);
+}
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also fences
+// global memory, which makes every wave drain its outstanding global loads
+// (the plane-ahead prefetch) at each barrier; the stencil only shares LDS.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Tiles are numbered bx fastest, then by, then bz.  Hardware hands block b to
@@ -82,29 +81,152 @@ __device__ __forceinline__ int tile_of(int b, int B) {
     return xcd * per + min(xcd, rem) + pos;
 }
 
-template <typename T, bool HET, bool VISC, bool FORCE, int BY>
-__global__ __launch_bounds__(64 * BY) void step_kernel(const StepArgs<T> a) {
-    static_assert(BY >= 2, "tile needs at least two rows");
+template <typename T>
+__device__ __forceinline__ T rcp_fast(T x);
+template <>
+__device__ __forceinline__ float rcp_fast<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double rcp_fast<double>(double x) {
+    return 1.0 / x;
+}
+
+// Vector of VEC consecutive x cells held by one lane.
+template <typename T, int V>
+struct VecT {
+    typedef T type __attribute__((ext_vector_type(V)));
+};
+template <typename T>
+struct VecT<T, 1> {
+    typedef T type;
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void vload(const T* p, T (&o)[V]) {
+    if constexpr (V == 1) {
+        o[0] = *p;
+    } else {
+        const typename VecT<T, V>::type x = *reinterpret_cast<const typename VecT<T, V>::type*>(p);
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = x[v];
+    }
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vload_nt(const T* p, T (&o)[V]) {
+    if constexpr (V == 1) {
+        o[0] = __builtin_nontemporal_load(p);
+    } else {
+        const typename VecT<T, V>::type x =
+            __builtin_nontemporal_load(reinterpret_cast<const typename VecT<T, V>::type*>(p));
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = x[v];
+    }
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vstore_nt(T* p, const T (&a)[V]) {
+    if constexpr (V == 1) {
+        __builtin_nontemporal_store(a[0], p);
+    } else {
+        typename VecT<T, V>::type x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = a[v];
+        __builtin_nontemporal_store(x, reinterpret_cast<typename VecT<T, V>::type*>(p));
+    }
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vlds_write(T* p, const T (&a)[V]) {
+    if constexpr (V == 1) {
+        *p = a[0];
+    } else {
+        typename VecT<T, V>::type x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = a[v];
+        *reinterpret_cast<typename VecT<T, V>::type*>(p) = x;
+    }
+}
+
+// The loop body is straight-line on purpose: every lane issues every load
+// (addresses clamped in bounds), writes LDS unconditionally (lanes without
+// halo work into a dummy row) and stores unconditionally (values of cells
+// that are not interior are 0, written into boundary cells that hold 0).
+// Branch-free memory code lets the compiler count outstanding loads exactly,
+// so the plane-ahead prefetch stays in flight across the barrier instead of
+// being drained every plane.
+//
+// A lane owns VEC consecutive x cells (one dword or dwordx2 access per
+// field); a wavefront covers TX = 64 VEC cells of one x row, a block BY rows.
+// LDS row layout: [pad][left halo][TX cells][right halo][pad], so that every
+// lane's VEC-wide write is naturally aligned, including the halo writes.
+template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WPE>
+__global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(const StepArgs<T> a) {
+    static_assert(BY >= 3 && 2 * BY <= 64, "halo lane assignment needs 3 <= BY <= 32");
     constexpr int NQ = 3 + (VISC ? 3 : 0) + (HET ? 1 : 0);
     constexpr int QG = VISC ? 6 : 3;
-    __shared__ T lds[NQ][BY + 2][66];
+    constexpr int TX = 64 * VEC;
+    constexpr int W = TX + 4;
+    constexpr int DUMMY = BY + 2;
+    __shared__ T lds[2][NQ][BY + 3][W];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int B = a.gx * a.gy * a.gz;
-    const int t = tile_of(blockIdx.x, B);
+    const int t = a.remap ? tile_of(blockIdx.x, B) : (int)blockIdx.x;
     const int bx = t % a.gx;
     const int by = (t / a.gx) % a.gy;
     const int bz = t / (a.gx * a.gy);
 
-    const int i = bx * 64 + tx;
+    const int nx = a.nx, ny = a.ny;
+    const int i0 = bx * TX + VEC * tx;  // first of this lane's cells
     const int j = by * BY + ty;
     const int kb = 1 + bz * a.kchunk;
     const int ke = min(a.nz - 1, kb + a.kchunk);  // planes kb .. ke-1
-    const bool in_x = i < a.nx, in_y = j < a.ny;
-    const bool inb = in_x && in_y;
-    const bool act = i >= 1 && i <= a.nx - 2 && j >= 1 && j <= a.ny - 2;
-    const int sxy = a.nx * a.ny;
-    const int col = inb ? i + a.nx * j : 0;
+    const bool inb = i0 < nx && j < ny;          // VEC > 1 needs nx % VEC == 0
+    bool act[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) act[v] = i0 + v >= 1 && i0 + v <= nx - 2 && j >= 1 && j <= ny - 2;
+    const int sxy = nx * ny;
+    const int col = inb ? i0 + nx * j : 0;
+    // store column: the lane's own cells; lanes outside the grid store zeros
+    // into boundary row ny-1
+    const int scol = inb ? col : min(i0, nx - VEC) + nx * (ny - 1);
+    const int lcol = 2 + VEC * tx;  // LDS column of the lane's first cell
+
+    // one halo slot per lane: wave 0 loads the row below the tile, wave BY-1
+    // the row above, lanes 0..2BY-1 of wave 1 the VEC-wide pieces whose
+    // last / first element is the left / right halo column of each row
+    int h_off = col, h_row = DUMMY, h_col = lcol;
+    bool h_real = true;
+    if (ty == 0) {
+        if (j >= 1 && i0 < nx) {
+            h_off = col - nx;
+            h_row = 0;
+        }
+    } else if (ty == BY - 1) {
+        if (j + 1 < ny && i0 < nx) {
+            h_off = col + nx;
+            h_row = BY + 1;
+        }
+    } else if (ty == 1 && tx < 2 * BY) {
+        h_real = false;
+        const int row = tx % BY;
+        const bool right = tx >= BY;
+        const int ii = bx * TX + (right ? TX : -VEC);
+        const int jj = by * BY + row;
+        if (ii >= 0 && ii < nx && jj < ny) {
+            h_off = ii + nx * jj;
+            h_row = row + 1;
+            h_col = right ? TX + 2 : 2 - VEC;
+            h_real = true;
+        }
+    } else {
+        h_real = false;
+    }
+    if (h_row == DUMMY) h_real = false;
+    // a lane without halo work re-reads its own prefetch address (plane k+2)
+    const int h_dz = h_real ? 1 : 2;
 
     const T* fp[NQ];
     fp[0] = a.u;
@@ -117,143 +239,228 @@ __global__ __launch_bounds__(64 * BY) void step_kernel(const StepArgs<T> a) {
     }
     if constexpr (HET) fp[QG] = a.G;
 
-    // halo roles: first/last tile row loads the row below/above, first/last
-    // lane loads the column left/right
-    const bool hyl = in_x && ((ty == 0 && j >= 1) || (ty == BY - 1 && j + 1 < a.ny));
-    const int hy_off = ty == 0 ? col - a.nx : col + a.nx;
-    const int hy_row = ty == 0 ? 0 : BY + 1;
-    const bool hxl = in_y && ((tx == 0 && i >= 1) || (tx == 63 && i + 1 < a.nx));
-    const int hx_off = tx == 0 ? col - 1 : col + 1;
-    const int hx_col = tx == 0 ? 0 : 65;
-
-    T zm[NQ], zc[NQ], zp[NQ], zn[NQ], hyc[NQ], hyn[NQ], hxc[NQ], hxn[NQ];
+    // z register queue (k-1, k, k+1, prefetched k+2), halo of plane k (and
+    // k+1 prefetched), per-cell values of plane k (and k+1 prefetched)
+    T zm[NQ][VEC], zc[NQ][VEC], zp[NQ][VEC], zn[NQ][VEC], hc[NQ][VEC], hn[NQ][VEC];
+    T wo_c[3][VEC], wo_n[3][VEC], fs_c[3][VEC], fs_n[3][VEC];
+    T crho_c[VEC], crho_n[VEC], eta_c[VEC], eta_n[VEC];
 #pragma unroll
     for (int f = 0; f < NQ; ++f) {
-        zm[f] = inb ? fp[f][(kb - 1) * sxy + col] : T(0);
-        zc[f] = inb ? fp[f][kb * sxy + col] : T(0);
-        zp[f] = inb ? fp[f][(kb + 1) * sxy + col] : T(0);
-        zn[f] = T(0);
-        hyc[f] = hyl ? fp[f][kb * sxy + hy_off] : T(0);
-        hxc[f] = hxl ? fp[f][kb * sxy + hx_off] : T(0);
-        hyn[f] = T(0);
-        hxn[f] = T(0);
+        vload<T, VEC>(fp[f] + (kb - 1) * sxy + col, zm[f]);
+        vload<T, VEC>(fp[f] + kb * sxy + col, zc[f]);
+        vload<T, VEC>(fp[f] + (kb + 1) * sxy + col, zp[f]);
+        vload<T, VEC>(fp[f] + kb * sxy + h_off, hc[f]);
+    }
+    {
+        const int q = kb * sxy + col;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                wo_c[c][v] = wo_n[c][v] = T(0);
+                fs_c[c][v] = fs_n[c][v] = T(0);
+            }
+            if constexpr (!VISC) vload<T, VEC>(a.w + c * a.N + q, wo_c[c]);
+            if constexpr (FORCE) vload<T, VEC>(a.FS + c * a.N + q, fs_c[c]);
+        }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            crho_c[v] = crho_n[v] = a.crho0;
+            eta_c[v] = eta_n[v] = T(0);
+        }
+        if constexpr (HET) {
+            vload<T, VEC>(a.crho + q, crho_c);
+            if constexpr (VISC) vload<T, VEC>(a.eta + q, eta_c);
+        }
     }
 
-    T rxy = T(0);
-    if (a.L > 0 && act) rxy = max(ramp<T>(i, a.nx, a.L, a.invL), ramp<T>(j, a.ny, a.L, a.invL));
+    T rxy[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+        rxy[v] = a.L > 0 ? max(ramp<T>(i0 + v, nx, a.L, a.invL), ramp<T>(j, ny, a.L, a.invL)) : T(0);
+    const T ihx2 = a.ihx2, ihy2 = a.ihy2, ihz2 = a.ihz2;
 
     for (int k = kb; k < ke; ++k) {
-        // prefetch centre values of plane k+2 and halos of plane k+1
-        if (k + 2 <= ke && inb) {
-#pragma unroll
-            for (int f = 0; f < NQ; ++f) zn[f] = fp[f][(k + 2) * sxy + col];
-        }
-        if (k + 1 < ke) {
-            if (hyl) {
-#pragma unroll
-                for (int f = 0; f < NQ; ++f) hyn[f] = fp[f][(k + 1) * sxy + hy_off];
-            }
-            if (hxl) {
-#pragma unroll
-                for (int f = 0; f < NQ; ++f) hxn[f] = fp[f][(k + 1) * sxy + hx_off];
-            }
-        }
-        const int idx = k * sxy + col;
-        // per-cell values used only here
-        T wc_own[3] = {T(0), T(0), T(0)};
-        T fsv[3] = {T(0), T(0), T(0)};
-        T crho_c = a.crho0, eta_dt = a.eta_dt0;
-        if (act) {
-            if constexpr (!VISC) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) wc_own[c] = a.w[c * a.N + idx];
-            }
-            if constexpr (FORCE) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) fsv[c] = __builtin_nontemporal_load(a.FS + c * a.N + idx);
-            }
-            if constexpr (HET) {
-                crho_c = __builtin_nontemporal_load(a.crho + idx);
-                if constexpr (VISC) eta_dt = __builtin_nontemporal_load(a.eta + idx) * a.inv_dt;
-            }
-        }
-
-        __syncthreads();  // previous plane fully consumed
+        const int buf = k & 1;
 #pragma unroll
         for (int f = 0; f < NQ; ++f) {
-            lds[f][ty + 1][tx + 1] = zc[f];
-            if (hyl) lds[f][hy_row][tx + 1] = hyc[f];
-            if (hxl) lds[f][ty + 1][hx_col] = hxc[f];
+            vlds_write<T, VEC>(&lds[buf][f][ty + 1][lcol], zc[f]);
+            vlds_write<T, VEC>(&lds[buf][f][h_row][h_col], hc[f]);
         }
-        __syncthreads();
-
-        if (act) {
-            T a1 = T(1), a2 = crho_c;
-            if (a.L > 0) {
-                const T s = a.half_dt_smax * max(rxy, ramp<T>(k, a.nz, a.L, a.invL));
-                if (s > T(0)) {
-                    const T inv = recip<T>(T(1) + s);
-                    a1 = (T(1) - s) * inv;
-                    a2 = crho_c * inv;
-                }
+        // prefetch: centre of plane k+2, halo and per-cell values of k+1
+        // (clamped to planes that exist; the clamped values go unused)
+        const int k2 = min(k + 2, ke);
+        const int k1 = min(k + 1, ke - 1);
+#pragma unroll
+        for (int f = 0; f < NQ; ++f) {
+            vload<T, VEC>(fp[f] + k2 * sxy + col, zn[f]);
+            vload<T, VEC>(fp[f] + min(k + h_dz, ke) * sxy + h_off, hn[f]);
+        }
+        {
+            const int q = k1 * sxy + col;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if constexpr (!VISC) vload<T, VEC>(a.w + c * a.N + q, wo_n[c]);
+                if constexpr (FORCE) vload_nt<T, VEC>(a.FS + c * a.N + q, fs_n[c]);
             }
+            if constexpr (HET) {
+                vload_nt<T, VEC>(a.crho + q, crho_n);
+                if constexpr (VISC) vload_nt<T, VEC>(a.eta + q, eta_n);
+            }
+        }
+        lds_barrier();
+
+        const T rz = a.L > 0 ? ramp<T>(k, a.nz, a.L, a.invL) : T(0);
+        T uo[3][VEC], wo[3][VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            const int lc = lcol + v;
+            const T s = a.half_dt_smax * max(rxy[v], rz);
+            const T inv1ps = rcp_fast<T>(T(1) + s);
+            const T a1 = (T(1) - s) * inv1ps;
+            const T a2 = crho_c[v] * inv1ps;
+            const T eta_dt = HET ? eta_c[v] * a.inv_dt : a.eta_dt0;
             T gxm, gxp, gym, gyp, gzm, gzp;
             if constexpr (HET) {
-                const T Gc = zc[QG];
-                gxm = harm<T>(Gc, lds[QG][ty + 1][tx]) * a.ihx2;
-                gxp = harm<T>(Gc, lds[QG][ty + 1][tx + 2]) * a.ihx2;
-                gym = harm<T>(Gc, lds[QG][ty][tx + 1]) * a.ihy2;
-                gyp = harm<T>(Gc, lds[QG][ty + 2][tx + 1]) * a.ihy2;
-                gzm = harm<T>(Gc, zm[QG]) * a.ihz2;
-                gzp = harm<T>(Gc, zp[QG]) * a.ihz2;
+                const T Gc = zc[QG][v];
+                gxm = harm<T>(Gc, lds[buf][QG][ty + 1][lc - 1]) * ihx2;
+                gxp = harm<T>(Gc, lds[buf][QG][ty + 1][lc + 1]) * ihx2;
+                gym = harm<T>(Gc, lds[buf][QG][ty][lc]) * ihy2;
+                gyp = harm<T>(Gc, lds[buf][QG][ty + 2][lc]) * ihy2;
+                gzm = harm<T>(Gc, zm[QG][v]) * ihz2;
+                gzp = harm<T>(Gc, zp[QG][v]) * ihz2;
             } else {
-                gxm = gxp = a.G0 * a.ihx2;
-                gym = gyp = a.G0 * a.ihy2;
-                gzm = gzp = a.G0 * a.ihz2;
+                gxm = gxp = a.G0 * ihx2;
+                gym = gyp = a.G0 * ihy2;
+                gzm = gzp = a.G0 * ihz2;
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const T uc = zc[c];
-                T acc = gxp * (lds[c][ty + 1][tx + 2] - uc) - gxm * (uc - lds[c][ty + 1][tx])
-                      + gyp * (lds[c][ty + 2][tx + 1] - uc) - gym * (uc - lds[c][ty][tx + 1])
-                      + gzp * (zp[c] - uc) - gzm * (uc - zm[c]);
+                const T uc = zc[c][v];
+                T acc = gxp * (lds[buf][c][ty + 1][lc + 1] - uc) - gxm * (uc - lds[buf][c][ty + 1][lc - 1])
+                      + gyp * (lds[buf][c][ty + 2][lc] - uc) - gym * (uc - lds[buf][c][ty][lc])
+                      + gzp * (zp[c][v] - uc) - gzm * (uc - zm[c][v]);
                 T wc;
                 if constexpr (VISC) {
-                    wc = zc[3 + c];
-                    const T lw = (lds[3 + c][ty + 1][tx + 2] + lds[3 + c][ty + 1][tx] - T(2) * wc) * a.ihx2
-                               + (lds[3 + c][ty + 2][tx + 1] + lds[3 + c][ty][tx + 1] - T(2) * wc) * a.ihy2
-                               + (zp[3 + c] + zm[3 + c] - T(2) * wc) * a.ihz2;
+                    wc = zc[3 + c][v];
+                    const T lw = (lds[buf][3 + c][ty + 1][lc + 1] + lds[buf][3 + c][ty + 1][lc - 1] - T(2) * wc) * ihx2
+                               + (lds[buf][3 + c][ty + 2][lc] + lds[buf][3 + c][ty][lc] - T(2) * wc) * ihy2
+                               + (zp[3 + c][v] + zm[3 + c][v] - T(2) * wc) * ihz2;
                     acc += eta_dt * lw;
                 } else {
-                    wc = wc_own[c];
+                    wc = wo_c[c][v];
                 }
-                if constexpr (FORCE) acc += a.gn * fsv[c];
+                if constexpr (FORCE) acc += a.gn * fs_c[c][v];
                 const T wnew = a1 * wc + a2 * acc;
-                __builtin_nontemporal_store(wnew, a.wn + c * a.N + idx);
-                __builtin_nontemporal_store(uc + wnew, a.un + c * a.N + idx);
+                wo[c][v] = act[v] ? wnew : T(0);
+                uo[c][v] = act[v] ? uc + wnew : T(0);
             }
         }
+        const int sidx = k * sxy + scol;
 #pragma unroll
-        for (int f = 0; f < NQ; ++f) {
-            zm[f] = zc[f];
-            zc[f] = zp[f];
-            zp[f] = zn[f];
-            hyc[f] = hyn[f];
-            hxc[f] = hxn[f];
+        for (int c = 0; c < 3; ++c) {
+            vstore_nt<T, VEC>(a.wn + c * a.N + sidx, wo[c]);
+            vstore_nt<T, VEC>(a.un + c * a.N + sidx, uo[c]);
+        }
+#pragma unroll
+        for (int f = 0; f < NQ; ++f)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                zm[f][v] = zc[f][v];
+                zc[f][v] = zp[f][v];
+                zp[f][v] = zn[f][v];
+                hc[f][v] = hn[f][v];
+            }
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                wo_c[c][v] = wo_n[c][v];
+                fs_c[c][v] = fs_n[c][v];
+            }
+            crho_c[v] = crho_n[v];
+            eta_c[v] = eta_n[v];
         }
     }
 }
 
-constexpr int kBY = 4;
+// Blocks of one kernel instance that fit on the chip at once.
+template <typename K>
+int resident_blocks(K kernel, int threads) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1024;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    return per_cu * prop.multiProcessorCount;
+}
 
-template <typename T, bool HET, bool VISC, bool FORCE>
-hipError_t launch_typed(kvs_ctx* c, const StepArgs<T>& a, int blocks) {
-    hipLaunchKernelGGL((step_kernel<T, HET, VISC, FORCE, kBY>), dim3(blocks), dim3(64, kBY), 0, c->stream, a);
+// Split z into segments so that (xy tiles) x (segments) fills whole rounds of
+// resident blocks; fewer, longer segments re-read fewer halo planes.
+int choose_kchunk(int xytiles, int planes, int cap) {
+    int best_seg = 1;
+    double best = -1.0;
+    const int max_seg = std::max(1, planes / 8);
+    for (int seg = 1; seg <= max_seg; ++seg) {
+        const int chunk = (planes + seg - 1) / seg;
+        const int nseg = (planes + chunk - 1) / chunk;
+        const long long blocks = (long long)xytiles * nseg;
+        const long long rounds = (blocks + cap - 1) / cap;
+        const double fill = (double)blocks / (double)(rounds * cap);
+        const double halo = 2.0 / (double)chunk;
+        const double score = fill / (1.0 + halo);
+        if (score > best + 1e-9) {
+            best = score;
+            best_seg = seg;
+        }
+    }
+    return (planes + best_seg - 1) / best_seg;
+}
+
+// Step-kernel variants (tile rows BY, cells per lane VEC) chosen by
+// kvs_autotune_step; variant 0 is the default.
+struct StepVariant {
+    int by, vec, wpe;
+};
+// wpe: minimum waves per SIMD asked of the register allocator (1 = free)
+constexpr StepVariant kVariants[] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {8, 2, 1}, {16, 1, 1}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WPE = 1>
+hipError_t launch_shape(kvs_ctx* c, StepArgs<T> a) {
+    auto kern = step_kernel<T, HET, VISC, FORCE, BY, VEC, WPE>;
+    static const int cap = resident_blocks(kern, 64 * BY);  // one value per instantiation
+    a.gx = (a.nx + 64 * VEC - 1) / (64 * VEC);
+    a.gy = (a.ny + BY - 1) / BY;
+    a.kchunk = c->step_zchunk > 0 ? std::min(c->step_zchunk, a.nz - 2) : choose_kchunk(a.gx * a.gy, a.nz - 2, cap);
+    a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
+    const int blocks = a.gx * a.gy * a.gz;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64, BY), 0, c->stream, a);
     return hipGetLastError();
 }
 
+template <typename T, bool HET, bool VISC, bool FORCE>
+hipError_t launch_typed(kvs_ctx* c, const StepArgs<T>& a, int variant) {
+    // VEC = 2 needs an even nx so that every lane's pair is aligned and whole;
+    // FP64 (the parity mode) uses one cell per lane
+    const bool narrow = sizeof(T) == 8 || (a.nx % 2) != 0;
+    if (kVariants[variant].vec == 2 && narrow) variant = kVariants[variant].by == 8 ? 1 : 0;
+    if constexpr (sizeof(T) == 8) {
+        // FP64 tiles stay at <= 8 rows (16-row FP64 tiles spill registers)
+        return (variant == 1 || variant == 4) ? launch_shape<T, HET, VISC, FORCE, 8, 1>(c, a) : launch_shape<T, HET, VISC, FORCE, 4, 1>(c, a);
+    } else {
+        switch (variant) {
+            case 4: return launch_shape<T, HET, VISC, FORCE, 16, 1>(c, a);
+            case 1: return launch_shape<T, HET, VISC, FORCE, 8, 1>(c, a);
+            case 2: return launch_shape<T, HET, VISC, FORCE, 4, 2>(c, a);
+            case 3: return launch_shape<T, HET, VISC, FORCE, 8, 2>(c, a);
+            default: return launch_shape<T, HET, VISC, FORCE, 4, 1>(c, a);
+        }
+    }
+}
+
 template <typename T>
-hipError_t launch_step_t(kvs_ctx* c, double gn) {
+hipError_t launch_step_t(kvs_ctx* c, double gn, int variant) {
     const kvs_grid& g = c->grid;
     StepArgs<T> a{};
     const int nb = 1 - c->cur;
@@ -269,10 +476,6 @@ hipError_t launch_step_t(kvs_ctx* c, double gn) {
     a.nx = (int)g.nx;
     a.ny = (int)g.ny;
     a.nz = (int)g.nz;
-    a.kchunk = (int)std::min<int64_t>(g.nz - 2, 32);
-    a.gx = (a.nx + 63) / 64;
-    a.gy = (a.ny + kBY - 1) / kBY;
-    a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
     a.L = c->sponge_cells;
     a.invL = a.L > 0 ? T(1.0 / a.L) : T(0);
     a.ihx2 = T(1.0 / (g.hx * g.hx));
@@ -284,14 +487,16 @@ hipError_t launch_step_t(kvs_ctx* c, double gn) {
     a.inv_dt = T(1.0 / c->dt);
     a.gn = T(gn);
     a.half_dt_smax = T(0.5 * c->sigma_max * c->dt);
-    const int blocks = a.gx * a.gy * a.gz;
+    a.remap = c->step_remap;
     const bool F = gn != 0.0;
     if (c->hetero) {
-        if (c->viscous) return F ? launch_typed<T, true, true, true>(c, a, blocks) : launch_typed<T, true, true, false>(c, a, blocks);
-        return F ? launch_typed<T, true, false, true>(c, a, blocks) : launch_typed<T, true, false, false>(c, a, blocks);
+        if (c->viscous)
+            return F ? launch_typed<T, true, true, true>(c, a, variant) : launch_typed<T, true, true, false>(c, a, variant);
+        return F ? launch_typed<T, true, false, true>(c, a, variant) : launch_typed<T, true, false, false>(c, a, variant);
     }
-    if (c->viscous) return F ? launch_typed<T, false, true, true>(c, a, blocks) : launch_typed<T, false, true, false>(c, a, blocks);
-    return F ? launch_typed<T, false, false, true>(c, a, blocks) : launch_typed<T, false, false, false>(c, a, blocks);
+    if (c->viscous)
+        return F ? launch_typed<T, false, true, true>(c, a, variant) : launch_typed<T, false, true, false>(c, a, variant);
+    return F ? launch_typed<T, false, false, true>(c, a, variant) : launch_typed<T, false, false, false>(c, a, variant);
 }
 
 // ---- helpers ---------------------------------------------------------------
@@ -419,7 +624,20 @@ int grid_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 8192
 }  // namespace
 
 hipError_t kvs_launch_step(kvs_ctx* c, double gn) {
-    return c->prec == KVS_FP32 ? launch_step_t<float>(c, gn) : launch_step_t<double>(c, gn);
+    return kvs_launch_step_variant(c, gn, c->step_variant);
+}
+
+hipError_t kvs_launch_step_variant(kvs_ctx* c, double gn, int variant) {
+    if (variant < 0 || variant >= kNumVariants) variant = 0;
+    return c->prec == KVS_FP32 ? launch_step_t<float>(c, gn, variant) : launch_step_t<double>(c, gn, variant);
+}
+
+int kvs_step_variant_count() { return kNumVariants; }
+
+void kvs_step_variant_shape(int variant, int* by, int* vec) {
+    if (variant < 0 || variant >= kNumVariants) variant = 0;
+    *by = kVariants[variant].by;
+    *vec = kVariants[variant].vec;
 }
 
 hipError_t kvs_launch_probe_gather(kvs_ctx* c, const void* u_new, int64_t slot) {

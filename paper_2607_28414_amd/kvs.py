@@ -83,6 +83,10 @@ SIGNATURES = {
     "kvs_set_state": ([_P, _D, _D, C.c_int64], C.c_int),
     "kvs_reset_state": ([_P], C.c_int),
     "kvs_enable_kernel_timing": ([_P, C.c_int32], C.c_int),
+    "kvs_num_step_variants": ([], C.c_int32),
+    "kvs_set_step_variant": ([_P, C.c_int32], C.c_int),
+    "kvs_set_step_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
 }
 
@@ -262,3 +266,23 @@ def kvs_kernel_time(ctx):
     n = C.c_int64()
     _check(lib().kvs_kernel_time(ctx, C.byref(ms), C.byref(n)), ctx)
     return ms.value, n.value
+
+
+def kvs_num_step_variants():
+    return lib().kvs_num_step_variants()
+
+
+def kvs_set_step_variant(ctx, v):
+    _check(lib().kvs_set_step_variant(ctx, int(v)), ctx)
+
+
+def kvs_autotune_step(ctx, trial_steps=20):
+    n = kvs_num_step_variants()
+    ms = np.zeros(n)
+    chosen = C.c_int32()
+    _check(lib().kvs_autotune_step(ctx, int(trial_steps), C.byref(chosen), _dptr(ms), n), ctx)
+    return chosen.value, ms
+
+
+def kvs_set_step_tuning(ctx, v, zchunk=0, remap=True):
+    _check(lib().kvs_set_step_tuning(ctx, int(v), int(zchunk), int(bool(remap))), ctx)

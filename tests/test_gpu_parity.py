@@ -301,3 +301,59 @@ def test_cfg2_full_size_sampled_parity(kvs):
     wg = w1.reshape(3, -1)[:, cells].T
     assert np.max(np.abs(wg - wo)) <= 1e-5 * np.max(np.abs(w1))
     assert np.max(np.abs(ug - uo)) <= 1e-6 * np.max(np.abs(u1))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_step_variant_matches_oracle(kvs, precision):
+    """The autotuner may pick any step-kernel variant: each one, on a
+    heterogeneous viscous grid with sponge and force (even nx, so the
+    two-cells-per-lane shapes run), matches the oracle (FP64 to 1e-12,
+    FP32 traces to 2e-5)."""
+    grid, G, rho, eta, F = hetero_case((130, 21, 37), 23)
+    L = 4
+    smax = oracle.default_sigma_max(grid, G, rho, L)
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    env = np.array([1.0, 0.5, 0.25, 1.0])
+    probes = np.array([[i, 10, 18] for i in range(130)])
+    FS_o, _, _ = oracle.project(grid, F, tol=1e-12)
+    _, _, tr_o = oracle.run(grid, G, rho, eta, dt, 120, FS=FS_o, env=env, probes=probes, comp=3,
+                            sponge_cells=L, sigma_max=smax)
+    for v in range(kvs.kvs_num_step_variants()):
+        say(f"case variant {v} precision {precision}")
+        ctx = kvs.kvs_create(grid, precision=precision, sponge_cells=L, sponge_sigma_max=smax)
+        try:
+            kvs.kvs_set_material(ctx, G, rho, eta)
+            kvs.kvs_set_dt(ctx, dt)
+            kvs.kvs_set_projected_force(ctx, FS_o)
+            kvs.kvs_set_envelope(ctx, env)
+            kvs.kvs_set_probes(ctx, probes, 3)
+            kvs.kvs_set_step_variant(ctx, v)
+            kvs.kvs_step(ctx, 120)
+            tr = kvs.kvs_read_traces(ctx, len(probes), 3)
+            u, w, _ = kvs.kvs_get_state(ctx, (37, 21, 130))
+        finally:
+            kvs.kvs_destroy(ctx)
+        err = rel_l2(tr, tr_o)
+        assert err < (1e-12 if precision == 0 else 2e-5), (v, err)
+        assert not u[:, 0].any() and not u[:, :, 0].any() and not u[:, :, :, -1].any() and not w[:, -1].any()
+
+
+def test_autotune_keeps_state_and_picks_a_variant(kvs):
+    say("case autotune")
+    grid, G, rho, eta, F = hetero_case((128, 40, 30), 29)
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    FS_o, _, _ = oracle.project(grid, F, tol=1e-10)
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, sponge_cells=3)
+    try:
+        kvs.kvs_set_material(ctx, G, rho, eta)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_projected_force(ctx, FS_o)
+        kvs.kvs_set_envelope(ctx, np.ones(5))
+        kvs.kvs_step(ctx, 7)
+        u0, w0, s0 = kvs.kvs_get_state(ctx, (30, 40, 128))
+        best, ms = kvs.kvs_autotune_step(ctx, 3)
+        u1, w1, s1 = kvs.kvs_get_state(ctx, (30, 40, 128))
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert 0 <= best < len(ms) and np.all(ms > 0) and ms[best] == ms.min()
+    assert s0 == s1 == 7 and np.array_equal(u0, u1) and np.array_equal(w0, w1)
