@@ -8,12 +8,17 @@
 // One CG iteration is two fused HBM sweeps plus two one-block finalize
 // kernels, with every scalar (alpha, beta, r.r, the stop flag) kept on the
 // device, so the host only polls a flag once per chunk of iterations:
-//   sweep 1: p' = z + beta p (z = r, or r / diag(A) for Jacobi), Ap' = -lap p',
-//            block partials of p'.Ap'            (reads r, p; writes p', Ap')
+//   sweep 1: p' = z + beta p (z = r, or r / diag(A) for Jacobi), A p' from
+//            the 7-point stencil, block partials of p'.Ap'
+//            (reads r, p; writes p': 24 B per cell)
 //   finalize: alpha = r.z / p.Ap with the breakdown guard
-//   sweep 2: phi += alpha p', r -= alpha Ap', partials of r.r and r.z
+//   sweep 2: A p' recomputed from p', phi += alpha p', r -= alpha Ap',
+//            partials of r.r and r.z (reads phi, p', r; writes phi, r: 40 B)
 //   finalize: beta, the stop test, the iteration count
+// Recomputing A p' costs a few flops and saves storing and re-reading it.
 // p is ping-ponged because sweep 1 reads p at neighbours while writing p'.
+// Both sweeps are LDS-staged z-marches like the FDTD step (64 x 8 tiles,
+// straight-line memory code, plane-ahead prefetch).
 // Reductions are deterministic: fixed-shape wavefront shuffles inside a
 // block, one partial per block, and a one-block fixed-order final sum.
 #include <hip/hip_runtime.h>
@@ -22,8 +27,11 @@
 #include <cmath>
 
 #include "kvs_internal.hpp"
+#include "kvs_tiling.hpp"
 
 namespace {
+
+using kvs_tiling::lds_barrier;
 
 constexpr int CBY = 4;    // rows per block
 constexpr int CKZ = 16;   // z planes per block
@@ -38,11 +46,7 @@ struct CgGeom {
 
 enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3 };
 
-__device__ __forceinline__ int tile_of(int b, int B) {
-    const int xcd = b & 7, pos = b >> 3;
-    const int per = B >> 3, rem = B & 7;
-    return xcd * per + min(xcd, rem) + pos;
-}
+using kvs_tiling::tile_of;
 
 struct Tile {
     int i, j, kb, ke;
@@ -135,56 +139,177 @@ __global__ __launch_bounds__(64 * CBY) void cg_init_kernel(const CgGeom g, const
     block_partials<3>(s1, s2, s3, partials, npart);
 }
 
-// p' = z + beta p, Ap' = -lap p', partial p'.Ap'
-__global__ __launch_bounds__(64 * CBY) void cg_matvec_kernel(const CgGeom g, const double* r, const double* p_old,
-                                                             double* p_new, double* Ap, const CgState* st,
-                                                             double* partials, int npart) {
-    if (st->done) return;
-    const Tile t = tile_coords(g);
-    const double beta = st->beta;
-    const double zs = st->jacobi ? g.dinv : 1.0;
-    const int sxy = g.nx * g.ny, sy = g.nx;
-    double s1 = 0;
-    if (t.act) {
-        auto pn = [&](int q) { return beta == 0.0 ? r[q] * zs : r[q] * zs + beta * p_old[q]; };
-        double pm = pn((t.kb - 1) * sxy + t.col);
-        double pc = pn(t.kb * sxy + t.col);
-        for (int k = t.kb; k < t.ke; ++k) {
-            const int idx = k * sxy + t.col;
-            const double pp = pn(idx + sxy);
-            const double c2 = 2.0 * pc;
-            const double ap = -((pn(idx + 1) + pn(idx - 1) - c2) * g.ihx2 + (pn(idx + sy) + pn(idx - sy) - c2) * g.ihy2
-                                + (pp + pm - c2) * g.ihz2);
-            p_new[idx] = pc;
-            Ap[idx] = ap;
-            s1 += pc * ap;
-            pm = pc;
-            pc = pp;
+// Geometry of the two CG sweeps: 64 x SBY tiles, z segments of `kchunk`.
+constexpr int SBY = 8;
+
+struct SweepGeom {
+    int gx, gy, gz, kchunk;
+};
+
+// Per-lane tile coordinates and halo slot of a z-marching sweep (same
+// scheme as the FDTD step: wave 0 loads the row below the tile, wave SBY-1
+// the row above, lanes 0..2 SBY-1 of wave 1 the left/right columns; other
+// lanes re-read their own plane-(k+2) address and write a dummy LDS row).
+struct Lane {
+    int i, j, kb, ke, col, scol, h_off, h_row, h_col, h_dz;
+    bool act;
+};
+
+__device__ __forceinline__ Lane sweep_lane(const CgGeom& g, const SweepGeom& s) {
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int B = s.gx * s.gy * s.gz;
+    const int t = tile_of(blockIdx.x, B);
+    const int bx = t % s.gx, by = (t / s.gx) % s.gy, bz = t / (s.gx * s.gy);
+    Lane L;
+    L.i = bx * 64 + tx;
+    L.j = by * SBY + ty;
+    L.kb = 1 + bz * s.kchunk;
+    L.ke = min(g.nz - 1, L.kb + s.kchunk);
+    const bool inb = L.i < g.nx && L.j < g.ny;
+    L.act = L.i >= 1 && L.i <= g.nx - 2 && L.j >= 1 && L.j <= g.ny - 2;
+    L.col = inb ? L.i + g.nx * L.j : 0;
+    L.scol = min(L.i, g.nx - 1) + g.nx * min(L.j, g.ny - 1);
+    L.h_off = L.col;
+    L.h_row = SBY + 2;  // dummy row
+    L.h_col = tx + 1;
+    bool real = false;
+    if (ty == 0) {
+        if (L.j >= 1 && L.i < g.nx) {
+            L.h_off = L.col - g.nx;
+            L.h_row = 0;
+            real = true;
+        }
+    } else if (ty == SBY - 1) {
+        if (L.j + 1 < g.ny && L.i < g.nx) {
+            L.h_off = L.col + g.nx;
+            L.h_row = SBY + 1;
+            real = true;
+        }
+    } else if (ty == 1 && tx < 2 * SBY) {
+        const int row = tx % SBY;
+        const bool right = tx >= SBY;
+        const int ii = bx * 64 + (right ? 64 : -1);
+        const int jj = by * SBY + row;
+        if (ii >= 0 && ii < g.nx && jj < g.ny) {
+            L.h_off = ii + g.nx * jj;
+            L.h_row = row + 1;
+            L.h_col = right ? 65 : 0;
+            real = true;
         }
     }
-    block_partials<1>(s1, 0, 0, partials, npart);
+    L.h_dz = real ? 1 : 2;
+    return L;
 }
 
-// phi += alpha p, r -= alpha Ap, partials of r.r and r.z
-__global__ __launch_bounds__(64 * CBY) void cg_update_kernel(const CgGeom g, double* phi, double* r, const double* p,
-                                                             const double* Ap, const CgState* st, double* partials,
-                                                             int npart) {
-    if (st->done) return;
-    const Tile t = tile_coords(g);
-    const double alpha = st->alpha;
-    const int sxy = g.nx * g.ny;
-    double s1 = 0, s2 = 0;
-    if (t.act) {
-        for (int k = t.kb; k < t.ke; ++k) {
-            const int idx = k * sxy + t.col;
-            phi[idx] += alpha * p[idx];
-            const double rv = r[idx] - alpha * Ap[idx];
-            r[idx] = rv;
-            s1 += rv * rv;
-            s2 += rv * (rv * g.dinv);
-        }
+// Sum over the block (SBY waves) of up to two values; lane (0,0) writes them
+// to partials[block] and partials[npart + block].
+template <int NS>
+__device__ __forceinline__ void sweep_partials(double v0, double v1, double* partials, int npart) {
+    __shared__ double sh[2][SBY];
+    v0 = wave_sum(v0);
+    if (NS > 1) v1 = wave_sum(v1);
+    if (threadIdx.x == 0) {
+        sh[0][threadIdx.y] = v0;
+        if (NS > 1) sh[1][threadIdx.y] = v1;
     }
-    block_partials<2>(s1, s2, 0, partials, npart);
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        double a = 0, b = 0;
+        for (int w = 0; w < SBY; ++w) {
+            a += sh[0][w];
+            if (NS > 1) b += sh[1][w];
+        }
+        partials[blockIdx.x] = a;
+        if (NS > 1) partials[npart + blockIdx.x] = b;
+    }
+}
+
+// sweep 1: p' = z + beta p, A p' = -lap p', partial p'.Ap'
+__global__ __launch_bounds__(64 * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const double* r,
+                                                          const double* p_old, double* p_new, const CgState* st,
+                                                          double* partials, int npart) {
+    if (st->done) return;
+    __shared__ double lds[2][SBY + 3][68];
+    const Lane L = sweep_lane(g, sg);
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int sxy = g.nx * g.ny;
+    const double beta = st->beta;
+    const double zs = st->jacobi ? g.dinv : 1.0;
+    const bool first = beta == 0.0;
+    auto pv = [&](double rv, double po) { return first ? rv * zs : rv * zs + beta * po; };
+    const int kb = L.kb, ke = L.ke;
+    double pm = pv(r[(kb - 1) * sxy + L.col], p_old[(kb - 1) * sxy + L.col]);
+    double pc = pv(r[kb * sxy + L.col], p_old[kb * sxy + L.col]);
+    double pp = pv(r[(kb + 1) * sxy + L.col], p_old[(kb + 1) * sxy + L.col]);
+    double hc = pv(r[kb * sxy + L.h_off], p_old[kb * sxy + L.h_off]);
+    double s1 = 0.0;
+    for (int k = kb; k < ke; ++k) {
+        const int buf = k & 1;
+        lds[buf][ty + 1][tx + 1] = pc;
+        lds[buf][L.h_row][L.h_col] = hc;
+        const int q2 = min(k + 2, ke) * sxy + L.col;
+        const int qh = min(k + L.h_dz, ke) * sxy + L.h_off;
+        const double rn = r[q2], on = p_old[q2], hrn = r[qh], hon = p_old[qh];
+        lds_barrier();
+        const double c2 = 2.0 * pc;
+        const double ap = -((lds[buf][ty + 1][tx + 2] + lds[buf][ty + 1][tx] - c2) * g.ihx2
+                            + (lds[buf][ty + 2][tx + 1] + lds[buf][ty][tx + 1] - c2) * g.ihy2
+                            + (pp + pm - c2) * g.ihz2);
+        s1 += L.act ? pc * ap : 0.0;
+        p_new[k * sxy + L.scol] = L.act ? pc : 0.0;
+        pm = pc;
+        pc = pp;
+        pp = pv(rn, on);
+        hc = pv(hrn, hon);
+    }
+    sweep_partials<1>(s1, 0.0, partials, npart);
+}
+
+// sweep 2: A p recomputed, phi += alpha p, r -= alpha A p, partials r.r, r.z
+__global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const SweepGeom sg, double* phi, double* r,
+                                                          const double* p, const CgState* st, double* partials,
+                                                          int npart) {
+    if (st->done) return;
+    __shared__ double lds[2][SBY + 3][68];
+    const Lane L = sweep_lane(g, sg);
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int sxy = g.nx * g.ny;
+    const double alpha = st->alpha;
+    const int kb = L.kb, ke = L.ke;
+    double pm = p[(kb - 1) * sxy + L.col];
+    double pc = p[kb * sxy + L.col];
+    double pp = p[(kb + 1) * sxy + L.col];
+    double hc = p[kb * sxy + L.h_off];
+    double phc = phi[kb * sxy + L.col], rc = r[kb * sxy + L.col];
+    double s1 = 0.0, s2 = 0.0;
+    for (int k = kb; k < ke; ++k) {
+        const int buf = k & 1;
+        lds[buf][ty + 1][tx + 1] = pc;
+        lds[buf][L.h_row][L.h_col] = hc;
+        const double pn = p[min(k + 2, ke) * sxy + L.col];
+        const double hn = p[min(k + L.h_dz, ke) * sxy + L.h_off];
+        const int q1 = min(k + 1, ke - 1) * sxy + L.col;
+        const double phn = phi[q1], rn = r[q1];
+        lds_barrier();
+        const double c2 = 2.0 * pc;
+        const double ap = -((lds[buf][ty + 1][tx + 2] + lds[buf][ty + 1][tx] - c2) * g.ihx2
+                            + (lds[buf][ty + 2][tx + 1] + lds[buf][ty][tx + 1] - c2) * g.ihy2
+                            + (pp + pm - c2) * g.ihz2);
+        const double phv = phc + alpha * pc;
+        const double rv = rc - alpha * ap;
+        const int q = k * sxy + L.scol;
+        phi[q] = L.act ? phv : 0.0;
+        r[q] = L.act ? rv : 0.0;
+        s1 += L.act ? rv * rv : 0.0;
+        s2 += L.act ? rv * (rv * g.dinv) : 0.0;
+        pm = pc;
+        pc = pp;
+        pp = pn;
+        hc = hn;
+        phc = phn;
+        rc = rn;
+    }
+    sweep_partials<2>(s1, s2, partials, npart);
 }
 
 // partials of (-b - A phi)^2 and b^2
@@ -226,13 +351,14 @@ __global__ __launch_bounds__(64 * CBY) void grad_subtract_kernel(const CgGeom g,
 }
 
 // One block: fixed-order sums of the partials, then the scalar logic.
-__global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials, int npart, int nsum, int mode,
-                                                          CgState* st) {
+// partials[s * stride + q], q < count, s < nsum
+__global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials, int count, int stride, int nsum,
+                                                          int mode, CgState* st) {
     if (mode != FIN_INIT && mode != FIN_TRUE && st->done) return;
     __shared__ double sh[3][256];
     for (int s = 0; s < nsum; ++s) {
         double acc = 0.0;
-        for (int q = threadIdx.x; q < npart; q += 256) acc += partials[s * npart + q];
+        for (int q = threadIdx.x; q < count; q += 256) acc += partials[s * stride + q];
         sh[s][threadIdx.x] = acc;
     }
     __syncthreads();
@@ -329,7 +455,8 @@ kvs_status fail(kvs_ctx* c, kvs_status s, const std::string& msg) {
 
 int64_t kvs_cg_partials_needed(const kvs_grid& gr) {
     CgGeom g = make_geom(gr);
-    return nblocks(g);
+    const int sweep_xy = ((g.nx + 63) / 64) * ((g.ny + SBY - 1) / SBY);
+    return std::max<int64_t>(nblocks(g), kvs_tiling::max_tiled_blocks(sweep_xy, g.nz - 2));
 }
 
 #define CG_HIP(call)                                                                          \
@@ -361,22 +488,32 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     if (!warm) CG_HIP(hipMemsetAsync(c->phi, 0, sizeof(double) * c->N, c->stream));
 
     hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, c->r, warm ? 1 : 0, part, npart);
-    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 3, (int)FIN_INIT, c->cgs);
+    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3, (int)FIN_INIT, c->cgs);
     CG_HIP(hipGetLastError());
 
+    SweepGeom sg{};
+    sg.gx = (g.nx + 63) / 64;
+    sg.gy = (g.ny + SBY - 1) / SBY;
+    {
+        static const int cap = kvs_tiling::resident_blocks(cg_dir_kernel, 64 * SBY);
+        sg.kchunk = kvs_tiling::choose_kchunk(sg.gx * sg.gy, g.nz - 2, cap);
+        sg.gz = (g.nz - 2 + sg.kchunk - 1) / sg.kchunk;
+    }
+    const int nbs = sg.gx * sg.gy * sg.gz;
+    const dim3 sblk(64, SBY);
     int pi = 0;  // p[pi] holds the current search direction
     int chunk = 4;
     long long launched = 0;
     const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
     while (true) {
         for (int m = 0; m < chunk; ++m) {
-            hipLaunchKernelGGL(cg_matvec_kernel, dim3(nb), blk, 0, c->stream, g, c->r, c->p[pi], c->p[1 - pi], c->Ap,
+            hipLaunchKernelGGL(cg_dir_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->r, c->p[pi], c->p[1 - pi],
                                c->cgs, part, npart);
-            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 1, (int)FIN_ALPHA,
+            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 1, (int)FIN_ALPHA,
                                c->cgs);
-            hipLaunchKernelGGL(cg_update_kernel, dim3(nb), blk, 0, c->stream, g, c->phi, c->r, c->p[1 - pi], c->Ap,
-                               c->cgs, part, npart);
-            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 2, (int)FIN_BETA,
+            hipLaunchKernelGGL(cg_upd_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, c->r, c->p[1 - pi], c->cgs,
+                               part, npart);
+            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 2, (int)FIN_BETA,
                                c->cgs);
             pi = 1 - pi;
         }
@@ -388,12 +525,12 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
         if (launched > cap) return fail(c, KVS_EDEVICE, "CG driver: iteration cap passed without a stop flag");
         chunk = std::min(chunk * 2, 64);
     }
-    // Iterations that were launched after the stop flag returned early, so
-    // the direction buffers flipped once per performed iteration only for the
-    // performed ones; the buffers are rebuilt from r on the next solve.
+    // Launches after the stop flag return at once; the host-side flip of pi
+    // may then be off by those, which is harmless: the next solve starts with
+    // beta = 0, which rebuilds the direction from r alone.
 
     hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, part, npart);
-    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, 3, (int)FIN_TRUE, c->cgs);
+    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3, (int)FIN_TRUE, c->cgs);
     const int status = c->cgs_host->status;
     if (status != KVS_EBREAKDOWN) {
         if (c->prec == KVS_FP32)
