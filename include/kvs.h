@@ -200,6 +200,41 @@ kvs_status kvs_reset_state(kvs_ctx* ctx);
 kvs_status kvs_enable_kernel_timing(kvs_ctx* ctx, int32_t on);
 kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* launches);
 
+/* ---- batched parameter sweeps ----------------------------------------------- */
+
+/* A batch advances n homogeneous instances (each its own grid, medium, dt,
+ * force, envelope and probes) together: every step is one kernel launch
+ * covering all instances' tiles, and a run of steps is one hipGraph launch
+ * (captured on first use, replayed while the start step, step count and
+ * trace slot repeat, e.g. after kvs_batch_reset).  Instances are ordinary
+ * contexts: configure each through kvs_batch_instance() with the functions
+ * above (material must be uniform).  All instances share the batch's
+ * stream. */
+typedef struct kvs_batch kvs_batch;
+/* grids: n grids; opts as for kvs_create (one precision and sponge for all). */
+kvs_status kvs_batch_create(const kvs_grid* grids, int32_t n, const kvs_opts* opts, kvs_batch** out);
+void kvs_batch_destroy(kvs_batch* b);
+const char* kvs_batch_last_error(const kvs_batch* b);
+/* Instance i (0 <= i < n), owned by the batch; NULL when out of range. */
+kvs_ctx* kvs_batch_instance(kvs_batch* b, int32_t i);
+/* Copy instance src's projected force to instance dst (same grid required):
+ * the projection depends on the grid and force pattern only, not on the
+ * medium. */
+kvs_status kvs_batch_share_projection(kvs_batch* b, int32_t src, int32_t dst);
+/* Probes of instance i (replaces its list; clears the batch traces) and the
+ * recorded component for all instances (0..2). */
+kvs_status kvs_batch_set_probes(kvs_batch* b, int32_t i, const int64_t* ijk, int64_t n);
+kvs_status kvs_batch_set_component(kvs_batch* b, int32_t comp);
+/* Advance every instance nsteps steps.  Every instance needs uniform
+ * material, dt, and a current projection on steps where its envelope is
+ * non-zero, and all must be at the batch's step index (else KVS_ESTATE). */
+kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps);
+/* All instances to rest, step index 0, traces cleared. */
+kvs_status kvs_batch_reset(kvs_batch* b);
+kvs_status kvs_batch_trace_count(const kvs_batch* b, int64_t* nsteps_recorded);
+/* Traces of instance i, [step][probe] doubles, into out (cap doubles). */
+kvs_status kvs_batch_read_traces(kvs_batch* b, int32_t i, double* out, int64_t cap, int64_t* n_written);
+
 /* ---- tuning --------------------------------------------------------------- */
 
 /* Number of FDTD step-kernel variants (tile rows x cells per lane). */

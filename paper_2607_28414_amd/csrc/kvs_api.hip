@@ -709,4 +709,250 @@ kvs_status kvs_autotune_step(kvs_ctx* c, int32_t trial_steps, int32_t* chosen, d
     return KVS_OK;
 }
 
+// ---- batches -------------------------------------------------------------------
+
+static kvs_status bfail(kvs_batch* b, kvs_status s, const std::string& msg) {
+    if (b)
+        b->err = msg;
+    else
+        g_create_err = msg;
+    return s;
+}
+
+#define BATCH_HIP(b, call)                                                                                \
+    do {                                                                                                  \
+        hipError_t e_ = (call);                                                                           \
+        if (e_ != hipSuccess) return bfail(b, KVS_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static void batch_release(kvs_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (kvs_ctx* c : b->inst) kvs_destroy(c);
+    b->inst.clear();
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    dfree(b->dev_params);
+    dfree(b->dev_work);
+    dfree(b->dev_probes);
+    dfree(b->traces);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    b->stream = nullptr;
+}
+
+kvs_status kvs_batch_create(const kvs_grid* grids, int32_t n, const kvs_opts* opts, kvs_batch** out) {
+    if (!out) return bfail(nullptr, KVS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grids || n < 1) return bfail(nullptr, KVS_EINVAL, "need at least one grid");
+    kvs_opts o{};
+    o.precision = KVS_FP32;
+    o.sponge_sigma_max = -1.0;
+    if (opts) o = *opts;
+    if (o.device < 0) return bfail(nullptr, KVS_EINVAL, "device ordinal out of range");
+    if (hipSetDevice(o.device) != hipSuccess) return bfail(nullptr, KVS_EDEVICE, "hipSetDevice failed");
+    kvs_batch* b = new (std::nothrow) kvs_batch();
+    if (!b) return bfail(nullptr, KVS_ENOMEM, "host allocation failed");
+    b->device = o.device;
+    b->prec = o.precision;
+    if (o.stream) {
+        b->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return bfail(nullptr, KVS_EDEVICE, "hipStreamCreate failed");
+        }
+        b->own_stream = true;
+    }
+    o.stream = b->stream;
+    for (int32_t i = 0; i < n; ++i) {
+        kvs_ctx* c = nullptr;
+        kvs_status st = kvs_create(&grids[i], &o, &c);
+        if (st != KVS_OK) {
+            const std::string msg = "instance " + std::to_string(i) + ": " + kvs_last_error(nullptr);
+            batch_release(b);
+            delete b;
+            return bfail(nullptr, st, msg);
+        }
+        b->inst.push_back(c);
+    }
+    b->probe_first.assign((size_t)n + 1, 0);
+    *out = b;
+    return KVS_OK;
+}
+
+void kvs_batch_destroy(kvs_batch* b) {
+    if (!b) return;
+    batch_release(b);
+    delete b;
+}
+
+const char* kvs_batch_last_error(const kvs_batch* b) { return b ? b->err.c_str() : g_create_err.c_str(); }
+
+kvs_ctx* kvs_batch_instance(kvs_batch* b, int32_t i) {
+    if (!b || i < 0 || i >= (int32_t)b->inst.size()) return nullptr;
+    return b->inst[(size_t)i];
+}
+
+kvs_status kvs_batch_share_projection(kvs_batch* b, int32_t src, int32_t dst) {
+    if (!b) return KVS_EINVAL;
+    kvs_ctx* s = kvs_batch_instance(b, src);
+    kvs_ctx* d = kvs_batch_instance(b, dst);
+    if (!s || !d) return bfail(b, KVS_EINVAL, "instance out of range");
+    const kvs_grid &gs = s->grid, &gd = d->grid;
+    if (gs.nx != gd.nx || gs.ny != gd.ny || gs.nz != gd.nz || gs.hx != gd.hx || gs.hy != gd.hy || gs.hz != gd.hz)
+        return bfail(b, KVS_EINVAL, "share_projection needs identical grids");
+    if (!s->fs_current) return bfail(b, KVS_ESTATE, "source instance has no current projection");
+    if (src == dst) return KVS_OK;
+    BATCH_HIP(b, hipMemcpyAsync(d->FS, s->FS, 3 * (size_t)s->N * tsize(s), hipMemcpyDeviceToDevice, b->stream));
+    BATCH_HIP(b, hipStreamSynchronize(b->stream));
+    d->fs_current = true;
+    return KVS_OK;
+}
+
+static kvs_status batch_upload_probes(kvs_batch* b) {
+    const size_t np = b->probe_inst.size();
+    dfree(b->dev_probes);
+    dfree(b->traces);
+    b->trace_cap = 0;
+    b->trace_steps = 0;
+    b->graph_valid = false;
+    if (np == 0) return KVS_OK;
+    std::vector<int64_t> flat(2 * np);
+    for (size_t p = 0; p < np; ++p) {
+        flat[2 * p] = b->probe_inst[p];
+        flat[2 * p + 1] = b->probe_cell[p];
+    }
+    BATCH_HIP(b, hipMalloc(&b->dev_probes, sizeof(int64_t) * flat.size()));
+    BATCH_HIP(b, hipMemcpyAsync(b->dev_probes, flat.data(), sizeof(int64_t) * flat.size(), hipMemcpyHostToDevice,
+                                b->stream));
+    BATCH_HIP(b, hipStreamSynchronize(b->stream));
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_set_probes(kvs_batch* b, int32_t i, const int64_t* ijk, int64_t n) {
+    if (!b) return KVS_EINVAL;
+    kvs_ctx* c = kvs_batch_instance(b, i);
+    if (!c) return bfail(b, KVS_EINVAL, "instance out of range");
+    if (n < 0 || (n > 0 && !ijk)) return bfail(b, KVS_EINVAL, "bad probe list");
+    const kvs_grid& g = c->grid;
+    std::vector<int64_t> cells((size_t)n);
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t x = ijk[3 * p], y = ijk[3 * p + 1], z = ijk[3 * p + 2];
+        if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz)
+            return bfail(b, KVS_EINVAL, "probe " + std::to_string(p) + " outside instance " + std::to_string(i));
+        cells[(size_t)p] = x + g.nx * (y + g.ny * z);
+    }
+    // rebuild the flat list with instance i's probes replaced
+    std::vector<int64_t> pi, pc;
+    const int ni = (int)b->inst.size();
+    std::vector<int64_t> first((size_t)ni + 1, 0);
+    for (int k = 0; k < ni; ++k) {
+        first[(size_t)k] = (int64_t)pi.size();
+        if (k == i) {
+            for (int64_t p = 0; p < n; ++p) {
+                pi.push_back(k);
+                pc.push_back(cells[(size_t)p]);
+            }
+        } else {
+            for (int64_t p = b->probe_first[(size_t)k]; p < b->probe_first[(size_t)k + 1]; ++p) {
+                pi.push_back(k);
+                pc.push_back(b->probe_cell[(size_t)p]);
+            }
+        }
+    }
+    first[(size_t)ni] = (int64_t)pi.size();
+    b->probe_inst.swap(pi);
+    b->probe_cell.swap(pc);
+    b->probe_first.swap(first);
+    return batch_upload_probes(b);
+}
+
+kvs_status kvs_batch_set_component(kvs_batch* b, int32_t comp) {
+    if (!b) return KVS_EINVAL;
+    if (comp < 0 || comp > 2) return bfail(b, KVS_EINVAL, "component must be 0..2");
+    b->comp = comp;
+    b->trace_steps = 0;
+    b->graph_valid = false;
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
+    if (!b) return KVS_EINVAL;
+    if (nsteps < 0) return bfail(b, KVS_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return KVS_OK;
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        kvs_ctx* c = b->inst[i];
+        const std::string who = "instance " + std::to_string(i) + ": ";
+        if (!c->have_material || c->hetero) return bfail(b, KVS_ESTATE, who + "needs a uniform material");
+        if (!c->have_dt) return bfail(b, KVS_ESTATE, who + "no time step set");
+        if (c->step != b->step) return bfail(b, KVS_ESTATE, who + "stepped outside the batch");
+        const int64_t n_env = (int64_t)c->env.size();
+        for (int64_t n = b->step; n < std::min(b->step + nsteps, n_env); ++n)
+            if (c->env[(size_t)n] != 0.0 && !c->fs_current)
+                return bfail(b, KVS_ESTATE, who + "envelope on but no current projection");
+    }
+    BATCH_HIP(b, hipSetDevice(b->device));
+    const int64_t np = (int64_t)b->probe_inst.size();
+    if (np > 0 && b->trace_steps + nsteps > b->trace_cap) {
+        const int64_t cap = std::max<int64_t>(b->trace_steps + nsteps, 2 * b->trace_cap);
+        double* nb = nullptr;
+        BATCH_HIP(b, hipMalloc(&nb, sizeof(double) * np * cap));
+        if (b->traces && b->trace_steps > 0)
+            BATCH_HIP(b, hipMemcpyAsync(nb, b->traces, sizeof(double) * np * b->trace_steps, hipMemcpyDeviceToDevice,
+                                        b->stream));
+        BATCH_HIP(b, hipStreamSynchronize(b->stream));
+        dfree(b->traces);
+        b->traces = nb;
+        b->trace_cap = cap;
+        b->graph_valid = false;
+    }
+    BATCH_HIP(b, kvs_batch_prepare(b));
+    BATCH_HIP(b, kvs_batch_run(b, nsteps));
+    for (kvs_ctx* c : b->inst) {
+        if (nsteps & 1) c->cur = 1 - c->cur;
+        c->step += nsteps;
+    }
+    b->step += nsteps;
+    if (np > 0) b->trace_steps += nsteps;
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_reset(kvs_batch* b) {
+    if (!b) return KVS_EINVAL;
+    for (kvs_ctx* c : b->inst) {
+        kvs_status s = kvs_reset_state(c);
+        if (s != KVS_OK) return bfail(b, s, c->err);
+    }
+    b->step = 0;
+    b->trace_steps = 0;
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_trace_count(const kvs_batch* b, int64_t* n) {
+    if (!b || !n) return KVS_EINVAL;
+    *n = b->trace_steps;
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_read_traces(kvs_batch* b, int32_t i, double* out, int64_t cap, int64_t* n_written) {
+    if (!b) return KVS_EINVAL;
+    if (!kvs_batch_instance(b, i)) return bfail(b, KVS_EINVAL, "instance out of range");
+    if (cap < 0 || (cap > 0 && !out)) return bfail(b, KVS_EINVAL, "bad output buffer");
+    const int64_t np = (int64_t)b->probe_inst.size();
+    const int64_t p0 = b->probe_first[(size_t)i], p1 = b->probe_first[(size_t)i + 1];
+    const int64_t per = p1 - p0;
+    std::vector<double> all((size_t)(np * b->trace_steps));
+    if (!all.empty()) {
+        BATCH_HIP(b, hipMemcpyAsync(all.data(), b->traces, sizeof(double) * all.size(), hipMemcpyDeviceToHost,
+                                    b->stream));
+    }
+    BATCH_HIP(b, hipStreamSynchronize(b->stream));
+    int64_t w = 0;
+    for (int64_t s = 0; s < b->trace_steps && w < cap; ++s)
+        for (int64_t p = 0; p < per && w < cap; ++p) out[w++] = all[(size_t)(s * np + p0 + p)];
+    if (n_written) *n_written = w;
+    return KVS_OK;
+}
+
 }  // extern "C"

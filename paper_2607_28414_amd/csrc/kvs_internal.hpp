@@ -97,6 +97,36 @@ struct kvs_ctx {
 
 inline int ncomp_of(int comp) { return comp == 3 ? 3 : 1; }
 
+// A batch of homogeneous instances advanced together (one launch per step
+// covering every instance's tiles, the step loop replayed as a hipGraph).
+struct kvs_batch {
+    std::vector<kvs_ctx*> inst;
+    int device = 0;
+    int prec = KVS_FP32;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int comp = 2;
+    int64_t step = 0;  // common step index of all instances
+
+    // device tables (rebuilt when the instances' parameters change)
+    void* dev_params = nullptr;  // BatchInst<T>[n], then the envelopes
+    size_t params_bytes = 0;
+    void* dev_work = nullptr;    // int4[nwork]
+    int nwork = 0;
+    bool viscous = false;
+    // probes: flat (instance, cell) list and traces [slot][nprobes] doubles
+    std::vector<int64_t> probe_inst, probe_cell;
+    std::vector<int64_t> probe_first;  // first probe of instance i (size n+1)
+    void* dev_probes = nullptr;        // int64 pairs
+    double* traces = nullptr;
+    int64_t trace_cap = 0, trace_steps = 0;
+    // cached graph for (start step, nsteps, first trace slot)
+    hipGraphExec_t graph = nullptr;
+    bool graph_valid = false;
+    int64_t graph_start = -1, graph_steps = 0, graph_trace0 = -1;
+};
+
 // ---- launchers (kvs_step.hip) -------------------------------------------
 // One FDTD step from (u[cur], w[cur]) into (u[1-cur], w[1-cur]) with source
 // amplitude gn (0: no force read).  Returns the launch error.
@@ -114,6 +144,11 @@ hipError_t kvs_launch_zero_boundary(kvs_ctx* c, void* field3);
 // stable dt: per-cell bound reduced to its minimum in *out (device double)
 hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho, const double* deta,
                                 double* partial, int64_t npartial, double* out);
+
+// batched stepping (kvs_step.hip): refresh the device parameter table, then
+// replay (or capture) the graph of nsteps steps starting at b->step
+hipError_t kvs_batch_prepare(kvs_batch* b);
+hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps);
 
 // ---- projection (kvs_cg.hip) ---------------------------------------------
 kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep);

@@ -149,8 +149,8 @@ __device__ __forceinline__ void vlds_write(T* p, const T (&a)[V]) {
 // field); a wavefront covers TX = 64 VEC cells of one x row, a block BY rows.
 // LDS row layout: [pad][left halo][TX cells][right halo][pad], so that every
 // lane's VEC-wide write is naturally aligned, including the halo writes.
-template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WPE>
-__global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(const StepArgs<T> a) {
+template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC>
+__device__ __forceinline__ void step_tile(const StepArgs<T>& a, int bx, int by, int bz) {
     static_assert(BY >= 3 && 2 * BY <= 64, "halo lane assignment needs 3 <= BY <= 32");
     constexpr int NQ = 3 + (VISC ? 3 : 0) + (HET ? 1 : 0);
     constexpr int QG = VISC ? 6 : 3;
@@ -160,12 +160,6 @@ __global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) 
     __shared__ T lds[2][NQ][BY + 3][W];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int B = a.gx * a.gy * a.gz;
-    const int t = a.remap ? tile_of(blockIdx.x, B) : (int)blockIdx.x;
-    const int bx = t % a.gx;
-    const int by = (t / a.gx) % a.gy;
-    const int bz = t / (a.gx * a.gy);
-
     const int nx = a.nx, ny = a.ny;
     const int i0 = bx * TX + VEC * tx;  // first of this lane's cells
     const int j = by * BY + ty;
@@ -370,6 +364,36 @@ __global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) 
             eta_c[v] = eta_n[v];
         }
     }
+}
+
+// One context: tile from the block index (XCD-contiguous order when remap).
+template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WPE>
+__global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(const StepArgs<T> a) {
+    const int B = a.gx * a.gy * a.gz;
+    const int t = a.remap ? tile_of(blockIdx.x, B) : (int)blockIdx.x;
+    step_tile<T, HET, VISC, FORCE, BY, VEC>(a, t % a.gx, (t / a.gx) % a.gy, t / (a.gx * a.gy));
+}
+
+// Batched homogeneous instances: one launch covers every instance's tiles
+// through a work list (instance, bx, by, bz).  `parity` (steps since the
+// table was built, mod 2) selects which ping-pong buffers are current; the
+// absolute step n indexes each instance's envelope.
+template <typename T>
+struct BatchInst {
+    StepArgs<T> a[2];  // [parity]: u, w current / next swapped
+    const double* env;
+    long long n_env;
+};
+
+template <typename T, bool VISC, bool FORCE, int BY, int VEC>
+__global__ __launch_bounds__(64 * BY) void batch_step_kernel(const BatchInst<T>* inst, const int4* work, int nwork,
+                                                             long long n, int parity) {
+    const int t = tile_of(blockIdx.x, nwork);
+    const int4 wi = work[t];
+    const BatchInst<T>& bi = inst[wi.x];
+    StepArgs<T> a = bi.a[parity];
+    a.gn = n < bi.n_env ? T(bi.env[n]) : T(0);
+    step_tile<T, false, VISC, FORCE, BY, VEC>(a, wi.y, wi.z, wi.w);
 }
 
 // Step-kernel variants (tile rows BY, cells per lane VEC) chosen by
@@ -680,4 +704,169 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
                        (int)g.nz, S, partial, partial + nb);
     hipLaunchKernelGGL(minmax_finalize_kernel, dim3(1), dim3(256), 0, c->stream, partial, partial + nb, nb, out);
     return hipGetLastError();
+}
+
+// ---- batched stepping -------------------------------------------------------
+
+namespace {
+
+constexpr int kBatchBY = 8;
+constexpr int kBatchVEC = 1;
+constexpr int kBatchChunk = 32;
+
+template <typename T>
+StepArgs<T> instance_args(kvs_ctx* c, int cur) {
+    const kvs_grid& g = c->grid;
+    StepArgs<T> a{};
+    a.u = static_cast<const T*>(c->u[cur]);
+    a.w = static_cast<const T*>(c->w[cur]);
+    a.un = static_cast<T*>(c->u[1 - cur]);
+    a.wn = static_cast<T*>(c->w[1 - cur]);
+    a.FS = static_cast<const T*>(c->FS);
+    a.N = c->N;
+    a.nx = (int)g.nx;
+    a.ny = (int)g.ny;
+    a.nz = (int)g.nz;
+    a.gx = (a.nx + 64 * kBatchVEC - 1) / (64 * kBatchVEC);
+    a.gy = (a.ny + kBatchBY - 1) / kBatchBY;
+    a.kchunk = std::min(kBatchChunk, a.nz - 2);
+    a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
+    a.L = c->sponge_cells;
+    a.invL = a.L > 0 ? T(1.0 / a.L) : T(0);
+    a.ihx2 = T(1.0 / (g.hx * g.hx));
+    a.ihy2 = T(1.0 / (g.hy * g.hy));
+    a.ihz2 = T(1.0 / (g.hz * g.hz));
+    a.G0 = T(c->G0);
+    a.eta_dt0 = T(c->eta0 / c->dt);
+    a.crho0 = T(c->dt * c->dt / c->rho0);
+    a.inv_dt = T(1.0 / c->dt);
+    a.gn = T(0);
+    a.half_dt_smax = T(0.5 * c->sigma_max * c->dt);
+    a.remap = 1;
+    return a;
+}
+
+template <typename T>
+__global__ void batch_probe_kernel(const BatchInst<T>* inst, const long long* probes, int np, int comp, int parity,
+                                   double* out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const StepArgs<T>& a = inst[probes[2 * p]].a[parity];
+    out[p] = (double)a.un[comp * a.N + probes[2 * p + 1]];  // u after the step
+}
+
+template <typename T>
+hipError_t prepare_t(kvs_batch* b) {
+    const int n = (int)b->inst.size();
+    std::vector<BatchInst<T>> params((size_t)n);
+    std::vector<int4> work;
+    bool visc = false;
+    size_t env_total = 0;
+    for (int i = 0; i < n; ++i) env_total += b->inst[(size_t)i]->env.size();
+    const size_t pbytes = sizeof(BatchInst<T>) * (size_t)n;
+    const size_t ebytes = sizeof(double) * std::max<size_t>(env_total, 1);
+    hipError_t e = hipSuccess;
+    if (!b->dev_params || b->params_bytes < pbytes + ebytes) {
+        if (b->dev_params) e = hipFree(b->dev_params);
+        b->dev_params = nullptr;
+        if (e == hipSuccess) e = hipMalloc(&b->dev_params, pbytes + ebytes);
+        if (e != hipSuccess) return e;
+        b->params_bytes = pbytes + ebytes;
+        b->graph_valid = false;  // the graph holds the old table's address
+    }
+    double* env_dev = reinterpret_cast<double*>(static_cast<char*>(b->dev_params) + pbytes);
+    std::vector<double> env_host(std::max<size_t>(env_total, 1), 0.0);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        kvs_ctx* c = b->inst[(size_t)i];
+        params[(size_t)i].a[0] = instance_args<T>(c, c->cur);
+        params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur);
+        params[(size_t)i].env = env_dev + off;
+        params[(size_t)i].n_env = (long long)c->env.size();
+        std::copy(c->env.begin(), c->env.end(), env_host.begin() + off);
+        off += c->env.size();
+        visc = visc || c->viscous;
+        if (!b->dev_work) {
+            const StepArgs<T>& a = params[(size_t)i].a[0];
+            for (int bz = 0; bz < a.gz; ++bz)
+                for (int by = 0; by < a.gy; ++by)
+                    for (int bx = 0; bx < a.gx; ++bx) work.push_back(make_int4(i, bx, by, bz));
+        }
+    }
+    e = hipMemcpyAsync(b->dev_params, params.data(), pbytes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(env_dev, env_host.data(), ebytes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !b->dev_work) {
+        e = hipMalloc(&b->dev_work, sizeof(int4) * work.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->dev_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice,
+                               b->stream);
+        b->nwork = (int)work.size();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (visc != b->viscous) b->graph_valid = false;
+    b->viscous = visc;
+    return e;
+}
+
+template <typename T, bool VISC, bool FORCE>
+void launch_batch_step(kvs_batch* b, long long n, int parity) {
+    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, kBatchBY, kBatchVEC>), dim3(b->nwork),
+                       dim3(64, kBatchBY), 0, b->stream, static_cast<const BatchInst<T>*>(b->dev_params),
+                       static_cast<const int4*>(b->dev_work), b->nwork, n, parity);
+}
+
+template <typename T>
+hipError_t capture_t(kvs_batch* b, int64_t nsteps) {
+    const int np = (int)b->probe_inst.size();
+    for (int64_t q = 0; q < nsteps; ++q) {
+        const int64_t n = b->step + q;
+        bool force = false;
+        for (kvs_ctx* c : b->inst) force = force || (n < (int64_t)c->env.size() && c->env[(size_t)n] != 0.0);
+        const int parity = (int)(q & 1);
+        if (b->viscous)
+            force ? launch_batch_step<T, true, true>(b, n, parity) : launch_batch_step<T, true, false>(b, n, parity);
+        else
+            force ? launch_batch_step<T, false, true>(b, n, parity) : launch_batch_step<T, false, false>(b, n, parity);
+        if (np > 0)
+            hipLaunchKernelGGL(batch_probe_kernel<T>, dim3((np + 255) / 256), dim3(256), 0, b->stream,
+                               static_cast<const BatchInst<T>*>(b->dev_params),
+                               static_cast<const long long*>(b->dev_probes), np, b->comp, parity,
+                               b->traces + (b->trace_steps + q) * np);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t kvs_batch_prepare(kvs_batch* b) {
+    return b->prec == KVS_FP32 ? prepare_t<float>(b) : prepare_t<double>(b);
+}
+
+hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
+    // Replay the cached graph when it was captured for the same start step,
+    // step count and trace slot (the parameter table it reads was refreshed
+    // in place by kvs_batch_prepare); otherwise capture a new one.
+    const bool hit = b->graph_valid && b->graph && b->graph_start == b->step && b->graph_steps == nsteps &&
+                     b->graph_trace0 == b->trace_steps;
+    hipError_t e = hipSuccess;
+    if (!hit) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        b->graph_valid = false;
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t le = b->prec == KVS_FP32 ? capture_t<float>(b, nsteps) : capture_t<double>(b, nsteps);
+            e = hipStreamEndCapture(b->stream, &graph);
+            if (e == hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        b->graph_valid = true;
+        b->graph_start = b->step;
+        b->graph_steps = nsteps;
+        b->graph_trace0 = b->trace_steps;
+    }
+    return hipGraphLaunch(b->graph, b->stream);
 }

@@ -84,6 +84,17 @@ SIGNATURES = {
     "kvs_reset_state": ([_P], C.c_int),
     "kvs_enable_kernel_timing": ([_P, C.c_int32], C.c_int),
     "kvs_num_step_variants": ([], C.c_int32),
+    "kvs_batch_create": ([C.POINTER(kvs_grid), C.c_int32, C.POINTER(kvs_opts), C.POINTER(C.c_void_p)], C.c_int),
+    "kvs_batch_destroy": ([_P], None),
+    "kvs_batch_last_error": ([_P], C.c_char_p),
+    "kvs_batch_instance": ([_P, C.c_int32], C.c_void_p),
+    "kvs_batch_share_projection": ([_P, C.c_int32, C.c_int32], C.c_int),
+    "kvs_batch_set_probes": ([_P, C.c_int32, _I64, C.c_int64], C.c_int),
+    "kvs_batch_set_component": ([_P, C.c_int32], C.c_int),
+    "kvs_batch_step": ([_P, C.c_int64], C.c_int),
+    "kvs_batch_reset": ([_P], C.c_int),
+    "kvs_batch_trace_count": ([_P, _I64], C.c_int),
+    "kvs_batch_read_traces": ([_P, C.c_int32, _D, C.c_int64, _I64], C.c_int),
     "kvs_set_step_variant": ([_P, C.c_int32], C.c_int),
     "kvs_set_step_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
@@ -286,3 +297,67 @@ def kvs_autotune_step(ctx, trial_steps=20):
 
 def kvs_set_step_tuning(ctx, v, zchunk=0, remap=True):
     _check(lib().kvs_set_step_tuning(ctx, int(v), int(zchunk), int(bool(remap))), ctx)
+
+
+# ---- batches ----------------------------------------------------------------
+
+def _bcheck(status, b):
+    if status != KVS_OK:
+        msg = lib().kvs_batch_last_error(b)
+        raise KvsError(status, msg.decode() if msg else "")
+
+
+def kvs_batch_create(grids, precision=KVS_FP32, sponge_cells=0, sponge_sigma_max=-1.0, device=0, stream=None):
+    arr = (kvs_grid * len(grids))(*[kvs_grid(int(g[0]), int(g[1]), int(g[2]), float(g[3]), float(g[4]), float(g[5]))
+                                    for g in grids])
+    o = kvs_opts(int(precision), int(sponge_cells), float(sponge_sigma_max), int(device), stream or None)
+    out = C.c_void_p()
+    _bcheck(lib().kvs_batch_create(arr, len(grids), C.byref(o), C.byref(out)), None)
+    return out
+
+
+def kvs_batch_destroy(b):
+    lib().kvs_batch_destroy(b)
+
+
+def kvs_batch_instance(b, i):
+    p = lib().kvs_batch_instance(b, int(i))
+    if not p:
+        raise KvsError(KVS_EINVAL, f"no instance {i}")
+    return C.c_void_p(p)
+
+
+def kvs_batch_share_projection(b, src, dst):
+    _bcheck(lib().kvs_batch_share_projection(b, int(src), int(dst)), b)
+
+
+def kvs_batch_set_probes(b, i, ijk):
+    a = np.ascontiguousarray(np.asarray(ijk, dtype=np.int64).reshape(-1, 3))
+    _bcheck(lib().kvs_batch_set_probes(b, int(i), a.ctypes.data_as(_I64) if len(a) else None, len(a)), b)
+
+
+def kvs_batch_set_component(b, comp):
+    _bcheck(lib().kvs_batch_set_component(b, int(comp)), b)
+
+
+def kvs_batch_step(b, nsteps):
+    _bcheck(lib().kvs_batch_step(b, int(nsteps)), b)
+
+
+def kvs_batch_reset(b):
+    _bcheck(lib().kvs_batch_reset(b), b)
+
+
+def kvs_batch_trace_count(b):
+    v = C.c_int64()
+    _bcheck(lib().kvs_batch_trace_count(b, C.byref(v)), b)
+    return v.value
+
+
+def kvs_batch_read_traces(b, i, nprobes):
+    n = kvs_batch_trace_count(b)
+    out = np.empty((n, nprobes))
+    nw = C.c_int64()
+    _bcheck(lib().kvs_batch_read_traces(b, int(i), _dptr(out), out.size, C.byref(nw)), b)
+    assert nw.value == out.size
+    return out

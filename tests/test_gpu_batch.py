@@ -1,0 +1,151 @@
+"""Batched sweeps: many homogeneous instances advanced by one launch per step
+(replayed as a hipGraph), checked instance by instance against the oracle
+and against single-context stepping."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.analysis import rel_l2
+from workloads import gaussian_push, x_line_probes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kvs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2607_28414_amd import kvs as k
+    k.lib()
+    return k
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+H = 0.25e-3
+CASES = [  # (edge or (nx, ny, nz), G, eta)
+    ((24, 24, 24), 2e3, 0.0),
+    ((30, 28, 26), 5e3, 0.7),
+    ((32, 32, 32), 1e3, 1.5),
+    ((32, 32, 32), 8e3, 0.2),
+    ((40, 22, 34), 3e3, 0.0),
+]
+L_SPONGE = 4
+NSTEPS = 90
+
+
+def setup_instance(kvs, ctx, grid, G, eta, F, FS=None):
+    """Uniform medium, dt = 0.4 x limit, 30 us push; the projected force is
+    the given FS (the oracle's, so that only stepping is compared), else the
+    GPU projection of F."""
+    kvs.kvs_set_material_uniform(ctx, G, 1000.0, eta)
+    dt = 0.4 * kvs.kvs_stable_dt(ctx)
+    kvs.kvs_set_dt(ctx, dt)
+    env = np.ones(max(1, int(round(30e-6 / dt))))
+    kvs.kvs_set_envelope(ctx, env)
+    if FS is not None:
+        kvs.kvs_set_projected_force(ctx, FS)
+    else:
+        kvs.kvs_set_force(ctx, F)
+        kvs.kvs_project(ctx, tol=1e-12)
+    return dt, env
+
+
+def make_batch(kvs, precision):
+    grids = [tuple(s) + (H, H, H) for s, _, _ in CASES]
+    b = kvs.kvs_batch_create(grids, precision=precision, sponge_cells=L_SPONGE, sponge_sigma_max=800.0)
+    info = []
+    for i, ((shape), G, eta) in enumerate(CASES):
+        grid = grids[i]
+        ctx = kvs.kvs_batch_instance(b, i)
+        F = gaussian_push(grid, 0.75e-3, 1.5e-3, 1e4)
+        FS_o, _, _ = oracle.project(grid, F, tol=1e-12)
+        dt, env = setup_instance(kvs, ctx, grid, G, eta, F, FS=FS_o)
+        probes = x_line_probes(grid)
+        kvs.kvs_batch_set_probes(b, i, probes)
+        info.append((grid, G, eta, FS_o, dt, env, probes))
+    kvs.kvs_batch_set_component(b, 2)
+    return b, info
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_instances_match_oracle(kvs, precision):
+    say(f"case batch vs oracle precision {precision}")
+    b, info = make_batch(kvs, precision)
+    try:
+        kvs.kvs_batch_step(b, NSTEPS)
+        traces = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    for i, (grid, G, eta, FS_o, dt, env, probes) in enumerate(info):
+        _, _, tr_o = oracle.run(grid, G, 1000.0, eta, dt, NSTEPS, FS=FS_o, env=env, probes=probes, comp=2,
+                                sponge_cells=L_SPONGE, sigma_max=800.0)
+        err = rel_l2(traces[i], tr_o[:, :, 0])
+        say(f"instance {i}: rel L2 {err:.2e}")
+        assert err < (1e-12 if precision == 0 else 2e-5), (i, err)
+
+
+def test_batch_equals_single_context_bitwise_and_replays(kvs):
+    """FP32: the batched step computes exactly what the single-context step
+    (same tile shape) computes; a replayed graph after reset and a run split
+    at an odd step give identical traces."""
+    say("case batch bitwise / replay / odd split")
+    b, info = make_batch(kvs, 1)
+    try:
+        kvs.kvs_batch_step(b, NSTEPS)
+        first = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+        kvs.kvs_batch_reset(b)
+        kvs.kvs_batch_step(b, NSTEPS)  # same start, steps, trace slot: graph replay
+        second = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+        kvs.kvs_batch_reset(b)
+        kvs.kvs_batch_step(b, 37)
+        kvs.kvs_batch_step(b, NSTEPS - 37)
+        split = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+        shp = [(g[2], g[1], g[0]) for g, *_ in info]
+        states = [kvs.kvs_get_state(kvs.kvs_batch_instance(b, i), shp[i]) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    for i in range(len(info)):
+        assert np.array_equal(first[i], second[i]) and np.array_equal(first[i], split[i])
+        assert states[i][2] == NSTEPS
+    # single contexts, tile shape of the batch (64 x 8, one cell per lane)
+    for i, (grid, G, eta, FS_o, dt, env, probes) in enumerate(info):
+        ctx = kvs.kvs_create(grid, precision=1, sponge_cells=L_SPONGE, sponge_sigma_max=800.0)
+        try:
+            setup_instance(kvs, ctx, grid, G, eta, None, FS=FS_o)
+            kvs.kvs_set_probes(ctx, probes, 2)
+            kvs.kvs_set_step_variant(ctx, 1)
+            kvs.kvs_step(ctx, NSTEPS)
+            tr = kvs.kvs_read_traces(ctx, len(probes), 1)[:, :, 0]
+        finally:
+            kvs.kvs_destroy(ctx)
+        assert np.array_equal(tr, first[i]), i
+
+
+def test_batch_shared_projection_and_call_order(kvs):
+    say("case batch share projection / call order")
+    grid = (32, 32, 32, H, H, H)
+    b = kvs.kvs_batch_create([grid, grid], precision=1, sponge_cells=L_SPONGE)
+    try:
+        F = gaussian_push(grid, 0.75e-3, 1.5e-3, 1e4)
+        c0, c1 = kvs.kvs_batch_instance(b, 0), kvs.kvs_batch_instance(b, 1)
+        setup_instance(kvs, c0, grid, 2e3, 0.3, F)
+        kvs.kvs_set_material_uniform(c1, 6e3, 1000.0, 0.9)
+        kvs.kvs_set_dt(c1, 0.4 * kvs.kvs_stable_dt(c1))
+        kvs.kvs_set_envelope(c1, [1.0, 1.0])
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_batch_step(b, 3)  # instance 1 has no projection
+        assert e.value.status == kvs.KVS_ESTATE
+        kvs.kvs_batch_share_projection(b, 0, 1)
+        shp = (32, 32, 32)
+        assert np.array_equal(kvs.kvs_get_projected_force(c0, shp), kvs.kvs_get_projected_force(c1, shp))
+        kvs.kvs_batch_step(b, 3)
+        kvs.kvs_step(c1, 1)  # outside the batch
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_batch_step(b, 1)
+        assert e.value.status == kvs.KVS_ESTATE
+    finally:
+        kvs.kvs_batch_destroy(b)
