@@ -1,11 +1,18 @@
 """Benchmark of the shear solver's hot path on one MI355X.
 
-One benchmark step is one whole simulation of the 256^3 heterogeneous
-inclusion workload (FP32 stencil state, FP64 projection): return the medium
-to rest, take the force pattern from device memory, project it (divergence,
-Jacobi-PCG to 1e-8, gradient subtraction), advance 4000 FDTD steps with the
-push envelope and the lateral-line probe traces, and read the traces back.
-The material, force pattern and probes are resident in HBM before timing.
+Default workload (--workload inclusions): one benchmark step is one whole
+simulation of the 256^3 heterogeneous inclusion workload (FP32 stencil
+state, FP64 projection): return the medium to rest, take the force pattern
+from device memory, project it (divergence, Jacobi-PCG to 1e-8, gradient
+subtraction), advance 4000 FDTD steps with the push envelope and the
+lateral-line probe traces, and read the traces back.  The material, force
+pattern and probes are resident in HBM before timing.
+
+--workload batch: one benchmark step is the 64-instance homogeneous sweep
+(edges 96..192, G and eta from the sweep values): all instances to rest, one
+projection per distinct grid shared by its instances, 2000 steps of every
+instance as one replayed hipGraph (one launch per step over all instances),
+lateral-line traces read back.
 
 value = interior cell-updates of the timed steps / timed wall time
         (whole job, projection included), in Gcell-updates/s.
@@ -34,6 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["inclusions", "batch"], default="inclusions")
     ap.add_argument("--grid", type=int, default=256, help="cubic grid edge of the inclusion workload")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
@@ -63,12 +71,110 @@ def cpu_baseline(w, dt, smax, FS_host, nsteps):
                       f"(FP64 C oracle, OpenMP), {el:.1f} s; projection not included"}
 
 
+def run_batch(args):
+    """The 64-instance batched sweep; returns the result line."""
+    import numpy as np
+    import torch
+
+    from paper_2607_28414_amd import kvs
+    from workloads import cfg3_batch_draws, gaussian_push, x_line_probes
+
+    torch.cuda.set_device(0)
+    h = 0.25e-3
+    draws = cfg3_batch_draws(64)
+    grids = [(e, e, e, h, h, h) for e, _, _, _ in draws]
+    log(f"bench: building 64-instance batch ({sum(e ** 3 for e, *_ in draws) / 1e6:.0f} M cells)")
+    b = kvs.kvs_batch_create(grids, precision=kvs.KVS_FP32, sponge_cells=8, sponge_sigma_max=-1.0,
+                             stream=torch.cuda.current_stream().cuda_stream)
+    nsteps = 2000
+    try:
+        first_of = {}
+        F_dev = {}
+        n_push = []
+        for i, (e, G, rho, eta) in enumerate(draws):
+            ctx = kvs.kvs_batch_instance(b, i)
+            kvs.kvs_set_material_uniform(ctx, G, rho, eta)
+            dt = 0.4 * kvs.kvs_stable_dt(ctx)
+            kvs.kvs_set_dt(ctx, dt)
+            env = np.ones(int(round(100e-6 / dt)))
+            n_push.append(min(len(env), nsteps))
+            kvs.kvs_set_envelope(ctx, env)
+            kvs.kvs_batch_set_probes(b, i, x_line_probes(grids[i]))
+            if e not in first_of:
+                first_of[e] = i
+                F_dev[e] = torch.from_numpy(gaussian_push(grids[i], 1e-3, 4e-3, 1e4)).to("cuda")
+        kvs.kvs_batch_set_component(b, 2)
+        bv, bz, bms = kvs.kvs_batch_autotune(b, 5)
+        log(f"bench: batch tile variant {bv}, z planes {bz} ({', '.join(f'{m:.2f}' for m in bms)} ms per step)")
+        cells = [(e - 2) ** 3 for e, *_ in draws]
+
+        def one_step():
+            kvs.kvs_batch_reset(b)
+            reps = {}
+            for e, i in first_of.items():
+                ctx = kvs.kvs_batch_instance(b, i)
+                kvs.kvs_set_force_device(ctx, F_dev[e].data_ptr(), 0)
+                reps[e] = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_JACOBI)
+            for i, (e, *_) in enumerate(draws):
+                if first_of[e] != i:
+                    kvs.kvs_batch_share_projection(b, first_of[e], i)
+            kvs.kvs_batch_step(b, nsteps)
+            tr = [kvs.kvs_batch_read_traces(b, i, grids[i][0]) for i in range(len(draws))]
+            return reps, tr
+
+        for q in range(args.warmup):
+            log(f"bench: warmup step {q} (graph capture)")
+            one_step()
+        torch.cuda.synchronize()
+        log(f"bench: timing {args.steps} steps")
+        t0 = time.perf_counter()
+        for q in range(args.steps):
+            reps, tr = one_step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # stepping alone: one replayed graph, between two device synchronisations
+        kvs.kvs_batch_reset(b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kvs.kvs_batch_step(b, nsteps)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t1) * 1e3
+        assert all(np.all(np.isfinite(t)) for t in tr), "non-finite traces"
+    finally:
+        kvs.kvs_batch_destroy(b)
+    total = sum(cells) * nsteps
+    value = args.steps * total / el / 1e9
+    bytes_total = 48.0 * total + 12.0 * sum(c * p for c, p in zip(cells, n_push))
+    achieved = bytes_total / (step_ms * 1e-3) / 1e9
+    return {
+        "metric": METRIC, "value": value, "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched sweep: 64 homogeneous instances, edges 96-192 (cubic), G 1-10 kPa, "
+                               "eta 0-1.5 Pa s, rho 1000, dx 0.25 mm, 8-cell sponge, Gaussian push 100 us, "
+                               "projection per distinct grid shared, 2000 steps each as one hipGraph, FP32",
+                   "instances": 64, "total_cells": sum(e ** 3 for e, *_ in draws), "fdtd_steps": nsteps,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "batch_step_kernel (one launch per step over all instances; graph time incl. probes)",
+                     "algorithmic_bytes_per_cell_update": "48 (+12 on push steps)", "graph_ms": step_ms,
+                     "variant": bv, "zchunk": bz},
+        "projection": {"precond": "jacobi", "tol": 1e-8,
+                       "per_grid": {str(e): {"iters": r["iters"], "ms": r["ms"]} for e, r in reps.items()}},
+        "cpu_baseline": None,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the solver has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args)), flush=True)
+        return
     import numpy as np
     import torch
 

@@ -235,6 +235,16 @@ kvs_status kvs_batch_trace_count(const kvs_batch* b, int64_t* nsteps_recorded);
 /* Traces of instance i, [step][probe] doubles, into out (cap doubles). */
 kvs_status kvs_batch_read_traces(kvs_batch* b, int32_t i, double* out, int64_t cap, int64_t* n_written);
 
+/* Batch tile shape (a step-kernel variant, as for kvs_set_step_variant) and
+ * z planes per block (>= 1). */
+kvs_status kvs_batch_set_tuning(kvs_batch* b, int32_t variant, int32_t zchunk);
+/* Time every (variant, z planes in {16, 32, 64}) with trial_steps launches
+ * that do not advance the state, keep the fastest, return it.  Needs every
+ * instance's material and dt.  ms_per_launch (cap entries, one per variant,
+ * best z) may be NULL. */
+kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* variant, int32_t* zchunk,
+                              double* ms_per_launch, int32_t cap);
+
 /* ---- tuning --------------------------------------------------------------- */
 
 /* Number of FDTD step-kernel variants (tile rows x cells per lane). */

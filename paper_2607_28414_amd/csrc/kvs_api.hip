@@ -817,6 +817,7 @@ static kvs_status batch_upload_probes(kvs_batch* b) {
     b->trace_cap = 0;
     b->trace_steps = 0;
     b->graph_valid = false;
+    b->host_traces_valid = false;
     if (np == 0) return KVS_OK;
     std::vector<int64_t> flat(2 * np);
     for (size_t p = 0; p < np; ++p) {
@@ -874,6 +875,7 @@ kvs_status kvs_batch_set_component(kvs_batch* b, int32_t comp) {
     b->comp = comp;
     b->trace_steps = 0;
     b->graph_valid = false;
+    b->host_traces_valid = false;
     return KVS_OK;
 }
 
@@ -915,6 +917,76 @@ kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
     }
     b->step += nsteps;
     if (np > 0) b->trace_steps += nsteps;
+    b->host_traces_valid = false;
+    return KVS_OK;
+}
+
+static void batch_retile(kvs_batch* b) {
+    dfree(b->dev_work);  // rebuilt for the new tile shape by the next prepare
+    b->nwork = 0;
+    b->graph_valid = false;
+}
+
+kvs_status kvs_batch_set_tuning(kvs_batch* b, int32_t variant, int32_t zchunk) {
+    if (!b) return KVS_EINVAL;
+    if (variant < 0 || variant >= kvs_step_variant_count()) return bfail(b, KVS_EINVAL, "no such variant");
+    if (zchunk < 1) return bfail(b, KVS_EINVAL, "zchunk < 1");
+    b->variant = variant;
+    b->zchunk = zchunk;
+    batch_retile(b);
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* variant, int32_t* zchunk,
+                              double* ms_per_launch, int32_t cap) {
+    if (!b) return KVS_EINVAL;
+    if (trial_steps < 1) return bfail(b, KVS_EINVAL, "trial_steps < 1");
+    for (size_t i = 0; i < b->inst.size(); ++i) {
+        kvs_ctx* c = b->inst[i];
+        if (!c->have_material || c->hetero || !c->have_dt)
+            return bfail(b, KVS_ESTATE, "instance " + std::to_string(i) + ": needs uniform material and dt");
+    }
+    BATCH_HIP(b, hipSetDevice(b->device));
+    hipEvent_t e0, e1;
+    BATCH_HIP(b, hipEventCreate(&e0));
+    BATCH_HIP(b, hipEventCreate(&e1));
+    const int nv = kvs_step_variant_count();
+    const int zs[3] = {16, 32, 64};
+    int best_v = b->variant, best_z = b->zchunk;
+    double best = 1e300;
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+        double vbest = 1e300;
+        for (int zi = 0; zi < 3 && e == hipSuccess; ++zi) {
+            b->variant = v;
+            b->zchunk = zs[zi];
+            batch_retile(b);
+            e = kvs_batch_prepare(b);
+            if (e == hipSuccess) e = kvs_batch_trial_launch(b);
+            if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+            for (int q = 0; q < trial_steps && e == hipSuccess; ++q) e = kvs_batch_trial_launch(b);
+            if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            const double per = ms / trial_steps;
+            vbest = std::min(vbest, per);
+            if (e == hipSuccess && per < best) {
+                best = per;
+                best_v = v;
+                best_z = zs[zi];
+            }
+        }
+        if (ms_per_launch && v < cap) ms_per_launch[v] = vbest;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->variant = best_v;
+    b->zchunk = best_z;
+    batch_retile(b);
+    if (e != hipSuccess) return bfail(b, KVS_EDEVICE, std::string("batch autotune: ") + hipGetErrorString(e));
+    if (variant) *variant = best_v;
+    if (zchunk) *zchunk = best_z;
     return KVS_OK;
 }
 
@@ -926,6 +998,7 @@ kvs_status kvs_batch_reset(kvs_batch* b) {
     }
     b->step = 0;
     b->trace_steps = 0;
+    b->host_traces_valid = false;
     return KVS_OK;
 }
 
@@ -942,15 +1015,19 @@ kvs_status kvs_batch_read_traces(kvs_batch* b, int32_t i, double* out, int64_t c
     const int64_t np = (int64_t)b->probe_inst.size();
     const int64_t p0 = b->probe_first[(size_t)i], p1 = b->probe_first[(size_t)i + 1];
     const int64_t per = p1 - p0;
-    std::vector<double> all((size_t)(np * b->trace_steps));
-    if (!all.empty()) {
-        BATCH_HIP(b, hipMemcpyAsync(all.data(), b->traces, sizeof(double) * all.size(), hipMemcpyDeviceToHost,
-                                    b->stream));
+    const int64_t rows = per > 0 ? std::min<int64_t>(b->trace_steps, cap / per) : 0;
+    if (!b->host_traces_valid) {
+        // one contiguous copy of every instance's traces; later calls slice it
+        b->host_traces.resize((size_t)(np * b->trace_steps));
+        if (!b->host_traces.empty())
+            BATCH_HIP(b, hipMemcpyAsync(b->host_traces.data(), b->traces, sizeof(double) * b->host_traces.size(),
+                                        hipMemcpyDeviceToHost, b->stream));
+        BATCH_HIP(b, hipStreamSynchronize(b->stream));
+        b->host_traces_valid = true;
     }
-    BATCH_HIP(b, hipStreamSynchronize(b->stream));
-    int64_t w = 0;
-    for (int64_t s = 0; s < b->trace_steps && w < cap; ++s)
-        for (int64_t p = 0; p < per && w < cap; ++p) out[w++] = all[(size_t)(s * np + p0 + p)];
+    for (int64_t r = 0; r < rows; ++r)
+        std::copy_n(b->host_traces.data() + r * np + p0, per, out + r * per);
+    const int64_t w = rows * per;
     if (n_written) *n_written = w;
     return KVS_OK;
 }

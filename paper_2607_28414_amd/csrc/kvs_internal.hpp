@@ -108,6 +108,8 @@ struct kvs_batch {
     std::string err;
     int comp = 2;
     int64_t step = 0;  // common step index of all instances
+    int variant = 1;   // tile shape (index into the step-kernel variants)
+    int zchunk = 32;   // z planes per block
 
     // device tables (rebuilt when the instances' parameters change)
     void* dev_params = nullptr;  // BatchInst<T>[n], then the envelopes
@@ -121,6 +123,8 @@ struct kvs_batch {
     void* dev_probes = nullptr;        // int64 pairs
     double* traces = nullptr;
     int64_t trace_cap = 0, trace_steps = 0;
+    std::vector<double> host_traces;  // host copy of the traces, valid while
+    bool host_traces_valid = false;   // no step, reset or probe change happened
     // cached graph for (start step, nsteps, first trace slot)
     hipGraphExec_t graph = nullptr;
     bool graph_valid = false;
@@ -148,6 +152,7 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
 // batched stepping (kvs_step.hip): refresh the device parameter table, then
 // replay (or capture) the graph of nsteps steps starting at b->step
 hipError_t kvs_batch_prepare(kvs_batch* b);
+hipError_t kvs_batch_trial_launch(kvs_batch* b);
 hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps);
 
 // ---- projection (kvs_cg.hip) ---------------------------------------------

@@ -710,12 +710,8 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
 
 namespace {
 
-constexpr int kBatchBY = 8;
-constexpr int kBatchVEC = 1;
-constexpr int kBatchChunk = 32;
-
 template <typename T>
-StepArgs<T> instance_args(kvs_ctx* c, int cur) {
+StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int zchunk) {
     const kvs_grid& g = c->grid;
     StepArgs<T> a{};
     a.u = static_cast<const T*>(c->u[cur]);
@@ -727,9 +723,9 @@ StepArgs<T> instance_args(kvs_ctx* c, int cur) {
     a.nx = (int)g.nx;
     a.ny = (int)g.ny;
     a.nz = (int)g.nz;
-    a.gx = (a.nx + 64 * kBatchVEC - 1) / (64 * kBatchVEC);
-    a.gy = (a.ny + kBatchBY - 1) / kBatchBY;
-    a.kchunk = std::min(kBatchChunk, a.nz - 2);
+    a.gx = (a.nx + 64 * vec - 1) / (64 * vec);
+    a.gy = (a.ny + by - 1) / by;
+    a.kchunk = std::min(zchunk, a.nz - 2);
     a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
     a.L = c->sponge_cells;
     a.invL = a.L > 0 ? T(1.0 / a.L) : T(0);
@@ -744,6 +740,20 @@ StepArgs<T> instance_args(kvs_ctx* c, int cur) {
     a.half_dt_smax = T(0.5 * c->sigma_max * c->dt);
     a.remap = 1;
     return a;
+}
+
+// The batch's tile shape, narrowed like the single-context launch: FP64
+// uses one cell per lane and at most 8 rows; two cells per lane need every
+// instance's nx even.
+int batch_variant(const kvs_batch* b) {
+    int v = b->variant;
+    if (v < 0 || v >= kNumVariants) v = 1;
+    bool even = true;
+    for (const kvs_ctx* c : b->inst) even = even && (c->grid.nx % 2 == 0);
+    const bool narrow = b->prec == KVS_FP64 || !even;
+    if (kVariants[v].vec == 2 && narrow) v = kVariants[v].by == 8 ? 1 : 0;
+    if (b->prec == KVS_FP64 && v == 4) v = 1;
+    return v;
 }
 
 template <typename T>
@@ -777,10 +787,12 @@ hipError_t prepare_t(kvs_batch* b) {
     double* env_dev = reinterpret_cast<double*>(static_cast<char*>(b->dev_params) + pbytes);
     std::vector<double> env_host(std::max<size_t>(env_total, 1), 0.0);
     size_t off = 0;
+    const int v = batch_variant(b);
+    const int by = kVariants[v].by, vec = kVariants[v].vec;
     for (int i = 0; i < n; ++i) {
         kvs_ctx* c = b->inst[(size_t)i];
-        params[(size_t)i].a[0] = instance_args<T>(c, c->cur);
-        params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur);
+        params[(size_t)i].a[0] = instance_args<T>(c, c->cur, by, vec, b->zchunk);
+        params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur, by, vec, b->zchunk);
         params[(size_t)i].env = env_dev + off;
         params[(size_t)i].n_env = (long long)c->env.size();
         std::copy(c->env.begin(), c->env.end(), env_host.begin() + off);
@@ -808,11 +820,29 @@ hipError_t prepare_t(kvs_batch* b) {
     return e;
 }
 
+template <typename T, bool VISC, bool FORCE, int BY, int VEC>
+void launch_batch_shape(kvs_batch* b, long long n, int parity) {
+    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, BY, VEC>), dim3(b->nwork), dim3(64, BY), 0, b->stream,
+                       static_cast<const BatchInst<T>*>(b->dev_params), static_cast<const int4*>(b->dev_work),
+                       b->nwork, n, parity);
+}
+
 template <typename T, bool VISC, bool FORCE>
 void launch_batch_step(kvs_batch* b, long long n, int parity) {
-    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, kBatchBY, kBatchVEC>), dim3(b->nwork),
-                       dim3(64, kBatchBY), 0, b->stream, static_cast<const BatchInst<T>*>(b->dev_params),
-                       static_cast<const int4*>(b->dev_work), b->nwork, n, parity);
+    if constexpr (sizeof(T) == 8) {
+        switch (batch_variant(b)) {
+            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1>(b, n, parity);
+            default: return launch_batch_shape<T, VISC, FORCE, 4, 1>(b, n, parity);
+        }
+    } else {
+        switch (batch_variant(b)) {
+            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1>(b, n, parity);
+            case 2: return launch_batch_shape<T, VISC, FORCE, 4, 2>(b, n, parity);
+            case 3: return launch_batch_shape<T, VISC, FORCE, 8, 2>(b, n, parity);
+            case 4: return launch_batch_shape<T, VISC, FORCE, 16, 1>(b, n, parity);
+            default: return launch_batch_shape<T, VISC, FORCE, 4, 1>(b, n, parity);
+        }
+    }
 }
 
 template <typename T>
@@ -837,6 +867,19 @@ hipError_t capture_t(kvs_batch* b, int64_t nsteps) {
 }
 
 }  // namespace
+
+// One uncaptured step launch that only rewrites the next buffers (parity 0,
+// no force): used to time tile shapes without advancing the state.
+hipError_t kvs_batch_trial_launch(kvs_batch* b) {
+    if (b->prec == KVS_FP32) {
+        b->viscous ? launch_batch_step<float, true, false>(b, b->step, 0)
+                   : launch_batch_step<float, false, false>(b, b->step, 0);
+    } else {
+        b->viscous ? launch_batch_step<double, true, false>(b, b->step, 0)
+                   : launch_batch_step<double, false, false>(b, b->step, 0);
+    }
+    return hipGetLastError();
+}
 
 hipError_t kvs_batch_prepare(kvs_batch* b) {
     return b->prec == KVS_FP32 ? prepare_t<float>(b) : prepare_t<double>(b);

@@ -95,6 +95,8 @@ SIGNATURES = {
     "kvs_batch_reset": ([_P], C.c_int),
     "kvs_batch_trace_count": ([_P, _I64], C.c_int),
     "kvs_batch_read_traces": ([_P, C.c_int32, _D, C.c_int64, _I64], C.c_int),
+    "kvs_batch_set_tuning": ([_P, C.c_int32, C.c_int32], C.c_int),
+    "kvs_batch_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_set_step_variant": ([_P, C.c_int32], C.c_int),
     "kvs_set_step_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
@@ -361,3 +363,15 @@ def kvs_batch_read_traces(b, i, nprobes):
     _bcheck(lib().kvs_batch_read_traces(b, int(i), _dptr(out), out.size, C.byref(nw)), b)
     assert nw.value == out.size
     return out
+
+
+def kvs_batch_set_tuning(b, variant, zchunk):
+    _bcheck(lib().kvs_batch_set_tuning(b, int(variant), int(zchunk)), b)
+
+
+def kvs_batch_autotune(b, trial_steps=5):
+    n = kvs_num_step_variants()
+    ms = np.zeros(n)
+    v, z = C.c_int32(), C.c_int32()
+    _bcheck(lib().kvs_batch_autotune(b, int(trial_steps), C.byref(v), C.byref(z), _dptr(ms), n), b)
+    return v.value, z.value, ms

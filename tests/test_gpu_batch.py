@@ -149,3 +149,29 @@ def test_batch_shared_projection_and_call_order(kvs):
         assert e.value.status == kvs.KVS_ESTATE
     finally:
         kvs.kvs_batch_destroy(b)
+
+
+def test_every_batch_tile_shape_matches_oracle(kvs):
+    """Each batch tile shape and a short z chunk give the oracle's traces
+    (FP32 bar), and autotuning leaves the state untouched."""
+    b, info = make_batch(kvs, 1)
+    try:
+        v0, z0, ms = kvs.kvs_batch_autotune(b, 2)
+        assert 0 <= v0 < len(ms) and z0 in (16, 32, 64)
+        for i in range(len(info)):
+            u, w, s = kvs.kvs_get_state(kvs.kvs_batch_instance(b, i), (info[i][0][2], info[i][0][1], info[i][0][0]))
+            assert s == 0 and not u.any() and not w.any()
+        results = {}
+        for v in range(kvs.kvs_num_step_variants()):
+            say(f"case batch shape {v}")
+            kvs.kvs_batch_reset(b)
+            kvs.kvs_batch_set_tuning(b, v, 16)
+            kvs.kvs_batch_step(b, NSTEPS)
+            results[v] = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    for i, (grid, G, eta, FS_o, dt, env, probes) in enumerate(info):
+        _, _, tr_o = oracle.run(grid, G, 1000.0, eta, dt, NSTEPS, FS=FS_o, env=env, probes=probes, comp=2,
+                                sponge_cells=L_SPONGE, sigma_max=800.0)
+        for v, tr in results.items():
+            assert rel_l2(tr[i], tr_o[:, :, 0]) < 2e-5, (v, i)
