@@ -245,6 +245,40 @@ kvs_status kvs_batch_set_tuning(kvs_batch* b, int32_t variant, int32_t zchunk);
 kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* variant, int32_t* zchunk,
                               double* ms_per_launch, int32_t cap);
 
+/* ---- learned preconditioner (a small linear U-Net) -------------------------- */
+
+/* Network z = U(r): e0 = conv(r; 1 -> C0); e1 = conv(pool(e0); C0 -> C1);
+ * bottleneck at 1/4 resolution: conv(pool(e1); C1 -> C2), n_bottleneck - 2
+ * convs C2 -> C2 with dilations 2, 4, ..., conv(C2 -> C1);
+ * g1 = conv(e1 + up(bottleneck); C1 -> C0); g0 = conv(e0 + up(g1); C0 -> C0);
+ * z = conv(g0; C0 -> 1), zero outside the interior.  conv = 3x3x3 (dilated)
+ * cross-correlation with zero padding, no bias, no nonlinearity; pool = mean
+ * of the existing 2x2x2 children; up = nearest neighbour.  Activations and
+ * weights are BF16, accumulation FP32 (MFMA).  Used as the preconditioner of
+ * a flexible PCG on the projection's Poisson problem (not part of the
+ * paper's method; plain CG / Jacobi-PCG remain the reference). */
+typedef struct kvs_unet kvs_unet;
+/* channels = {C0, C1, C2} (NULL: 16, 32, 64; only these are built);
+ * 2 <= n_bottleneck <= 8.  Weights start at zero. */
+kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_unet** out);
+void kvs_unet_destroy(kvs_unet* net);
+const char* kvs_unet_last_error(const kvs_unet* net);
+/* FP32 master weights, layer by layer in network order, each [co][27 * ci]
+ * with k = tap * ci + c, tap = 9 (dz + 1) + 3 (dy + 1) + (dx + 1). */
+int64_t kvs_unet_num_weights(const kvs_unet* net);
+kvs_status kvs_unet_set_weights(kvs_unet* net, const float* w, int64_t n);
+kvs_status kvs_unet_get_weights(const kvs_unet* net, float* w, int64_t n);
+/* z = out_scale * U(in_scale * r) on an nx*ny*nz grid; r and z are FP64
+ * device fields [nz][ny][nx] ordered on `stream` (hipStream_t or NULL). */
+kvs_status kvs_unet_forward(kvs_unet* net, const double* r, double in_scale, double out_scale, double* z, int64_t nx,
+                            int64_t ny, int64_t nz, void* stream);
+/* Verification hook: one MFMA convolution on host BF16 bit patterns,
+ * out[v][co] = sum_k W[co][k] (A[p][c] + B[p/2][c]) with W rows padded to
+ * kvs_unet_conv_kpad(ci) entries (B may be NULL).  Blocks. */
+int64_t kvs_unet_conv_kpad(int32_t ci);
+kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16_t* A, const uint16_t* B, int64_t nx,
+                               int64_t ny, int64_t nz, const uint16_t* W, uint16_t* out);
+
 /* ---- tuning --------------------------------------------------------------- */
 
 /* Number of FDTD step-kernel variants (tile rows x cells per lane). */

@@ -96,6 +96,17 @@ SIGNATURES = {
     "kvs_batch_trace_count": ([_P, _I64], C.c_int),
     "kvs_batch_read_traces": ([_P, C.c_int32, _D, C.c_int64, _I64], C.c_int),
     "kvs_batch_set_tuning": ([_P, C.c_int32, C.c_int32], C.c_int),
+    "kvs_unet_create": ([C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
+    "kvs_unet_destroy": ([_P], None),
+    "kvs_unet_last_error": ([_P], C.c_char_p),
+    "kvs_unet_num_weights": ([_P], C.c_int64),
+    "kvs_unet_set_weights": ([_P, C.POINTER(C.c_float), C.c_int64], C.c_int),
+    "kvs_unet_get_weights": ([_P, C.POINTER(C.c_float), C.c_int64], C.c_int),
+    "kvs_unet_forward": ([_P, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                          C.c_void_p], C.c_int),
+    "kvs_unet_conv_kpad": ([C.c_int32], C.c_int64),
+    "kvs_unet_conv_check": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint16), C.POINTER(C.c_uint16), C.c_int64,
+                             C.c_int64, C.c_int64, C.POINTER(C.c_uint16), C.POINTER(C.c_uint16)], C.c_int),
     "kvs_batch_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_set_step_variant": ([_P, C.c_int32], C.c_int),
     "kvs_set_step_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
@@ -375,3 +386,60 @@ def kvs_batch_autotune(b, trial_steps=5):
     v, z = C.c_int32(), C.c_int32()
     _bcheck(lib().kvs_batch_autotune(b, int(trial_steps), C.byref(v), C.byref(z), _dptr(ms), n), b)
     return v.value, z.value, ms
+
+
+# ---- learned preconditioner -------------------------------------------------
+
+def _ucheck(status, net):
+    if status != KVS_OK:
+        msg = lib().kvs_unet_last_error(net)
+        raise KvsError(status, msg.decode() if msg else "")
+
+
+def kvs_unet_create(channels=(16, 32, 64), n_bottleneck=4):
+    ch = (C.c_int32 * 3)(*channels)
+    out = C.c_void_p()
+    _ucheck(lib().kvs_unet_create(ch, int(n_bottleneck), C.byref(out)), None)
+    return out
+
+
+def kvs_unet_destroy(net):
+    lib().kvs_unet_destroy(net)
+
+
+def kvs_unet_num_weights(net):
+    return lib().kvs_unet_num_weights(net)
+
+
+def kvs_unet_set_weights(net, w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _ucheck(lib().kvs_unet_set_weights(net, w.ctypes.data_as(C.POINTER(C.c_float)), w.size), net)
+
+
+def kvs_unet_get_weights(net):
+    w = np.empty(kvs_unet_num_weights(net), dtype=np.float32)
+    _ucheck(lib().kvs_unet_get_weights(net, w.ctypes.data_as(C.POINTER(C.c_float)), w.size), net)
+    return w
+
+
+def kvs_unet_forward(net, r_ptr, in_scale, out_scale, z_ptr, dims, stream=None):
+    nx, ny, nz = dims
+    _ucheck(lib().kvs_unet_forward(net, C.c_void_p(r_ptr), float(in_scale), float(out_scale), C.c_void_p(z_ptr),
+                                   int(nx), int(ny), int(nz), stream or None), net)
+
+
+def kvs_unet_conv_kpad(ci):
+    return lib().kvs_unet_conv_kpad(int(ci))
+
+
+def kvs_unet_conv_check(ci, co, dil, A_bits, B_bits, dims, W_bits):
+    nx, ny, nz = dims
+    A = np.ascontiguousarray(A_bits, dtype=np.uint16)
+    W = np.ascontiguousarray(W_bits, dtype=np.uint16)
+    B = None if B_bits is None else np.ascontiguousarray(B_bits, dtype=np.uint16)
+    out = np.empty(nx * ny * nz * co, dtype=np.uint16)
+    u16 = C.POINTER(C.c_uint16)
+    _ucheck(lib().kvs_unet_conv_check(int(ci), int(co), int(dil), A.ctypes.data_as(u16),
+                                      B.ctypes.data_as(u16) if B is not None else None, int(nx), int(ny), int(nz),
+                                      W.ctypes.data_as(u16), out.ctypes.data_as(u16)), None)
+    return out

@@ -1,0 +1,74 @@
+"""Pins of the U-Net oracle (CPU): BF16 rounding, convolution, pooling and
+upsampling against independent library routines (torch CPU) and hand
+values."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet
+
+
+def test_bf16_round_hand_values_and_torch():
+    # 1 + 2^-8 is a tie between 1 and 1 + 2^-7: ties go to even (1.0);
+    # 1 + 3 * 2^-8 is a tie between 1 + 2^-7 and 1 + 2^-6 ... -> 1 + 2^-6
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.5, 3.14159, 1e-20, 65504.0], dtype=np.float32)
+    r = unet.bf16_round(vals)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1 + 2 ** -6
+    ref = torch.from_numpy(vals).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(r, ref)
+    x = np.random.default_rng(0).standard_normal(10000).astype(np.float32) * 10.0 ** np.random.default_rng(1).uniform(-8, 8, 10000).astype(np.float32)
+    np.testing.assert_array_equal(unet.bf16_round(x), torch.from_numpy(x).to(torch.bfloat16).double().numpy())
+    np.testing.assert_array_equal(unet.from_bits(unet.to_bits(unet.bf16_round(x))), unet.bf16_round(x))
+
+
+@pytest.mark.parametrize("dil", [1, 2, 3])
+def test_conv3_matches_torch_conv3d(dil):
+    rng = np.random.default_rng(dil)
+    Z, Y, X, CI, CO = 7, 9, 11, 5, 4
+    x = rng.standard_normal((Z, Y, X, CI))
+    W = rng.standard_normal((CO, 27, CI))
+    ours = unet.conv3(x, W, dil)
+    xt = torch.from_numpy(x).permute(3, 0, 1, 2)[None]            # [1][CI][Z][Y][X]
+    wt = torch.from_numpy(W.reshape(CO, 3, 3, 3, CI)).permute(0, 4, 1, 2, 3)  # taps (dz, dy, dx)
+    ref = torch.nn.functional.conv3d(xt, wt, padding=dil, dilation=dil)[0].permute(1, 2, 3, 0).numpy()
+    np.testing.assert_allclose(ours, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_tap_order_hand_case():
+    """tap = 9 (dz + 1) + 3 (dy + 1) + (dx + 1): a single weight on tap
+    9*1 + 3*1 + 2 = 14 (dx = +1) reads the right neighbour."""
+    x = np.zeros((3, 3, 5, 1))
+    x[1, 1, 3, 0] = 2.0
+    W = np.zeros((1, 27, 1))
+    W[0, 14, 0] = 0.5
+    out = unet.conv3(x, W)
+    assert out[1, 1, 2, 0] == 1.0 and np.count_nonzero(out) == 1
+
+
+def test_pool_and_up_against_torch_and_hand_values():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((6, 8, 10, 3))
+    ref = torch.nn.functional.avg_pool3d(torch.from_numpy(x).permute(3, 0, 1, 2)[None], 2)[0].permute(1, 2, 3, 0)
+    np.testing.assert_allclose(unet.pool(x), ref.numpy(), rtol=1e-14)
+    # odd sizes: the last coarse cell averages only the children that exist
+    y = np.arange(3, dtype=float).reshape(1, 1, 3, 1)
+    p = unet.pool(y)
+    assert p.shape == (1, 1, 2, 1) and p[0, 0, 0, 0] == 0.5 and p[0, 0, 1, 0] == 2.0
+    c = rng.standard_normal((2, 3, 2, 2))
+    u = unet.up(c, (3, 5, 4))
+    assert u.shape == (3, 5, 4, 2) and np.array_equal(u[2, 4, 3], c[1, 2, 1]) and np.array_equal(u[0, 1, 0], c[0, 0, 0])
+    up_t = torch.nn.functional.interpolate(torch.from_numpy(c).permute(3, 0, 1, 2)[None], scale_factor=2, mode="nearest")
+    np.testing.assert_array_equal(unet.up(c, (4, 6, 4)), up_t[0].permute(1, 2, 3, 0).numpy())
+
+
+def test_forward_is_linear_and_masked():
+    rng = np.random.default_rng(4)
+    shapes = unet.layer_shapes(16, 32, 64, 3)
+    n = sum(27 * ci * co for ci, co, _ in shapes)
+    w = rng.standard_normal(n) * 0.05
+    r = np.zeros((10, 12, 14))
+    r[1:-1, 1:-1, 1:-1] = rng.standard_normal((8, 10, 12))
+    z = unet.forward(r, 1.0, 2.0, w, nbott=3)
+    assert not z[0].any() and not z[:, :, -1].any() and np.abs(z).max() > 0
+    z2 = unet.forward(r, 1.0, 4.0, w, nbott=3)
+    np.testing.assert_allclose(z2, 2 * z)
