@@ -64,6 +64,7 @@ extern "C" {
 #endif
 
 typedef struct kvs_ctx kvs_ctx;
+typedef struct kvs_unet kvs_unet;
 
 typedef enum {
     KVS_OK = 0,
@@ -96,7 +97,8 @@ typedef struct {
 typedef struct {
     double tol;          /* stop when sqrt(r.r / r0.r0) < tol (Sec. 3.2.3) */
     int64_t max_iter;    /* > 0 */
-    int32_t precond;     /* kvs_precond: NONE = the paper's CG; JACOBI = z = r / diag(A) */
+    int32_t precond;     /* kvs_precond: NONE = the paper's CG; JACOBI = z = r / diag(A); UNET = flexible
+                            PCG with the network set by kvs_set_preconditioner */
     int64_t fixed_iters; /* > 0: run exactly this many iterations, ignore tol (parity mode) */
     int32_t warm_start;  /* != 0: start from the previous phi instead of phi_0 = 0 */
 } kvs_solve_opts;
@@ -161,6 +163,15 @@ kvs_status kvs_set_envelope(kvs_ctx* ctx, const double* g, int64_t n_env);
  * KVS_EBREAKDOWN); f_S is produced in every case but EBREAKDOWN.  `report`
  * may be NULL. */
 kvs_status kvs_project(kvs_ctx* ctx, const kvs_solve_opts* opts, kvs_solve_report* report);
+/* Network used by kvs_project with precond = KVS_PC_UNET (flexible PCG:
+ * z = U(r) with the network's input scaled to unit RMS of r and its output
+ * by h^2 rms(r); beta = z_{k+1}.(r_{k+1} - r_k) / (z_k.r_k); when z.r <= 0
+ * or non-finite that iteration uses z = r / diag(A) instead).  The network
+ * is borrowed: keep it alive while the context uses it; NULL unsets it.
+ * The grid spacings must be equal. */
+kvs_status kvs_set_preconditioner(kvs_ctx* ctx, kvs_unet* net);
+/* Number of Jacobi fallbacks taken by the last flexible solve. */
+kvs_status kvs_last_fallbacks(const kvs_ctx* ctx, int64_t* n);
 /* Inject / read back the projected force f_S (host, 3*N doubles).  Setting
  * it marks it current (no projection needed before stepping). */
 kvs_status kvs_set_projected_force(kvs_ctx* ctx, const double* FS);
@@ -257,7 +268,6 @@ kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* varian
  * weights are BF16, accumulation FP32 (MFMA).  Used as the preconditioner of
  * a flexible PCG on the projection's Poisson problem (not part of the
  * paper's method; plain CG / Jacobi-PCG remain the reference). */
-typedef struct kvs_unet kvs_unet;
 /* channels = {C0, C1, C2} (NULL: 16, 32, 64; only these are built);
  * 2 <= n_bottleneck <= 8.  Weights start at zero. */
 kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_unet** out);
@@ -272,6 +282,30 @@ kvs_status kvs_unet_get_weights(const kvs_unet* net, float* w, int64_t n);
  * device fields [nz][ny][nx] ordered on `stream` (hipStream_t or NULL). */
 kvs_status kvs_unet_forward(kvs_unet* net, const double* r, double in_scale, double out_scale, double* z, int64_t nx,
                             int64_t ny, int64_t nz, void* stream);
+/* Backward pass of the last kvs_unet_forward (same r, in_scale, grid): the
+ * gradient of the raw network output (before out_scale) is dz_scale * dz
+ * (dz: FP64 device field, zero outside the interior).  Writes, or with
+ * accumulate != 0 adds to, the FP32 weight gradient (master layout).
+ * Activation gradients are FP32; each is rounded to BF16 where it feeds a
+ * transposed convolution. */
+kvs_status kvs_unet_backward(kvs_unet* net, const double* r, double in_scale, const double* dz, double dz_scale,
+                             int64_t nx, int64_t ny, int64_t nz, int32_t accumulate, void* stream);
+kvs_status kvs_unet_get_grad(const kvs_unet* net, float* g, int64_t n);
+/* One training sample at unit grid spacing: forward of b (unit RMS, scales
+ * 1), loss L = (z - x)^T A (z - x) / (x^T A x) with A = -lap_1 on the
+ * interior, backward; gradient written or accumulated.  b, x: FP64 device
+ * fields. */
+kvs_status kvs_unet_train_sample(kvs_unet* net, const double* b, const double* x, int64_t nx, int64_t ny, int64_t nz,
+                                 int32_t accumulate, double* loss, void* stream);
+/* Adam (beta 0.9, 0.999, eps 1e-8) on the FP32 master weights with the
+ * gradient averaged over n_samples, then repack the BF16 weights. */
+kvs_status kvs_unet_adam_step(kvs_unet* net, double lr, int32_t n_samples, void* stream);
+/* Training pair generated by the solver itself on context ctx (FP64, force
+ * set): phi* = Jacobi-PCG solution of the current force to 1e-11; x = phi*
+ * (k_snapshot = 0) or the CG error phi* - phi_k after k_snapshot iterations;
+ * b = A x with ctx's spacing; both divided by rms(b) (returned in b_rms).
+ * b, x: device fields of N doubles. */
+kvs_status kvs_unet_make_sample(kvs_ctx* ctx, int64_t k_snapshot, double* b, double* x, double* b_rms);
 /* Verification hook: one MFMA convolution on host BF16 bit patterns,
  * out[v][co] = sum_k W[co][k] (A[p][c] + B[p/2][c]) with W rows padded to
  * kvs_unet_conv_kpad(ci) entries (B may be NULL).  Blocks. */

@@ -108,21 +108,104 @@ def split_weights(flat, shapes):
     return out
 
 
-def forward(r, in_scale, out_scale, flat_w, c0=16, c1=32, c2=64, nbott=4):
-    """Network output z (FP64 [Z][Y][X]) for the residual r [Z][Y][X]."""
+def _identity(x):
+    return np.asarray(x, dtype=np.float64)
+
+
+def forward(r, in_scale, out_scale, flat_w, c0=16, c1=32, c2=64, nbott=4, exact=False, keep=False):
+    """Network output z (FP64 [Z][Y][X]) for the residual r [Z][Y][X].
+    exact=True drops every BF16 rounding (for finite-difference checks);
+    keep=True also returns the stored activations for the backward pass."""
+    rnd = _identity if exact else bf16_round
     shapes = layer_shapes(c0, c1, c2, nbott)
-    Ws = [bf16_round(w) for w in split_weights(flat_w, shapes)]
-    x = bf16_round(np.float32(in_scale * np.asarray(r, dtype=np.float64)))[..., None]
-    e0 = bf16_round(conv3(x, Ws[0]))
-    e1 = bf16_round(conv3(bf16_round(pool(e0)), Ws[1]))
-    b = bf16_round(pool(e1))
+    Ws = [rnd(w) for w in split_weights(flat_w, shapes)]
+    x = rnd(np.float32(in_scale * np.asarray(r, dtype=np.float64)) if not exact else in_scale * np.asarray(r))[..., None]
+    e0 = rnd(conv3(x, Ws[0]))
+    p0 = rnd(pool(e0))
+    e1 = rnd(conv3(p0, Ws[1]))
+    b = rnd(pool(e1))
+    bins = []
     for li in range(2, 2 + nbott):
-        b = bf16_round(conv3(b, Ws[li], shapes[li][2]))
-    i1 = bf16_round(np.float32(e1) + np.float32(up(b, e1.shape[:3])))
-    g1 = bf16_round(conv3(i1, Ws[2 + nbott]))
-    i0 = bf16_round(np.float32(e0) + np.float32(up(g1, e0.shape[:3])))
-    g0 = bf16_round(conv3(i0, Ws[3 + nbott]))
+        bins.append(b)
+        b = rnd(conv3(b, Ws[li], shapes[li][2]))
+    i1 = rnd(np.float32(e1) + np.float32(up(b, e1.shape[:3])) if not exact else e1 + up(b, e1.shape[:3]))
+    g1 = rnd(conv3(i1, Ws[2 + nbott]))
+    i0 = rnd(np.float32(e0) + np.float32(up(g1, e0.shape[:3])) if not exact else e0 + up(g1, e0.shape[:3]))
+    g0 = rnd(conv3(i0, Ws[3 + nbott]))
     z = out_scale * conv3(g0, Ws[4 + nbott])[..., 0]
     m = np.zeros_like(z)
     m[1:-1, 1:-1, 1:-1] = 1.0
-    return z * m
+    z = z * m
+    if keep:
+        return z, dict(x=x, e0=e0, p0=p0, e1=e1, bins=bins, i1=i1, g1=g1, i0=i0, g0=g0, Ws=Ws, shapes=shapes)
+    return z
+
+
+def conv3_adjoint(dy, W, dil=1):
+    """Adjoint of conv3 in its input: dx[v][ci] = sum W[co][t][ci] dy[v - t][co]."""
+    dx = np.zeros(dy.shape[:3] + (W.shape[2],))
+    for t, (dz, dyy, dx_) in enumerate(taps()):
+        dx += shift(dy, -dil * dz, -dil * dyy, -dil * dx_) @ W[:, t, :]
+    return dx
+
+
+def conv3_weight_grad(x, dy, dil=1):
+    """dW[co][t][ci] = sum_v x(v + dil t)[ci] dy[v][co]."""
+    co, ci = dy.shape[3], x.shape[3]
+    g = np.zeros((co, 27, ci))
+    for t, (dz, dyy, dx_) in enumerate(taps()):
+        xs = shift(x, dil * dz, dil * dyy, dil * dx_)
+        g[:, t, :] = dy.reshape(-1, co).T @ xs.reshape(-1, ci)
+    return g
+
+
+def up_adjoint(df, cshape):
+    """Adjoint of nearest upsampling: sum over the children."""
+    Z, Y, X = df.shape[:3]
+    out = np.zeros(tuple(cshape) + df.shape[3:])
+    np.add.at(out, (np.arange(Z)[:, None, None] // 2, np.arange(Y)[None, :, None] // 2,
+                    np.arange(X)[None, None, :] // 2), df)
+    return out
+
+
+def pool_adjoint(dc, fshape):
+    """Adjoint of the children mean: each child gets dc / (children of its parent)."""
+    Z, Y, X = fshape
+    cnt = np.zeros(dc.shape[:3] + (1,))
+    for dz in range(2):
+        for dy in range(2):
+            for dx in range(2):
+                cnt[:len(range(dz, Z, 2)), :len(range(dy, Y, 2)), :len(range(dx, X, 2))] += 1
+    return up(dc / cnt, (Z, Y, X))
+
+
+def backward(r, in_scale, flat_w, dz, dz_scale, c0=16, c1=32, c2=64, nbott=4, exact=False):
+    """Flat weight gradient for the gradient dz_scale * dz of the raw network
+    output (dz zero outside the interior), mirroring the GPU: FP32 gradient of
+    the output, activation gradients rounded to BF16 where they feed a
+    transposed convolution (not in exact mode)."""
+    rnd = _identity if exact else bf16_round
+    f32 = _identity if exact else (lambda a: np.asarray(np.float32(a), dtype=np.float64))
+    _, A = forward(r, in_scale, 1.0, flat_w, c0, c1, c2, nbott, exact=exact, keep=True)
+    Ws, shapes = A["Ws"], A["shapes"]
+    grads = [None] * len(shapes)
+    dzf = f32(dz_scale * np.asarray(dz, dtype=np.float64))[..., None]
+    lo, ld0, ld1 = len(shapes) - 1, len(shapes) - 2, len(shapes) - 3
+    grads[lo] = conv3_weight_grad(A["g0"], dzf)
+    dg0 = conv3_adjoint(dzf, Ws[lo])
+    grads[ld0] = conv3_weight_grad(A["i0"], dg0)
+    de0 = conv3_adjoint(rnd(dg0), Ws[ld0])
+    dg1 = up_adjoint(de0, A["g1"].shape[:3])
+    grads[ld1] = conv3_weight_grad(A["i1"], dg1)
+    de1 = conv3_adjoint(rnd(dg1), Ws[ld1])
+    dcur = up_adjoint(de1, A["bins"][-1].shape[:3])
+    for li in range(ld1 - 1, 1, -1):
+        xin = A["bins"][li - 2]
+        grads[li] = conv3_weight_grad(xin, dcur, shapes[li][2])
+        dcur = conv3_adjoint(rnd(dcur), Ws[li], shapes[li][2])
+    de1 = de1 + pool_adjoint(dcur, A["e1"].shape[:3])
+    grads[1] = conv3_weight_grad(A["p0"], de1)
+    dp0 = conv3_adjoint(rnd(de1), Ws[1])
+    de0 = de0 + pool_adjoint(dp0, A["e0"].shape[:3])
+    grads[0] = conv3_weight_grad(A["x"], de0)
+    return np.concatenate([g.reshape(-1) for g in grads])

@@ -414,10 +414,28 @@ kvs_status kvs_project(kvs_ctx* c, const kvs_solve_opts* opts, kvs_solve_report*
     if (o.fixed_iters < 0) return fail(c, KVS_EINVAL, "fixed_iters < 0");
     if (o.fixed_iters == 0 && !(o.tol > 0.0 && std::isfinite(o.tol))) return fail(c, KVS_EINVAL, "tol must be > 0");
     if (o.max_iter <= 0) return fail(c, KVS_EINVAL, "max_iter must be > 0");
-    if (o.precond != KVS_PC_NONE && o.precond != KVS_PC_JACOBI)
-        return fail(c, KVS_EINVAL, "preconditioner not available on this context");
+    if (o.precond != KVS_PC_NONE && o.precond != KVS_PC_JACOBI && o.precond != KVS_PC_UNET)
+        return fail(c, KVS_EINVAL, "unknown preconditioner");
+    if (o.precond == KVS_PC_UNET) {
+        if (!c->net) return fail(c, KVS_ESTATE, "no network set (kvs_set_preconditioner)");
+        const kvs_grid& g = c->grid;
+        if (std::fabs(g.hx - g.hy) > 1e-12 * g.hx || std::fabs(g.hx - g.hz) > 1e-12 * g.hx)
+            return fail(c, KVS_EINVAL, "the network preconditioner needs equal spacings");
+    }
     API_HIP(c, hipSetDevice(c->device));
     return kvs_run_projection(c, &o, rep);
+}
+
+kvs_status kvs_set_preconditioner(kvs_ctx* c, kvs_unet* net) {
+    if (!c) return KVS_EINVAL;
+    c->net = net;
+    return KVS_OK;
+}
+
+kvs_status kvs_last_fallbacks(const kvs_ctx* c, int64_t* n) {
+    if (!c || !n) return KVS_EINVAL;
+    *n = c->last_fallbacks;
+    return KVS_OK;
 }
 
 kvs_status kvs_set_projected_force(kvs_ctx* c, const double* FS) {

@@ -44,7 +44,7 @@ struct CgGeom {
     double dinv;              // 1/diag(A)
 };
 
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3, FIN_FZ0 = 4, FIN_FBETA = 5 };
 
 using kvs_tiling::tile_of;
 
@@ -224,17 +224,21 @@ __device__ __forceinline__ void sweep_partials(double v0, double v1, double* par
     }
 }
 
-// sweep 1: p' = z + beta p, A p' = -lap p', partial p'.Ap'
-__global__ __launch_bounds__(64 * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const double* r,
-                                                          const double* p_old, double* p_new, const CgState* st,
-                                                          double* partials, int npart) {
+// sweep 1: p' = z + beta p, A p' = -lap p', partial p'.Ap'.  z = zs * src
+// with src = r (CG: zs = 1, Jacobi: zs = 1/diag) or, in flexible PCG, the
+// network output zf (zs = 1) unless this iteration fell back to Jacobi.
+__global__ __launch_bounds__(64 * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const double* r_in,
+                                                          const double* zf, const double* p_old, double* p_new,
+                                                          const CgState* st, double* partials, int npart) {
     if (st->done) return;
     __shared__ double lds[2][SBY + 3][68];
     const Lane L = sweep_lane(g, sg);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int sxy = g.nx * g.ny;
     const double beta = st->beta;
-    const double zs = st->jacobi ? g.dinv : 1.0;
+    const bool net_z = st->flexible && !st->zjacobi;
+    const double* r = net_z ? zf : r_in;
+    const double zs = (st->jacobi || (st->flexible && st->zjacobi)) ? g.dinv : 1.0;
     const bool first = beta == 0.0;
     auto pv = [&](double rv, double po) { return first ? rv * zs : rv * zs + beta * po; };
     const int kb = L.kb, ke = L.ke;
@@ -312,6 +316,68 @@ __global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const 
     sweep_partials<2>(s1, s2, partials, npart);
 }
 
+// flexible PCG: partials of z.r, z.Ap and r.Ap (A p recomputed from p)
+__global__ __launch_bounds__(64 * SBY) void cg_fdot_kernel(const CgGeom g, const SweepGeom sg, const double* z,
+                                                           const double* r, const double* p, const CgState* st,
+                                                           double* partials, int npart) {
+    if (st->done) return;
+    __shared__ double lds[2][SBY + 3][68];
+    __shared__ double sh[3][SBY];
+    const Lane L = sweep_lane(g, sg);
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int sxy = g.nx * g.ny;
+    const int kb = L.kb, ke = L.ke;
+    double pm = p[(kb - 1) * sxy + L.col];
+    double pc = p[kb * sxy + L.col];
+    double pp = p[(kb + 1) * sxy + L.col];
+    double hc = p[kb * sxy + L.h_off];
+    double zc = z[kb * sxy + L.col], rc = r[kb * sxy + L.col];
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int k = kb; k < ke; ++k) {
+        const int buf = k & 1;
+        lds[buf][ty + 1][tx + 1] = pc;
+        lds[buf][L.h_row][L.h_col] = hc;
+        const double pn = p[min(k + 2, ke) * sxy + L.col];
+        const double hn = p[min(k + L.h_dz, ke) * sxy + L.h_off];
+        const int q1 = min(k + 1, ke - 1) * sxy + L.col;
+        const double zn = z[q1], rn = r[q1];
+        lds_barrier();
+        const double c2 = 2.0 * pc;
+        const double ap = -((lds[buf][ty + 1][tx + 2] + lds[buf][ty + 1][tx] - c2) * g.ihx2
+                            + (lds[buf][ty + 2][tx + 1] + lds[buf][ty][tx + 1] - c2) * g.ihy2
+                            + (pp + pm - c2) * g.ihz2);
+        s1 += L.act ? zc * rc : 0.0;
+        s2 += L.act ? zc * ap : 0.0;
+        s3 += L.act ? rc * ap : 0.0;
+        pm = pc;
+        pc = pp;
+        pp = pn;
+        hc = hn;
+        zc = zn;
+        rc = rn;
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+    if (tx == 0) {
+        sh[0][ty] = s1;
+        sh[1][ty] = s2;
+        sh[2][ty] = s3;
+    }
+    __syncthreads();
+    if (tx == 0 && ty == 0) {
+        double a = 0, b = 0, c = 0;
+        for (int w = 0; w < SBY; ++w) {
+            a += sh[0][w];
+            b += sh[1][w];
+            c += sh[2][w];
+        }
+        partials[blockIdx.x] = a;
+        partials[npart + blockIdx.x] = b;
+        partials[2 * npart + blockIdx.x] = c;
+    }
+}
+
 // partials of (-b - A phi)^2 and b^2
 __global__ __launch_bounds__(64 * CBY) void cg_true_residual_kernel(const CgGeom g, const double* F, const double* phi,
                                                                     double* partials, int npart) {
@@ -355,6 +421,12 @@ __global__ __launch_bounds__(64 * CBY) void grad_subtract_kernel(const CgGeom g,
 __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials, int count, int stride, int nsum,
                                                           int mode, CgState* st) {
     if (mode != FIN_INIT && mode != FIN_TRUE && st->done) return;
+    // network scales of the flexible PCG from the current residual
+    auto set_net_scales = [&](double rr) {
+        const double rms = sqrt(rr / st->n_interior);
+        st->net_in = rms > 0.0 ? 1.0 / rms : 0.0;
+        st->net_out = rms * st->h2;
+    };
     __shared__ double sh[3][256];
     for (int s = 0; s < nsum; ++s) {
         double acc = 0.0;
@@ -392,6 +464,30 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
         } else if (st->fixed_iters <= 0 && !(1.0 >= sqrt(st->tol2))) {
             st->done = 1;  // tol > 1: the initial residual already satisfies the test
         }
+        set_net_scales(s1);
+    } else if (mode == FIN_FZ0) {
+        // flexible PCG, first z: z.r, else fall back to Jacobi for this z
+        if (s1 > 0.0 && isfinite(s1)) {
+            st->rz = s1;
+            st->zjacobi = 0;
+        } else {
+            st->rz = st->rr * st->dinv;
+            st->zjacobi = 1;
+            st->fallbacks += 1;
+        }
+    } else if (mode == FIN_FBETA) {
+        const double zr = s1, zAp = s2, rAp = s3;
+        const double rz_old = st->rz;
+        if (zr > 0.0 && isfinite(zr) && isfinite(zAp)) {
+            st->beta = -st->alpha * zAp / rz_old;
+            st->rz = zr;
+            st->zjacobi = 0;
+        } else {
+            st->fallbacks += 1;
+            st->zjacobi = 1;
+            st->beta = -st->alpha * rAp * st->dinv / rz_old;
+            st->rz = st->rr * st->dinv;
+        }
     } else if (mode == FIN_ALPHA) {
         st->pAp = s1;
         if (!(s1 > 0.0) || !isfinite(s1)) {
@@ -405,6 +501,20 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
         if (!isfinite(s1) || s1 < 0.0 || !isfinite(s2)) {
             st->status = KVS_EBREAKDOWN;
             st->done = 1;
+            return;
+        }
+        if (st->flexible) {
+            // residual, stop test and network scales only; beta comes later
+            st->rr = s1;
+            set_net_scales(s1);
+            if (st->fixed_iters > 0) {
+                if (st->iters >= st->fixed_iters) st->done = 1;
+            } else if (sqrt(st->rr / st->rr0) < sqrt(st->tol2)) {
+                st->done = 1;
+            } else if (st->iters >= st->max_iter) {
+                st->status = KVS_ENOTCONV;
+                st->done = 1;
+            }
             return;
         }
         const double rz_new = st->jacobi ? s2 : s1;
@@ -477,11 +587,16 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     CG_HIP(hipEventCreate(&e1));
     CG_HIP(hipEventRecord(e0, c->stream));
 
+    const bool flexible = o->precond == KVS_PC_UNET;
     CgState init{};
     init.tol2 = o->tol * o->tol;
     init.max_iter = o->max_iter;
     init.fixed_iters = o->fixed_iters;
     init.jacobi = o->precond == KVS_PC_JACOBI ? 1 : 0;
+    init.flexible = flexible ? 1 : 0;
+    init.dinv = g.dinv;
+    init.h2 = c->grid.hx * c->grid.hx;
+    init.n_interior = (double)(g.nx - 2) * (double)(g.ny - 2) * (double)(g.nz - 2);
     *c->cgs_host = init;
     CG_HIP(hipMemcpyAsync(c->cgs, c->cgs_host, sizeof(CgState), hipMemcpyHostToDevice, c->stream));
     const bool warm = o->warm_start && c->have_phi;
@@ -502,12 +617,21 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     const int nbs = sg.gx * sg.gy * sg.gz;
     const dim3 sblk(64, SBY);
     int pi = 0;  // p[pi] holds the current search direction
-    int chunk = 4;
+    int chunk = flexible ? 2 : 4;
     long long launched = 0;
     const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
+    double* z = c->Ap;  // flexible PCG: the preconditioned residual
+    const int* stop = &c->cgs->done;
+    if (flexible) {
+        CG_HIP(kvs_unet_precondition(c->net, c->r, z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop, c->stream));
+        hipLaunchKernelGGL(cg_fdot_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, z, c->r, c->p[pi], c->cgs, part, npart);
+        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 3, (int)FIN_FZ0,
+                           c->cgs);
+        CG_HIP(hipGetLastError());
+    }
     while (true) {
         for (int m = 0; m < chunk; ++m) {
-            hipLaunchKernelGGL(cg_dir_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->r, c->p[pi], c->p[1 - pi],
+            hipLaunchKernelGGL(cg_dir_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->r, z, c->p[pi], c->p[1 - pi],
                                c->cgs, part, npart);
             hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 1, (int)FIN_ALPHA,
                                c->cgs);
@@ -515,6 +639,14 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
                                part, npart);
             hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 2, (int)FIN_BETA,
                                c->cgs);
+            if (flexible) {
+                CG_HIP(kvs_unet_precondition(c->net, c->r, z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop,
+                                             c->stream));
+                hipLaunchKernelGGL(cg_fdot_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, z, c->r, c->p[1 - pi], c->cgs,
+                                   part, npart);
+                hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 3,
+                                   (int)FIN_FBETA, c->cgs);
+            }
             pi = 1 - pi;
         }
         CG_HIP(hipGetLastError());
@@ -523,7 +655,7 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
         CG_HIP(hipStreamSynchronize(c->stream));
         if (c->cgs_host->done) break;
         if (launched > cap) return fail(c, KVS_EDEVICE, "CG driver: iteration cap passed without a stop flag");
-        chunk = std::min(chunk * 2, 64);
+        chunk = std::min(chunk * 2, flexible ? 8 : 64);
     }
     // Launches after the stop flag return at once; the host-side flip of pi
     // may then be off by those, which is harmless: the next solve starts with
@@ -552,6 +684,7 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     const CgState& s = *c->cgs_host;
     c->have_phi = true;
     if (s.status != KVS_EBREAKDOWN) c->fs_current = true;
+    c->last_fallbacks = s.fallbacks;
     if (rep) {
         rep->iters = s.iters;
         rep->relres_recursive = s.rr0 > 0 ? std::sqrt(s.rr / s.rr0) : 0.0;

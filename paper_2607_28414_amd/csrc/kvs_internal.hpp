@@ -19,8 +19,14 @@ struct CgState {
     double pAp, alpha, beta;
     double tol2;            // tol^2 (compared with rr / rr0)
     double relres_true2;    // ||-b - A phi||^2 / ||b||^2
+    double net_in, net_out; // flexible PCG: network input / output scales
+    double n_interior;      // interior cells (for the RMS of r)
+    double h2;              // grid spacing^2 (network output scale)
+    double dinv;            // 1 / diag(A)
     long long iters, max_iter, fixed_iters;
-    int done, status, jacobi, pad;
+    int done, status, jacobi, flexible;
+    int zjacobi;            // flexible PCG: this iteration's z is r / diag(A)
+    int fallbacks;          // number of Jacobi fallbacks taken
 };
 
 struct kvs_ctx {
@@ -88,6 +94,10 @@ struct kvs_ctx {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
 
+    // learned preconditioner (borrowed; set by kvs_set_preconditioner)
+    kvs_unet* net = nullptr;
+    int64_t last_fallbacks = 0;  // Jacobi fallbacks in the last flexible solve
+
     // tuning of the step kernel: shape variant, z planes per block (0: fill
     // whole rounds of resident blocks), XCD-contiguous tile order
     int step_variant = 0;
@@ -154,6 +164,12 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
 hipError_t kvs_batch_prepare(kvs_batch* b);
 hipError_t kvs_batch_trial_launch(kvs_batch* b);
 hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps);
+
+// ---- learned preconditioner (kvs_unet.hip) ---------------------------------
+// z = out_scale * U(in_scale * r) on the context grid, scales read from
+// device memory, every kernel returns at once while *stop is set.
+hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const kvs_grid& g, const double* in_scale,
+                                 const double* out_scale, const int* stop, hipStream_t s);
 
 // ---- projection (kvs_cg.hip) ---------------------------------------------
 kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep);

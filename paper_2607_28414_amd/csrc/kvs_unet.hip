@@ -56,10 +56,12 @@ __device__ __forceinline__ int tap_dz(int tap) { return tap / 9 - 1; }
 // out[v][co] = sum_{tap, ci} W[co][tap * CI + ci] * in(v + dil * tap)[ci],
 // in(p) = A[p][ci] + (B ? B[p / 2][ci] : 0), zero outside the grid.
 // out may be BF16 (store) — every output is rounded once, to nearest even.
-template <int CI, int CO>
+template <int CI, int CO, typename OUT>
 __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, const bf16* __restrict__ B, Dims d,
-                                                  int dil, const bf16* __restrict__ W, bf16* __restrict__ out) {
+                                                  int dil, const bf16* __restrict__ W, OUT* __restrict__ out,
+                                                  const int* stop) {
     static_assert(CI % 8 == 0 && CO % 16 == 0, "channel counts");
+    if (stop && *stop) return;
     constexpr int K = 27 * CI;
     constexpr int KP = (K + 31) / 32 * 32;
     constexpr int MT = CO / 16;
@@ -106,18 +108,34 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, co
     if (!valid) return;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-        bf16x4 o;
+        if constexpr (sizeof(OUT) == 2) {
+            bf16x4 o;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[m][i];
-        *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
+            for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[m][i];
+            *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
+        } else {
+            *reinterpret_cast<f32x4*>(out + v * CO + 16 * m + 4 * kg) = acc[m];
+        }
     }
 }
 
+// Scales of the network input and output: device values (the flexible PCG
+// computes them from the residual norm without a host round trip) or host
+// values; `stop` (device flag) makes every kernel return at once.
+struct NetCtl {
+    const double* in_dev;
+    const double* out_dev;
+    const int* stop;
+    double in_v, out_v;
+};
+
 // first layer: one input channel read from an FP64 field, scaled
 template <int CO>
-__global__ __launch_bounds__(256) void conv3_first(const double* __restrict__ r, double in_scale, Dims d,
+__global__ __launch_bounds__(256) void conv3_first(const double* __restrict__ r, NetCtl ctl, Dims d,
                                                    const bf16* __restrict__ W, bf16* __restrict__ out) {
     constexpr int MT = CO / 16;
+    if (ctl.stop && *ctl.stop) return;
+    const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
     const int lane = threadIdx.x & 63;
     const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int vl = lane & 15, kg = lane >> 4;
@@ -157,7 +175,9 @@ __global__ __launch_bounds__(256) void conv3_first(const double* __restrict__ r,
 // output layer: one channel, FP64 result scaled, 0 outside the interior
 template <int CI>
 __global__ __launch_bounds__(256) void conv3_out(const bf16* __restrict__ g, Dims d, const float* __restrict__ W,
-                                                 double out_scale, double* __restrict__ z) {
+                                                 NetCtl ctl, double* __restrict__ z) {
+    if (ctl.stop && *ctl.stop) return;
+    const double out_scale = ctl.out_dev ? *ctl.out_dev : ctl.out_v;
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= d.n()) return;
     const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), zz = (int)(v / ((long long)d.nx * d.ny));
@@ -180,7 +200,8 @@ __global__ __launch_bounds__(256) void conv3_out(const bf16* __restrict__ g, Dim
 
 // mean of the children of coarse voxel V (8 channels per thread)
 template <int C>
-__global__ void pool2(const bf16* __restrict__ fine, Dims d, bf16* __restrict__ out) {
+__global__ void pool2(const bf16* __restrict__ fine, Dims d, bf16* __restrict__ out, const int* stop) {
+    if (stop && *stop) return;
     const Dims c = coarse(d);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long V = t / (C / 8);
@@ -207,69 +228,15 @@ __global__ void pool2(const bf16* __restrict__ fine, Dims d, bf16* __restrict__ 
 
 int blocks_for_waves(long long voxels) { return (int)((voxels + 63) / 64); }
 
-}  // namespace
-
-// ---- network object ------------------------------------------------------------
-
-struct UnetLayerDesc {
-    int ci, co, dil, level;  // level of the output
-    bool skip_in;            // input = skip tensor + up(previous)
-};
-
-struct kvs_unet {
-    int c0 = 16, c1 = 32, c2 = 64, nbott = 4;
-    std::vector<UnetLayerDesc> layers;  // 0 first, 1 enc1, 2.. bottleneck, dec1, dec0, out
-    std::vector<int64_t> w_off;         // offset of each layer's bf16 weights (elements)
-    std::vector<int64_t> kp;            // padded K per layer
-    int64_t n_w = 0;                    // total bf16 weight elements
-    bf16* w = nullptr;                  // device bf16 weights (inference layout)
-    float* w_out = nullptr;             // device fp32 weights of the output layer [27][C0]
-    std::vector<float> host_master;     // fp32 master weights, layer by layer, [co][27*ci] (out: [27][c0])
-    // activation buffers for the last grid
-    Dims dims{0, 0, 0};
-    bf16 *e0 = nullptr, *p0 = nullptr, *e1 = nullptr, *p1 = nullptr, *ba = nullptr, *bb = nullptr, *g1 = nullptr,
-         *g0 = nullptr;
-    std::string err;
-};
-
-namespace {
-
-void unet_free_acts(kvs_unet* u) {
-    for (bf16** p : {&u->e0, &u->p0, &u->e1, &u->p1, &u->ba, &u->bb, &u->g1, &u->g0}) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-    }
-}
-
-hipError_t unet_ensure_acts(kvs_unet* u, Dims d) {
-    if (u->e0 && u->dims.nx == d.nx && u->dims.ny == d.ny && u->dims.nz == d.nz) return hipSuccess;
-    unet_free_acts(u);
-    const Dims d1 = coarse(d), d2 = coarse(d1);
-    const long long n0 = d.n(), n1 = d1.n(), n2 = d2.n();
-    hipError_t e = hipMalloc(&u->e0, sizeof(bf16) * n0 * u->c0);
-    if (e == hipSuccess) e = hipMalloc(&u->g0, sizeof(bf16) * n0 * u->c0);
-    if (e == hipSuccess) e = hipMalloc(&u->p0, sizeof(bf16) * n1 * u->c0);
-    if (e == hipSuccess) e = hipMalloc(&u->e1, sizeof(bf16) * n1 * u->c1);
-    if (e == hipSuccess) e = hipMalloc(&u->g1, sizeof(bf16) * n1 * u->c0);
-    if (e == hipSuccess) e = hipMalloc(&u->p1, sizeof(bf16) * n2 * u->c1);
-    if (e == hipSuccess) e = hipMalloc(&u->ba, sizeof(bf16) * n2 * u->c2);
-    if (e == hipSuccess) e = hipMalloc(&u->bb, sizeof(bf16) * n2 * u->c2);
-    if (e != hipSuccess) {
-        unet_free_acts(u);
-        return e;
-    }
-    u->dims = d;
-    return hipSuccess;
-}
-
 // dispatch of the MFMA conv over the channel pairs this network uses
-hipError_t launch_conv(int ci, int co, const bf16* A, const bf16* B, Dims d, int dil, const bf16* W, bf16* out,
-                       hipStream_t s) {
+template <typename OUT>
+hipError_t launch_conv(int ci, int co, const bf16* A, const bf16* B, Dims d, int dil, const bf16* W, OUT* out,
+                       hipStream_t s, const int* stop = nullptr) {
     const int nb = blocks_for_waves(d.n());
-#define KVS_CONV_CASE(CI_, CO_)                                                                          \
-    if (ci == CI_ && co == CO_) {                                                                        \
-        hipLaunchKernelGGL((conv3_mfma<CI_, CO_>), dim3(nb), dim3(256), 0, s, A, B, d, dil, W, out);    \
-        return hipGetLastError();                                                                        \
+#define KVS_CONV_CASE(CI_, CO_)                                                                                  \
+    if (ci == CI_ && co == CO_) {                                                                                \
+        hipLaunchKernelGGL((conv3_mfma<CI_, CO_, OUT>), dim3(nb), dim3(256), 0, s, A, B, d, dil, W, out, stop); \
+        return hipGetLastError();                                                                                \
     }
     KVS_CONV_CASE(16, 32)
     KVS_CONV_CASE(32, 64)
@@ -283,18 +250,369 @@ hipError_t launch_conv(int ci, int co, const bf16* A, const bf16* B, Dims d, int
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pool(int c, const bf16* fine, Dims d, bf16* out, hipStream_t s) {
-    const long long threads = coarse(d).n() * (c / 8);
-    const int nb = (int)((threads + 255) / 256);
-    switch (c) {
-        case 8: hipLaunchKernelGGL(pool2<8>, dim3(nb), dim3(256), 0, s, fine, d, out); break;
-        case 16: hipLaunchKernelGGL(pool2<16>, dim3(nb), dim3(256), 0, s, fine, d, out); break;
-        case 32: hipLaunchKernelGGL(pool2<32>, dim3(nb), dim3(256), 0, s, fine, d, out); break;
-        case 64: hipLaunchKernelGGL(pool2<64>, dim3(nb), dim3(256), 0, s, fine, d, out); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+}  // namespace
+
+// ---- training kernels ------------------------------------------------------------
+
+namespace {
+
+__global__ void f32_to_bf16(const float* __restrict__ a, bf16* __restrict__ b, long long n) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) b[q] = (bf16)a[q];
 }
+
+// Weight gradient of one conv: part[tap][blk][co * CI + ci] =
+//   sum over the block's voxels v of x(v + dil tap)[ci] * dy[v][co],
+// x(p) = bf16(A[p] + up(B)[p]) as the forward read it (or, FIRST, the
+// scaled FP64 input rounded to BF16); dy in FP32.  64 voxels are staged in
+// LDS at a time; each thread owns a fixed set of (co, ci) pairs.
+template <int CI, int CO, bool FIRST>
+__global__ __launch_bounds__(256) void dw_partial(const bf16* __restrict__ A, const bf16* __restrict__ B,
+                                                  const double* __restrict__ r, double in_scale, Dims d, int dil,
+                                                  const float* __restrict__ dy, float* __restrict__ part) {
+    constexpr int NP = CI * CO;
+    constexpr int PER = (NP + 255) / 256;
+    __shared__ float xs[64][CI];
+    __shared__ float ys[64][CO];
+    const int tap = blockIdx.y;
+    const int ox = dil * tap_dx(tap), oy = dil * tap_dy(tap), oz = dil * tap_dz(tap);
+    const long long N = d.n();
+    const Dims dB = coarse(d);
+    float acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] = 0.f;
+    for (long long base = (long long)blockIdx.x * 64; base < N; base += (long long)gridDim.x * 64) {
+        for (int idx = threadIdx.x; idx < 64 * CI; idx += 256) {
+            const int vox = idx / CI, c = idx % CI;
+            const long long v = base + vox;
+            float val = 0.f;
+            if (v < N) {
+                const int x = (int)(v % d.nx) + ox, y = (int)((v / d.nx) % d.ny) + oy,
+                          z = (int)(v / ((long long)d.nx * d.ny)) + oz;
+                if (x >= 0 && x < d.nx && y >= 0 && y < d.ny && z >= 0 && z < d.nz) {
+                    const long long p = x + (long long)d.nx * (y + (long long)d.ny * z);
+                    if constexpr (FIRST) {
+                        val = (float)(bf16)(float)(in_scale * r[p]);
+                    } else {
+                        val = (float)A[p * CI + c];
+                        if (B) {
+                            val += (float)B[((x >> 1) + (long long)dB.nx * ((y >> 1) + (long long)dB.ny * (z >> 1))) * CI + c];
+                            val = (float)(bf16)val;
+                        }
+                    }
+                }
+            }
+            xs[vox][c] = val;
+        }
+        for (int idx = threadIdx.x; idx < 64 * CO; idx += 256) {
+            const int vox = idx / CO, c = idx % CO;
+            const long long v = base + vox;
+            ys[vox][c] = v < N ? dy[v * CO + c] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int pidx = threadIdx.x + 256 * q;
+            if (pidx < NP) {
+                const int co = pidx / CI, ci = pidx % CI;
+                float a = acc[q];
+                for (int vox = 0; vox < 64; ++vox) a += xs[vox][ci] * ys[vox][co];
+                acc[q] = a;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int pidx = threadIdx.x + 256 * q;
+        if (pidx < NP) part[((long long)tap * gridDim.x + blockIdx.x) * NP + pidx] = acc[q];
+    }
+}
+
+// grad[co][tap * CI + ci] (+)= sum over blocks, fixed order
+__global__ void dw_reduce(const float* __restrict__ part, int nblk, int CI, int CO, float* __restrict__ grad,
+                          int accumulate) {
+    const int NP = CI * CO;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 27LL * NP) return;
+    const int tap = (int)(t / NP), pidx = (int)(t % NP);
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[((long long)tap * nblk + b) * NP + pidx];
+    const int co = pidx / CI, ci = pidx % CI;
+    float* g = grad + (long long)co * 27 * CI + tap * CI + ci;
+    *g = accumulate ? *g + s : s;
+}
+
+// dg[v][ci] = sum_tap W[tap][ci] * dz[v - tap]   (output layer, one channel)
+template <int CI>
+__global__ void out_backward(const float* __restrict__ dz, Dims d, const float* __restrict__ W, float* __restrict__ dg) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= d.n()) return;
+    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long long)d.nx * d.ny));
+    float acc[CI];
+#pragma unroll
+    for (int c = 0; c < CI; ++c) acc[c] = 0.f;
+    for (int tap = 0; tap < 27; ++tap) {
+        const int px = x - tap_dx(tap), py = y - tap_dy(tap), pz = z - tap_dz(tap);
+        if (px < 0 || px >= d.nx || py < 0 || py >= d.ny || pz < 0 || pz >= d.nz) continue;
+        const float g = dz[px + (long long)d.nx * (py + (long long)d.ny * pz)];
+#pragma unroll
+        for (int c = 0; c < CI; ++c) acc[c] += W[tap * CI + c] * g;
+    }
+#pragma unroll
+    for (int c = 0; c < CI; ++c) dg[v * CI + c] = acc[c];
+}
+
+// adjoint of nearest upsampling: dc[V][c] = sum over the children of df
+__global__ void up_adjoint(const float* __restrict__ df, Dims d, int C, float* __restrict__ dc) {
+    const Dims cd = coarse(d);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cd.n() * C) return;
+    const long long V = t / C;
+    const int c = (int)(t % C);
+    const int X = (int)(V % cd.nx), Y = (int)((V / cd.nx) % cd.ny), Z = (int)(V / ((long long)cd.nx * cd.ny));
+    float s = 0.f;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int x = 2 * X + dx, y = 2 * Y + dy, z = 2 * Z + dz;
+                if (x < d.nx && y < d.ny && z < d.nz) s += df[(x + (long long)d.nx * (y + (long long)d.ny * z)) * C + c];
+            }
+    dc[t] = s;
+}
+
+// adjoint of mean pooling, added: df[v][c] += dc[v/2][c] / (children of v/2)
+__global__ void pool_adjoint_add(const float* __restrict__ dc, Dims d, int C, float* __restrict__ df) {
+    const Dims cd = coarse(d);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d.n() * C) return;
+    const long long v = t / C;
+    const int c = (int)(t % C);
+    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), z = (int)(v / ((long long)d.nx * d.ny));
+    const int X = x >> 1, Y = y >> 1, Z = z >> 1;
+    const int cnt = (std::min(2 * X + 2, d.nx) - 2 * X) * (std::min(2 * Y + 2, d.ny) - 2 * Y) * (std::min(2 * Z + 2, d.nz) - 2 * Z);
+    df[t] += dc[(X + (long long)cd.nx * (Y + (long long)cd.ny * Z)) * C + c] / (float)cnt;
+}
+
+// A-norm loss of the unit-spacing Poisson operator A = -lap (interior):
+// e = z - xs; dz_raw = A e (0 outside the interior); block partials of
+// e.Ae and xs.A xs.
+__global__ void anorm_loss(const double* __restrict__ z, const double* __restrict__ xs, Dims d,
+                           double* __restrict__ dz_raw, double* __restrict__ part) {
+    __shared__ double sh[2][256];
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    if (v < d.n()) {
+        const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), zz = (int)(v / ((long long)d.nx * d.ny));
+        double ae = 0.0;
+        if (x >= 1 && x <= d.nx - 2 && y >= 1 && y <= d.ny - 2 && zz >= 1 && zz <= d.nz - 2) {
+            const long long sy = d.nx, sz = (long long)d.nx * d.ny;
+            auto e = [&](long long q) { return z[q] - xs[q]; };
+            ae = 6.0 * e(v) - e(v - 1) - e(v + 1) - e(v - sy) - e(v + sy) - e(v - sz) - e(v + sz);
+            const double ax = 6.0 * xs[v] - xs[v - 1] - xs[v + 1] - xs[v - sy] - xs[v + sy] - xs[v - sz] - xs[v + sz];
+            s1 = e(v) * ae;
+            s2 = xs[v] * ax;
+        }
+        dz_raw[v] = ae;
+    }
+    sh[0][threadIdx.x] = s1;
+    sh[1][threadIdx.x] = s2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0];
+        part[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
+__global__ void scale_to_f32(const double* __restrict__ a, double s, float* __restrict__ b, long long n) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) b[q] = (float)(s * a[q]);
+}
+
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1,
+                            float c2, float gscale) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float gq = g[q] * gscale;
+    const float mq = b1 * m[q] + (1.f - b1) * gq;
+    const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    w[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// x = xs - xk, then both scaled later
+__global__ void sub_kernel(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
+                           long long n) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[q] = a[q] - b[q];
+}
+
+__global__ void scale_kernel(double* __restrict__ a, double s, long long n) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) a[q] *= s;
+}
+
+// y = A x = -lap_h x on the interior (0 elsewhere); block partials of y.y
+__global__ void apply_A_kernel(const double* __restrict__ x, Dims d, double ihx2, double ihy2, double ihz2,
+                               double* __restrict__ y, double* __restrict__ part) {
+    __shared__ double sh[256];
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (v < d.n()) {
+        const int i = (int)(v % d.nx), j = (int)((v / d.nx) % d.ny), k = (int)(v / ((long long)d.nx * d.ny));
+        double a = 0.0;
+        if (i >= 1 && i <= d.nx - 2 && j >= 1 && j <= d.ny - 2 && k >= 1 && k <= d.nz - 2) {
+            const long long sy = d.nx, sz = (long long)d.nx * d.ny;
+            const double c2 = 2.0 * x[v];
+            a = -((x[v + 1] + x[v - 1] - c2) * ihx2 + (x[v + sy] + x[v - sy] - c2) * ihy2 +
+                  (x[v + sz] + x[v - sz] - c2) * ihz2);
+            s = a * a;
+        }
+        y[v] = a;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+int nblocks256(long long n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+// ---- network object ------------------------------------------------------------
+
+struct UnetLayerDesc {
+    int ci, co, dil, level;  // level of the output
+    bool skip_in;            // input = skip tensor + up(previous)
+};
+
+struct kvs_unet {
+    int c0 = 16, c1 = 32, c2 = 64, nbott = 4;
+    std::vector<UnetLayerDesc> layers;  // 0 first, 1 enc1, 2.. bottleneck, dec1, dec0, out
+    std::vector<int64_t> w_off, wt_off;  // offsets of each layer's bf16 weights (forward, transposed)
+    std::vector<int64_t> kp, kpt;        // padded K per layer (forward, transposed)
+    std::vector<int64_t> m_off;          // offset of each layer in the flat master layout
+    int64_t n_w = 0, n_wt = 0, n_master = 0;
+    bf16* w = nullptr;       // device bf16 forward weights
+    bf16* wt = nullptr;      // device bf16 transposed weights (for the backward pass)
+    float* w_out = nullptr;  // device fp32 (bf16-rounded) output weights [27][C0]
+    float* master = nullptr; // device fp32 master weights (flat)
+    float* grad = nullptr;   // device fp32 gradient (flat, same layout)
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    int64_t adam_t = 0;
+    std::vector<float> host_master;
+    // activations of the last grid: e0, p0, e1, p1, bottleneck outputs (kept
+    // for the backward pass), g1, g0
+    Dims dims{0, 0, 0};
+    bf16 *e0 = nullptr, *p0 = nullptr, *e1 = nullptr, *p1 = nullptr, *g1 = nullptr, *g0 = nullptr;
+    std::vector<bf16*> bott;
+    // training buffers (allocated on first use)
+    Dims tdims{0, 0, 0};
+    float *dg0 = nullptr, *de0 = nullptr, *dp0 = nullptr, *dg1 = nullptr, *de1 = nullptr, *dp1 = nullptr;
+    std::vector<float*> dbott;  // gradient of each bottleneck output, and of its input p1 (last)
+    bf16* gb = nullptr;         // bf16 staging of a gradient (conv^T input)
+    float* dzf = nullptr;
+    double* dz_raw = nullptr;
+    double* part = nullptr;
+    float* wpart = nullptr;
+    int64_t wpart_n = 0;
+    std::string err;
+};
+
+namespace {
+
+template <typename P>
+void ufree(P*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void unet_free_acts(kvs_unet* u) {
+    for (bf16** p : {&u->e0, &u->p0, &u->e1, &u->p1, &u->g1, &u->g0}) ufree(*p);
+    for (bf16*& p : u->bott) ufree(p);
+    u->bott.clear();
+    u->dims = Dims{0, 0, 0};
+}
+
+void unet_free_train(kvs_unet* u) {
+    for (float** p : {&u->dg0, &u->de0, &u->dp0, &u->dg1, &u->de1, &u->dp1, &u->dzf}) ufree(*p);
+    for (float*& p : u->dbott) ufree(p);
+    u->dbott.clear();
+    ufree(u->gb);
+    ufree(u->dz_raw);
+    ufree(u->part);
+    ufree(u->wpart);
+    u->wpart_n = 0;
+    u->tdims = Dims{0, 0, 0};
+}
+
+hipError_t unet_ensure_acts(kvs_unet* u, Dims d) {
+    if (u->e0 && u->dims.nx == d.nx && u->dims.ny == d.ny && u->dims.nz == d.nz) return hipSuccess;
+    unet_free_acts(u);
+    const Dims d1 = coarse(d), d2 = coarse(d1);
+    const long long n0 = d.n(), n1 = d1.n(), n2 = d2.n();
+    hipError_t e = hipMalloc(&u->e0, sizeof(bf16) * n0 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->g0, sizeof(bf16) * n0 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->p0, sizeof(bf16) * n1 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->e1, sizeof(bf16) * n1 * u->c1);
+    if (e == hipSuccess) e = hipMalloc(&u->g1, sizeof(bf16) * n1 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->p1, sizeof(bf16) * n2 * u->c1);
+    for (int q = 0; q < u->nbott && e == hipSuccess; ++q) {
+        bf16* b = nullptr;
+        e = hipMalloc(&b, sizeof(bf16) * n2 * u->c2);
+        u->bott.push_back(b);
+    }
+    if (e != hipSuccess) {
+        unet_free_acts(u);
+        return e;
+    }
+    u->dims = d;
+    return hipSuccess;
+}
+
+hipError_t unet_ensure_train(kvs_unet* u, Dims d) {
+    if (u->dg0 && u->tdims.nx == d.nx && u->tdims.ny == d.ny && u->tdims.nz == d.nz) return hipSuccess;
+    unet_free_train(u);
+    const Dims d1 = coarse(d), d2 = coarse(d1);
+    const long long n0 = d.n(), n1 = d1.n(), n2 = d2.n();
+    hipError_t e = hipMalloc(&u->dg0, sizeof(float) * n0 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->de0, sizeof(float) * n0 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->dp0, sizeof(float) * n1 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->dg1, sizeof(float) * n1 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->de1, sizeof(float) * n1 * u->c1);
+    if (e == hipSuccess) e = hipMalloc(&u->dp1, sizeof(float) * n2 * u->c1);
+    for (int q = 0; q < u->nbott && e == hipSuccess; ++q) {
+        float* b = nullptr;
+        e = hipMalloc(&b, sizeof(float) * n2 * u->c2);
+        u->dbott.push_back(b);
+    }
+    if (e == hipSuccess) e = hipMalloc(&u->gb, sizeof(bf16) * n0 * std::max(u->c0, u->c2));
+    if (e == hipSuccess) e = hipMalloc(&u->dzf, sizeof(float) * n0);
+    if (e == hipSuccess) e = hipMalloc(&u->dz_raw, sizeof(double) * n0);
+    if (e == hipSuccess) e = hipMalloc(&u->part, sizeof(double) * 2 * nblocks256(n0));
+    if (e != hipSuccess) {
+        unet_free_train(u);
+        return e;
+    }
+    u->tdims = d;
+    return hipSuccess;
+}
+
+hipError_t launch_pool(int c, const bf16* fine, Dims d, bf16* out, hipStream_t s, const int* stop);
 
 void build_layers(kvs_unet* u) {
     u->layers.clear();
@@ -308,60 +626,187 @@ void build_layers(kvs_unet* u) {
     u->layers.push_back({u->c0, u->c0, 1, 0, true});   // g0 = conv(e0 + up g1)
     u->layers.push_back({u->c0, 1, 1, 0, false});      // z
     u->w_off.clear();
+    u->wt_off.clear();
     u->kp.clear();
-    int64_t off = 0;
-    for (size_t l = 0; l + 1 < u->layers.size(); ++l) {
+    u->kpt.clear();
+    u->m_off.clear();
+    int64_t off = 0, offt = 0, offm = 0;
+    for (size_t l = 0; l < u->layers.size(); ++l) {
         const UnetLayerDesc& L = u->layers[l];
+        u->m_off.push_back(offm);
+        offm += 27LL * L.ci * L.co;
+        if (l + 1 == u->layers.size()) break;
         const int64_t kp = L.ci == 1 ? 32 : (27 * L.ci + 31) / 32 * 32;
+        const int64_t kpt = (27 * L.co + 31) / 32 * 32;
         u->w_off.push_back(off);
         u->kp.push_back(kp);
         off += kp * L.co;
+        u->wt_off.push_back(offt);
+        u->kpt.push_back(kpt);
+        offt += L.ci == 1 ? 0 : kpt * L.ci;
     }
     u->n_w = off;
+    u->n_wt = offt;
+    u->n_master = offm;
 }
 
 }  // namespace
 
-hipError_t kvs_unet_apply(kvs_unet* u, const double* r, double in_scale, double out_scale, double* z, Dims d,
-                          hipStream_t s);
-
-hipError_t kvs_unet_apply(kvs_unet* u, const double* r, double in_scale, double out_scale, double* z, Dims d,
-                          hipStream_t s) {
+// Network application: z = out_scale * U(in_scale * r) (scales from ctl).
+hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, double* z, Dims d, hipStream_t s) {
     hipError_t e = unet_ensure_acts(u, d);
     if (e != hipSuccess) return e;
     const Dims d1 = coarse(d), d2 = coarse(d1);
     const std::vector<UnetLayerDesc>& L = u->layers;
     const int nl = (int)L.size();
-    // e0
-    {
-        const int nb = blocks_for_waves(d.n());
-        const bf16* W = u->w + u->w_off[0];
-        hipLaunchKernelGGL(conv3_first<16>, dim3(nb), dim3(256), 0, s, r, in_scale, d, W, u->e0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if ((e = launch_pool(u->c0, u->e0, d, u->p0, s)) != hipSuccess) return e;
-    if ((e = launch_conv(u->c0, u->c1, u->p0, nullptr, d1, 1, u->w + u->w_off[1], u->e1, s)) != hipSuccess) return e;
-    if ((e = launch_pool(u->c1, u->e1, d1, u->p1, s)) != hipSuccess) return e;
-    // bottleneck: layers 2 .. nl-4
+    const int* stop = ctl.stop;
+    hipLaunchKernelGGL(conv3_first<16>, dim3(blocks_for_waves(d.n())), dim3(256), 0, s, r, ctl, d, u->w + u->w_off[0],
+                       u->e0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_pool(u->c0, u->e0, d, u->p0, s, stop)) != hipSuccess) return e;
+    if ((e = launch_conv(u->c0, u->c1, u->p0, (const bf16*)nullptr, d1, 1, u->w + u->w_off[1], u->e1, s, stop)) != hipSuccess)
+        return e;
+    if ((e = launch_pool(u->c1, u->e1, d1, u->p1, s, stop)) != hipSuccess) return e;
     const bf16* in = u->p1;
-    bf16* outb = u->ba;
     for (int l = 2; l <= nl - 4; ++l) {
-        if ((e = launch_conv(L[l].ci, L[l].co, in, nullptr, d2, L[l].dil, u->w + u->w_off[l], outb, s)) != hipSuccess)
+        bf16* out = u->bott[(size_t)(l - 2)];
+        if ((e = launch_conv(L[l].ci, L[l].co, in, (const bf16*)nullptr, d2, L[l].dil, u->w + u->w_off[l], out, s,
+                             stop)) != hipSuccess)
             return e;
-        in = outb;
-        outb = outb == u->ba ? u->bb : u->ba;
+        in = out;
     }
-    const int ld1 = nl - 3, ld0 = nl - 2, lo = nl - 1;
-    if ((e = launch_conv(u->c1, u->c0, u->e1, in, d1, 1, u->w + u->w_off[ld1], u->g1, s)) != hipSuccess) return e;
-    if ((e = launch_conv(u->c0, u->c0, u->e0, u->g1, d, 1, u->w + u->w_off[ld0], u->g0, s)) != hipSuccess) return e;
-    (void)lo;
-    {
-        const int nb = (int)((d.n() + 255) / 256);
-        hipLaunchKernelGGL(conv3_out<16>, dim3(nb), dim3(256), 0, s, u->g0, d, u->w_out, out_scale, z);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const int ld1 = nl - 3, ld0 = nl - 2;
+    if ((e = launch_conv(u->c1, u->c0, u->e1, in, d1, 1, u->w + u->w_off[ld1], u->g1, s, stop)) != hipSuccess) return e;
+    if ((e = launch_conv(u->c0, u->c0, u->e0, u->g1, d, 1, u->w + u->w_off[ld0], u->g0, s, stop)) != hipSuccess) return e;
+    hipLaunchKernelGGL(conv3_out<16>, dim3(nblocks256(d.n())), dim3(256), 0, s, u->g0, d, u->w_out, ctl, z);
+    return hipGetLastError();
 }
+
+hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const kvs_grid& g, const double* in_scale,
+                                 const double* out_scale, const int* stop, hipStream_t s) {
+    NetCtl ctl{in_scale, out_scale, stop, 1.0, 1.0};
+    return kvs_unet_apply(u, r, ctl, z, Dims{(int)g.nx, (int)g.ny, (int)g.nz}, s);
+}
+
+namespace {
+
+// dispatch of the weight-gradient reduction
+hipError_t launch_dw(kvs_unet* u, int ci, int co, bool first, const bf16* A, const bf16* B, const double* r,
+                     double in_scale, Dims d, int dil, const float* dy, int64_t m_off, int accumulate, hipStream_t s) {
+    const int nblk = (int)std::min<long long>(256, (d.n() + 63) / 64);
+    const int64_t need = 27LL * nblk * ci * co;
+    if (need > u->wpart_n) {
+        ufree(u->wpart);
+        hipError_t e = hipMalloc(&u->wpart, sizeof(float) * need);
+        if (e != hipSuccess) return e;
+        u->wpart_n = need;
+    }
+    const dim3 grid(nblk, 27);
+#define KVS_DW_CASE(CI_, CO_, F_)                                                                                  \
+    if (ci == CI_ && co == CO_ && first == F_) {                                                                   \
+        hipLaunchKernelGGL((dw_partial<CI_, CO_, F_>), grid, dim3(256), 0, s, A, B, r, in_scale, d, dil, dy, u->wpart); \
+    } else
+    KVS_DW_CASE(1, 16, true)
+    KVS_DW_CASE(16, 32, false)
+    KVS_DW_CASE(32, 64, false)
+    KVS_DW_CASE(64, 64, false)
+    KVS_DW_CASE(64, 32, false)
+    KVS_DW_CASE(32, 16, false)
+    KVS_DW_CASE(16, 16, false)
+    KVS_DW_CASE(16, 1, false) { return hipErrorInvalidValue; }
+#undef KVS_DW_CASE
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(dw_reduce, dim3(nblocks256(27LL * ci * co)), dim3(256), 0, s, u->wpart, nblk, ci, co,
+                       u->grad + m_off, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float* a, bf16* b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(f32_to_bf16, dim3(nblocks256(n)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+
+// Backward pass of the last forward (input r, in_scale), given the FP32
+// gradient dzf of the raw network output (before out_scale) on the interior.
+// Accumulates (or writes) the flat FP32 weight gradient.
+hipError_t unet_backward(kvs_unet* u, const double* r, double in_scale, Dims d, int accumulate, hipStream_t s) {
+    hipError_t e = unet_ensure_train(u, d);
+    if (e != hipSuccess) return e;
+    const Dims d1 = coarse(d), d2 = coarse(d1);
+    const std::vector<UnetLayerDesc>& L = u->layers;
+    const int nl = (int)L.size();
+    const int lo = nl - 1, ld0 = nl - 2, ld1 = nl - 3;
+    const int c0 = u->c0, c1 = u->c1;
+    // output layer
+    if ((e = launch_dw(u, c0, 1, false, u->g0, nullptr, nullptr, 0.0, d, 1, u->dzf, u->m_off[lo], accumulate, s)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(out_backward<16>, dim3(nblocks256(d.n())), dim3(256), 0, s, u->dzf, d, u->w_out, u->dg0);
+    // dec0: g0 = conv(e0 + up g1)
+    if ((e = launch_dw(u, c0, c0, false, u->e0, u->g1, nullptr, 0.0, d, 1, u->dg0, u->m_off[ld0], accumulate, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = to_bf16(u->dg0, u->gb, d.n() * c0, s)) != hipSuccess) return e;
+    if ((e = launch_conv(c0, c0, u->gb, (const bf16*)nullptr, d, 1, u->wt + u->wt_off[ld0], u->de0, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(up_adjoint, dim3(nblocks256(d1.n() * c0)), dim3(256), 0, s, u->de0, d, c0, u->dg1);
+    // dec1: g1 = conv(e1 + up b_last)
+    const bf16* b_last = u->bott[(size_t)(u->nbott - 1)];
+    if ((e = launch_dw(u, c1, c0, false, u->e1, b_last, nullptr, 0.0, d1, 1, u->dg1, u->m_off[ld1], accumulate, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = to_bf16(u->dg1, u->gb, d1.n() * c0, s)) != hipSuccess) return e;
+    if ((e = launch_conv(c0, c1, u->gb, (const bf16*)nullptr, d1, 1, u->wt + u->wt_off[ld1], u->de1, s)) != hipSuccess)
+        return e;
+    float* dcur = u->dbott[(size_t)(u->nbott - 1)];  // gradient of the last bottleneck output (C1 channels)
+    hipLaunchKernelGGL(up_adjoint, dim3(nblocks256(d2.n() * c1)), dim3(256), 0, s, u->de1, d1, c1, dcur);
+    // bottleneck, last to first
+    for (int l = nl - 4; l >= 2; --l) {
+        const int q = l - 2;
+        const bf16* xin = q == 0 ? u->p1 : u->bott[(size_t)(q - 1)];
+        float* dxin = q == 0 ? u->dp1 : u->dbott[(size_t)(q - 1)];
+        if ((e = launch_dw(u, L[l].ci, L[l].co, false, xin, nullptr, nullptr, 0.0, d2, L[l].dil, dcur, u->m_off[l],
+                           accumulate, s)) != hipSuccess)
+            return e;
+        if ((e = to_bf16(dcur, u->gb, d2.n() * L[l].co, s)) != hipSuccess) return e;
+        if ((e = launch_conv(L[l].co, L[l].ci, u->gb, (const bf16*)nullptr, d2, L[l].dil, u->wt + u->wt_off[l], dxin,
+                             s)) != hipSuccess)
+            return e;
+        dcur = dxin;
+    }
+    // pool(e1) -> bottleneck input
+    hipLaunchKernelGGL(pool_adjoint_add, dim3(nblocks256(d1.n() * c1)), dim3(256), 0, s, u->dp1, d1, c1, u->de1);
+    // e1 = conv(pool e0)
+    if ((e = launch_dw(u, c0, c1, false, u->p0, nullptr, nullptr, 0.0, d1, 1, u->de1, u->m_off[1], accumulate, s)) !=
+        hipSuccess)
+        return e;
+    if ((e = to_bf16(u->de1, u->gb, d1.n() * c1, s)) != hipSuccess) return e;
+    if ((e = launch_conv(c1, c0, u->gb, (const bf16*)nullptr, d1, 1, u->wt + u->wt_off[1], u->dp0, s)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(pool_adjoint_add, dim3(nblocks256(d.n() * c0)), dim3(256), 0, s, u->dp0, d, c0, u->de0);
+    // e0 = conv(in_scale r)
+    return launch_dw(u, 1, c0, true, nullptr, nullptr, r, in_scale, d, 1, u->de0, u->m_off[0], accumulate, s);
+}
+
+}  // namespace
+
+namespace {
+
+hipError_t launch_pool(int c, const bf16* fine, Dims d, bf16* out, hipStream_t s, const int* stop) {
+    const long long threads = coarse(d).n() * (c / 8);
+    const int nb = (int)((threads + 255) / 256);
+    switch (c) {
+        case 8: hipLaunchKernelGGL(pool2<8>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
+        case 16: hipLaunchKernelGGL(pool2<16>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
+        case 32: hipLaunchKernelGGL(pool2<32>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
+        case 64: hipLaunchKernelGGL(pool2<64>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
 
 // ---- C ABI ---------------------------------------------------------------------
 
@@ -375,30 +820,36 @@ kvs_status ufail(kvs_unet* u, kvs_status s, const std::string& m) {
     return s;
 }
 
-// fp32 master -> device bf16 (inference layout) and fp32 output weights
+// host master -> device master, bf16 forward / transposed layouts, fp32 out
 kvs_status upload_weights(kvs_unet* u) {
-    std::vector<bf16> wb((size_t)u->n_w, (bf16)0.f);
-    size_t m = 0;
+    std::vector<bf16> wb((size_t)u->n_w, (bf16)0.f), wtb((size_t)std::max<int64_t>(u->n_wt, 1), (bf16)0.f);
     const int nl = (int)u->layers.size();
     for (int l = 0; l < nl - 1; ++l) {
         const UnetLayerDesc& L = u->layers[(size_t)l];
-        const int64_t K = 27 * L.ci, kp = u->kp[(size_t)l];
+        const float* m = u->host_master.data() + u->m_off[(size_t)l];
+        const int64_t K = 27LL * L.ci, kp = u->kp[(size_t)l], kpt = u->kpt[(size_t)l];
         for (int co = 0; co < L.co; ++co)
-            for (int64_t k = 0; k < K; ++k) wb[(size_t)(u->w_off[(size_t)l] + co * kp + k)] = (bf16)u->host_master[m++];
+            for (int64_t k = 0; k < K; ++k) wb[(size_t)(u->w_off[(size_t)l] + co * kp + k)] = (bf16)m[co * K + k];
+        if (L.ci == 1) continue;
+        // transposed: Wt[ci][tap' * co + c] = W[c][(26 - tap') * ci + ci]
+        for (int ci = 0; ci < L.ci; ++ci)
+            for (int tp = 0; tp < 27; ++tp)
+                for (int c = 0; c < L.co; ++c)
+                    wtb[(size_t)(u->wt_off[(size_t)l] + ci * kpt + tp * L.co + c)] =
+                        (bf16)m[(int64_t)c * K + (26 - tp) * L.ci + ci];
     }
     std::vector<float> wo((size_t)27 * u->c0);
-    for (size_t q = 0; q < wo.size(); ++q) wo[q] = (float)(bf16)u->host_master[m++];
+    const float* mo = u->host_master.data() + u->m_off[(size_t)(nl - 1)];
+    for (size_t q = 0; q < wo.size(); ++q) wo[q] = (float)(bf16)mo[q];
     if (hipMemcpy(u->w, wb.data(), sizeof(bf16) * wb.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(u->w_out, wo.data(), sizeof(float) * wo.size(), hipMemcpyHostToDevice) != hipSuccess)
+        (u->n_wt > 0 && hipMemcpy(u->wt, wtb.data(), sizeof(bf16) * u->n_wt, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(u->w_out, wo.data(), sizeof(float) * wo.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(u->master, u->host_master.data(), sizeof(float) * u->n_master, hipMemcpyHostToDevice) != hipSuccess)
         return ufail(u, KVS_EDEVICE, "weight upload failed");
     return KVS_OK;
 }
 
-int64_t master_count(const kvs_unet* u) {
-    int64_t n = 0;
-    for (const UnetLayerDesc& L : u->layers) n += (int64_t)27 * L.ci * L.co;
-    return n;
-}
+Dims dims_of(int64_t nx, int64_t ny, int64_t nz) { return Dims{(int)nx, (int)ny, (int)nz}; }
 }  // namespace
 
 extern "C" {
@@ -407,8 +858,7 @@ kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_un
     if (!out) return ufail(nullptr, KVS_EINVAL, "out is NULL");
     *out = nullptr;
     const int c0 = channels ? channels[0] : 16, c1 = channels ? channels[1] : 32, c2 = channels ? channels[2] : 64;
-    if (c0 != 16 || c1 != 32 || c2 != 64)
-        return ufail(nullptr, KVS_EINVAL, "supported channel counts: 16, 32, 64");
+    if (c0 != 16 || c1 != 32 || c2 != 64) return ufail(nullptr, KVS_EINVAL, "supported channel counts: 16, 32, 64");
     if (n_bottleneck < 2 || n_bottleneck > 8) return ufail(nullptr, KVS_EINVAL, "n_bottleneck must be 2..8");
     kvs_unet* u = new (std::nothrow) kvs_unet();
     if (!u) return ufail(nullptr, KVS_ENOMEM, "host allocation failed");
@@ -417,41 +867,60 @@ kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_un
     u->c2 = c2;
     u->nbott = n_bottleneck;
     build_layers(u);
-    u->host_master.assign((size_t)master_count(u), 0.f);
-    if (hipMalloc(&u->w, sizeof(bf16) * u->n_w) != hipSuccess ||
-        hipMalloc(&u->w_out, sizeof(float) * 27 * c0) != hipSuccess) {
-        if (u->w) (void)hipFree(u->w);
-        delete u;
+    u->host_master.assign((size_t)u->n_master, 0.f);
+    bool ok = hipMalloc(&u->w, sizeof(bf16) * u->n_w) == hipSuccess;
+    ok = ok && hipMalloc(&u->wt, sizeof(bf16) * std::max<int64_t>(u->n_wt, 1)) == hipSuccess;
+    ok = ok && hipMalloc(&u->w_out, sizeof(float) * 27 * c0) == hipSuccess;
+    for (float** p : {&u->master, &u->grad, &u->adam_m, &u->adam_v})
+        ok = ok && hipMalloc(p, sizeof(float) * u->n_master) == hipSuccess;
+    ok = ok && hipMemset(u->grad, 0, sizeof(float) * u->n_master) == hipSuccess;
+    ok = ok && hipMemset(u->adam_m, 0, sizeof(float) * u->n_master) == hipSuccess;
+    ok = ok && hipMemset(u->adam_v, 0, sizeof(float) * u->n_master) == hipSuccess;
+    if (!ok) {
+        kvs_unet_destroy(u);
         return ufail(nullptr, KVS_ENOMEM, "device allocation failed");
     }
     kvs_status s = upload_weights(u);
-    if (s != KVS_OK) return s;
+    if (s != KVS_OK) {
+        kvs_unet_destroy(u);
+        return s;
+    }
     *out = u;
     return KVS_OK;
 }
 
 void kvs_unet_destroy(kvs_unet* u) {
     if (!u) return;
+    (void)hipDeviceSynchronize();
     unet_free_acts(u);
-    if (u->w) (void)hipFree(u->w);
-    if (u->w_out) (void)hipFree(u->w_out);
+    unet_free_train(u);
+    ufree(u->w);
+    ufree(u->wt);
+    ufree(u->w_out);
+    ufree(u->master);
+    ufree(u->grad);
+    ufree(u->adam_m);
+    ufree(u->adam_v);
     delete u;
 }
 
 const char* kvs_unet_last_error(const kvs_unet* u) { return u ? u->err.c_str() : g_unet_err.c_str(); }
 
-int64_t kvs_unet_num_weights(const kvs_unet* u) { return u ? (int64_t)u->host_master.size() : 0; }
+int64_t kvs_unet_num_weights(const kvs_unet* u) { return u ? u->n_master : 0; }
 
 kvs_status kvs_unet_set_weights(kvs_unet* u, const float* w, int64_t n) {
     if (!u || !w) return KVS_EINVAL;
-    if (n != (int64_t)u->host_master.size()) return ufail(u, KVS_EINVAL, "wrong weight count");
+    if (n != u->n_master) return ufail(u, KVS_EINVAL, "wrong weight count");
     std::memcpy(u->host_master.data(), w, sizeof(float) * n);
+    u->adam_t = 0;
+    if (hipMemset(u->adam_m, 0, sizeof(float) * n) != hipSuccess || hipMemset(u->adam_v, 0, sizeof(float) * n) != hipSuccess)
+        return ufail(u, KVS_EDEVICE, "reset of the optimiser state failed");
     return upload_weights(u);
 }
 
 kvs_status kvs_unet_get_weights(const kvs_unet* u, float* w, int64_t n) {
     if (!u || !w) return KVS_EINVAL;
-    if (n != (int64_t)u->host_master.size()) return KVS_EINVAL;
+    if (n != u->n_master) return KVS_EINVAL;
     std::memcpy(w, u->host_master.data(), sizeof(float) * n);
     return KVS_OK;
 }
@@ -460,15 +929,92 @@ kvs_status kvs_unet_forward(kvs_unet* u, const double* r, double in_scale, doubl
                             int64_t ny, int64_t nz, void* stream) {
     if (!u || !r || !z) return KVS_EINVAL;
     if (nx < 3 || ny < 3 || nz < 3) return ufail(u, KVS_EINVAL, "grid needs >= 3 nodes per axis");
-    const Dims d{(int)nx, (int)ny, (int)nz};
-    hipError_t e = kvs_unet_apply(u, r, in_scale, out_scale, z, d, (hipStream_t)stream);
+    NetCtl ctl{nullptr, nullptr, nullptr, in_scale, out_scale};
+    hipError_t e = kvs_unet_apply(u, r, ctl, z, dims_of(nx, ny, nz), (hipStream_t)stream);
     if (e != hipSuccess) return ufail(u, KVS_EDEVICE, std::string("unet forward: ") + hipGetErrorString(e));
     return KVS_OK;
 }
 
-// One MFMA conv on host buffers (BF16 bit patterns), for verification:
-// out[v][co] = sum W[co][tap*ci + c] * (A[p][c] + B[p/2][c]), W padded to
-// kvs_unet_conv_kpad(ci) columns.
+kvs_status kvs_unet_backward(kvs_unet* u, const double* r, double in_scale, const double* dz, double dz_scale,
+                             int64_t nx, int64_t ny, int64_t nz, int32_t accumulate, void* stream) {
+    if (!u || !r || !dz) return KVS_EINVAL;
+    const Dims d = dims_of(nx, ny, nz);
+    if (u->dims.nx != d.nx || u->dims.ny != d.ny || u->dims.nz != d.nz)
+        return ufail(u, KVS_ESTATE, "backward needs a forward pass on the same grid first");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = unet_ensure_train(u, d);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(scale_to_f32, dim3(nblocks256(d.n())), dim3(256), 0, s, dz, dz_scale, u->dzf, d.n());
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = unet_backward(u, r, in_scale, d, accumulate, s);
+    if (e != hipSuccess) return ufail(u, KVS_EDEVICE, std::string("unet backward: ") + hipGetErrorString(e));
+    return KVS_OK;
+}
+
+kvs_status kvs_unet_get_grad(const kvs_unet* u, float* g, int64_t n) {
+    if (!u || !g || n != u->n_master) return KVS_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(g, u->grad, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess)
+        return KVS_EDEVICE;
+    return KVS_OK;
+}
+
+kvs_status kvs_unet_train_sample(kvs_unet* u, const double* b, const double* xs, int64_t nx, int64_t ny, int64_t nz,
+                                 int32_t accumulate, double* loss, void* stream) {
+    if (!u || !b || !xs) return KVS_EINVAL;
+    const Dims d = dims_of(nx, ny, nz);
+    hipStream_t s = (hipStream_t)stream;
+    NetCtl ctl{nullptr, nullptr, nullptr, 1.0, 1.0};
+    hipError_t e = unet_ensure_train(u, d);
+    double* z = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&z, sizeof(double) * d.n());
+    if (e == hipSuccess) e = kvs_unet_apply(u, b, ctl, z, d, s);
+    const int nb = nblocks256(d.n());
+    std::vector<double> part((size_t)2 * nb);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(anorm_loss, dim3(nb), dim3(256), 0, s, z, xs, d, u->dz_raw, u->part);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(part.data(), u->part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    double eAe = 0.0, xAx = 0.0;
+    for (int q = 0; q < nb; ++q) {
+        eAe += part[(size_t)2 * q];
+        xAx += part[(size_t)2 * q + 1];
+    }
+    if (e == hipSuccess && !(xAx > 0.0)) {
+        (void)hipFree(z);
+        return ufail(u, KVS_EINVAL, "training target has zero A-norm");
+    }
+    // L = e.Ae / xAx, dL/dz = 2 A e / xAx
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(scale_to_f32, dim3(nb), dim3(256), 0, s, u->dz_raw, 2.0 / xAx, u->dzf, d.n());
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = unet_backward(u, b, 1.0, d, accumulate, s);
+    if (z) (void)hipFree(z);
+    if (e != hipSuccess) return ufail(u, KVS_EDEVICE, std::string("unet train: ") + hipGetErrorString(e));
+    if (loss) *loss = eAe / xAx;
+    return KVS_OK;
+}
+
+kvs_status kvs_unet_adam_step(kvs_unet* u, double lr, int32_t n_samples, void* stream) {
+    if (!u || n_samples < 1 || !(lr > 0.0)) return KVS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    u->adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)u->adam_t), c2 = 1.f - std::pow(b2, (float)u->adam_t);
+    hipLaunchKernelGGL(adam_kernel, dim3(nblocks256(u->n_master)), dim3(256), 0, s, u->master, u->grad, u->adam_m,
+                       u->adam_v, (long long)u->n_master, (float)lr, b1, b2, 1e-8f, c1, c2, 1.f / (float)n_samples);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(u->host_master.data(), u->master, sizeof(float) * u->n_master, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return ufail(u, KVS_EDEVICE, std::string("adam: ") + hipGetErrorString(e));
+    return upload_weights(u);
+}
+
 int64_t kvs_unet_conv_kpad(int32_t ci) { return ci == 1 ? 32 : (27 * (int64_t)ci + 31) / 32 * 32; }
 
 kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16_t* A, const uint16_t* B, int64_t nx,
@@ -486,12 +1032,61 @@ kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16
     if (e == hipSuccess) e = hipMemcpy(dA, A, 2 * na, hipMemcpyHostToDevice);
     if (e == hipSuccess && B) e = hipMemcpy(dB, B, 2 * nbb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dW, W, 2 * nw, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_conv(ci, co, dA, dB, d, dil, dW, dO, nullptr);
+    if (e == hipSuccess) e = launch_conv(ci, co, dA, (const bf16*)dB, d, dil, dW, dO, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(out, dO, 2 * no, hipMemcpyDeviceToHost);
     for (bf16* p : {dA, dB, dW, dO})
         if (p) (void)hipFree(p);
     if (e != hipSuccess) return ufail(nullptr, KVS_EDEVICE, std::string("conv check: ") + hipGetErrorString(e));
+    return KVS_OK;
+}
+
+// Training pair from the solver's own projection on ctx (FP64 context):
+// phi* = converged solution of the current force (Jacobi-PCG to 1e-11); with
+// k_snapshot > 0 the pair is the CG error after k iterations,
+// x = phi* - phi_k, else x = phi*; b = A x with the context's spacing; both
+// scaled so that b has unit RMS.  b, x: device fields of N doubles.
+kvs_status kvs_unet_make_sample(kvs_ctx* c, int64_t k_snapshot, double* b, double* x, double* b_rms) {
+    if (!c || !b || !x || k_snapshot < 0) return KVS_EINVAL;
+    const Dims d{(int)c->grid.nx, (int)c->grid.ny, (int)c->grid.nz};
+    kvs_solve_opts o{};
+    o.tol = 1e-11;
+    o.max_iter = 100000;
+    o.precond = KVS_PC_JACOBI;
+    kvs_status st = kvs_project(c, &o, nullptr);
+    if (st != KVS_OK) return st;
+    hipStream_t s = c->stream;
+    const int nb = nblocks256(d.n());
+    hipError_t e = hipMemcpyAsync(x, c->phi, sizeof(double) * d.n(), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && k_snapshot > 0) {
+        o.fixed_iters = k_snapshot;
+        if (hipStreamSynchronize(s) != hipSuccess) return KVS_EDEVICE;
+        st = kvs_project(c, &o, nullptr);
+        if (st != KVS_OK) return st;
+        hipLaunchKernelGGL(sub_kernel, dim3(nb), dim3(256), 0, s, x, c->phi, x, d.n());
+        e = hipGetLastError();
+    }
+    double* part = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&part, sizeof(double) * nb);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(apply_A_kernel, dim3(nb), dim3(256), 0, s, x, d, 1.0 / (c->grid.hx * c->grid.hx),
+                           1.0 / (c->grid.hy * c->grid.hy), 1.0 / (c->grid.hz * c->grid.hz), b, part);
+        e = hipGetLastError();
+    }
+    std::vector<double> hp((size_t)nb);
+    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (part) (void)hipFree(part);
+    if (e != hipSuccess) return KVS_EDEVICE;
+    double bb = 0.0;
+    for (double v : hp) bb += v;
+    const long long nint = (long long)(d.nx - 2) * (d.ny - 2) * (d.nz - 2);
+    const double rms = std::sqrt(bb / (double)nint);
+    if (!(rms > 0.0)) return KVS_EINVAL;
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, s, b, 1.0 / rms, d.n());
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, s, x, 1.0 / rms, d.n());
+    if (hipStreamSynchronize(s) != hipSuccess) return KVS_EDEVICE;
+    if (b_rms) *b_rms = rms;
     return KVS_OK;
 }
 

@@ -72,6 +72,8 @@ SIGNATURES = {
     "kvs_set_envelope": ([_P, _D, C.c_int64], C.c_int),
     "kvs_project": ([_P, C.POINTER(kvs_solve_opts), C.POINTER(kvs_solve_report)], C.c_int),
     "kvs_set_projected_force": ([_P, _D], C.c_int),
+    "kvs_set_preconditioner": ([_P, _P], C.c_int),
+    "kvs_last_fallbacks": ([_P, _I64], C.c_int),
     "kvs_get_projected_force": ([_P, _D], C.c_int),
     "kvs_get_phi": ([_P, _D], C.c_int),
     "kvs_set_probes": ([_P, _I64, C.c_int64, C.c_int32], C.c_int),
@@ -105,6 +107,13 @@ SIGNATURES = {
     "kvs_unet_forward": ([_P, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                           C.c_void_p], C.c_int),
     "kvs_unet_conv_kpad": ([C.c_int32], C.c_int64),
+    "kvs_unet_backward": ([_P, C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_int64, C.c_int64, C.c_int64,
+                           C.c_int32, C.c_void_p], C.c_int),
+    "kvs_unet_get_grad": ([_P, C.POINTER(C.c_float), C.c_int64], C.c_int),
+    "kvs_unet_train_sample": ([_P, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
+                               C.POINTER(C.c_double), C.c_void_p], C.c_int),
+    "kvs_unet_adam_step": ([_P, C.c_double, C.c_int32, C.c_void_p], C.c_int),
+    "kvs_unet_make_sample": ([_P, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "kvs_unet_conv_check": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint16), C.POINTER(C.c_uint16), C.c_int64,
                              C.c_int64, C.c_int64, C.POINTER(C.c_uint16), C.POINTER(C.c_uint16)], C.c_int),
     "kvs_batch_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
@@ -443,3 +452,43 @@ def kvs_unet_conv_check(ci, co, dil, A_bits, B_bits, dims, W_bits):
                                       B.ctypes.data_as(u16) if B is not None else None, int(nx), int(ny), int(nz),
                                       W.ctypes.data_as(u16), out.ctypes.data_as(u16)), None)
     return out
+
+
+def kvs_unet_backward(net, r_ptr, in_scale, dz_ptr, dz_scale, dims, accumulate=False, stream=None):
+    nx, ny, nz = dims
+    _ucheck(lib().kvs_unet_backward(net, C.c_void_p(r_ptr), float(in_scale), C.c_void_p(dz_ptr), float(dz_scale),
+                                    int(nx), int(ny), int(nz), int(bool(accumulate)), stream or None), net)
+
+
+def kvs_unet_get_grad(net):
+    g = np.empty(kvs_unet_num_weights(net), dtype=np.float32)
+    _ucheck(lib().kvs_unet_get_grad(net, g.ctypes.data_as(C.POINTER(C.c_float)), g.size), net)
+    return g
+
+
+def kvs_unet_train_sample(net, b_ptr, x_ptr, dims, accumulate=False, stream=None):
+    nx, ny, nz = dims
+    loss = C.c_double()
+    _ucheck(lib().kvs_unet_train_sample(net, C.c_void_p(b_ptr), C.c_void_p(x_ptr), int(nx), int(ny), int(nz),
+                                        int(bool(accumulate)), C.byref(loss), stream or None), net)
+    return loss.value
+
+
+def kvs_unet_adam_step(net, lr, n_samples=1, stream=None):
+    _ucheck(lib().kvs_unet_adam_step(net, float(lr), int(n_samples), stream or None), net)
+
+
+def kvs_unet_make_sample(ctx, k_snapshot, b_ptr, x_ptr):
+    rms = C.c_double()
+    _check(lib().kvs_unet_make_sample(ctx, int(k_snapshot), C.c_void_p(b_ptr), C.c_void_p(x_ptr), C.byref(rms)), ctx)
+    return rms.value
+
+
+def kvs_set_preconditioner(ctx, net):
+    _check(lib().kvs_set_preconditioner(ctx, net), ctx)
+
+
+def kvs_last_fallbacks(ctx):
+    v = C.c_int64()
+    _check(lib().kvs_last_fallbacks(ctx, C.byref(v)), ctx)
+    return v.value

@@ -86,3 +86,167 @@ def test_network_forward_matches_oracle(kvs):
     say(f"forward rel L2 {err:.2e}")
     assert not z[0].any() and not z[:, 0].any() and np.isfinite(z).all()
     assert err < 2e-2
+
+
+def random_weights(rng, nbott=4, scale=1.0):
+    shapes = unet.layer_shapes(16, 32, 64, nbott)
+    return np.concatenate([scale * rng.standard_normal(27 * ci * co) / np.sqrt(27 * ci) for ci, co, _ in shapes])
+
+
+def test_backward_matches_oracle(kvs):
+    """Weight gradients of the GPU backward pass against the oracle's, which
+    rounds to BF16 at the same points; per layer within 2e-2 relative L2
+    (the residue is BF16 rounding flips of activation gradients where the
+    FP32 sums of the two sides straddle a rounding boundary)."""
+    import torch
+    say("case unet backward")
+    rng = np.random.default_rng(21)
+    w = random_weights(rng).astype(np.float32)
+    net = kvs.kvs_unet_create((16, 32, 64), 4)
+    nz, ny, nx = 18, 20, 22
+    r = np.zeros((nz, ny, nx))
+    r[1:-1, 1:-1, 1:-1] = rng.standard_normal((nz - 2, ny - 2, nx - 2))
+    dz = np.zeros_like(r)
+    dz[1:-1, 1:-1, 1:-1] = rng.standard_normal((nz - 2, ny - 2, nx - 2))
+    try:
+        kvs.kvs_unet_set_weights(net, w)
+        rd, dzd = torch.from_numpy(r).cuda(), torch.from_numpy(dz).cuda()
+        zd = torch.zeros_like(rd)
+        st = torch.cuda.current_stream().cuda_stream
+        kvs.kvs_unet_forward(net, rd.data_ptr(), 0.8, 1.0, zd.data_ptr(), (nx, ny, nz), st)
+        kvs.kvs_unet_backward(net, rd.data_ptr(), 0.8, dzd.data_ptr(), 1.5, (nx, ny, nz), False, st)
+        g = kvs.kvs_unet_get_grad(net).astype(np.float64)
+    finally:
+        kvs.kvs_unet_destroy(net)
+    go = unet.backward(r, 0.8, w.astype(np.float64), dz, 1.5, nbott=4)
+    off = 0
+    for li, (ci, co, _) in enumerate(unet.layer_shapes(16, 32, 64, 4)):
+        n = 27 * ci * co
+        err = np.linalg.norm(g[off:off + n] - go[off:off + n]) / np.linalg.norm(go[off:off + n])
+        say(f"layer {li} ({ci}->{co}): grad rel L2 {err:.2e}")
+        assert err < 2e-2, (li, err)
+        off += n
+
+
+def unit_ctx(kvs, n, seed):
+    """FP64 context on an n^3 grid of unit spacing with a random smooth
+    force (sum of Gaussian pushes with random centres, widths, directions)."""
+    from workloads import gaussian_push
+    rng = np.random.default_rng(seed)
+    grid = (n, n, n, 1.0, 1.0, 1.0)
+    F = np.zeros((3, n, n, n))
+    for _ in range(3):
+        c = rng.uniform(-n / 4, n / 4, 3)
+        F += rng.standard_normal() * gaussian_push(grid, rng.uniform(1, n / 8), rng.uniform(2, n / 4), 1.0,
+                                                   centre=tuple(c), axis=int(rng.integers(0, 3)))
+    ctx = kvs.kvs_create(grid)
+    kvs.kvs_set_force(ctx, F)
+    return ctx, grid
+
+
+def test_make_sample_and_training_loss(kvs):
+    import torch
+    import oracle
+    say("case make_sample / train loss")
+    n = 24
+    ctx, grid = unit_ctx(kvs, n, 3)
+    net = kvs.kvs_unet_create((16, 32, 64), 4)
+    try:
+        b = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        x = torch.zeros_like(b)
+        for k in (0, 5):
+            kvs.kvs_unet_make_sample(ctx, k, b.data_ptr(), x.data_ptr())
+            bh, xh = b.cpu().numpy(), x.cpu().numpy()
+            # b = A x with A = -lap on the interior, unit RMS
+            np.testing.assert_allclose(bh, -oracle.laplacian(grid, xh), atol=1e-12 * np.abs(bh).max())
+            assert np.sqrt(np.mean(bh[1:-1, 1:-1, 1:-1] ** 2)) == pytest.approx(1.0, rel=1e-12)
+        w = random_weights(np.random.default_rng(5), scale=0.5).astype(np.float32)
+        kvs.kvs_unet_set_weights(net, w)
+        st = torch.cuda.current_stream().cuda_stream
+        loss = kvs.kvs_unet_train_sample(net, b.data_ptr(), x.data_ptr(), (n, n, n), False, st)
+        z = torch.zeros_like(b)
+        kvs.kvs_unet_forward(net, b.data_ptr(), 1.0, 1.0, z.data_ptr(), (n, n, n), st)
+        torch.cuda.synchronize()
+        e = z.cpu().numpy() - xh
+        ref = np.vdot(e, -oracle.laplacian(grid, e)) / np.vdot(xh, -oracle.laplacian(grid, xh))
+        assert loss == pytest.approx(ref, rel=1e-9)
+    finally:
+        kvs.kvs_unet_destroy(net)
+        kvs.kvs_destroy(ctx)
+
+
+def test_untrained_network_falls_back_to_jacobi(kvs):
+    """All-zero weights give z = 0, so every flexible-PCG iteration takes the
+    Jacobi fallback: the solve converges like Jacobi-PCG."""
+    say("case fpcg fallback")
+    from workloads import cfg1_homogeneous_fp64
+    w = cfg1_homogeneous_fp64()
+    net = kvs.kvs_unet_create((16, 32, 64), 4)
+    ctx = kvs.kvs_create(w.grid)
+    try:
+        kvs.kvs_set_force(ctx, w.F)
+        rj = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_JACOBI)
+        kvs.kvs_set_preconditioner(ctx, net)
+        rf = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_UNET)
+        fb = kvs.kvs_last_fallbacks(ctx)
+    finally:
+        kvs.kvs_destroy(ctx)
+        kvs.kvs_unet_destroy(net)
+    assert rf["status"] == 0 and rf["relres_true"] < 2e-8
+    assert abs(rf["iters"] - rj["iters"]) <= 2
+    # one fallback for the first z and one per iteration that continues; the
+    # converging iteration needs no new z
+    assert fb == rf["iters"]
+
+
+def test_training_then_fpcg_converges(kvs):
+    """A short training on solver-generated samples (force divergences and
+    CG-error snapshots at unit spacing) lowers the A-norm loss, and the
+    flexible PCG with the trained network converges to 1e-8 on a physical
+    grid without Jacobi fallbacks; the final phi is judged by the FP64 true
+    residual."""
+    import torch
+    import oracle
+    from workloads import gaussian_push
+    say("case short training + fpcg")
+    n = 40
+    net = kvs.kvs_unet_create((16, 32, 64), 4)
+    rng = np.random.default_rng(9)
+    kvs.kvs_unet_set_weights(net, random_weights(rng, scale=0.3).astype(np.float32))
+    samples = []
+    for sidx in range(6):
+        ctx, _ = unit_ctx(kvs, n, 100 + sidx)
+        for k in (0, 8, 30):
+            b = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+            x = torch.zeros_like(b)
+            kvs.kvs_unet_make_sample(ctx, k, b.data_ptr(), x.data_ptr())
+            samples.append((b, x))
+        kvs.kvs_destroy(ctx)
+    st = torch.cuda.current_stream().cuda_stream
+    losses = []
+    for it in range(80):
+        tot = 0.0
+        for q, (b, x) in enumerate(samples):
+            tot += kvs.kvs_unet_train_sample(net, b.data_ptr(), x.data_ptr(), (n, n, n), q > 0, st)
+        kvs.kvs_unet_adam_step(net, 2e-3, len(samples), st)
+        losses.append(tot / len(samples))
+    say(f"training loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.5 * losses[0]
+    h = 0.25e-3
+    grid = (64, 64, 64, h, h, h)
+    F = gaussian_push(grid, 1e-3, 3e-3, 1e4)
+    ctx = kvs.kvs_create(grid)
+    try:
+        kvs.kvs_set_force(ctx, F)
+        rj = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_JACOBI)
+        kvs.kvs_set_preconditioner(ctx, net)
+        rf = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_UNET)
+        phi = kvs.kvs_get_phi(ctx, (64, 64, 64))
+        fb = kvs.kvs_last_fallbacks(ctx)
+    finally:
+        kvs.kvs_destroy(ctx)
+        kvs.kvs_unet_destroy(net)
+    say(f"jacobi {rj['iters']} it {rj['ms']:.1f} ms; fpcg {rf['iters']} it {rf['ms']:.1f} ms, fallbacks {fb}")
+    b = oracle.divergence(grid, F)
+    assert oracle.true_relres(grid, b, phi) < 2e-8
+    assert rf["status"] == 0 and rj["status"] == 0

@@ -72,3 +72,40 @@ def test_forward_is_linear_and_masked():
     assert not z[0].any() and not z[:, :, -1].any() and np.abs(z).max() > 0
     z2 = unet.forward(r, 1.0, 4.0, w, nbott=3)
     np.testing.assert_allclose(z2, 2 * z)
+
+
+def test_backward_matches_finite_differences():
+    """In exact arithmetic the gradient of L(w) = <dz, y(w)> (y = raw network
+    output) returned by the oracle's backward pass equals the central finite
+    difference of L along random weight directions."""
+    rng = np.random.default_rng(11)
+    nb = 3
+    shapes = unet.layer_shapes(16, 32, 64, nb)
+    w = np.concatenate([rng.standard_normal(27 * ci * co) / np.sqrt(27 * ci) for ci, co, _ in shapes])
+    shp = (9, 10, 12)
+    r = np.zeros(shp)
+    r[1:-1, 1:-1, 1:-1] = rng.standard_normal((7, 8, 10))
+    dz = np.zeros(shp)
+    dz[1:-1, 1:-1, 1:-1] = rng.standard_normal((7, 8, 10))
+    g = unet.backward(r, 0.7, w, dz, 1.3, nbott=nb, exact=True)
+    assert g.shape == w.shape
+
+    def L(wv):
+        return 1.3 * np.sum(dz * unet.forward(r, 0.7, 1.0, wv, nbott=nb, exact=True))
+
+    # all layers at once: L is a polynomial of degree (number of layers) in
+    # w, so the central difference carries an O(eps^2) term
+    for trial in range(2):
+        d = rng.standard_normal(w.size)
+        eps = 1e-5
+        fd = (L(w + eps * d) - L(w - eps * d)) / (2 * eps)
+        assert np.dot(g, d) == pytest.approx(fd, rel=1e-6)
+    # one layer at a time L is linear in the perturbation: exact to rounding
+    off = 0
+    for li, (ci, co, _) in enumerate(shapes):
+        n = 27 * ci * co
+        d = np.zeros(w.size)
+        d[off:off + n] = rng.standard_normal(n)
+        fd = (L(w + 1e-3 * d) - L(w - 1e-3 * d)) / 2e-3
+        assert np.dot(g, d) == pytest.approx(fd, rel=1e-9), li
+        off += n
