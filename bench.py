@@ -33,6 +33,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of the FDTD step kernel from rocprofv3 counter runs of this
+# benchmark (256^3 inclusion workload, one launch without force): FETCH_SIZE
+# and WRITE_SIZE in KiB per dispatch, per tile-shape variant, taken on the
+# step-kernel source whose SHA-256 is STEP_SOURCE_SHA.  Each counter is
+# scaled by what it reads for a plain copy of known size (--copy-calibration):
+# FETCH_SIZE reports half of the bytes a copy reads, WRITE_SIZE all of the
+# bytes it writes.  A changed source voids the figures (traffic -> null).
+STEP_SOURCE_SHA = "7e7039c99904de06c94e81cd5a71de735a450936dd1b747289a518e66767ad0d"
+STEP_COUNTERS_KIB = {  # variant -> (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
+    0: (423027.7, 390144.0),
+    1: (398799.0, 390144.0),
+    2: (322245.5, 390144.0),
+    3: (302652.0, 390144.0),
+    4: (354507.6, 390144.0),
+}
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 METRIC = "FDTD Gcell-updates/s (% HBM roofline); projection time, learned-FPCG vs PCG @1e-8"
 
 
@@ -44,12 +61,46 @@ def parse():
     ap.add_argument("--workload", choices=["inclusions", "batch"], default="inclusions")
     ap.add_argument("--grid", type=int, default=256, help="cubic grid edge of the inclusion workload")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--cpu-sample-steps", type=int, default=100)
+    ap.add_argument("--step-variant", type=int, default=-1,
+                    help="pin the step-kernel tile shape (default: autotune); used by the counter runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     return ap.parse_args()
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def step_source_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2607_28414_amd", "csrc", "kvs_step.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def step_traffic(variant):
+    """Measured HBM bytes per step-kernel launch, or None when the counters
+    are not for this source or this tile shape."""
+    if STEP_SOURCE_SHA is None or variant not in STEP_COUNTERS_KIB or step_source_sha() != STEP_SOURCE_SHA:
+        return None
+    fetch, write = STEP_COUNTERS_KIB[variant]
+    return (fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024.0
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of `mib` MiB (the HIP runtime's copy
+    kernel behind a same-type tensor copy), five launches: the reference for
+    the HBM byte counters."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4}), flush=True)
 
 
 def cpu_baseline(w, dt, smax, FS_host, nsteps):
@@ -172,6 +223,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the solver has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.workload == "batch":
         print(json.dumps(run_batch(args)), flush=True)
         return
@@ -197,8 +251,13 @@ def main():
         kvs.kvs_set_envelope(ctx, env)
         kvs.kvs_set_probes(ctx, w.probes, w.comp)
         F_dev = torch.from_numpy(np.ascontiguousarray(w.F)).to("cuda")
-        variant, variant_ms = kvs.kvs_autotune_step(ctx, 20)
-        log(f"bench: step-kernel variant {variant} ({', '.join(f'{m * 1e3:.1f}' for m in variant_ms)} us)")
+        if args.step_variant >= 0:
+            variant = args.step_variant
+            kvs.kvs_set_step_variant(ctx, variant)
+            log(f"bench: step-kernel variant {variant} (pinned)")
+        else:
+            variant, variant_ms = kvs.kvs_autotune_step(ctx, 20)
+            log(f"bench: step-kernel variant {variant} ({', '.join(f'{m * 1e3:.1f}' for m in variant_ms)} us)")
         torch.cuda.synchronize()
         nsteps = w.nsteps
         cells = w.interior_cells
@@ -239,6 +298,7 @@ def main():
     # algorithmic bytes of the step kernel over the timed launches
     bytes_total = args.steps * (nsteps * cells * 60 + n_push * cells * 12)
     achieved = bytes_total / (k_ms * 1e-3) / 1e9
+    traffic = step_traffic(variant)
     res = {
         "metric": METRIC,
         "value": value,
@@ -266,7 +326,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_over_algorithmic": traffic / (cells * 60) if traffic else None,
             "kernel": "step_kernel (FDTD step)",
             "algorithmic_bytes_per_cell_update": "60 (+12 on push steps)",
             "kernel_ms_avg": k_ms / max(k_launches, 1),
