@@ -7,9 +7,9 @@ GPU's FP32 accumulation order.
 
 Network (linear, no biases): e0 = conv(r; 1->C0); e1 = conv(pool(e0));
 bottleneck convs at 1/4 resolution (dilations 1, 2, 4, ..., then 1);
-g1 = conv(e1 + up(b)); g0 = conv(e0 + up(g1)); z = conv(g0; C0->1) on the
-interior.  conv = 3x3x3 cross-correlation with zero padding; pool = mean of
-the existing children; up = nearest neighbour.  Arrays are channels-last
+g1 = conv(e1 + up(b)); z = conv(e0 + up(g1); C0->1) on the interior.
+conv = 3x3x3 cross-correlation with zero padding; pool = mean of the
+existing children; up = nearest neighbour.  Arrays are channels-last
 [z][y][x][C].
 """
 from __future__ import annotations
@@ -94,7 +94,7 @@ def layer_shapes(c0=16, c1=32, c2=64, nbott=4):
     for _ in range(nbott - 2):
         L.append((c2, c2, dil))
         dil *= 2
-    L += [(c2, c1, 1), (c1, c0, 1), (c0, c0, 1), (c0, 1, 1)]
+    L += [(c2, c1, 1), (c1, c0, 1), (c0, 1, 1)]
     return L
 
 
@@ -131,13 +131,12 @@ def forward(r, in_scale, out_scale, flat_w, c0=16, c1=32, c2=64, nbott=4, exact=
     i1 = rnd(np.float32(e1) + np.float32(up(b, e1.shape[:3])) if not exact else e1 + up(b, e1.shape[:3]))
     g1 = rnd(conv3(i1, Ws[2 + nbott]))
     i0 = rnd(np.float32(e0) + np.float32(up(g1, e0.shape[:3])) if not exact else e0 + up(g1, e0.shape[:3]))
-    g0 = rnd(conv3(i0, Ws[3 + nbott]))
-    z = out_scale * conv3(g0, Ws[4 + nbott])[..., 0]
+    z = out_scale * conv3(i0, Ws[3 + nbott])[..., 0]
     m = np.zeros_like(z)
     m[1:-1, 1:-1, 1:-1] = 1.0
     z = z * m
     if keep:
-        return z, dict(x=x, e0=e0, p0=p0, e1=e1, bins=bins, i1=i1, g1=g1, i0=i0, g0=g0, Ws=Ws, shapes=shapes)
+        return z, dict(x=x, e0=e0, p0=p0, e1=e1, bins=bins, i1=i1, g1=g1, i0=i0, Ws=Ws, shapes=shapes)
     return z
 
 
@@ -190,11 +189,9 @@ def backward(r, in_scale, flat_w, dz, dz_scale, c0=16, c1=32, c2=64, nbott=4, ex
     Ws, shapes = A["Ws"], A["shapes"]
     grads = [None] * len(shapes)
     dzf = f32(dz_scale * np.asarray(dz, dtype=np.float64))[..., None]
-    lo, ld0, ld1 = len(shapes) - 1, len(shapes) - 2, len(shapes) - 3
-    grads[lo] = conv3_weight_grad(A["g0"], dzf)
-    dg0 = conv3_adjoint(dzf, Ws[lo])
-    grads[ld0] = conv3_weight_grad(A["i0"], dg0)
-    de0 = conv3_adjoint(rnd(dg0), Ws[ld0])
+    lo, ld1 = len(shapes) - 1, len(shapes) - 2
+    grads[lo] = conv3_weight_grad(A["i0"], dzf)
+    de0 = conv3_adjoint(dzf, Ws[lo])
     dg1 = up_adjoint(de0, A["g1"].shape[:3])
     grads[ld1] = conv3_weight_grad(A["i1"], dg1)
     de1 = conv3_adjoint(rnd(dg1), Ws[ld1])

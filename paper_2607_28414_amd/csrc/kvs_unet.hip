@@ -33,11 +33,13 @@
 #include <vector>
 
 #include "kvs_internal.hpp"
+#include "kvs_tiling.hpp"
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short short4v __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -52,11 +54,26 @@ __device__ __forceinline__ int tap_dx(int tap) { return tap % 3 - 1; }
 __device__ __forceinline__ int tap_dy(int tap) { return (tap / 3) % 3 - 1; }
 __device__ __forceinline__ int tap_dz(int tap) { return tap / 9 - 1; }
 
-// ---- forward conv (MFMA) -----------------------------------------------------
+// ---- forward kernels (MFMA) --------------------------------------------------
+
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// 16x16x16 BF16 MFMA (K = 16: four k per lane)
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4v, a), __builtin_bit_cast(short4v, b), c,
+                                                     0, 0, 0);
+}
+
+// Convolution at the coarse levels:
 // out[v][co] = sum_{tap, ci} W[co][tap * CI + ci] * in(v + dil * tap)[ci],
-// in(p) = A[p][ci] + (B ? B[p / 2][ci] : 0), zero outside the grid.
-// out may be BF16 (store) — every output is rounded once, to nearest even.
-template <int CI, int CO, typename OUT>
+// in(p) = bf16(A[p][ci] + B[p / 2][ci]) with SKIP, else A[p][ci]; zero
+// outside the grid.
+// Each wavefront computes NV groups of 16 consecutive voxels for all CO
+// channels, so every weight fragment it loads feeds NV MFMAs.  Outputs are
+// rounded once (BF16) or stored as FP32.
+template <int CI, int CO, int NV, bool SKIP, typename OUT>
 __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, const bf16* __restrict__ B, Dims d,
                                                   int dil, const bf16* __restrict__ W, OUT* __restrict__ out,
                                                   const int* stop) {
@@ -66,58 +83,87 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, co
     constexpr int KP = (K + 31) / 32 * 32;
     constexpr int MT = CO / 16;
     const int lane = threadIdx.x & 63;
-    const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int vl = lane & 15, kg = lane >> 4;
+    const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
+    const long long v0 = ((long long)blk * 4 + (threadIdx.x >> 6)) * (16 * NV);
     const long long N = d.n();
-    const long long v = wave * 16 + vl;
-    const bool valid = v < N;
-    const long long vc = valid ? v : 0;
-    const int x = (int)(vc % d.nx), y = (int)((vc / d.nx) % d.ny), z = (int)(vc / ((long long)d.nx * d.ny));
+    if (v0 >= N) return;
+    const int vl = lane & 15, kg = lane >> 4;
     const Dims dB = coarse(d);
-    f32x4 acc[MT];
+    int gx[NV], gy[NV], gz[NV];
+    bool valid[NV];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < NV; ++g) {  // voxel counts stay below 2^31
+        const long long v = v0 + 16 * g + vl;
+        valid[g] = v < N;
+        const unsigned vc = valid[g] ? (unsigned)v : 0u, row = vc / (unsigned)d.nx;
+        gx[g] = (int)(vc - row * (unsigned)d.nx);
+        gy[g] = (int)(row % (unsigned)d.ny);
+        gz[g] = (int)(row / (unsigned)d.ny);
+    }
+    f32x4 acc[NV][MT];
+#pragma unroll
+    for (int g = 0; g < NV; ++g)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int kc = 0; kc < KP / 32; ++kc) {
         const int k0 = kc * 32 + 8 * kg;
         const int tap = k0 / CI, ci0 = k0 % CI;
-        bf16x8 xb;
-        float xf[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (tap < 27 && valid) {
-            const int px = x + dil * tap_dx(tap), py = y + dil * tap_dy(tap), pz = z + dil * tap_dz(tap);
-            if (px >= 0 && px < d.nx && py >= 0 && py < d.ny && pz >= 0 && pz < d.nz) {
-                const long long p = px + (long long)d.nx * (py + (long long)d.ny * pz);
-                const bf16x8 a8 = *reinterpret_cast<const bf16x8*>(A + p * CI + ci0);
+        const bool tap_ok = tap < 27;
+        const int ox = dil * tap_dx(tap), oy = dil * tap_dy(tap), oz = dil * tap_dz(tap);
+        bf16x8 wf[MT];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) xf[j] = (float)a8[j];
-                if (B) {
-                    const long long q = (px >> 1) + (long long)dB.nx * ((py >> 1) + (long long)dB.ny * (pz >> 1));
-                    const bf16x8 b8 = *reinterpret_cast<const bf16x8*>(B + q * CI + ci0);
+        for (int m = 0; m < MT; ++m) wf[m] = *reinterpret_cast<const bf16x8*>(W + (long long)(16 * m + vl) * KP + k0);
+        // operands of all groups: unconditional loads from clamped addresses,
+        // masked after arrival (no branch around a load)
+        bf16x8 a8[NV], b8[NV];
+        bool ok[NV];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) xf[j] += (float)b8[j];
-                }
+        for (int g = 0; g < NV; ++g) {
+            const int px = gx[g] + ox, py = gy[g] + oy, pz = gz[g] + oz;
+            ok[g] = tap_ok && valid[g] && px >= 0 && px < d.nx && py >= 0 && py < d.ny && pz >= 0 && pz < d.nz;
+            const int cx = min(max(px, 0), d.nx - 1), cy = min(max(py, 0), d.ny - 1), cz = min(max(pz, 0), d.nz - 1);
+            const size_t p = (size_t)cx + (size_t)d.nx * (size_t)(cy + d.ny * cz);
+            a8[g] = *reinterpret_cast<const bf16x8*>(A + p * CI + ci0);
+            if constexpr (SKIP) {
+                const size_t q = (size_t)(cx >> 1) + (size_t)dB.nx * (size_t)((cy >> 1) + dB.ny * (cz >> 1));
+                b8[g] = *reinterpret_cast<const bf16x8*>(B + q * CI + ci0);
             }
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xb[j] = (bf16)xf[j];
+        for (int g = 0; g < NV; ++g) {
+            bf16x8 xb;
+            if constexpr (SKIP) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(W + (long long)(16 * m + vl) * KP + k0);
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, xb, acc[m], 0, 0, 0);
+                for (int j = 0; j < 8; ++j) xb[j] = ok[g] ? (bf16)((float)a8[g][j] + (float)b8[g][j]) : (bf16)0.f;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) xb[j] = ok[g] ? a8[g][j] : (bf16)0.f;
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], xb, acc[g][m]);
         }
     }
-    if (!valid) return;
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        if constexpr (sizeof(OUT) == 2) {
-            bf16x4 o;
+    for (int g = 0; g < NV; ++g) {
+        if (!valid[g]) continue;
+        const long long v = v0 + 16 * g + vl;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[m][i];
-            *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
-        } else {
-            *reinterpret_cast<f32x4*>(out + v * CO + 16 * m + 4 * kg) = acc[m];
+        for (int m = 0; m < MT; ++m) {
+            if constexpr (sizeof(OUT) == 2) {
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[g][m][i];
+                *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
+            } else {
+                *reinterpret_cast<f32x4*>(out + v * CO + 16 * m + 4 * kg) = acc[g][m];
+            }
         }
     }
 }
+
+// voxel groups per wavefront: fewer for wide inputs or outputs (register budget)
+constexpr int conv_nv(int ci, int co) { return (co >= 64 || ci >= 32) ? 4 : 8; }
 
 // Scales of the network input and output: device values (the flexible PCG
 // computes them from the residual norm without a host round trip) or host
@@ -129,73 +175,294 @@ struct NetCtl {
     double in_v, out_v;
 };
 
-// first layer: one input channel read from an FP64 field, scaled
-template <int CO>
-__global__ __launch_bounds__(256) void conv3_first(const double* __restrict__ r, NetCtl ctl, Dims d,
-                                                   const bf16* __restrict__ W, bf16* __restrict__ out) {
-    constexpr int MT = CO / 16;
+// Level 0 of the encoder, fused: e0 = bf16(conv(x; 1 -> 16)) on the fine
+// grid, x = bf16(in_scale r), and p0 = bf16(mean of the existing children
+// of e0); e0 itself is not stored.  A block owns FP_CX x FP_CY coarse voxels
+// of each coarse plane and marches up a segment of coarse planes.  The fine
+// planes of x it needs (two new ones per coarse plane, halo 1 in x and y)
+// are staged in an LDS ring of six planes, loaded one coarse plane ahead, so
+// one barrier per coarse plane suffices.  Wavefront w owns coarse row Y0 + w
+// and four groups of 16 fine x; per group four MFMAs (fine rows y = 2Y + gy,
+// z = 2Z + gz) are summed in registers, then the x pairs by a lane exchange.
+constexpr int FP_CX = 32, FP_CY = 4;
+constexpr int FP_RX = 2 * FP_CX + 2, FP_RY = 2 * FP_CY + 2, FP_RN = FP_RX * FP_RY, FP_SLOTS = 6;
+
+__global__ __launch_bounds__(256) void first_pool_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
+                                                         int nty, int zchunk, const bf16* __restrict__ W,
+                                                         bf16* __restrict__ p0) {
+    __shared__ float rs[FP_SLOTS * FP_RN + 1];  // the last element is a constant 0
     if (ctl.stop && *ctl.stop) return;
     const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
-    const int lane = threadIdx.x & 63;
-    const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int vl = lane & 15, kg = lane >> 4;
-    const long long N = d.n();
-    const long long v = wave * 16 + vl;
-    const bool valid = v < N;
-    const long long vc = valid ? v : 0;
-    const int x = (int)(vc % d.nx), y = (int)((vc / d.nx) % d.ny), z = (int)(vc / ((long long)d.nx * d.ny));
-    bf16x8 xb;
+    const Dims c = coarse(d);
+    const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
+    const int tx = blk % ntx, t2 = blk / ntx;
+    const int ty = t2 % nty, tz = t2 / nty;
+    const int X0 = tx * FP_CX, Y0 = ty * FP_CY;
+    const int Zs = tz * zchunk, Ze = min(c.nz, Zs + zchunk);
+    const int fx0 = 2 * X0 - 1, fy0 = 2 * Y0 - 1;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, vl = lane & 15, kg = lane >> 4;
+    const int sxy = d.nx * d.ny;
+    const int pbase = 2 * Zs - 1;  // ring slot of fine plane p: (p - pbase) % FP_SLOTS
+    constexpr int ZERO = FP_SLOTS * FP_RN;
+    if (t == 0) rs[ZERO] = 0.f;
+    // per-lane taps 8 kg .. 8 kg + 7: in-plane offset and z offset
+    int toff[8], tdz[8];
+    bool tok[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int tap = 8 * kg + j;
-        float val = 0.f;
-        if (tap < 27 && valid) {
-            const int px = x + tap_dx(tap), py = y + tap_dy(tap), pz = z + tap_dz(tap);
-            if (px >= 0 && px < d.nx && py >= 0 && py < d.ny && pz >= 0 && pz < d.nz)
-                val = (float)(in_scale * r[px + (long long)d.nx * (py + (long long)d.ny * pz)]);
+        tok[j] = tap < 27;
+        toff[j] = tok[j] ? tap_dy(tap) * FP_RX + tap_dx(tap) : 0;
+        tdz[j] = tok[j] ? tap_dz(tap) : 0;
+    }
+    const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(W + vl * 32 + 8 * kg);
+    // Loads are unconditional from clamped (in-bounds) addresses and masked
+    // when stored to LDS, so that a prefetch stays in flight until then.
+    auto fload = [&](int p, int h, double& v, bool& m) {
+        const int idx = min(t + 256 * h, FP_RN - 1);
+        const int gx = fx0 + idx % FP_RX, gy = fy0 + idx / FP_RX;
+        m = t + 256 * h < FP_RN && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
+        const int pc = min(max(p, 0), d.nz - 1), yc = min(max(gy, 0), d.ny - 1), xc = min(max(gx, 0), d.nx - 1);
+        v = r[(size_t)pc * sxy + (size_t)(yc * d.nx + xc)];
+    };
+    auto fstore = [&](int p, const double* v, const bool* m) {
+        float* sl = rs + ((p - pbase) % FP_SLOTS) * FP_RN;
+        float f[3];
+#pragma unroll
+        for (int h = 0; h < 3; ++h) f[h] = m[h] ? (float)(bf16)(float)(in_scale * v[h]) : 0.f;
+        sl[t] = f[0];
+        sl[t + 256] = f[1];
+        if (t + 512 < FP_RN) sl[t + 512] = f[2];
+    };
+    double va[3], vb[3];
+    bool ma[3], mb[3];
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        fload(pbase, h, va[h], ma[h]);
+        fload(pbase + 1, h, vb[h], mb[h]);
+    }
+    fstore(pbase, va, ma);
+    fstore(pbase + 1, vb, mb);
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        fload(2 * Zs + 1, h, va[h], ma[h]);
+        fload(2 * Zs + 2, h, vb[h], mb[h]);
+    }
+    const int Y = Y0 + w;
+    for (int Z = Zs; Z < Ze; ++Z) {
+        fstore(2 * Z + 1, va, ma);
+        fstore(2 * Z + 2, vb, mb);
+        if (Z + 1 < Ze) {
+#pragma unroll
+            for (int h = 0; h < 3; ++h) {
+                fload(2 * Z + 3, h, va[h], ma[h]);
+                fload(2 * Z + 4, h, vb[h], mb[h]);
+            }
         }
-        xb[j] = (bf16)val;
-    }
-    f32x4 acc[MT];
+        kvs_tiling::lds_barrier();
+        // LDS address of each tap for gz = 0, 1 (row and x added per group)
+        int sb[4];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(W + (16 * m + vl) * 32 + 8 * kg);
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w8, xb, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    }
-    if (!valid) return;
+        for (int q = 0; q < 4; ++q) sb[q] = ((2 * Z - 1 + q - pbase) % FP_SLOTS) * FP_RN;
+        int ab[2][8];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        bf16x4 o;
+        for (int gz = 0; gz < 2; ++gz)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[m][i];
-        *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
+            for (int j = 0; j < 8; ++j) {
+                const int sl = tdz[j] < 0 ? sb[gz] : (tdz[j] == 0 ? sb[gz + 1] : sb[gz + 2]);
+                ab[gz][j] = sl + toff[j];
+            }
+#pragma unroll
+        for (int xg = 0; xg < 4; ++xg) {
+            const int fx = 2 * X0 + 16 * xg + vl;
+            float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int gz = 0; gz < 2; ++gz)
+#pragma unroll
+                for (int gy = 0; gy < 2; ++gy) {
+                    const int rowbase = (2 * w + gy + 1) * FP_RX + 16 * xg + vl + 1;
+                    bf16x8 xb;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[tok[j] ? ab[gz][j] + rowbase : ZERO];
+                    const f32x4 e = mfma32(w8, xb, f32x4{0.f, 0.f, 0.f, 0.f});
+                    const bool valid = fx < d.nx && 2 * Y + gy < d.ny && 2 * Z + gz < d.nz;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) s[i] += valid ? (float)(bf16)e[i] : 0.f;
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s[i] += __shfl_xor(s[i], 1);
+            const int X = X0 + 8 * xg + (vl >> 1);
+            if ((vl & 1) == 0 && X < c.nx && Y < c.ny) {
+                const int cnt =
+                    (min(2 * X + 2, d.nx) - 2 * X) * (min(2 * Y + 2, d.ny) - 2 * Y) * (min(2 * Z + 2, d.nz) - 2 * Z);
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = (bf16)(s[i] / (float)cnt);
+                *reinterpret_cast<bf16x4*>(p0 + ((size_t)(Z * c.ny + Y) * c.nx + X) * 16 + 4 * kg) = o;
+            }
+        }
     }
 }
 
-// output layer: one channel, FP64 result scaled, 0 outside the interior
-template <int CI>
-__global__ __launch_bounds__(256) void conv3_out(const bf16* __restrict__ g, Dims d, const float* __restrict__ W,
-                                                 NetCtl ctl, double* __restrict__ z) {
+// Output of the network, fused with a recomputation of e0:
+//   i0(v) = bf16(e0(v) + g1(v / 2))            (0 outside the grid)
+//   y(v)[tap] = sum_c Wo[tap][c] i0(v)[c]      (MFMA 16x16x16, FP32)
+//   z(v) = out_scale * sum_tap y(v + tap)[tap] on the interior, 0 on the outer layer.
+// A block owns an OT_X x OT_Y column of output voxels and marches up a z
+// segment.  Per plane q it stages x = bf16(in_scale r) of plane q + 1 in an
+// LDS ring (3 planes, halo 2), computes i0 and y on the haloed OT_X+2 x
+// OT_Y+2 plane (16 groups of 16 voxels, 4 per wavefront) into LDS, and every
+// output thread adds the 9 in-plane taps of y(q) to its rolling sums for the
+// output planes q - 1, q, q + 1; plane q - 1 is then complete and stored.
+// x and g1 are loaded one plane ahead.  With keep != null, i0 of the
+// block's own voxels is stored (training).
+constexpr int OT_X = 30, OT_Y = 6, HT_X = 32, HT_Y = 8, RT_X = 34, RT_Y = 10, YS = 28;
+
+__global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx, int nty,
+                                                  int zchunk, const bf16* __restrict__ W0, const bf16* __restrict__ WoT,
+                                                  const bf16* __restrict__ g1, double* __restrict__ z,
+                                                  bf16* __restrict__ keep) {
+    constexpr int RN = RT_X * RT_Y;
+    __shared__ float rs[3 * RN + 1];  // the last element is a constant 0
+    __shared__ float ys[HT_Y * HT_X][YS];
     if (ctl.stop && *ctl.stop) return;
+    const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
     const double out_scale = ctl.out_dev ? *ctl.out_dev : ctl.out_v;
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= d.n()) return;
-    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), zz = (int)(v / ((long long)d.nx * d.ny));
-    if (x < 1 || x > d.nx - 2 || y < 1 || y > d.ny - 2 || zz < 1 || zz > d.nz - 2) {
-        z[v] = 0.0;
-        return;
+    const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
+    const int tx = blk % ntx, t2 = blk / ntx;
+    const int ty = t2 % nty, tz = t2 / nty;
+    const int ox0 = tx * OT_X, oy0 = ty * OT_Y;
+    const int zs = tz * zchunk, ze = min(d.nz, zs + zchunk);
+    const int hx0 = ox0 - 1, hy0 = oy0 - 1, rx0 = ox0 - 2, ry0 = oy0 - 2;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, vl = lane & 15, kg = lane >> 4;
+    const int sxy = d.nx * d.ny;
+    const Dims c = coarse(d);
+    const int base = zs - 2;  // ring slot of plane p: (p - base) % 3, p >= base
+    constexpr int ZERO = 3 * RN;
+    if (t == 0) rs[ZERO] = 0.f;
+    const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(W0 + vl * 32 + 8 * kg);
+    const bf16x4 wo0 = *reinterpret_cast<const bf16x4*>(WoT + vl * 16 + 4 * kg);
+    const bf16x4 wo1 = *reinterpret_cast<const bf16x4*>(WoT + (16 + vl) * 16 + 4 * kg);
+    int toff[8], tdz[8];
+    bool tok[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int tap = 8 * kg + j;
+        tok[j] = tap < 27;
+        toff[j] = tok[j] ? tap_dy(tap) * RT_X + tap_dx(tap) : 0;
+        tdz[j] = tok[j] ? tap_dz(tap) : 0;
     }
-    float acc = 0.f;
-    for (int tap = 0; tap < 27; ++tap) {
-        const long long p = (x + tap_dx(tap)) + (long long)d.nx * ((y + tap_dy(tap)) + (long long)d.ny * (zz + tap_dz(tap)));
+    // Loads are unconditional from clamped (in-bounds) addresses and masked
+    // at their use, so that a prefetch stays in flight until then.
+    auto rload = [&](int p, int h, double& v, bool& m) {
+        const int idx = min(t + 256 * h, RN - 1);
+        const int gx = rx0 + idx % RT_X, gy = ry0 + idx / RT_X;
+        m = t + 256 * h < RN && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
+        const int pc = min(max(p, 0), d.nz - 1), yc = min(max(gy, 0), d.ny - 1), xc = min(max(gx, 0), d.nx - 1);
+        v = r[(size_t)pc * sxy + (size_t)(yc * d.nx + xc)];
+    };
+    auto rstore = [&](int p, const double* v, const bool* m) {
+        float* slot = rs + ((p - base) % 3) * RN;
+        const float a = m[0] ? (float)(bf16)(float)(in_scale * v[0]) : 0.f;
+        const float b = m[1] ? (float)(bf16)(float)(in_scale * v[1]) : 0.f;
+        slot[t] = a;
+        if (t + 256 < RN) slot[t + 256] = b;
+    };
+    // g1 of the wavefront's 4 groups on plane q (validity applied at use)
+    auto gload = [&](int q, bf16x4* gv) {
+        const int qc = min(max(q, 0), d.nz - 1);
 #pragma unroll
-        for (int c8 = 0; c8 < CI; c8 += 8) {
-            const bf16x8 a8 = *reinterpret_cast<const bf16x8*>(g + p * CI + c8);
+        for (int gi = 0; gi < 4; ++gi) {
+            const int hy = 2 * w + (gi >> 1), hx = 16 * (gi & 1) + vl;
+            const int gx = min(max(hx0 + hx, 0), d.nx - 1), gy = min(max(hy0 + hy, 0), d.ny - 1);
+            const size_t pi = ((size_t)((qc >> 1) * c.ny + (gy >> 1)) * c.nx + (gx >> 1)) * 16 + 4 * kg;
+            gv[gi] = *reinterpret_cast<const bf16x4*>(g1 + pi);
+        }
+    };
+    double rv[2];
+    bool rm[2];
+    rload(zs - 2, 0, rv[0], rm[0]);
+    rload(zs - 2, 1, rv[1], rm[1]);
+    rstore(zs - 2, rv, rm);
+    rload(zs - 1, 0, rv[0], rm[0]);
+    rload(zs - 1, 1, rv[1], rm[1]);
+    rstore(zs - 1, rv, rm);
+    rload(zs, 0, rv[0], rm[0]);
+    rload(zs, 1, rv[1], rm[1]);
+    bf16x4 gcur[4];
+    gload(zs - 1, gcur);
+
+    const bool has_out = t < OT_X * OT_Y;
+    const int oxl = t % OT_X, oyl = t / OT_X;
+    const int gxo = ox0 + oxl, gyo = oy0 + oyl;
+    const bool out_in = has_out && gxo < d.nx && gyo < d.ny;
+    const bool inner_xy = gxo >= 1 && gxo <= d.nx - 2 && gyo >= 1 && gyo <= d.ny - 2;
+    const int ybase = (oyl + 1) * HT_X + oxl + 1;
+    float a_prev = 0.f, a_cur = 0.f, a_next = 0.f;
+    for (int q = zs - 1; q <= ze; ++q) {
+        rstore(q + 1, rv, rm);
+        if (q + 2 <= ze + 1) {
+            rload(q + 2, 0, rv[0], rm[0]);
+            rload(q + 2, 1, rv[1], rm[1]);
+        }
+        bf16x4 gnext[4];
+        gload(q + 1, gnext);
+        kvs_tiling::lds_barrier();
+        const int s0 = ((q - 1 - base) % 3) * RN, s1 = ((q - base) % 3) * RN, s2 = ((q + 1 - base) % 3) * RN;
+        int ab[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) acc += W[tap * CI + c8 + j] * (float)a8[j];
+        for (int j = 0; j < 8; ++j) ab[j] = (tdz[j] < 0 ? s0 : (tdz[j] == 0 ? s1 : s2)) + toff[j];
+        const bool qin = q >= 0 && q < d.nz;
+#pragma unroll
+        for (int gi = 0; gi < 4; ++gi) {
+            const int hy = 2 * w + (gi >> 1), hx = 16 * (gi & 1) + vl;
+            const int gx = hx0 + hx, gy = hy0 + hy;
+            const bool valid = qin && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
+            const int rowbase = (hy + 1) * RT_X + hx + 1;
+            bf16x8 xb;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[tok[j] ? ab[j] + rowbase : ZERO];
+            const f32x4 e = mfma32(w0, xb, f32x4{0.f, 0.f, 0.f, 0.f});
+            bf16x4 iv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) iv[i] = valid ? (bf16)((float)(bf16)e[i] + (float)gcur[gi][i]) : (bf16)0.f;
+            if (keep && valid && hx >= 1 && hx <= OT_X && hy >= 1 && hy <= OT_Y && q >= zs && q < ze)
+                *reinterpret_cast<bf16x4*>(keep + ((size_t)q * sxy + (size_t)(gy * d.nx + gx)) * 16 + 4 * kg) = iv;
+            const f32x4 y0 = mfma16(wo0, iv, f32x4{0.f, 0.f, 0.f, 0.f});
+            const f32x4 y1 = mfma16(wo1, iv, f32x4{0.f, 0.f, 0.f, 0.f});
+            float* yr = ys[hy * HT_X + hx];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) yr[4 * kg + i] = y0[i];
+            if (kg < 2)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) yr[16 + 4 * kg + i] = y1[i];
+            else if (kg == 2)
+                yr[24] = y1[0], yr[25] = y1[1], yr[26] = y1[2];
+        }
+#pragma unroll
+        for (int gi = 0; gi < 4; ++gi) gcur[gi] = gnext[gi];
+        kvs_tiling::lds_barrier();
+        if (has_out) {
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const float* yy = ys[ybase + dy * HT_X + dx];
+                    const int tin = 3 * (dy + 1) + (dx + 1);
+                    a_next += yy[tin];
+                    a_cur += yy[9 + tin];
+                    a_prev += yy[18 + tin];
+                }
+            const int o = q - 1;
+            if (o >= zs && o < ze && out_in) {
+                const bool inner = inner_xy && o >= 1 && o <= d.nz - 2;
+                z[(size_t)o * sxy + (size_t)(gyo * d.nx + gxo)] = inner ? out_scale * (double)a_prev : 0.0;
+            }
+            a_prev = a_cur;
+            a_cur = a_next;
+            a_next = 0.f;
         }
     }
-    z[v] = out_scale * (double)acc;
 }
 
 // mean of the children of coarse voxel V (8 channels per thread)
@@ -226,17 +493,21 @@ __global__ void pool2(const bf16* __restrict__ fine, Dims d, bf16* __restrict__ 
     *reinterpret_cast<bf16x8*>(out + V * C + c8) = o;
 }
 
-int blocks_for_waves(long long voxels) { return (int)((voxels + 63) / 64); }
-
 // dispatch of the MFMA conv over the channel pairs this network uses
 template <typename OUT>
 hipError_t launch_conv(int ci, int co, const bf16* A, const bf16* B, Dims d, int dil, const bf16* W, OUT* out,
                        hipStream_t s, const int* stop = nullptr) {
-    const int nb = blocks_for_waves(d.n());
-#define KVS_CONV_CASE(CI_, CO_)                                                                                  \
-    if (ci == CI_ && co == CO_) {                                                                                \
-        hipLaunchKernelGGL((conv3_mfma<CI_, CO_, OUT>), dim3(nb), dim3(256), 0, s, A, B, d, dil, W, out, stop); \
-        return hipGetLastError();                                                                                \
+#define KVS_CONV_CASE(CI_, CO_)                                                                                \
+    if (ci == CI_ && co == CO_) {                                                                              \
+        constexpr int NV = conv_nv(CI_, CO_);                                                                  \
+        const int nb = (int)((d.n() + 64 * NV - 1) / (64 * NV));                                               \
+        if (B)                                                                                                 \
+            hipLaunchKernelGGL((conv3_mfma<CI_, CO_, NV, true, OUT>), dim3(nb), dim3(256), 0, s, A, B, d, dil, W, \
+                               out, stop);                                                                     \
+        else                                                                                                   \
+            hipLaunchKernelGGL((conv3_mfma<CI_, CO_, NV, false, OUT>), dim3(nb), dim3(256), 0, s, A, B, d, dil,   \
+                               W, out, stop);                                                                  \
+        return hipGetLastError();                                                                              \
     }
     KVS_CONV_CASE(16, 32)
     KVS_CONV_CASE(32, 64)
@@ -248,6 +519,31 @@ hipError_t launch_conv(int ci, int co, const bf16* A, const bf16* B, Dims d, int
     KVS_CONV_CASE(32, 32)
 #undef KVS_CONV_CASE
     return hipErrorInvalidValue;
+}
+
+struct OutLaunch {
+    int ntx, nty, zchunk, nblocks;
+};
+
+OutLaunch first_pool_launch(Dims d) {
+    const Dims c = coarse(d);
+    OutLaunch L;
+    L.ntx = (c.nx + FP_CX - 1) / FP_CX;
+    L.nty = (c.ny + FP_CY - 1) / FP_CY;
+    static const int cap = kvs_tiling::resident_blocks(first_pool_kernel, 256);
+    L.zchunk = kvs_tiling::choose_kchunk(L.ntx * L.nty, c.nz, cap);
+    L.nblocks = L.ntx * L.nty * ((c.nz + L.zchunk - 1) / L.zchunk);
+    return L;
+}
+
+OutLaunch out_launch(Dims d) {
+    OutLaunch L;
+    L.ntx = (d.nx + OT_X - 1) / OT_X;
+    L.nty = (d.ny + OT_Y - 1) / OT_Y;
+    static const int cap = kvs_tiling::resident_blocks(out_kernel, 256);
+    L.zchunk = kvs_tiling::choose_kchunk(L.ntx * L.nty, d.nz, cap);
+    L.nblocks = L.ntx * L.nty * ((d.nz + L.zchunk - 1) / L.zchunk);
+    return L;
 }
 
 }  // namespace
@@ -508,21 +804,26 @@ struct kvs_unet {
     int64_t n_w = 0, n_wt = 0, n_master = 0;
     bf16* w = nullptr;       // device bf16 forward weights
     bf16* wt = nullptr;      // device bf16 transposed weights (for the backward pass)
-    float* w_out = nullptr;  // device fp32 (bf16-rounded) output weights [27][C0]
+    float* w_out = nullptr;  // device fp32 (bf16-rounded) output weights [27][C0] (backward pass)
+    bf16* w_outT = nullptr;  // device bf16 output weights [32 taps][C0], taps >= 27 zero (forward MFMA)
     float* master = nullptr; // device fp32 master weights (flat)
     float* grad = nullptr;   // device fp32 gradient (flat, same layout)
     float* adam_m = nullptr;
     float* adam_v = nullptr;
     int64_t adam_t = 0;
     std::vector<float> host_master;
-    // activations of the last grid: e0, p0, e1, p1, bottleneck outputs (kept
-    // for the backward pass), g1, g0
+    // activations of the last grid: p0, e1, p1, bottleneck outputs, g1 (kept
+    // for the backward pass); i0 at full resolution only when a forward pass
+    // is asked to keep it (training)
     Dims dims{0, 0, 0};
-    bf16 *e0 = nullptr, *p0 = nullptr, *e1 = nullptr, *p1 = nullptr, *g1 = nullptr, *g0 = nullptr;
+    bf16 *p0 = nullptr, *e1 = nullptr, *p1 = nullptr, *g1 = nullptr;
     std::vector<bf16*> bott;
+    bf16* i0 = nullptr;
+    Dims i0_dims{0, 0, 0};
+    bool kept = false;  // the last forward pass stored i0 for this grid
     // training buffers (allocated on first use)
     Dims tdims{0, 0, 0};
-    float *dg0 = nullptr, *de0 = nullptr, *dp0 = nullptr, *dg1 = nullptr, *de1 = nullptr, *dp1 = nullptr;
+    float *de0 = nullptr, *dp0 = nullptr, *dg1 = nullptr, *de1 = nullptr, *dp1 = nullptr;
     std::vector<float*> dbott;  // gradient of each bottleneck output, and of its input p1 (last)
     bf16* gb = nullptr;         // bf16 staging of a gradient (conv^T input)
     float* dzf = nullptr;
@@ -542,14 +843,16 @@ void ufree(P*& p) {
 }
 
 void unet_free_acts(kvs_unet* u) {
-    for (bf16** p : {&u->e0, &u->p0, &u->e1, &u->p1, &u->g1, &u->g0}) ufree(*p);
+    for (bf16** p : {&u->p0, &u->e1, &u->p1, &u->g1, &u->i0}) ufree(*p);
     for (bf16*& p : u->bott) ufree(p);
     u->bott.clear();
     u->dims = Dims{0, 0, 0};
+    u->i0_dims = Dims{0, 0, 0};
+    u->kept = false;
 }
 
 void unet_free_train(kvs_unet* u) {
-    for (float** p : {&u->dg0, &u->de0, &u->dp0, &u->dg1, &u->de1, &u->dp1, &u->dzf}) ufree(*p);
+    for (float** p : {&u->de0, &u->dp0, &u->dg1, &u->de1, &u->dp1, &u->dzf}) ufree(*p);
     for (float*& p : u->dbott) ufree(p);
     u->dbott.clear();
     ufree(u->gb);
@@ -561,13 +864,11 @@ void unet_free_train(kvs_unet* u) {
 }
 
 hipError_t unet_ensure_acts(kvs_unet* u, Dims d) {
-    if (u->e0 && u->dims.nx == d.nx && u->dims.ny == d.ny && u->dims.nz == d.nz) return hipSuccess;
+    if (u->p0 && u->dims.nx == d.nx && u->dims.ny == d.ny && u->dims.nz == d.nz) return hipSuccess;
     unet_free_acts(u);
     const Dims d1 = coarse(d), d2 = coarse(d1);
-    const long long n0 = d.n(), n1 = d1.n(), n2 = d2.n();
-    hipError_t e = hipMalloc(&u->e0, sizeof(bf16) * n0 * u->c0);
-    if (e == hipSuccess) e = hipMalloc(&u->g0, sizeof(bf16) * n0 * u->c0);
-    if (e == hipSuccess) e = hipMalloc(&u->p0, sizeof(bf16) * n1 * u->c0);
+    const long long n1 = d1.n(), n2 = d2.n();
+    hipError_t e = hipMalloc(&u->p0, sizeof(bf16) * n1 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->e1, sizeof(bf16) * n1 * u->c1);
     if (e == hipSuccess) e = hipMalloc(&u->g1, sizeof(bf16) * n1 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->p1, sizeof(bf16) * n2 * u->c1);
@@ -584,13 +885,22 @@ hipError_t unet_ensure_acts(kvs_unet* u, Dims d) {
     return hipSuccess;
 }
 
+// i0 at full resolution, for a forward pass that keeps it
+hipError_t unet_ensure_i0(kvs_unet* u, Dims d) {
+    if (u->i0 && u->i0_dims.nx == d.nx && u->i0_dims.ny == d.ny && u->i0_dims.nz == d.nz) return hipSuccess;
+    ufree(u->i0);
+    u->i0_dims = Dims{0, 0, 0};
+    hipError_t e = hipMalloc(&u->i0, sizeof(bf16) * d.n() * u->c0);
+    if (e == hipSuccess) u->i0_dims = d;
+    return e;
+}
+
 hipError_t unet_ensure_train(kvs_unet* u, Dims d) {
-    if (u->dg0 && u->tdims.nx == d.nx && u->tdims.ny == d.ny && u->tdims.nz == d.nz) return hipSuccess;
+    if (u->de0 && u->tdims.nx == d.nx && u->tdims.ny == d.ny && u->tdims.nz == d.nz) return hipSuccess;
     unet_free_train(u);
     const Dims d1 = coarse(d), d2 = coarse(d1);
     const long long n0 = d.n(), n1 = d1.n(), n2 = d2.n();
-    hipError_t e = hipMalloc(&u->dg0, sizeof(float) * n0 * u->c0);
-    if (e == hipSuccess) e = hipMalloc(&u->de0, sizeof(float) * n0 * u->c0);
+    hipError_t e = hipMalloc(&u->de0, sizeof(float) * n0 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->dp0, sizeof(float) * n1 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->dg1, sizeof(float) * n1 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->de1, sizeof(float) * n1 * u->c1);
@@ -600,7 +910,7 @@ hipError_t unet_ensure_train(kvs_unet* u, Dims d) {
         e = hipMalloc(&b, sizeof(float) * n2 * u->c2);
         u->dbott.push_back(b);
     }
-    if (e == hipSuccess) e = hipMalloc(&u->gb, sizeof(bf16) * n0 * std::max(u->c0, u->c2));
+    if (e == hipSuccess) e = hipMalloc(&u->gb, sizeof(bf16) * std::max(n1 * u->c1, n2 * u->c2));
     if (e == hipSuccess) e = hipMalloc(&u->dzf, sizeof(float) * n0);
     if (e == hipSuccess) e = hipMalloc(&u->dz_raw, sizeof(double) * n0);
     if (e == hipSuccess) e = hipMalloc(&u->part, sizeof(double) * 2 * nblocks256(n0));
@@ -623,8 +933,7 @@ void build_layers(kvs_unet* u) {
     for (int q = 0; q < u->nbott - 2; ++q, dil *= 2) u->layers.push_back({u->c2, u->c2, dil, 2, false});
     u->layers.push_back({u->c2, u->c1, 1, 2, false});  // bottleneck out
     u->layers.push_back({u->c1, u->c0, 1, 1, true});   // g1 = conv(e1 + up b)
-    u->layers.push_back({u->c0, u->c0, 1, 0, true});   // g0 = conv(e0 + up g1)
-    u->layers.push_back({u->c0, 1, 1, 0, false});      // z
+    u->layers.push_back({u->c0, 1, 1, 0, true});       // z = conv(e0 + up g1)
     u->w_off.clear();
     u->wt_off.clear();
     u->kp.clear();
@@ -652,34 +961,42 @@ void build_layers(kvs_unet* u) {
 
 }  // namespace
 
-// Network application: z = out_scale * U(in_scale * r) (scales from ctl).
-hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, double* z, Dims d, hipStream_t s) {
+// Network application: z = out_scale * U(in_scale * r) (scales from ctl);
+// keep: also store i0 at full resolution for a backward pass.
+hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, double* z, Dims d, hipStream_t s,
+                          bool keep = false) {
+    if (d.n() >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit voxel indices in the kernels
     hipError_t e = unet_ensure_acts(u, d);
+    if (e == hipSuccess && keep) e = unet_ensure_i0(u, d);
     if (e != hipSuccess) return e;
+    u->kept = false;
     const Dims d1 = coarse(d), d2 = coarse(d1);
     const std::vector<UnetLayerDesc>& L = u->layers;
     const int nl = (int)L.size();
     const int* stop = ctl.stop;
-    hipLaunchKernelGGL(conv3_first<16>, dim3(blocks_for_waves(d.n())), dim3(256), 0, s, r, ctl, d, u->w + u->w_off[0],
-                       u->e0);
+    const OutLaunch fl = first_pool_launch(d);
+    hipLaunchKernelGGL(first_pool_kernel, dim3(fl.nblocks), dim3(256), 0, s, r, ctl, d, fl.ntx, fl.nty, fl.zchunk,
+                       u->w + u->w_off[0], u->p0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_pool(u->c0, u->e0, d, u->p0, s, stop)) != hipSuccess) return e;
     if ((e = launch_conv(u->c0, u->c1, u->p0, (const bf16*)nullptr, d1, 1, u->w + u->w_off[1], u->e1, s, stop)) != hipSuccess)
         return e;
     if ((e = launch_pool(u->c1, u->e1, d1, u->p1, s, stop)) != hipSuccess) return e;
     const bf16* in = u->p1;
-    for (int l = 2; l <= nl - 4; ++l) {
+    for (int l = 2; l <= nl - 3; ++l) {
         bf16* out = u->bott[(size_t)(l - 2)];
         if ((e = launch_conv(L[l].ci, L[l].co, in, (const bf16*)nullptr, d2, L[l].dil, u->w + u->w_off[l], out, s,
                              stop)) != hipSuccess)
             return e;
         in = out;
     }
-    const int ld1 = nl - 3, ld0 = nl - 2;
+    const int ld1 = nl - 2;
     if ((e = launch_conv(u->c1, u->c0, u->e1, in, d1, 1, u->w + u->w_off[ld1], u->g1, s, stop)) != hipSuccess) return e;
-    if ((e = launch_conv(u->c0, u->c0, u->e0, u->g1, d, 1, u->w + u->w_off[ld0], u->g0, s, stop)) != hipSuccess) return e;
-    hipLaunchKernelGGL(conv3_out<16>, dim3(nblocks256(d.n())), dim3(256), 0, s, u->g0, d, u->w_out, ctl, z);
-    return hipGetLastError();
+    const OutLaunch ol = out_launch(d);
+    hipLaunchKernelGGL(out_kernel, dim3(ol.nblocks), dim3(256), 0, s, r, ctl, d, ol.ntx, ol.nty, ol.zchunk,
+                       u->w + u->w_off[0], u->w_outT, u->g1, z, keep ? u->i0 : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    u->kept = keep;
+    return hipSuccess;
 }
 
 hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const kvs_grid& g, const double* in_scale,
@@ -736,20 +1053,13 @@ hipError_t unet_backward(kvs_unet* u, const double* r, double in_scale, Dims d, 
     const Dims d1 = coarse(d), d2 = coarse(d1);
     const std::vector<UnetLayerDesc>& L = u->layers;
     const int nl = (int)L.size();
-    const int lo = nl - 1, ld0 = nl - 2, ld1 = nl - 3;
+    const int lo = nl - 1, ld1 = nl - 2;
     const int c0 = u->c0, c1 = u->c1;
-    // output layer
-    if ((e = launch_dw(u, c0, 1, false, u->g0, nullptr, nullptr, 0.0, d, 1, u->dzf, u->m_off[lo], accumulate, s)) !=
+    // output layer: z = conv(i0), i0 = e0 + up(g1)
+    if ((e = launch_dw(u, c0, 1, false, u->i0, nullptr, nullptr, 0.0, d, 1, u->dzf, u->m_off[lo], accumulate, s)) !=
         hipSuccess)
         return e;
-    hipLaunchKernelGGL(out_backward<16>, dim3(nblocks256(d.n())), dim3(256), 0, s, u->dzf, d, u->w_out, u->dg0);
-    // dec0: g0 = conv(e0 + up g1)
-    if ((e = launch_dw(u, c0, c0, false, u->e0, u->g1, nullptr, 0.0, d, 1, u->dg0, u->m_off[ld0], accumulate, s)) !=
-        hipSuccess)
-        return e;
-    if ((e = to_bf16(u->dg0, u->gb, d.n() * c0, s)) != hipSuccess) return e;
-    if ((e = launch_conv(c0, c0, u->gb, (const bf16*)nullptr, d, 1, u->wt + u->wt_off[ld0], u->de0, s)) != hipSuccess)
-        return e;
+    hipLaunchKernelGGL(out_backward<16>, dim3(nblocks256(d.n())), dim3(256), 0, s, u->dzf, d, u->w_out, u->de0);
     hipLaunchKernelGGL(up_adjoint, dim3(nblocks256(d1.n() * c0)), dim3(256), 0, s, u->de0, d, c0, u->dg1);
     // dec1: g1 = conv(e1 + up b_last)
     const bf16* b_last = u->bott[(size_t)(u->nbott - 1)];
@@ -762,7 +1072,7 @@ hipError_t unet_backward(kvs_unet* u, const double* r, double in_scale, Dims d, 
     float* dcur = u->dbott[(size_t)(u->nbott - 1)];  // gradient of the last bottleneck output (C1 channels)
     hipLaunchKernelGGL(up_adjoint, dim3(nblocks256(d2.n() * c1)), dim3(256), 0, s, u->de1, d1, c1, dcur);
     // bottleneck, last to first
-    for (int l = nl - 4; l >= 2; --l) {
+    for (int l = nl - 3; l >= 2; --l) {
         const int q = l - 2;
         const bf16* xin = q == 0 ? u->p1 : u->bott[(size_t)(q - 1)];
         float* dxin = q == 0 ? u->dp1 : u->dbott[(size_t)(q - 1)];
@@ -839,11 +1149,16 @@ kvs_status upload_weights(kvs_unet* u) {
                         (bf16)m[(int64_t)c * K + (26 - tp) * L.ci + ci];
     }
     std::vector<float> wo((size_t)27 * u->c0);
+    std::vector<bf16> woT((size_t)32 * u->c0, (bf16)0.f);  // [tap][c], taps 27..31 zero
     const float* mo = u->host_master.data() + u->m_off[(size_t)(nl - 1)];
-    for (size_t q = 0; q < wo.size(); ++q) wo[q] = (float)(bf16)mo[q];
+    for (size_t q = 0; q < wo.size(); ++q) {
+        wo[q] = (float)(bf16)mo[q];
+        woT[q] = (bf16)mo[q];
+    }
     if (hipMemcpy(u->w, wb.data(), sizeof(bf16) * wb.size(), hipMemcpyHostToDevice) != hipSuccess ||
         (u->n_wt > 0 && hipMemcpy(u->wt, wtb.data(), sizeof(bf16) * u->n_wt, hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemcpy(u->w_out, wo.data(), sizeof(float) * wo.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(u->w_outT, woT.data(), sizeof(bf16) * woT.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->master, u->host_master.data(), sizeof(float) * u->n_master, hipMemcpyHostToDevice) != hipSuccess)
         return ufail(u, KVS_EDEVICE, "weight upload failed");
     return KVS_OK;
@@ -871,6 +1186,7 @@ kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_un
     bool ok = hipMalloc(&u->w, sizeof(bf16) * u->n_w) == hipSuccess;
     ok = ok && hipMalloc(&u->wt, sizeof(bf16) * std::max<int64_t>(u->n_wt, 1)) == hipSuccess;
     ok = ok && hipMalloc(&u->w_out, sizeof(float) * 27 * c0) == hipSuccess;
+    ok = ok && hipMalloc(&u->w_outT, sizeof(bf16) * 32 * c0) == hipSuccess;
     for (float** p : {&u->master, &u->grad, &u->adam_m, &u->adam_v})
         ok = ok && hipMalloc(p, sizeof(float) * u->n_master) == hipSuccess;
     ok = ok && hipMemset(u->grad, 0, sizeof(float) * u->n_master) == hipSuccess;
@@ -897,6 +1213,7 @@ void kvs_unet_destroy(kvs_unet* u) {
     ufree(u->w);
     ufree(u->wt);
     ufree(u->w_out);
+    ufree(u->w_outT);
     ufree(u->master);
     ufree(u->grad);
     ufree(u->adam_m);
@@ -930,7 +1247,7 @@ kvs_status kvs_unet_forward(kvs_unet* u, const double* r, double in_scale, doubl
     if (!u || !r || !z) return KVS_EINVAL;
     if (nx < 3 || ny < 3 || nz < 3) return ufail(u, KVS_EINVAL, "grid needs >= 3 nodes per axis");
     NetCtl ctl{nullptr, nullptr, nullptr, in_scale, out_scale};
-    hipError_t e = kvs_unet_apply(u, r, ctl, z, dims_of(nx, ny, nz), (hipStream_t)stream);
+    hipError_t e = kvs_unet_apply(u, r, ctl, z, dims_of(nx, ny, nz), (hipStream_t)stream, true);
     if (e != hipSuccess) return ufail(u, KVS_EDEVICE, std::string("unet forward: ") + hipGetErrorString(e));
     return KVS_OK;
 }
@@ -939,7 +1256,7 @@ kvs_status kvs_unet_backward(kvs_unet* u, const double* r, double in_scale, cons
                              int64_t nx, int64_t ny, int64_t nz, int32_t accumulate, void* stream) {
     if (!u || !r || !dz) return KVS_EINVAL;
     const Dims d = dims_of(nx, ny, nz);
-    if (u->dims.nx != d.nx || u->dims.ny != d.ny || u->dims.nz != d.nz)
+    if (!u->kept || u->dims.nx != d.nx || u->dims.ny != d.ny || u->dims.nz != d.nz)
         return ufail(u, KVS_ESTATE, "backward needs a forward pass on the same grid first");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = unet_ensure_train(u, d);
@@ -969,7 +1286,7 @@ kvs_status kvs_unet_train_sample(kvs_unet* u, const double* b, const double* xs,
     hipError_t e = unet_ensure_train(u, d);
     double* z = nullptr;
     if (e == hipSuccess) e = hipMalloc(&z, sizeof(double) * d.n());
-    if (e == hipSuccess) e = kvs_unet_apply(u, b, ctl, z, d, s);
+    if (e == hipSuccess) e = kvs_unet_apply(u, b, ctl, z, d, s, true);
     const int nb = nblocks256(d.n());
     std::vector<double> part((size_t)2 * nb);
     if (e == hipSuccess) {
