@@ -162,6 +162,143 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, co
     }
 }
 
+// Convolution with dilation 1 as an LDS-staged z-march (same result as
+// conv3_mfma).  A block owns a 32 x TY column of output voxels and marches up
+// a z segment; the haloed input planes z - 1, z, z + 1 (34 x (TY + 2) voxels,
+// channel stride CI + 8 against bank conflicts) live in an LDS ring, the
+// plane after next is prefetched into registers.  With SKIP the input
+// bf16(A + B[p / 2]) is formed once per voxel when a plane is staged.  Each
+// wavefront owns TY / 2 groups of 16 voxels along x (rows 2w.., both x
+// halves) and reuses every weight fragment for all of them.
+template <int CI, int TY>
+struct ZmGeom {
+    static constexpr int TX = 32, HX = TX + 2, HY = TY + 2, HV = HX * HY;
+    static constexpr int VS = CI + 8;                    // LDS voxel stride (bf16)
+    static constexpr int PL = HV * VS;                   // plane (bf16)
+    static constexpr int ITEMS = HV * (CI / 8);          // 16-byte items per plane
+    static constexpr int IPT = (ITEMS + 255) / 256;      // items per thread
+};
+
+template <int CI, int CO, int TY, bool SKIP, typename OUT>
+__global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, const bf16* __restrict__ B, Dims d,
+                                                int ntx, int nty, int zchunk, const bf16* __restrict__ W,
+                                                OUT* __restrict__ out, const int* stop) {
+    using G = ZmGeom<CI, TY>;
+    constexpr int K = 27 * CI, KP = (K + 31) / 32 * 32, NC = KP / 32, MT = CO / 16, NG = TY / 2;
+    static_assert(TY % 2 == 0 && CI % 8 == 0 && CO % 16 == 0, "tile");
+    __shared__ __attribute__((aligned(16))) bf16 lds[3 * G::PL];
+    if (stop && *stop) return;
+    const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
+    const int tx = blk % ntx, t2 = blk / ntx;
+    const int ty = t2 % nty, tz = t2 / nty;
+    const int x0 = tx * G::TX, y0 = ty * TY;
+    const int zs = tz * zchunk, ze = min(d.nz, zs + zchunk);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, vl = lane & 15, kg = lane >> 4;
+    const Dims dB = coarse(d);
+    const int pbase = zs - 1;  // ring slot of plane p: (p - pbase) % 3
+    // staging: item -> (haloed voxel, 8 channels)
+    bf16x8 pa[G::IPT], pb[G::IPT];
+    bool pm[G::IPT];
+    auto sload = [&](int p) {
+#pragma unroll
+        for (int h = 0; h < G::IPT; ++h) {
+            const int it = min(t + 256 * h, G::ITEMS - 1);
+            const int hv = it / (CI / 8), c8 = it % (CI / 8);
+            const int gx = x0 - 1 + hv % G::HX, gy = y0 - 1 + hv / G::HX;
+            pm[h] = t + 256 * h < G::ITEMS && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
+            const int cx = min(max(gx, 0), d.nx - 1), cy = min(max(gy, 0), d.ny - 1), cz = min(max(p, 0), d.nz - 1);
+            pa[h] = *reinterpret_cast<const bf16x8*>(A + ((size_t)cx + (size_t)d.nx * (size_t)(cy + d.ny * cz)) * CI + 8 * c8);
+            if constexpr (SKIP)
+                pb[h] = *reinterpret_cast<const bf16x8*>(
+                    B + ((size_t)(cx >> 1) + (size_t)dB.nx * (size_t)((cy >> 1) + dB.ny * (cz >> 1))) * CI + 8 * c8);
+        }
+    };
+    auto sstore = [&](int p) {
+        bf16* slot = lds + ((p - pbase) % 3) * G::PL;
+#pragma unroll
+        for (int h = 0; h < G::IPT; ++h) {
+            const int it = t + 256 * h;
+            if (it >= G::ITEMS) break;
+            const int hv = it / (CI / 8), c8 = it % (CI / 8);
+            bf16x8 v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if constexpr (SKIP)
+                    v[j] = pm[h] ? (bf16)((float)pa[h][j] + (float)pb[h][j]) : (bf16)0.f;
+                else
+                    v[j] = pm[h] ? pa[h][j] : (bf16)0.f;
+            }
+            *reinterpret_cast<bf16x8*>(slot + hv * G::VS + 8 * c8) = v;
+        }
+    };
+    // this lane's weight fragments of every chunk, held for the whole segment
+    bf16x8 wreg[NC][MT];
+#pragma unroll
+    for (int kc = 0; kc < NC; ++kc)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+            wreg[kc][m] = *reinterpret_cast<const bf16x8*>(W + (size_t)(16 * m + vl) * KP + kc * 32 + 8 * kg);
+    // group g of wavefront w: plane row (w NG + g) / 2, x half (w NG + g) % 2
+    const int lane_base = (w * NG / 2) * G::HX * G::VS + vl * G::VS;
+    sload(zs - 1);
+    sstore(zs - 1);
+    sload(zs);
+    sstore(zs);
+    sload(zs + 1);
+    sstore(zs + 1);
+    sload(zs + 2);
+    kvs_tiling::lds_barrier();
+    for (int z = zs; z < ze; ++z) {
+        const int s0 = ((z - 1 - pbase) % 3) * G::PL, s1 = ((z - pbase) % 3) * G::PL, s2 = ((z + 1 - pbase) % 3) * G::PL;
+        f32x4 acc[NG][MT];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < NC; ++kc) {
+            // chunk kc covers k = 32 kc + 8 kg .. + 7: one tap, 8 channels;
+            // k >= 27 CI has zero weights and reads a valid tap instead
+            const int k0 = kc * 32 + 8 * kg;
+            const int tap = min(k0 / CI, 26), ci0 = k0 % CI;
+            const int tdz = tap_dz(tap);
+            const int toff = (tdz < 0 ? s0 : (tdz == 0 ? s1 : s2)) +
+                             ((1 + tap_dy(tap)) * G::HX + 1 + tap_dx(tap)) * G::VS + ci0 + lane_base;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int gdelta = ((g >> 1) * G::HX + 16 * (g & 1)) * G::VS;
+                const bf16x8 xb = *reinterpret_cast<const bf16x8*>(lds + toff + gdelta);
+#pragma unroll
+                for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wreg[kc][m], xb, acc[g][m]);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const int gl = w * NG + g;
+            const int gx = x0 + 16 * (gl & 1) + vl, gy = y0 + (gl >> 1);
+            if (gx >= d.nx || gy >= d.ny) continue;
+            const size_t v = (size_t)gx + (size_t)d.nx * (size_t)(gy + d.ny * z);
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                if constexpr (sizeof(OUT) == 2) {
+                    bf16x4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[g][m][i];
+                    *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
+                } else {
+                    *reinterpret_cast<f32x4*>(out + v * CO + 16 * m + 4 * kg) = acc[g][m];
+                }
+            }
+        }
+        if (z + 1 < ze) {
+            kvs_tiling::lds_barrier();  // plane z - 1 no longer read
+            sstore(z + 2);
+            if (z + 3 <= ze) sload(z + 3);
+            kvs_tiling::lds_barrier();
+        }
+    }
+}
+
 // voxel groups per wavefront: fewer for wide inputs or outputs (register budget)
 constexpr int conv_nv(int ci, int co) { return (co >= 64 || ci >= 32) ? 4 : 8; }
 
@@ -205,16 +342,16 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
     const int pbase = 2 * Zs - 1;  // ring slot of fine plane p: (p - pbase) % FP_SLOTS
     constexpr int ZERO = FP_SLOTS * FP_RN;
     if (t == 0) rs[ZERO] = 0.f;
-    // per-lane taps 8 kg .. 8 kg + 7: in-plane offset and z offset
+    // per-lane taps 8 kg .. 8 kg + 7: LDS offset within a plane and z offset;
+    // taps >= 27 have zero weights and read the centre tap instead
     int toff[8], tdz[8];
-    bool tok[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int tap = 8 * kg + j;
-        tok[j] = tap < 27;
-        toff[j] = tok[j] ? tap_dy(tap) * FP_RX + tap_dx(tap) : 0;
-        tdz[j] = tok[j] ? tap_dz(tap) : 0;
+        toff[j] = tap < 27 ? tap_dy(tap) * FP_RX + tap_dx(tap) : 0;
+        tdz[j] = tap < 27 ? tap_dz(tap) : 0;
     }
+    const int lane_base = (2 * w + 1) * FP_RX + vl + 1;  // group xg = 0, gy = 0
     const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(W + vl * 32 + 8 * kg);
     // Loads are unconditional from clamped (in-bounds) addresses and masked
     // when stored to LDS, so that a prefetch stays in flight until then.
@@ -260,7 +397,8 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
             }
         }
         kvs_tiling::lds_barrier();
-        // LDS address of each tap for gz = 0, 1 (row and x added per group)
+        // LDS address of each tap for gz = 0, 1; the group offsets
+        // (gy * FP_RX + 16 * xg) are constants of the unrolled loops
         int sb[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) sb[q] = ((2 * Z - 1 + q - pbase) % FP_SLOTS) * FP_RN;
@@ -268,26 +406,25 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
 #pragma unroll
         for (int gz = 0; gz < 2; ++gz)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int sl = tdz[j] < 0 ? sb[gz] : (tdz[j] == 0 ? sb[gz + 1] : sb[gz + 2]);
-                ab[gz][j] = sl + toff[j];
-            }
+            for (int j = 0; j < 8; ++j)
+                ab[gz][j] = (tdz[j] < 0 ? sb[gz] : (tdz[j] == 0 ? sb[gz + 1] : sb[gz + 2])) + toff[j] + lane_base;
+        const float mz[2] = {2 * Z < d.nz ? 1.f : 0.f, 2 * Z + 1 < d.nz ? 1.f : 0.f};
 #pragma unroll
         for (int xg = 0; xg < 4; ++xg) {
-            const int fx = 2 * X0 + 16 * xg + vl;
+            const float mx = 2 * X0 + 16 * xg + vl < d.nx ? 1.f : 0.f;
             float s[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int gz = 0; gz < 2; ++gz)
 #pragma unroll
                 for (int gy = 0; gy < 2; ++gy) {
-                    const int rowbase = (2 * w + gy + 1) * FP_RX + 16 * xg + vl + 1;
+                    const int delta = gy * FP_RX + 16 * xg;
                     bf16x8 xb;
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[tok[j] ? ab[gz][j] + rowbase : ZERO];
+                    for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[ab[gz][j] + delta];
                     const f32x4 e = mfma32(w8, xb, f32x4{0.f, 0.f, 0.f, 0.f});
-                    const bool valid = fx < d.nx && 2 * Y + gy < d.ny && 2 * Z + gz < d.nz;
+                    const float m = mx * mz[gz] * (2 * Y + gy < d.ny ? 1.f : 0.f);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) s[i] += valid ? (float)(bf16)e[i] : 0.f;
+                    for (int i = 0; i < 4; ++i) s[i] = fmaf(m, (float)(bf16)e[i], s[i]);
                 }
 #pragma unroll
             for (int i = 0; i < 4; ++i) s[i] += __shfl_xor(s[i], 1);
@@ -316,7 +453,7 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
 // output planes q - 1, q, q + 1; plane q - 1 is then complete and stored.
 // x and g1 are loaded one plane ahead.  With keep != null, i0 of the
 // block's own voxels is stored (training).
-constexpr int OT_X = 30, OT_Y = 6, HT_X = 32, HT_Y = 8, RT_X = 34, RT_Y = 10, YS = 28;
+constexpr int OT_X = 30, OT_Y = 6, HT_X = 32, HT_Y = 8, RT_X = 34, RT_Y = 10, YS = 33;
 
 __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx, int nty,
                                                   int zchunk, const bf16* __restrict__ W0, const bf16* __restrict__ WoT,
@@ -324,7 +461,7 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
                                                   bf16* __restrict__ keep) {
     constexpr int RN = RT_X * RT_Y;
     __shared__ float rs[3 * RN + 1];  // the last element is a constant 0
-    __shared__ float ys[HT_Y * HT_X][YS];
+    __shared__ float ys[HT_Y * HT_X * YS];  // y of the haloed plane, 27 taps + 6 padding per voxel
     if (ctl.stop && *ctl.stop) return;
     const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
     const double out_scale = ctl.out_dev ? *ctl.out_dev : ctl.out_v;
@@ -343,14 +480,24 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
     const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(W0 + vl * 32 + 8 * kg);
     const bf16x4 wo0 = *reinterpret_cast<const bf16x4*>(WoT + vl * 16 + 4 * kg);
     const bf16x4 wo1 = *reinterpret_cast<const bf16x4*>(WoT + (16 + vl) * 16 + 4 * kg);
+    // per-lane taps 8 kg .. 8 kg + 7 (taps >= 27 have zero weights and read
+    // the centre tap instead)
     int toff[8], tdz[8];
-    bool tok[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int tap = 8 * kg + j;
-        tok[j] = tap < 27;
-        toff[j] = tok[j] ? tap_dy(tap) * RT_X + tap_dx(tap) : 0;
-        tdz[j] = tok[j] ? tap_dz(tap) : 0;
+        toff[j] = tap < 27 ? tap_dy(tap) * RT_X + tap_dx(tap) : 0;
+        tdz[j] = tap < 27 ? tap_dz(tap) : 0;
+    }
+    // haloed voxels of the wavefront's 4 groups: gi -> row 2w + gi / 2, x 16 (gi % 2) + vl;
+    // the group offsets are constants of the unrolled loops
+    const int rbase = (2 * w + 1) * RT_X + vl + 1;  // r tile, group 0
+    const int ybw = (2 * w * HT_X + vl) * YS + 4 * kg;  // y tile, group 0, this lane's taps
+    bool vxy[4];
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi) {
+        const int gx = hx0 + 16 * (gi & 1) + vl, gy = hy0 + 2 * w + (gi >> 1);
+        vxy[gi] = gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
     }
     // Loads are unconditional from clamped (in-bounds) addresses and masked
     // at their use, so that a prefetch stays in flight until then.
@@ -397,7 +544,7 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
     const int gxo = ox0 + oxl, gyo = oy0 + oyl;
     const bool out_in = has_out && gxo < d.nx && gyo < d.ny;
     const bool inner_xy = gxo >= 1 && gxo <= d.nx - 2 && gyo >= 1 && gyo <= d.ny - 2;
-    const int ybase = (oyl + 1) * HT_X + oxl + 1;
+    const int ybase = ((oyl + 1) * HT_X + oxl + 1) * YS;
     float a_prev = 0.f, a_cur = 0.f, a_next = 0.f;
     for (int q = zs - 1; q <= ze; ++q) {
         rstore(q + 1, rv, rm);
@@ -411,33 +558,35 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
         const int s0 = ((q - 1 - base) % 3) * RN, s1 = ((q - base) % 3) * RN, s2 = ((q + 1 - base) % 3) * RN;
         int ab[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) ab[j] = (tdz[j] < 0 ? s0 : (tdz[j] == 0 ? s1 : s2)) + toff[j];
+        for (int j = 0; j < 8; ++j) ab[j] = (tdz[j] < 0 ? s0 : (tdz[j] == 0 ? s1 : s2)) + toff[j] + rbase;
         const bool qin = q >= 0 && q < d.nz;
 #pragma unroll
         for (int gi = 0; gi < 4; ++gi) {
-            const int hy = 2 * w + (gi >> 1), hx = 16 * (gi & 1) + vl;
-            const int gx = hx0 + hx, gy = hy0 + hy;
-            const bool valid = qin && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
-            const int rowbase = (hy + 1) * RT_X + hx + 1;
+            const int rdelta = (gi >> 1) * RT_X + 16 * (gi & 1);
             bf16x8 xb;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[tok[j] ? ab[j] + rowbase : ZERO];
+            for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[ab[j] + rdelta];
             const f32x4 e = mfma32(w0, xb, f32x4{0.f, 0.f, 0.f, 0.f});
+            const bool valid = qin && vxy[gi];
             bf16x4 iv;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) iv[i] = valid ? (bf16)((float)(bf16)e[i] + (float)gcur[gi][i]) : (bf16)0.f;
-            if (keep && valid && hx >= 1 && hx <= OT_X && hy >= 1 && hy <= OT_Y && q >= zs && q < ze)
-                *reinterpret_cast<bf16x4*>(keep + ((size_t)q * sxy + (size_t)(gy * d.nx + gx)) * 16 + 4 * kg) = iv;
+            for (int i = 0; i < 4; ++i) iv[i] = (bf16)((float)(bf16)e[i] + (float)gcur[gi][i]);
+            if (!valid) iv = bf16x4{};
+            if (keep) {
+                const int hy = 2 * w + (gi >> 1), hx = 16 * (gi & 1) + vl;
+                if (valid && hx >= 1 && hx <= OT_X && hy >= 1 && hy <= OT_Y && q >= zs && q < ze)
+                    *reinterpret_cast<bf16x4*>(keep + ((size_t)q * sxy + (size_t)((hy0 + hy) * d.nx + hx0 + hx)) * 16 +
+                                               4 * kg) = iv;
+            }
             const f32x4 y0 = mfma16(wo0, iv, f32x4{0.f, 0.f, 0.f, 0.f});
             const f32x4 y1 = mfma16(wo1, iv, f32x4{0.f, 0.f, 0.f, 0.f});
-            float* yr = ys[hy * HT_X + hx];
+            // taps 4 kg + i and 16 + 4 kg + i; 27..31 land in the padding
+            float* yr = ys + ybw + ((gi >> 1) * HT_X + 16 * (gi & 1)) * YS;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) yr[4 * kg + i] = y0[i];
-            if (kg < 2)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) yr[16 + 4 * kg + i] = y1[i];
-            else if (kg == 2)
-                yr[24] = y1[0], yr[25] = y1[1], yr[26] = y1[2];
+            for (int i = 0; i < 4; ++i) {
+                yr[i] = y0[i];
+                yr[16 + i] = y1[i];
+            }
         }
 #pragma unroll
         for (int gi = 0; gi < 4; ++gi) gcur[gi] = gnext[gi];
@@ -447,7 +596,7 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
-                    const float* yy = ys[ybase + dy * HT_X + dx];
+                    const float* yy = ys + ybase + (dy * HT_X + dx) * YS;
                     const int tin = 3 * (dy + 1) + (dx + 1);
                     a_next += yy[tin];
                     a_cur += yy[9 + tin];
@@ -493,12 +642,32 @@ __global__ void pool2(const bf16* __restrict__ fine, Dims d, bf16* __restrict__ 
     *reinterpret_cast<bf16x8*>(out + V * C + c8) = o;
 }
 
-// dispatch of the MFMA conv over the channel pairs this network uses
+// rows of a z-march tile: LDS of about 50-60 KB per block for any CI
+constexpr int zm_rows(int ci) { return ci <= 16 ? 8 : (ci <= 32 ? 4 : 2); }
+
+template <int CI, int CO, bool SKIP, typename OUT>
+hipError_t launch_zm(const bf16* A, const bf16* B, Dims d, const bf16* W, OUT* out, hipStream_t s, const int* stop) {
+    constexpr int TY = zm_rows(CI);
+    auto kern = conv3_zm<CI, CO, TY, SKIP, OUT>;
+    static const int cap = kvs_tiling::resident_blocks(kern, 256);
+    const int ntx = (d.nx + 31) / 32, nty = (d.ny + TY - 1) / TY;
+    const int zchunk = kvs_tiling::choose_kchunk(ntx * nty, d.nz, cap);
+    const int nb = ntx * nty * ((d.nz + zchunk - 1) / zchunk);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, A, B, d, ntx, nty, zchunk, W, out, stop);
+    return hipGetLastError();
+}
+
+// dispatch of the MFMA conv over the channel pairs this network uses:
+// dilation 1 with up to 32 channels -> LDS z-march; dilated or 64-channel
+// layers (the 1/4-resolution bottleneck) -> gathering kernel
 template <typename OUT>
 hipError_t launch_conv(int ci, int co, const bf16* A, const bf16* B, Dims d, int dil, const bf16* W, OUT* out,
                        hipStream_t s, const int* stop = nullptr) {
 #define KVS_CONV_CASE(CI_, CO_)                                                                                \
     if (ci == CI_ && co == CO_) {                                                                              \
+        if (dil == 1 && CI_ <= 32 && CO_ <= 32)                                                                \
+            return B ? launch_zm<CI_, CO_, true, OUT>(A, B, d, W, out, s, stop)                                \
+                     : launch_zm<CI_, CO_, false, OUT>(A, B, d, W, out, s, stop);                              \
         constexpr int NV = conv_nv(CI_, CO_);                                                                  \
         const int nb = (int)((d.n() + 64 * NV - 1) / (64 * NV));                                               \
         if (B)                                                                                                 \
