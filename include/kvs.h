@@ -261,20 +261,25 @@ kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* varian
 /* Network z = U(r): e0 = conv(r; 1 -> C0); e1 = conv(pool(e0); C0 -> C1);
  * bottleneck at 1/4 resolution: conv(pool(e1); C1 -> C2), n_bottleneck - 2
  * convs C2 -> C2 with dilations 2, 4, ..., conv(C2 -> C1);
- * g1 = conv(e1 + up(bottleneck); C1 -> C0); g0 = conv(e0 + up(g1); C0 -> C0);
- * z = conv(g0; C0 -> 1), zero outside the interior.  conv = 3x3x3 (dilated)
- * cross-correlation with zero padding, no bias, no nonlinearity; pool = mean
- * of the existing 2x2x2 children; up = nearest neighbour.  Activations and
- * weights are BF16, accumulation FP32 (MFMA).  Used as the preconditioner of
- * a flexible PCG on the projection's Poisson problem (not part of the
- * paper's method; plain CG / Jacobi-PCG remain the reference). */
+ * g1 = conv(e1 + up(bottleneck); C1 -> C0) and gz = g1 . wp (pointwise
+ * C0 -> 1) at 1/2 resolution; z = conv(e0; C0 -> 1) + up(gz), zero outside
+ * the interior: a local stencil of r plus the interpolated coarse
+ * correction.  conv = 3x3x3 (dilated) cross-correlation with zero padding,
+ * no bias, no nonlinearity; pool = mean of the existing 2x2x2 children;
+ * up = cell-centred trilinear interpolation (per axis 3/4 of the parent,
+ * 1/4 of its neighbour on the fine cell's side, clamped at the edges).
+ * Activations and weights are BF16, accumulation FP32 (MFMA); gz is FP32.
+ * Used as the preconditioner of a flexible PCG on the projection's Poisson
+ * problem (not part of the paper's method; plain CG / Jacobi-PCG remain the
+ * reference). */
 /* channels = {C0, C1, C2} (NULL: 16, 32, 64; only these are built);
  * 2 <= n_bottleneck <= 8.  Weights start at zero. */
 kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_unet** out);
 void kvs_unet_destroy(kvs_unet* net);
 const char* kvs_unet_last_error(const kvs_unet* net);
 /* FP32 master weights, layer by layer in network order, each [co][27 * ci]
- * with k = tap * ci + c, tap = 9 (dz + 1) + 3 (dy + 1) + (dx + 1). */
+ * with k = tap * ci + c, tap = 9 (dz + 1) + 3 (dy + 1) + (dx + 1); the
+ * pointwise projection is [1][ci]. */
 int64_t kvs_unet_num_weights(const kvs_unet* net);
 kvs_status kvs_unet_set_weights(kvs_unet* net, const float* w, int64_t n);
 kvs_status kvs_unet_get_weights(const kvs_unet* net, float* w, int64_t n);
@@ -307,8 +312,10 @@ kvs_status kvs_unet_adam_step(kvs_unet* net, double lr, int32_t n_samples, void*
  * b, x: device fields of N doubles. */
 kvs_status kvs_unet_make_sample(kvs_ctx* ctx, int64_t k_snapshot, double* b, double* x, double* b_rms);
 /* Verification hook: one MFMA convolution on host BF16 bit patterns,
- * out[v][co] = sum_k W[co][k] (A[p][c] + B[p/2][c]) with W rows padded to
- * kvs_unet_conv_kpad(ci) entries (B may be NULL).  Blocks. */
+ * out[v][co] = sum_k W[co][k] x[p][c] with W rows padded to
+ * kvs_unet_conv_kpad(ci) entries; x = A, or with B (the next coarser grid,
+ * (n + 1) / 2 per axis) x = bf16(A + up(B)) as the decoder forms its skip
+ * input.  Blocks. */
 int64_t kvs_unet_conv_kpad(int32_t ci);
 kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16_t* A, const uint16_t* B, int64_t nx,
                                int64_t ny, int64_t nz, const uint16_t* W, uint16_t* out);

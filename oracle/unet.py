@@ -7,10 +7,14 @@ GPU's FP32 accumulation order.
 
 Network (linear, no biases): e0 = conv(r; 1->C0); e1 = conv(pool(e0));
 bottleneck convs at 1/4 resolution (dilations 1, 2, 4, ..., then 1);
-g1 = conv(e1 + up(b)); z = conv(e0 + up(g1); C0->1) on the interior.
+g1 = conv(e1 + up(b); C1->C0); gz = g1 . wp (pointwise C0->1) at 1/2
+resolution; z = conv(e0; C0->1) + up(gz) on the interior: a local stencil
+of r plus the interpolated coarse correction.
 conv = 3x3x3 cross-correlation with zero padding; pool = mean of the
-existing children; up = nearest neighbour.  Arrays are channels-last
-[z][y][x][C].
+existing children; up = cell-centred trilinear interpolation (per axis a
+fine cell takes 3/4 of its parent and 1/4 of the parent's neighbour on its
+side, the neighbour index clamped to the coarse grid).  Arrays are
+channels-last [z][y][x][C].
 """
 from __future__ import annotations
 
@@ -81,29 +85,56 @@ def pool(x):
     return s / cnt
 
 
-def up(c, shape):
+def _repeat(c, shape):
     """Nearest-neighbour copy of a coarse field onto `shape` (first 3 axes)."""
     Z, Y, X = shape
     return c[np.arange(Z) // 2][:, np.arange(Y) // 2][:, :, np.arange(X) // 2]
 
 
+def _interp_index(n, nc):
+    """Parent I and side neighbour J (clamped) of fine cells 0..n-1."""
+    i = np.arange(n)
+    I = i // 2
+    J = np.clip(np.where(i % 2 == 0, I - 1, I + 1), 0, nc - 1)
+    return I, J
+
+
+def up(c, shape):
+    """Trilinear (cell-centred, factor 2) interpolation of a coarse field onto
+    `shape`, one axis after the other: f[i] = 3/4 c[I] + 1/4 c[J]."""
+    out = np.asarray(c, dtype=np.float64)
+    for ax in range(3):
+        I, J = _interp_index(shape[ax], out.shape[ax])
+        out = 0.75 * np.take(out, I, axis=ax) + 0.25 * np.take(out, J, axis=ax)
+    return out
+
+
 def layer_shapes(c0=16, c1=32, c2=64, nbott=4):
-    """(ci, co, dil) of every layer in order, as the GPU network builds them."""
+    """(ci, co, dil) of every layer in order, as the GPU network builds them;
+    dil = 0 marks the pointwise projection (one tap)."""
     L = [(1, c0, 1), (c0, c1, 1), (c1, c2, 1)]
     dil = 2
     for _ in range(nbott - 2):
         L.append((c2, c2, dil))
         dil *= 2
-    L += [(c2, c1, 1), (c1, c0, 1), (c0, 1, 1)]
+    L += [(c2, c1, 1), (c1, c0, 1), (c0, 1, 0), (c0, 1, 1)]
     return L
 
 
+def layer_taps(dil):
+    return 27 if dil > 0 else 1
+
+
+def layer_size(ci, co, dil):
+    return co * layer_taps(dil) * ci
+
+
 def split_weights(flat, shapes):
-    """Flat master weights ([co][27*ci] per layer) -> list of [co][27][ci]."""
+    """Flat master weights ([co][taps*ci] per layer) -> list of [co][taps][ci]."""
     out, off = [], 0
-    for ci, co, _ in shapes:
-        n = co * 27 * ci
-        out.append(np.asarray(flat[off:off + n], dtype=np.float64).reshape(co, 27, ci))
+    for ci, co, dil in shapes:
+        n = layer_size(ci, co, dil)
+        out.append(np.asarray(flat[off:off + n], dtype=np.float64).reshape(co, layer_taps(dil), ci))
         off += n
     return out
 
@@ -130,13 +161,14 @@ def forward(r, in_scale, out_scale, flat_w, c0=16, c1=32, c2=64, nbott=4, exact=
         b = rnd(conv3(b, Ws[li], shapes[li][2]))
     i1 = rnd(np.float32(e1) + np.float32(up(b, e1.shape[:3])) if not exact else e1 + up(b, e1.shape[:3]))
     g1 = rnd(conv3(i1, Ws[2 + nbott]))
-    i0 = rnd(np.float32(e0) + np.float32(up(g1, e0.shape[:3])) if not exact else e0 + up(g1, e0.shape[:3]))
-    z = out_scale * conv3(i0, Ws[3 + nbott])[..., 0]
+    f32 = _identity if exact else (lambda a: np.asarray(np.float32(a), dtype=np.float64))
+    gz = f32(g1 @ Ws[3 + nbott][0, 0, :])[..., None]
+    z = out_scale * (conv3(e0, Ws[4 + nbott])[..., 0] + up(gz, e0.shape[:3])[..., 0])
     m = np.zeros_like(z)
     m[1:-1, 1:-1, 1:-1] = 1.0
     z = z * m
     if keep:
-        return z, dict(x=x, e0=e0, p0=p0, e1=e1, bins=bins, i1=i1, g1=g1, i0=i0, Ws=Ws, shapes=shapes)
+        return z, dict(x=x, e0=e0, p0=p0, e1=e1, bins=bins, i1=i1, g1=g1, gz=gz, Ws=Ws, shapes=shapes)
     return z
 
 
@@ -159,11 +191,18 @@ def conv3_weight_grad(x, dy, dil=1):
 
 
 def up_adjoint(df, cshape):
-    """Adjoint of nearest upsampling: sum over the children."""
-    Z, Y, X = df.shape[:3]
-    out = np.zeros(tuple(cshape) + df.shape[3:])
-    np.add.at(out, (np.arange(Z)[:, None, None] // 2, np.arange(Y)[None, :, None] // 2,
-                    np.arange(X)[None, None, :] // 2), df)
+    """Adjoint of the trilinear interpolation: each fine value is returned to
+    its parent with weight 3/4 and to the side neighbour with weight 1/4."""
+    out = np.asarray(df, dtype=np.float64)
+    for ax in (2, 1, 0):
+        I, J = _interp_index(out.shape[ax], cshape[ax])
+        shp = list(out.shape)
+        shp[ax] = cshape[ax]
+        acc = np.zeros(shp)
+        for src, w in ((I, 0.75), (J, 0.25)):
+            moved = np.moveaxis(acc, ax, 0)
+            np.add.at(moved, src, w * np.moveaxis(out, ax, 0))
+        out = acc
     return out
 
 
@@ -175,7 +214,7 @@ def pool_adjoint(dc, fshape):
         for dy in range(2):
             for dx in range(2):
                 cnt[:len(range(dz, Z, 2)), :len(range(dy, Y, 2)), :len(range(dx, X, 2))] += 1
-    return up(dc / cnt, (Z, Y, X))
+    return _repeat(dc / cnt, (Z, Y, X))
 
 
 def backward(r, in_scale, flat_w, dz, dz_scale, c0=16, c1=32, c2=64, nbott=4, exact=False):
@@ -189,10 +228,13 @@ def backward(r, in_scale, flat_w, dz, dz_scale, c0=16, c1=32, c2=64, nbott=4, ex
     Ws, shapes = A["Ws"], A["shapes"]
     grads = [None] * len(shapes)
     dzf = f32(dz_scale * np.asarray(dz, dtype=np.float64))[..., None]
-    lo, ld1 = len(shapes) - 1, len(shapes) - 2
-    grads[lo] = conv3_weight_grad(A["i0"], dzf)
+    lo, lp, ld1 = len(shapes) - 1, len(shapes) - 2, len(shapes) - 3
+    # z = conv(e0; W_out) + up(gz), gz = g1 . wp
+    grads[lo] = conv3_weight_grad(A["e0"], dzf)
     de0 = conv3_adjoint(dzf, Ws[lo])
-    dg1 = up_adjoint(de0, A["g1"].shape[:3])
+    dgz = up_adjoint(dzf, A["g1"].shape[:3])
+    grads[lp] = (A["g1"].reshape(-1, A["g1"].shape[3]).T @ dgz.reshape(-1)).reshape(1, 1, -1)
+    dg1 = dgz * Ws[lp][0, 0, :]
     grads[ld1] = conv3_weight_grad(A["i1"], dg1)
     de1 = conv3_adjoint(rnd(dg1), Ws[ld1])
     dcur = up_adjoint(de1, A["bins"][-1].shape[:3])

@@ -68,13 +68,12 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
 
 // Convolution at the coarse levels:
 // out[v][co] = sum_{tap, ci} W[co][tap * CI + ci] * in(v + dil * tap)[ci],
-// in(p) = bf16(A[p][ci] + B[p / 2][ci]) with SKIP, else A[p][ci]; zero
-// outside the grid.
+// in(p) = A[p][ci], zero outside the grid.
 // Each wavefront computes NV groups of 16 consecutive voxels for all CO
 // channels, so every weight fragment it loads feeds NV MFMAs.  Outputs are
 // rounded once (BF16) or stored as FP32.
-template <int CI, int CO, int NV, bool SKIP, typename OUT>
-__global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, const bf16* __restrict__ B, Dims d,
+template <int CI, int CO, int NV, typename OUT>
+__global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Dims d,
                                                   int dil, const bf16* __restrict__ W, OUT* __restrict__ out,
                                                   const int* stop) {
     static_assert(CI % 8 == 0 && CO % 16 == 0, "channel counts");
@@ -88,7 +87,6 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, co
     const long long N = d.n();
     if (v0 >= N) return;
     const int vl = lane & 15, kg = lane >> 4;
-    const Dims dB = coarse(d);
     int gx[NV], gy[NV], gz[NV];
     bool valid[NV];
 #pragma unroll
@@ -116,7 +114,7 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, co
         for (int m = 0; m < MT; ++m) wf[m] = *reinterpret_cast<const bf16x8*>(W + (long long)(16 * m + vl) * KP + k0);
         // operands of all groups: unconditional loads from clamped addresses,
         // masked after arrival (no branch around a load)
-        bf16x8 a8[NV], b8[NV];
+        bf16x8 a8[NV];
         bool ok[NV];
 #pragma unroll
         for (int g = 0; g < NV; ++g) {
@@ -125,21 +123,12 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, co
             const int cx = min(max(px, 0), d.nx - 1), cy = min(max(py, 0), d.ny - 1), cz = min(max(pz, 0), d.nz - 1);
             const size_t p = (size_t)cx + (size_t)d.nx * (size_t)(cy + d.ny * cz);
             a8[g] = *reinterpret_cast<const bf16x8*>(A + p * CI + ci0);
-            if constexpr (SKIP) {
-                const size_t q = (size_t)(cx >> 1) + (size_t)dB.nx * (size_t)((cy >> 1) + dB.ny * (cz >> 1));
-                b8[g] = *reinterpret_cast<const bf16x8*>(B + q * CI + ci0);
-            }
         }
 #pragma unroll
         for (int g = 0; g < NV; ++g) {
             bf16x8 xb;
-            if constexpr (SKIP) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) xb[j] = ok[g] ? (bf16)((float)a8[g][j] + (float)b8[g][j]) : (bf16)0.f;
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) xb[j] = ok[g] ? a8[g][j] : (bf16)0.f;
-            }
+            for (int j = 0; j < 8; ++j) xb[j] = ok[g] ? a8[g][j] : (bf16)0.f;
 #pragma unroll
             for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], xb, acc[g][m]);
         }
@@ -166,10 +155,11 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, co
 // conv3_mfma).  A block owns a 32 x TY column of output voxels and marches up
 // a z segment; the haloed input planes z - 1, z, z + 1 (34 x (TY + 2) voxels,
 // channel stride CI + 8 against bank conflicts) live in an LDS ring, the
-// plane after next is prefetched into registers.  With SKIP the input
-// bf16(A + B[p / 2]) is formed once per voxel when a plane is staged.  Each
-// wavefront owns TY / 2 groups of 16 voxels along x (rows 2w.., both x
-// halves) and reuses every weight fragment for all of them.
+// plane after next is prefetched into registers.  Each wavefront owns
+// TY / 2 groups of 16 voxels along x and keeps its weight fragments of all
+// chunks in registers.  With PROJ (CO = 16) the epilogue also forms the
+// pointwise projection gz = sum_c wp[c] bf16(out[c]) (FP32), and `out` may
+// be null (only gz is needed at inference).
 template <int CI, int TY>
 struct ZmGeom {
     static constexpr int TX = 32, HX = TX + 2, HY = TY + 2, HV = HX * HY;
@@ -179,13 +169,14 @@ struct ZmGeom {
     static constexpr int IPT = (ITEMS + 255) / 256;      // items per thread
 };
 
-template <int CI, int CO, int TY, bool SKIP, typename OUT>
-__global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, const bf16* __restrict__ B, Dims d,
-                                                int ntx, int nty, int zchunk, const bf16* __restrict__ W,
-                                                OUT* __restrict__ out, const int* stop) {
+template <int CI, int CO, int TY, bool PROJ, typename OUT>
+__global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, Dims d, int ntx, int nty, int zchunk,
+                                                const bf16* __restrict__ W, OUT* __restrict__ out,
+                                                const float* __restrict__ wp, float* __restrict__ gz,
+                                                const int* stop) {
     using G = ZmGeom<CI, TY>;
     constexpr int K = 27 * CI, KP = (K + 31) / 32 * 32, NC = KP / 32, MT = CO / 16, NG = TY / 2;
-    static_assert(TY % 2 == 0 && CI % 8 == 0 && CO % 16 == 0, "tile");
+    static_assert(TY % 2 == 0 && CI % 8 == 0 && CO % 16 == 0 && (!PROJ || CO == 16), "tile");
     __shared__ __attribute__((aligned(16))) bf16 lds[3 * G::PL];
     if (stop && *stop) return;
     const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
@@ -194,10 +185,9 @@ __global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, cons
     const int x0 = tx * G::TX, y0 = ty * TY;
     const int zs = tz * zchunk, ze = min(d.nz, zs + zchunk);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, vl = lane & 15, kg = lane >> 4;
-    const Dims dB = coarse(d);
     const int pbase = zs - 1;  // ring slot of plane p: (p - pbase) % 3
     // staging: item -> (haloed voxel, 8 channels)
-    bf16x8 pa[G::IPT], pb[G::IPT];
+    bf16x8 pa[G::IPT];
     bool pm[G::IPT];
     auto sload = [&](int p) {
 #pragma unroll
@@ -208,9 +198,6 @@ __global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, cons
             pm[h] = t + 256 * h < G::ITEMS && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
             const int cx = min(max(gx, 0), d.nx - 1), cy = min(max(gy, 0), d.ny - 1), cz = min(max(p, 0), d.nz - 1);
             pa[h] = *reinterpret_cast<const bf16x8*>(A + ((size_t)cx + (size_t)d.nx * (size_t)(cy + d.ny * cz)) * CI + 8 * c8);
-            if constexpr (SKIP)
-                pb[h] = *reinterpret_cast<const bf16x8*>(
-                    B + ((size_t)(cx >> 1) + (size_t)dB.nx * (size_t)((cy >> 1) + dB.ny * (cz >> 1))) * CI + 8 * c8);
         }
     };
     auto sstore = [&](int p) {
@@ -222,12 +209,7 @@ __global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, cons
             const int hv = it / (CI / 8), c8 = it % (CI / 8);
             bf16x8 v;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if constexpr (SKIP)
-                    v[j] = pm[h] ? (bf16)((float)pa[h][j] + (float)pb[h][j]) : (bf16)0.f;
-                else
-                    v[j] = pm[h] ? pa[h][j] : (bf16)0.f;
-            }
+            for (int j = 0; j < 8; ++j) v[j] = pm[h] ? pa[h][j] : (bf16)0.f;
             *reinterpret_cast<bf16x8*>(slot + hv * G::VS + 8 * c8) = v;
         }
     };
@@ -276,8 +258,18 @@ __global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, cons
         for (int g = 0; g < NG; ++g) {
             const int gl = w * NG + g;
             const int gx = x0 + 16 * (gl & 1) + vl, gy = y0 + (gl >> 1);
-            if (gx >= d.nx || gy >= d.ny) continue;
-            const size_t v = (size_t)gx + (size_t)d.nx * (size_t)(gy + d.ny * z);
+            const bool inside = gx < d.nx && gy < d.ny;
+            const size_t v = (size_t)min(gx, d.nx - 1) + (size_t)d.nx * (size_t)(min(gy, d.ny - 1) + d.ny * z);
+            if constexpr (PROJ) {
+                // lane holds channels 4 kg .. 4 kg + 3 of voxel vl; sum over the 4 lane groups
+                float pz = 0.f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pz = fmaf(wp[4 * kg + i], (float)(bf16)acc[g][0][i], pz);
+                pz += __shfl_xor(pz, 16);
+                pz += __shfl_xor(pz, 32);
+                if (inside && kg == 0) gz[v] = pz;
+            }
+            if (!inside || !out) continue;
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 if constexpr (sizeof(OUT) == 2) {
@@ -441,23 +433,31 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
     }
 }
 
+// Cell-centred trilinear interpolation (factor 2), per axis: parent I and
+// the neighbour J on the fine cell's side (clamped), weights 3/4 and 1/4.
+__device__ __forceinline__ void up_axis(int i, int nc, int& I, int& J) {
+    I = i >> 1;
+    J = (i & 1) ? min(I + 1, nc - 1) : max(I - 1, 0);
+}
+
 // Output of the network, fused with a recomputation of e0:
-//   i0(v) = bf16(e0(v) + g1(v / 2))            (0 outside the grid)
-//   y(v)[tap] = sum_c Wo[tap][c] i0(v)[c]      (MFMA 16x16x16, FP32)
-//   z(v) = out_scale * sum_tap y(v + tap)[tap] on the interior, 0 on the outer layer.
+//   e0(v) = bf16(conv(x; W0))                  (0 outside the grid)
+//   y(v)[tap] = sum_c Wo[tap][c] e0(v)[c]      (MFMA 16x16x16, FP32)
+//   z(v) = out_scale * (sum_tap y(v + tap)[tap] + up(gz)(v)) on the
+//          interior, 0 on the outer layer (gz: FP32 at 1/2 resolution).
 // A block owns an OT_X x OT_Y column of output voxels and marches up a z
 // segment.  Per plane q it stages x = bf16(in_scale r) of plane q + 1 in an
-// LDS ring (3 planes, halo 2), computes i0 and y on the haloed OT_X+2 x
+// LDS ring (3 planes, halo 2), computes e0 and y on the haloed OT_X+2 x
 // OT_Y+2 plane (16 groups of 16 voxels, 4 per wavefront) into LDS, and every
 // output thread adds the 9 in-plane taps of y(q) to its rolling sums for the
 // output planes q - 1, q, q + 1; plane q - 1 is then complete and stored.
-// x and g1 are loaded one plane ahead.  With keep != null, i0 of the
-// block's own voxels is stored (training).
+// x and the 8 gz values of the next output are loaded one plane ahead.  With
+// keep != null, e0 of the block's own voxels is stored (training).
 constexpr int OT_X = 30, OT_Y = 6, HT_X = 32, HT_Y = 8, RT_X = 34, RT_Y = 10, YS = 33;
 
 __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx, int nty,
                                                   int zchunk, const bf16* __restrict__ W0, const bf16* __restrict__ WoT,
-                                                  const bf16* __restrict__ g1, double* __restrict__ z,
+                                                  const float* __restrict__ gz, double* __restrict__ z,
                                                   bf16* __restrict__ keep) {
     constexpr int RN = RT_X * RT_Y;
     __shared__ float rs[3 * RN + 1];  // the last element is a constant 0
@@ -515,17 +515,6 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
         slot[t] = a;
         if (t + 256 < RN) slot[t + 256] = b;
     };
-    // g1 of the wavefront's 4 groups on plane q (validity applied at use)
-    auto gload = [&](int q, bf16x4* gv) {
-        const int qc = min(max(q, 0), d.nz - 1);
-#pragma unroll
-        for (int gi = 0; gi < 4; ++gi) {
-            const int hy = 2 * w + (gi >> 1), hx = 16 * (gi & 1) + vl;
-            const int gx = min(max(hx0 + hx, 0), d.nx - 1), gy = min(max(hy0 + hy, 0), d.ny - 1);
-            const size_t pi = ((size_t)((qc >> 1) * c.ny + (gy >> 1)) * c.nx + (gx >> 1)) * 16 + 4 * kg;
-            gv[gi] = *reinterpret_cast<const bf16x4*>(g1 + pi);
-        }
-    };
     double rv[2];
     bool rm[2];
     rload(zs - 2, 0, rv[0], rm[0]);
@@ -536,8 +525,6 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
     rstore(zs - 1, rv, rm);
     rload(zs, 0, rv[0], rm[0]);
     rload(zs, 1, rv[1], rm[1]);
-    bf16x4 gcur[4];
-    gload(zs - 1, gcur);
 
     const bool has_out = t < OT_X * OT_Y;
     const int oxl = t % OT_X, oyl = t / OT_X;
@@ -545,6 +532,25 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
     const bool out_in = has_out && gxo < d.nx && gyo < d.ny;
     const bool inner_xy = gxo >= 1 && gxo <= d.nx - 2 && gyo >= 1 && gyo <= d.ny - 2;
     const int ybase = ((oyl + 1) * HT_X + oxl + 1) * YS;
+    // the 8 gz values of this thread's output voxel on plane o (coordinates clamped)
+    const int gxo_c = min(gxo, d.nx - 1), gyo_c = min(gyo, d.ny - 1);
+    int Ix, Jx, Iy, Jy;
+    up_axis(gxo_c, c.nx, Ix, Jx);
+    up_axis(gyo_c, c.ny, Iy, Jy);
+    auto gzload = [&](int o, float* gv) {
+        int Iz, Jz;
+        up_axis(min(max(o, 0), d.nz - 1), c.nz, Iz, Jz);
+        const int zz[2] = {Iz, Jz}, yy[2] = {Iy, Jy}, xx[2] = {Ix, Jx};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    gv[4 * a + 2 * b + e] = gz[((size_t)zz[a] * c.ny + yy[b]) * c.nx + xx[e]];
+    };
+    float gzv[8];
+    gzload(zs, gzv);
     float a_prev = 0.f, a_cur = 0.f, a_next = 0.f;
     for (int q = zs - 1; q <= ze; ++q) {
         rstore(q + 1, rv, rm);
@@ -552,8 +558,6 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
             rload(q + 2, 0, rv[0], rm[0]);
             rload(q + 2, 1, rv[1], rm[1]);
         }
-        bf16x4 gnext[4];
-        gload(q + 1, gnext);
         kvs_tiling::lds_barrier();
         const int s0 = ((q - 1 - base) % 3) * RN, s1 = ((q - base) % 3) * RN, s2 = ((q + 1 - base) % 3) * RN;
         int ab[8];
@@ -570,7 +574,7 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
             const bool valid = qin && vxy[gi];
             bf16x4 iv;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) iv[i] = (bf16)((float)(bf16)e[i] + (float)gcur[gi][i]);
+            for (int i = 0; i < 4; ++i) iv[i] = (bf16)e[i];
             if (!valid) iv = bf16x4{};
             if (keep) {
                 const int hy = 2 * w + (gi >> 1), hx = 16 * (gi & 1) + vl;
@@ -588,8 +592,6 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
                 yr[16 + i] = y1[i];
             }
         }
-#pragma unroll
-        for (int gi = 0; gi < 4; ++gi) gcur[gi] = gnext[gi];
         kvs_tiling::lds_barrier();
         if (has_out) {
 #pragma unroll
@@ -603,9 +605,22 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
                     a_prev += yy[18 + tin];
                 }
             const int o = q - 1;
-            if (o >= zs && o < ze && out_in) {
-                const bool inner = inner_xy && o >= 1 && o <= d.nz - 2;
-                z[(size_t)o * sxy + (size_t)(gyo * d.nx + gxo)] = inner ? out_scale * (double)a_prev : 0.0;
+            if (o >= zs && o < ze) {
+                // coarse correction: trilinear weights 3/4, 1/4 per axis
+                float up = 0.f;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+                            up = fmaf((a ? 0.25f : 0.75f) * (b ? 0.25f : 0.75f) * (e ? 0.25f : 0.75f),
+                                      gzv[4 * a + 2 * b + e], up);
+                if (out_in) {
+                    const bool inner = inner_xy && o >= 1 && o <= d.nz - 2;
+                    z[(size_t)o * sxy + (size_t)(gyo * d.nx + gxo)] = inner ? out_scale * (double)(a_prev + up) : 0.0;
+                }
+                if (o + 1 < ze) gzload(o + 1, gzv);
             }
             a_prev = a_cur;
             a_cur = a_next;
@@ -642,18 +657,74 @@ __global__ void pool2(const bf16* __restrict__ fine, Dims d, bf16* __restrict__ 
     *reinterpret_cast<bf16x8*>(out + V * C + c8) = o;
 }
 
+// Skip input of a decoder level: out(v) = bf16(A(v) + up(B)(v)) with up the
+// cell-centred trilinear interpolation from the coarser grid (8 channels per
+// thread; the 8 coarse values summed in FP32).
+template <int C>
+__global__ __launch_bounds__(256) void skip_up_kernel(const bf16* __restrict__ A, const bf16* __restrict__ B, Dims d,
+                                                      bf16* __restrict__ out, const int* stop) {
+    if (stop && *stop) return;
+    const Dims c = coarse(d);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = t / (C / 8);
+    const int c8 = (int)(t % (C / 8)) * 8;
+    if (v >= d.n()) return;
+    const unsigned vu = (unsigned)v, row = vu / (unsigned)d.nx;
+    const int x = (int)(vu - row * (unsigned)d.nx), y = (int)(row % (unsigned)d.ny), z = (int)(row / (unsigned)d.ny);
+    int Ix, Jx, Iy, Jy, Iz, Jz;
+    up_axis(x, c.nx, Ix, Jx);
+    up_axis(y, c.ny, Iy, Jy);
+    up_axis(z, c.nz, Iz, Jz);
+    const int zz[2] = {Iz, Jz}, yy[2] = {Iy, Jy}, xx[2] = {Ix, Jx};
+    bf16x8 cv[8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                cv[4 * a + 2 * b + e] =
+                    *reinterpret_cast<const bf16x8*>(B + (((size_t)zz[a] * c.ny + yy[b]) * c.nx + xx[e]) * C + c8);
+    const bf16x8 a8 = *reinterpret_cast<const bf16x8*>(A + (size_t)v * C + c8);
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float u = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            u = fmaf(((q >> 2) ? 0.25f : 0.75f) * (((q >> 1) & 1) ? 0.25f : 0.75f) * ((q & 1) ? 0.25f : 0.75f),
+                     (float)cv[q][j], u);
+        o[j] = (bf16)((float)a8[j] + u);
+    }
+    *reinterpret_cast<bf16x8*>(out + (size_t)v * C + c8) = o;
+}
+
+hipError_t launch_skip_up(int ch, const bf16* A, const bf16* B, Dims d, bf16* out, hipStream_t s, const int* stop) {
+    const long long threads = d.n() * (ch / 8);
+    const int nb = (int)((threads + 255) / 256);
+    switch (ch) {
+        case 8: hipLaunchKernelGGL(skip_up_kernel<8>, dim3(nb), dim3(256), 0, s, A, B, d, out, stop); break;
+        case 16: hipLaunchKernelGGL(skip_up_kernel<16>, dim3(nb), dim3(256), 0, s, A, B, d, out, stop); break;
+        case 32: hipLaunchKernelGGL(skip_up_kernel<32>, dim3(nb), dim3(256), 0, s, A, B, d, out, stop); break;
+        case 64: hipLaunchKernelGGL(skip_up_kernel<64>, dim3(nb), dim3(256), 0, s, A, B, d, out, stop); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // rows of a z-march tile: LDS of about 50-60 KB per block for any CI
 constexpr int zm_rows(int ci) { return ci <= 16 ? 8 : (ci <= 32 ? 4 : 2); }
 
-template <int CI, int CO, bool SKIP, typename OUT>
-hipError_t launch_zm(const bf16* A, const bf16* B, Dims d, const bf16* W, OUT* out, hipStream_t s, const int* stop) {
+template <int CI, int CO, bool PROJ, typename OUT>
+hipError_t launch_zm(const bf16* A, Dims d, const bf16* W, OUT* out, const float* wp, float* gz, hipStream_t s,
+                     const int* stop) {
     constexpr int TY = zm_rows(CI);
-    auto kern = conv3_zm<CI, CO, TY, SKIP, OUT>;
+    auto kern = conv3_zm<CI, CO, TY, PROJ, OUT>;
     static const int cap = kvs_tiling::resident_blocks(kern, 256);
     const int ntx = (d.nx + 31) / 32, nty = (d.ny + TY - 1) / TY;
     const int zchunk = kvs_tiling::choose_kchunk(ntx * nty, d.nz, cap);
     const int nb = ntx * nty * ((d.nz + zchunk - 1) / zchunk);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, A, B, d, ntx, nty, zchunk, W, out, stop);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, A, d, ntx, nty, zchunk, W, out, wp, gz, stop);
     return hipGetLastError();
 }
 
@@ -661,21 +732,15 @@ hipError_t launch_zm(const bf16* A, const bf16* B, Dims d, const bf16* W, OUT* o
 // dilation 1 with up to 32 channels -> LDS z-march; dilated or 64-channel
 // layers (the 1/4-resolution bottleneck) -> gathering kernel
 template <typename OUT>
-hipError_t launch_conv(int ci, int co, const bf16* A, const bf16* B, Dims d, int dil, const bf16* W, OUT* out,
-                       hipStream_t s, const int* stop = nullptr) {
+hipError_t launch_conv(int ci, int co, const bf16* A, Dims d, int dil, const bf16* W, OUT* out, hipStream_t s,
+                       const int* stop = nullptr) {
 #define KVS_CONV_CASE(CI_, CO_)                                                                                \
     if (ci == CI_ && co == CO_) {                                                                              \
         if (dil == 1 && CI_ <= 32 && CO_ <= 32)                                                                \
-            return B ? launch_zm<CI_, CO_, true, OUT>(A, B, d, W, out, s, stop)                                \
-                     : launch_zm<CI_, CO_, false, OUT>(A, B, d, W, out, s, stop);                              \
+            return launch_zm<CI_, CO_, false, OUT>(A, d, W, out, nullptr, nullptr, s, stop);                   \
         constexpr int NV = conv_nv(CI_, CO_);                                                                  \
         const int nb = (int)((d.n() + 64 * NV - 1) / (64 * NV));                                               \
-        if (B)                                                                                                 \
-            hipLaunchKernelGGL((conv3_mfma<CI_, CO_, NV, true, OUT>), dim3(nb), dim3(256), 0, s, A, B, d, dil, W, \
-                               out, stop);                                                                     \
-        else                                                                                                   \
-            hipLaunchKernelGGL((conv3_mfma<CI_, CO_, NV, false, OUT>), dim3(nb), dim3(256), 0, s, A, B, d, dil,   \
-                               W, out, stop);                                                                  \
+        hipLaunchKernelGGL((conv3_mfma<CI_, CO_, NV, OUT>), dim3(nb), dim3(256), 0, s, A, d, dil, W, out, stop); \
         return hipGetLastError();                                                                              \
     }
     KVS_CONV_CASE(16, 32)
@@ -728,12 +793,12 @@ __global__ void f32_to_bf16(const float* __restrict__ a, bf16* __restrict__ b, l
 
 // Weight gradient of one conv: part[tap][blk][co * CI + ci] =
 //   sum over the block's voxels v of x(v + dil tap)[ci] * dy[v][co],
-// x(p) = bf16(A[p] + up(B)[p]) as the forward read it (or, FIRST, the
-// scaled FP64 input rounded to BF16); dy in FP32.  64 voxels are staged in
+// x(p) = A[p] as the forward read it (or, FIRST, the scaled FP64 input
+// rounded to BF16); dy in FP32.  64 voxels are staged in
 // LDS at a time; each thread owns a fixed set of (co, ci) pairs.
 template <int CI, int CO, bool FIRST>
-__global__ __launch_bounds__(256) void dw_partial(const bf16* __restrict__ A, const bf16* __restrict__ B,
-                                                  const double* __restrict__ r, double in_scale, Dims d, int dil,
+__global__ __launch_bounds__(256) void dw_partial(const bf16* __restrict__ A, const double* __restrict__ r,
+                                                  double in_scale, Dims d, int dil,
                                                   const float* __restrict__ dy, float* __restrict__ part) {
     constexpr int NP = CI * CO;
     constexpr int PER = (NP + 255) / 256;
@@ -742,7 +807,6 @@ __global__ __launch_bounds__(256) void dw_partial(const bf16* __restrict__ A, co
     const int tap = blockIdx.y;
     const int ox = dil * tap_dx(tap), oy = dil * tap_dy(tap), oz = dil * tap_dz(tap);
     const long long N = d.n();
-    const Dims dB = coarse(d);
     float acc[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) acc[q] = 0.f;
@@ -760,10 +824,6 @@ __global__ __launch_bounds__(256) void dw_partial(const bf16* __restrict__ A, co
                         val = (float)(bf16)(float)(in_scale * r[p]);
                     } else {
                         val = (float)A[p * CI + c];
-                        if (B) {
-                            val += (float)B[((x >> 1) + (long long)dB.nx * ((y >> 1) + (long long)dB.ny * (z >> 1))) * CI + c];
-                            val = (float)(bf16)val;
-                        }
                     }
                 }
             }
@@ -828,7 +888,15 @@ __global__ void out_backward(const float* __restrict__ dz, Dims d, const float* 
     for (int c = 0; c < CI; ++c) dg[v * CI + c] = acc[c];
 }
 
-// adjoint of nearest upsampling: dc[V][c] = sum over the children of df
+// weight of fine cell i in the interpolation of coarse cell V (one axis)
+__device__ __forceinline__ float up_weight(int i, int V, int nc) {
+    int I, J;
+    up_axis(i, nc, I, J);
+    return (I == V ? 0.75f : 0.f) + (J == V ? 0.25f : 0.f);
+}
+
+// adjoint of the trilinear interpolation: dc[V][c] = sum over the fine cells
+// 2V-1 .. 2V+2 (per axis) of their interpolation weight on V times df
 __global__ void up_adjoint(const float* __restrict__ df, Dims d, int C, float* __restrict__ dc) {
     const Dims cd = coarse(d);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -837,13 +905,58 @@ __global__ void up_adjoint(const float* __restrict__ df, Dims d, int C, float* _
     const int c = (int)(t % C);
     const int X = (int)(V % cd.nx), Y = (int)((V / cd.nx) % cd.ny), Z = (int)(V / ((long long)cd.nx * cd.ny));
     float s = 0.f;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                const int x = 2 * X + dx, y = 2 * Y + dy, z = 2 * Z + dz;
-                if (x < d.nx && y < d.ny && z < d.nz) s += df[(x + (long long)d.nx * (y + (long long)d.ny * z)) * C + c];
+    for (int z = 2 * Z - 1; z <= 2 * Z + 2; ++z) {
+        if (z < 0 || z >= d.nz) continue;
+        const float wz = up_weight(z, Z, cd.nz);
+        if (wz == 0.f) continue;
+        for (int y = 2 * Y - 1; y <= 2 * Y + 2; ++y) {
+            if (y < 0 || y >= d.ny) continue;
+            const float wy = up_weight(y, Y, cd.ny);
+            if (wy == 0.f) continue;
+            for (int x = 2 * X - 1; x <= 2 * X + 2; ++x) {
+                if (x < 0 || x >= d.nx) continue;
+                const float wx = up_weight(x, X, cd.nx);
+                if (wx == 0.f) continue;
+                s = fmaf(wz * wy * wx, df[(x + (long long)d.nx * (y + (long long)d.ny * z)) * C + c], s);
             }
+        }
+    }
     dc[t] = s;
+}
+
+// pointwise projection gz = g . wp (C channels): block partials of
+// sum_V g[V][c] dgz[V] for the weight gradient ...
+template <int C>
+__global__ __launch_bounds__(256) void proj_grad_partial(const bf16* __restrict__ g, const float* __restrict__ dgz,
+                                                         long long n, float* __restrict__ part) {
+    __shared__ float sh[256];
+    float acc = 0.f;
+    const int c = threadIdx.x % C;
+    for (long long v = (long long)blockIdx.x * (256 / C) + threadIdx.x / C; v < n; v += (long long)gridDim.x * (256 / C))
+        acc = fmaf((float)g[v * C + c], dgz[v], acc);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float s = 0.f;
+        for (int q = threadIdx.x; q < 256; q += C) s += sh[q];
+        part[(long long)blockIdx.x * C + threadIdx.x] = s;
+    }
+}
+
+__global__ void proj_grad_reduce(const float* __restrict__ part, int nblk, int C, float* __restrict__ grad,
+                                 int accumulate) {
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(long long)b * C + c];
+    grad[c] = accumulate ? grad[c] + s : s;
+}
+
+// ... and its adjoint dg[V][c] = wp[c] dgz[V]
+__global__ void proj_adjoint(const float* __restrict__ dgz, const float* __restrict__ wp, long long n, int C,
+                             float* __restrict__ dg) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n * C) dg[t] = wp[t % C] * dgz[t / C];
 }
 
 // adjoint of mean pooling, added: df[v][c] += dc[v/2][c] / (children of v/2)
@@ -960,19 +1073,20 @@ int nblocks256(long long n) { return (int)((n + 255) / 256); }
 // ---- network object ------------------------------------------------------------
 
 struct UnetLayerDesc {
-    int ci, co, dil, level;  // level of the output
-    bool skip_in;            // input = skip tensor + up(previous)
+    int ci, co, dil, level;  // dil 0: pointwise (one tap); level of the output
+    int taps() const { return dil > 0 ? 27 : 1; }
 };
 
 struct kvs_unet {
     int c0 = 16, c1 = 32, c2 = 64, nbott = 4;
-    std::vector<UnetLayerDesc> layers;  // 0 first, 1 enc1, 2.. bottleneck, dec1, dec0, out
+    std::vector<UnetLayerDesc> layers;  // 0 first, 1 enc1, 2.. bottleneck, dec1, projection, out
     std::vector<int64_t> w_off, wt_off;  // offsets of each layer's bf16 weights (forward, transposed)
     std::vector<int64_t> kp, kpt;        // padded K per layer (forward, transposed)
     std::vector<int64_t> m_off;          // offset of each layer in the flat master layout
     int64_t n_w = 0, n_wt = 0, n_master = 0;
     bf16* w = nullptr;       // device bf16 forward weights
     bf16* wt = nullptr;      // device bf16 transposed weights (for the backward pass)
+    float* w_proj = nullptr; // device fp32 (bf16-rounded) projection weights [C0]
     float* w_out = nullptr;  // device fp32 (bf16-rounded) output weights [27][C0] (backward pass)
     bf16* w_outT = nullptr;  // device bf16 output weights [32 taps][C0], taps >= 27 zero (forward MFMA)
     float* master = nullptr; // device fp32 master weights (flat)
@@ -981,18 +1095,19 @@ struct kvs_unet {
     float* adam_v = nullptr;
     int64_t adam_t = 0;
     std::vector<float> host_master;
-    // activations of the last grid: p0, e1, p1, bottleneck outputs, g1 (kept
-    // for the backward pass); i0 at full resolution only when a forward pass
-    // is asked to keep it (training)
+    // activations of the last grid: p0, e1, p1, bottleneck outputs, i1 (kept
+    // for the backward pass), gz; g1 (1/2 resolution) and e0 (full
+    // resolution) only when a forward pass is asked to keep them (training)
     Dims dims{0, 0, 0};
-    bf16 *p0 = nullptr, *e1 = nullptr, *p1 = nullptr, *g1 = nullptr;
+    bf16 *p0 = nullptr, *e1 = nullptr, *p1 = nullptr, *i1 = nullptr, *g1 = nullptr;
+    float* gz = nullptr;
     std::vector<bf16*> bott;
-    bf16* i0 = nullptr;
-    Dims i0_dims{0, 0, 0};
-    bool kept = false;  // the last forward pass stored i0 for this grid
+    bf16* e0k = nullptr;
+    Dims e0_dims{0, 0, 0};
+    bool kept = false;  // the last forward pass stored g1 and e0 for this grid
     // training buffers (allocated on first use)
     Dims tdims{0, 0, 0};
-    float *de0 = nullptr, *dp0 = nullptr, *dg1 = nullptr, *de1 = nullptr, *dp1 = nullptr;
+    float *de0 = nullptr, *dp0 = nullptr, *dg1 = nullptr, *de1 = nullptr, *dp1 = nullptr, *dgz = nullptr;
     std::vector<float*> dbott;  // gradient of each bottleneck output, and of its input p1 (last)
     bf16* gb = nullptr;         // bf16 staging of a gradient (conv^T input)
     float* dzf = nullptr;
@@ -1012,16 +1127,17 @@ void ufree(P*& p) {
 }
 
 void unet_free_acts(kvs_unet* u) {
-    for (bf16** p : {&u->p0, &u->e1, &u->p1, &u->g1, &u->i0}) ufree(*p);
+    for (bf16** p : {&u->p0, &u->e1, &u->p1, &u->i1, &u->g1, &u->e0k}) ufree(*p);
+    ufree(u->gz);
     for (bf16*& p : u->bott) ufree(p);
     u->bott.clear();
     u->dims = Dims{0, 0, 0};
-    u->i0_dims = Dims{0, 0, 0};
+    u->e0_dims = Dims{0, 0, 0};
     u->kept = false;
 }
 
 void unet_free_train(kvs_unet* u) {
-    for (float** p : {&u->de0, &u->dp0, &u->dg1, &u->de1, &u->dp1, &u->dzf}) ufree(*p);
+    for (float** p : {&u->de0, &u->dp0, &u->dg1, &u->de1, &u->dp1, &u->dgz, &u->dzf}) ufree(*p);
     for (float*& p : u->dbott) ufree(p);
     u->dbott.clear();
     ufree(u->gb);
@@ -1039,7 +1155,9 @@ hipError_t unet_ensure_acts(kvs_unet* u, Dims d) {
     const long long n1 = d1.n(), n2 = d2.n();
     hipError_t e = hipMalloc(&u->p0, sizeof(bf16) * n1 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->e1, sizeof(bf16) * n1 * u->c1);
+    if (e == hipSuccess) e = hipMalloc(&u->i1, sizeof(bf16) * n1 * u->c1);
     if (e == hipSuccess) e = hipMalloc(&u->g1, sizeof(bf16) * n1 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->gz, sizeof(float) * n1);
     if (e == hipSuccess) e = hipMalloc(&u->p1, sizeof(bf16) * n2 * u->c1);
     for (int q = 0; q < u->nbott && e == hipSuccess; ++q) {
         bf16* b = nullptr;
@@ -1054,13 +1172,13 @@ hipError_t unet_ensure_acts(kvs_unet* u, Dims d) {
     return hipSuccess;
 }
 
-// i0 at full resolution, for a forward pass that keeps it
-hipError_t unet_ensure_i0(kvs_unet* u, Dims d) {
-    if (u->i0 && u->i0_dims.nx == d.nx && u->i0_dims.ny == d.ny && u->i0_dims.nz == d.nz) return hipSuccess;
-    ufree(u->i0);
-    u->i0_dims = Dims{0, 0, 0};
-    hipError_t e = hipMalloc(&u->i0, sizeof(bf16) * d.n() * u->c0);
-    if (e == hipSuccess) u->i0_dims = d;
+// e0 at full resolution, for a forward pass that keeps it
+hipError_t unet_ensure_e0(kvs_unet* u, Dims d) {
+    if (u->e0k && u->e0_dims.nx == d.nx && u->e0_dims.ny == d.ny && u->e0_dims.nz == d.nz) return hipSuccess;
+    ufree(u->e0k);
+    u->e0_dims = Dims{0, 0, 0};
+    hipError_t e = hipMalloc(&u->e0k, sizeof(bf16) * d.n() * u->c0);
+    if (e == hipSuccess) u->e0_dims = d;
     return e;
 }
 
@@ -1072,6 +1190,7 @@ hipError_t unet_ensure_train(kvs_unet* u, Dims d) {
     hipError_t e = hipMalloc(&u->de0, sizeof(float) * n0 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->dp0, sizeof(float) * n1 * u->c0);
     if (e == hipSuccess) e = hipMalloc(&u->dg1, sizeof(float) * n1 * u->c0);
+    if (e == hipSuccess) e = hipMalloc(&u->dgz, sizeof(float) * n1);
     if (e == hipSuccess) e = hipMalloc(&u->de1, sizeof(float) * n1 * u->c1);
     if (e == hipSuccess) e = hipMalloc(&u->dp1, sizeof(float) * n2 * u->c1);
     for (int q = 0; q < u->nbott && e == hipSuccess; ++q) {
@@ -1095,25 +1214,27 @@ hipError_t launch_pool(int c, const bf16* fine, Dims d, bf16* out, hipStream_t s
 
 void build_layers(kvs_unet* u) {
     u->layers.clear();
-    u->layers.push_back({1, u->c0, 1, 0, false});      // e0
-    u->layers.push_back({u->c0, u->c1, 1, 1, false});  // e1 = conv(pool e0)
-    u->layers.push_back({u->c1, u->c2, 1, 2, false});  // bottleneck in
+    u->layers.push_back({1, u->c0, 1, 0});      // e0
+    u->layers.push_back({u->c0, u->c1, 1, 1});  // e1 = conv(pool e0)
+    u->layers.push_back({u->c1, u->c2, 1, 2});  // bottleneck in
     int dil = 2;
-    for (int q = 0; q < u->nbott - 2; ++q, dil *= 2) u->layers.push_back({u->c2, u->c2, dil, 2, false});
-    u->layers.push_back({u->c2, u->c1, 1, 2, false});  // bottleneck out
-    u->layers.push_back({u->c1, u->c0, 1, 1, true});   // g1 = conv(e1 + up b)
-    u->layers.push_back({u->c0, 1, 1, 0, true});       // z = conv(e0 + up g1)
+    for (int q = 0; q < u->nbott - 2; ++q, dil *= 2) u->layers.push_back({u->c2, u->c2, dil, 2});
+    u->layers.push_back({u->c2, u->c1, 1, 2});  // bottleneck out
+    u->layers.push_back({u->c1, u->c0, 1, 1});  // g1 = conv(e1 + up b)
+    u->layers.push_back({u->c0, 1, 0, 1});      // gz = g1 . wp
+    u->layers.push_back({u->c0, 1, 1, 0});      // z = conv(e0) + up(gz)
     u->w_off.clear();
     u->wt_off.clear();
     u->kp.clear();
     u->kpt.clear();
     u->m_off.clear();
     int64_t off = 0, offt = 0, offm = 0;
+    const size_t nconv = u->layers.size() - 2;  // 27-tap layers with MFMA weight layouts
     for (size_t l = 0; l < u->layers.size(); ++l) {
         const UnetLayerDesc& L = u->layers[l];
         u->m_off.push_back(offm);
-        offm += 27LL * L.ci * L.co;
-        if (l + 1 == u->layers.size()) break;
+        offm += (int64_t)L.taps() * L.ci * L.co;
+        if (l >= nconv) continue;
         const int64_t kp = L.ci == 1 ? 32 : (27 * L.ci + 31) / 32 * 32;
         const int64_t kpt = (27 * L.co + 31) / 32 * 32;
         u->w_off.push_back(off);
@@ -1131,38 +1252,40 @@ void build_layers(kvs_unet* u) {
 }  // namespace
 
 // Network application: z = out_scale * U(in_scale * r) (scales from ctl);
-// keep: also store i0 at full resolution for a backward pass.
+// keep: also store g1 (1/2 resolution) and e0 (full resolution) for a
+// backward pass.
 hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, double* z, Dims d, hipStream_t s,
                           bool keep = false) {
     if (d.n() >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit voxel indices in the kernels
     hipError_t e = unet_ensure_acts(u, d);
-    if (e == hipSuccess && keep) e = unet_ensure_i0(u, d);
+    if (e == hipSuccess && keep) e = unet_ensure_e0(u, d);
     if (e != hipSuccess) return e;
     u->kept = false;
     const Dims d1 = coarse(d), d2 = coarse(d1);
     const std::vector<UnetLayerDesc>& L = u->layers;
     const int nl = (int)L.size();
+    const int ld1 = nl - 3;
     const int* stop = ctl.stop;
     const OutLaunch fl = first_pool_launch(d);
     hipLaunchKernelGGL(first_pool_kernel, dim3(fl.nblocks), dim3(256), 0, s, r, ctl, d, fl.ntx, fl.nty, fl.zchunk,
                        u->w + u->w_off[0], u->p0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_conv(u->c0, u->c1, u->p0, (const bf16*)nullptr, d1, 1, u->w + u->w_off[1], u->e1, s, stop)) != hipSuccess)
-        return e;
+    if ((e = launch_conv(u->c0, u->c1, u->p0, d1, 1, u->w + u->w_off[1], u->e1, s, stop)) != hipSuccess) return e;
     if ((e = launch_pool(u->c1, u->e1, d1, u->p1, s, stop)) != hipSuccess) return e;
     const bf16* in = u->p1;
-    for (int l = 2; l <= nl - 3; ++l) {
+    for (int l = 2; l < ld1; ++l) {
         bf16* out = u->bott[(size_t)(l - 2)];
-        if ((e = launch_conv(L[l].ci, L[l].co, in, (const bf16*)nullptr, d2, L[l].dil, u->w + u->w_off[l], out, s,
-                             stop)) != hipSuccess)
+        if ((e = launch_conv(L[l].ci, L[l].co, in, d2, L[l].dil, u->w + u->w_off[l], out, s, stop)) != hipSuccess)
             return e;
         in = out;
     }
-    const int ld1 = nl - 2;
-    if ((e = launch_conv(u->c1, u->c0, u->e1, in, d1, 1, u->w + u->w_off[ld1], u->g1, s, stop)) != hipSuccess) return e;
+    if ((e = launch_skip_up(u->c1, u->e1, in, d1, u->i1, s, stop)) != hipSuccess) return e;
+    if ((e = launch_zm<32, 16, true, bf16>(u->i1, d1, u->w + u->w_off[ld1], keep ? u->g1 : nullptr, u->w_proj, u->gz,
+                                          s, stop)) != hipSuccess)
+        return e;
     const OutLaunch ol = out_launch(d);
     hipLaunchKernelGGL(out_kernel, dim3(ol.nblocks), dim3(256), 0, s, r, ctl, d, ol.ntx, ol.nty, ol.zchunk,
-                       u->w + u->w_off[0], u->w_outT, u->g1, z, keep ? u->i0 : nullptr);
+                       u->w + u->w_off[0], u->w_outT, u->gz, z, keep ? u->e0k : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     u->kept = keep;
     return hipSuccess;
@@ -1177,7 +1300,7 @@ hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const 
 namespace {
 
 // dispatch of the weight-gradient reduction
-hipError_t launch_dw(kvs_unet* u, int ci, int co, bool first, const bf16* A, const bf16* B, const double* r,
+hipError_t launch_dw(kvs_unet* u, int ci, int co, bool first, const bf16* A, const double* r,
                      double in_scale, Dims d, int dil, const float* dy, int64_t m_off, int accumulate, hipStream_t s) {
     const int nblk = (int)std::min<long long>(256, (d.n() + 63) / 64);
     const int64_t need = 27LL * nblk * ci * co;
@@ -1190,7 +1313,7 @@ hipError_t launch_dw(kvs_unet* u, int ci, int co, bool first, const bf16* A, con
     const dim3 grid(nblk, 27);
 #define KVS_DW_CASE(CI_, CO_, F_)                                                                                  \
     if (ci == CI_ && co == CO_ && first == F_) {                                                                   \
-        hipLaunchKernelGGL((dw_partial<CI_, CO_, F_>), grid, dim3(256), 0, s, A, B, r, in_scale, d, dil, dy, u->wpart); \
+        hipLaunchKernelGGL((dw_partial<CI_, CO_, F_>), grid, dim3(256), 0, s, A, r, in_scale, d, dil, dy, u->wpart); \
     } else
     KVS_DW_CASE(1, 16, true)
     KVS_DW_CASE(16, 32, false)
@@ -1222,50 +1345,58 @@ hipError_t unet_backward(kvs_unet* u, const double* r, double in_scale, Dims d, 
     const Dims d1 = coarse(d), d2 = coarse(d1);
     const std::vector<UnetLayerDesc>& L = u->layers;
     const int nl = (int)L.size();
-    const int lo = nl - 1, ld1 = nl - 2;
+    const int lo = nl - 1, lp = nl - 2, ld1 = nl - 3;
     const int c0 = u->c0, c1 = u->c1;
-    // output layer: z = conv(i0), i0 = e0 + up(g1)
-    if ((e = launch_dw(u, c0, 1, false, u->i0, nullptr, nullptr, 0.0, d, 1, u->dzf, u->m_off[lo], accumulate, s)) !=
-        hipSuccess)
+    // output: z = conv(e0; W_out) + up(gz)
+    if ((e = launch_dw(u, c0, 1, false, u->e0k, nullptr, 0.0, d, 1, u->dzf, u->m_off[lo], accumulate, s)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(out_backward<16>, dim3(nblocks256(d.n())), dim3(256), 0, s, u->dzf, d, u->w_out, u->de0);
-    hipLaunchKernelGGL(up_adjoint, dim3(nblocks256(d1.n() * c0)), dim3(256), 0, s, u->de0, d, c0, u->dg1);
-    // dec1: g1 = conv(e1 + up b_last)
-    const bf16* b_last = u->bott[(size_t)(u->nbott - 1)];
-    if ((e = launch_dw(u, c1, c0, false, u->e1, b_last, nullptr, 0.0, d1, 1, u->dg1, u->m_off[ld1], accumulate, s)) !=
+    hipLaunchKernelGGL(up_adjoint, dim3(nblocks256(d1.n())), dim3(256), 0, s, u->dzf, d, 1, u->dgz);
+    // projection gz = g1 . wp
+    {
+        const int nblk = (int)std::min<long long>(256, (d1.n() + 15) / 16);
+        if ((long long)nblk * c0 > u->wpart_n) {
+            ufree(u->wpart);
+            if ((e = hipMalloc(&u->wpart, sizeof(float) * nblk * c0)) != hipSuccess) return e;
+            u->wpart_n = (int64_t)nblk * c0;
+        }
+        hipLaunchKernelGGL(proj_grad_partial<16>, dim3(nblk), dim3(256), 0, s, u->g1, u->dgz, d1.n(), u->wpart);
+        hipLaunchKernelGGL(proj_grad_reduce, dim3(1), dim3(64), 0, s, u->wpart, nblk, c0, u->grad + u->m_off[lp],
+                           accumulate);
+        hipLaunchKernelGGL(proj_adjoint, dim3(nblocks256(d1.n() * c0)), dim3(256), 0, s, u->dgz, u->w_proj, d1.n(), c0,
+                           u->dg1);
+    }
+    // dec1: g1 = conv(i1), i1 = e1 + up(b_last)
+    if ((e = launch_dw(u, c1, c0, false, u->i1, nullptr, 0.0, d1, 1, u->dg1, u->m_off[ld1], accumulate, s)) !=
         hipSuccess)
         return e;
     if ((e = to_bf16(u->dg1, u->gb, d1.n() * c0, s)) != hipSuccess) return e;
-    if ((e = launch_conv(c0, c1, u->gb, (const bf16*)nullptr, d1, 1, u->wt + u->wt_off[ld1], u->de1, s)) != hipSuccess)
-        return e;
+    if ((e = launch_conv(c0, c1, u->gb, d1, 1, u->wt + u->wt_off[ld1], u->de1, s)) != hipSuccess) return e;
     float* dcur = u->dbott[(size_t)(u->nbott - 1)];  // gradient of the last bottleneck output (C1 channels)
     hipLaunchKernelGGL(up_adjoint, dim3(nblocks256(d2.n() * c1)), dim3(256), 0, s, u->de1, d1, c1, dcur);
     // bottleneck, last to first
-    for (int l = nl - 3; l >= 2; --l) {
+    for (int l = ld1 - 1; l >= 2; --l) {
         const int q = l - 2;
         const bf16* xin = q == 0 ? u->p1 : u->bott[(size_t)(q - 1)];
         float* dxin = q == 0 ? u->dp1 : u->dbott[(size_t)(q - 1)];
-        if ((e = launch_dw(u, L[l].ci, L[l].co, false, xin, nullptr, nullptr, 0.0, d2, L[l].dil, dcur, u->m_off[l],
-                           accumulate, s)) != hipSuccess)
+        if ((e = launch_dw(u, L[l].ci, L[l].co, false, xin, nullptr, 0.0, d2, L[l].dil, dcur, u->m_off[l], accumulate,
+                           s)) != hipSuccess)
             return e;
         if ((e = to_bf16(dcur, u->gb, d2.n() * L[l].co, s)) != hipSuccess) return e;
-        if ((e = launch_conv(L[l].co, L[l].ci, u->gb, (const bf16*)nullptr, d2, L[l].dil, u->wt + u->wt_off[l], dxin,
-                             s)) != hipSuccess)
+        if ((e = launch_conv(L[l].co, L[l].ci, u->gb, d2, L[l].dil, u->wt + u->wt_off[l], dxin, s)) != hipSuccess)
             return e;
         dcur = dxin;
     }
     // pool(e1) -> bottleneck input
     hipLaunchKernelGGL(pool_adjoint_add, dim3(nblocks256(d1.n() * c1)), dim3(256), 0, s, u->dp1, d1, c1, u->de1);
     // e1 = conv(pool e0)
-    if ((e = launch_dw(u, c0, c1, false, u->p0, nullptr, nullptr, 0.0, d1, 1, u->de1, u->m_off[1], accumulate, s)) !=
-        hipSuccess)
+    if ((e = launch_dw(u, c0, c1, false, u->p0, nullptr, 0.0, d1, 1, u->de1, u->m_off[1], accumulate, s)) != hipSuccess)
         return e;
     if ((e = to_bf16(u->de1, u->gb, d1.n() * c1, s)) != hipSuccess) return e;
-    if ((e = launch_conv(c1, c0, u->gb, (const bf16*)nullptr, d1, 1, u->wt + u->wt_off[1], u->dp0, s)) != hipSuccess)
-        return e;
+    if ((e = launch_conv(c1, c0, u->gb, d1, 1, u->wt + u->wt_off[1], u->dp0, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(pool_adjoint_add, dim3(nblocks256(d.n() * c0)), dim3(256), 0, s, u->dp0, d, c0, u->de0);
     // e0 = conv(in_scale r)
-    return launch_dw(u, 1, c0, true, nullptr, nullptr, r, in_scale, d, 1, u->de0, u->m_off[0], accumulate, s);
+    return launch_dw(u, 1, c0, true, nullptr, r, in_scale, d, 1, u->de0, u->m_off[0], accumulate, s);
 }
 
 }  // namespace
@@ -1303,7 +1434,7 @@ kvs_status ufail(kvs_unet* u, kvs_status s, const std::string& m) {
 kvs_status upload_weights(kvs_unet* u) {
     std::vector<bf16> wb((size_t)u->n_w, (bf16)0.f), wtb((size_t)std::max<int64_t>(u->n_wt, 1), (bf16)0.f);
     const int nl = (int)u->layers.size();
-    for (int l = 0; l < nl - 1; ++l) {
+    for (int l = 0; l < nl - 2; ++l) {
         const UnetLayerDesc& L = u->layers[(size_t)l];
         const float* m = u->host_master.data() + u->m_off[(size_t)l];
         const int64_t K = 27LL * L.ci, kp = u->kp[(size_t)l], kpt = u->kpt[(size_t)l];
@@ -1317,6 +1448,9 @@ kvs_status upload_weights(kvs_unet* u) {
                     wtb[(size_t)(u->wt_off[(size_t)l] + ci * kpt + tp * L.co + c)] =
                         (bf16)m[(int64_t)c * K + (26 - tp) * L.ci + ci];
     }
+    std::vector<float> wpj((size_t)u->c0);
+    const float* mp = u->host_master.data() + u->m_off[(size_t)(nl - 2)];
+    for (size_t q = 0; q < wpj.size(); ++q) wpj[q] = (float)(bf16)mp[q];
     std::vector<float> wo((size_t)27 * u->c0);
     std::vector<bf16> woT((size_t)32 * u->c0, (bf16)0.f);  // [tap][c], taps 27..31 zero
     const float* mo = u->host_master.data() + u->m_off[(size_t)(nl - 1)];
@@ -1326,6 +1460,7 @@ kvs_status upload_weights(kvs_unet* u) {
     }
     if (hipMemcpy(u->w, wb.data(), sizeof(bf16) * wb.size(), hipMemcpyHostToDevice) != hipSuccess ||
         (u->n_wt > 0 && hipMemcpy(u->wt, wtb.data(), sizeof(bf16) * u->n_wt, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(u->w_proj, wpj.data(), sizeof(float) * wpj.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->w_out, wo.data(), sizeof(float) * wo.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->w_outT, woT.data(), sizeof(bf16) * woT.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->master, u->host_master.data(), sizeof(float) * u->n_master, hipMemcpyHostToDevice) != hipSuccess)
@@ -1354,6 +1489,7 @@ kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_un
     u->host_master.assign((size_t)u->n_master, 0.f);
     bool ok = hipMalloc(&u->w, sizeof(bf16) * u->n_w) == hipSuccess;
     ok = ok && hipMalloc(&u->wt, sizeof(bf16) * std::max<int64_t>(u->n_wt, 1)) == hipSuccess;
+    ok = ok && hipMalloc(&u->w_proj, sizeof(float) * c0) == hipSuccess;
     ok = ok && hipMalloc(&u->w_out, sizeof(float) * 27 * c0) == hipSuccess;
     ok = ok && hipMalloc(&u->w_outT, sizeof(bf16) * 32 * c0) == hipSuccess;
     for (float** p : {&u->master, &u->grad, &u->adam_m, &u->adam_v})
@@ -1381,6 +1517,7 @@ void kvs_unet_destroy(kvs_unet* u) {
     unet_free_train(u);
     ufree(u->w);
     ufree(u->wt);
+    ufree(u->w_proj);
     ufree(u->w_out);
     ufree(u->w_outT);
     ufree(u->master);
@@ -1510,18 +1647,21 @@ kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16
     const Dims c = coarse(d);
     const size_t na = (size_t)d.n() * ci, nbb = B ? (size_t)c.n() * ci : 0, nw = (size_t)co * kvs_unet_conv_kpad(ci),
                  no = (size_t)d.n() * co;
-    bf16 *dA = nullptr, *dB = nullptr, *dW = nullptr, *dO = nullptr;
+    bf16 *dA = nullptr, *dB = nullptr, *dI = nullptr, *dW = nullptr, *dO = nullptr;
     hipError_t e = hipMalloc(&dA, 2 * na);
     if (e == hipSuccess && B) e = hipMalloc(&dB, 2 * nbb);
+    if (e == hipSuccess && B) e = hipMalloc(&dI, 2 * na);
     if (e == hipSuccess) e = hipMalloc(&dW, 2 * nw);
     if (e == hipSuccess) e = hipMalloc(&dO, 2 * no);
     if (e == hipSuccess) e = hipMemcpy(dA, A, 2 * na, hipMemcpyHostToDevice);
     if (e == hipSuccess && B) e = hipMemcpy(dB, B, 2 * nbb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dW, W, 2 * nw, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_conv(ci, co, dA, (const bf16*)dB, d, dil, dW, dO, nullptr);
+    // with a skip input: in = bf16(A + up(B)) first, then the convolution
+    if (e == hipSuccess && B) e = launch_skip_up(ci, dA, dB, d, dI, nullptr, nullptr);
+    if (e == hipSuccess) e = launch_conv(ci, co, B ? dI : dA, d, dil, dW, dO, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(out, dO, 2 * no, hipMemcpyDeviceToHost);
-    for (bf16* p : {dA, dB, dW, dO})
+    for (bf16* p : {dA, dB, dI, dW, dO})
         if (p) (void)hipFree(p);
     if (e != hipSuccess) return ufail(nullptr, KVS_EDEVICE, std::string("conv check: ") + hipGetErrorString(e));
     return KVS_OK;

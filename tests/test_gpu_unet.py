@@ -66,7 +66,8 @@ def test_network_forward_matches_oracle(kvs):
     try:
         n = kvs.kvs_unet_num_weights(net)
         shapes = unet.layer_shapes(16, 32, 64, 4)
-        w = np.concatenate([rng.standard_normal(27 * ci * co) / np.sqrt(27 * ci) for ci, co, _ in shapes])
+        w = np.concatenate([rng.standard_normal(unet.layer_size(ci, co, dl)) / np.sqrt(unet.layer_taps(dl) * ci)
+                        for ci, co, dl in shapes])
         assert w.size == n
         kvs.kvs_unet_set_weights(net, w.astype(np.float32))
         assert np.array_equal(kvs.kvs_unet_get_weights(net), w.astype(np.float32))
@@ -90,7 +91,8 @@ def test_network_forward_matches_oracle(kvs):
 
 def random_weights(rng, nbott=4, scale=1.0):
     shapes = unet.layer_shapes(16, 32, 64, nbott)
-    return np.concatenate([scale * rng.standard_normal(27 * ci * co) / np.sqrt(27 * ci) for ci, co, _ in shapes])
+    return np.concatenate([scale * rng.standard_normal(unet.layer_size(ci, co, dl)) / np.sqrt(unet.layer_taps(dl) * ci)
+                           for ci, co, dl in shapes])
 
 
 def test_backward_matches_oracle(kvs):
@@ -120,8 +122,8 @@ def test_backward_matches_oracle(kvs):
         kvs.kvs_unet_destroy(net)
     go = unet.backward(r, 0.8, w.astype(np.float64), dz, 1.5, nbott=4)
     off = 0
-    for li, (ci, co, _) in enumerate(unet.layer_shapes(16, 32, 64, 4)):
-        n = 27 * ci * co
+    for li, (ci, co, dl) in enumerate(unet.layer_shapes(16, 32, 64, 4)):
+        n = unet.layer_size(ci, co, dl)
         err = np.linalg.norm(g[off:off + n] - go[off:off + n]) / np.linalg.norm(go[off:off + n])
         say(f"layer {li} ({ci}->{co}): grad rel L2 {err:.2e}")
         assert err < 2e-2, (li, err)

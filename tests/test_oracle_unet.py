@@ -54,17 +54,31 @@ def test_pool_and_up_against_torch_and_hand_values():
     y = np.arange(3, dtype=float).reshape(1, 1, 3, 1)
     p = unet.pool(y)
     assert p.shape == (1, 1, 2, 1) and p[0, 0, 0, 0] == 0.5 and p[0, 0, 1, 0] == 2.0
-    c = rng.standard_normal((2, 3, 2, 2))
-    u = unet.up(c, (3, 5, 4))
-    assert u.shape == (3, 5, 4, 2) and np.array_equal(u[2, 4, 3], c[1, 2, 1]) and np.array_equal(u[0, 1, 0], c[0, 0, 0])
-    up_t = torch.nn.functional.interpolate(torch.from_numpy(c).permute(3, 0, 1, 2)[None], scale_factor=2, mode="nearest")
-    np.testing.assert_array_equal(unet.up(c, (4, 6, 4)), up_t[0].permute(1, 2, 3, 0).numpy())
+    # trilinear upsampling: torch's cell-centred trilinear interpolation at
+    # scale 2 (edges clamped), cropped to odd fine sizes
+    c = rng.standard_normal((3, 4, 5, 2))
+    ct = torch.from_numpy(c).permute(3, 0, 1, 2)[None].requires_grad_(True)
+    up_t = torch.nn.functional.interpolate(ct, scale_factor=2, mode="trilinear", align_corners=False)
+    full = up_t[0].permute(1, 2, 3, 0).detach().numpy()
+    np.testing.assert_allclose(unet.up(c, (6, 8, 10)), full, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(unet.up(c, (5, 7, 9)), full[:5, :7, :9], rtol=0, atol=1e-14)
+    # hand values in 1-D: interior cells 3/4 : 1/4, edge cells clamped
+    line = unet.up(np.array([0.0, 4.0, 8.0]).reshape(1, 1, 3, 1), (1, 1, 6))[0, 0, :, 0]
+    np.testing.assert_allclose(line, [0.0, 1.0, 3.0, 5.0, 7.0, 8.0])
+    # adjoint: torch's gradient of the same interpolation, and <P c, f> = <c, P^T f>
+    f = rng.standard_normal((6, 8, 10, 2))
+    up_t.backward(torch.from_numpy(f).permute(3, 0, 1, 2)[None])
+    np.testing.assert_allclose(unet.up_adjoint(f, (3, 4, 5)), ct.grad[0].permute(1, 2, 3, 0).numpy(), atol=1e-13)
+    f2 = rng.standard_normal((5, 7, 9, 2))
+    lhs = np.vdot(unet.up(c, (5, 7, 9)), f2)
+    rhs = np.vdot(c, unet.up_adjoint(f2, (3, 4, 5)))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
 
 
 def test_forward_is_linear_and_masked():
     rng = np.random.default_rng(4)
     shapes = unet.layer_shapes(16, 32, 64, 3)
-    n = sum(27 * ci * co for ci, co, _ in shapes)
+    n = sum(unet.layer_size(*sh) for sh in shapes)
     w = rng.standard_normal(n) * 0.05
     r = np.zeros((10, 12, 14))
     r[1:-1, 1:-1, 1:-1] = rng.standard_normal((8, 10, 12))
@@ -81,7 +95,8 @@ def test_backward_matches_finite_differences():
     rng = np.random.default_rng(11)
     nb = 3
     shapes = unet.layer_shapes(16, 32, 64, nb)
-    w = np.concatenate([rng.standard_normal(27 * ci * co) / np.sqrt(27 * ci) for ci, co, _ in shapes])
+    w = np.concatenate([rng.standard_normal(unet.layer_size(ci, co, dl)) / np.sqrt(unet.layer_taps(dl) * ci)
+                        for ci, co, dl in shapes])
     shp = (9, 10, 12)
     r = np.zeros(shp)
     r[1:-1, 1:-1, 1:-1] = rng.standard_normal((7, 8, 10))
@@ -102,8 +117,8 @@ def test_backward_matches_finite_differences():
         assert np.dot(g, d) == pytest.approx(fd, rel=1e-6)
     # one layer at a time L is linear in the perturbation: exact to rounding
     off = 0
-    for li, (ci, co, _) in enumerate(shapes):
-        n = 27 * ci * co
+    for li, (ci, co, dl) in enumerate(shapes):
+        n = unet.layer_size(ci, co, dl)
         d = np.zeros(w.size)
         d[off:off + n] = rng.standard_normal(n)
         fd = (L(w + 1e-3 * d) - L(w - 1e-3 * d)) / 2e-3
