@@ -281,6 +281,10 @@ const char* kvs_unet_last_error(const kvs_unet* net);
  * with k = tap * ci + c, tap = 9 (dz + 1) + 3 (dy + 1) + (dx + 1); the
  * pointwise projection is [1][ci]. */
 int64_t kvs_unet_num_weights(const kvs_unet* net);
+/* Layers in network order: input / output channels, dilation (0 for the
+ * pointwise projection) and taps (27 or 1) of layer l. */
+int32_t kvs_unet_num_layers(const kvs_unet* net);
+kvs_status kvs_unet_layer(const kvs_unet* net, int32_t l, int32_t* ci, int32_t* co, int32_t* dil, int32_t* taps);
 kvs_status kvs_unet_set_weights(kvs_unet* net, const float* w, int64_t n);
 kvs_status kvs_unet_get_weights(const kvs_unet* net, float* w, int64_t n);
 /* z = out_scale * U(in_scale * r) on an nx*ny*nz grid; r and z are FP64
@@ -307,15 +311,24 @@ kvs_status kvs_unet_train_sample(kvs_unet* net, const double* b, const double* x
 kvs_status kvs_unet_adam_step(kvs_unet* net, double lr, int32_t n_samples, void* stream);
 /* Training pair generated by the solver itself on context ctx (FP64, force
  * set): phi* = Jacobi-PCG solution of the current force to 1e-11; x = phi*
- * (k_snapshot = 0) or the CG error phi* - phi_k after k_snapshot iterations;
- * b = A x with ctx's spacing; both divided by rms(b) (returned in b_rms).
- * b, x: device fields of N doubles. */
-kvs_status kvs_unet_make_sample(kvs_ctx* ctx, int64_t k_snapshot, double* b, double* x, double* b_rms);
+ * (k_snapshot = 0) or the error phi* - phi_k after k_snapshot iterations of
+ * the solver with preconditioner `precond` (KVS_PC_JACOBI, or KVS_PC_UNET
+ * with ctx's network: the residuals the flexible PCG meets); b = A x with
+ * ctx's spacing (= the residual r_k); both divided by rms(b) (returned in
+ * b_rms).  b, x: device fields of N doubles. */
+kvs_status kvs_unet_make_sample(kvs_ctx* ctx, int64_t k_snapshot, int32_t precond, double* b, double* x,
+                                double* b_rms);
 /* Verification hook: one MFMA convolution on host BF16 bit patterns,
  * out[v][co] = sum_k W[co][k] x[p][c] with W rows padded to
  * kvs_unet_conv_kpad(ci) entries; x = A, or with B (the next coarser grid,
  * (n + 1) / 2 per axis) x = bf16(A + up(B)) as the decoder forms its skip
  * input.  Blocks. */
+/* Training pair from a given field: b = A x with A = -lap_1 (unit spacing)
+ * on the interior of an nx*ny*nz grid, then b and x divided by rms(b)
+ * (returned in b_rms).  x is read (and rescaled in place); b is written.
+ * Device FP64 fields ordered on `stream`.  Blocks. */
+kvs_status kvs_unet_sample_from_x(double* x, double* b, int64_t nx, int64_t ny, int64_t nz, double* b_rms,
+                                  void* stream);
 int64_t kvs_unet_conv_kpad(int32_t ci);
 kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16_t* A, const uint16_t* B, int64_t nx,
                                int64_t ny, int64_t nz, const uint16_t* W, uint16_t* out);

@@ -1531,6 +1531,18 @@ const char* kvs_unet_last_error(const kvs_unet* u) { return u ? u->err.c_str() :
 
 int64_t kvs_unet_num_weights(const kvs_unet* u) { return u ? u->n_master : 0; }
 
+int32_t kvs_unet_num_layers(const kvs_unet* u) { return u ? (int32_t)u->layers.size() : 0; }
+
+kvs_status kvs_unet_layer(const kvs_unet* u, int32_t l, int32_t* ci, int32_t* co, int32_t* dil, int32_t* taps) {
+    if (!u || l < 0 || l >= (int32_t)u->layers.size()) return KVS_EINVAL;
+    const UnetLayerDesc& L = u->layers[(size_t)l];
+    if (ci) *ci = L.ci;
+    if (co) *co = L.co;
+    if (dil) *dil = L.dil;
+    if (taps) *taps = L.taps();
+    return KVS_OK;
+}
+
 kvs_status kvs_unet_set_weights(kvs_unet* u, const float* w, int64_t n) {
     if (!u || !w) return KVS_EINVAL;
     if (n != u->n_master) return ufail(u, KVS_EINVAL, "wrong weight count");
@@ -1638,6 +1650,35 @@ kvs_status kvs_unet_adam_step(kvs_unet* u, double lr, int32_t n_samples, void* s
     return upload_weights(u);
 }
 
+kvs_status kvs_unet_sample_from_x(double* x, double* b, int64_t nx, int64_t ny, int64_t nz, double* b_rms,
+                                  void* stream) {
+    if (!x || !b || nx < 3 || ny < 3 || nz < 3) return ufail(nullptr, KVS_EINVAL, "bad arguments");
+    const Dims d = dims_of(nx, ny, nz);
+    if (d.n() >= (1LL << 31)) return ufail(nullptr, KVS_EINVAL, "grid too large");
+    hipStream_t s = (hipStream_t)stream;
+    const int nb = nblocks256(d.n());
+    double* part = nullptr;
+    hipError_t e = hipMalloc(&part, sizeof(double) * nb);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(apply_A_kernel, dim3(nb), dim3(256), 0, s, x, d, 1.0, 1.0, 1.0, b, part);
+        e = hipGetLastError();
+    }
+    std::vector<double> hp((size_t)nb);
+    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (part) (void)hipFree(part);
+    if (e != hipSuccess) return ufail(nullptr, KVS_EDEVICE, std::string("sample: ") + hipGetErrorString(e));
+    double bb = 0.0;
+    for (double v : hp) bb += v;
+    const double rms = std::sqrt(bb / ((double)(nx - 2) * (double)(ny - 2) * (double)(nz - 2)));
+    if (!(rms > 0.0)) return ufail(nullptr, KVS_EINVAL, "A x vanishes on the interior");
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, s, b, 1.0 / rms, d.n());
+    hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, s, x, 1.0 / rms, d.n());
+    if (hipStreamSynchronize(s) != hipSuccess) return ufail(nullptr, KVS_EDEVICE, "sample: scaling failed");
+    if (b_rms) *b_rms = rms;
+    return KVS_OK;
+}
+
 int64_t kvs_unet_conv_kpad(int32_t ci) { return ci == 1 ? 32 : (27 * (int64_t)ci + 31) / 32 * 32; }
 
 kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16_t* A, const uint16_t* B, int64_t nx,
@@ -1672,8 +1713,9 @@ kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16
 // k_snapshot > 0 the pair is the CG error after k iterations,
 // x = phi* - phi_k, else x = phi*; b = A x with the context's spacing; both
 // scaled so that b has unit RMS.  b, x: device fields of N doubles.
-kvs_status kvs_unet_make_sample(kvs_ctx* c, int64_t k_snapshot, double* b, double* x, double* b_rms) {
-    if (!c || !b || !x || k_snapshot < 0) return KVS_EINVAL;
+kvs_status kvs_unet_make_sample(kvs_ctx* c, int64_t k_snapshot, int32_t precond, double* b, double* x,
+                                double* b_rms) {
+    if (!c || !b || !x || k_snapshot < 0 || (precond != KVS_PC_JACOBI && precond != KVS_PC_UNET)) return KVS_EINVAL;
     const Dims d{(int)c->grid.nx, (int)c->grid.ny, (int)c->grid.nz};
     kvs_solve_opts o{};
     o.tol = 1e-11;
@@ -1686,6 +1728,7 @@ kvs_status kvs_unet_make_sample(kvs_ctx* c, int64_t k_snapshot, double* b, doubl
     hipError_t e = hipMemcpyAsync(x, c->phi, sizeof(double) * d.n(), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess && k_snapshot > 0) {
         o.fixed_iters = k_snapshot;
+        o.precond = (kvs_precond)precond;
         if (hipStreamSynchronize(s) != hipSuccess) return KVS_EDEVICE;
         st = kvs_project(c, &o, nullptr);
         if (st != KVS_OK) return st;

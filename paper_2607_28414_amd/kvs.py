@@ -113,7 +113,12 @@ SIGNATURES = {
     "kvs_unet_train_sample": ([_P, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
                                C.POINTER(C.c_double), C.c_void_p], C.c_int),
     "kvs_unet_adam_step": ([_P, C.c_double, C.c_int32, C.c_void_p], C.c_int),
-    "kvs_unet_make_sample": ([_P, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "kvs_unet_num_layers": ([_P], C.c_int32),
+    "kvs_unet_layer": ([_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                        C.POINTER(C.c_int32)], C.c_int),
+    "kvs_unet_sample_from_x": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.POINTER(C.c_double),
+                                C.c_void_p], C.c_int),
+    "kvs_unet_make_sample": ([_P, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "kvs_unet_conv_check": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint16), C.POINTER(C.c_uint16), C.c_int64,
                              C.c_int64, C.c_int64, C.POINTER(C.c_uint16), C.POINTER(C.c_uint16)], C.c_int),
     "kvs_batch_autotune": ([_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
@@ -478,9 +483,28 @@ def kvs_unet_adam_step(net, lr, n_samples=1, stream=None):
     _ucheck(lib().kvs_unet_adam_step(net, float(lr), int(n_samples), stream or None), net)
 
 
-def kvs_unet_make_sample(ctx, k_snapshot, b_ptr, x_ptr):
+def kvs_unet_layers(net):
+    """[(ci, co, dil, taps)] of every layer in network order."""
+    out = []
+    for l in range(lib().kvs_unet_num_layers(net)):
+        v = [C.c_int32() for _ in range(4)]
+        _ucheck(lib().kvs_unet_layer(net, l, *[C.byref(a) for a in v]), net)
+        out.append(tuple(a.value for a in v))
+    return out
+
+
+def kvs_unet_sample_from_x(x_ptr, b_ptr, dims, stream=None):
     rms = C.c_double()
-    _check(lib().kvs_unet_make_sample(ctx, int(k_snapshot), C.c_void_p(b_ptr), C.c_void_p(x_ptr), C.byref(rms)), ctx)
+    nx, ny, nz = dims
+    _ucheck(lib().kvs_unet_sample_from_x(C.c_void_p(x_ptr), C.c_void_p(b_ptr), int(nx), int(ny), int(nz),
+                                         C.byref(rms), stream or None), None)
+    return rms.value
+
+
+def kvs_unet_make_sample(ctx, k_snapshot, b_ptr, x_ptr, precond=KVS_PC_JACOBI):
+    rms = C.c_double()
+    _check(lib().kvs_unet_make_sample(ctx, int(k_snapshot), int(precond), C.c_void_p(b_ptr), C.c_void_p(x_ptr),
+                                      C.byref(rms)), ctx)
     return rms.value
 
 
