@@ -20,6 +20,10 @@ roofline: the FDTD step kernel, algorithmic bytes per interior cell-update
           (48 B of FP32 u, w read + written, 12 B of G, eta, dt^2/rho, and
           12 B of f_S on push steps) over its HIP-event-timed launches.
 cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
+projection_learned (default run, outside the timed region): projection time
+to 1e-8 of the learned flexible PCG vs Jacobi-PCG on the time-varying
+workload's 384 x 384 x 512 grid, after training the network by the committed
+recipe (training time reported separately).
 """
 from __future__ import annotations
 
@@ -64,6 +68,10 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=100)
     ap.add_argument("--step-variant", type=int, default=-1,
                     help="pin the step-kernel tile shape (default: autotune); used by the counter runs")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-preconditioner projection comparison")
+    ap.add_argument("--learned-epochs", type=int, default=4,
+                    help="projections of the time-varying workload timed per method")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -101,6 +109,80 @@ def copy_calibration(mib):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4}), flush=True)
+
+
+def learned_projection(args):
+    """Projection time to 1e-8, learned flexible PCG vs Jacobi-PCG, on the
+    time-varying workload's grid (384 x 384 x 512, h = 0.2 mm): the network
+    is trained first by the committed recipe (timed separately), then each
+    method projects the pushes of `learned_epochs` re-projection epochs
+    (moving focus, redrawn modulation phases) from phi = 0, and again
+    warm-started from the previous epoch's phi.  Times are HIP events around
+    divergence + solve + gradient subtraction."""
+    import numpy as np
+    import torch
+
+    from paper_2607_28414_amd import kvs, train
+    from workloads import focal_modulated_force
+
+    nx, ny, nz, h = 384, 384, 512, 0.2e-3
+    grid = (nx, ny, nz, h, h, h)
+    log("bench: training the preconditioner (64^3 unit grids, 2 rounds on its own residuals)")
+    net = kvs.kvs_unet_create((16, 32, 64), 4)
+    ctx = None
+    try:
+        tr = train.train_default(net, n=64, seed=0, rounds=2)
+        ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, stream=torch.cuda.current_stream().cuda_stream)
+        kvs.kvs_set_preconditioner(ctx, net)
+        res = {"jacobi": {"iters": [], "ms": []}, "fpcg": {"iters": [], "ms": [], "fallbacks": []},
+               "jacobi_warm": {"iters": [], "ms": []}, "fpcg_warm": {"iters": [], "ms": []}}
+        F_dev = None
+        for e in range(args.learned_epochs):
+            F = focal_modulated_force(grid, epoch=e)
+            F_dev = torch.from_numpy(F).to("cuda")
+            del F
+            for name, pc in (("jacobi", kvs.KVS_PC_JACOBI), ("fpcg", kvs.KVS_PC_UNET)):
+                kvs.kvs_set_force_device(ctx, F_dev.data_ptr(), 0)
+                rep = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=pc)
+                res[name]["iters"].append(rep["iters"])
+                res[name]["ms"].append(rep["ms"])
+                if pc == kvs.KVS_PC_UNET:
+                    res[name]["fallbacks"].append(kvs.kvs_last_fallbacks(ctx))
+                assert rep["relres_true"] < 1.2e-8, rep
+            log(f"bench: epoch {e}: jacobi {res['jacobi']['iters'][-1]} it {res['jacobi']['ms'][-1]:.0f} ms, "
+                f"fpcg {res['fpcg']['iters'][-1]} it {res['fpcg']['ms'][-1]:.0f} ms")
+        # warm-started: consecutive epochs, phi kept from the previous solve of the same method
+        for name, pc in (("jacobi_warm", kvs.KVS_PC_JACOBI), ("fpcg_warm", kvs.KVS_PC_UNET)):
+            for e in range(args.learned_epochs):
+                F_dev = torch.from_numpy(focal_modulated_force(grid, epoch=e)).to("cuda")
+                kvs.kvs_set_force_device(ctx, F_dev.data_ptr(), 0)
+                rep = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=pc, warm_start=e > 0)
+                if e > 0:
+                    res[name]["iters"].append(rep["iters"])
+                    res[name]["ms"].append(rep["ms"])
+    finally:
+        if ctx is not None:
+            kvs.kvs_destroy(ctx)
+        kvs.kvs_unet_destroy(net)
+    jm, fm = float(np.mean(res["jacobi"]["ms"])), float(np.mean(res["fpcg"]["ms"]))
+    out = {
+        "workload": f"{nx}x{ny}x{nz}, h 0.2 mm, focal push (1 mm / 4 mm) x random-phase modulation, focus moving "
+                    f"1 mm per 20 us, epochs 0-{args.learned_epochs - 1} (10 steps of 1.75 us each)",
+        "tol": 1e-8,
+        "jacobi_ms": jm, "fpcg_ms": fm, "speedup": jm / fm,
+        "jacobi_iters": res["jacobi"]["iters"], "fpcg_iters": res["fpcg"]["iters"],
+        "fpcg_fallbacks": res["fpcg"]["fallbacks"],
+        "warm_start": {"jacobi_ms": float(np.mean(res["jacobi_warm"]["ms"])) if res["jacobi_warm"]["ms"] else None,
+                       "fpcg_ms": float(np.mean(res["fpcg_warm"]["ms"])) if res["fpcg_warm"]["ms"] else None,
+                       "jacobi_iters": res["jacobi_warm"]["iters"], "fpcg_iters": res["fpcg_warm"]["iters"]},
+        "network": "3-level linear U-Net 16/32/64 channels, 4 bottleneck convs, BF16 MFMA, FP32 accumulation",
+        "train_seconds": tr.train_seconds,
+        "train_samples": len(tr.samples),
+    }
+    ws = out["warm_start"]
+    if ws["jacobi_ms"] and ws["fpcg_ms"]:
+        ws["speedup"] = ws["jacobi_ms"] / ws["fpcg_ms"]
+    return out
 
 
 def cpu_baseline(w, dt, smax, FS_host, nsteps):
@@ -344,6 +426,7 @@ def main():
         res["cpu_baseline"] = cpu_baseline(w, dt, smax, FS_host, args.cpu_sample_steps)
     else:
         res["cpu_baseline"] = None
+    res["projection_learned"] = None if args.no_learned else learned_projection(args)
     print(json.dumps(res), flush=True)
 
 

@@ -201,54 +201,39 @@ def test_untrained_network_falls_back_to_jacobi(kvs):
     assert fb == rf["iters"]
 
 
-def test_training_then_fpcg_converges(kvs):
-    """A short training on solver-generated samples (force divergences and
-    CG-error snapshots at unit spacing) lowers the A-norm loss, and the
-    flexible PCG with the trained network converges to 1e-8 on a physical
-    grid without Jacobi fallbacks; the final phi is judged by the FP64 true
-    residual."""
-    import torch
+def test_trained_network_beats_jacobi_pcg(kvs):
+    """Ablation: the network trained by the committed recipe (solver-generated
+    samples and one round on the flexible PCG's own residuals, 64^3 unit
+    grids) against the method without it, Jacobi-PCG, on a 256^3 grid
+    (h = 0.2 mm) with a focal push times a random-phase modulation: to
+    1e-8 in at least 8x fewer iterations and at least 1.5x less projection
+    time, no Jacobi fallback, and the final phi within 1e-8 by the oracle's
+    FP64 true residual."""
     import oracle
-    from workloads import gaussian_push
-    say("case short training + fpcg")
-    n = 40
+    from paper_2607_28414_amd import train
+    from workloads import focal_modulated_force
+    say("case ablation: trained network vs Jacobi-PCG")
     net = kvs.kvs_unet_create((16, 32, 64), 4)
-    rng = np.random.default_rng(9)
-    kvs.kvs_unet_set_weights(net, random_weights(rng, scale=0.3).astype(np.float32))
-    samples = []
-    for sidx in range(6):
-        ctx, _ = unit_ctx(kvs, n, 100 + sidx)
-        for k in (0, 8, 30):
-            b = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
-            x = torch.zeros_like(b)
-            kvs.kvs_unet_make_sample(ctx, k, b.data_ptr(), x.data_ptr())
-            samples.append((b, x))
-        kvs.kvs_destroy(ctx)
-    st = torch.cuda.current_stream().cuda_stream
-    losses = []
-    for it in range(80):
-        tot = 0.0
-        for q, (b, x) in enumerate(samples):
-            tot += kvs.kvs_unet_train_sample(net, b.data_ptr(), x.data_ptr(), (n, n, n), q > 0, st)
-        kvs.kvs_unet_adam_step(net, 2e-3, len(samples), st)
-        losses.append(tot / len(samples))
-    say(f"training loss {losses[0]:.3e} -> {losses[-1]:.3e}")
-    assert losses[-1] < 0.5 * losses[0]
-    h = 0.25e-3
-    grid = (64, 64, 64, h, h, h)
-    F = gaussian_push(grid, 1e-3, 3e-3, 1e4)
-    ctx = kvs.kvs_create(grid)
     try:
-        kvs.kvs_set_force(ctx, F)
-        rj = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_JACOBI)
-        kvs.kvs_set_preconditioner(ctx, net)
-        rf = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_UNET)
-        phi = kvs.kvs_get_phi(ctx, (64, 64, 64))
-        fb = kvs.kvs_last_fallbacks(ctx)
+        tr = train.train_default(net, n=64, seed=1, rounds=1)
+        n, h = 256, 0.2e-3
+        grid = (n, n, n, h, h, h)
+        F = focal_modulated_force(grid, seed=2024, epoch=0)
+        ctx = kvs.kvs_create(grid)
+        try:
+            kvs.kvs_set_force(ctx, F)
+            rj = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_JACOBI)
+            kvs.kvs_set_preconditioner(ctx, net)
+            rf = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_UNET)
+            fb = kvs.kvs_last_fallbacks(ctx)
+            phi = kvs.kvs_get_phi(ctx, (n, n, n))
+        finally:
+            kvs.kvs_destroy(ctx)
     finally:
-        kvs.kvs_destroy(ctx)
         kvs.kvs_unet_destroy(net)
-    say(f"jacobi {rj['iters']} it {rj['ms']:.1f} ms; fpcg {rf['iters']} it {rf['ms']:.1f} ms, fallbacks {fb}")
-    b = oracle.divergence(grid, F)
-    assert oracle.true_relres(grid, b, phi) < 2e-8
-    assert rf["status"] == 0 and rj["status"] == 0
+    say(f"training {tr.train_seconds:.1f} s; jacobi {rj['iters']} it {rj['ms']:.1f} ms; "
+        f"fpcg {rf['iters']} it {rf['ms']:.1f} ms, fallbacks {fb}")
+    assert rf["status"] == 0 and rj["status"] == 0 and fb == 0
+    assert oracle.true_relres(grid, oracle.divergence(grid, F), phi) < 1.2e-8
+    assert rf["iters"] * 8 <= rj["iters"]
+    assert rf["ms"] * 1.5 <= rj["ms"]

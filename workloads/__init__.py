@@ -169,3 +169,49 @@ def random_force(grid, rng, scale=1.0):
     """Smooth-ish random 3-component force for operator tests."""
     nx, ny, nz = grid[:3]
     return scale * rng.standard_normal((3, nz, ny, nx))
+
+
+def focal_focus_z(grid, epoch, dt, steps_per_epoch=10, speed=1e-3 / 20e-6):
+    """Axial focus of the moving push at the start of `epoch`: it travels at
+    `speed` (1 mm per 20 us) and bounces between 25 % and 75 % of the depth
+    (node coordinates), starting at 25 %."""
+    nz, h = grid[2], grid[5]
+    zmin, zmax = -(nz // 2) * h, (nz - 1 - nz // 2) * h
+    lo, hi = zmin + 0.25 * (zmax - zmin), zmin + 0.75 * (zmax - zmin)
+    L = hi - lo
+    s = (speed * epoch * steps_per_epoch * dt) % (2 * L)
+    return lo + (s if s <= L else 2 * L - s)
+
+
+def focal_modulated_force(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=10, sigma_l=1e-3, sigma_a=4e-3,
+                          F0=1e4):
+    """Non-separable push of the time-varying workload: F_z = F0 exp(-(x^2 +
+    y^2) / (2 sigma_l^2) - (z - z_f)^2 / (2 sigma_a^2)) M(x), with the focus
+    z_f of `focal_focus_z` and M(x) = 1 + 0.5 / sqrt(8) sum_m cos(k_m . x +
+    phi_m): 8 plane waves, |k_m| uniform in [2 pi / 4 mm, 2 pi / 1 mm] with
+    random directions (fixed by `seed`), phases phi_m redrawn every epoch
+    (seeded by (seed, epoch)).  F is set to 0 where the Gaussian factor is
+    below 1e-16.  Returns [3][nz][ny][nx] FP64."""
+    nx, ny, nz, hx, hy, hz = grid
+    rng = np.random.default_rng(seed)
+    kmag = rng.uniform(2 * np.pi / 4e-3, 2 * np.pi / 1e-3, 8)
+    dirs = rng.standard_normal((8, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    kvec = kmag[:, None] * dirs
+    phases = np.random.default_rng([seed, epoch]).uniform(0, 2 * np.pi, 8)
+    zf = focal_focus_z(grid, epoch, dt, steps_per_epoch)
+    x, y, z = coords(nx, hx), coords(ny, hy), coords(nz, hz)
+    cut = np.sqrt(2 * np.log(1e16))
+    ix = np.nonzero(np.abs(x) <= cut * sigma_l)[0]
+    iy = np.nonzero(np.abs(y) <= cut * sigma_l)[0]
+    iz = np.nonzero(np.abs(z - zf) <= cut * sigma_a)[0]
+    F = np.zeros((3, nz, ny, nx))
+    if ix.size == 0 or iy.size == 0 or iz.size == 0:
+        return F
+    Z, Y, X = np.meshgrid(z[iz], y[iy], x[ix], indexing="ij")
+    g = np.exp(-(X ** 2 + Y ** 2) / (2 * sigma_l ** 2) - (Z - zf) ** 2 / (2 * sigma_a ** 2))
+    M = np.ones_like(g)
+    for m in range(8):
+        M += 0.5 / np.sqrt(8) * np.cos(kvec[m, 0] * X + kvec[m, 1] * Y + kvec[m, 2] * Z + phases[m])
+    F[2][np.ix_(iz, iy, ix)] = F0 * g * M
+    return F
