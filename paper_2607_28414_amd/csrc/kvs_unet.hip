@@ -103,6 +103,37 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Di
     for (int g = 0; g < NV; ++g)
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // Fast path for wavefronts whose voxels all have their 27 (dilated) taps
+    // inside the grid (most of them): a tap is a constant element offset, no
+    // bounds logic per operand.  Taps >= 27 (K padding) have zero weights and
+    // read tap 26 instead.
+    bool deep = true;
+#pragma unroll
+    for (int g = 0; g < NV; ++g)
+        deep = deep && valid[g] && gx[g] >= dil && gx[g] < d.nx - dil && gy[g] >= dil && gy[g] < d.ny - dil &&
+               gz[g] >= dil && gz[g] < d.nz - dil;
+    if (__all(deep)) {
+        const bf16* base[NV];
+#pragma unroll
+        for (int g = 0; g < NV; ++g) base[g] = A + (size_t)(v0 + 16 * g + vl) * CI;
+        const int sy = d.nx, sz = d.nx * d.ny;
+#pragma unroll 2
+        for (int kc = 0; kc < KP / 32; ++kc) {
+            const int k0 = kc * 32 + 8 * kg;
+            const int tap = min(k0 / CI, 26), ci0 = k0 % CI;
+            const int off = dil * (tap_dx(tap) + sy * tap_dy(tap) + sz * tap_dz(tap)) * CI + ci0;
+            bf16x8 wf[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) wf[m] = *reinterpret_cast<const bf16x8*>(W + (long long)(16 * m + vl) * KP + k0);
+            bf16x8 a8[NV];
+#pragma unroll
+            for (int g = 0; g < NV; ++g) a8[g] = *reinterpret_cast<const bf16x8*>(base[g] + off);
+#pragma unroll
+            for (int g = 0; g < NV; ++g)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], a8[g], acc[g][m]);
+        }
+    } else {
 #pragma unroll 2
     for (int kc = 0; kc < KP / 32; ++kc) {
         const int k0 = kc * 32 + 8 * kg;
@@ -132,6 +163,7 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Di
 #pragma unroll
             for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], xb, acc[g][m]);
         }
+    }
     }
 #pragma unroll
     for (int g = 0; g < NV; ++g) {
@@ -453,7 +485,10 @@ __device__ __forceinline__ void up_axis(int i, int nc, int& I, int& J) {
 // output planes q - 1, q, q + 1; plane q - 1 is then complete and stored.
 // x and the 8 gz values of the next output are loaded one plane ahead.  With
 // keep != null, e0 of the block's own voxels is stored (training).
-constexpr int OT_X = 30, OT_Y = 6, HT_X = 32, HT_Y = 8, RT_X = 34, RT_Y = 10, YS = 33;
+constexpr int OT_X = 30, OT_Y = 6, HT_X = 32, HT_Y = 8, RT_X = 34, RT_Y = 10;
+// y tile, tap-major: ys[tap * YT + voxel]; YT = 4 (mod 32) makes the 64 lanes
+// of a store (16 voxels x 4 tap groups) hit each LDS bank exactly twice
+constexpr int YT = HT_X * HT_Y + 4;
 
 __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx, int nty,
                                                   int zchunk, const bf16* __restrict__ W0, const bf16* __restrict__ WoT,
@@ -461,7 +496,7 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
                                                   bf16* __restrict__ keep) {
     constexpr int RN = RT_X * RT_Y;
     __shared__ float rs[3 * RN + 1];  // the last element is a constant 0
-    __shared__ float ys[HT_Y * HT_X * YS];  // y of the haloed plane, 27 taps + 6 padding per voxel
+    __shared__ float ys[32 * YT];  // y of the haloed plane, 27 taps (+ 5 rows written by the padding taps)
     if (ctl.stop && *ctl.stop) return;
     const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
     const double out_scale = ctl.out_dev ? *ctl.out_dev : ctl.out_v;
@@ -492,7 +527,7 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
     // haloed voxels of the wavefront's 4 groups: gi -> row 2w + gi / 2, x 16 (gi % 2) + vl;
     // the group offsets are constants of the unrolled loops
     const int rbase = (2 * w + 1) * RT_X + vl + 1;  // r tile, group 0
-    const int ybw = (2 * w * HT_X + vl) * YS + 4 * kg;  // y tile, group 0, this lane's taps
+    const int ybw = 4 * kg * YT + 2 * w * HT_X + vl;  // y tile, group 0, this lane's first tap
     bool vxy[4];
 #pragma unroll
     for (int gi = 0; gi < 4; ++gi) {
@@ -531,7 +566,7 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
     const int gxo = ox0 + oxl, gyo = oy0 + oyl;
     const bool out_in = has_out && gxo < d.nx && gyo < d.ny;
     const bool inner_xy = gxo >= 1 && gxo <= d.nx - 2 && gyo >= 1 && gyo <= d.ny - 2;
-    const int ybase = ((oyl + 1) * HT_X + oxl + 1) * YS;
+    const int ybase = (oyl + 1) * HT_X + oxl + 1;
     // the 8 gz values of this thread's output voxel on plane o (coordinates clamped)
     const int gxo_c = min(gxo, d.nx - 1), gyo_c = min(gyo, d.ny - 1);
     int Ix, Jx, Iy, Jy;
@@ -584,12 +619,12 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
             }
             const f32x4 y0 = mfma16(wo0, iv, f32x4{0.f, 0.f, 0.f, 0.f});
             const f32x4 y1 = mfma16(wo1, iv, f32x4{0.f, 0.f, 0.f, 0.f});
-            // taps 4 kg + i and 16 + 4 kg + i; 27..31 land in the padding
-            float* yr = ys + ybw + ((gi >> 1) * HT_X + 16 * (gi & 1)) * YS;
+            // taps 4 kg + i and 16 + 4 kg + i; 27..31 land in rows no one reads
+            float* yr = ys + ybw + (gi >> 1) * HT_X + 16 * (gi & 1);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                yr[i] = y0[i];
-                yr[16 + i] = y1[i];
+                yr[i * YT] = y0[i];
+                yr[(16 + i) * YT] = y1[i];
             }
         }
         kvs_tiling::lds_barrier();
@@ -598,11 +633,11 @@ __global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, 
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
-                    const float* yy = ys + ybase + (dy * HT_X + dx) * YS;
+                    const float* yy = ys + ybase + dy * HT_X + dx;
                     const int tin = 3 * (dy + 1) + (dx + 1);
-                    a_next += yy[tin];
-                    a_cur += yy[9 + tin];
-                    a_prev += yy[18 + tin];
+                    a_next += yy[tin * YT];
+                    a_cur += yy[(9 + tin) * YT];
+                    a_prev += yy[(18 + tin) * YT];
                 }
             const int o = q - 1;
             if (o >= zs && o < ze) {

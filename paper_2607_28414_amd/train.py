@@ -134,19 +134,20 @@ def init_weights(net, rng, scale=0.3):
     kvs.kvs_unet_set_weights(net, w.astype(np.float32))
 
 
-def train_default(net, n=64, seed=0, rounds=2, lr=2e-3, log=None):
-    """The training recipe: base samples (6 forces with their potentials and
-    the errors after 20 and 60 Jacobi-PCG iterations, 4 white-noise fields),
-    200 Adam steps at learning rate lr; then `rounds` times: 6 more forces
-    with the errors after 3, 10 and 30 flexible-PCG iterations with the
-    current network, 120 steps at lr / 2.  Returns the Trainer (train_seconds: the
+def train_default(net, n=64, seed=0, rounds=2, lr=2e-3, forces=6, base_steps=200, round_steps=120, log=None):
+    """The training recipe: base samples (`forces` random forces with their
+    potentials and the errors after 20 and 60 Jacobi-PCG iterations, 4
+    white-noise fields), `base_steps` Adam steps at learning rate lr; then
+    `rounds` times: `forces` more forces with the errors after 3, 10 and 30
+    flexible-PCG iterations with the current network, `round_steps` steps at
+    lr / 2.  Returns the Trainer (train_seconds: the
     whole time, sample generation included)."""
     tr = Trainer(net, n=n, seed=seed)
     init_weights(net, tr.rng)
-    tr.add_force_samples(6, snapshots=(0, 20, 60))
+    tr.add_force_samples(forces, snapshots=(0, 20, 60))
     tr.add_white(4)
-    tr.fit(200, lr, log=log)
+    tr.fit(base_steps, lr, log=log)
     for _ in range(rounds):
-        tr.add_force_samples(6, snapshots=(3, 10, 30), precond=kvs.KVS_PC_UNET)
-        tr.fit(120, lr / 2, log=log)
+        tr.add_force_samples(forces, snapshots=(3, 10, 30), precond=kvs.KVS_PC_UNET)
+        tr.fit(round_steps, lr / 2, log=log)
     return tr
