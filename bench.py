@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["inclusions", "batch"], default="inclusions")
+    ap.add_argument("--workload", choices=["inclusions", "batch", "fpcg"], default="inclusions",
+                    help="fpcg: profiling aid, flexible-PCG iterations on the 384 x 384 x 512 grid")
     ap.add_argument("--grid", type=int, default=256, help="cubic grid edge of the inclusion workload")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--cpu-sample-steps", type=int, default=100)
@@ -183,6 +184,34 @@ def learned_projection(args):
     if ws["jacobi_ms"] and ws["fpcg_ms"]:
         ws["speedup"] = ws["jacobi_ms"] / ws["fpcg_ms"]
     return out
+
+
+def run_fpcg_profile(args):
+    """Profiling aid for the learned preconditioner's kernels: two flexible-
+    PCG solves of 10 fixed iterations on the 384 x 384 x 512 grid with the
+    time-varying workload's epoch-0 force and a network with random weights
+    (the kernels' work does not depend on the weights).  Not a benchmark
+    result: prints the solve times only."""
+    import numpy as np
+    import torch
+
+    from paper_2607_28414_amd import kvs, train
+    from workloads import focal_modulated_force
+
+    g = (384, 384, 512, 0.2e-3, 0.2e-3, 0.2e-3)
+    net = kvs.kvs_unet_create((16, 32, 64), 4)
+    ctx = None
+    try:
+        train.init_weights(net, np.random.default_rng(0))
+        ctx = kvs.kvs_create(g, precision=kvs.KVS_FP32, stream=torch.cuda.current_stream().cuda_stream)
+        kvs.kvs_set_force(ctx, focal_modulated_force(g, epoch=0))
+        kvs.kvs_set_preconditioner(ctx, net)
+        ms = [kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_UNET, fixed_iters=10)["ms"] for _ in range(2)]
+    finally:
+        if ctx is not None:
+            kvs.kvs_destroy(ctx)
+        kvs.kvs_unet_destroy(net)
+    return {"profiling_aid": "flexible PCG, 10 fixed iterations, 384x384x512, untrained network", "solve_ms": ms}
 
 
 def cpu_baseline(w, dt, smax, FS_host, nsteps):
@@ -310,6 +339,9 @@ def main():
         return
     if args.workload == "batch":
         print(json.dumps(run_batch(args)), flush=True)
+        return
+    if args.workload == "fpcg":
+        print(json.dumps(run_fpcg_profile(args)), flush=True)
         return
     import numpy as np
     import torch
