@@ -70,22 +70,33 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
 // out[v][co] = sum_{tap, ci} W[co][tap * CI + ci] * in(v + dil * tap)[ci],
 // in(p) = A[p][ci], zero outside the grid.
 // Each wavefront computes NV groups of 16 consecutive voxels for all CO
-// channels, so every weight fragment it loads feeds NV MFMAs.  Outputs are
-// rounded once (BF16) or stored as FP32.
+// channels.  The weights are staged in LDS in slabs of WS K-chunks (double
+// buffered through registers) and shared by the block's 4 wavefronts, so a
+// block reads them from L2 once; the activation taps are gathered per group
+// (constant offsets for wavefronts away from the boundary).  Outputs are
+// rounded once (BF16) or stored as FP32.  Every wavefront runs the slab loop
+// (its barriers) even when its voxels lie beyond the grid.
+constexpr int WS = 6;  // K chunks per weight slab
+
 template <int CI, int CO, int NV, typename OUT>
 __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Dims d,
                                                   int dil, const bf16* __restrict__ W, OUT* __restrict__ out,
                                                   const int* stop) {
     static_assert(CI % 8 == 0 && CO % 16 == 0, "channel counts");
-    if (stop && *stop) return;
     constexpr int K = 27 * CI;
     constexpr int KP = (K + 31) / 32 * 32;
+    constexpr int NC = KP / 32;
+    constexpr int NSL = (NC + WS - 1) / WS;
     constexpr int MT = CO / 16;
-    const int lane = threadIdx.x & 63;
+    constexpr int WROW = 32 * WS + 8;                 // bf16 per output row of a slab (padded)
+    constexpr int ITEMS = CO * 4 * WS;                // 16-byte items per slab
+    constexpr int IPT = (ITEMS + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 wsl[2][CO * WROW];
+    if (stop && *stop) return;
+    const int t = threadIdx.x, lane = t & 63;
     const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
-    const long long v0 = ((long long)blk * 4 + (threadIdx.x >> 6)) * (16 * NV);
+    const long long v0 = ((long long)blk * 4 + (t >> 6)) * (16 * NV);
     const long long N = d.n();
-    if (v0 >= N) return;
     const int vl = lane & 15, kg = lane >> 4;
     int gx[NV], gy[NV], gz[NV];
     bool valid[NV];
@@ -98,72 +109,94 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Di
         gy[g] = (int)(row % (unsigned)d.ny);
         gz[g] = (int)(row / (unsigned)d.ny);
     }
-    f32x4 acc[NV][MT];
-#pragma unroll
-    for (int g = 0; g < NV; ++g)
-#pragma unroll
-        for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // Fast path for wavefronts whose voxels all have their 27 (dilated) taps
-    // inside the grid (most of them): a tap is a constant element offset, no
-    // bounds logic per operand.  Taps >= 27 (K padding) have zero weights and
-    // read tap 26 instead.
     bool deep = true;
 #pragma unroll
     for (int g = 0; g < NV; ++g)
         deep = deep && valid[g] && gx[g] >= dil && gx[g] < d.nx - dil && gy[g] >= dil && gy[g] < d.ny - dil &&
                gz[g] >= dil && gz[g] < d.nz - dil;
-    if (__all(deep)) {
-        const bf16* base[NV];
+    const bool fast = __all(deep);
+    const bf16* base[NV];
 #pragma unroll
-        for (int g = 0; g < NV; ++g) base[g] = A + (size_t)(v0 + 16 * g + vl) * CI;
-        const int sy = d.nx, sz = d.nx * d.ny;
+    for (int g = 0; g < NV; ++g) base[g] = A + (size_t)(valid[g] ? v0 + 16 * g + vl : 0) * CI;
+    const int sy = d.nx, sz = d.nx * d.ny;
+
+    // weight slab staging: item -> (output row, 16-byte piece of the slab)
+    bf16x8 wreg[IPT];
+    auto wload = [&](int sl) {
+#pragma unroll
+        for (int h = 0; h < IPT; ++h) {
+            const int it = min(t + 256 * h, ITEMS - 1);
+            const int co = it / (4 * WS), q = it % (4 * WS);
+            const int kcol = min(32 * WS * sl + 8 * q, KP - 8);  // past the last chunk: any valid address
+            wreg[h] = *reinterpret_cast<const bf16x8*>(W + (size_t)co * KP + kcol);
+        }
+    };
+    auto wstore = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < IPT; ++h) {
+            const int it = t + 256 * h;
+            if (it >= ITEMS) break;
+            const int co = it / (4 * WS), q = it % (4 * WS);
+            *reinterpret_cast<bf16x8*>(&wsl[buf][co * WROW + 8 * q]) = wreg[h];
+        }
+    };
+
+    f32x4 acc[NV][MT];
+#pragma unroll
+    for (int g = 0; g < NV; ++g)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    wload(0);
+    wstore(0);
+    kvs_tiling::lds_barrier();
+    for (int sl = 0; sl < NSL; ++sl) {
+        const int buf = sl & 1;
+        if (sl + 1 < NSL) wload(sl + 1);
 #pragma unroll 2
-        for (int kc = 0; kc < KP / 32; ++kc) {
+        for (int kk = 0; kk < WS; ++kk) {
+            const int kc = sl * WS + kk;
+            if (kc >= NC) break;
             const int k0 = kc * 32 + 8 * kg;
-            const int tap = min(k0 / CI, 26), ci0 = k0 % CI;
-            const int off = dil * (tap_dx(tap) + sy * tap_dy(tap) + sz * tap_dz(tap)) * CI + ci0;
             bf16x8 wf[MT];
 #pragma unroll
-            for (int m = 0; m < MT; ++m) wf[m] = *reinterpret_cast<const bf16x8*>(W + (long long)(16 * m + vl) * KP + k0);
+            for (int m = 0; m < MT; ++m)
+                wf[m] = *reinterpret_cast<const bf16x8*>(&wsl[buf][(16 * m + vl) * WROW + 32 * kk + 8 * kg]);
             bf16x8 a8[NV];
+            if (fast) {
+                // taps >= 27 (K padding) have zero weights and read tap 26 instead
+                const int tap = min(k0 / CI, 26), ci0 = k0 % CI;
+                const int off = dil * (tap_dx(tap) + sy * tap_dy(tap) + sz * tap_dz(tap)) * CI + ci0;
 #pragma unroll
-            for (int g = 0; g < NV; ++g) a8[g] = *reinterpret_cast<const bf16x8*>(base[g] + off);
+                for (int g = 0; g < NV; ++g) a8[g] = *reinterpret_cast<const bf16x8*>(base[g] + off);
+            } else {
+                // unconditional loads from clamped addresses, masked after arrival
+                const int tap = k0 / CI, ci0 = k0 % CI;
+                const bool tap_ok = tap < 27;
+                const int ox = dil * tap_dx(tap), oy = dil * tap_dy(tap), oz = dil * tap_dz(tap);
+#pragma unroll
+                for (int g = 0; g < NV; ++g) {
+                    const int px = gx[g] + ox, py = gy[g] + oy, pz = gz[g] + oz;
+                    const bool ok = tap_ok && valid[g] && px >= 0 && px < d.nx && py >= 0 && py < d.ny && pz >= 0 &&
+                                    pz < d.nz;
+                    const int cx = min(max(px, 0), d.nx - 1), cy = min(max(py, 0), d.ny - 1),
+                              cz = min(max(pz, 0), d.nz - 1);
+                    const size_t p = (size_t)cx + (size_t)d.nx * (size_t)(cy + d.ny * cz);
+                    const bf16x8 v = *reinterpret_cast<const bf16x8*>(A + p * CI + ci0);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) a8[g][j] = ok ? v[j] : (bf16)0.f;
+                }
+            }
 #pragma unroll
             for (int g = 0; g < NV; ++g)
 #pragma unroll
                 for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], a8[g], acc[g][m]);
         }
-    } else {
-#pragma unroll 2
-    for (int kc = 0; kc < KP / 32; ++kc) {
-        const int k0 = kc * 32 + 8 * kg;
-        const int tap = k0 / CI, ci0 = k0 % CI;
-        const bool tap_ok = tap < 27;
-        const int ox = dil * tap_dx(tap), oy = dil * tap_dy(tap), oz = dil * tap_dz(tap);
-        bf16x8 wf[MT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) wf[m] = *reinterpret_cast<const bf16x8*>(W + (long long)(16 * m + vl) * KP + k0);
-        // operands of all groups: unconditional loads from clamped addresses,
-        // masked after arrival (no branch around a load)
-        bf16x8 a8[NV];
-        bool ok[NV];
-#pragma unroll
-        for (int g = 0; g < NV; ++g) {
-            const int px = gx[g] + ox, py = gy[g] + oy, pz = gz[g] + oz;
-            ok[g] = tap_ok && valid[g] && px >= 0 && px < d.nx && py >= 0 && py < d.ny && pz >= 0 && pz < d.nz;
-            const int cx = min(max(px, 0), d.nx - 1), cy = min(max(py, 0), d.ny - 1), cz = min(max(pz, 0), d.nz - 1);
-            const size_t p = (size_t)cx + (size_t)d.nx * (size_t)(cy + d.ny * cz);
-            a8[g] = *reinterpret_cast<const bf16x8*>(A + p * CI + ci0);
+        if (sl + 1 < NSL) {
+            kvs_tiling::lds_barrier();  // every wavefront is done with buffer buf ^ 1's old slab
+            wstore(buf ^ 1);
+            kvs_tiling::lds_barrier();
         }
-#pragma unroll
-        for (int g = 0; g < NV; ++g) {
-            bf16x8 xb;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) xb[j] = ok[g] ? a8[g][j] : (bf16)0.f;
-#pragma unroll
-            for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], xb, acc[g][m]);
-        }
-    }
     }
 #pragma unroll
     for (int g = 0; g < NV; ++g) {
