@@ -95,7 +95,8 @@ typedef struct {
 } kvs_opts;
 
 typedef struct {
-    double tol;          /* stop when sqrt(r.r / r0.r0) < tol (Sec. 3.2.3) */
+    double tol;          /* stop when sqrt(r.r / b.b) < tol: the relative residual of Sec. 3.2.3,
+                            whose r0 = b for phi_0 = 0, kept relative to b under a warm start */
     int64_t max_iter;    /* > 0 */
     int32_t precond;     /* kvs_precond: NONE = the paper's CG; JACOBI = z = r / diag(A); UNET = flexible
                             PCG with the network set by kvs_set_preconditioner */
@@ -105,7 +106,7 @@ typedef struct {
 
 typedef struct {
     int64_t iters;           /* phi updates performed */
-    double relres_recursive; /* sqrt(r.r / r0.r0) at exit */
+    double relres_recursive; /* sqrt(r.r / b.b) at exit, r the recursively updated residual */
     double relres_true;      /* ||-b - A phi|| / ||b|| recomputed from phi, FP64 */
     double ms;               /* wall time of divergence + solve + gradient subtraction */
     int32_t status;          /* kvs_status of the solve */
@@ -123,6 +124,8 @@ const char* kvs_status_string(kvs_status s);
 const char* kvs_last_error(const kvs_ctx* ctx);
 /* Block until all work queued on the context's stream is done. */
 kvs_status kvs_synchronize(kvs_ctx* ctx);
+/* The grid the context was created with (sizes and spacings). */
+kvs_status kvs_get_grid(const kvs_ctx* ctx, kvs_grid* out);
 /* The hipStream_t the context runs on. */
 void* kvs_stream(const kvs_ctx* ctx);
 
@@ -202,6 +205,23 @@ kvs_status kvs_set_state(kvs_ctx* ctx, const double* u, const double* w, int64_t
 /* Return the medium to rest (u = w = 0), reset the step index to 0 and clear
  * the traces; material, dt, force, projection and probes are kept. */
 kvs_status kvs_reset_state(kvs_ctx* ctx);
+
+/* Peak displacement maps (the |u| slices of the transcranial demonstration,
+ * Sec. 5.1): after every kvs_step step, each registered plane keeps the
+ * running maximum over steps of |u| = sqrt(ux^2 + uy^2 + uz^2) per cell, in
+ * the state precision (a NaN, once seen, stays).  axis[p] 0..2 fixes
+ * i (x), j (y) or k (z) at index[p] (0 <= index < the grid extent on that
+ * axis); at most KVS_MAX_PEAK_PLANES planes, no (axis, index) pair twice.
+ * Registering replaces every earlier plane and starts each map at |u| of the
+ * current state; n = 0 switches the maps off.  kvs_reset_state zeroes them;
+ * kvs_set_state keeps them.  Device memory: one map per plane, owned by the
+ * context. */
+#define KVS_MAX_PEAK_PLANES 8
+kvs_status kvs_set_peak_planes(kvs_ctx* ctx, const int32_t* axis, const int64_t* index, int32_t n);
+/* Copy the map of the registered plane (axis, index) into out (host):
+ * axis 0 -> [nz][ny], axis 1 -> [nz][nx], axis 2 -> [ny][nx], last extent
+ * fastest.  An unregistered plane is KVS_EINVAL.  Blocks. */
+kvs_status kvs_peak_map(const kvs_ctx* ctx, int32_t axis, int64_t index, double* out);
 
 /* ---- measurement -------------------------------------------------------- */
 

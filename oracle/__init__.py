@@ -210,3 +210,32 @@ def step_cells(grid, G, rho, eta, dt, u, w, cells, FS=None, gn=0.0, sponge_cells
     if st != OK:
         raise RuntimeError(f"ora_step_cells failed with status {st}")
     return uo, wo
+
+
+def plane_view(a, axis, index):
+    """Slice [..][nz][ny][nx] arrays on a grid plane: axis 0 -> [nz][ny],
+    axis 1 -> [nz][nx], axis 2 -> [ny][nx]."""
+    return {0: lambda: a[..., :, :, index], 1: lambda: a[..., :, index, :], 2: lambda: a[..., index, :, :]}[axis]()
+
+
+def peak_maps(grid, G, rho, eta, dt, nsteps, planes, FS=None, env=None, u=None, w=None, step0=0,
+              sponge_cells=0, sigma_max=0.0):
+    """Running peak of the displacement magnitude |u| on grid planes (the
+    |u| slices and peak displacement of the transcranial demonstration,
+    Sec. 5.1): the maps start at |u| of the given state and after every step
+    take the larger of themselves and |u^{n+1}|.  planes = [(axis, index)].
+    Returns (maps, u, w)."""
+    shp = _shape(grid)
+    u = np.zeros((3,) + shp) if u is None else _f64(u).copy()
+    w = np.zeros((3,) + shp) if w is None else _f64(w).copy()
+
+    def mag(a, axis, index):
+        v = plane_view(a, axis, index)
+        return np.sqrt(v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+
+    maps = [mag(u, a, i) for a, i in planes]
+    for n in range(int(nsteps)):
+        u, w, _ = run(grid, G, rho, eta, dt, 1, FS=FS, env=env, u=u, w=w, step0=step0 + n,
+                      sponge_cells=sponge_cells, sigma_max=sigma_max)
+        maps = [np.maximum(m, mag(u, a, i)) for m, (a, i) in zip(maps, planes)]
+    return maps, u, w

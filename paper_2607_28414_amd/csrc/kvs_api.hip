@@ -82,6 +82,7 @@ void release(kvs_ctx* c) {
     dfree(c->cgs);
     dfree(c->probe_cells);
     dfree(c->traces);
+    dfree(c->peak);
     if (c->cgs_host) (void)hipHostFree(c->cgs_host);
     c->cgs_host = nullptr;
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -338,6 +339,12 @@ kvs_status kvs_set_material_uniform(kvs_ctx* c, double G, double rho, double eta
     return KVS_OK;
 }
 
+kvs_status kvs_get_grid(const kvs_ctx* c, kvs_grid* out) {
+    if (!c || !out) return KVS_EINVAL;
+    *out = c->grid;
+    return KVS_OK;
+}
+
 kvs_status kvs_stable_dt(const kvs_ctx* cc, double* dt_max) {
     kvs_ctx* c = const_cast<kvs_ctx*>(cc);
     kvs_status s = need_material(c);
@@ -542,6 +549,7 @@ kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
             API_HIP(c, kvs_launch_probe_gather(c, c->u[c->cur], c->trace_steps));
             c->trace_steps += 1;
         }
+        if (c->npeak > 0) API_HIP(c, kvs_launch_peak_update(c, c->u[c->cur]));
         c->step += 1;
     }
     return KVS_OK;
@@ -629,6 +637,67 @@ kvs_status kvs_reset_state(kvs_ctx* c) {
     }
     c->step = 0;
     c->trace_steps = 0;
+    if (c->peak) API_HIP(c, hipMemsetAsync(c->peak, 0, (size_t)c->peak_cells * tsize(c), c->stream));
+    return KVS_OK;
+}
+
+kvs_status kvs_set_peak_planes(kvs_ctx* c, const int32_t* axis, const int64_t* index, int32_t n) {
+    if (!c) return KVS_EINVAL;
+    if (n < 0 || n > KVS_MAX_PEAK_PLANES) return fail(c, KVS_EINVAL, "peak planes: n must be 0..KVS_MAX_PEAK_PLANES");
+    if (n > 0 && (!axis || !index)) return fail(c, KVS_EINVAL, "peak planes: NULL axis or index");
+    const kvs_grid& g = c->grid;
+    const int64_t ext[3] = {g.nx, g.ny, g.nz};
+    int64_t off[KVS_MAX_PEAK_PLANES] = {}, total = 0;
+    for (int p = 0; p < n; ++p) {
+        if (axis[p] < 0 || axis[p] > 2) return fail(c, KVS_EINVAL, "peak planes: axis must be 0..2");
+        if (index[p] < 0 || index[p] >= ext[axis[p]])
+            return fail(c, KVS_EINVAL, "peak plane " + std::to_string(p) + " outside the grid");
+        for (int q = 0; q < p; ++q)
+            if (axis[q] == axis[p] && index[q] == index[p])
+                return fail(c, KVS_EINVAL, "peak planes: the same plane twice");
+        off[p] = total;
+        total += ext[axis[p] == 0 ? 1 : 0] * ext[axis[p] == 2 ? 1 : 2];
+    }
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    dfree(c->peak);
+    c->npeak = 0;
+    c->peak_cells = 0;
+    if (n == 0) return KVS_OK;
+    API_HIP(c, hipMalloc(&c->peak, (size_t)total * tsize(c)));
+    API_HIP(c, hipMemsetAsync(c->peak, 0, (size_t)total * tsize(c), c->stream));
+    for (int p = 0; p < n; ++p) {
+        c->peak_axis[p] = axis[p];
+        c->peak_index[p] = index[p];
+        c->peak_off[p] = off[p];
+    }
+    c->npeak = n;
+    c->peak_cells = total;
+    API_HIP(c, kvs_launch_peak_update(c, c->u[c->cur]));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    return KVS_OK;
+}
+
+kvs_status kvs_peak_map(const kvs_ctx* cc, int32_t axis, int64_t index, double* out) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    if (!out) return fail(c, KVS_EINVAL, "peak map: out is NULL");
+    int p = 0;
+    while (p < c->npeak && !(c->peak_axis[p] == axis && c->peak_index[p] == index)) ++p;
+    if (p == c->npeak) return fail(c, KVS_EINVAL, "peak map: plane not registered");
+    const int64_t cells = (p + 1 < c->npeak ? c->peak_off[p + 1] : c->peak_cells) - c->peak_off[p];
+    API_HIP(c, hipSetDevice(c->device));
+    if (c->prec == KVS_FP64) {
+        API_HIP(c, hipMemcpyAsync(out, static_cast<double*>(c->peak) + c->peak_off[p], sizeof(double) * cells,
+                                  hipMemcpyDeviceToHost, c->stream));
+        API_HIP(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp((size_t)cells);
+        API_HIP(c, hipMemcpyAsync(tmp.data(), static_cast<float*>(c->peak) + c->peak_off[p], sizeof(float) * cells,
+                                  hipMemcpyDeviceToHost, c->stream));
+        API_HIP(c, hipStreamSynchronize(c->stream));
+        for (int64_t q = 0; q < cells; ++q) out[q] = (double)tmp[(size_t)q];
+    }
     return KVS_OK;
 }
 

@@ -1,7 +1,7 @@
 // Helmholtz projection of the body force (Sec. 3.2) on gfx950, all in FP64:
 //   b = centred divergence of F on interior nodes,
 //   CG on A phi = -b, A = -lap_h (interior mask after every update, phi_0 = 0
-//   or a warm start, stop at sqrt(r.r / r0.r0) < tol, guards on p.Ap <= 0 and
+//   or a warm start, stop at sqrt(r.r / b.b) < tol, guards on p.Ap <= 0 and
 //   non-finite inner products: Sec. 3.2.3),
 //   f_S,a = (F_a(-a) + 2 F_a + F_a(+a))/4 - (phi(+a) - phi(-a))/(2 h_a).
 //
@@ -459,8 +459,8 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
         if (!isfinite(s1) || !isfinite(s3) || !isfinite(st->rz)) {
             st->status = KVS_EBREAKDOWN;
             st->done = 1;
-        } else if (s1 == 0.0) {
-            st->done = 1;
+        } else if (s1 == 0.0 || s3 == 0.0) {
+            st->done = 1;  // nothing to solve, or b = 0 (phi is set to 0 by the driver)
         } else if (st->fixed_iters <= 0 && !(1.0 >= sqrt(st->tol2))) {
             st->done = 1;  // tol > 1: the initial residual already satisfies the test
         }
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
             set_net_scales(s1);
             if (st->fixed_iters > 0) {
                 if (st->iters >= st->fixed_iters) st->done = 1;
-            } else if (sqrt(st->rr / st->rr0) < sqrt(st->tol2)) {
+            } else if (sqrt(st->rr / st->bb) < sqrt(st->tol2)) {
                 st->done = 1;
             } else if (st->iters >= st->max_iter) {
                 st->status = KVS_ENOTCONV;
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
         st->rr = s1;
         if (st->fixed_iters > 0) {
             if (st->iters >= st->fixed_iters) st->done = 1;
-        } else if (sqrt(st->rr / st->rr0) < sqrt(st->tol2)) {
+        } else if (sqrt(st->rr / st->bb) < sqrt(st->tol2)) {
             st->done = 1;
         } else if (st->iters >= st->max_iter) {
             st->status = KVS_ENOTCONV;
@@ -657,6 +657,8 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
         if (launched > cap) return fail(c, KVS_EDEVICE, "CG driver: iteration cap passed without a stop flag");
         chunk = std::min(chunk * 2, flexible ? 8 : 64);
     }
+    // b = 0 gives phi = 0, also when a warm start began from an earlier phi
+    if (warm && c->cgs_host->bb == 0.0) CG_HIP(hipMemsetAsync(c->phi, 0, sizeof(double) * c->N, c->stream));
     // Launches after the stop flag return at once; the host-side flip of pi
     // may then be off by those, which is harmless: the next solve starts with
     // beta = 0, which rebuilds the direction from r alone.
@@ -687,7 +689,7 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     c->last_fallbacks = s.fallbacks;
     if (rep) {
         rep->iters = s.iters;
-        rep->relres_recursive = s.rr0 > 0 ? std::sqrt(s.rr / s.rr0) : 0.0;
+        rep->relres_recursive = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
         rep->relres_true = std::sqrt(s.relres_true2);
         rep->ms = ms;
         rep->status = s.status;

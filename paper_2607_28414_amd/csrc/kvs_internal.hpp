@@ -17,7 +17,7 @@ struct CgState {
     double rr, rr0, rz;     // r.r, r0.r0, r.z
     double bb;              // ||b||^2
     double pAp, alpha, beta;
-    double tol2;            // tol^2 (compared with rr / rr0)
+    double tol2;            // tol^2 (compared with rr / bb)
     double relres_true2;    // ||-b - A phi||^2 / ||b||^2
     double net_in, net_out; // flexible PCG: network input / output scales
     double n_interior;      // interior cells (for the RMS of r)
@@ -103,6 +103,25 @@ struct kvs_ctx {
     int step_variant = 0;
     int step_zchunk = 0;
     int step_remap = 1;
+
+    // running peak of |u| on registered grid planes: one map of T per plane,
+    // concatenated in registration order (peak_off[p] = first cell of plane p)
+    int npeak = 0;
+    int peak_axis[KVS_MAX_PEAK_PLANES] = {};
+    int64_t peak_index[KVS_MAX_PEAK_PLANES] = {};
+    int64_t peak_off[KVS_MAX_PEAK_PLANES] = {};
+    int64_t peak_cells = 0;
+    void* peak = nullptr;
+};
+
+// Plane table handed to the peak kernel by value: axis, index along it, the
+// in-plane extents (n1 fastest) and the map offset of every plane.
+struct PeakPlanes {
+    int axis[KVS_MAX_PEAK_PLANES];
+    long long index[KVS_MAX_PEAK_PLANES];
+    long long n1[KVS_MAX_PEAK_PLANES];
+    long long n2[KVS_MAX_PEAK_PLANES];
+    long long off[KVS_MAX_PEAK_PLANES];
 };
 
 inline int ncomp_of(int comp) { return comp == 3 ? 3 : 1; }
@@ -149,6 +168,8 @@ hipError_t kvs_launch_step_variant(kvs_ctx* c, double gn, int variant);
 int kvs_step_variant_count();
 void kvs_step_variant_shape(int variant, int* by, int* vec);
 hipError_t kvs_launch_probe_gather(kvs_ctx* c, const void* u_new, int64_t slot);
+// Fold |u_new| into the running peak maps of the registered planes.
+hipError_t kvs_launch_peak_update(kvs_ctx* c, const void* u_new);
 hipError_t kvs_launch_crho(kvs_ctx* c);
 hipError_t kvs_launch_cast_material(kvs_ctx* c, const double* dG, const double* drho, const double* deta);
 hipError_t kvs_launch_cast(kvs_ctx* c, const double* src, void* dst, int64_t n);

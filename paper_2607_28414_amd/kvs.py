@@ -61,6 +61,7 @@ SIGNATURES = {
     "kvs_status_string": ([C.c_int], C.c_char_p),
     "kvs_last_error": ([_P], C.c_char_p),
     "kvs_synchronize": ([_P], C.c_int),
+    "kvs_get_grid": ([_P, C.POINTER(kvs_grid)], C.c_int),
     "kvs_stream": ([_P], C.c_void_p),
     "kvs_set_material": ([_P, _D, _D, _D], C.c_int),
     "kvs_set_material_uniform": ([_P, C.c_double, C.c_double, C.c_double], C.c_int),
@@ -84,6 +85,8 @@ SIGNATURES = {
     "kvs_get_state": ([_P, _D, _D, _I64], C.c_int),
     "kvs_set_state": ([_P, _D, _D, C.c_int64], C.c_int),
     "kvs_reset_state": ([_P], C.c_int),
+    "kvs_set_peak_planes": ([_P, C.POINTER(C.c_int32), _I64, C.c_int32], C.c_int),
+    "kvs_peak_map": ([_P, C.c_int32, C.c_int64, _D], C.c_int),
     "kvs_enable_kernel_timing": ([_P, C.c_int32], C.c_int),
     "kvs_num_step_variants": ([], C.c_int32),
     "kvs_batch_create": ([C.POINTER(kvs_grid), C.c_int32, C.POINTER(kvs_opts), C.POINTER(C.c_void_p)], C.c_int),
@@ -162,6 +165,36 @@ def _f64(a):
 
 # ---- thin wrappers with the C names ------------------------------------
 
+def kvs_get_grid(ctx):
+    g = kvs_grid()
+    _check(lib().kvs_get_grid(ctx, C.byref(g)), ctx)
+    return (g.nx, g.ny, g.nz, g.hx, g.hy, g.hz)
+
+
+def _cells(ctx):
+    nx, ny, nz = kvs_get_grid(ctx)[:3]
+    return nx * ny * nz
+
+
+def _host(ctx, a, ncomp, broadcast=False):
+    """FP64 C-contiguous copy of a host argument of ncomp * N values; a
+    number is broadcast when `broadcast`.  A wrong size raises before the
+    library reads the buffer."""
+    n = ncomp * _cells(ctx)
+    if broadcast and np.isscalar(a):
+        return np.full(n, float(a))
+    a = _f64(a)
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _out_shape(ctx, shape):
+    if int(np.prod(shape)) != _cells(ctx):
+        raise ValueError(f"shape {tuple(shape)} does not match the grid")
+    return tuple(shape)
+
+
 def kvs_create(grid, precision=KVS_FP64, sponge_cells=0, sponge_sigma_max=-1.0, device=0, stream=None):
     nx, ny, nz, hx, hy, hz = grid
     g = kvs_grid(int(nx), int(ny), int(nz), float(hx), float(hy), float(hz))
@@ -184,7 +217,8 @@ def kvs_stream(ctx):
 
 
 def kvs_set_material(ctx, G, rho, eta):
-    G, rho, eta = _f64(G), _f64(rho), _f64(eta)
+    """Arrays of N values each; a number stands for a uniform field."""
+    G, rho, eta = (_host(ctx, v, 1, broadcast=True) for v in (G, rho, eta))
     _check(lib().kvs_set_material(ctx, _dptr(G), _dptr(rho), _dptr(eta)), ctx)
 
 
@@ -209,7 +243,7 @@ def kvs_set_dt(ctx, dt):
 
 
 def kvs_set_force(ctx, F):
-    F = _f64(F)
+    F = _host(ctx, F, 3)
     _check(lib().kvs_set_force(ctx, _dptr(F)), ctx)
 
 
@@ -234,18 +268,18 @@ def kvs_project(ctx, tol=1e-8, max_iter=10000, precond=KVS_PC_JACOBI, fixed_iter
 
 
 def kvs_set_projected_force(ctx, FS):
-    FS = _f64(FS)
+    FS = _host(ctx, FS, 3)
     _check(lib().kvs_set_projected_force(ctx, _dptr(FS)), ctx)
 
 
 def kvs_get_projected_force(ctx, shape):
-    out = np.empty((3,) + tuple(shape))
+    out = np.empty((3,) + _out_shape(ctx, shape))
     _check(lib().kvs_get_projected_force(ctx, _dptr(out)), ctx)
     return out
 
 
 def kvs_get_phi(ctx, shape):
-    out = np.empty(tuple(shape))
+    out = np.empty(_out_shape(ctx, shape))
     _check(lib().kvs_get_phi(ctx, _dptr(out)), ctx)
     return out
 
@@ -279,7 +313,8 @@ def kvs_clear_traces(ctx):
 
 
 def kvs_get_state(ctx, shape):
-    u = np.empty((3,) + tuple(shape))
+    shape = _out_shape(ctx, shape)
+    u = np.empty((3,) + shape)
     w = np.empty((3,) + tuple(shape))
     step = C.c_int64()
     _check(lib().kvs_get_state(ctx, _dptr(u), _dptr(w), C.byref(step)), ctx)
@@ -287,12 +322,32 @@ def kvs_get_state(ctx, shape):
 
 
 def kvs_set_state(ctx, u, w, step):
-    u, w = _f64(u), _f64(w)
+    u, w = _host(ctx, u, 3), _host(ctx, w, 3)
     _check(lib().kvs_set_state(ctx, _dptr(u), _dptr(w), int(step)), ctx)
 
 
 def kvs_reset_state(ctx):
     _check(lib().kvs_reset_state(ctx), ctx)
+
+
+def kvs_set_peak_planes(ctx, planes):
+    """planes: sequence of (axis, index) pairs; [] switches the maps off."""
+    planes = list(planes)
+    ax = np.ascontiguousarray([p[0] for p in planes], dtype=np.int32)
+    ix = np.ascontiguousarray([p[1] for p in planes], dtype=np.int64)
+    n = len(planes)
+    _check(lib().kvs_set_peak_planes(ctx, ax.ctypes.data_as(C.POINTER(C.c_int32)) if n else None,
+                                     ix.ctypes.data_as(_I64) if n else None, n), ctx)
+
+
+def kvs_peak_map(ctx, axis, index, grid):
+    """Running peak of |u| on a registered plane of `grid` (nx, ny, nz, ...):
+    [nz][ny] for axis 0, [nz][nx] for axis 1, [ny][nx] for axis 2."""
+    nx, ny, nz = (int(v) for v in grid[:3])
+    shape = {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[int(axis)]
+    out = np.empty(shape)
+    _check(lib().kvs_peak_map(ctx, int(axis), int(index), _dptr(out)), ctx)
+    return out
 
 
 def kvs_enable_kernel_timing(ctx, on):

@@ -255,6 +255,36 @@ def test_error_paths(kvs):
         kvs.kvs_destroy(ctx)
 
 
+def test_warm_start_stops_relative_to_b(kvs):
+    """A warm start from a poor phi (the potential of -F / 3, so r0 = 4/3 b)
+    still stops at ||r|| < tol ||b||: recursive and true residuals agree and
+    stay within tol, and f_S matches the oracle's tight cold solve.  b = 0
+    under a warm start gives phi = 0 and f_S = 0 without an iteration."""
+    say("case warm start")
+    grid = (40, 36, 44, 0.25e-3, 0.25e-3, 0.25e-3)
+    shp = (44, 36, 40)
+    F = gaussian_push(grid, 1e-3, 2e-3, 1e4) + 20.0 * np.random.default_rng(7).standard_normal((3,) + shp)
+    FS_o, _, _ = oracle.project(grid, F, tol=1e-13)
+    for pc in (kvs.KVS_PC_NONE, kvs.KVS_PC_JACOBI):
+        ctx = kvs.kvs_create(grid)
+        try:
+            kvs.kvs_set_force(ctx, -F / 3.0)
+            kvs.kvs_project(ctx, tol=1e-12, precond=pc)
+            kvs.kvs_set_force(ctx, F)
+            rep = kvs.kvs_project(ctx, tol=1e-8, precond=pc, warm_start=True)
+            FS = kvs.kvs_get_projected_force(ctx, shp)
+            kvs.kvs_set_force(ctx, np.zeros((3,) + shp))
+            rep0 = kvs.kvs_project(ctx, tol=1e-8, precond=pc, warm_start=True)
+            phi0 = kvs.kvs_get_phi(ctx, shp)
+            FS0 = kvs.kvs_get_projected_force(ctx, shp)
+        finally:
+            kvs.kvs_destroy(ctx)
+        assert rep["relres_recursive"] < 1e-8 and rep["relres_true"] < 1.001e-8
+        assert abs(rep["relres_true"] - rep["relres_recursive"]) < 1e-3 * rep["relres_true"]
+        assert rel_l2(FS, FS_o) < 1e-7
+        assert rep0["iters"] == 0 and not phi0.any() and not FS0.any()
+
+
 def test_cfg2_full_size_sampled_parity(kvs):
     """256^3 inclusion workload in the benchmark's launch configuration:
     projection judged by the FP64 true residual and by the oracle's
@@ -357,3 +387,76 @@ def test_autotune_keeps_state_and_picks_a_variant(kvs):
         kvs.kvs_destroy(ctx)
     assert 0 <= best < len(ms) and np.all(ms > 0) and ms[best] == ms.min()
     assert s0 == s1 == 7 and np.array_equal(u0, u1) and np.array_equal(w0, w1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_peak_maps_match_oracle(kvs, precision):
+    """Running peak of |u| on four planes (one of them the Dirichlet layer)
+    of a heterogeneous viscous run with sponge and a push switched off part
+    way: FP64 maps to 1e-12 of the peak, FP32 maps to 2e-5 relative L2."""
+    say(f"case peak maps precision {precision}")
+    grid, G, rho, eta, F = hetero_case((37, 29, 41), 31)
+    L, nsteps = 4, 60
+    smax = oracle.default_sigma_max(grid, G, rho, L)
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    env = np.ones(12)
+    planes = [(0, 18), (1, 3), (2, 20), (2, 40)]
+    FS_o, _, _ = oracle.project(grid, F, tol=1e-12)
+    maps_o, _, _ = oracle.peak_maps(grid, G, rho, eta, dt, nsteps, planes, FS=FS_o, env=env, sponge_cells=L,
+                                    sigma_max=smax)
+    ctx = kvs.kvs_create(grid, precision=precision, sponge_cells=L, sponge_sigma_max=smax)
+    try:
+        kvs.kvs_set_material(ctx, G, rho, eta)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_projected_force(ctx, FS_o)
+        kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_set_peak_planes(ctx, planes)
+        kvs.kvs_step(ctx, nsteps)
+        maps = [kvs.kvs_peak_map(ctx, a, i, grid) for a, i in planes]
+        # re-registering starts from |u| of the current state
+        u, _, _ = kvs.kvs_get_state(ctx, (41, 29, 37))
+        kvs.kvs_set_peak_planes(ctx, [(1, 14)])
+        m_now = kvs.kvs_peak_map(ctx, 1, 14, grid)
+        kvs.kvs_reset_state(ctx)
+        m_rest = kvs.kvs_peak_map(ctx, 1, 14, grid)
+        with pytest.raises(kvs.KvsError):
+            kvs.kvs_peak_map(ctx, 0, 18, grid)
+    finally:
+        kvs.kvs_destroy(ctx)
+    for (a, i), m, mo in zip(planes, maps, maps_o):
+        if i == 40:
+            assert not m.any() and not mo.any()
+            continue
+        assert mo.max() > 0
+        if precision == 0:
+            assert np.max(np.abs(m - mo)) <= 1e-12 * mo.max(), (a, i)
+        else:
+            assert rel_l2(m, mo) < 2e-5, (a, i, rel_l2(m, mo))
+    ref_now = np.sqrt((u[:, :, 14, :] ** 2).sum(axis=0))
+    np.testing.assert_allclose(m_now, ref_now, rtol=1e-6 if precision else 1e-14, atol=0)
+    assert not m_rest.any()
+
+
+def test_peak_plane_and_buffer_errors(kvs):
+    say("case peak plane and buffer errors")
+    grid = (9, 10, 11, 1e-3, 1e-3, 1e-3)
+    ctx = kvs.kvs_create(grid)
+    try:
+        kvs.kvs_set_material_uniform(ctx, 1e3, 1000.0, 0.0)
+        # the binding checks host buffer sizes against the grid before the call
+        with pytest.raises(ValueError):
+            kvs.kvs_set_material(ctx, np.ones(5), 1000.0, 0.0)
+        with pytest.raises(ValueError):
+            kvs.kvs_set_force(ctx, np.ones((3, 11, 10, 8)))
+        assert kvs.kvs_get_grid(ctx) == grid
+        for bad in ([(3, 0)], [(0, 9)], [(2, -1)], [(1, 2), (1, 2)], [(0, i) for i in range(9)]):
+            with pytest.raises(kvs.KvsError) as e:
+                kvs.kvs_set_peak_planes(ctx, bad)
+            assert e.value.status == kvs.KVS_EINVAL
+        kvs.kvs_set_peak_planes(ctx, [(0, 8), (1, 9), (2, 10)])
+        assert kvs.kvs_peak_map(ctx, 2, 10, grid).shape == (10, 9)
+        kvs.kvs_set_peak_planes(ctx, [])
+        with pytest.raises(kvs.KvsError):
+            kvs.kvs_peak_map(ctx, 2, 10, grid)
+    finally:
+        kvs.kvs_destroy(ctx)

@@ -543,3 +543,77 @@ def test_mode_recurrence_matches_discrete_dispersion():
     zz = np.exp(-1j * w * dt)
     K2b = (rho / dt ** 2) * (2 - zz - 1 / zz) / (G + (eta / dt) * (1 - 1 / zz))
     assert K2b == pytest.approx(K2, rel=1e-9)
+
+
+def _small_push_case(shape, seed):
+    from workloads import gaussian_push, spherical_inclusions
+    nx, ny, nz = shape
+    h = 0.25e-3
+    grid = (nx, ny, nz, h, h * 1.1, h * 0.9)
+    rng = np.random.default_rng(seed)
+    G, rho, eta, _ = spherical_inclusions(grid, rng, 3, (2e3, 1000.0, 0.5), (0.5e-3, 1e-3),
+                                          (1e3, 1e4), (1000.0, 1100.0), (0.0, 1.5), 2)
+    F = gaussian_push(grid, 0.5e-3, 1e-3, 1e4) + 50.0 * rng.standard_normal((3, nz, ny, nx))
+    return grid, G, rho, eta, F
+
+
+def test_peak_maps_equal_the_running_max_of_probe_traces():
+    """The peak map of a plane is the largest |u| over the recorded states at
+    every cell of the plane: rebuilt from all-component probe traces (the
+    oracle's C sensor path, not the plane slicing) on three orthogonal planes
+    of a heterogeneous viscous run with a sponge and a force switched off
+    part way."""
+    grid, G, rho, eta, F = _small_push_case((11, 9, 13), 5)
+    nx, ny, nz = grid[:3]
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    FS, _, _ = oracle.project(grid, F, tol=1e-12)
+    env = np.ones(7)
+    planes = [(0, 4), (1, 6), (2, 3)]
+    maps, u_end, _ = oracle.peak_maps(grid, G, rho, eta, dt, 30, planes, FS=FS, env=env, sponge_cells=2,
+                                      sigma_max=3e3)
+    for (axis, index), m in zip(planes, maps):
+        if axis == 0:
+            cells = [(index, j, k) for k in range(nz) for j in range(ny)]
+        elif axis == 1:
+            cells = [(i, index, k) for k in range(nz) for i in range(nx)]
+        else:
+            cells = [(i, j, index) for j in range(ny) for i in range(nx)]
+        _, _, tr = oracle.run(grid, G, rho, eta, dt, 30, FS=FS, env=env, probes=np.array(cells), comp=3,
+                              sponge_cells=2, sigma_max=3e3)
+        ref = np.sqrt((tr ** 2).sum(axis=2)).max(axis=0).reshape(m.shape)
+        assert m.max() > 0
+        np.testing.assert_allclose(m, ref, rtol=1e-15, atol=0)
+        # the map dominates the final state and is zero on the Dirichlet layer
+        fin = oracle.plane_view(u_end, axis, index)
+        assert np.all(m >= np.sqrt((fin ** 2).sum(axis=0)))
+        assert not m[0].any() and not m[-1].any() and not m[:, 0].any() and not m[:, -1].any()
+
+
+def test_peak_maps_mirror_symmetry_of_a_centred_push():
+    """Homogeneous odd cube, square cells, z push on the centre node: the x
+    and y slices through the centre carry the same map, and the z slice is
+    symmetric under x <-> y and under both mirrors."""
+    from workloads import gaussian_push
+    n, h = 15, 0.3e-3
+    grid = (n, n, n, h, h, h)
+    F = gaussian_push(grid, 0.6e-3, 1.2e-3, 1e4)
+    dt = 0.5 * oracle.stable_dt(grid, 2e3, 1000.0, 0.3)
+    FS, _, _ = oracle.project(grid, F, tol=1e-13)
+    c = n // 2
+    maps, _, _ = oracle.peak_maps(grid, 2e3, 1000.0, 0.3, dt, 25, [(0, c), (1, c), (2, c)], FS=FS,
+                                  env=np.ones(5))
+    mx, my, mz = maps
+    assert mz.max() > 0
+    np.testing.assert_allclose(mx, my, rtol=1e-12, atol=1e-12 * mx.max())
+    np.testing.assert_allclose(mz, mz.T, rtol=1e-12, atol=1e-12 * mz.max())
+    np.testing.assert_allclose(mz, mz[::-1, :], rtol=1e-12, atol=1e-12 * mz.max())
+    np.testing.assert_allclose(mz, mz[:, ::-1], rtol=1e-12, atol=1e-12 * mz.max())
+
+
+def test_peak_maps_start_from_the_given_state():
+    """With a state handed in and no steps, the map is |u| of that state."""
+    grid = (7, 8, 9, 1e-3, 1e-3, 1e-3)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((3, 9, 8, 7))
+    maps, _, _ = oracle.peak_maps(grid, 1e3, 1000.0, 0.0, 1e-5, 0, [(1, 2)], u=u, w=np.zeros_like(u))
+    np.testing.assert_array_equal(maps[0], np.sqrt(u[0, :, 2, :] ** 2 + u[1, :, 2, :] ** 2 + u[2, :, 2, :] ** 2))

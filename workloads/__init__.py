@@ -215,3 +215,155 @@ def focal_modulated_force(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=
         M += 0.5 / np.sqrt(8) * np.cos(kvec[m, 0] * X + kvec[m, 1] * Y + kvec[m, 2] * Z + phases[m])
     F[2][np.ix_(iz, iy, ix)] = F0 * g * M
     return F
+
+
+def gaussian_random_field(shape, h, corr_len, rng):
+    """Smooth random field on a [nz][ny][nx] grid of spacing h: white noise
+    convolved (periodically, in Fourier space) with a Gaussian of standard
+    deviation corr_len / sqrt(2), so the field's correlation is a Gaussian of
+    standard deviation corr_len; then standardised (mean 0, variance 1)."""
+    import scipy.fft
+    nz, ny, nx = shape
+    xi = rng.standard_normal(shape)
+    spec = scipy.fft.rfftn(xi, workers=-1)
+    del xi
+    s2 = 0.5 * corr_len ** 2
+    kz = 2 * np.pi * np.fft.fftfreq(nz, h)
+    ky = 2 * np.pi * np.fft.fftfreq(ny, h)
+    kx = 2 * np.pi * np.fft.rfftfreq(nx, h)
+    spec *= np.exp(-0.5 * s2 * kz ** 2)[:, None, None]
+    spec *= np.exp(-0.5 * s2 * ky ** 2)[None, :, None]
+    spec *= np.exp(-0.5 * s2 * kx ** 2)[None, None, :]
+    f = scipy.fft.irfftn(spec, s=shape, workers=-1)
+    del spec
+    f -= f.mean()
+    f /= f.std()
+    return f
+
+
+def cfg4_grf_material(n=(384, 384, 512), h=0.2e-3, corr_len=3e-3, seed=1004):
+    """Medium of the time-varying-source workload: G = 10^(3 + Phi(xi)) Pa
+    (so 1-10 kPa) and eta = 1.5 Phi(xi') Pa s from two independent standardised
+    Gaussian random fields (3 mm correlation length), Phi the standard normal
+    CDF; rho = 1000.  Returns (grid, G, rho, eta) with [nz][ny][nx] arrays."""
+    import scipy.special
+    nx, ny, nz = n
+    grid = (nx, ny, nz, h, h, h)
+    xi = gaussian_random_field((nz, ny, nx), h, corr_len, np.random.default_rng([seed, 1]))
+    G = 10.0 ** (3.0 + scipy.special.ndtr(xi))
+    del xi
+    xi = gaussian_random_field((nz, ny, nx), h, corr_len, np.random.default_rng([seed, 2]))
+    eta = 1.5 * scipy.special.ndtr(xi)
+    return grid, G, 1000.0, eta
+
+
+def real_sph_harm_sum(coef, theta, phi):
+    """sum over (l, m) of coef[(l, m)] Y_lm(theta, phi) with real, orthonormal
+    spherical harmonics: Y_l0 = N_l0 P_l^0(cos theta); for m > 0 sqrt(2) N_lm
+    P_l^m(cos theta) cos(m phi); for m < 0 sqrt(2) N_l|m| P_l^|m|(cos theta)
+    sin(|m| phi), with N_lm^2 = (2l + 1) / (4 pi) (l - m)! / (l + m)! and P_l^m
+    the associated Legendre functions with the Condon-Shortley phase, built by
+    the standard three-term recurrence in l."""
+    from math import factorial
+    x = np.cos(theta)
+    sx = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    lmax = max(l for l, _ in coef)
+    out = np.zeros(np.broadcast(theta, phi).shape)
+    pmm = np.ones_like(x)
+    for m in range(0, lmax + 1):
+        if m > 0:
+            pmm = -(2 * m - 1) * sx * pmm
+        cm, sm = (np.cos(m * phi), np.sin(m * phi)) if m > 0 else (None, None)
+        p_prev, p = None, pmm
+        for l in range(m, lmax + 1):
+            if l == m + 1:
+                p_prev, p = p, x * (2 * m + 1) * pmm
+            elif l > m + 1:
+                p_prev, p = p, ((2 * l - 1) * x * p - (l + m - 1) * p_prev) / (l - m)
+            N = np.sqrt((2 * l + 1) / (4 * np.pi) * factorial(l - m) / factorial(l + m))
+            if m == 0:
+                if (l, 0) in coef:
+                    out += coef[(l, 0)] * N * p
+                continue
+            if (l, m) in coef:
+                out += coef[(l, m)] * np.sqrt(2) * N * p * cm
+            if (l, -m) in coef:
+                out += coef[(l, -m)] * np.sqrt(2) * N * p * sm
+    return out
+
+
+@dataclass
+class ShellGeometry:
+    centre: tuple       # sphere centre (x, y, z), m, node coordinates
+    r_outer: float
+    coef: dict          # (l, m) -> spherical-harmonic coefficient
+    s_max: float        # max |s| over the 1-degree direction grid
+
+    def thickness(self, theta, phi):
+        return 6.5e-3 + 1.5e-3 * real_sph_harm_sum(self.coef, theta, phi) / self.s_max
+
+
+def shell_geometry(grid, rng, r_outer=70e-3, top_depth=10e-3, lmax=4):
+    """Spherical shell on the lateral centre line whose outer sphere (radius
+    r_outer) reaches up to depth top_depth below the z = first-node face;
+    thickness 6.5 mm + 1.5 mm s(theta, phi), s a sum of real spherical
+    harmonics l = 1..lmax with N(0, 1) coefficients, scaled to max |s| = 1 over
+    a 1-degree (theta, phi) grid (so 5-8 mm).  theta is measured from +z."""
+    nz, hz = grid[2], grid[5]
+    z_first = -(nz // 2) * hz
+    centre = (0.0, 0.0, z_first + top_depth + r_outer)
+    coef = {(l, m): float(rng.standard_normal()) for l in range(1, lmax + 1) for m in range(-l, l + 1)}
+    th = np.deg2rad(np.arange(181.0))[:, None]
+    ph = np.deg2rad(np.arange(360.0))[None, :]
+    s_max = float(np.abs(real_sph_harm_sum(coef, th, ph)).max())
+    return ShellGeometry(centre=centre, r_outer=r_outer, coef=coef, s_max=s_max)
+
+
+def shell_material(grid, geo, shell=(100e3, 1900.0, 2.0), soft=(1.5e3, 1040.0, 0.8)):
+    """(G, rho, eta) [nz][ny][nx]: `shell` properties where r_outer - T(theta,
+    phi) <= |x - centre| <= r_outer, `soft` elsewhere.  Built one z plane at a
+    time; the spherical harmonics are evaluated only in the radial band."""
+    nx, ny, nz, hx, hy, hz = grid
+    x = coords(nx, hx) - geo.centre[0]
+    y = coords(ny, hy) - geo.centre[1]
+    z = coords(nz, hz) - geo.centre[2]
+    G = np.full((nz, ny, nx), soft[0])
+    rho = np.full((nz, ny, nx), soft[1])
+    eta = np.full((nz, ny, nx), soft[2])
+    rxy2 = x[None, :] ** 2 + y[:, None] ** 2
+    inner_min = geo.r_outer - 8.0e-3
+    for k in range(nz):
+        r = np.sqrt(rxy2 + z[k] ** 2)
+        band = (r <= geo.r_outer) & (r >= inner_min)
+        if not band.any():
+            continue
+        jj, ii = np.nonzero(band)
+        rb = r[jj, ii]
+        theta = np.arccos(np.clip(z[k] / rb, -1.0, 1.0))
+        phi = np.arctan2(y[jj], x[ii])
+        inside = rb >= geo.r_outer - geo.thickness(theta, phi)
+        jj, ii = jj[inside], ii[inside]
+        G[k, jj, ii], rho[k, jj, ii], eta[k, jj, ii] = shell
+    return G, rho, eta
+
+
+def cfg5_shell(n=(512, 512, 640), h=0.2e-3, seed=1005):
+    """Transcranial-like case: curved shell (100 kPa, 1900, 2 Pa s, 5-8 mm
+    thick) over soft tissue (1.5 kPa, 1040, 0.8 Pa s); F_z Gaussian push
+    (1 mm lateral, 5 mm axial, F0 = 5e4) on the axis 20 mm below the shell's
+    inner surface, 200 us; dt = 0.4 x stable limit; 6000 steps; peak |u| on
+    the x, y and z planes through the push.  `n` shrinks the grid for tests
+    (the shell keeps its physical size, so small grids see only its top)."""
+    nx, ny, nz = n
+    grid = (nx, ny, nz, h, h, h)
+    geo = shell_geometry(grid, np.random.default_rng(seed))
+    G, rho, eta = shell_material(grid, geo)
+    t_top = float(geo.thickness(np.pi, 0.0))
+    z_push = geo.centre[2] - geo.r_outer + t_top + 20e-3
+    F = gaussian_push(grid, 1e-3, 5e-3, 5e4, centre=(0.0, 0.0, z_push))
+    k_push = int(round(z_push / h)) + nz // 2
+    planes = [(0, nx // 2), (1, ny // 2), (2, k_push)]
+    return Workload(name=f"shell {nx}x{ny}x{nz}", grid=grid, G=G, rho=rho, eta=eta, F=F, env=None, nsteps=6000,
+                    probes=x_line_probes(grid, k=k_push), comp=2, dt_factor=0.4, push_time=200e-6,
+                    sponge_cells=8, tol=1e-8, precision="fp32",
+                    meta={"geometry": geo, "z_push": z_push, "k_push": k_push, "peak_planes": planes})
