@@ -73,6 +73,10 @@ def parse():
                     help="skip the learned-preconditioner projection comparison")
     ap.add_argument("--learned-epochs", type=int, default=4,
                     help="projections of the time-varying workload timed per method")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the full-size time-varying and shell workload legs")
+    ap.add_argument("--tv-epochs", type=int, default=4, help="epochs of the time-varying workload window")
+    ap.add_argument("--shell-steps", type=int, default=300, help="steps of the shell workload window")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -112,10 +116,10 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4}), flush=True)
 
 
-def learned_projection(args):
+def learned_projection(args, net):
     """Projection time to 1e-8, learned flexible PCG vs Jacobi-PCG, on the
     time-varying workload's grid (384 x 384 x 512, h = 0.2 mm): the network
-    is trained first by the committed recipe (timed separately), then each
+    `net` is trained first by the committed recipe (timed separately), then each
     method projects the pushes of `learned_epochs` re-projection epochs
     (moving focus, redrawn modulation phases) from phi = 0, and again
     warm-started from the previous epoch's phi.  Times are HIP events around
@@ -129,7 +133,6 @@ def learned_projection(args):
     nx, ny, nz, h = 384, 384, 512, 0.2e-3
     grid = (nx, ny, nz, h, h, h)
     log("bench: training the preconditioner (64^3 unit grids, 2 rounds on its own residuals)")
-    net = kvs.kvs_unet_create((16, 32, 64), 4)
     ctx = None
     try:
         tr = train.train_default(net, n=64, seed=0, rounds=2)
@@ -164,7 +167,6 @@ def learned_projection(args):
     finally:
         if ctx is not None:
             kvs.kvs_destroy(ctx)
-        kvs.kvs_unet_destroy(net)
     jm, fm = float(np.mean(res["jacobi"]["ms"])), float(np.mean(res["fpcg"]["ms"]))
     out = {
         "workload": f"{nx}x{ny}x{nz}, h 0.2 mm, focal push (1 mm / 4 mm) x random-phase modulation, focus moving "
@@ -184,6 +186,149 @@ def learned_projection(args):
     if ws["jacobi_ms"] and ws["fpcg_ms"]:
         ws["speedup"] = ws["jacobi_ms"] / ws["fpcg_ms"]
     return out
+
+
+def time_varying_window(args, net):
+    """The time-varying-source workload in full (384 x 384 x 512, G and eta
+    from random fields, F_S always on), over a window of `tv_epochs`
+    re-projection epochs: per epoch the focal push of that epoch, a warm-
+    started learned-FPCG projection to 1e-8, then 10 FDTD steps.  Step-kernel
+    launches are timed with HIP events (72 algorithmic bytes per cell-update:
+    state 48, material 12, F_S 12); epochs are timed whole."""
+    import numpy as np
+    import torch
+
+    from paper_2607_28414_amd import kvs
+    from workloads import cfg4_grf_material, focal_modulated_force
+
+    log("bench: time-varying workload 384x384x512 (random medium, F_S always on)")
+    grid, G, rho, eta = cfg4_grf_material()
+    cells = (grid[0] - 2) * (grid[1] - 2) * (grid[2] - 2)
+    stream = torch.cuda.current_stream()
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, sponge_cells=8, sponge_sigma_max=-1.0,
+                         stream=stream.cuda_stream)
+    try:
+        kvs.kvs_set_material(ctx, G, rho, eta)
+        del G, eta
+        dt = 0.4 * kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_envelope(ctx, np.ones(3000))
+        kvs.kvs_set_preconditioner(ctx, net)
+        variant, _ = kvs.kvs_autotune_step(ctx, 10)
+        forces = [torch.from_numpy(focal_modulated_force(grid, epoch=e, dt=dt)).to("cuda")
+                  for e in range(args.tv_epochs)]
+        iters, pms, fbs, ems = [], [], [], []
+        kvs.kvs_enable_kernel_timing(ctx, True)
+        for e in range(args.tv_epochs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            kvs.kvs_set_force_device(ctx, forces[e].data_ptr(), 0)
+            rep = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=kvs.KVS_PC_UNET, warm_start=e > 0)
+            kvs.kvs_step(ctx, 10)
+            torch.cuda.synchronize()
+            ems.append((time.perf_counter() - t0) * 1e3)
+            assert rep["relres_true"] < 1.01e-8, rep
+            iters.append(rep["iters"])
+            pms.append(rep["ms"])
+            fbs.append(kvs.kvs_last_fallbacks(ctx))
+        k_ms, k_launches = kvs.kvs_kernel_time(ctx)
+        kvs.kvs_enable_kernel_timing(ctx, False)
+        u, _, step = kvs.kvs_get_state(ctx, (grid[2], grid[1], grid[0]))
+        assert np.all(np.isfinite(u)) and step == 10 * args.tv_epochs
+    finally:
+        kvs.kvs_destroy(ctx)
+    per = k_ms / k_launches
+    achieved = cells * 72 / (per * 1e-3) / 1e9
+    return {
+        "workload": f"384x384x512, h 0.2 mm, G = 10^(3 + Phi(xi)) Pa and eta = 1.5 Phi(xi') Pa s (3 mm random "
+                    f"fields), rho 1000, 8-cell sponge, dt {dt:.3e} s (0.4 x stable limit), epochs 0-"
+                    f"{args.tv_epochs - 1}: focal push re-projected by warm-started learned FPCG, then 10 steps",
+        "fdtd_kernel_ms_avg": per, "fdtd_kernel_gcells": cells / (per * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_cell_update": 72, "launches": k_launches, "variant": variant},
+        "projection_iters": iters, "projection_ms": pms, "fallbacks": fbs,
+        "epoch_ms": ems, "epoch_ms_mean_after_first": float(np.mean(ems[1:])) if len(ems) > 1 else None,
+    }
+
+
+def shell_workload(args, net):
+    """The transcranial-like workload in full (512 x 512 x 640, curved stiff
+    shell, 6000-step run window of `shell_steps` steps): one projection of
+    the separable push by learned FPCG and by Jacobi-PCG (both from phi = 0
+    to 1e-8), then stepping with the 90-step push and the peak-|u| maps on
+    the three planes through the push.  The step kernel is timed with HIP
+    events; the whole stepping (step kernel, probe gather and peak update)
+    with events around it."""
+    import numpy as np
+    import torch
+
+    from paper_2607_28414_amd import kvs
+    from workloads import cfg5_shell
+
+    log("bench: shell workload 512x512x640")
+    w = cfg5_shell()
+    cells = w.interior_cells
+    stream = torch.cuda.current_stream()
+    ctx = kvs.kvs_create(w.grid, precision=kvs.KVS_FP32, sponge_cells=w.sponge_cells, sponge_sigma_max=-1.0,
+                         stream=stream.cuda_stream)
+    try:
+        kvs.kvs_set_material(ctx, w.G, w.rho, w.eta)
+        w.G = w.rho = w.eta = None
+        dt = w.dt_factor * kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        env = w.envelope_for(dt)
+        kvs.kvs_set_envelope(ctx, env)
+        variant, _ = kvs.kvs_autotune_step(ctx, 10)
+        kvs.kvs_set_force(ctx, w.F)
+        w.F = None
+        kvs.kvs_set_preconditioner(ctx, net)
+        rj = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=kvs.KVS_PC_JACOBI)
+        rf = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=kvs.KVS_PC_UNET)
+        fb = kvs.kvs_last_fallbacks(ctx)
+        log(f"bench: shell projection jacobi {rj['iters']} it {rj['ms']:.0f} ms, fpcg {rf['iters']} it "
+            f"{rf['ms']:.0f} ms")
+        planes = w.meta["peak_planes"]
+        kvs.kvs_set_peak_planes(ctx, planes)
+        kvs.kvs_set_probes(ctx, w.probes, 2)
+        kvs.kvs_step(ctx, 5)  # warm-up launches
+        kvs.kvs_reset_state(ctx)
+        kvs.kvs_enable_kernel_timing(ctx, True)
+        # events on the context's own stream (the library makes one when the
+        # caller's stream is the null stream)
+        lib_stream = torch.cuda.ExternalStream(kvs.kvs_stream(ctx))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lib_stream)
+        kvs.kvs_step(ctx, args.shell_steps)
+        e1.record(lib_stream)
+        torch.cuda.synchronize()
+        k_ms, k_launches = kvs.kvs_kernel_time(ctx)
+        kvs.kvs_enable_kernel_timing(ctx, False)
+        all_ms = e0.elapsed_time(e1)
+        peak = {f"axis{a}_index{i}": float(kvs.kvs_peak_map(ctx, a, i, w.grid).max()) for a, i in planes}
+    finally:
+        kvs.kvs_destroy(ctx)
+    per = k_ms / k_launches
+    n_push = min(len(env), args.shell_steps)
+    bytes_total = cells * (60 * args.shell_steps + 12 * n_push)
+    achieved = bytes_total / (k_ms * 1e-3) / 1e9
+    return {
+        "workload": f"512x512x640, h 0.2 mm, curved shell 5-8 mm (100 kPa, 1900, 2 Pa s) over soft tissue "
+                    f"(1.5 kPa, 1040, 0.8 Pa s), 8-cell sponge, push 20 mm below the shell (1 mm / 5 mm, 5e4 "
+                    f"N/m^3, {len(env)} steps), dt {dt:.3e} s, first {args.shell_steps} of 6000 steps, peak |u| "
+                    f"maps on 3 planes",
+        "projection": {"tol": 1e-8, "jacobi_iters": rj["iters"], "jacobi_ms": rj["ms"], "fpcg_iters": rf["iters"],
+                       "fpcg_ms": rf["ms"], "speedup": rj["ms"] / rf["ms"], "fpcg_fallbacks": fb,
+                       "fpcg_relres_true": rf["relres_true"]},
+        "fdtd_kernel_ms_avg": per, "fdtd_kernel_gcells": cells * args.shell_steps / (k_ms * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_cell_update": "60 (+12 on push steps)", "launches": k_launches,
+                     "variant": variant},
+        "stepping_ms_per_step": all_ms / args.shell_steps,
+        "sensor_overhead_ms_per_step": all_ms / args.shell_steps - per,
+        "peak_u_m": peak,
+    }
 
 
 def run_fpcg_profile(args):
@@ -458,7 +603,16 @@ def main():
         res["cpu_baseline"] = cpu_baseline(w, dt, smax, FS_host, args.cpu_sample_steps)
     else:
         res["cpu_baseline"] = None
-    res["projection_learned"] = None if args.no_learned else learned_projection(args)
+    res["projection_learned"] = res["time_varying"] = res["shell"] = None
+    if not args.no_learned:
+        net = kvs.kvs_unet_create((16, 32, 64), 4)
+        try:
+            res["projection_learned"] = learned_projection(args, net)
+            if not args.no_workloads:
+                res["time_varying"] = time_varying_window(args, net)
+                res["shell"] = shell_workload(args, net)
+        finally:
+            kvs.kvs_unet_destroy(net)
     print(json.dumps(res), flush=True)
 
 

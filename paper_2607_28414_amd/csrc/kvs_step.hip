@@ -494,31 +494,6 @@ __global__ void probe_kernel(const T* u, long long N, const int64_t* cells, int6
     }
 }
 
-// Running peak of the displacement magnitude on grid planes: one y-row of
-// blocks per plane, a grid-stride loop over the plane's cells with the
-// plane's first in-plane axis fastest.  NaN wins over every number, so an
-// unstable run shows in the map instead of hiding behind fmax.
-template <typename T>
-__global__ void peak_kernel(const T* u, long long N, int nx, int ny, PeakPlanes P, T* maps) {
-    const int p = blockIdx.y;
-    const int axis = P.axis[p];
-    const long long idx = P.index[p];
-    const long long n1 = P.n1[p], cells = n1 * P.n2[p];
-    T* m = maps + P.off[p];
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < cells;
-         q += (long long)gridDim.x * blockDim.x) {
-        const long long a = q % n1, b = q / n1;
-        const long long i = axis == 0 ? idx : a;
-        const long long j = axis == 0 ? a : (axis == 1 ? idx : b);
-        const long long k = axis == 2 ? idx : b;
-        const long long c = i + nx * (j + ny * k);
-        const T x = u[c], y = u[N + c], z = u[2 * N + c];
-        const T v = sqrt(x * x + y * y + z * z);
-        const T old = m[q];
-        m[q] = (v > old || __builtin_isnan(v)) ? v : old;
-    }
-}
-
 template <typename T>
 __global__ void cast_kernel(const double* src, T* dst, int64_t n) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
@@ -656,29 +631,6 @@ hipError_t kvs_launch_probe_gather(kvs_ctx* c, const void* u_new, int64_t slot) 
         hipLaunchKernelGGL(probe_kernel<double>, dim3(blocks), dim3(256), 0, c->stream,
                            static_cast<const double*>(u_new), (long long)c->N, c->probe_cells, c->nprobes,
                            c->probe_comp, out);
-    return hipGetLastError();
-}
-
-hipError_t kvs_launch_peak_update(kvs_ctx* c, const void* u_new) {
-    if (c->npeak == 0) return hipSuccess;
-    PeakPlanes P{};
-    long long most = 0;
-    for (int p = 0; p < c->npeak; ++p) {
-        const int a = c->peak_axis[p];
-        P.axis[p] = a;
-        P.index[p] = c->peak_index[p];
-        P.n1[p] = a == 0 ? c->grid.ny : c->grid.nx;
-        P.n2[p] = a == 2 ? c->grid.ny : c->grid.nz;
-        P.off[p] = c->peak_off[p];
-        most = std::max(most, (long long)P.n1[p] * P.n2[p]);
-    }
-    const dim3 grid((unsigned)std::min<long long>((most + 255) / 256, 1024), (unsigned)c->npeak);
-    if (c->prec == KVS_FP32)
-        hipLaunchKernelGGL(peak_kernel<float>, grid, dim3(256), 0, c->stream, static_cast<const float*>(u_new),
-                           (long long)c->N, (int)c->grid.nx, (int)c->grid.ny, P, static_cast<float*>(c->peak));
-    else
-        hipLaunchKernelGGL(peak_kernel<double>, grid, dim3(256), 0, c->stream, static_cast<const double*>(u_new),
-                           (long long)c->N, (int)c->grid.nx, (int)c->grid.ny, P, static_cast<double*>(c->peak));
     return hipGetLastError();
 }
 
