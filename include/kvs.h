@@ -289,6 +289,9 @@ kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* varian
  * up = cell-centred trilinear interpolation (per axis 3/4 of the parent,
  * 1/4 of its neighbour on the fine cell's side, clamped at the edges).
  * Activations and weights are BF16, accumulation FP32 (MFMA); gz is FP32.
+ * e0 is rounded to BF16 where it is pooled; the output conv takes it
+ * unrounded, which on the interior equals one 5x5x5 FP32 stencil of the
+ * BF16 input with the composed weights (W_out after W0).
  * Used as the preconditioner of a flexible PCG on the projection's Poisson
  * problem (not part of the paper's method; plain CG / Jacobi-PCG remain the
  * reference). */

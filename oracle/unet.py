@@ -9,7 +9,9 @@ Network (linear, no biases): e0 = conv(r; 1->C0); e1 = conv(pool(e0));
 bottleneck convs at 1/4 resolution (dilations 1, 2, 4, ..., then 1);
 g1 = conv(e1 + up(b); C1->C0); gz = g1 . wp (pointwise C0->1) at 1/2
 resolution; z = conv(e0; C0->1) + up(gz) on the interior: a local stencil
-of r plus the interpolated coarse correction.
+of r plus the interpolated coarse correction.  e0 is rounded to BF16 where
+it feeds the pool (and where it is kept for the weight gradient); the
+output conv takes it unrounded.
 conv = 3x3x3 cross-correlation with zero padding; pool = mean of the
 existing children; up = cell-centred trilinear interpolation (per axis a
 fine cell takes 3/4 of its parent and 1/4 of the parent's neighbour on its
@@ -48,6 +50,8 @@ def shift(a, dz, dy, dx):
     """out[z, y, x] = a[z + dz, y + dy, x + dx], zero outside (first 3 axes)."""
     out = np.zeros_like(a)
     Z, Y, X = a.shape[:3]
+    if abs(dz) >= Z or abs(dy) >= Y or abs(dx) >= X:
+        return out  # shifted entirely outside: zero padding
 
     def rng(n, d):
         return slice(max(0, -d), min(n, n - d)), slice(max(0, d), min(n, n + d))
@@ -151,7 +155,8 @@ def forward(r, in_scale, out_scale, flat_w, c0=16, c1=32, c2=64, nbott=4, exact=
     shapes = layer_shapes(c0, c1, c2, nbott)
     Ws = [rnd(w) for w in split_weights(flat_w, shapes)]
     x = rnd(np.float32(in_scale * np.asarray(r, dtype=np.float64)) if not exact else in_scale * np.asarray(r))[..., None]
-    e0 = rnd(conv3(x, Ws[0]))
+    e0_out = conv3(x, Ws[0])  # the output path takes e0 unrounded
+    e0 = rnd(e0_out)
     p0 = rnd(pool(e0))
     e1 = rnd(conv3(p0, Ws[1]))
     b = rnd(pool(e1))
@@ -163,7 +168,7 @@ def forward(r, in_scale, out_scale, flat_w, c0=16, c1=32, c2=64, nbott=4, exact=
     g1 = rnd(conv3(i1, Ws[2 + nbott]))
     f32 = _identity if exact else (lambda a: np.asarray(np.float32(a), dtype=np.float64))
     gz = f32(g1 @ Ws[3 + nbott][0, 0, :])[..., None]
-    z = out_scale * (conv3(e0, Ws[4 + nbott])[..., 0] + up(gz, e0.shape[:3])[..., 0])
+    z = out_scale * (conv3(e0_out, Ws[4 + nbott])[..., 0] + up(gz, e0.shape[:3])[..., 0])
     m = np.zeros_like(z)
     m[1:-1, 1:-1, 1:-1] = 1.0
     z = z * m
@@ -221,7 +226,8 @@ def backward(r, in_scale, flat_w, dz, dz_scale, c0=16, c1=32, c2=64, nbott=4, ex
     """Flat weight gradient for the gradient dz_scale * dz of the raw network
     output (dz zero outside the interior), mirroring the GPU: FP32 gradient of
     the output, activation gradients rounded to BF16 where they feed a
-    transposed convolution (not in exact mode)."""
+    transposed convolution, and the output weights' gradient taken against the
+    kept BF16 e0 (not in exact mode)."""
     rnd = _identity if exact else bf16_round
     f32 = _identity if exact else (lambda a: np.asarray(np.float32(a), dtype=np.float64))
     _, A = forward(r, in_scale, 1.0, flat_w, c0, c1, c2, nbott, exact=exact, keep=True)

@@ -505,195 +505,167 @@ __device__ __forceinline__ void up_axis(int i, int nc, int& I, int& J) {
     J = (i & 1) ? min(I + 1, nc - 1) : max(I - 1, 0);
 }
 
-// Output of the network, fused with a recomputation of e0:
-//   e0(v) = bf16(conv(x; W0))                  (0 outside the grid)
-//   y(v)[tap] = sum_c Wo[tap][c] e0(v)[c]      (MFMA 16x16x16, FP32)
-//   z(v) = out_scale * (sum_tap y(v + tap)[tap] + up(gz)(v)) on the
-//          interior, 0 on the outer layer (gz: FP32 at 1/2 resolution).
-// A block owns an OT_X x OT_Y column of output voxels and marches up a z
-// segment.  Per plane q it stages x = bf16(in_scale r) of plane q + 1 in an
-// LDS ring (3 planes, halo 2), computes e0 and y on the haloed OT_X+2 x
-// OT_Y+2 plane (16 groups of 16 voxels, 4 per wavefront) into LDS, and every
-// output thread adds the 9 in-plane taps of y(q) to its rolling sums for the
-// output planes q - 1, q, q + 1; plane q - 1 is then complete and stored.
-// x and the 8 gz values of the next output are loaded one plane ahead.  With
-// keep != null, e0 of the block's own voxels is stored (training).
-constexpr int OT_X = 30, OT_Y = 6, HT_X = 32, HT_Y = 8, RT_X = 34, RT_Y = 10;
-// y tile, tap-major: ys[tap * YT + voxel]; YT = 4 (mod 32) makes the 64 lanes
-// of a store (16 voxels x 4 tap groups) hit each LDS bank exactly twice
-constexpr int YT = HT_X * HT_Y + 4;
+// Output of the network at the fine level as one 5x5x5 stencil:
+//   z(v) = out_scale * (sum_t Wc[t] x(v + t) + up(gz)(v)) on the interior,
+//   0 on the outer layer, x = bf16(in_scale r) (0 outside the grid),
+//   Wc = W_out composed with W0 (summed over the C0 channels).
+// An interior output reads e0 = conv(x; W0) only at voxels inside the grid,
+// so conv(e0; W_out) there equals the composed stencil of x exactly; e0 is
+// taken unrounded on this path.  125 FP32 FMAs per voxel replace the C0
+// channels of e0 and the 27-tap gather.
+// A block owns ZO_TX x ZO_TY outputs per plane (a lane: one x column, two
+// adjacent rows) and marches up a z segment.  Each x plane (halo 2) is staged
+// once in a double-buffered LDS plane, read as a 6 x 5 window per lane, and
+// added with the five dz slices of Wc into rolling sums for the outputs two
+// planes below to two above; the lowest is then complete.  The coarse
+// correction is interpolated in z while it is staged (one LDS tile per
+// output plane) and bilinearly in the plane.  One barrier per plane; x and
+// gz are loaded one plane ahead.
+constexpr int ZO_TX = 64, ZO_TY = 8;
+constexpr int ZO_RX = ZO_TX + 4, ZO_RY = ZO_TY + 4, ZO_RS = 72, ZO_PLANE = ZO_RY * ZO_RS;
+constexpr int ZO_NX = ZO_RX * ZO_RY;  // staged x values per plane (816)
+constexpr int ZO_GX = ZO_TX / 2 + 2, ZO_GY = ZO_TY / 2 + 2, ZO_GN = ZO_GX * ZO_GY;  // coarse tile 34 x 6
 
-__global__ __launch_bounds__(256) void out_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx, int nty,
-                                                  int zchunk, const bf16* __restrict__ W0, const bf16* __restrict__ WoT,
-                                                  const float* __restrict__ gz, double* __restrict__ z,
-                                                  bf16* __restrict__ keep) {
-    constexpr int RN = RT_X * RT_Y;
-    __shared__ float rs[3 * RN + 1];  // the last element is a constant 0
-    __shared__ float ys[32 * YT];  // y of the haloed plane, 27 taps (+ 5 rows written by the padding taps)
+__global__ __launch_bounds__(256) void zout_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
+                                                   int nty, int zchunk, const float* __restrict__ Wc,
+                                                   const float* __restrict__ gz, double* __restrict__ z) {
+    __shared__ float xs[2][ZO_PLANE];
+    __shared__ float gs[2][ZO_GN];
     if (ctl.stop && *ctl.stop) return;
     const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
     const double out_scale = ctl.out_dev ? *ctl.out_dev : ctl.out_v;
     const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
     const int tx = blk % ntx, t2 = blk / ntx;
     const int ty = t2 % nty, tz = t2 / nty;
-    const int ox0 = tx * OT_X, oy0 = ty * OT_Y;
+    const int x0 = tx * ZO_TX, y0 = ty * ZO_TY;
     const int zs = tz * zchunk, ze = min(d.nz, zs + zchunk);
-    const int hx0 = ox0 - 1, hy0 = oy0 - 1, rx0 = ox0 - 2, ry0 = oy0 - 2;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6, vl = lane & 15, kg = lane >> 4;
+    const int t = threadIdx.x, lx = t & 63, ya = 2 * (t >> 6);
     const int sxy = d.nx * d.ny;
     const Dims c = coarse(d);
-    const int base = zs - 2;  // ring slot of plane p: (p - base) % 3, p >= base
-    constexpr int ZERO = 3 * RN;
-    if (t == 0) rs[ZERO] = 0.f;
-    const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(W0 + vl * 32 + 8 * kg);
-    const bf16x4 wo0 = *reinterpret_cast<const bf16x4*>(WoT + vl * 16 + 4 * kg);
-    const bf16x4 wo1 = *reinterpret_cast<const bf16x4*>(WoT + (16 + vl) * 16 + 4 * kg);
-    // per-lane taps 8 kg .. 8 kg + 7 (taps >= 27 have zero weights and read
-    // the centre tap instead)
-    int toff[8], tdz[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int tap = 8 * kg + j;
-        toff[j] = tap < 27 ? tap_dy(tap) * RT_X + tap_dx(tap) : 0;
-        tdz[j] = tap < 27 ? tap_dz(tap) : 0;
-    }
-    // haloed voxels of the wavefront's 4 groups: gi -> row 2w + gi / 2, x 16 (gi % 2) + vl;
-    // the group offsets are constants of the unrolled loops
-    const int rbase = (2 * w + 1) * RT_X + vl + 1;  // r tile, group 0
-    const int ybw = 4 * kg * YT + 2 * w * HT_X + vl;  // y tile, group 0, this lane's first tap
-    bool vxy[4];
-#pragma unroll
-    for (int gi = 0; gi < 4; ++gi) {
-        const int gx = hx0 + 16 * (gi & 1) + vl, gy = hy0 + 2 * w + (gi >> 1);
-        vxy[gi] = gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
-    }
-    // Loads are unconditional from clamped (in-bounds) addresses and masked
-    // at their use, so that a prefetch stays in flight until then.
-    auto rload = [&](int p, int h, double& v, bool& m) {
-        const int idx = min(t + 256 * h, RN - 1);
-        const int gx = rx0 + idx % RT_X, gy = ry0 + idx / RT_X;
-        m = t + 256 * h < RN && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
+
+    // x plane: value i of the haloed tile (row i / ZO_RX, column i % ZO_RX);
+    // loads are unconditional from clamped addresses, masked when stored
+    auto xload = [&](int p, int h, double& v, bool& m) {
+        const int i = t + 256 * h;
+        const int ic = min(i, ZO_NX - 1);
+        const int gx = x0 - 2 + ic % ZO_RX, gy = y0 - 2 + ic / ZO_RX;
+        m = i < ZO_NX && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
         const int pc = min(max(p, 0), d.nz - 1), yc = min(max(gy, 0), d.ny - 1), xc = min(max(gx, 0), d.nx - 1);
         v = r[(size_t)pc * sxy + (size_t)(yc * d.nx + xc)];
     };
-    auto rstore = [&](int p, const double* v, const bool* m) {
-        float* slot = rs + ((p - base) % 3) * RN;
-        const float a = m[0] ? (float)(bf16)(float)(in_scale * v[0]) : 0.f;
-        const float b = m[1] ? (float)(bf16)(float)(in_scale * v[1]) : 0.f;
-        slot[t] = a;
-        if (t + 256 < RN) slot[t + 256] = b;
-    };
-    double rv[2];
-    bool rm[2];
-    rload(zs - 2, 0, rv[0], rm[0]);
-    rload(zs - 2, 1, rv[1], rm[1]);
-    rstore(zs - 2, rv, rm);
-    rload(zs - 1, 0, rv[0], rm[0]);
-    rload(zs - 1, 1, rv[1], rm[1]);
-    rstore(zs - 1, rv, rm);
-    rload(zs, 0, rv[0], rm[0]);
-    rload(zs, 1, rv[1], rm[1]);
-
-    const bool has_out = t < OT_X * OT_Y;
-    const int oxl = t % OT_X, oyl = t / OT_X;
-    const int gxo = ox0 + oxl, gyo = oy0 + oyl;
-    const bool out_in = has_out && gxo < d.nx && gyo < d.ny;
-    const bool inner_xy = gxo >= 1 && gxo <= d.nx - 2 && gyo >= 1 && gyo <= d.ny - 2;
-    const int ybase = (oyl + 1) * HT_X + oxl + 1;
-    // the 8 gz values of this thread's output voxel on plane o (coordinates clamped)
-    const int gxo_c = min(gxo, d.nx - 1), gyo_c = min(gyo, d.ny - 1);
-    int Ix, Jx, Iy, Jy;
-    up_axis(gxo_c, c.nx, Ix, Jx);
-    up_axis(gyo_c, c.ny, Iy, Jy);
-    auto gzload = [&](int o, float* gv) {
+    // coarse tile entry t: column X0 - 1 + t % ZO_GX, row Y0 - 1 + t / ZO_GX
+    // (clamped; outputs only reference entries inside the coarse grid)
+    const int gcol = min(t, ZO_GN - 1) % ZO_GX, grow = min(t, ZO_GN - 1) / ZO_GX;
+    const int gX = min(max(x0 / 2 - 1 + gcol, 0), c.nx - 1), gY = min(max(y0 / 2 - 1 + grow, 0), c.ny - 1);
+    auto gload = [&](int o, float& a, float& b) {
         int Iz, Jz;
         up_axis(min(max(o, 0), d.nz - 1), c.nz, Iz, Jz);
-        const int zz[2] = {Iz, Jz}, yy[2] = {Iy, Jy}, xx[2] = {Ix, Jx};
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int e = 0; e < 2; ++e)
-                    gv[4 * a + 2 * b + e] = gz[((size_t)zz[a] * c.ny + yy[b]) * c.nx + xx[e]];
+        const size_t col = (size_t)gY * c.nx + gX;
+        a = gz[(size_t)Iz * c.ny * c.nx + col];
+        b = gz[(size_t)Jz * c.ny * c.nx + col];
     };
-    float gzv[8];
-    gzload(zs, gzv);
-    float a_prev = 0.f, a_cur = 0.f, a_next = 0.f;
-    for (int q = zs - 1; q <= ze; ++q) {
-        rstore(q + 1, rv, rm);
-        if (q + 2 <= ze + 1) {
-            rload(q + 2, 0, rv[0], rm[0]);
-            rload(q + 2, 1, rv[1], rm[1]);
+    // this lane's outputs: column x, rows y and y + 1 (clamped for the gz
+    // indices; outputs outside the grid are not stored)
+    const int xo = x0 + lx, yo = y0 + ya;
+    int Ix, Jx, Iy0, Jy0, Iy1, Jy1;
+    up_axis(min(xo, d.nx - 1), c.nx, Ix, Jx);
+    up_axis(min(yo, d.ny - 1), c.ny, Iy0, Jy0);
+    up_axis(min(yo + 1, d.ny - 1), c.ny, Iy1, Jy1);
+    const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1;
+    const int gIx = Ix - cx0, gJx = Jx - cx0;
+    const int gI0 = (Iy0 - cy0) * ZO_GX, gJ0 = (Jy0 - cy0) * ZO_GX;
+    const int gI1 = (Iy1 - cy0) * ZO_GX, gJ1 = (Jy1 - cy0) * ZO_GX;
+    const bool inx = xo >= 1 && xo <= d.nx - 2;
+    const bool st0 = xo < d.nx && yo < d.ny, st1 = xo < d.nx && yo + 1 < d.ny;
+    const bool in0 = inx && yo >= 1 && yo <= d.ny - 2, in1 = inx && yo + 1 >= 1 && yo + 1 <= d.ny - 2;
+    const int lbase = ya * ZO_RS + lx;  // window origin: tile row ya, column lx
+
+    double xv[4];
+    bool xm[4];
+    float ga = 0.f, gb = 0.f;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) xload(zs - 2, h, xv[h], xm[h]);
+    float a0[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, a1[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int p = zs - 2; p <= ze + 1; ++p) {
+        const int buf = (p - zs) & 1;
+        float* xb = xs[buf];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int i = t + 256 * h;
+            if (h < 3 || i < ZO_NX) {
+                const int ic = min(i, ZO_NX - 1);
+                xb[(ic / ZO_RX) * ZO_RS + ic % ZO_RX] = xm[h] ? (float)(bf16)(float)(in_scale * xv[h]) : 0.f;
+            }
         }
+        if (t < ZO_GN) gs[buf][t] = 0.75f * ga + 0.25f * gb;  // output plane p - 2
+        if (p + 1 <= ze + 1) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) xload(p + 1, h, xv[h], xm[h]);
+        }
+        if (p - 1 >= zs && p - 1 < ze) gload(p - 1, ga, gb);
         kvs_tiling::lds_barrier();
-        const int s0 = ((q - 1 - base) % 3) * RN, s1 = ((q - base) % 3) * RN, s2 = ((q + 1 - base) % 3) * RN;
-        int ab[8];
+        float v[6][5];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) ab[j] = (tdz[j] < 0 ? s0 : (tdz[j] == 0 ? s1 : s2)) + toff[j] + rbase;
-        const bool qin = q >= 0 && q < d.nz;
+        for (int rr = 0; rr < 6; ++rr)
 #pragma unroll
-        for (int gi = 0; gi < 4; ++gi) {
-            const int rdelta = (gi >> 1) * RT_X + 16 * (gi & 1);
-            bf16x8 xb;
+            for (int cc = 0; cc < 5; ++cc) v[rr][cc] = xb[lbase + rr * ZO_RS + cc];
+        // plane p contributes to output p - 2 + k with the dz = 2 - k slice
 #pragma unroll
-            for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[ab[j] + rdelta];
-            const f32x4 e = mfma32(w0, xb, f32x4{0.f, 0.f, 0.f, 0.f});
-            const bool valid = qin && vxy[gi];
-            bf16x4 iv;
+        for (int k = 0; k < 5; ++k) {
+            const float* wk = Wc + (4 - k) * 25;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) iv[i] = (bf16)e[i];
-            if (!valid) iv = bf16x4{};
-            if (keep) {
-                const int hy = 2 * w + (gi >> 1), hx = 16 * (gi & 1) + vl;
-                if (valid && hx >= 1 && hx <= OT_X && hy >= 1 && hy <= OT_Y && q >= zs && q < ze)
-                    *reinterpret_cast<bf16x4*>(keep + ((size_t)q * sxy + (size_t)((hy0 + hy) * d.nx + hx0 + hx)) * 16 +
-                                               4 * kg) = iv;
-            }
-            const f32x4 y0 = mfma16(wo0, iv, f32x4{0.f, 0.f, 0.f, 0.f});
-            const f32x4 y1 = mfma16(wo1, iv, f32x4{0.f, 0.f, 0.f, 0.f});
-            // taps 4 kg + i and 16 + 4 kg + i; 27..31 land in rows no one reads
-            float* yr = ys + ybw + (gi >> 1) * HT_X + 16 * (gi & 1);
+            for (int dy = 0; dy < 5; ++dy)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                yr[i * YT] = y0[i];
-                yr[(16 + i) * YT] = y1[i];
-            }
-        }
-        kvs_tiling::lds_barrier();
-        if (has_out) {
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const float* yy = ys + ybase + dy * HT_X + dx;
-                    const int tin = 3 * (dy + 1) + (dx + 1);
-                    a_next += yy[tin * YT];
-                    a_cur += yy[(9 + tin) * YT];
-                    a_prev += yy[(18 + tin) * YT];
+                for (int dx = 0; dx < 5; ++dx) {
+                    const float wt = wk[dy * 5 + dx];
+                    a0[k] = fmaf(wt, v[dy][dx], a0[k]);
+                    a1[k] = fmaf(wt, v[dy + 1][dx], a1[k]);
                 }
-            const int o = q - 1;
-            if (o >= zs && o < ze) {
-                // coarse correction: trilinear weights 3/4, 1/4 per axis
-                float up = 0.f;
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-#pragma unroll
-                        for (int e = 0; e < 2; ++e)
-                            up = fmaf((a ? 0.25f : 0.75f) * (b ? 0.25f : 0.75f) * (e ? 0.25f : 0.75f),
-                                      gzv[4 * a + 2 * b + e], up);
-                if (out_in) {
-                    const bool inner = inner_xy && o >= 1 && o <= d.nz - 2;
-                    z[(size_t)o * sxy + (size_t)(gyo * d.nx + gxo)] = inner ? out_scale * (double)(a_prev + up) : 0.0;
-                }
-                if (o + 1 < ze) gzload(o + 1, gzv);
-            }
-            a_prev = a_cur;
-            a_cur = a_next;
-            a_next = 0.f;
         }
+        const int o = p - 2;
+        if (o >= zs && o < ze) {
+            const float* g = gs[buf];
+            const float up0 = 0.75f * (0.75f * g[gI0 + gIx] + 0.25f * g[gI0 + gJx]) +
+                              0.25f * (0.75f * g[gJ0 + gIx] + 0.25f * g[gJ0 + gJx]);
+            const float up1 = 0.75f * (0.75f * g[gI1 + gIx] + 0.25f * g[gI1 + gJx]) +
+                              0.25f * (0.75f * g[gJ1 + gIx] + 0.25f * g[gJ1 + gJx]);
+            const bool inz = o >= 1 && o <= d.nz - 2;
+            const size_t zo = (size_t)o * sxy + (size_t)yo * d.nx + xo;
+            if (st0) z[zo] = in0 && inz ? out_scale * (double)(a0[0] + up0) : 0.0;
+            if (st1) z[zo + d.nx] = in1 && inz ? out_scale * (double)(a1[0] + up1) : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a0[k] = a0[k + 1];
+            a1[k] = a1[k + 1];
+        }
+        a0[4] = 0.f;
+        a1[4] = 0.f;
+    }
+}
+
+// e0 = bf16(conv(x; W0)) at every voxel, for a training forward pass that
+// keeps it (the backward pass of the output layer reads it).
+__global__ void e0_keep_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, const bf16* __restrict__ W0,
+                               bf16* __restrict__ e0) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= d.n()) return;
+    const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
+    const int x = (int)(v % d.nx), y = (int)((v / d.nx) % d.ny), zz = (int)(v / ((long long)d.nx * d.ny));
+    float xt[27];
+    for (int tap = 0; tap < 27; ++tap) {
+        const int gx = x + tap_dx(tap), gy = y + tap_dy(tap), gzz = zz + tap_dz(tap);
+        const bool in = gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gzz >= 0 && gzz < d.nz;
+        xt[tap] = in ? (float)(bf16)(float)(in_scale * r[((size_t)gzz * d.ny + gy) * d.nx + gx]) : 0.f;
+    }
+    for (int c0 = 0; c0 < 16; c0 += 8) {
+        bf16x8 o;
+        for (int c = 0; c < 8; ++c) {
+            float s = 0.f;
+            for (int tap = 0; tap < 27; ++tap) s = fmaf((float)W0[(c0 + c) * 32 + tap], xt[tap], s);
+            o[c] = (bf16)s;
+        }
+        *reinterpret_cast<bf16x8*>(e0 + v * 16 + c0) = o;
     }
 }
 
@@ -840,9 +812,9 @@ OutLaunch first_pool_launch(Dims d) {
 
 OutLaunch out_launch(Dims d) {
     OutLaunch L;
-    L.ntx = (d.nx + OT_X - 1) / OT_X;
-    L.nty = (d.ny + OT_Y - 1) / OT_Y;
-    static const int cap = kvs_tiling::resident_blocks(out_kernel, 256);
+    L.ntx = (d.nx + ZO_TX - 1) / ZO_TX;
+    L.nty = (d.ny + ZO_TY - 1) / ZO_TY;
+    static const int cap = kvs_tiling::resident_blocks(zout_kernel, 256);
     L.zchunk = kvs_tiling::choose_kchunk(L.ntx * L.nty, d.nz, cap);
     L.nblocks = L.ntx * L.nty * ((d.nz + L.zchunk - 1) / L.zchunk);
     return L;
@@ -1156,7 +1128,7 @@ struct kvs_unet {
     bf16* wt = nullptr;      // device bf16 transposed weights (for the backward pass)
     float* w_proj = nullptr; // device fp32 (bf16-rounded) projection weights [C0]
     float* w_out = nullptr;  // device fp32 (bf16-rounded) output weights [27][C0] (backward pass)
-    bf16* w_outT = nullptr;  // device bf16 output weights [32 taps][C0], taps >= 27 zero (forward MFMA)
+    float* w_comp = nullptr; // device fp32 composed output stencil [5][5][5] (dz, dy, dx): W_out after W0
     float* master = nullptr; // device fp32 master weights (flat)
     float* grad = nullptr;   // device fp32 gradient (flat, same layout)
     float* adam_m = nullptr;
@@ -1352,9 +1324,14 @@ hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, doubl
                                           s, stop)) != hipSuccess)
         return e;
     const OutLaunch ol = out_launch(d);
-    hipLaunchKernelGGL(out_kernel, dim3(ol.nblocks), dim3(256), 0, s, r, ctl, d, ol.ntx, ol.nty, ol.zchunk,
-                       u->w + u->w_off[0], u->w_outT, u->gz, z, keep ? u->e0k : nullptr);
+    hipLaunchKernelGGL(zout_kernel, dim3(ol.nblocks), dim3(256), 0, s, r, ctl, d, ol.ntx, ol.nty, ol.zchunk, u->w_comp,
+                       u->gz, z);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (keep) {
+        hipLaunchKernelGGL(e0_keep_kernel, dim3(nblocks256(d.n())), dim3(256), 0, s, r, ctl, d, u->w + u->w_off[0],
+                           u->e0k);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     u->kept = keep;
     return hipSuccess;
 }
@@ -1520,17 +1497,25 @@ kvs_status upload_weights(kvs_unet* u) {
     const float* mp = u->host_master.data() + u->m_off[(size_t)(nl - 2)];
     for (size_t q = 0; q < wpj.size(); ++q) wpj[q] = (float)(bf16)mp[q];
     std::vector<float> wo((size_t)27 * u->c0);
-    std::vector<bf16> woT((size_t)32 * u->c0, (bf16)0.f);  // [tap][c], taps 27..31 zero
     const float* mo = u->host_master.data() + u->m_off[(size_t)(nl - 1)];
-    for (size_t q = 0; q < wo.size(); ++q) {
-        wo[q] = (float)(bf16)mo[q];
-        woT[q] = (bf16)mo[q];
-    }
+    for (size_t q = 0; q < wo.size(); ++q) wo[q] = (float)(bf16)mo[q];
+    // composed output stencil: Wc[t1 + t2] += sum_c W_out[t1][c] W0[c][t2]
+    // (bf16-rounded factors, FP64 sums, one rounding to FP32)
+    std::vector<double> wc(125, 0.0);
+    const float* m0 = u->host_master.data() + u->m_off[0];  // W0[c][tap], ci = 1
+    for (int t1 = 0; t1 < 27; ++t1)
+        for (int t2 = 0; t2 < 27; ++t2) {
+            const int dz = t1 / 9 + t2 / 9, dy = (t1 / 3) % 3 + (t2 / 3) % 3, dx = t1 % 3 + t2 % 3;
+            double acc = 0.0;
+            for (int c = 0; c < u->c0; ++c) acc += (double)wo[(size_t)(t1 * u->c0 + c)] * (double)(float)(bf16)m0[c * 27 + t2];
+            wc[(size_t)(25 * dz + 5 * dy + dx)] += acc;
+        }
+    std::vector<float> wcf(wc.begin(), wc.end());
     if (hipMemcpy(u->w, wb.data(), sizeof(bf16) * wb.size(), hipMemcpyHostToDevice) != hipSuccess ||
         (u->n_wt > 0 && hipMemcpy(u->wt, wtb.data(), sizeof(bf16) * u->n_wt, hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemcpy(u->w_proj, wpj.data(), sizeof(float) * wpj.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->w_out, wo.data(), sizeof(float) * wo.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(u->w_outT, woT.data(), sizeof(bf16) * woT.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(u->w_comp, wcf.data(), sizeof(float) * wcf.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->master, u->host_master.data(), sizeof(float) * u->n_master, hipMemcpyHostToDevice) != hipSuccess)
         return ufail(u, KVS_EDEVICE, "weight upload failed");
     return KVS_OK;
@@ -1559,7 +1544,7 @@ kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_un
     ok = ok && hipMalloc(&u->wt, sizeof(bf16) * std::max<int64_t>(u->n_wt, 1)) == hipSuccess;
     ok = ok && hipMalloc(&u->w_proj, sizeof(float) * c0) == hipSuccess;
     ok = ok && hipMalloc(&u->w_out, sizeof(float) * 27 * c0) == hipSuccess;
-    ok = ok && hipMalloc(&u->w_outT, sizeof(bf16) * 32 * c0) == hipSuccess;
+    ok = ok && hipMalloc(&u->w_comp, sizeof(float) * 125) == hipSuccess;
     for (float** p : {&u->master, &u->grad, &u->adam_m, &u->adam_v})
         ok = ok && hipMalloc(p, sizeof(float) * u->n_master) == hipSuccess;
     ok = ok && hipMemset(u->grad, 0, sizeof(float) * u->n_master) == hipSuccess;
@@ -1587,7 +1572,7 @@ void kvs_unet_destroy(kvs_unet* u) {
     ufree(u->wt);
     ufree(u->w_proj);
     ufree(u->w_out);
-    ufree(u->w_outT);
+    ufree(u->w_comp);
     ufree(u->master);
     ufree(u->grad);
     ufree(u->adam_m);

@@ -89,6 +89,44 @@ def test_network_forward_matches_oracle(kvs):
     assert err < 2e-2
 
 
+@pytest.mark.parametrize("dims", [(70, 19, 23), (130, 9, 41), (5, 4, 3)])
+def test_output_stencil_matches_oracle(kvs, dims):
+    """Only the first and the output layer non-zero, so gz = 0 and z is the
+    fine-level path alone: conv(conv(x; W0); W_out) with the unrounded e0,
+    which the GPU applies as one composed 5x5x5 FP32 stencil.  Several x and
+    y tiles with ragged tails and several z segments; within 1e-5 of max|z|
+    elementwise (FP32 sums of 125 terms against FP64)."""
+    import torch
+    nx, ny, nz = dims
+    say(f"case output stencil {dims}")
+    rng = np.random.default_rng(nx + ny + nz)
+    shapes = unet.layer_shapes(16, 32, 64, 4)
+    parts = []
+    for li, (ci, co, dl) in enumerate(shapes):
+        n = unet.layer_size(ci, co, dl)
+        keep = li == 0 or li == len(shapes) - 1
+        parts.append(rng.standard_normal(n) / np.sqrt(unet.layer_taps(dl) * ci) if keep else np.zeros(n))
+    w = np.concatenate(parts).astype(np.float32)
+    r = np.zeros((nz, ny, nx))
+    r[1:-1, 1:-1, 1:-1] = rng.standard_normal((nz - 2, ny - 2, nx - 2))
+    net = kvs.kvs_unet_create((16, 32, 64), 4)
+    try:
+        kvs.kvs_unet_set_weights(net, w)
+        rd = torch.from_numpy(r).cuda()
+        zd = torch.full_like(rd, np.nan)
+        kvs.kvs_unet_forward(net, rd.data_ptr(), 0.7, 2.0, zd.data_ptr(), (nx, ny, nz),
+                             torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        z = zd.cpu().numpy()
+    finally:
+        kvs.kvs_unet_destroy(net)
+    zo = unet.forward(r, 0.7, 2.0, w.astype(np.float64), nbott=4)
+    assert np.isfinite(z).all()
+    assert not z[0].any() and not z[-1].any() and not z[:, 0].any() and not z[:, :, -1].any()
+    scale = max(np.abs(zo).max(), 1e-300)
+    assert np.max(np.abs(z - zo)) <= 1e-5 * scale, np.max(np.abs(z - zo)) / scale
+
+
 def random_weights(rng, nbott=4, scale=1.0):
     shapes = unet.layer_shapes(16, 32, 64, nbott)
     return np.concatenate([scale * rng.standard_normal(unet.layer_size(ci, co, dl)) / np.sqrt(unet.layer_taps(dl) * ci)

@@ -124,3 +124,23 @@ def test_backward_matches_finite_differences():
         fd = (L(w + 1e-3 * d) - L(w - 1e-3 * d)) / 2e-3
         assert np.dot(g, d) == pytest.approx(fd, rel=1e-9), li
         off += n
+
+
+def test_shift_beyond_the_grid_is_zero_padding():
+    """A tap farther than the grid extent reads only padding: a dilated conv
+    on an axis shorter than its dilation keeps just the in-grid taps (brute
+    force over every voxel and tap)."""
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((3, 2, 5, 2))
+    W = rng.standard_normal((3, 27, 2))
+    got = unet.conv3(x, W, dil=4)
+    Z, Y, X = x.shape[:3]
+    ref = np.zeros((Z, Y, X, 3))
+    for z in range(Z):
+        for y in range(Y):
+            for xx in range(X):
+                for t, (dz, dy, dx) in enumerate(unet.taps()):
+                    p = (z + 4 * dz, y + 4 * dy, xx + 4 * dx)
+                    if 0 <= p[0] < Z and 0 <= p[1] < Y and 0 <= p[2] < X:
+                        ref[z, y, xx] += W[:, t, :] @ x[p]
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
