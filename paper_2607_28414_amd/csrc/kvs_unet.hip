@@ -526,12 +526,16 @@ constexpr int ZO_RX = ZO_TX + 4, ZO_RY = ZO_TY + 4, ZO_RS = 72, ZO_PLANE = ZO_RY
 constexpr int ZO_NX = ZO_RX * ZO_RY;  // staged x values per plane (816)
 constexpr int ZO_GX = ZO_TX / 2 + 2, ZO_GY = ZO_TY / 2 + 2, ZO_GN = ZO_GX * ZO_GY;  // coarse tile 34 x 6
 
-__global__ __launch_bounds__(256) void zout_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void zout_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
                                                    int nty, int zchunk, const float* __restrict__ Wc,
                                                    const float* __restrict__ gz, double* __restrict__ z) {
     __shared__ float xs[2][ZO_PLANE];
     __shared__ float gs[2][ZO_GN];
+    // weights, one dz slice per 28 floats (16-byte aligned slices, read as
+    // float4 broadcasts; as scalar operands all 125 would not fit the SGPRs)
+    __shared__ __attribute__((aligned(16))) float wsh[5 * 28];
     if (ctl.stop && *ctl.stop) return;
+    if (threadIdx.x < 125) wsh[(threadIdx.x / 25) * 28 + threadIdx.x % 25] = Wc[threadIdx.x];
     const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
     const double out_scale = ctl.out_dev ? *ctl.out_dev : ctl.out_v;
     const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
@@ -610,9 +614,24 @@ __global__ __launch_bounds__(256) void zout_kernel(const double* __restrict__ r,
 #pragma unroll
             for (int cc = 0; cc < 5; ++cc) v[rr][cc] = xb[lbase + rr * ZO_RS + cc];
         // plane p contributes to output p - 2 + k with the dz = 2 - k slice
+        // the weight slice of the next k is read while this one is used; the
+        // scheduling barriers keep two slices live at most
+        // an opaque base offset keeps the weight reads in the loop (hoisted
+        // out, all 125 would stay live in registers)
+        int wo = 0;
+        asm volatile("" : "+s"(wo));
+        const float* wb = wsh + wo;
+        float4 wc[7], wn[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) wc[q] = *reinterpret_cast<const float4*>(wb + 4 * 28 + 4 * q);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            const float* wk = Wc + (4 - k) * 25;
+            if (k < 4) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) wn[q] = *reinterpret_cast<const float4*>(wb + (3 - k) * 28 + 4 * q);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            const float* wk = reinterpret_cast<const float*>(wc);
 #pragma unroll
             for (int dy = 0; dy < 5; ++dy)
 #pragma unroll
@@ -621,6 +640,12 @@ __global__ __launch_bounds__(256) void zout_kernel(const double* __restrict__ r,
                     a0[k] = fmaf(wt, v[dy][dx], a0[k]);
                     a1[k] = fmaf(wt, v[dy + 1][dx], a1[k]);
                 }
+            // the sums of this slice are final here (not sunk to the loop end,
+            // where every slice's weights would be live at once)
+            asm volatile("" : "+v"(a0[k]), "+v"(a1[k]));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 7; ++q) wc[q] = wn[q];
         }
         const int o = p - 2;
         if (o >= zs && o < ze) {
