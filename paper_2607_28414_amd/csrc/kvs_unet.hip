@@ -30,6 +30,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kvs_internal.hpp"
@@ -46,6 +47,15 @@ namespace {
 struct Dims {
     int nx, ny, nz;
     __host__ __device__ long long n() const { return (long long)nx * ny * nz; }
+};
+
+// 16 bytes of zeros: the source of taps outside the grid in the gathering conv
+__device__ __attribute__((aligned(16))) bf16 kZeroRow[8];
+
+// Bricks of 16 x NV x 4 voxels covering a grid (counts along x, y, z);
+// bx = 0 selects blocks of consecutive voxels instead.
+struct Bricks {
+    int bx, by, bz;
 };
 
 __host__ __device__ inline Dims coarse(Dims d) { return Dims{(d.nx + 1) / 2, (d.ny + 1) / 2, (d.nz + 1) / 2}; }
@@ -76,12 +86,15 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
 // (constant offsets for wavefronts away from the boundary).  Outputs are
 // rounded once (BF16) or stored as FP32.  Every wavefront runs the slab loop
 // (its barriers) even when its voxels lie beyond the grid.
+// The register budget is capped for two wavefronts per SIMD: uncapped, the
+// 64-channel instances took 260 registers and ran one wavefront per SIMD,
+// which leaves the gather loads' latency exposed.
 constexpr int WS = 6;  // K chunks per weight slab
 
 template <int CI, int CO, int NV, typename OUT>
-__global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Dims d,
-                                                  int dil, const bf16* __restrict__ W, OUT* __restrict__ out,
-                                                  const int* stop) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3_mfma(const bf16* __restrict__ A, Dims d,
+                                                  int dil, Bricks bk, const bf16* __restrict__ W,
+                                                  OUT* __restrict__ out, const int* stop) {
     static_assert(CI % 8 == 0 && CO % 16 == 0, "channel counts");
     constexpr int K = 27 * CI;
     constexpr int KP = (K + 31) / 32 * 32;
@@ -94,20 +107,37 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Di
     __shared__ __attribute__((aligned(16))) bf16 wsl[2][CO * WROW];
     if (stop && *stop) return;
     const int t = threadIdx.x, lane = t & 63;
+    // Voxels of the block: with bricks (dilation 1), brick (kx, ky, kz) of
+    // 16 x NV x 4 voxels, wavefront w taking layer z = w, group g row y = g,
+    // lane vl column x = vl (a compact 3-D footprint per XCD); otherwise 4 x
+    // 16 NV consecutive voxels in memory order.
     const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
-    const long long v0 = ((long long)blk * 4 + (t >> 6)) * (16 * NV);
-    const long long N = d.n();
     const int vl = lane & 15, kg = lane >> 4;
     int gx[NV], gy[NV], gz[NV];
     bool valid[NV];
+    int vox[NV];  // voxel counts stay below 2^31
+    if (bk.bx > 0) {
+        const int kx = blk % bk.bx, ky = (blk / bk.bx) % bk.by, kz = blk / (bk.bx * bk.by);
 #pragma unroll
-    for (int g = 0; g < NV; ++g) {  // voxel counts stay below 2^31
-        const long long v = v0 + 16 * g + vl;
-        valid[g] = v < N;
-        const unsigned vc = valid[g] ? (unsigned)v : 0u, row = vc / (unsigned)d.nx;
-        gx[g] = (int)(vc - row * (unsigned)d.nx);
-        gy[g] = (int)(row % (unsigned)d.ny);
-        gz[g] = (int)(row / (unsigned)d.ny);
+        for (int g = 0; g < NV; ++g) {
+            gx[g] = 16 * kx + vl;
+            gy[g] = NV * ky + g;
+            gz[g] = 4 * kz + (t >> 6);
+            valid[g] = gx[g] < d.nx && gy[g] < d.ny && gz[g] < d.nz;
+            vox[g] = valid[g] ? gx[g] + d.nx * (gy[g] + d.ny * gz[g]) : 0;
+        }
+    } else {
+        const long long v0 = ((long long)blk * 4 + (t >> 6)) * (16 * NV);
+#pragma unroll
+        for (int g = 0; g < NV; ++g) {
+            const long long v = v0 + 16 * g + vl;
+            valid[g] = v < d.n();
+            const unsigned vc = valid[g] ? (unsigned)v : 0u, row = vc / (unsigned)d.nx;
+            gx[g] = (int)(vc - row * (unsigned)d.nx);
+            gy[g] = (int)(row % (unsigned)d.ny);
+            gz[g] = (int)(row / (unsigned)d.ny);
+            vox[g] = (int)vc;
+        }
     }
     bool deep = true;
 #pragma unroll
@@ -117,8 +147,28 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Di
     const bool fast = __all(deep);
     const bf16* base[NV];
 #pragma unroll
-    for (int g = 0; g < NV; ++g) base[g] = A + (size_t)(valid[g] ? v0 + 16 * g + vl : 0) * CI;
-    const int sy = d.nx, sz = d.nx * d.ny;
+    for (int g = 0; g < NV; ++g) base[g] = A + (size_t)vox[g] * CI;
+    // taps whose source voxel lies inside the grid: bit tap of tm[g]
+    unsigned tm[NV];
+#pragma unroll
+    for (int g = 0; g < NV; ++g) {
+        const unsigned mx = (gx[g] >= dil ? 1u : 0u) | 2u | (gx[g] + dil < d.nx ? 4u : 0u);
+        const unsigned my = (gy[g] >= dil ? 1u : 0u) | 2u | (gy[g] + dil < d.ny ? 4u : 0u);
+        const unsigned mz = (gz[g] >= dil ? 1u : 0u) | 2u | (gz[g] + dil < d.nz ? 4u : 0u);
+        unsigned m = 0u;
+#pragma unroll
+        for (int tap = 0; tap < 27; ++tap)
+            m |= ((mx >> (tap % 3)) & (my >> ((tap / 3) % 3)) & (mz >> (tap / 9)) & 1u) << tap;
+        tm[g] = valid[g] ? m : 0u;
+    }
+    // per chunk and lane group: source offset (elements) and tap index; taps
+    // >= 27 (K padding) have zero weights and take tap 26's offset
+    static_assert(NC * 4 <= 256, "one tap-table entry per thread");
+    __shared__ int2 ktab[NC * 4];
+    if (t < NC * 4) {
+        const int k0 = (t / 4) * 32 + 8 * (t % 4), tap = k0 / CI, tc = min(tap, 26);
+        ktab[t] = int2{dil * (tap_dx(tc) + d.nx * tap_dy(tc) + d.nx * d.ny * tap_dz(tc)) * CI + k0 % CI, tap};
+    }
 
     // weight slab staging: item -> (output row, 16-byte piece of the slab)
     bf16x8 wreg[IPT];
@@ -147,61 +197,74 @@ __global__ __launch_bounds__(256) void conv3_mfma(const bf16* __restrict__ A, Di
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    wload(0);
-    wstore(0);
-    kvs_tiling::lds_barrier();
-    for (int sl = 0; sl < NSL; ++sl) {
-        const int buf = sl & 1;
-        if (sl + 1 < NSL) wload(sl + 1);
-#pragma unroll 2
-        for (int kk = 0; kk < WS; ++kk) {
-            const int kc = sl * WS + kk;
-            if (kc >= NC) break;
-            const int k0 = kc * 32 + 8 * kg;
+    // Activation patch of chunk kc for every group.  Loads are unconditional
+    // (clamped addresses; chunks past the end re-read the last one) and masked
+    // when the patch is used, so the gather of chunk kc + 1 stays in flight
+    // while chunk kc runs, across the LDS-only barriers.  Two patch buffers
+    // alternate by chunk parity (no register copies that would wait on a
+    // load), and the interior case (constant offsets, no masks) is its own
+    // loop.
+    auto run = [&](auto fast_tag) {
+        constexpr bool FAST = decltype(fast_tag)::value;
+        // out-of-grid taps read a row of zeros instead of being masked
+        auto gather = [&](int kc, bf16x8 (&a8)[NV]) {
+            const int2 e = ktab[min(kc, NC - 1) * 4 + kg];
+#pragma unroll
+            for (int g = 0; g < NV; ++g) {
+                const bf16* src = base[g] + e.x;
+                if constexpr (!FAST) src = ((tm[g] >> e.y) & 1u) ? src : kZeroRow;
+                a8[g] = *reinterpret_cast<const bf16x8*>(src);
+            }
+        };
+        auto compute = [&](int kc, const bf16x8 (&a8)[NV]) {
+            const int sl = kc / WS, kk = kc % WS;
+            if (kk == 0) {
+                if (sl > 0) {
+                    kvs_tiling::lds_barrier();  // every wavefront is done with the old slab of this buffer
+                    wstore(sl & 1);
+                    kvs_tiling::lds_barrier();
+                }
+                if (sl + 1 < NSL) wload(sl + 1);
+            }
             bf16x8 wf[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m)
-                wf[m] = *reinterpret_cast<const bf16x8*>(&wsl[buf][(16 * m + vl) * WROW + 32 * kk + 8 * kg]);
-            bf16x8 a8[NV];
-            if (fast) {
-                // taps >= 27 (K padding) have zero weights and read tap 26 instead
-                const int tap = min(k0 / CI, 26), ci0 = k0 % CI;
-                const int off = dil * (tap_dx(tap) + sy * tap_dy(tap) + sz * tap_dz(tap)) * CI + ci0;
-#pragma unroll
-                for (int g = 0; g < NV; ++g) a8[g] = *reinterpret_cast<const bf16x8*>(base[g] + off);
-            } else {
-                // unconditional loads from clamped addresses, masked after arrival
-                const int tap = k0 / CI, ci0 = k0 % CI;
-                const bool tap_ok = tap < 27;
-                const int ox = dil * tap_dx(tap), oy = dil * tap_dy(tap), oz = dil * tap_dz(tap);
-#pragma unroll
-                for (int g = 0; g < NV; ++g) {
-                    const int px = gx[g] + ox, py = gy[g] + oy, pz = gz[g] + oz;
-                    const bool ok = tap_ok && valid[g] && px >= 0 && px < d.nx && py >= 0 && py < d.ny && pz >= 0 &&
-                                    pz < d.nz;
-                    const int cx = min(max(px, 0), d.nx - 1), cy = min(max(py, 0), d.ny - 1),
-                              cz = min(max(pz, 0), d.nz - 1);
-                    const size_t p = (size_t)cx + (size_t)d.nx * (size_t)(cy + d.ny * cz);
-                    const bf16x8 v = *reinterpret_cast<const bf16x8*>(A + p * CI + ci0);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) a8[g][j] = ok ? v[j] : (bf16)0.f;
-                }
-            }
+                wf[m] = *reinterpret_cast<const bf16x8*>(&wsl[sl & 1][(16 * m + vl) * WROW + 32 * kk + 8 * kg]);
 #pragma unroll
             for (int g = 0; g < NV; ++g)
 #pragma unroll
                 for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], a8[g], acc[g][m]);
+        };
+        // the scheduling barriers keep each gather ahead of the chunk that
+        // runs while it is in flight (left alone, the scheduler moves loads
+        // next to their use)
+        bf16x8 pa[NV], pb[NV];
+        gather(0, pa);
+        for (int kc = 0; kc < NC; kc += 2) {
+            gather(kc + 1, pb);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(kc, pa);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kc + 1 < NC) {
+                gather(kc + 2, pa);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(kc + 1, pb);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
-        if (sl + 1 < NSL) {
-            kvs_tiling::lds_barrier();  // every wavefront is done with buffer buf ^ 1's old slab
-            wstore(buf ^ 1);
-            kvs_tiling::lds_barrier();
-        }
-    }
+    };
+
+    wload(0);
+    wstore(0);
+    kvs_tiling::lds_barrier();
+    if (fast)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 #pragma unroll
     for (int g = 0; g < NV; ++g) {
         if (!valid[g]) continue;
-        const long long v = v0 + 16 * g + vl;
+        const size_t v = (size_t)vox[g];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             if constexpr (sizeof(OUT) == 2) {
@@ -234,8 +297,12 @@ struct ZmGeom {
     static constexpr int IPT = (ITEMS + 255) / 256;      // items per thread
 };
 
+// Two wavefronts per SIMD where the register file allows it without spills
+// (the 32 -> 32 instance keeps its registers and runs one).
+constexpr int zm_waves(int ci, int co) { return ci == 32 && co == 32 ? 1 : 2; }
+
 template <int CI, int CO, int TY, bool PROJ, typename OUT>
-__global__ __launch_bounds__(256) void conv3_zm(const bf16* __restrict__ A, Dims d, int ntx, int nty, int zchunk,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(zm_waves(CI, CO)))) void conv3_zm(const bf16* __restrict__ A, Dims d, int ntx, int nty, int zchunk,
                                                 const bf16* __restrict__ W, OUT* __restrict__ out,
                                                 const float* __restrict__ wp, float* __restrict__ gz,
                                                 const int* stop) {
@@ -801,11 +868,18 @@ hipError_t launch_conv(int ci, int co, const bf16* A, Dims d, int dil, const bf1
                        const int* stop = nullptr) {
 #define KVS_CONV_CASE(CI_, CO_)                                                                                \
     if (ci == CI_ && co == CO_) {                                                                              \
-        if (dil == 1 && CI_ <= 32 && CO_ <= 32)                                                                \
-            return launch_zm<CI_, CO_, false, OUT>(A, d, W, out, nullptr, nullptr, s, stop);                   \
+        if constexpr (CI_ <= 32 && CO_ <= 32) {                                                                \
+            if (dil == 1) return launch_zm<CI_, CO_, false, OUT>(A, d, W, out, nullptr, nullptr, s, stop);     \
+        }                                                                                                      \
         constexpr int NV = conv_nv(CI_, CO_);                                                                  \
-        const int nb = (int)((d.n() + 64 * NV - 1) / (64 * NV));                                               \
-        hipLaunchKernelGGL((conv3_mfma<CI_, CO_, NV, OUT>), dim3(nb), dim3(256), 0, s, A, d, dil, W, out, stop); \
+        /* bricks for dilation 1 (measured faster there; with dilation the       \
+           linear order was as fast and wastes no lanes on partial bricks) */    \
+        const Bricks bk = dil == 1 ? Bricks{(d.nx + 15) / 16, (d.ny + NV - 1) / NV, (d.nz + 3) / 4}                \
+                                   : Bricks{0, 0, 0};                                                          \
+        const long long nb = dil == 1 ? (long long)bk.bx * bk.by * bk.bz : (d.n() + 64 * NV - 1) / (64 * NV);  \
+        if (nb >= (1LL << 31)) return hipErrorInvalidValue;                                                    \
+        hipLaunchKernelGGL((conv3_mfma<CI_, CO_, NV, OUT>), dim3((unsigned)nb), dim3(256), 0, s, A, d, dil, bk, W, \
+                           out, stop);                                                                         \
         return hipGetLastError();                                                                              \
     }
     KVS_CONV_CASE(16, 32)
