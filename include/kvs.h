@@ -225,9 +225,11 @@ kvs_status kvs_peak_map(const kvs_ctx* ctx, int32_t axis, int64_t index, double*
 
 /* ---- measurement -------------------------------------------------------- */
 
-/* When on, kvs_step brackets every launch of the FDTD step kernel with HIP
- * events on the context's stream; kvs_kernel_time returns the summed
- * duration [ms] and the launch count since timing was switched on. */
+/* When on, every launch of the FDTD step kernel by kvs_step records its own
+ * start and end in a pair of HIP events on the context's stream (events
+ * attached to the dispatch, hipExtLaunchKernel: the kernel's duration, no
+ * extra queue packets); kvs_kernel_time returns the summed duration [ms] and
+ * the launch count since timing was switched on. */
 kvs_status kvs_enable_kernel_timing(kvs_ctx* ctx, int32_t on);
 kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* launches);
 
@@ -368,9 +370,9 @@ kvs_status kvs_set_step_variant(kvs_ctx* ctx, int32_t v);
  * issues tiles XCD by XCD in contiguous ranges (y-adjacent tiles share L2). */
 kvs_status kvs_set_step_tuning(kvs_ctx* ctx, int32_t v, int32_t zchunk, int32_t remap);
 /* Time every variant on this context's grid, precision and medium, each with
- * the automatic z split and with 32-plane z segments (trial_steps >= 1
- * launches each, after one untimed launch), and keep the fastest.
- * ms_per_launch[v] is the better of the two for variant v.  The state is not advanced: trial launches only write the
+ * the automatic z split and with 16-, 32- and 64-plane z segments
+ * (trial_steps >= 1 launches each, after one untimed launch), and keep the
+ * fastest.  ms_per_launch[v] is the best z split's time for variant v.  The state is not advanced: trial launches only write the
  * buffers the next real step overwrites.  Needs material and dt.  chosen and
  * ms_per_launch (cap entries, one per variant) may be NULL. */
 kvs_status kvs_autotune_step(kvs_ctx* ctx, int32_t trial_steps, int32_t* chosen, double* ms_per_launch,

@@ -536,14 +536,16 @@ kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
     for (int64_t q = 0; q < nsteps; ++q) {
         const int64_t n = c->step;
         const double gn = n < n_env ? c->env[(size_t)n] : 0.0;
-        hipEvent_t ea = nullptr, eb = nullptr;
         if (c->timing) {
+            hipEvent_t ea = nullptr, eb = nullptr;
             s = next_event_pair(c, &ea, &eb);
             if (s != KVS_OK) return s;
-            API_HIP(c, hipEventRecord(ea, c->stream));
+            c->launch_ev[0] = ea;
+            c->launch_ev[1] = eb;
         }
-        API_HIP(c, kvs_launch_step(c, gn));
-        if (c->timing) API_HIP(c, hipEventRecord(eb, c->stream));
+        const hipError_t le = kvs_launch_step(c, gn);
+        c->launch_ev[0] = c->launch_ev[1] = nullptr;
+        API_HIP(c, le);
         c->cur = 1 - c->cur;
         if (c->nprobes > 0) {
             API_HIP(c, kvs_launch_probe_gather(c, c->u[c->cur], c->trace_steps));
@@ -755,13 +757,13 @@ kvs_status kvs_autotune_step(kvs_ctx* c, int32_t trial_steps, int32_t* chosen, d
     API_HIP(c, hipEventCreate(&e0));
     API_HIP(c, hipEventCreate(&e1));
     const int nv = kvs_step_variant_count();
-    const int zchunks[2] = {0, 32};  // auto split, and 32-plane segments
+    const int zchunks[4] = {0, 16, 32, 64};  // auto split, and fixed segment lengths
     int best = 0, best_z = 0;
     double best_ms = 1e300;
     const int saved_z = c->step_zchunk;
     for (int v = 0; v < nv; ++v) {
         double v_best = 1e300;
-        for (int zi = 0; zi < 2; ++zi) {
+        for (int zi = 0; zi < 4; ++zi) {
             c->step_zchunk = zchunks[zi];
             // warm-up launch, then timed launches; cur is not flipped, so every
             // launch recomputes the same next state from the same current state

@@ -103,6 +103,9 @@ struct kvs_ctx {
     int step_variant = 0;
     int step_zchunk = 0;
     int step_remap = 1;
+    // when set, the next step-kernel launch records its own start and end in
+    // these events (the dispatch's timestamps, no extra queue packets)
+    hipEvent_t launch_ev[2] = {nullptr, nullptr};
 
     // running peak of |u| on registered grid planes: one map of T per plane,
     // concatenated in registration order (peak_off[p] = first cell of plane p)

@@ -18,6 +18,8 @@
 // per-thread register queue (k-1, k, k+1, with k+2 prefetched).  Each cell's
 // state is therefore read from HBM once per step; halo rows of adjacent tiles
 // are served by L2 because tiles are issued XCD-contiguously (see tile_of).
+#include <hip/hip_ext.h>
+
 #include "kvs_internal.hpp"
 #include "kvs_tiling.hpp"
 
@@ -414,7 +416,10 @@ hipError_t launch_shape(kvs_ctx* c, StepArgs<T> a) {
     a.kchunk = c->step_zchunk > 0 ? std::min(c->step_zchunk, a.nz - 2) : choose_kchunk(a.gx * a.gy, a.nz - 2, cap);
     a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
     const int blocks = a.gx * a.gy * a.gz;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64, BY), 0, c->stream, a);
+    if (c->launch_ev[0])
+        hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(64, BY), 0, c->stream, c->launch_ev[0], c->launch_ev[1], 0, a);
+    else
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(64, BY), 0, c->stream, a);
     return hipGetLastError();
 }
 
