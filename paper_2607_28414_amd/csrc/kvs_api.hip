@@ -77,6 +77,7 @@ void release(kvs_ctx* c) {
     dfree(c->FS);
     dfree(c->phi);
     dfree(c->r);
+    dfree(c->r2);
     dfree(c->Ap);
     dfree(c->partials);
     dfree(c->cgs);

@@ -16,6 +16,10 @@
 //            partials of r.r and r.z (reads phi, p', r; writes phi, r: 40 B)
 //   finalize: beta, the stop test, the iteration count
 // Recomputing A p' costs a few flops and saves storing and re-reading it.
+// Flexible PCG (learned preconditioner): the update writes the new residual
+// into a second buffer, and the network's output kernel, as it writes z, also
+// sums z.r, z.r_old and r.r_old per block, from which the Polak-Ribiere beta
+// z.(r - r_old) / (z_old . r_old) follows without another sweep.
 // p is ping-ponged because sweep 1 reads p at neighbours while writing p'.
 // Both sweeps are LDS-staged z-marches like the FDTD step (64 x 8 tiles,
 // straight-line memory code, plane-ahead prefetch).
@@ -269,10 +273,11 @@ __global__ __launch_bounds__(64 * SBY) void cg_dir_kernel(const CgGeom g, const 
     sweep_partials<1>(s1, 0.0, partials, npart);
 }
 
-// sweep 2: A p recomputed, phi += alpha p, r -= alpha A p, partials r.r, r.z
-__global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const SweepGeom sg, double* phi, double* r,
-                                                          const double* p, const CgState* st, double* partials,
-                                                          int npart) {
+// sweep 2: A p recomputed, phi += alpha p, r_out = r - alpha A p (r_out may
+// be r itself), partials r.r, r.z
+__global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const SweepGeom sg, double* phi,
+                                                          const double* r, double* r_out, const double* p,
+                                                          const CgState* st, double* partials, int npart) {
     if (st->done) return;
     __shared__ double lds[2][SBY + 3][68];
     const Lane L = sweep_lane(g, sg);
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const 
         const double rv = rc - alpha * ap;
         const int q = k * sxy + L.scol;
         phi[q] = L.act ? phv : 0.0;
-        r[q] = L.act ? rv : 0.0;
+        r_out[q] = L.act ? rv : 0.0;
         s1 += L.act ? rv * rv : 0.0;
         s2 += L.act ? rv * (rv * g.dinv) : 0.0;
         pm = pc;
@@ -316,67 +321,6 @@ __global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const 
     sweep_partials<2>(s1, s2, partials, npart);
 }
 
-// flexible PCG: partials of z.r, z.Ap and r.Ap (A p recomputed from p)
-__global__ __launch_bounds__(64 * SBY) void cg_fdot_kernel(const CgGeom g, const SweepGeom sg, const double* z,
-                                                           const double* r, const double* p, const CgState* st,
-                                                           double* partials, int npart) {
-    if (st->done) return;
-    __shared__ double lds[2][SBY + 3][68];
-    __shared__ double sh[3][SBY];
-    const Lane L = sweep_lane(g, sg);
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int sxy = g.nx * g.ny;
-    const int kb = L.kb, ke = L.ke;
-    double pm = p[(kb - 1) * sxy + L.col];
-    double pc = p[kb * sxy + L.col];
-    double pp = p[(kb + 1) * sxy + L.col];
-    double hc = p[kb * sxy + L.h_off];
-    double zc = z[kb * sxy + L.col], rc = r[kb * sxy + L.col];
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int k = kb; k < ke; ++k) {
-        const int buf = k & 1;
-        lds[buf][ty + 1][tx + 1] = pc;
-        lds[buf][L.h_row][L.h_col] = hc;
-        const double pn = p[min(k + 2, ke) * sxy + L.col];
-        const double hn = p[min(k + L.h_dz, ke) * sxy + L.h_off];
-        const int q1 = min(k + 1, ke - 1) * sxy + L.col;
-        const double zn = z[q1], rn = r[q1];
-        lds_barrier();
-        const double c2 = 2.0 * pc;
-        const double ap = -((lds[buf][ty + 1][tx + 2] + lds[buf][ty + 1][tx] - c2) * g.ihx2
-                            + (lds[buf][ty + 2][tx + 1] + lds[buf][ty][tx + 1] - c2) * g.ihy2
-                            + (pp + pm - c2) * g.ihz2);
-        s1 += L.act ? zc * rc : 0.0;
-        s2 += L.act ? zc * ap : 0.0;
-        s3 += L.act ? rc * ap : 0.0;
-        pm = pc;
-        pc = pp;
-        pp = pn;
-        hc = hn;
-        zc = zn;
-        rc = rn;
-    }
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    s3 = wave_sum(s3);
-    if (tx == 0) {
-        sh[0][ty] = s1;
-        sh[1][ty] = s2;
-        sh[2][ty] = s3;
-    }
-    __syncthreads();
-    if (tx == 0 && ty == 0) {
-        double a = 0, b = 0, c = 0;
-        for (int w = 0; w < SBY; ++w) {
-            a += sh[0][w];
-            b += sh[1][w];
-            c += sh[2][w];
-        }
-        partials[blockIdx.x] = a;
-        partials[npart + blockIdx.x] = b;
-        partials[2 * npart + blockIdx.x] = c;
-    }
-}
 
 // partials of (-b - A phi)^2 and b^2
 __global__ __launch_bounds__(64 * CBY) void cg_true_residual_kernel(const CgGeom g, const double* F, const double* phi,
@@ -476,16 +420,18 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
             st->fallbacks += 1;
         }
     } else if (mode == FIN_FBETA) {
-        const double zr = s1, zAp = s2, rAp = s3;
+        // Polak-Ribiere: beta = z.(r - r_old) / (z_old . r_old); Jacobi z for
+        // this iteration when z.r <= 0 or a product is not finite
+        const double zr = s1, zro = s2, rro = s3;
         const double rz_old = st->rz;
-        if (zr > 0.0 && isfinite(zr) && isfinite(zAp)) {
-            st->beta = -st->alpha * zAp / rz_old;
+        if (zr > 0.0 && isfinite(zr) && isfinite(zro)) {
+            st->beta = (zr - zro) / rz_old;
             st->rz = zr;
             st->zjacobi = 0;
         } else {
             st->fallbacks += 1;
             st->zjacobi = 1;
-            st->beta = -st->alpha * rAp * st->dinv / rz_old;
+            st->beta = st->dinv * (st->rr - rro) / rz_old;
             st->rz = st->rr * st->dinv;
         }
     } else if (mode == FIN_ALPHA) {
@@ -566,7 +512,8 @@ kvs_status fail(kvs_ctx* c, kvs_status s, const std::string& msg) {
 int64_t kvs_cg_partials_needed(const kvs_grid& gr) {
     CgGeom g = make_geom(gr);
     const int sweep_xy = ((g.nx + 63) / 64) * ((g.ny + SBY - 1) / SBY);
-    return std::max<int64_t>(nblocks(g), kvs_tiling::max_tiled_blocks(sweep_xy, g.nz - 2));
+    return std::max<int64_t>(std::max<int64_t>(nblocks(g), kvs_tiling::max_tiled_blocks(sweep_xy, g.nz - 2)),
+                             kvs_unet_out_blocks(gr));
 }
 
 #define CG_HIP(call)                                                                          \
@@ -622,30 +569,40 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
     double* z = c->Ap;  // flexible PCG: the preconditioned residual
     const int* stop = &c->cgs->done;
+    // flexible PCG keeps the previous residual for beta: the update writes
+    // the new residual into the other buffer (rb[ri] is the current one)
+    if (flexible && !c->r2) CG_HIP(hipMalloc(&c->r2, sizeof(double) * c->N));
+    double* rb[2] = {c->r, flexible ? c->r2 : c->r};
+    int ri = 0;
     if (flexible) {
-        CG_HIP(kvs_unet_precondition(c->net, c->r, z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop, c->stream));
-        hipLaunchKernelGGL(cg_fdot_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, z, c->r, c->p[pi], c->cgs, part, npart);
-        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 3, (int)FIN_FZ0,
+        // z = U(r) and the partial sums of z.r from the network's output kernel
+        const UnetDots dots{nullptr, part, npart};
+        int nbo = 0;
+        CG_HIP(kvs_unet_precondition(c->net, rb[0], z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop, c->stream,
+                                     &dots, &nbo));
+        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbo, npart, 3, (int)FIN_FZ0,
                            c->cgs);
         CG_HIP(hipGetLastError());
     }
     while (true) {
         for (int m = 0; m < chunk; ++m) {
-            hipLaunchKernelGGL(cg_dir_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->r, z, c->p[pi], c->p[1 - pi],
+            hipLaunchKernelGGL(cg_dir_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, rb[ri], z, c->p[pi], c->p[1 - pi],
                                c->cgs, part, npart);
             hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 1, (int)FIN_ALPHA,
                                c->cgs);
-            hipLaunchKernelGGL(cg_upd_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, c->r, c->p[1 - pi], c->cgs,
-                               part, npart);
+            hipLaunchKernelGGL(cg_upd_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, rb[ri], rb[1 - ri],
+                               c->p[1 - pi], c->cgs, part, npart);
             hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 2, (int)FIN_BETA,
                                c->cgs);
             if (flexible) {
-                CG_HIP(kvs_unet_precondition(c->net, c->r, z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop,
-                                             c->stream));
-                hipLaunchKernelGGL(cg_fdot_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, z, c->r, c->p[1 - pi], c->cgs,
-                                   part, npart);
-                hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 3,
+                // z = U(r_new) with the partial sums of z.r_new, z.r_old, r_new.r_old
+                const UnetDots dots{rb[ri], part, npart};
+                int nbo = 0;
+                CG_HIP(kvs_unet_precondition(c->net, rb[1 - ri], z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop,
+                                             c->stream, &dots, &nbo));
+                hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbo, npart, 3,
                                    (int)FIN_FBETA, c->cgs);
+                ri = 1 - ri;
             }
             pi = 1 - pi;
         }

@@ -71,6 +71,7 @@ struct kvs_ctx {
 
     double* phi = nullptr;
     double* r = nullptr;
+    double* r2 = nullptr;  // flexible PCG: the residual of the previous iteration (ping-pong with r)
     double* p[2] = {nullptr, nullptr};
     double* Ap = nullptr;
     double* partials = nullptr;  // 3 * npart
@@ -190,10 +191,23 @@ hipError_t kvs_batch_trial_launch(kvs_batch* b);
 hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps);
 
 // ---- learned preconditioner (kvs_unet.hip) ---------------------------------
+// Inner products the flexible PCG needs from the preconditioned residual z,
+// accumulated by the network's output kernel as it writes z (interior cells,
+// FP64): partial sums z.r, z.r_old and r.r_old per block at part[block],
+// part[npart + block], part[2 npart + block].  r_old = null: z.r only.
+struct UnetDots {
+    const double* r_old;
+    double* part;
+    int npart;
+};
 // z = out_scale * U(in_scale * r) on the context grid, scales read from
-// device memory, every kernel returns at once while *stop is set.
+// device memory, every kernel returns at once while *stop is set; with
+// dots != null also the partial sums above, over *nblocks blocks.
 hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const kvs_grid& g, const double* in_scale,
-                                 const double* out_scale, const int* stop, hipStream_t s);
+                                 const double* out_scale, const int* stop, hipStream_t s, const UnetDots* dots = nullptr,
+                                 int* nblocks = nullptr);
+// Blocks of the network's output kernel on a grid (the partial sums above).
+int64_t kvs_unet_out_blocks(const kvs_grid& g);
 
 // ---- projection (kvs_cg.hip) ---------------------------------------------
 kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep);

@@ -301,14 +301,26 @@ struct ZmGeom {
 // (the 32 -> 32 instance keeps its registers and runs one).
 constexpr int zm_waves(int ci, int co) { return ci == 32 && co == 32 ? 1 : 2; }
 
-template <int CI, int CO, int TY, bool PROJ, typename OUT>
+template <int CI, int CO, int TY, bool PROJ, typename OUT, bool POOL = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(zm_waves(CI, CO)))) void conv3_zm(const bf16* __restrict__ A, Dims d, int ntx, int nty, int zchunk,
                                                 const bf16* __restrict__ W, OUT* __restrict__ out,
                                                 const float* __restrict__ wp, float* __restrict__ gz,
-                                                const int* stop) {
+                                                const int* stop, bf16* __restrict__ pooled) {
     using G = ZmGeom<CI, TY>;
     constexpr int K = 27 * CI, KP = (K + 31) / 32 * 32, NC = KP / 32, MT = CO / 16, NG = TY / 2;
     static_assert(TY % 2 == 0 && CI % 8 == 0 && CO % 16 == 0 && (!PROJ || CO == 16), "tile");
+    // POOL: the BF16 outputs are also pooled into `pooled` (mean of the
+    // existing 2 x 2 x 2 children): a wavefront's groups g and g + 2 are the
+    // rows 2w and 2w + 1, x pairs are neighbouring lanes, z pairs consecutive
+    // planes of the segment (segments start on even planes)
+    static_assert(!POOL || (NG == 4 && sizeof(OUT) == 2 && !PROJ), "pooling layout");
+    float ps[2][MT][4];
+#pragma unroll
+    for (int xh = 0; xh < 2; ++xh)
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ps[xh][m][i] = 0.f;
     __shared__ __attribute__((aligned(16))) bf16 lds[3 * G::PL];
     if (stop && *stop) return;
     const int blk = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
@@ -411,6 +423,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(zm_waves(CI
                     *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
                 } else {
                     *reinterpret_cast<f32x4*>(out + v * CO + 16 * m + 4 * kg) = acc[g][m];
+                }
+            }
+        }
+        if constexpr (POOL) {
+#pragma unroll
+            for (int xh = 0; xh < 2; ++xh)
+#pragma unroll
+                for (int gg = 0; gg < 2; ++gg) {
+                    const int gl = w * NG + xh + 2 * gg;
+                    const bool in = x0 + 16 * (gl & 1) + vl < d.nx && y0 + (gl >> 1) < d.ny;
+#pragma unroll
+                    for (int m = 0; m < MT; ++m)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            ps[xh][m][i] += in ? (float)(bf16)acc[xh + 2 * gg][m][i] : 0.f;
+                }
+            if ((z & 1) || z == d.nz - 1) {
+                const Dims c = coarse(d);
+                const int Z = z >> 1, Y = (y0 >> 1) + w;
+#pragma unroll
+                for (int xh = 0; xh < 2; ++xh) {
+                    const int X = (x0 + 16 * xh + vl) >> 1;
+                    const int cnt = (min(2 * X + 2, d.nx) - 2 * X) * (min(2 * Y + 2, d.ny) - 2 * Y) *
+                                    (min(2 * Z + 2, d.nz) - 2 * Z);
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) {
+                        bf16x4 o;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float v = ps[xh][m][i] + __shfl_xor(ps[xh][m][i], 1);
+                            o[i] = (bf16)(v / (float)cnt);
+                            ps[xh][m][i] = 0.f;
+                        }
+                        if ((vl & 1) == 0 && X < c.nx && Y < c.ny)
+                            *reinterpret_cast<bf16x4*>(pooled + ((size_t)(Z * c.ny + Y) * c.nx + X) * CO + 16 * m +
+                                                       4 * kg) = o;
+                    }
                 }
             }
         }
@@ -593,11 +642,16 @@ constexpr int ZO_RX = ZO_TX + 4, ZO_RY = ZO_TY + 4, ZO_RS = 72, ZO_PLANE = ZO_RY
 constexpr int ZO_NX = ZO_RX * ZO_RY;  // staged x values per plane (816)
 constexpr int ZO_GX = ZO_TX / 2 + 2, ZO_GY = ZO_TY / 2 + 2, ZO_GN = ZO_GX * ZO_GY;  // coarse tile 34 x 6
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void zout_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void zout_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
                                                    int nty, int zchunk, const float* __restrict__ Wc,
-                                                   const float* __restrict__ gz, double* __restrict__ z) {
+                                                   const float* __restrict__ gz, double* __restrict__ z,
+                                                   const double* __restrict__ r_old, double* __restrict__ part,
+                                                   int npart) {
     __shared__ float xs[2][ZO_PLANE];
     __shared__ float gs[2][ZO_GN];
+    // FP64 residual of the block's own outputs, kept from the staging of
+    // plane q (iteration q) until output plane q is finished (iteration q + 2)
+    __shared__ double rring[4][ZO_TY][ZO_TX];
     // weights, one dz slice per 28 floats (16-byte aligned slices, read as
     // float4 broadcasts; as scalar operands all 125 would not fit the SGPRs)
     __shared__ __attribute__((aligned(16))) float wsh[5 * 28];
@@ -657,6 +711,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void z
 #pragma unroll
     for (int h = 0; h < 4; ++h) xload(zs - 2, h, xv[h], xm[h]);
     float a0[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, a1[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    double dzr = 0.0, dzo = 0.0, dro = 0.0;  // partial inner products (part != null)
     for (int p = zs - 2; p <= ze + 1; ++p) {
         const int buf = (p - zs) & 1;
         float* xb = xs[buf];
@@ -666,7 +721,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void z
             if (h < 3 || i < ZO_NX) {
                 const int ic = min(i, ZO_NX - 1);
                 xb[(ic / ZO_RX) * ZO_RS + ic % ZO_RX] = xm[h] ? (float)(bf16)(float)(in_scale * xv[h]) : 0.f;
+                if (part) {
+                    const int row = ic / ZO_RX - 2, col = ic % ZO_RX - 2;
+                    if (row >= 0 && row < ZO_TY && col >= 0 && col < ZO_TX) rring[p & 3][row][col] = xm[h] ? xv[h] : 0.0;
+                }
             }
+        }
+        // r_old at this iteration's outputs (plane p - 2), used after the stencil
+        double ro0 = 0.0, ro1 = 0.0;
+        if (r_old && p - 2 >= zs && p - 2 < ze) {
+            const size_t zq = (size_t)(p - 2) * sxy + (size_t)yo * d.nx + xo;
+            ro0 = r_old[st0 ? zq : 0];
+            ro1 = r_old[st1 ? zq + d.nx : 0];
         }
         if (t < ZO_GN) gs[buf][t] = 0.75f * ga + 0.25f * gb;  // output plane p - 2
         if (p + 1 <= ze + 1) {
@@ -723,8 +789,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void z
                               0.25f * (0.75f * g[gJ1 + gIx] + 0.25f * g[gJ1 + gJx]);
             const bool inz = o >= 1 && o <= d.nz - 2;
             const size_t zo = (size_t)o * sxy + (size_t)yo * d.nx + xo;
-            if (st0) z[zo] = in0 && inz ? out_scale * (double)(a0[0] + up0) : 0.0;
-            if (st1) z[zo + d.nx] = in1 && inz ? out_scale * (double)(a1[0] + up1) : 0.0;
+            const double z0 = in0 && inz ? out_scale * (double)(a0[0] + up0) : 0.0;
+            const double z1 = in1 && inz ? out_scale * (double)(a1[0] + up1) : 0.0;
+            if (st0) z[zo] = z0;
+            if (st1) z[zo + d.nx] = z1;
+            if (part) {
+                // residuals at this lane's two outputs (outputs past the grid
+                // have z = 0 and are left out of r.r_old)
+                const double rn0 = rring[o & 3][ya][lx], rn1 = rring[o & 3][ya + 1][lx];
+                dzr += z0 * rn0 + z1 * rn1;
+                dzo += z0 * ro0 + z1 * ro1;
+                dro += (in0 && inz ? rn0 * ro0 : 0.0) + (in1 && inz ? rn1 * ro1 : 0.0);
+            }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -733,6 +809,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void z
         }
         a0[4] = 0.f;
         a1[4] = 0.f;
+    }
+    if (part) {
+        // fixed-order block sums: wavefront butterflies, then wavefront 0
+        __shared__ double dsum[3][4];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dzr += __shfl_xor(dzr, o);
+            dzo += __shfl_xor(dzo, o);
+            dro += __shfl_xor(dro, o);
+        }
+        if ((t & 63) == 0) {
+            dsum[0][t >> 6] = dzr;
+            dsum[1][t >> 6] = dzo;
+            dsum[2][t >> 6] = dro;
+        }
+        __syncthreads();
+        if (t == 0) {
+            part[blockIdx.x] = (dsum[0][0] + dsum[0][1]) + (dsum[0][2] + dsum[0][3]);
+            part[npart + blockIdx.x] = (dsum[1][0] + dsum[1][1]) + (dsum[1][2] + dsum[1][3]);
+            part[2 * npart + blockIdx.x] = (dsum[2][0] + dsum[2][1]) + (dsum[2][2] + dsum[2][3]);
+        }
     }
 }
 
@@ -847,16 +944,17 @@ hipError_t launch_skip_up(int ch, const bf16* A, const bf16* B, Dims d, bf16* ou
 // rows of a z-march tile: LDS of about 50-60 KB per block for any CI
 constexpr int zm_rows(int ci) { return ci <= 16 ? 8 : (ci <= 32 ? 4 : 2); }
 
-template <int CI, int CO, bool PROJ, typename OUT>
+template <int CI, int CO, bool PROJ, typename OUT, bool POOL = false>
 hipError_t launch_zm(const bf16* A, Dims d, const bf16* W, OUT* out, const float* wp, float* gz, hipStream_t s,
-                     const int* stop) {
+                     const int* stop, bf16* pooled = nullptr) {
     constexpr int TY = zm_rows(CI);
-    auto kern = conv3_zm<CI, CO, TY, PROJ, OUT>;
+    auto kern = conv3_zm<CI, CO, TY, PROJ, OUT, POOL>;
     static const int cap = kvs_tiling::resident_blocks(kern, 256);
     const int ntx = (d.nx + 31) / 32, nty = (d.ny + TY - 1) / TY;
-    const int zchunk = kvs_tiling::choose_kchunk(ntx * nty, d.nz, cap);
+    int zchunk = kvs_tiling::choose_kchunk(ntx * nty, d.nz, cap);
+    if (POOL) zchunk += zchunk & 1;  // segments start on even planes (z pairs of the pooling)
     const int nb = ntx * nty * ((d.nz + zchunk - 1) / zchunk);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, A, d, ntx, nty, zchunk, W, out, wp, gz, stop);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), 0, s, A, d, ntx, nty, zchunk, W, out, wp, gz, stop, pooled);
     return hipGetLastError();
 }
 
@@ -1394,7 +1492,7 @@ void build_layers(kvs_unet* u) {
 // keep: also store g1 (1/2 resolution) and e0 (full resolution) for a
 // backward pass.
 hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, double* z, Dims d, hipStream_t s,
-                          bool keep = false) {
+                          bool keep = false, const UnetDots* dots = nullptr, int* nblocks = nullptr) {
     if (d.n() >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit voxel indices in the kernels
     hipError_t e = unet_ensure_acts(u, d);
     if (e == hipSuccess && keep) e = unet_ensure_e0(u, d);
@@ -1409,8 +1507,10 @@ hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, doubl
     hipLaunchKernelGGL(first_pool_kernel, dim3(fl.nblocks), dim3(256), 0, s, r, ctl, d, fl.ntx, fl.nty, fl.zchunk,
                        u->w + u->w_off[0], u->p0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_conv(u->c0, u->c1, u->p0, d1, 1, u->w + u->w_off[1], u->e1, s, stop)) != hipSuccess) return e;
-    if ((e = launch_pool(u->c1, u->e1, d1, u->p1, s, stop)) != hipSuccess) return e;
+    // e1 = conv(p0) and its pooling p1 in one z-march
+    if ((e = launch_zm<16, 32, false, bf16, true>(u->p0, d1, u->w + u->w_off[1], u->e1, nullptr, nullptr, s, stop,
+                                                  u->p1)) != hipSuccess)
+        return e;
     const bf16* in = u->p1;
     for (int l = 2; l < ld1; ++l) {
         bf16* out = u->bott[(size_t)(l - 2)];
@@ -1423,8 +1523,10 @@ hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, doubl
                                           s, stop)) != hipSuccess)
         return e;
     const OutLaunch ol = out_launch(d);
+    if (dots && ol.nblocks > dots->npart) return hipErrorInvalidValue;  // partials sized at context creation
     hipLaunchKernelGGL(zout_kernel, dim3(ol.nblocks), dim3(256), 0, s, r, ctl, d, ol.ntx, ol.nty, ol.zchunk, u->w_comp,
-                       u->gz, z);
+                       u->gz, z, dots ? dots->r_old : nullptr, dots ? dots->part : nullptr, dots ? dots->npart : 0);
+    if (nblocks) *nblocks = ol.nblocks;
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (keep) {
         hipLaunchKernelGGL(e0_keep_kernel, dim3(nblocks256(d.n())), dim3(256), 0, s, r, ctl, d, u->w + u->w_off[0],
@@ -1436,9 +1538,14 @@ hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, doubl
 }
 
 hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const kvs_grid& g, const double* in_scale,
-                                 const double* out_scale, const int* stop, hipStream_t s) {
+                                 const double* out_scale, const int* stop, hipStream_t s, const UnetDots* dots,
+                                 int* nblocks) {
     NetCtl ctl{in_scale, out_scale, stop, 1.0, 1.0};
-    return kvs_unet_apply(u, r, ctl, z, Dims{(int)g.nx, (int)g.ny, (int)g.nz}, s);
+    return kvs_unet_apply(u, r, ctl, z, Dims{(int)g.nx, (int)g.ny, (int)g.nz}, s, false, dots, nblocks);
+}
+
+int64_t kvs_unet_out_blocks(const kvs_grid& g) {
+    return out_launch(Dims{(int)g.nx, (int)g.ny, (int)g.nz}).nblocks;
 }
 
 namespace {
