@@ -9,9 +9,9 @@ Network (linear, no biases): e0 = conv(r; 1->C0); e1 = conv(pool(e0));
 bottleneck convs at 1/4 resolution (dilations 1, 2, 4, ..., then 1);
 g1 = conv(e1 + up(b); C1->C0); gz = g1 . wp (pointwise C0->1) at 1/2
 resolution; z = conv(e0; C0->1) + up(gz) on the interior: a local stencil
-of r plus the interpolated coarse correction.  e0 is rounded to BF16 where
-it feeds the pool (and where it is kept for the weight gradient); the
-output conv takes it unrounded.
+of r plus the interpolated coarse correction.  e0 itself is never rounded:
+the pool and the output conv take it in full precision (only the copy kept
+for the output weights' gradient is BF16).
 conv = 3x3x3 cross-correlation with zero padding; pool = mean of the
 existing children; up = cell-centred trilinear interpolation (per axis a
 fine cell takes 3/4 of its parent and 1/4 of the parent's neighbour on its
@@ -155,9 +155,9 @@ def forward(r, in_scale, out_scale, flat_w, c0=16, c1=32, c2=64, nbott=4, exact=
     shapes = layer_shapes(c0, c1, c2, nbott)
     Ws = [rnd(w) for w in split_weights(flat_w, shapes)]
     x = rnd(np.float32(in_scale * np.asarray(r, dtype=np.float64)) if not exact else in_scale * np.asarray(r))[..., None]
-    e0_out = conv3(x, Ws[0])  # the output path takes e0 unrounded
-    e0 = rnd(e0_out)
-    p0 = rnd(pool(e0))
+    e0_out = conv3(x, Ws[0])  # pooled and used by the output conv unrounded
+    e0 = rnd(e0_out)          # the activation kept for the output weights' gradient
+    p0 = rnd(pool(e0_out))
     e1 = rnd(conv3(p0, Ws[1]))
     b = rnd(pool(e1))
     bins = []

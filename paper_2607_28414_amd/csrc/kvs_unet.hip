@@ -485,22 +485,30 @@ struct NetCtl {
     double in_v, out_v;
 };
 
-// Level 0 of the encoder, fused: e0 = bf16(conv(x; 1 -> 16)) on the fine
-// grid, x = bf16(in_scale r), and p0 = bf16(mean of the existing children
-// of e0); e0 itself is not stored.  A block owns FP_CX x FP_CY coarse voxels
-// of each coarse plane and marches up a segment of coarse planes.  The fine
-// planes of x it needs (two new ones per coarse plane, halo 1 in x and y)
-// are staged in an LDS ring of six planes, loaded one coarse plane ahead, so
-// one barrier per coarse plane suffices.  Wavefront w owns coarse row Y0 + w
-// and four groups of 16 fine x; per group four MFMAs (fine rows y = 2Y + gy,
-// z = 2Z + gz) are summed in registers, then the x pairs by a lane exchange.
-constexpr int FP_CX = 32, FP_CY = 4;
-constexpr int FP_RX = 2 * FP_CX + 2, FP_RY = 2 * FP_CY + 2, FP_RN = FP_RX * FP_RY, FP_SLOTS = 6;
+// Level 0 of the encoder: p0 = bf16(pool(conv(x; W0))) with x = bf16(in_scale
+// r) and e0 = conv(x; W0) unrounded.  For a coarse voxel whose 8 children all
+// exist, the mean of the children's 3x3x3 convs is one 4x4x4 stride-2 conv of
+// x with the composed weights Wp[c][s] = 1/8 sum_o W0[c][s - o] (s = 0..3 per
+// axis from the fine voxel 2V - 1, o the child offset): K = 64, two MFMA
+// chunks per 16 coarse voxels.  Wp is carried as a BF16 pair (hi + lo, two
+// MFMAs per chunk), so the result is FP32-accurate before its one BF16
+// rounding.  Coarse voxels with a missing child (odd fine extents) are
+// recomputed exactly by pool0_edge_kernel afterwards.
+// A block owns FP_CX x FP_CY coarse voxels of each coarse plane (wavefront w:
+// coarse row Y0 + w, FP_CX / 16 groups of 16 along x) and marches up a
+// segment of coarse planes; the fine planes of x it needs (two new ones per
+// coarse plane, halo 1 at the low side and 2 at the high side) are staged as
+// BF16 in a 6-plane LDS ring, loaded one coarse plane ahead (one barrier per
+// coarse plane).  Lane (v, kg) of a chunk reads 2 rows x 4 consecutive fine x.
+constexpr int FP_CX = 64, FP_CY = 4;
+constexpr int FP_RX = 2 * FP_CX + 2, FP_RY = 2 * FP_CY + 2, FP_RS = FP_RX + 2, FP_RN = FP_RY * FP_RS, FP_SLOTS = 6;
+constexpr int FP_ITEMS = FP_RX * FP_RY;            // staged values per fine plane
+constexpr int FP_IPT = (FP_ITEMS + 255) / 256;     // per thread
 
 __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
-                                                         int nty, int zchunk, const bf16* __restrict__ W,
+                                                         int nty, int zchunk, const bf16* __restrict__ Wp,
                                                          bf16* __restrict__ p0) {
-    __shared__ float rs[FP_SLOTS * FP_RN + 1];  // the last element is a constant 0
+    __shared__ __attribute__((aligned(16))) bf16 xs[FP_SLOTS * FP_RN];
     if (ctl.stop && *ctl.stop) return;
     const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
     const Dims c = coarse(d);
@@ -513,105 +521,125 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, vl = lane & 15, kg = lane >> 4;
     const int sxy = d.nx * d.ny;
     const int pbase = 2 * Zs - 1;  // ring slot of fine plane p: (p - pbase) % FP_SLOTS
-    constexpr int ZERO = FP_SLOTS * FP_RN;
-    if (t == 0) rs[ZERO] = 0.f;
-    // per-lane taps 8 kg .. 8 kg + 7: LDS offset within a plane and z offset;
-    // taps >= 27 have zero weights and read the centre tap instead
-    int toff[8], tdz[8];
+    // composed weights, chunk ch, hi and lo: A[row = channel vl][k = 8 kg + j]
+    bf16x8 wa[2][2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int tap = 8 * kg + j;
-        toff[j] = tap < 27 ? tap_dy(tap) * FP_RX + tap_dx(tap) : 0;
-        tdz[j] = tap < 27 ? tap_dz(tap) : 0;
-    }
-    const int lane_base = (2 * w + 1) * FP_RX + vl + 1;  // group xg = 0, gy = 0
-    const bf16x8 w8 = *reinterpret_cast<const bf16x8*>(W + vl * 32 + 8 * kg);
+    for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl)
+            wa[ch][hl] = *reinterpret_cast<const bf16x8*>(Wp + (size_t)hl * 16 * 64 + vl * 64 + 32 * ch + 8 * kg);
     // Loads are unconditional from clamped (in-bounds) addresses and masked
     // when stored to LDS, so that a prefetch stays in flight until then.
-    auto fload = [&](int p, int h, double& v, bool& m) {
-        const int idx = min(t + 256 * h, FP_RN - 1);
-        const int gx = fx0 + idx % FP_RX, gy = fy0 + idx / FP_RX;
-        m = t + 256 * h < FP_RN && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
-        const int pc = min(max(p, 0), d.nz - 1), yc = min(max(gy, 0), d.ny - 1), xc = min(max(gx, 0), d.nx - 1);
-        v = r[(size_t)pc * sxy + (size_t)(yc * d.nx + xc)];
-    };
-    auto fstore = [&](int p, const double* v, const bool* m) {
-        float* sl = rs + ((p - pbase) % FP_SLOTS) * FP_RN;
-        float f[3];
+    auto fload = [&](int p, double (&v)[FP_IPT], bool (&m)[FP_IPT]) {
 #pragma unroll
-        for (int h = 0; h < 3; ++h) f[h] = m[h] ? (float)(bf16)(float)(in_scale * v[h]) : 0.f;
-        sl[t] = f[0];
-        sl[t + 256] = f[1];
-        if (t + 512 < FP_RN) sl[t + 512] = f[2];
+        for (int h = 0; h < FP_IPT; ++h) {
+            const int i = min(t + 256 * h, FP_ITEMS - 1);
+            const int gx = fx0 + i % FP_RX, gy = fy0 + i / FP_RX;
+            m[h] = t + 256 * h < FP_ITEMS && p >= 0 && p < d.nz && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
+            const int pc = min(max(p, 0), d.nz - 1), yc = min(max(gy, 0), d.ny - 1), xc = min(max(gx, 0), d.nx - 1);
+            v[h] = r[(size_t)pc * sxy + (size_t)(yc * d.nx + xc)];
+        }
     };
-    double va[3], vb[3];
-    bool ma[3], mb[3];
+    auto fstore = [&](int p, const double (&v)[FP_IPT], const bool (&m)[FP_IPT]) {
+        bf16* sl = xs + ((p - pbase) % FP_SLOTS) * FP_RN;
 #pragma unroll
-    for (int h = 0; h < 3; ++h) {
-        fload(pbase, h, va[h], ma[h]);
-        fload(pbase + 1, h, vb[h], mb[h]);
-    }
+        for (int h = 0; h < FP_IPT; ++h) {
+            const int i = t + 256 * h;
+            if (h + 1 < FP_IPT || i < FP_ITEMS)
+                sl[(i / FP_RX) * FP_RS + i % FP_RX] = m[h] ? (bf16)(float)(in_scale * v[h]) : (bf16)0.f;
+        }
+    };
+    double va[FP_IPT], vb[FP_IPT];
+    bool ma[FP_IPT], mb[FP_IPT];
+    fload(pbase, va, ma);
+    fload(pbase + 1, vb, mb);
     fstore(pbase, va, ma);
     fstore(pbase + 1, vb, mb);
-#pragma unroll
-    for (int h = 0; h < 3; ++h) {
-        fload(2 * Zs + 1, h, va[h], ma[h]);
-        fload(2 * Zs + 2, h, vb[h], mb[h]);
-    }
+    fload(2 * Zs + 1, va, ma);
+    fload(2 * Zs + 2, vb, mb);
     const int Y = Y0 + w;
     for (int Z = Zs; Z < Ze; ++Z) {
         fstore(2 * Z + 1, va, ma);
         fstore(2 * Z + 2, vb, mb);
         if (Z + 1 < Ze) {
-#pragma unroll
-            for (int h = 0; h < 3; ++h) {
-                fload(2 * Z + 3, h, va[h], ma[h]);
-                fload(2 * Z + 4, h, vb[h], mb[h]);
-            }
+            fload(2 * Z + 3, va, ma);
+            fload(2 * Z + 4, vb, mb);
         }
         kvs_tiling::lds_barrier();
-        // LDS address of each tap for gz = 0, 1; the group offsets
-        // (gy * FP_RX + 16 * xg) are constants of the unrolled loops
-        int sb[4];
+        // rows of this lane's chunk: fine plane 2Z - 1 + 2 ch + (kg >> 1),
+        // tile rows 2w + 2 (kg & 1) and the next
+        int rb[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sb[q] = ((2 * Z - 1 + q - pbase) % FP_SLOTS) * FP_RN;
-        int ab[2][8];
+        for (int ch = 0; ch < 2; ++ch)
+            rb[ch] = ((2 * Z - 1 + 2 * ch + (kg >> 1) - pbase) % FP_SLOTS) * FP_RN + (2 * w + 2 * (kg & 1)) * FP_RS;
 #pragma unroll
-        for (int gz = 0; gz < 2; ++gz)
+        for (int g = 0; g < FP_CX / 16; ++g) {
+            const int col = 2 * (16 * g + vl);  // even: 4-byte aligned pairs
+            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                ab[gz][j] = (tdz[j] < 0 ? sb[gz] : (tdz[j] == 0 ? sb[gz + 1] : sb[gz + 2])) + toff[j] + lane_base;
-        const float mz[2] = {2 * Z < d.nz ? 1.f : 0.f, 2 * Z + 1 < d.nz ? 1.f : 0.f};
-#pragma unroll
-        for (int xg = 0; xg < 4; ++xg) {
-            const float mx = 2 * X0 + 16 * xg + vl < d.nx ? 1.f : 0.f;
-            float s[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int gz = 0; gz < 2; ++gz)
-#pragma unroll
-                for (int gy = 0; gy < 2; ++gy) {
-                    const int delta = gy * FP_RX + 16 * xg;
-                    bf16x8 xb;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) xb[j] = (bf16)rs[ab[gz][j] + delta];
-                    const f32x4 e = mfma32(w8, xb, f32x4{0.f, 0.f, 0.f, 0.f});
-                    const float m = mx * mz[gz] * (2 * Y + gy < d.ny ? 1.f : 0.f);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) s[i] = fmaf(m, (float)(bf16)e[i], s[i]);
-                }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) s[i] += __shfl_xor(s[i], 1);
-            const int X = X0 + 8 * xg + (vl >> 1);
-            if ((vl & 1) == 0 && X < c.nx && Y < c.ny) {
-                const int cnt =
-                    (min(2 * X + 2, d.nx) - 2 * X) * (min(2 * Y + 2, d.ny) - 2 * Y) * (min(2 * Z + 2, d.nz) - 2 * Z);
+            for (int ch = 0; ch < 2; ++ch) {
+                const bf16* q = xs + rb[ch] + col;
+                typedef unsigned int u32;
+                const u32 a0 = *reinterpret_cast<const u32*>(q), a1 = *reinterpret_cast<const u32*>(q + 2);
+                const u32 b0 = *reinterpret_cast<const u32*>(q + FP_RS), b1 = *reinterpret_cast<const u32*>(q + FP_RS + 2);
+                typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+                const bf16x8 xb = __builtin_bit_cast(bf16x8, u32x4{a0, a1, b0, b1});
+                acc = mfma32(wa[ch][0], xb, acc);
+                acc = mfma32(wa[ch][1], xb, acc);
+            }
+            const int X = X0 + 16 * g + vl;
+            if (X < c.nx && Y < c.ny) {
                 bf16x4 o;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = (bf16)(s[i] / (float)cnt);
+                for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[i];
                 *reinterpret_cast<bf16x4*>(p0 + ((size_t)(Z * c.ny + Y) * c.nx + X) * 16 + 4 * kg) = o;
             }
         }
     }
+}
+
+// p0 of the coarse voxels with a missing child (the last coarse index along
+// an axis whose fine extent is odd): the exact mean over the existing
+// children of e0 = conv(x; W0) (unrounded, FP32), rounded once.  One thread
+// per such voxel and channel; the faces are enumerated x, then y, then z
+// (voxels on two faces are written twice with the same value).
+__global__ void pool0_edge_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, const bf16* __restrict__ W0,
+                                  bf16* __restrict__ p0) {
+    if (ctl.stop && *ctl.stop) return;
+    const Dims c = coarse(d);
+    const long long fx = (d.nx & 1) ? (long long)c.ny * c.nz : 0, fy = (d.ny & 1) ? (long long)c.nx * c.nz : 0;
+    const long long fz = (d.nz & 1) ? (long long)c.nx * c.ny : 0;
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long v = q / 16;
+    const int ch = (int)(q % 16);
+    if (v >= fx + fy + fz) return;
+    int X, Y, Z;
+    if (v < fx) {
+        X = c.nx - 1, Y = (int)(v % c.ny), Z = (int)(v / c.ny);
+    } else if (v < fx + fy) {
+        const long long u = v - fx;
+        Y = c.ny - 1, X = (int)(u % c.nx), Z = (int)(u / c.nx);
+    } else {
+        const long long u = v - fx - fy;
+        Z = c.nz - 1, X = (int)(u % c.nx), Y = (int)(u / c.nx);
+    }
+    const double in_scale = ctl.in_dev ? *ctl.in_dev : ctl.in_v;
+    float sum = 0.f;
+    int cnt = 0;
+    for (int oz = 0; oz < 2; ++oz)
+        for (int oy = 0; oy < 2; ++oy)
+            for (int ox = 0; ox < 2; ++ox) {
+                const int x = 2 * X + ox, y = 2 * Y + oy, z = 2 * Z + oz;
+                if (x >= d.nx || y >= d.ny || z >= d.nz) continue;
+                ++cnt;
+                for (int tap = 0; tap < 27; ++tap) {
+                    const int gx = x + tap_dx(tap), gy = y + tap_dy(tap), gzz = z + tap_dz(tap);
+                    if (gx < 0 || gx >= d.nx || gy < 0 || gy >= d.ny || gzz < 0 || gzz >= d.nz) continue;
+                    const float xv = (float)(bf16)(float)(in_scale * r[((size_t)gzz * d.ny + gy) * d.nx + gx]);
+                    sum = fmaf((float)W0[ch * 32 + tap], xv, sum);
+                }
+            }
+    p0[((size_t)(Z * c.ny + Y) * c.nx + X) * 16 + ch] = (bf16)(sum / (float)cnt);
 }
 
 // Cell-centred trilinear interpolation (factor 2), per axis: parent I and
@@ -856,34 +884,6 @@ __global__ void e0_keep_kernel(const double* __restrict__ r, NetCtl ctl, Dims d,
         }
         *reinterpret_cast<bf16x8*>(e0 + v * 16 + c0) = o;
     }
-}
-
-// mean of the children of coarse voxel V (8 channels per thread)
-template <int C>
-__global__ void pool2(const bf16* __restrict__ fine, Dims d, bf16* __restrict__ out, const int* stop) {
-    if (stop && *stop) return;
-    const Dims c = coarse(d);
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long V = t / (C / 8);
-    const int c8 = (int)(t % (C / 8)) * 8;
-    if (V >= c.n()) return;
-    const int X = (int)(V % c.nx), Y = (int)((V / c.nx) % c.ny), Z = (int)(V / ((long long)c.nx * c.ny));
-    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int cnt = 0;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                const int x = 2 * X + dx, y = 2 * Y + dy, z = 2 * Z + dz;
-                if (x >= d.nx || y >= d.ny || z >= d.nz) continue;
-                const bf16x8 a8 = *reinterpret_cast<const bf16x8*>(fine + (x + (long long)d.nx * (y + (long long)d.ny * z)) * C + c8);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) s[j] += (float)a8[j];
-                ++cnt;
-            }
-    bf16x8 o;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) o[j] = (bf16)(s[j] / (float)cnt);
-    *reinterpret_cast<bf16x8*>(out + V * C + c8) = o;
 }
 
 // Skip input of a decoder level: out(v) = bf16(A(v) + up(B)(v)) with up the
@@ -1326,6 +1326,7 @@ struct kvs_unet {
     float* w_proj = nullptr; // device fp32 (bf16-rounded) projection weights [C0]
     float* w_out = nullptr;  // device fp32 (bf16-rounded) output weights [27][C0] (backward pass)
     float* w_comp = nullptr; // device fp32 composed output stencil [5][5][5] (dz, dy, dx): W_out after W0
+    bf16* w_pool = nullptr;  // device bf16 pair (hi, lo) of the composed pooled first conv [2][16][64]
     float* master = nullptr; // device fp32 master weights (flat)
     float* grad = nullptr;   // device fp32 gradient (flat, same layout)
     float* adam_m = nullptr;
@@ -1447,7 +1448,6 @@ hipError_t unet_ensure_train(kvs_unet* u, Dims d) {
     return hipSuccess;
 }
 
-hipError_t launch_pool(int c, const bf16* fine, Dims d, bf16* out, hipStream_t s, const int* stop);
 
 void build_layers(kvs_unet* u) {
     u->layers.clear();
@@ -1505,8 +1505,16 @@ hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, doubl
     const int* stop = ctl.stop;
     const OutLaunch fl = first_pool_launch(d);
     hipLaunchKernelGGL(first_pool_kernel, dim3(fl.nblocks), dim3(256), 0, s, r, ctl, d, fl.ntx, fl.nty, fl.zchunk,
-                       u->w + u->w_off[0], u->p0);
+                       u->w_pool, u->p0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((d.nx | d.ny | d.nz) & 1) {
+        const Dims c = coarse(d);
+        const long long faces = ((d.nx & 1) ? (long long)c.ny * c.nz : 0) + ((d.ny & 1) ? (long long)c.nx * c.nz : 0) +
+                                ((d.nz & 1) ? (long long)c.nx * c.ny : 0);
+        hipLaunchKernelGGL(pool0_edge_kernel, dim3(nblocks256(faces * 16)), dim3(256), 0, s, r, ctl, d,
+                           u->w + u->w_off[0], u->p0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // e1 = conv(p0) and its pooling p1 in one z-march
     if ((e = launch_zm<16, 32, false, bf16, true>(u->p0, d1, u->w + u->w_off[1], u->e1, nullptr, nullptr, s, stop,
                                                   u->p1)) != hipSuccess)
@@ -1652,22 +1660,6 @@ hipError_t unet_backward(kvs_unet* u, const double* r, double in_scale, Dims d, 
 
 }  // namespace
 
-namespace {
-
-hipError_t launch_pool(int c, const bf16* fine, Dims d, bf16* out, hipStream_t s, const int* stop) {
-    const long long threads = coarse(d).n() * (c / 8);
-    const int nb = (int)((threads + 255) / 256);
-    switch (c) {
-        case 8: hipLaunchKernelGGL(pool2<8>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
-        case 16: hipLaunchKernelGGL(pool2<16>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
-        case 32: hipLaunchKernelGGL(pool2<32>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
-        case 64: hipLaunchKernelGGL(pool2<64>, dim3(nb), dim3(256), 0, s, fine, d, out, stop); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-}  // namespace
 
 // ---- C ABI ---------------------------------------------------------------------
 
@@ -1717,11 +1709,29 @@ kvs_status upload_weights(kvs_unet* u) {
             wc[(size_t)(25 * dz + 5 * dy + dx)] += acc;
         }
     std::vector<float> wcf(wc.begin(), wc.end());
+    // pooled first conv: Wp[c][s] = 1/8 sum_o W0[c][s - o], s = (sz, sy, sx) in
+    // 0..3 (k = 16 sz + 4 sy + sx), o in {0, 1}^3; as a BF16 pair hi + lo
+    std::vector<bf16> wpl((size_t)2 * 16 * 64);
+    for (int ch = 0; ch < 16; ++ch)
+        for (int k = 0; k < 64; ++k) {
+            const int sz = k / 16, sy = (k / 4) % 4, sx = k % 4;
+            double acc = 0.0;
+            for (int o = 0; o < 8; ++o) {
+                const int tz = sz - (o >> 2), ty = sy - ((o >> 1) & 1), tx = sx - (o & 1);
+                if (tz < 0 || tz > 2 || ty < 0 || ty > 2 || tx < 0 || tx > 2) continue;
+                acc += (double)(float)(bf16)m0[ch * 27 + 9 * tz + 3 * ty + tx];
+            }
+            acc *= 0.125;
+            const bf16 hi = (bf16)(float)acc;
+            wpl[(size_t)ch * 64 + k] = hi;
+            wpl[(size_t)16 * 64 + ch * 64 + k] = (bf16)(float)(acc - (double)(float)hi);
+        }
     if (hipMemcpy(u->w, wb.data(), sizeof(bf16) * wb.size(), hipMemcpyHostToDevice) != hipSuccess ||
         (u->n_wt > 0 && hipMemcpy(u->wt, wtb.data(), sizeof(bf16) * u->n_wt, hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemcpy(u->w_proj, wpj.data(), sizeof(float) * wpj.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->w_out, wo.data(), sizeof(float) * wo.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->w_comp, wcf.data(), sizeof(float) * wcf.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(u->w_pool, wpl.data(), sizeof(bf16) * wpl.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(u->master, u->host_master.data(), sizeof(float) * u->n_master, hipMemcpyHostToDevice) != hipSuccess)
         return ufail(u, KVS_EDEVICE, "weight upload failed");
     return KVS_OK;
@@ -1751,6 +1761,7 @@ kvs_status kvs_unet_create(const int32_t* channels, int32_t n_bottleneck, kvs_un
     ok = ok && hipMalloc(&u->w_proj, sizeof(float) * c0) == hipSuccess;
     ok = ok && hipMalloc(&u->w_out, sizeof(float) * 27 * c0) == hipSuccess;
     ok = ok && hipMalloc(&u->w_comp, sizeof(float) * 125) == hipSuccess;
+    ok = ok && hipMalloc(&u->w_pool, sizeof(bf16) * 2 * 16 * 64) == hipSuccess;
     for (float** p : {&u->master, &u->grad, &u->adam_m, &u->adam_v})
         ok = ok && hipMalloc(p, sizeof(float) * u->n_master) == hipSuccess;
     ok = ok && hipMemset(u->grad, 0, sizeof(float) * u->n_master) == hipSuccess;
@@ -1779,6 +1790,7 @@ void kvs_unet_destroy(kvs_unet* u) {
     ufree(u->w_proj);
     ufree(u->w_out);
     ufree(u->w_comp);
+    ufree(u->w_pool);
     ufree(u->master);
     ufree(u->grad);
     ufree(u->adam_m);
