@@ -360,7 +360,8 @@ kvs_status kvs_unet_conv_check(int32_t ci, int32_t co, int32_t dil, const uint16
 
 /* ---- tuning --------------------------------------------------------------- */
 
-/* Number of FDTD step-kernel variants (tile rows x cells per lane). */
+/* Number of FDTD step-kernel variants (tile rows x cells per lane x
+ * wavefronts per x row). */
 int32_t kvs_num_step_variants(void);
 /* Use variant v (0 <= v < kvs_num_step_variants()) for kvs_step.  Every
  * variant computes the same update; they differ in tile shape only. */

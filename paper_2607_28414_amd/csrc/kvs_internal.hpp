@@ -170,7 +170,7 @@ struct kvs_batch {
 hipError_t kvs_launch_step(kvs_ctx* c, double gn);
 hipError_t kvs_launch_step_variant(kvs_ctx* c, double gn, int variant);
 int kvs_step_variant_count();
-void kvs_step_variant_shape(int variant, int* by, int* vec);
+void kvs_step_variant_shape(int variant, int* by, int* vec, int* wx);
 hipError_t kvs_launch_probe_gather(kvs_ctx* c, const void* u_new, int64_t slot);
 // Fold |u_new| into the running peak maps of the registered planes.
 hipError_t kvs_launch_peak_update(kvs_ctx* c, const void* u_new);

@@ -9,10 +9,12 @@
 //   u'  = u_c + w'
 // with s = sigma dt / 2 from the linear sponge ramp and harmonic face moduli.
 //
-// Kernel layout ("2.5-D" blocking).  A block of 64 x BY threads owns a 64 x BY
-// column tile in the xy plane and marches over a chunk of z planes.  One
-// 64-lane wavefront covers one 64-cell x row, so every global access is one
-// fully coalesced 256 B (fp32) row segment.  Per plane the block stages the
+// Kernel layout ("2.5-D" blocking).  A block of 64 WX x BY threads owns a
+// TX x BY column tile in the xy plane (TX = 64 WX VEC) and marches over a
+// chunk of z planes.  One 64-lane wavefront covers 64 VEC consecutive cells of
+// an x row, so every global access is a fully coalesced row segment; WX > 1
+// puts several wavefronts side by side on a row, which spreads the two x-halo
+// columns over a wider tile without more registers per lane.  Per plane the block stages the
 // fields that are needed at xy neighbours (u, plus w when eta != 0, plus G
 // when heterogeneous) in LDS with a one-cell halo; z neighbours live in a
 // per-thread register queue (k-1, k, k+1, with k+2 prefetched).  Each cell's
@@ -148,15 +150,17 @@ __device__ __forceinline__ void vlds_write(T* p, const T (&a)[V]) {
 // being drained every plane.
 //
 // A lane owns VEC consecutive x cells (one dword or dwordx2 access per
-// field); a wavefront covers TX = 64 VEC cells of one x row, a block BY rows.
+// field); WX wavefronts cover TX = 64 WX VEC cells of one x row, a block BY
+// rows.
 // LDS row layout: [pad][left halo][TX cells][right halo][pad], so that every
 // lane's VEC-wide write is naturally aligned, including the halo writes.
-template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC>
+template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WX>
 __device__ __forceinline__ void step_tile(const StepArgs<T>& a, int bx, int by, int bz) {
     static_assert(BY >= 3 && 2 * BY <= 64, "halo lane assignment needs 3 <= BY <= 32");
+    static_assert(64 * WX * BY <= 1024, "at most 1024 threads per block");
     constexpr int NQ = 3 + (VISC ? 3 : 0) + (HET ? 1 : 0);
     constexpr int QG = VISC ? 6 : 3;
-    constexpr int TX = 64 * VEC;
+    constexpr int TX = 64 * WX * VEC;
     constexpr int W = TX + 4;
     constexpr int DUMMY = BY + 2;
     __shared__ T lds[2][NQ][BY + 3][W];
@@ -369,11 +373,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, int bx, int by, 
 }
 
 // One context: tile from the block index (XCD-contiguous order when remap).
-template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WPE>
-__global__ __launch_bounds__(64 * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(const StepArgs<T> a) {
+template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WX, int WPE>
+__global__ __launch_bounds__(64 * WX * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(
+    const StepArgs<T> a) {
     const int B = a.gx * a.gy * a.gz;
     const int t = a.remap ? tile_of(blockIdx.x, B) : (int)blockIdx.x;
-    step_tile<T, HET, VISC, FORCE, BY, VEC>(a, t % a.gx, (t / a.gx) % a.gy, t / (a.gx * a.gy));
+    step_tile<T, HET, VISC, FORCE, BY, VEC, WX>(a, t % a.gx, (t / a.gx) % a.gy, t / (a.gx * a.gy));
 }
 
 // Batched homogeneous instances: one launch covers every instance's tiles
@@ -387,58 +392,77 @@ struct BatchInst {
     long long n_env;
 };
 
-template <typename T, bool VISC, bool FORCE, int BY, int VEC>
-__global__ __launch_bounds__(64 * BY) void batch_step_kernel(const BatchInst<T>* inst, const int4* work, int nwork,
-                                                             long long n, int parity) {
+template <typename T, bool VISC, bool FORCE, int BY, int VEC, int WX>
+__global__ __launch_bounds__(64 * WX * BY) void batch_step_kernel(const BatchInst<T>* inst, const int4* work,
+                                                                  int nwork, long long n, int parity) {
     const int t = tile_of(blockIdx.x, nwork);
     const int4 wi = work[t];
     const BatchInst<T>& bi = inst[wi.x];
     StepArgs<T> a = bi.a[parity];
     a.gn = n < bi.n_env ? T(bi.env[n]) : T(0);
-    step_tile<T, false, VISC, FORCE, BY, VEC>(a, wi.y, wi.z, wi.w);
+    step_tile<T, false, VISC, FORCE, BY, VEC, WX>(a, wi.y, wi.z, wi.w);
 }
 
-// Step-kernel variants (tile rows BY, cells per lane VEC) chosen by
-// kvs_autotune_step; variant 0 is the default.
+// Step-kernel variants (tile rows BY, cells per lane VEC, wavefronts per row
+// WX) chosen by kvs_autotune_step; variant 0 is the default.
 struct StepVariant {
-    int by, vec, wpe;
+    int by, vec, wx, wpe;
 };
 // wpe: minimum waves per SIMD asked of the register allocator (1 = free)
-constexpr StepVariant kVariants[] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {8, 2, 1}, {16, 1, 1}};
+constexpr StepVariant kVariants[] = {{4, 1, 1, 1}, {8, 1, 1, 1}, {4, 2, 1, 1}, {8, 2, 1, 1},
+                                     {16, 1, 1, 1}, {4, 1, 2, 1}, {8, 1, 2, 1}, {4, 1, 4, 1}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WPE = 1>
+// The shape a launch actually uses.  VEC = 2 needs an even nx so that every
+// lane's pair is aligned and whole.  FP64 (the parity mode) uses one cell per
+// lane and tiles of at most 8 rows and 128 columns: larger FP64 tiles spill
+// registers or exceed the 160 KB of LDS (two buffered planes of 7 fields).
+int effective_variant(int v, bool fp64, bool odd_nx) {
+    if (v < 0 || v >= kNumVariants) v = 0;
+    if (kVariants[v].vec == 2 && (fp64 || odd_nx)) v = kVariants[v].by == 8 ? 1 : 0;
+    if (fp64) {
+        if (v == 4) v = 1;
+        if (v == 6 || v == 7) v = 5;
+    }
+    return v;
+}
+
+template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WX, int WPE = 1>
 hipError_t launch_shape(kvs_ctx* c, StepArgs<T> a) {
-    auto kern = step_kernel<T, HET, VISC, FORCE, BY, VEC, WPE>;
-    static const int cap = resident_blocks(kern, 64 * BY);  // one value per instantiation
-    a.gx = (a.nx + 64 * VEC - 1) / (64 * VEC);
+    auto kern = step_kernel<T, HET, VISC, FORCE, BY, VEC, WX, WPE>;
+    static const int cap = resident_blocks(kern, 64 * WX * BY);  // one value per instantiation
+    a.gx = (a.nx + 64 * WX * VEC - 1) / (64 * WX * VEC);
     a.gy = (a.ny + BY - 1) / BY;
     a.kchunk = c->step_zchunk > 0 ? std::min(c->step_zchunk, a.nz - 2) : choose_kchunk(a.gx * a.gy, a.nz - 2, cap);
     a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
     const int blocks = a.gx * a.gy * a.gz;
     if (c->launch_ev[0])
-        hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(64, BY), 0, c->stream, c->launch_ev[0], c->launch_ev[1], 0, a);
+        hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(64 * WX, BY), 0, c->stream, c->launch_ev[0],
+                              c->launch_ev[1], 0, a);
     else
-        hipLaunchKernelGGL(kern, dim3(blocks), dim3(64, BY), 0, c->stream, a);
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * WX, BY), 0, c->stream, a);
     return hipGetLastError();
 }
 
 template <typename T, bool HET, bool VISC, bool FORCE>
 hipError_t launch_typed(kvs_ctx* c, const StepArgs<T>& a, int variant) {
-    // VEC = 2 needs an even nx so that every lane's pair is aligned and whole;
-    // FP64 (the parity mode) uses one cell per lane
-    const bool narrow = sizeof(T) == 8 || (a.nx % 2) != 0;
-    if (kVariants[variant].vec == 2 && narrow) variant = kVariants[variant].by == 8 ? 1 : 0;
+    const int v = effective_variant(variant, sizeof(T) == 8, (a.nx % 2) != 0);
     if constexpr (sizeof(T) == 8) {
-        // FP64 tiles stay at <= 8 rows (16-row FP64 tiles spill registers)
-        return (variant == 1 || variant == 4) ? launch_shape<T, HET, VISC, FORCE, 8, 1>(c, a) : launch_shape<T, HET, VISC, FORCE, 4, 1>(c, a);
+        switch (v) {
+            case 1: return launch_shape<T, HET, VISC, FORCE, 8, 1, 1>(c, a);
+            case 5: return launch_shape<T, HET, VISC, FORCE, 4, 1, 2>(c, a);
+            default: return launch_shape<T, HET, VISC, FORCE, 4, 1, 1>(c, a);
+        }
     } else {
-        switch (variant) {
-            case 4: return launch_shape<T, HET, VISC, FORCE, 16, 1>(c, a);
-            case 1: return launch_shape<T, HET, VISC, FORCE, 8, 1>(c, a);
-            case 2: return launch_shape<T, HET, VISC, FORCE, 4, 2>(c, a);
-            case 3: return launch_shape<T, HET, VISC, FORCE, 8, 2>(c, a);
-            default: return launch_shape<T, HET, VISC, FORCE, 4, 1>(c, a);
+        switch (v) {
+            case 1: return launch_shape<T, HET, VISC, FORCE, 8, 1, 1>(c, a);
+            case 2: return launch_shape<T, HET, VISC, FORCE, 4, 2, 1>(c, a);
+            case 3: return launch_shape<T, HET, VISC, FORCE, 8, 2, 1>(c, a);
+            case 4: return launch_shape<T, HET, VISC, FORCE, 16, 1, 1>(c, a);
+            case 5: return launch_shape<T, HET, VISC, FORCE, 4, 1, 2>(c, a);
+            case 6: return launch_shape<T, HET, VISC, FORCE, 8, 1, 2>(c, a);
+            case 7: return launch_shape<T, HET, VISC, FORCE, 4, 1, 4>(c, a);
+            default: return launch_shape<T, HET, VISC, FORCE, 4, 1, 1>(c, a);
         }
     }
 }
@@ -618,10 +642,11 @@ hipError_t kvs_launch_step_variant(kvs_ctx* c, double gn, int variant) {
 
 int kvs_step_variant_count() { return kNumVariants; }
 
-void kvs_step_variant_shape(int variant, int* by, int* vec) {
+void kvs_step_variant_shape(int variant, int* by, int* vec, int* wx) {
     if (variant < 0 || variant >= kNumVariants) variant = 0;
     *by = kVariants[variant].by;
     *vec = kVariants[variant].vec;
+    *wx = kVariants[variant].wx;
 }
 
 hipError_t kvs_launch_probe_gather(kvs_ctx* c, const void* u_new, int64_t slot) {
@@ -716,7 +741,7 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
 namespace {
 
 template <typename T>
-StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int zchunk) {
+StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int wx, int zchunk) {
     const kvs_grid& g = c->grid;
     StepArgs<T> a{};
     a.u = static_cast<const T*>(c->u[cur]);
@@ -728,7 +753,7 @@ StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int zchunk) {
     a.nx = (int)g.nx;
     a.ny = (int)g.ny;
     a.nz = (int)g.nz;
-    a.gx = (a.nx + 64 * vec - 1) / (64 * vec);
+    a.gx = (a.nx + 64 * wx * vec - 1) / (64 * wx * vec);
     a.gy = (a.ny + by - 1) / by;
     a.kchunk = std::min(zchunk, a.nz - 2);
     a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
@@ -747,18 +772,14 @@ StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int zchunk) {
     return a;
 }
 
-// The batch's tile shape, narrowed like the single-context launch: FP64
-// uses one cell per lane and at most 8 rows; two cells per lane need every
-// instance's nx even.
+// The batch's tile shape, narrowed like the single-context launch (two
+// cells per lane need every instance's nx even).
 int batch_variant(const kvs_batch* b) {
     int v = b->variant;
     if (v < 0 || v >= kNumVariants) v = 1;
     bool even = true;
     for (const kvs_ctx* c : b->inst) even = even && (c->grid.nx % 2 == 0);
-    const bool narrow = b->prec == KVS_FP64 || !even;
-    if (kVariants[v].vec == 2 && narrow) v = kVariants[v].by == 8 ? 1 : 0;
-    if (b->prec == KVS_FP64 && v == 4) v = 1;
-    return v;
+    return effective_variant(v, b->prec == KVS_FP64, !even);
 }
 
 template <typename T>
@@ -793,11 +814,11 @@ hipError_t prepare_t(kvs_batch* b) {
     std::vector<double> env_host(std::max<size_t>(env_total, 1), 0.0);
     size_t off = 0;
     const int v = batch_variant(b);
-    const int by = kVariants[v].by, vec = kVariants[v].vec;
+    const int by = kVariants[v].by, vec = kVariants[v].vec, wx = kVariants[v].wx;
     for (int i = 0; i < n; ++i) {
         kvs_ctx* c = b->inst[(size_t)i];
-        params[(size_t)i].a[0] = instance_args<T>(c, c->cur, by, vec, b->zchunk);
-        params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur, by, vec, b->zchunk);
+        params[(size_t)i].a[0] = instance_args<T>(c, c->cur, by, vec, wx, b->zchunk);
+        params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur, by, vec, wx, b->zchunk);
         params[(size_t)i].env = env_dev + off;
         params[(size_t)i].n_env = (long long)c->env.size();
         std::copy(c->env.begin(), c->env.end(), env_host.begin() + off);
@@ -825,9 +846,10 @@ hipError_t prepare_t(kvs_batch* b) {
     return e;
 }
 
-template <typename T, bool VISC, bool FORCE, int BY, int VEC>
+template <typename T, bool VISC, bool FORCE, int BY, int VEC, int WX>
 void launch_batch_shape(kvs_batch* b, long long n, int parity) {
-    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, BY, VEC>), dim3(b->nwork), dim3(64, BY), 0, b->stream,
+    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, BY, VEC, WX>), dim3(b->nwork), dim3(64 * WX, BY), 0,
+                       b->stream,
                        static_cast<const BatchInst<T>*>(b->dev_params), static_cast<const int4*>(b->dev_work),
                        b->nwork, n, parity);
 }
@@ -836,16 +858,20 @@ template <typename T, bool VISC, bool FORCE>
 void launch_batch_step(kvs_batch* b, long long n, int parity) {
     if constexpr (sizeof(T) == 8) {
         switch (batch_variant(b)) {
-            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1>(b, n, parity);
-            default: return launch_batch_shape<T, VISC, FORCE, 4, 1>(b, n, parity);
+            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity);
+            case 5: return launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity);
+            default: return launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity);
         }
     } else {
         switch (batch_variant(b)) {
-            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1>(b, n, parity);
-            case 2: return launch_batch_shape<T, VISC, FORCE, 4, 2>(b, n, parity);
-            case 3: return launch_batch_shape<T, VISC, FORCE, 8, 2>(b, n, parity);
-            case 4: return launch_batch_shape<T, VISC, FORCE, 16, 1>(b, n, parity);
-            default: return launch_batch_shape<T, VISC, FORCE, 4, 1>(b, n, parity);
+            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity);
+            case 2: return launch_batch_shape<T, VISC, FORCE, 4, 2, 1>(b, n, parity);
+            case 3: return launch_batch_shape<T, VISC, FORCE, 8, 2, 1>(b, n, parity);
+            case 4: return launch_batch_shape<T, VISC, FORCE, 16, 1, 1>(b, n, parity);
+            case 5: return launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity);
+            case 6: return launch_batch_shape<T, VISC, FORCE, 8, 1, 2>(b, n, parity);
+            case 7: return launch_batch_shape<T, VISC, FORCE, 4, 1, 4>(b, n, parity);
+            default: return launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity);
         }
     }
 }
