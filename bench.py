@@ -65,8 +65,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["inclusions", "batch", "fpcg"], default="inclusions",
-                    help="fpcg: profiling aid, flexible-PCG iterations on the 384 x 384 x 512 grid")
+    ap.add_argument("--workload", choices=["inclusions", "batch", "fpcg", "arf"], default="inclusions",
+                    help="fpcg: profiling aid, flexible-PCG iterations on the 384 x 384 x 512 grid; "
+                         "arf: the ARF accumulation leg alone")
     ap.add_argument("--grid", type=int, default=256, help="cubic grid edge of the inclusion workload")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--cpu-sample-steps", type=int, default=100)
@@ -80,6 +81,7 @@ def parse():
                     help="skip the full-size time-varying and shell workload legs")
     ap.add_argument("--tv-epochs", type=int, default=4, help="epochs of the time-varying workload window")
     ap.add_argument("--shell-steps", type=int, default=300, help="steps of the shell workload window")
+    ap.add_argument("--arf-repeats", type=int, default=8, help="accumulate launches of the ARF leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -252,6 +254,65 @@ def time_varying_window(args, net):
                      "algorithmic_bytes_per_cell_update": 72, "launches": k_launches, "variant": variant},
         "projection_iters": iters, "projection_ms": pms, "fallbacks": fbs,
         "epoch_ms": ems, "epoch_ms_mean_after_first": float(np.mean(ems[1:])) if len(ems) > 1 else None,
+    }
+
+
+def arf_workload(args):
+    """Acoustic radiation force accumulation on the 512 x 512 x 640 grid of the
+    transcranial workload: Poynting form, FP32 samples of a synthetic focused
+    1 MHz tone burst (8 samples per launch, the same 8 samples folded in
+    `arf_repeats` times), then the force pattern with a uniform alpha and c.
+    Each accumulate launch is timed with HIP events on the context's stream;
+    algorithmic bytes per launch = (8 x 16 + 2 x 24) B per cell (the samples
+    read once, the three FP64 sums read and written once)."""
+    import torch
+
+    from paper_2607_28414_amd import kvs
+    from workloads import acoustic_beam_samples
+
+    grid = (512, 512, 640, 0.2e-3, 0.2e-3, 0.2e-3)
+    N = 512 * 512 * 640
+    ns = 8
+    log("bench: ARF accumulation 512x512x640")
+    p, v = acoustic_beam_samples(grid, ns, per=8, cycles=2, focus=(0.0, 0.0, 0.03), xp=torch, device="cuda",
+                                 dtype=torch.float32)
+    torch.cuda.synchronize()
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        lib_stream = torch.cuda.ExternalStream(kvs.kvs_stream(ctx))
+        kvs.kvs_arf_begin(ctx, kvs.KVS_ARF_POYNTING)
+        kvs.kvs_arf_accumulate_device(ctx, p.data_ptr(), v.data_ptr(), ns, 1)  # warm-up
+        kvs.kvs_arf_begin(ctx, kvs.KVS_ARF_POYNTING)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.arf_repeats)]
+        for e0, e1 in ev:
+            e0.record(lib_stream)
+            kvs.kvs_arf_accumulate_device(ctx, p.data_ptr(), v.data_ptr(), ns, 1)
+            e1.record(lib_stream)
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(lib_stream)
+        kvs.kvs_arf_set_force(ctx, 5.8, 1540.0, 8 * 2, mask=None)
+        f1.record(lib_stream)
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in ev]
+        force_ms = f0.elapsed_time(f1)
+    finally:
+        kvs.kvs_destroy(ctx)
+        del p, v
+        torch.cuda.empty_cache()
+    per = sum(ms) / len(ms)
+    achieved = N * (ns * 16 + 2 * 24) / (per * 1e-3) / 1e9
+    return {
+        "workload": "512x512x640 grid, Poynting form, FP32 samples of a focused 1 MHz tone burst (8 per launch), "
+                    f"{args.arf_repeats} launches, then the force pattern (uniform alpha 5.8 Np/m, c 1540 m/s)",
+        "samples": ns * args.arf_repeats,
+        "accumulate_ms_avg": per,
+        "gcell_samples_per_s": N * ns / (per * 1e-3) / 1e9,
+        "set_force_ms": force_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_cell": "8 x 16 (samples) + 48 (sums read and written) per launch"},
     }
 
 
@@ -479,7 +540,7 @@ def run_batch(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the solver has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
@@ -490,6 +551,9 @@ def main():
         return
     if args.workload == "fpcg":
         print(json.dumps(run_fpcg_profile(args)), flush=True)
+        return
+    if args.workload == "arf":
+        print(json.dumps(arf_workload(args)), flush=True)
         return
     import numpy as np
     import torch
@@ -606,7 +670,7 @@ def main():
         res["cpu_baseline"] = cpu_baseline(w, dt, smax, FS_host, args.cpu_sample_steps)
     else:
         res["cpu_baseline"] = None
-    res["projection_learned"] = res["time_varying"] = res["shell"] = None
+    res["projection_learned"] = res["time_varying"] = res["shell"] = res["arf"] = None
     if not args.no_learned:
         net = kvs.kvs_unet_create((16, 32, 64), 4)
         try:
@@ -614,6 +678,7 @@ def main():
             if not args.no_workloads:
                 res["time_varying"] = time_varying_window(args, net)
                 res["shell"] = shell_workload(args, net)
+                res["arf"] = arf_workload(args)
         finally:
             kvs.kvs_unet_destroy(net)
     print(json.dumps(res), flush=True)

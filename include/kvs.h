@@ -157,6 +157,9 @@ kvs_status kvs_set_force(kvs_ctx* ctx, const double* F);
 /* Same from device memory: dtype 0 = double, 1 = float; copied on the
  * context's stream. */
 kvs_status kvs_set_force_device(kvs_ctx* ctx, const void* F, int32_t dtype);
+/* Read back the force pattern (host, 3*N doubles).  No force: KVS_ESTATE.
+ * Blocks. */
+kvs_status kvs_get_force(const kvs_ctx* ctx, double* F);
 /* Temporal envelope g[n] for steps n < n_env (absolute step index since the
  * state was last reset); steps n >= n_env use g = 0. n_env may be 0. */
 kvs_status kvs_set_envelope(kvs_ctx* ctx, const double* g, int64_t n_env);
@@ -222,6 +225,51 @@ kvs_status kvs_set_peak_planes(kvs_ctx* ctx, const int32_t* axis, const int64_t*
  * axis 0 -> [nz][ny], axis 1 -> [nz][nx], axis 2 -> [ny][nx], last extent
  * fastest.  An unregistered plane is KVS_EINVAL.  Blocks. */
 kvs_status kvs_peak_map(const kvs_ctx* ctx, int32_t axis, int64_t index, double* out);
+
+/* ---- acoustic radiation force (Sec. 3.4, Eqs. isppa_norm and arf_poynting) -- */
+
+/* The body force is derived from a time series of the acoustic field sampled
+ * on the context grid, then used like kvs_set_force (project, then step).
+ * The library keeps per-cell running sums over the samples in FP64, sample
+ * by sample in the order given (products and sums not fused, so the sums are
+ * the plain sequential ones), and turns them into the force pattern:
+ *   KVS_ARF_PLANE     S = sum p^2;       F = b0 d,
+ *                     b0 = (2 alpha / c) S / (rho c N_pulse)   (Eq. isppa_norm)
+ *   KVS_ARF_POYNTING  S_i = sum p v_i;   F_i = (2 alpha / c) S_i / N_pulse
+ *                                                           (Eq. arf_poynting)
+ * alpha: absorption [Np/m] at the transmit frequency; c: sound speed [m/s];
+ * rho: density [kg/m^3]; N_pulse: samples in one pulse (the sums run over
+ * all samples, silent ones included, and are normalised by the pulse
+ * length); d: unit beam direction.  Cells whose mask byte is 0 get F = 0
+ * (regions outside the tissue of interest, Sec. 5.1).  p in Pa, v in m/s,
+ * layouts [sample][nz][ny][nx] and [sample][3][nz][ny][nx]. */
+typedef enum { KVS_ARF_PLANE = 1, KVS_ARF_POYNTING = 2 } kvs_arf_mode;
+/* Start a time average in `mode`: zero the sums and the sample count.  The
+ * sums (N doubles, or 3N in the Poynting form) are device memory owned by
+ * the context.  Unknown mode: KVS_EINVAL. */
+kvs_status kvs_arf_begin(kvs_ctx* ctx, int32_t mode);
+/* Add nsamp >= 1 samples from device memory (dtype 0 = double, 1 = float):
+ * p [nsamp][N]; v [nsamp][3][N] in the Poynting form, NULL in the plane-wave
+ * form (anything else: KVS_EINVAL).  Read asynchronously on the context's
+ * stream: keep the buffers alive until it synchronises.  Before
+ * kvs_arf_begin: KVS_ESTATE. */
+kvs_status kvs_arf_accumulate_device(kvs_ctx* ctx, const void* p, const void* v, int64_t nsamp, int32_t dtype);
+/* Same from host doubles (copied sample by sample; blocks). */
+kvs_status kvs_arf_accumulate(kvs_ctx* ctx, const double* p, const double* v, int64_t nsamp);
+/* Samples added since kvs_arf_begin (nsamp, may be NULL) and the raw sums
+ * (out: host, N doubles in the plane-wave form, 3N [3][N] in the Poynting
+ * form; may be NULL).  Blocks. */
+kvs_status kvs_arf_get_sums(const kvs_ctx* ctx, double* out, int64_t* nsamp);
+/* Turn the sums into the force pattern F (replaces the force; the projected
+ * force becomes stale, as after kvs_set_force).  alpha, c, rho: host arrays
+ * of n_alpha, n_c, n_rho values, each 1 (uniform) or N (a map); alpha >= 0,
+ * c > 0, rho > 0, all finite; rho and beam_dir (3 doubles, non-zero,
+ * normalised here) are read in the plane-wave form only and may be NULL in
+ * the Poynting form.  mask: host, N bytes, or NULL to keep every cell.
+ * n_pulse > 0.  No samples yet: KVS_ESTATE.  Blocks. */
+kvs_status kvs_arf_set_force(kvs_ctx* ctx, const double* alpha, int64_t n_alpha, const double* c, int64_t n_c,
+                             const double* rho, int64_t n_rho, const uint8_t* mask, double n_pulse,
+                             const double* beam_dir);
 
 /* ---- measurement -------------------------------------------------------- */
 

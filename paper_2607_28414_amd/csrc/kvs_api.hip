@@ -84,6 +84,7 @@ void release(kvs_ctx* c) {
     dfree(c->probe_cells);
     dfree(c->traces);
     dfree(c->peak);
+    dfree(c->arf_sum);
     if (c->cgs_host) (void)hipHostFree(c->cgs_host);
     c->cgs_host = nullptr;
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -402,6 +403,17 @@ kvs_status kvs_set_force_device(kvs_ctx* c, const void* F, int32_t dtype) {
     return KVS_OK;
 }
 
+kvs_status kvs_get_force(const kvs_ctx* cc, double* F) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    if (!F) return fail(c, KVS_EINVAL, "F is NULL");
+    if (!c->have_force) return fail(c, KVS_ESTATE, "no force set");
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, hipMemcpyAsync(F, c->F, sizeof(double) * 3 * c->N, hipMemcpyDeviceToHost, c->stream));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    return KVS_OK;
+}
+
 kvs_status kvs_set_envelope(kvs_ctx* c, const double* g, int64_t n) {
     if (!c) return KVS_EINVAL;
     if (n < 0 || (n > 0 && !g)) return fail(c, KVS_EINVAL, "bad envelope");
@@ -701,6 +713,135 @@ kvs_status kvs_peak_map(const kvs_ctx* cc, int32_t axis, int64_t index, double* 
         API_HIP(c, hipStreamSynchronize(c->stream));
         for (int64_t q = 0; q < cells; ++q) out[q] = (double)tmp[(size_t)q];
     }
+    return KVS_OK;
+}
+
+// ---- acoustic radiation force ----------------------------------------------
+
+kvs_status kvs_arf_begin(kvs_ctx* c, int32_t mode) {
+    if (!c) return KVS_EINVAL;
+    if (mode != KVS_ARF_PLANE && mode != KVS_ARF_POYNTING)
+        return fail(c, KVS_EINVAL, "arf: mode must be KVS_ARF_PLANE or KVS_ARF_POYNTING");
+    const int64_t need = (mode == KVS_ARF_PLANE ? 1 : 3) * c->N;
+    API_HIP(c, hipSetDevice(c->device));
+    if (c->arf_sum_cap < need) {
+        API_HIP(c, hipStreamSynchronize(c->stream));
+        dfree(c->arf_sum);
+        c->arf_sum_cap = 0;
+        c->arf_mode = 0;
+        API_HIP(c, hipMalloc(&c->arf_sum, sizeof(double) * (size_t)need));
+        c->arf_sum_cap = need;
+    }
+    API_HIP(c, hipMemsetAsync(c->arf_sum, 0, sizeof(double) * (size_t)need, c->stream));
+    c->arf_mode = mode;
+    c->arf_samples = 0;
+    return KVS_OK;
+}
+
+kvs_status kvs_arf_accumulate_device(kvs_ctx* c, const void* p, const void* v, int64_t nsamp, int32_t dtype) {
+    if (!c) return KVS_EINVAL;
+    if (c->arf_mode == 0) return fail(c, KVS_ESTATE, "arf: no kvs_arf_begin");
+    if (nsamp < 1) return fail(c, KVS_EINVAL, "arf: nsamp must be >= 1");
+    if (dtype != 0 && dtype != 1) return fail(c, KVS_EINVAL, "arf: dtype must be 0 (double) or 1 (float)");
+    if (!p) return fail(c, KVS_EINVAL, "arf: p is NULL");
+    if (c->arf_mode == KVS_ARF_POYNTING && !v) return fail(c, KVS_EINVAL, "arf: v is NULL in the Poynting form");
+    if (c->arf_mode == KVS_ARF_PLANE && v) return fail(c, KVS_EINVAL, "arf: v must be NULL in the plane-wave form");
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, kvs_launch_arf_accumulate(c, p, v, nsamp, dtype));
+    c->arf_samples += nsamp;
+    return KVS_OK;
+}
+
+kvs_status kvs_arf_accumulate(kvs_ctx* c, const double* p, const double* v, int64_t nsamp) {
+    if (!c) return KVS_EINVAL;
+    if (c->arf_mode == 0) return fail(c, KVS_ESTATE, "arf: no kvs_arf_begin");
+    if (nsamp < 1) return fail(c, KVS_EINVAL, "arf: nsamp must be >= 1");
+    if (!p) return fail(c, KVS_EINVAL, "arf: p is NULL");
+    if (c->arf_mode == KVS_ARF_POYNTING && !v) return fail(c, KVS_EINVAL, "arf: v is NULL in the Poynting form");
+    if (c->arf_mode == KVS_ARF_PLANE && v) return fail(c, KVS_EINVAL, "arf: v must be NULL in the plane-wave form");
+    API_HIP(c, hipSetDevice(c->device));
+    // stage one sample at a time (p, then v) through one device buffer
+    const int64_t per = (v ? 4 : 1) * c->N;
+    double* stage = nullptr;
+    API_HIP(c, hipMalloc(&stage, sizeof(double) * (size_t)per));
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < nsamp && e == hipSuccess; ++s) {
+        e = hipMemcpyAsync(stage, p + s * c->N, sizeof(double) * (size_t)c->N, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && v)
+            e = hipMemcpyAsync(stage + c->N, v + s * 3 * c->N, sizeof(double) * 3 * (size_t)c->N,
+                               hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = kvs_launch_arf_accumulate(c, stage, v ? stage + c->N : nullptr, 1, 0);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(stage);
+    if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("arf accumulate: ") + hipGetErrorString(e));
+    c->arf_samples += nsamp;
+    return KVS_OK;
+}
+
+kvs_status kvs_arf_get_sums(const kvs_ctx* cc, double* out, int64_t* nsamp) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    if (c->arf_mode == 0) return fail(c, KVS_ESTATE, "arf: no kvs_arf_begin");
+    if (nsamp) *nsamp = c->arf_samples;
+    if (!out) return KVS_OK;
+    const int64_t n = (c->arf_mode == KVS_ARF_PLANE ? 1 : 3) * c->N;
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, hipMemcpyAsync(out, c->arf_sum, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    return KVS_OK;
+}
+
+kvs_status kvs_arf_set_force(kvs_ctx* c, const double* alpha, int64_t n_alpha, const double* cs, int64_t n_c,
+                             const double* rho, int64_t n_rho, const uint8_t* mask, double n_pulse,
+                             const double* beam_dir) {
+    if (!c) return KVS_EINVAL;
+    if (c->arf_mode == 0) return fail(c, KVS_ESTATE, "arf: no kvs_arf_begin");
+    if (c->arf_samples == 0) return fail(c, KVS_ESTATE, "arf: no samples accumulated");
+    const bool plane = c->arf_mode == KVS_ARF_PLANE;
+    auto bad_count = [&](int64_t n) { return n != 1 && n != c->N; };
+    if (!alpha || bad_count(n_alpha)) return fail(c, KVS_EINVAL, "arf: alpha needs 1 or N values");
+    if (!cs || bad_count(n_c)) return fail(c, KVS_EINVAL, "arf: c needs 1 or N values");
+    if (plane && (!rho || bad_count(n_rho))) return fail(c, KVS_EINVAL, "arf: rho needs 1 or N values");
+    if (!(std::isfinite(n_pulse) && n_pulse > 0.0)) return fail(c, KVS_EINVAL, "arf: n_pulse must be > 0");
+    for (int64_t q = 0; q < n_alpha; ++q)
+        if (!(std::isfinite(alpha[q]) && alpha[q] >= 0.0)) return fail(c, KVS_EINVAL, "arf: alpha must be finite, >= 0");
+    for (int64_t q = 0; q < n_c; ++q)
+        if (!finite_pos(cs[q])) return fail(c, KVS_EINVAL, "arf: c must be finite, > 0");
+    if (plane)
+        for (int64_t q = 0; q < n_rho; ++q)
+            if (!finite_pos(rho[q])) return fail(c, KVS_EINVAL, "arf: rho must be finite, > 0");
+    double d[3] = {0.0, 0.0, 0.0};
+    if (plane) {
+        if (!beam_dir) return fail(c, KVS_EINVAL, "arf: beam_dir is NULL in the plane-wave form");
+        const double n2 = beam_dir[0] * beam_dir[0] + beam_dir[1] * beam_dir[1] + beam_dir[2] * beam_dir[2];
+        if (!(std::isfinite(n2) && n2 > 0.0)) return fail(c, KVS_EINVAL, "arf: beam_dir must be non-zero");
+        const double nn = std::sqrt(n2);
+        for (int q = 0; q < 3; ++q) d[q] = beam_dir[q] / nn;
+    }
+    API_HIP(c, hipSetDevice(c->device));
+    // coefficient maps and mask staged in one temporary device buffer
+    const int64_t nr = plane ? n_rho : 0;
+    const size_t doubles = (size_t)(n_alpha + n_c + nr);
+    const size_t bytes = sizeof(double) * doubles + (mask ? (size_t)c->N : 0);
+    char* tmp = nullptr;
+    API_HIP(c, hipMalloc(&tmp, bytes));
+    double* dA = reinterpret_cast<double*>(tmp);
+    double* dC = dA + n_alpha;
+    double* dR = plane ? dC + n_c : nullptr;
+    unsigned char* dM = mask ? reinterpret_cast<unsigned char*>(tmp + sizeof(double) * doubles) : nullptr;
+    hipError_t e = hipMemcpyAsync(dA, alpha, sizeof(double) * n_alpha, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dC, cs, sizeof(double) * n_c, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && plane) e = hipMemcpyAsync(dR, rho, sizeof(double) * n_rho, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && mask) e = hipMemcpyAsync(dM, mask, (size_t)c->N, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = kvs_launch_arf_force(c, dA, n_alpha == 1 ? 0 : 1, dC, n_c == 1 ? 0 : 1, dR, n_rho == 1 ? 0 : 1, dM,
+                                 n_pulse, d);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("arf force: ") + hipGetErrorString(e));
+    c->have_force = true;
+    c->fs_current = false;
     return KVS_OK;
 }
 

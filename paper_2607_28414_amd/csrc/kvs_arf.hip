@@ -1,0 +1,183 @@
+// Acoustic radiation body force from a time series of the acoustic field
+// (Sec. 3.4: plane-wave form, Eq. isppa_norm; Poynting form, Eq. arf_poynting).
+//
+// Two streaming kernels:
+//   arf_acc_kernel   folds nsamp samples of p (and v) into per-cell FP64 sums,
+//                    S += p^2 (plane-wave form) or S_i += p v_i (Poynting form),
+//                    sample by sample in the order given;
+//   arf_force_kernel turns the sums into the force pattern F (FP64, [3][N]).
+//
+// The accumulation is HBM-bound (16 B of FP32 input per cell and sample in
+// the Poynting form, plus one read and one write of the sums per launch):
+// each lane owns VEC consecutive cells so that every access is a 16-byte
+// vector load of a contiguous run, the samples of one launch are streamed
+// with non-temporal loads (read once), and the sums stay in registers across
+// the launch's samples.  Products and sums are FP64 and are not contracted
+// into fused multiply-adds, so the result is the plain sequential sum.
+#include "kvs_internal.hpp"
+
+namespace {
+
+template <typename T, int V>
+struct Vec {
+    typedef T type __attribute__((ext_vector_type(V)));
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void load_nt(const T* p, double (&o)[V]) {
+    if constexpr (V == 1) {
+        o[0] = (double)__builtin_nontemporal_load(p);
+    } else {
+        const typename Vec<T, V>::type x = __builtin_nontemporal_load(reinterpret_cast<const typename Vec<T, V>::type*>(p));
+#pragma unroll
+        for (int j = 0; j < V; ++j) o[j] = (double)x[j];
+    }
+}
+
+// MODE 1: plane-wave form (one sum), MODE 2: Poynting form (three sums).
+// Lane t owns cells [V t, V t + V); the host picks V > 1 only when N is a
+// multiple of V and the inputs are 16-byte aligned, so no lane straddles the
+// end of a sample.
+template <typename T, int MODE, int V>
+__global__ __launch_bounds__(256) void arf_acc_kernel(const T* __restrict__ p, const T* __restrict__ v, long long N,
+                                                      int nsamp, double* __restrict__ S) {
+#pragma clang fp contract(off)
+    constexpr int NS = MODE == 1 ? 1 : 3;
+    const long long c0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * V;
+    if (c0 >= N) return;
+    double acc[NS][V];
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+        for (int j = 0; j < V; ++j) acc[i][j] = S[i * N + c0 + j];
+#pragma unroll 2
+    for (int s = 0; s < nsamp; ++s) {
+        double ps[V];
+        load_nt<T, V>(p + (long long)s * N + c0, ps);
+        if constexpr (MODE == 1) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) acc[0][j] = acc[0][j] + ps[j] * ps[j];
+        } else {
+            const T* vs = v + (long long)s * 3 * N + c0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double vi[V];
+                load_nt<T, V>(vs + i * N, vi);
+#pragma unroll
+                for (int j = 0; j < V; ++j) acc[i][j] = acc[i][j] + ps[j] * vi[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+#pragma unroll
+        for (int j = 0; j < V; ++j) S[i * N + c0 + j] = acc[i][j];
+}
+
+// Coefficient maps are indexed with stride 0 (one uniform value) or 1 (a
+// value per cell).  mask == nullptr keeps every cell.
+struct ForceArgs {
+    const double* S;
+    long long N;
+    int mode;
+    const double* alpha;
+    const double* c;
+    const double* rho;
+    int sa, sc, sr;
+    const unsigned char* mask;
+    double n_pulse;
+    double d0, d1, d2;  // unit beam direction (plane-wave form)
+    double* F;
+};
+
+__global__ __launch_bounds__(256) void arf_force_kernel(const ForceArgs a) {
+#pragma clang fp contract(off)
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const bool keep = a.mask == nullptr || a.mask[i] != 0;
+        const double al = a.alpha[i * a.sa], cc = a.c[i * a.sc];
+        const double coef = 2.0 * al / cc;
+        double f0, f1, f2;
+        if (a.mode == 1) {
+            const double intensity = a.S[i] / (a.rho[i * a.sr] * cc * a.n_pulse);
+            const double b0 = coef * intensity;
+            f0 = b0 * a.d0;
+            f1 = b0 * a.d1;
+            f2 = b0 * a.d2;
+        } else {
+            f0 = coef * (a.S[i] / a.n_pulse);
+            f1 = coef * (a.S[a.N + i] / a.n_pulse);
+            f2 = coef * (a.S[2 * a.N + i] / a.n_pulse);
+        }
+        a.F[i] = keep ? f0 : 0.0;
+        a.F[a.N + i] = keep ? f1 : 0.0;
+        a.F[2 * a.N + i] = keep ? f2 : 0.0;
+    }
+}
+
+template <typename T, int MODE, int V>
+void launch_acc(hipStream_t s, const void* p, const void* v, long long N, int nsamp, double* S) {
+    const long long lanes = (N + V - 1) / V;
+    const unsigned blocks = (unsigned)((lanes + 255) / 256);
+    hipLaunchKernelGGL((arf_acc_kernel<T, MODE, V>), dim3(blocks), dim3(256), 0, s, static_cast<const T*>(p),
+                       static_cast<const T*>(v), N, nsamp, S);
+}
+
+template <typename T, int MODE>
+void launch_acc_mode(hipStream_t s, const void* p, const void* v, long long N, int nsamp, double* S) {
+    constexpr int V = sizeof(T) == 4 ? 4 : 2;  // 16-byte accesses
+    const bool aligned = (reinterpret_cast<uintptr_t>(p) % 16 == 0) &&
+                         (MODE == 1 || reinterpret_cast<uintptr_t>(v) % 16 == 0) && (N % V == 0);
+    if (aligned)
+        launch_acc<T, MODE, V>(s, p, v, N, nsamp, S);
+    else
+        launch_acc<T, MODE, 1>(s, p, v, N, nsamp, S);
+}
+
+}  // namespace
+
+// Samples per launch: bounds the index arithmetic of one launch and keeps
+// a launch short enough to interleave with other work on the stream.
+static constexpr int64_t kMaxSamplesPerLaunch = 64;
+
+hipError_t kvs_launch_arf_accumulate(kvs_ctx* c, const void* p, const void* v, int64_t nsamp, int dtype) {
+    const long long N = (long long)c->N;
+    const size_t es = dtype == 1 ? sizeof(float) : sizeof(double);
+    for (int64_t s0 = 0; s0 < nsamp; s0 += kMaxSamplesPerLaunch) {
+        const int ns = (int)std::min<int64_t>(kMaxSamplesPerLaunch, nsamp - s0);
+        const char* ps = static_cast<const char*>(p) + (size_t)s0 * N * es;
+        const char* vs = v ? static_cast<const char*>(v) + (size_t)s0 * 3 * N * es : nullptr;
+        if (c->arf_mode == 1)
+            dtype == 1 ? launch_acc_mode<float, 1>(c->stream, ps, vs, N, ns, c->arf_sum)
+                       : launch_acc_mode<double, 1>(c->stream, ps, vs, N, ns, c->arf_sum);
+        else
+            dtype == 1 ? launch_acc_mode<float, 2>(c->stream, ps, vs, N, ns, c->arf_sum)
+                       : launch_acc_mode<double, 2>(c->stream, ps, vs, N, ns, c->arf_sum);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t kvs_launch_arf_force(kvs_ctx* c, const double* alpha, int sa, const double* cs, int sc, const double* rho,
+                                int sr, const unsigned char* mask, double n_pulse, const double d[3]) {
+    ForceArgs a{};
+    a.S = c->arf_sum;
+    a.N = (long long)c->N;
+    a.mode = c->arf_mode;
+    a.alpha = alpha;
+    a.c = cs;
+    a.rho = rho ? rho : cs;  // unread in the Poynting form
+    a.sa = sa;
+    a.sc = sc;
+    a.sr = rho ? sr : 0;
+    a.mask = mask;
+    a.n_pulse = n_pulse;
+    a.d0 = d[0];
+    a.d1 = d[1];
+    a.d2 = d[2];
+    a.F = c->F;
+    const unsigned blocks = (unsigned)std::min<long long>((a.N + 255) / 256, 16384);
+    hipLaunchKernelGGL(arf_force_kernel, dim3(blocks), dim3(256), 0, c->stream, a);
+    return hipGetLastError();
+}

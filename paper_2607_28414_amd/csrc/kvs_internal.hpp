@@ -116,6 +116,13 @@ struct kvs_ctx {
     int64_t peak_off[KVS_MAX_PEAK_PLANES] = {};
     int64_t peak_cells = 0;
     void* peak = nullptr;
+
+    // acoustic radiation force: running FP64 sums over the acoustic samples,
+    // [N] (plane-wave form: p^2) or [3][N] (Poynting form: p v_i)
+    int arf_mode = 0;  // 0: none, KVS_ARF_PLANE, KVS_ARF_POYNTING
+    double* arf_sum = nullptr;
+    int64_t arf_sum_cap = 0;  // doubles allocated
+    int64_t arf_samples = 0;
 };
 
 // Plane table handed to the peak kernel by value: axis, index along it, the
@@ -181,6 +188,13 @@ hipError_t kvs_launch_widen(kvs_ctx* c, const void* src, double* dst, int64_t n)
 hipError_t kvs_launch_f32_to_f64(kvs_ctx* c, const float* src, double* dst, int64_t n);
 hipError_t kvs_launch_zero_boundary(kvs_ctx* c, void* field3);
 // stable dt: per-cell bound reduced to its minimum in *out (device double)
+// acoustic radiation force (kvs_arf.hip): fold nsamp samples (dtype 0 =
+// double, 1 = float; p [nsamp][N], v [nsamp][3][N] in the Poynting form) into
+// c->arf_sum; then write F from the sums with coefficient maps of stride 0
+// (uniform) or 1 (per cell), an optional mask and the unit beam direction d
+hipError_t kvs_launch_arf_accumulate(kvs_ctx* c, const void* p, const void* v, int64_t nsamp, int dtype);
+hipError_t kvs_launch_arf_force(kvs_ctx* c, const double* alpha, int sa, const double* cs, int sc, const double* rho,
+                                int sr, const unsigned char* mask, double n_pulse, const double d[3]);
 hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho, const double* deta,
                                 double* partial, int64_t npartial, double* out);
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(PKG, "libkvs.so")
 KVS_OK, KVS_EINVAL, KVS_ENOMEM, KVS_EDEVICE, KVS_ENOTCONV, KVS_EBREAKDOWN, KVS_EUNSTABLE, KVS_ESTATE = range(8)
 KVS_FP64, KVS_FP32 = 0, 1
 KVS_PC_NONE, KVS_PC_JACOBI, KVS_PC_UNET = 0, 1, 2
+KVS_ARF_PLANE, KVS_ARF_POYNTING = 1, 2
 STATUS_NAMES = {0: "KVS_OK", 1: "KVS_EINVAL", 2: "KVS_ENOMEM", 3: "KVS_EDEVICE", 4: "KVS_ENOTCONV",
                 5: "KVS_EBREAKDOWN", 6: "KVS_EUNSTABLE", 7: "KVS_ESTATE"}
 
@@ -70,6 +71,7 @@ SIGNATURES = {
     "kvs_set_dt": ([_P, C.c_double], C.c_int),
     "kvs_set_force": ([_P, _D], C.c_int),
     "kvs_set_force_device": ([_P, C.c_void_p, C.c_int32], C.c_int),
+    "kvs_get_force": ([_P, _D], C.c_int),
     "kvs_set_envelope": ([_P, _D, C.c_int64], C.c_int),
     "kvs_project": ([_P, C.POINTER(kvs_solve_opts), C.POINTER(kvs_solve_report)], C.c_int),
     "kvs_set_projected_force": ([_P, _D], C.c_int),
@@ -129,6 +131,12 @@ SIGNATURES = {
     "kvs_set_step_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
+    "kvs_arf_begin": ([_P, C.c_int32], C.c_int),
+    "kvs_arf_accumulate_device": ([_P, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32], C.c_int),
+    "kvs_arf_accumulate": ([_P, _D, _D, C.c_int64], C.c_int),
+    "kvs_arf_get_sums": ([_P, _D, _I64], C.c_int),
+    "kvs_arf_set_force": ([_P, _D, C.c_int64, _D, C.c_int64, _D, C.c_int64, C.POINTER(C.c_uint8), C.c_double,
+                           _D], C.c_int),
 }
 
 
@@ -249,6 +257,12 @@ def kvs_set_force(ctx, F):
 
 def kvs_set_force_device(ctx, ptr, dtype):
     _check(lib().kvs_set_force_device(ctx, C.c_void_p(ptr), int(dtype)), ctx)
+
+
+def kvs_get_force(ctx, shape):
+    out = np.empty((3,) + _out_shape(ctx, shape))
+    _check(lib().kvs_get_force(ctx, _dptr(out)), ctx)
+    return out
 
 
 def kvs_set_envelope(ctx, g):
@@ -571,3 +585,64 @@ def kvs_last_fallbacks(ctx):
     v = C.c_int64()
     _check(lib().kvs_last_fallbacks(ctx, C.byref(v)), ctx)
     return v.value
+
+
+# ---- acoustic radiation force ---------------------------------------------
+
+def kvs_arf_begin(ctx, mode):
+    _check(lib().kvs_arf_begin(ctx, int(mode)), ctx)
+
+
+def kvs_arf_accumulate_device(ctx, p_ptr, v_ptr, nsamp, dtype):
+    """Device pointers (ints, e.g. a tensor's data_ptr()); v_ptr None in the
+    plane-wave form."""
+    _check(lib().kvs_arf_accumulate_device(ctx, C.c_void_p(p_ptr), C.c_void_p(v_ptr) if v_ptr else None,
+                                           int(nsamp), int(dtype)), ctx)
+
+
+def kvs_arf_accumulate(ctx, p, v=None):
+    """Host samples: p [nsamp][N...], v [nsamp][3][N...] or None."""
+    n = _cells(ctx)
+    p = _f64(p)
+    if p.size % n:
+        raise ValueError(f"p holds {p.size} values, not a whole number of samples of {n}")
+    nsamp = p.size // n
+    if v is not None:
+        v = _f64(v)
+        if v.size != 3 * n * nsamp:
+            raise ValueError(f"v holds {v.size} values, expected {3 * n * nsamp}")
+    _check(lib().kvs_arf_accumulate(ctx, _dptr(p), _dptr(v) if v is not None else None, nsamp), ctx)
+
+
+def kvs_arf_get_sums(ctx, shape, mode):
+    """(sums, nsamp): sums [nz][ny][nx] (plane-wave form) or [3][nz][ny][nx]."""
+    shape = _out_shape(ctx, shape)
+    out = np.empty(shape if mode == KVS_ARF_PLANE else (3,) + shape)
+    ns = C.c_int64()
+    _check(lib().kvs_arf_get_sums(ctx, _dptr(out), C.byref(ns)), ctx)
+    return out, ns.value
+
+
+def _coef(ctx, a):
+    """A number (uniform) or a per-cell map: (array, count)."""
+    if np.isscalar(a):
+        return np.array([float(a)]), 1
+    a = _host(ctx, a, 1)
+    return a, a.size
+
+
+def kvs_arf_set_force(ctx, alpha, c, n_pulse, rho=None, mask=None, beam_dir=None):
+    A, na = _coef(ctx, alpha)
+    Cs, nc = _coef(ctx, c)
+    R, nr = _coef(ctx, rho) if rho is not None else (None, 0)
+    M = None
+    if mask is not None:
+        M = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+        if M.size != _cells(ctx):
+            raise ValueError("mask needs N values")
+    d = _f64(beam_dir) if beam_dir is not None else None
+    if d is not None and d.size != 3:
+        raise ValueError("beam_dir needs 3 values")
+    _check(lib().kvs_arf_set_force(ctx, _dptr(A), na, _dptr(Cs), nc, _dptr(R) if R is not None else None, nr,
+                                   M.ctypes.data_as(C.POINTER(C.c_uint8)) if M is not None else None,
+                                   float(n_pulse), _dptr(d) if d is not None else None), ctx)

@@ -1,0 +1,243 @@
+"""Parity of the acoustic radiation force path (Sec. 3.4, Eqs. isppa_norm and
+arf_poynting) with the FP64 oracle, through the C ABI.
+
+Bars: the per-cell sums are bit-identical to the oracle's sequential FP64
+sums of the same inputs (FP64 products of FP32 inputs are exact, and both
+sides add sample by sample in the same order without fused multiply-adds);
+the force pattern agrees to 4e-16 relative (a few roundings of FP64
+coefficient arithmetic; the test checks 1e-15)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import arf as oarf
+from oracle.analysis import rel_l2
+from workloads import acoustic_beam_samples
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kvs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2607_28414_amd import kvs as k
+    k.lib()
+    return k
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def shape_of(grid):
+    return (grid[2], grid[1], grid[0])
+
+
+def random_series(rng, grid, ns, dtype):
+    shp = shape_of(grid)
+    p = (rng.standard_normal((ns,) + shp) * 1e5).astype(dtype)
+    v = (rng.standard_normal((ns, 3) + shp) * 0.1).astype(dtype)
+    return p, v
+
+
+def accumulate_in_chunks(kvs, ctx, p, v, chunks, dtype_code):
+    """Device path: contiguous device copies of the chunks, in order."""
+    import torch
+    s = 0
+    keep = []
+    for n in chunks:
+        pt = torch.from_numpy(np.ascontiguousarray(p[s:s + n])).to("cuda")
+        vt = torch.from_numpy(np.ascontiguousarray(v[s:s + n])).to("cuda") if v is not None else None
+        keep += [pt, vt]
+        kvs.kvs_arf_accumulate_device(ctx, pt.data_ptr(), vt.data_ptr() if vt is not None else None, n, dtype_code)
+        s += n
+    kvs.kvs_synchronize(ctx)
+    return s
+
+
+# grids: N odd (one cell per lane), N a multiple of 4 (16-byte vector lanes)
+GRIDS = [(37, 29, 41, 2e-4, 2e-4, 2e-4), (64, 12, 10, 2e-4, 2e-4, 2e-4)]
+
+
+@pytest.mark.parametrize("grid", GRIDS, ids=["odd", "vec"])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+@pytest.mark.parametrize("mode", [1, 2], ids=["plane", "poynting"])
+def test_sums_are_the_oracle_sums_bitwise(kvs, grid, dtype, mode):
+    say(f"case arf sums grid {grid[:3]} dtype {dtype.__name__} mode {mode}")
+    rng = np.random.default_rng(77)
+    ns = 3 + 1 + 70 + 2  # the 70-sample chunk spans two launches
+    p, v = random_series(rng, grid, ns, dtype)
+    if mode == 1:
+        v = None
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        kvs.kvs_arf_begin(ctx, mode)
+        n = accumulate_in_chunks(kvs, ctx, p, v, [3, 1, 70], 1 if dtype == np.float32 else 0)
+        # the last two samples through the host path
+        kvs.kvs_arf_accumulate(ctx, p[n:].astype(np.float64), v[n:].astype(np.float64) if v is not None else None)
+        S, count = kvs.kvs_arf_get_sums(ctx, shape_of(grid), mode)
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert count == ns
+    S_o = oarf.time_sums_pp(p) if mode == 1 else oarf.time_sums_pv(p, v)
+    assert np.array_equal(S, S_o), np.max(np.abs(S - S_o))
+
+
+def test_begin_restarts_and_switches_form(kvs):
+    grid = GRIDS[1]
+    rng = np.random.default_rng(3)
+    p, v = random_series(rng, grid, 5, np.float32)
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        kvs.kvs_arf_begin(ctx, 1)
+        accumulate_in_chunks(kvs, ctx, p, None, [5], 1)
+        kvs.kvs_arf_begin(ctx, 2)
+        accumulate_in_chunks(kvs, ctx, p[:2], v[:2], [2], 1)
+        S, count = kvs.kvs_arf_get_sums(ctx, shape_of(grid), 2)
+        kvs.kvs_arf_begin(ctx, 1)
+        _, zero = kvs.kvs_arf_get_sums(ctx, shape_of(grid), 1)
+        S1, _ = kvs.kvs_arf_get_sums(ctx, shape_of(grid), 1)
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert count == 2 and zero == 0 and not S1.any()
+    assert np.array_equal(S, oarf.time_sums_pv(p[:2], v[:2]))
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["plane", "poynting"])
+def test_force_pattern_and_projection_match_oracle(kvs, mode):
+    """Focused tone burst on a ragged grid, per-cell alpha and c (and rho),
+    a mask, then the projection of the resulting force."""
+    grid = (33, 30, 47, 2e-4, 2e-4, 2e-4)
+    shp = shape_of(grid)
+    say(f"case arf force mode {mode}")
+    p, v = acoustic_beam_samples(grid, 60, per=12, cycles=4, w0=1.2e-3, dtype=np.float32)
+    rng = np.random.default_rng(11)
+    alpha = rng.uniform(3.0, 40.0, shp)
+    c = rng.uniform(1450.0, 2900.0, shp)
+    rho = rng.uniform(1000.0, 1900.0, shp)
+    mask = rng.uniform(size=shp) < 0.8
+    n_pulse = 48.0
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP64)
+    try:
+        kvs.kvs_arf_begin(ctx, mode)
+        accumulate_in_chunks(kvs, ctx, p, v if mode == 2 else None, [25, 35], 1)
+        if mode == 1:
+            kvs.kvs_arf_set_force(ctx, alpha, c, n_pulse, rho=rho, mask=mask, beam_dir=(0.0, 0.5, 2.0))
+        else:
+            kvs.kvs_arf_set_force(ctx, alpha, c, n_pulse, mask=mask)
+        F = kvs.kvs_get_force(ctx, shp)
+        if mode == 1:
+            F_o = oarf.plane_wave_force(oarf.time_sums_pp(p), alpha, c, rho, n_pulse, (0.0, 0.5, 2.0), mask=mask)
+        else:
+            F_o = oarf.poynting_force(oarf.time_sums_pv(p, v), alpha, c, n_pulse, mask=mask)
+        FS_o, _, rep_o = oracle.project(grid, F_o, tol=1e-10, jacobi=True)
+        rep = kvs.kvs_project(ctx, tol=1e-10, fixed_iters=rep_o["iters"])
+        FS = kvs.kvs_get_projected_force(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert np.abs(F_o).max() > 0
+    assert np.all(np.abs(F - F_o) <= 1e-15 * np.abs(F_o)), np.max(np.abs(F - F_o) / np.maximum(np.abs(F_o), 1e-300))
+    assert not F[:, ~mask].any()
+    assert rep_o["status"] == 0 and rep["iters"] == rep_o["iters"]
+    assert rel_l2(FS, FS_o) < 1e-12
+
+
+def test_uniform_coefficients_and_unit_direction(kvs):
+    grid = GRIDS[1]
+    shp = shape_of(grid)
+    rng = np.random.default_rng(9)
+    p, _ = random_series(rng, grid, 7, np.float64)
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP64)
+    try:
+        kvs.kvs_arf_begin(ctx, 1)
+        accumulate_in_chunks(kvs, ctx, p, None, [7], 0)
+        kvs.kvs_arf_set_force(ctx, 5.8, 1540.0, 7, rho=1000.0, beam_dir=(0, 0, 3.0))
+        F = kvs.kvs_get_force(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    F_o = oarf.plane_wave_force(oarf.time_sums_pp(p), 5.8, 1540.0, 1000.0, 7, (0, 0, 1))
+    assert not F[0].any() and not F[1].any()
+    assert np.all(np.abs(F - F_o) <= 1e-15 * np.abs(F_o))
+
+
+def test_arf_errors(kvs):
+    import ctypes as C
+    grid = GRIDS[1]
+    L = kvs.lib()
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        assert L.kvs_arf_begin(ctx, 3) == kvs.KVS_EINVAL
+        assert L.kvs_arf_accumulate_device(ctx, C.c_void_p(1), None, 1, 1) == kvs.KVS_ESTATE
+        assert L.kvs_arf_get_sums(ctx, None, None) == kvs.KVS_ESTATE
+        kvs.kvs_arf_begin(ctx, 2)
+        one = np.ones(1)
+        d = one.ctypes.data_as(C.POINTER(C.c_double))
+        # no samples yet
+        assert L.kvs_arf_set_force(ctx, d, 1, d, 1, None, 0, None, 1.0, None) == kvs.KVS_ESTATE
+        assert L.kvs_arf_accumulate_device(ctx, C.c_void_p(1), None, 1, 1) == kvs.KVS_EINVAL  # v missing
+        assert L.kvs_arf_accumulate_device(ctx, C.c_void_p(1), C.c_void_p(1), 0, 1) == kvs.KVS_EINVAL
+        assert L.kvs_arf_accumulate_device(ctx, C.c_void_p(1), C.c_void_p(1), 1, 2) == kvs.KVS_EINVAL
+        assert L.kvs_arf_accumulate_device(ctx, None, C.c_void_p(1), 1, 1) == kvs.KVS_EINVAL
+        kvs.kvs_arf_accumulate(ctx, np.ones(int(np.prod(grid[:3]))), np.ones(3 * int(np.prod(grid[:3]))))
+        assert L.kvs_arf_set_force(ctx, d, 2, d, 1, None, 0, None, 1.0, None) == kvs.KVS_EINVAL  # count
+        bad = np.array([-1.0])
+        b = bad.ctypes.data_as(C.POINTER(C.c_double))
+        assert L.kvs_arf_set_force(ctx, b, 1, d, 1, None, 0, None, 1.0, None) == kvs.KVS_EINVAL  # alpha < 0
+        assert L.kvs_arf_set_force(ctx, d, 1, b, 1, None, 0, None, 1.0, None) == kvs.KVS_EINVAL  # c <= 0
+        assert L.kvs_arf_set_force(ctx, d, 1, d, 1, None, 0, None, 0.0, None) == kvs.KVS_EINVAL  # n_pulse
+        assert L.kvs_arf_set_force(ctx, d, 1, d, 1, None, 0, None, 1.0, None) == kvs.KVS_OK
+        kvs.kvs_arf_begin(ctx, 1)
+        assert L.kvs_arf_accumulate_device(ctx, C.c_void_p(1), C.c_void_p(1), 1, 1) == kvs.KVS_EINVAL  # v given
+        kvs.kvs_arf_accumulate(ctx, np.ones(int(np.prod(grid[:3]))))
+        zero3 = np.zeros(3)
+        z3 = zero3.ctypes.data_as(C.POINTER(C.c_double))
+        assert L.kvs_arf_set_force(ctx, d, 1, d, 1, None, 0, None, 1.0, z3) == kvs.KVS_EINVAL  # rho missing
+        assert L.kvs_arf_set_force(ctx, d, 1, d, 1, d, 1, None, 1.0, z3) == kvs.KVS_EINVAL  # zero direction
+        assert L.kvs_arf_set_force(ctx, d, 1, d, 1, d, 1, None, 1.0, None) == kvs.KVS_EINVAL  # no direction
+    finally:
+        kvs.kvs_destroy(ctx)
+
+
+def test_full_size_shell_grid_sampled(kvs):
+    """512 x 512 x 640 (the transcranial grid), Poynting form, 16 FP32 samples
+    of the focused burst in two launches; sums at sampled cells are the
+    oracle's sums of the same cells' samples, bit for bit."""
+    import torch
+    grid = (512, 512, 640, 2e-4, 2e-4, 2e-4)
+    shp = shape_of(grid)
+    N = int(np.prod(shp))
+    say("case arf full size 512x512x640")
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    rng = np.random.default_rng(21)
+    cells = np.unique(np.concatenate([rng.integers(0, N, 3000), [0, N - 1, N // 2 + 256 * 512 + 256]]))
+    idx = torch.from_numpy(cells).to("cuda")
+    sp, sv = [], []
+    try:
+        kvs.kvs_arf_begin(ctx, 2)
+        for s0 in (0, 8):
+            p, v = acoustic_beam_samples(grid, 8, per=8, cycles=2, s0=s0, focus=(0.0, 0.0, 0.03),
+                                         xp=torch, device="cuda", dtype=torch.float32)
+            # the samples are written on torch's stream; the library reads
+            # them on its own stream
+            torch.cuda.synchronize()
+            kvs.kvs_arf_accumulate_device(ctx, p.data_ptr(), v.data_ptr(), 8, 1)
+            kvs.kvs_synchronize(ctx)
+            sp.append(p.reshape(8, -1)[:, idx].cpu().numpy())
+            sv.append(v.reshape(8, 3, -1)[:, :, idx].cpu().numpy())
+            del p, v
+        S = np.empty((3, N))
+        L = kvs.lib()
+        import ctypes as C
+        ns = C.c_int64()
+        kvs._check(L.kvs_arf_get_sums(ctx, S.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ns)), ctx)
+    finally:
+        kvs.kvs_destroy(ctx)
+        torch.cuda.empty_cache()
+    assert ns.value == 16
+    P = np.concatenate(sp)
+    V = np.concatenate(sv)
+    S_o = oarf.time_sums_pv(P, V)
+    assert np.abs(S_o).max() > 0
+    assert np.array_equal(S[:, cells], S_o)

@@ -367,3 +367,53 @@ def cfg5_shell(n=(512, 512, 640), h=0.2e-3, seed=1005):
                     probes=x_line_probes(grid, k=k_push), comp=2, dt_factor=0.4, push_time=200e-6,
                     sponge_cells=8, tol=1e-8, precision="fp32",
                     meta={"geometry": geo, "z_push": z_push, "k_push": k_push, "peak_planes": planes})
+
+
+def acoustic_beam_samples(grid, samples, f0=1.0e6, c=1540.0, rho=1000.0, alpha=5.8, p0=1.5e6, w0=1.5e-3,
+                          focus=(0.0, 0.0, 0.0), per=20, cycles=10, s0=0, xp=np, device=None,
+                          dtype=np.float32):
+    """A synthetic focused tone burst standing in for an acoustic solver's
+    output (the paper's Fullwave fields are not available): a Gaussian beam
+    along +z focused at `focus` (waist w0, wavelength c/f0, attenuated by
+    e^{-alpha (z - z_min)}), `cycles` periods of `per` samples each, silence
+    after; v = p n / (rho c) with n the local direction of the phase front
+    (x/R, y/R, 1), normalised.
+
+    Returns (p, v): p [samples][nz][ny][nx], v [samples][3][nz][ny][nx] for
+    sample indices s0 .. s0 + samples - 1, built with `xp` (numpy, or torch
+    with `device`) in FP64 and cast to `dtype`.
+    """
+    nx, ny, nz, hx, hy, hz = grid
+    if xp is np:
+        arange = lambda n, h: (np.arange(n) - n // 2) * h
+        zeros = lambda shape: np.zeros(shape)
+        cast = lambda a: a.astype(dtype)
+    else:
+        arange = lambda n, h: (xp.arange(n, device=device, dtype=xp.float64) - n // 2) * h
+        zeros = lambda shape: xp.zeros(shape, device=device, dtype=xp.float64)
+        cast = lambda a: a.to(dtype)
+    x = arange(nx, hx)[None, None, :] - focus[0]
+    y = arange(ny, hy)[None, :, None] - focus[1]
+    z = arange(nz, hz)[:, None, None]
+    dz = z - focus[2]
+    lam = c / f0
+    k = 2 * np.pi / lam
+    zr = np.pi * w0 ** 2 / lam
+    w = w0 * (1 + (dz / zr) ** 2) ** 0.5
+    inv_r = dz / (dz ** 2 + zr ** 2)
+    rr = x ** 2 + y ** 2
+    amp = p0 * (w0 / w) * xp.exp(-rr / w ** 2) * xp.exp(-alpha * (z - z.min()))
+    phase = k * dz + k * rr * inv_r / 2 - xp.arctan(dz / zr)
+    nxv, nyv = x * inv_r, y * inv_r
+    norm = (nxv ** 2 + nyv ** 2 + 1.0) ** 0.5
+    p = zeros((samples, nz, ny, nx))
+    for q in range(samples):
+        s = s0 + q
+        if s < per * cycles:
+            p[q] = amp * xp.cos(2 * np.pi * s / per - phase)
+    scale = 1.0 / (rho * c)
+    v = zeros((samples, 3, nz, ny, nx))
+    v[:, 0] = p * (scale * nxv / norm)
+    v[:, 1] = p * (scale * nyv / norm)
+    v[:, 2] = p * (scale / norm)
+    return cast(p), cast(v)
