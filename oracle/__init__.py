@@ -239,3 +239,35 @@ def peak_maps(grid, G, rho, eta, dt, nsteps, planes, FS=None, env=None, u=None, 
                       sponge_cells=sponge_cells, sigma_max=sigma_max)
         maps = [np.maximum(m, mag(u, a, i)) for m, (a, i) in zip(maps, planes)]
     return maps, u, w
+
+
+def curl(grid, A):
+    """Centred curl of a vector potential A ([3][nz][ny][nx]) on the interior
+    nodes, zero on the outer layer: the curl-based initialisation of Sec. 3.5
+    (a divergence-free field built from a vector potential), with the centred
+    first differences (f(+a) - f(-a)) / (2 h_a) of the grid."""
+    nx, ny, nz, hx, hy, hz = grid
+    A = _f64(A).reshape((3,) + _shape(grid))
+
+    def dx(f):
+        return (f[1:-1, 1:-1, 2:] - f[1:-1, 1:-1, :-2]) / (2 * hx)
+
+    def dy(f):
+        return (f[1:-1, 2:, 1:-1] - f[1:-1, :-2, 1:-1]) / (2 * hy)
+
+    def dz(f):
+        return (f[2:, 1:-1, 1:-1] - f[:-2, 1:-1, 1:-1]) / (2 * hz)
+
+    Ax, Ay, Az = A
+    out = np.zeros_like(A)
+    out[0, 1:-1, 1:-1, 1:-1] = dy(Az) - dz(Ay)
+    out[1, 1:-1, 1:-1, 1:-1] = dz(Ax) - dx(Az)
+    out[2, 1:-1, 1:-1, 1:-1] = dx(Ay) - dy(Ax)
+    return out
+
+
+def curl_state(grid, A, dt):
+    """Initial state (u, w) of the summed form for an initial velocity equal
+    to the curl of A: u = 0 and w = u^0 - u^{-1} = dt * curl(A)."""
+    v = curl(grid, A)
+    return np.zeros_like(v), dt * v
