@@ -205,6 +205,15 @@ kvs_status kvs_clear_traces(kvs_ctx* ctx);
  * absolute step index n.  get blocks; set resets the outer layer to 0. */
 kvs_status kvs_get_state(const kvs_ctx* ctx, double* u, double* w, int64_t* step);
 kvs_status kvs_set_state(kvs_ctx* ctx, const double* u, const double* w, int64_t step);
+/* Curl-based initial state (Sec. 3.5; the source of the wavespeed validation,
+ * Sec. 4.1): an initial velocity v0 = curl_h A, divergence-free by
+ * construction, at rest displacement: u = 0 and w = dt v0, where curl_h
+ * takes the centred first differences (f(+a) - f(-a)) / (2 h_a) on the
+ * interior nodes and is 0 on the outer layer.  A: host, 3*N doubles
+ * [3][nz][ny][nx] (copied); step: the absolute step index of the new state
+ * (>= 0).  Needs dt (else KVS_ESTATE).  Traces and peak maps are kept, as
+ * with kvs_set_state.  Blocks. */
+kvs_status kvs_set_state_curl(kvs_ctx* ctx, const double* A, int64_t step);
 /* Return the medium to rest (u = w = 0), reset the step index to 0 and clear
  * the traces; material, dt, force, projection and probes are kept. */
 kvs_status kvs_reset_state(kvs_ctx* ctx);

@@ -82,3 +82,31 @@ def two_sensor_k(a1, a2, dx, k_guess):
     m = np.round((kr_guess * dx - ph) / (2 * np.pi))
     kr = (ph + 2 * np.pi * m) / dx
     return complex(kr, alpha)
+
+
+def xcorr_lag(ref, sig, dt):
+    """Delay of `sig` relative to `ref` (positive: sig later): the lag of the
+    maximum of their full cross-correlation, with parabolic sub-sample
+    refinement."""
+    ref = np.asarray(ref, dtype=float)
+    sig = np.asarray(sig, dtype=float)
+    cc = np.correlate(sig, ref, mode="full")  # entry k <-> lag k - (len(ref) - 1)
+    n = int(np.argmax(cc))
+    frac = 0.0
+    if 0 < n < len(cc) - 1:
+        y0, y1, y2 = cc[n - 1], cc[n], cc[n + 1]
+        den = y0 - 2.0 * y1 + y2
+        if den != 0:
+            frac = 0.5 * (y0 - y2) / den
+    return (n - (len(ref) - 1) + frac) * dt
+
+
+def group_speed_xcorr(traces, offsets, dt):
+    """Shear-wave group speed from traces [time][sensor] at lateral offsets:
+    lags of every trace against the first by cross-correlation, then the
+    least-squares slope of offset vs lag (Sec. 4.4 estimator).  Returns
+    (speed, lags)."""
+    tr = np.asarray(traces, dtype=float)
+    lags = np.array([xcorr_lag(tr[:, 0], tr[:, i], dt) for i in range(tr.shape[1])])
+    speed, _ = fit_speed(offsets, lags)
+    return speed, lags

@@ -643,6 +643,23 @@ kvs_status kvs_set_state(kvs_ctx* c, const double* u, const double* w, int64_t s
     return KVS_OK;
 }
 
+kvs_status kvs_set_state_curl(kvs_ctx* c, const double* A, int64_t step) {
+    if (!c) return KVS_EINVAL;
+    if (!A || step < 0) return fail(c, KVS_EINVAL, "curl state: A is NULL or step < 0");
+    if (!c->have_dt) return fail(c, KVS_ESTATE, "curl state: no dt set");
+    const size_t bytes = sizeof(double) * 3 * c->N;
+    API_HIP(c, hipSetDevice(c->device));
+    double* tmp = nullptr;
+    API_HIP(c, hipMalloc(&tmp, bytes));
+    hipError_t e = hipMemcpyAsync(tmp, A, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = kvs_launch_curl_state(c, tmp);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("curl state: ") + hipGetErrorString(e));
+    c->step = step;
+    return KVS_OK;
+}
+
 kvs_status kvs_reset_state(kvs_ctx* c) {
     if (!c) return KVS_EINVAL;
     const size_t bytes = 3 * (size_t)c->N * tsize(c);

@@ -195,6 +195,9 @@ hipError_t kvs_launch_zero_boundary(kvs_ctx* c, void* field3);
 hipError_t kvs_launch_arf_accumulate(kvs_ctx* c, const void* p, const void* v, int64_t nsamp, int dtype);
 hipError_t kvs_launch_arf_force(kvs_ctx* c, const double* alpha, int sa, const double* cs, int sc, const double* rho,
                                 int sr, const unsigned char* mask, double n_pulse, const double d[3]);
+// curl-based initial state (kvs_init.hip): u[cur] = 0, w[cur] = dt curl_h A
+// (A: device, 3N doubles)
+hipError_t kvs_launch_curl_state(kvs_ctx* c, const double* A);
 hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho, const double* deta,
                                 double* partial, int64_t npartial, double* out);
 

@@ -1,0 +1,124 @@
+"""The paper's validation workloads on the GPU, through the C ABI.
+
+Curl-based initial state (Sec. 3.5) and the non-viscous wavespeed recovery
+(Sec. 4.1): the state matches the oracle's exactly (FP64) or to the FP32
+rounding of the same FP64 value; runs from it match the oracle's traces
+(FP64 to 1e-12, FP32 to 2e-5 relative L2); at the paper's 180^3 size the
+FP32 traces match the oracle's stored ones (2e-5) and the peak-arrival fit
+recovers cs = 2 m/s within 1 %."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.analysis import arrival_time, fit_speed, rel_l2
+from workloads import curl_wavespeed_case
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "curl_wavespeed_180.txt")
+
+
+@pytest.fixture(scope="module")
+def kvs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2607_28414_amd import kvs as k
+    k.lib()
+    return k
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_curl_state_matches_oracle(kvs, precision):
+    grid = (37, 29, 41, 2e-4, 2.5e-4, 3e-4)
+    shp = (grid[2], grid[1], grid[0])
+    say(f"case curl state precision {precision}")
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((3,) + shp) * 1e-6
+    dt = 1.7e-5
+    ctx = kvs.kvs_create(grid, precision=precision)
+    try:
+        kvs.kvs_set_material_uniform(ctx, 4e3, 1000.0, 0.0)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_state_curl(ctx, A, 7)
+        u, w, step = kvs.kvs_get_state(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    u_o, w_o = oracle.curl_state(grid, A, dt)
+    assert step == 7 and not u.any()
+    if precision == 0:
+        assert np.array_equal(w, w_o)
+    else:
+        assert np.array_equal(w, w_o.astype(np.float32).astype(np.float64))
+
+
+def test_curl_state_needs_dt(kvs):
+    grid = (8, 8, 8, 1e-3, 1e-3, 1e-3)
+    ctx = kvs.kvs_create(grid)
+    try:
+        kvs.kvs_set_material_uniform(ctx, 4e3, 1000.0, 0.0)
+        with pytest.raises(kvs.KvsError) as e:
+            kvs.kvs_set_state_curl(ctx, np.zeros(3 * 512))
+        assert e.value.status == kvs.KVS_ESTATE
+    finally:
+        kvs.kvs_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_run_from_curl_state_matches_oracle(kvs, precision):
+    """The Sec. 4.1 source on a 64^3 grid (sensors at 3.6 and 6.0 mm), 150 steps."""
+    w = curl_wavespeed_case(n=64, nsteps=150, offsets_mm=(3.6, 6.0))
+    say(f"case curl run 64^3 precision {precision}")
+    dt = w["dt_factor"] * oracle.stable_dt(w["grid"], w["G"], w["rho"], w["eta"])
+    u0, w0 = oracle.curl_state(w["grid"], w["A"], dt)
+    _, _, tr_o = oracle.run(w["grid"], w["G"], w["rho"], w["eta"], dt, w["nsteps"], u=u0, w=w0,
+                            probes=w["probes"], comp=2)
+    ctx = kvs.kvs_create(w["grid"], precision=precision)
+    try:
+        kvs.kvs_set_material_uniform(ctx, w["G"], w["rho"], w["eta"])
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_state_curl(ctx, w["A"])
+        kvs.kvs_set_probes(ctx, w["probes"], 2)
+        kvs.kvs_step(ctx, w["nsteps"])
+        tr = kvs.kvs_read_traces(ctx, len(w["probes"]), 1)
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert rel_l2(tr, tr_o) < (1e-12 if precision == 0 else 2e-5)
+
+
+def test_wavespeed_recovery_180(kvs):
+    """Sec. 4.1 at the paper's size: 180^3, h = 0.2 mm, cs = 2 m/s, FP32 state."""
+    w = curl_wavespeed_case()
+    say("case wavespeed recovery 180^3")
+    dt_g, offsets_g, tr_g = None, None, np.loadtxt(GOLDEN)
+    for line in open(GOLDEN):
+        if line.startswith("# dt "):
+            dt_g = float(line.split()[2])
+        elif line.startswith("# offsets_m "):
+            offsets_g = np.array([float(v) for v in line.split()[2:]])
+    ctx = kvs.kvs_create(w["grid"], precision=kvs.KVS_FP32)
+    try:
+        kvs.kvs_set_material_uniform(ctx, w["G"], w["rho"], w["eta"])
+        dt = w["dt_factor"] * kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_state_curl(ctx, w["A"])
+        kvs.kvs_set_probes(ctx, w["probes"], 2)
+        kvs.kvs_step(ctx, w["nsteps"])
+        tr = kvs.kvs_read_traces(ctx, len(w["probes"]), 1)[:, :, 0]
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert dt == pytest.approx(dt_g, rel=1e-14)
+    assert np.allclose(w["offsets"], offsets_g, rtol=1e-15)
+    assert rel_l2(tr, tr_g) < 2e-5
+    times = np.array([arrival_time(tr[:, i], dt, t0=dt) for i in range(tr.shape[1])])
+    c_fit, _ = fit_speed(w["offsets"], times)
+    times_g = np.array([arrival_time(tr_g[:, i], dt_g, t0=dt_g) for i in range(tr_g.shape[1])])
+    c_g, _ = fit_speed(offsets_g, times_g)
+    say(f"wavespeed: fit {c_fit:.4f} m/s (oracle {c_g:.4f}), per sensor {w['offsets'] / times}")
+    assert abs(c_fit - 2.0) < 0.02
+    assert abs(c_fit - c_g) < 1e-4 * c_g

@@ -417,3 +417,60 @@ def acoustic_beam_samples(grid, samples, f0=1.0e6, c=1540.0, rho=1000.0, alpha=5
     v[:, 1] = p * (scale * nyv / norm)
     v[:, 2] = p * (scale / norm)
     return cast(p), cast(v)
+
+
+def curl_wavespeed_case(n=180, h=0.2e-3, cs=2.0, rho=1000.0, sigma=1.0e-3, psi0=1.0e-6, dt_factor=0.4,
+                        nsteps=360, offsets_mm=(3.6, 6.0, 8.4, 10.8)):
+    """Non-viscous wavespeed recovery (Sec. 4.1): a cube of n^3 nodes
+    (h = 0.2 mm, 36 mm wide at n = 180), homogeneous G = rho cs^2 with
+    cs = 2 m/s, eta = 0, Dirichlet walls only; the initial velocity is the
+    curl of the vector potential A = psi y_hat, psi a Gaussian of width sigma
+    centred on the centre node (motion in the x-z plane, u_z odd in x);
+    sensors on the x (depth) axis through the centre at the given offsets,
+    recording u_z.
+
+    Returns a dict: grid, G, rho, eta, A [3][nz][ny][nx], dt_factor, nsteps,
+    probes [n][3], offsets [m].
+    """
+    grid = (n, n, n, h, h, h)
+    x = coords(n, h)
+    X, Y, Z = x[None, None, :], x[None, :, None], x[:, None, None]
+    A = np.zeros((3, n, n, n))
+    A[1] = psi0 * np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / (2 * sigma ** 2))
+    c = n // 2
+    steps = [int(round(o * 1e-3 / h)) for o in offsets_mm]
+    probes = np.array([[c + s, c, c] for s in steps], dtype=np.int64)
+    return dict(grid=grid, G=rho * cs ** 2, rho=rho, eta=0.0, A=A, dt_factor=dt_factor, nsteps=nsteps,
+                probes=probes, offsets=np.array(steps) * h)
+
+
+def qiba_phantoms(shape=(240, 200, 200), h=0.25e-3, G=(1e3, 2e3, 5e3, 10e3), rho=1000.0, amp=1e4,
+                  x_focus=30e-3, sigma=(4.3e-3, 0.62e-3, 1.1e-3), push_time=167e-6, nsteps=400, dt_factor=0.4,
+                  offsets_mm=tuple(4.0 + 0.5 * q for q in range(21))):
+    """QIBA-like elastic phantoms (Sec. 4.4): an nx x ny x nz grid (x = depth,
+    measured from the first node; y lateral and z elevational, centred),
+    h = 0.25 mm (60 x 50 x 50 mm at the default size), homogeneous media with
+    the given shear moduli, rho = 1000, eta = 0; body force along the depth
+    axis with the Gaussian profile of Eq. gaussexc,
+    amp exp(-((x - x_f)/s_x)^2 - (y/s_y)^2 - (z/s_z)^2) (1/e widths: axial
+    4.3 mm, lateral 0.62 mm, elevational 1.1 mm; focus at 30 mm depth), on for
+    167 us; sensors at the focal depth on the lateral axis at 4-14 mm from the
+    push axis, recording the axial displacement.
+
+    Returns a dict: grid, G (tuple), rho, eta, F [3][nz][ny][nx], push_time,
+    dt_factor, nsteps, probes [n][3], offsets [n] (m), comp (0 = x).
+    """
+    nx, ny, nz = shape
+    grid = (nx, ny, nz, h, h, h)
+    depth = np.arange(nx) * h
+    y = coords(ny, h)
+    z = coords(nz, h)
+    sx, sy, sz = sigma
+    F = np.zeros((3, nz, ny, nx))
+    F[0] = amp * np.exp(-((depth[None, None, :] - x_focus) / sx) ** 2 - (y[None, :, None] / sy) ** 2
+                        - (z[:, None, None] / sz) ** 2)
+    i_f = int(round(x_focus / h))
+    steps = [int(round(o * 1e-3 / h)) for o in offsets_mm]
+    probes = np.array([[i_f, ny // 2 + s, nz // 2] for s in steps], dtype=np.int64)
+    return dict(grid=grid, G=tuple(G), rho=rho, eta=0.0, F=F, push_time=push_time, dt_factor=dt_factor,
+                nsteps=nsteps, probes=probes, offsets=np.array(steps) * h, comp=0)
