@@ -1,5 +1,5 @@
-"""Acoustic radiation body force from acoustic field time series: plain FP64
-numpy oracle.
+"""Acoustic radiation body force and acoustic strain from acoustic field time
+series: plain FP64 numpy oracle.
 
 TEST INFRASTRUCTURE ONLY: imported by ``tests/`` and by the CPU-baseline leg
 of ``bench.py``; the GPU library never uses it and it never uses the GPU
@@ -21,6 +21,10 @@ alpha is the absorption in Np/m at the transmit frequency.  Regions outside
 the tissue of interest are masked to zero (Sec. 5.1).  Sec. 6.3 (Table
 tab:arf_scaling) gives the frequency scaling at fixed intensity with
 alpha = alpha0 f0 converted from dB/(cm MHz) to Np/m.
+
+Sec. 5.2 also derives, from the pressure series alone and without the pulse
+normalisation, the volumetric acoustic strain eps = -p / K (K = rho c^2) and
+its spatial gradient, reported as their peaks over time.
 
 Arrays are [nz][ny][nx] per scalar field and [3][nz][ny][nx] per vector field
 (x fastest); a time series carries the sample index in front.
@@ -107,3 +111,30 @@ def poynting_force(S_pv, alpha, c, n_pulse, mask=None):
     for i in range(3):
         F[i] = np.where(keep, coef * (S_pv[i] / float(n_pulse)), 0.0)
     return F
+
+
+def strain_peaks(grid, p_series, K):
+    """Peak volumetric acoustic strain and peak strain-gradient magnitude per
+    cell over a pressure time series (Sec. 5.2): eps = -p / K with the bulk
+    modulus K = rho c^2 (scalar or per cell), its gradient by the grid's
+    centred differences (eps(+a) - eps(-a)) / (2 h_a) on the interior nodes
+    (0 on the outer layer), |grad eps| = sqrt(gx^2 + gy^2 + gz^2); running
+    maxima over the samples in sample order, with no pulse normalisation.  A
+    NaN, once seen, stays (numpy's maximum).
+
+    p_series: [nsamp][nz][ny][nx].  Returns (peak |eps|, peak |grad eps|).
+    """
+    nx, ny, nz, hx, hy, hz = grid
+    p = np.asarray(p_series)
+    K = np.broadcast_to(np.asarray(K, dtype=np.float64), p.shape[1:])
+    pe = np.zeros(p.shape[1:])
+    pg = np.zeros(p.shape[1:])
+    for t in range(p.shape[0]):
+        eps = -(p[t].astype(np.float64)) / K
+        pe = np.maximum(pe, np.abs(eps))
+        gx = (eps[1:-1, 1:-1, 2:] - eps[1:-1, 1:-1, :-2]) / (2 * hx)
+        gy = (eps[1:-1, 2:, 1:-1] - eps[1:-1, :-2, 1:-1]) / (2 * hy)
+        gz = (eps[2:, 1:-1, 1:-1] - eps[:-2, 1:-1, 1:-1]) / (2 * hz)
+        g = np.sqrt(gx * gx + gy * gy + gz * gz)
+        pg[1:-1, 1:-1, 1:-1] = np.maximum(pg[1:-1, 1:-1, 1:-1], g)
+    return pe, pg

@@ -118,3 +118,39 @@ def test_travelling_plane_wave_forms_agree():
     assert np.allclose(Fp[2, :, 0, 0], b0, rtol=1e-12)
     assert np.allclose(Fv[2, :, 0, 0], b0, rtol=1e-12)
     assert not Fv[:2].any()
+
+
+def test_strain_peaks_of_a_sampled_plane_wave():
+    """p = P0 cos(2 pi n / M - k x) with k h = 2 pi q / M and M divisible by 4:
+    every cell's phase hits a multiple of pi/2, so the peak strain is P0 / K
+    and the peak gradient the discrete closed form (P0 / K) sin(k h) / h."""
+    M, q, P0, K = 16, 3, 2.0e5, 2.37e9
+    grid = (20, 5, 6, 2e-4, 2e-4, 2e-4)
+    h = grid[3]
+    k = 2 * np.pi * q / (M * h)
+    x = np.arange(grid[0]) * h
+    n = np.arange(2 * M)
+    p = P0 * np.cos(2 * np.pi * n[:, None] / M - k * x[None, :])
+    p = np.broadcast_to(p[:, None, None, :], (2 * M, grid[2], grid[1], grid[0]))
+    pe, pg = arf.strain_peaks(grid, p, K)
+    assert np.allclose(pe, P0 / K, rtol=1e-13)
+    assert np.allclose(pg[1:-1, 1:-1, 1:-1], P0 / K * np.sin(k * h) / h, rtol=1e-12)
+    assert not pg[0].any() and not pg[:, :, -1].any()
+
+
+def test_strain_gradient_is_of_p_over_k():
+    """Uniform pressure over a medium whose 1/K varies linearly along y: the
+    gradient is p d(1/K)/dy (exact for a linear profile), not grad(p) / K = 0;
+    and silence or repeated samples do not change the peaks (no pulse
+    normalisation)."""
+    grid = (6, 11, 7, 2e-4, 3e-4, 2e-4)
+    y = np.arange(grid[1]) * grid[4]
+    invK = 1.0 / 2.0e9 + 3.0e-8 * y
+    K = np.broadcast_to(1.0 / invK[None, :, None], (grid[2], grid[1], grid[0]))
+    P0 = 1.5e5
+    p = np.stack([np.full(K.shape, P0), np.full(K.shape, -0.5 * P0), np.zeros(K.shape)])
+    pe, pg = arf.strain_peaks(grid, p, K)
+    assert np.allclose(pe, P0 / K, rtol=1e-14)
+    assert np.allclose(pg[1:-1, 1:-1, 1:-1], P0 * 3.0e-8, rtol=1e-6)
+    pe2, pg2 = arf.strain_peaks(grid, np.concatenate([p, p[::-1], np.zeros((5,) + K.shape)]), K)
+    assert np.array_equal(pe2, pe) and np.array_equal(pg2, pg)
