@@ -294,8 +294,19 @@ def arf_workload(args):
         f0.record(lib_stream)
         kvs.kvs_arf_set_force(ctx, 5.8, 1540.0, 8 * 2, mask=None)
         f1.record(lib_stream)
+        # peak acoustic strain maps from the same pressure samples
+        kvs.kvs_strain_begin(ctx, 1000.0 * 1540.0 ** 2)
+        kvs.kvs_strain_accumulate_device(ctx, p.data_ptr(), ns, 1)  # warm-up
+        kvs.kvs_strain_begin(ctx, 1000.0 * 1540.0 ** 2)
+        sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.arf_repeats)]
+        for e0, e1 in sev:
+            e0.record(lib_stream)
+            kvs.kvs_strain_accumulate_device(ctx, p.data_ptr(), ns, 1)
+            e1.record(lib_stream)
         torch.cuda.synchronize()
         ms = [a.elapsed_time(b) for a, b in ev]
+        strain_ms = [a.elapsed_time(b) for a, b in sev]
         force_ms = f0.elapsed_time(f1)
     finally:
         kvs.kvs_destroy(ctx)
@@ -303,6 +314,8 @@ def arf_workload(args):
         torch.cuda.empty_cache()
     per = sum(ms) / len(ms)
     achieved = N * (ns * 16 + 2 * 24) / (per * 1e-3) / 1e9
+    sper = sum(strain_ms) / len(strain_ms)
+    s_achieved = N * (ns * 4 + 2 * 16) / (sper * 1e-3) / 1e9
     return {
         "workload": "512x512x640 grid, Poynting form, FP32 samples of a focused 1 MHz tone burst (8 per launch), "
                     f"{args.arf_repeats} launches, then the force pattern (uniform alpha 5.8 Np/m, c 1540 m/s)",
@@ -313,6 +326,10 @@ def arf_workload(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_cell": "8 x 16 (samples) + 48 (sums read and written) per launch"},
+        "strain": {"accumulate_ms_avg": sper, "gcell_samples_per_s": N * ns / (sper * 1e-3) / 1e9,
+                   "achieved_GBs": s_achieved, "frac_of_hbm_peak": s_achieved / HBM_PEAK_GBS,
+                   "algorithmic_bytes_per_cell": "8 x 4 (pressure samples) + 32 (two FP64 peak maps read and "
+                                                 "written) per launch; one FP64 division, 7 cached p reads per cell and sample"},
     }
 
 

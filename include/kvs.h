@@ -280,6 +280,24 @@ kvs_status kvs_arf_set_force(kvs_ctx* ctx, const double* alpha, int64_t n_alpha,
                              const double* rho, int64_t n_rho, const uint8_t* mask, double n_pulse,
                              const double* beam_dir);
 
+/* Peak acoustic strain maps (Sec. 5.2), from the pressure series alone and
+ * with no pulse normalisation: per cell the running maxima over the samples
+ * of |eps| with eps = -p / K (K = rho c^2 the bulk modulus), and of
+ * |grad eps| = sqrt(gx^2 + gy^2 + gz^2) with the centred differences
+ * g_a = (eps(+a) - eps(-a)) / (2 h_a) on the interior nodes (0 on the outer
+ * layer); FP64 arithmetic, maxima in sample order (a NaN, once seen, stays).
+ * kvs_strain_begin: K host, n_K = 1 (uniform) or N values, finite and > 0
+ * (else KVS_EINVAL); zeroes both maps and the sample count.  Device memory
+ * (K and the two maps) is owned by the context. */
+kvs_status kvs_strain_begin(kvs_ctx* ctx, const double* K, int64_t n_K);
+/* Add nsamp >= 1 pressure samples, p [nsamp][N] in device memory (dtype 0 =
+ * double, 1 = float), read on the context's stream.  Before kvs_strain_begin:
+ * KVS_ESTATE. */
+kvs_status kvs_strain_accumulate_device(kvs_ctx* ctx, const void* p, int64_t nsamp, int32_t dtype);
+/* Copy the maps (host, N doubles each; either may be NULL) and the sample
+ * count (may be NULL).  Blocks. */
+kvs_status kvs_strain_get(const kvs_ctx* ctx, double* peak_strain, double* peak_gradient, int64_t* nsamp);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* When on, every launch of the FDTD step kernel by kvs_step records its own

@@ -85,6 +85,8 @@ void release(kvs_ctx* c) {
     dfree(c->traces);
     dfree(c->peak);
     dfree(c->arf_sum);
+    dfree(c->strain_K);
+    dfree(c->strain_peak);
     if (c->cgs_host) (void)hipHostFree(c->cgs_host);
     c->cgs_host = nullptr;
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -859,6 +861,57 @@ kvs_status kvs_arf_set_force(kvs_ctx* c, const double* alpha, int64_t n_alpha, c
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("arf force: ") + hipGetErrorString(e));
     c->have_force = true;
     c->fs_current = false;
+    return KVS_OK;
+}
+
+kvs_status kvs_strain_begin(kvs_ctx* c, const double* K, int64_t n_K) {
+    if (!c) return KVS_EINVAL;
+    if (!K || (n_K != 1 && n_K != c->N)) return fail(c, KVS_EINVAL, "strain: K needs 1 or N values");
+    for (int64_t q = 0; q < n_K; ++q)
+        if (!finite_pos(K[q])) return fail(c, KVS_EINVAL, "strain: K must be finite, > 0");
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    if (!c->strain_peak) API_HIP(c, hipMalloc(&c->strain_peak, sizeof(double) * 2 * (size_t)c->N));
+    if (c->strain_K_cap < n_K) {
+        dfree(c->strain_K);
+        c->strain_K_cap = 0;
+        API_HIP(c, hipMalloc(&c->strain_K, sizeof(double) * (size_t)n_K));
+        c->strain_K_cap = n_K;
+    }
+    API_HIP(c, hipMemcpyAsync(c->strain_K, K, sizeof(double) * (size_t)n_K, hipMemcpyHostToDevice, c->stream));
+    API_HIP(c, hipMemsetAsync(c->strain_peak, 0, sizeof(double) * 2 * (size_t)c->N, c->stream));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    c->strain_sK = n_K == 1 ? 0 : 1;
+    c->strain_samples = 0;
+    c->strain_on = true;
+    return KVS_OK;
+}
+
+kvs_status kvs_strain_accumulate_device(kvs_ctx* c, const void* p, int64_t nsamp, int32_t dtype) {
+    if (!c) return KVS_EINVAL;
+    if (!c->strain_on) return fail(c, KVS_ESTATE, "strain: no kvs_strain_begin");
+    if (nsamp < 1) return fail(c, KVS_EINVAL, "strain: nsamp must be >= 1");
+    if (dtype != 0 && dtype != 1) return fail(c, KVS_EINVAL, "strain: dtype must be 0 (double) or 1 (float)");
+    if (!p) return fail(c, KVS_EINVAL, "strain: p is NULL");
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, kvs_launch_strain(c, p, nsamp, dtype));
+    c->strain_samples += nsamp;
+    return KVS_OK;
+}
+
+kvs_status kvs_strain_get(const kvs_ctx* cc, double* peak_strain, double* peak_gradient, int64_t* nsamp) {
+    kvs_ctx* c = const_cast<kvs_ctx*>(cc);
+    if (!c) return KVS_EINVAL;
+    if (!c->strain_on) return fail(c, KVS_ESTATE, "strain: no kvs_strain_begin");
+    if (nsamp) *nsamp = c->strain_samples;
+    API_HIP(c, hipSetDevice(c->device));
+    if (peak_strain)
+        API_HIP(c, hipMemcpyAsync(peak_strain, c->strain_peak, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToHost,
+                                  c->stream));
+    if (peak_gradient)
+        API_HIP(c, hipMemcpyAsync(peak_gradient, c->strain_peak + c->N, sizeof(double) * (size_t)c->N,
+                                  hipMemcpyDeviceToHost, c->stream));
+    API_HIP(c, hipStreamSynchronize(c->stream));
     return KVS_OK;
 }
 

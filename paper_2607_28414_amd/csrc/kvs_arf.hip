@@ -1,11 +1,14 @@
 // Acoustic radiation body force from a time series of the acoustic field
-// (Sec. 3.4: plane-wave form, Eq. isppa_norm; Poynting form, Eq. arf_poynting).
+// (Sec. 3.4: plane-wave form, Eq. isppa_norm; Poynting form, Eq. arf_poynting),
+// and the peak acoustic strain maps of Sec. 5.2 from the pressure series.
 //
-// Two streaming kernels:
+// Three streaming kernels:
 //   arf_acc_kernel   folds nsamp samples of p (and v) into per-cell FP64 sums,
 //                    S += p^2 (plane-wave form) or S_i += p v_i (Poynting form),
 //                    sample by sample in the order given;
-//   arf_force_kernel turns the sums into the force pattern F (FP64, [3][N]).
+//   arf_force_kernel turns the sums into the force pattern F (FP64, [3][N]);
+//   strain_kernel    folds pressure samples into the peak |eps| and peak
+//                    |grad eps| maps.
 //
 // The accumulation is HBM-bound (16 B of FP32 input per cell and sample in
 // the Poynting form, plus one read and one write of the sums per launch):
@@ -115,6 +118,52 @@ __global__ __launch_bounds__(256) void arf_force_kernel(const ForceArgs a) {
     }
 }
 
+// Peak acoustic strain eps = -p / K and peak |grad eps| (Sec. 5.2), one lane
+// per cell, the launch's samples in order.  The cell's own strain is the
+// division -p / K (so the peak-strain map is the definition's value); the six
+// neighbour strains in the gradient use the neighbours' 1/K, formed once per
+// launch, and the differences are scaled by 1/(2 h): products instead of
+// nine more FP64 divisions per cell and sample, which made the kernel bound
+// by FP64 issue (each gradient term differs from the divided form by a few
+// roundings).  The neighbours' p reads hit the caches: concurrent blocks
+// cover adjacent rows and planes.  Running maxima in registers; a NaN, once
+// seen, stays.
+template <typename T>
+__global__ __launch_bounds__(256) void strain_kernel(const T* __restrict__ p, long long N, int nsamp, int nx, int ny,
+                                                     int nz, const double* __restrict__ K, int sK, double inv_2hx,
+                                                     double inv_2hy, double inv_2hz, double* __restrict__ peak) {
+#pragma clang fp contract(off)
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const long long sxy = (long long)nx * ny;
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / sxy);
+    const bool inner = x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2 && z >= 1 && z <= nz - 2;
+    const double Kc = K[i * sK];
+    const long long off[6] = {-1, 1, -(long long)nx, nx, -sxy, sxy};
+    double rK[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) rK[q] = inner ? -1.0 / K[(i + off[q]) * sK] : 0.0;
+    double pe = peak[i], pg = peak[N + i];
+    for (int s = 0; s < nsamp; ++s) {
+        const T* ps = p + (long long)s * N;
+        const double e = -(double)ps[i] / Kc;
+        const double ae = fabs(e);
+        pe = (ae > pe || __builtin_isnan(ae)) ? ae : pe;
+        if (inner) {
+            double en[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) en[q] = (double)ps[i + off[q]] * rK[q];
+            const double gx = (en[1] - en[0]) * inv_2hx;
+            const double gy = (en[3] - en[2]) * inv_2hy;
+            const double gz = (en[5] - en[4]) * inv_2hz;
+            const double g = sqrt(gx * gx + gy * gy + gz * gz);
+            pg = (g > pg || __builtin_isnan(g)) ? g : pg;
+        }
+    }
+    peak[i] = pe;
+    peak[N + i] = pg;
+}
+
 template <typename T, int MODE, int V>
 void launch_acc(hipStream_t s, const void* p, const void* v, long long N, int nsamp, double* S) {
     const long long lanes = (N + V - 1) / V;
@@ -153,6 +202,28 @@ hipError_t kvs_launch_arf_accumulate(kvs_ctx* c, const void* p, const void* v, i
         else
             dtype == 1 ? launch_acc_mode<float, 2>(c->stream, ps, vs, N, ns, c->arf_sum)
                        : launch_acc_mode<double, 2>(c->stream, ps, vs, N, ns, c->arf_sum);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t kvs_launch_strain(kvs_ctx* c, const void* p, int64_t nsamp, int dtype) {
+    const kvs_grid& g = c->grid;
+    const long long N = (long long)c->N;
+    const size_t es = dtype == 1 ? sizeof(float) : sizeof(double);
+    const unsigned blocks = (unsigned)((N + 255) / 256);
+    for (int64_t s0 = 0; s0 < nsamp; s0 += kMaxSamplesPerLaunch) {
+        const int ns = (int)std::min<int64_t>(kMaxSamplesPerLaunch, nsamp - s0);
+        const void* ps = static_cast<const char*>(p) + (size_t)s0 * N * es;
+        if (dtype == 1)
+            hipLaunchKernelGGL(strain_kernel<float>, dim3(blocks), dim3(256), 0, c->stream, static_cast<const float*>(ps),
+                               N, ns, (int)g.nx, (int)g.ny, (int)g.nz, c->strain_K, c->strain_sK, 0.5 / g.hx,
+                               0.5 / g.hy, 0.5 / g.hz, c->strain_peak);
+        else
+            hipLaunchKernelGGL(strain_kernel<double>, dim3(blocks), dim3(256), 0, c->stream,
+                               static_cast<const double*>(ps), N, ns, (int)g.nx, (int)g.ny, (int)g.nz, c->strain_K,
+                               c->strain_sK, 0.5 / g.hx, 0.5 / g.hy, 0.5 / g.hz, c->strain_peak);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

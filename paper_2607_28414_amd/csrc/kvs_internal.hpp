@@ -123,6 +123,15 @@ struct kvs_ctx {
     double* arf_sum = nullptr;
     int64_t arf_sum_cap = 0;  // doubles allocated
     int64_t arf_samples = 0;
+
+    // acoustic strain peaks: K (1 or N doubles, stride strain_sK), peaks [2][N]
+    // (|eps|, then |grad eps|)
+    double* strain_K = nullptr;
+    int strain_sK = 0;
+    int64_t strain_K_cap = 0;
+    double* strain_peak = nullptr;
+    int64_t strain_samples = 0;
+    bool strain_on = false;
 };
 
 // Plane table handed to the peak kernel by value: axis, index along it, the
@@ -193,6 +202,9 @@ hipError_t kvs_launch_zero_boundary(kvs_ctx* c, void* field3);
 // c->arf_sum; then write F from the sums with coefficient maps of stride 0
 // (uniform) or 1 (per cell), an optional mask and the unit beam direction d
 hipError_t kvs_launch_arf_accumulate(kvs_ctx* c, const void* p, const void* v, int64_t nsamp, int dtype);
+// peak strain maps (kvs_arf.hip): fold nsamp pressure samples (dtype 0 =
+// double, 1 = float, [nsamp][N]) into c->strain_peak with c->strain_K
+hipError_t kvs_launch_strain(kvs_ctx* c, const void* p, int64_t nsamp, int dtype);
 hipError_t kvs_launch_arf_force(kvs_ctx* c, const double* alpha, int sa, const double* cs, int sc, const double* rho,
                                 int sr, const unsigned char* mask, double n_pulse, const double d[3]);
 // curl-based initial state (kvs_init.hip): u[cur] = 0, w[cur] = dt curl_h A

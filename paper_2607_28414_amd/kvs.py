@@ -133,6 +133,9 @@ SIGNATURES = {
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
     "kvs_arf_begin": ([_P, C.c_int32], C.c_int),
+    "kvs_strain_begin": ([_P, _D, C.c_int64], C.c_int),
+    "kvs_strain_accumulate_device": ([_P, C.c_void_p, C.c_int64, C.c_int32], C.c_int),
+    "kvs_strain_get": ([_P, _D, _D, _I64], C.c_int),
     "kvs_arf_accumulate_device": ([_P, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32], C.c_int),
     "kvs_arf_accumulate": ([_P, _D, _D, C.c_int64], C.c_int),
     "kvs_arf_get_sums": ([_P, _D, _I64], C.c_int),
@@ -652,3 +655,23 @@ def kvs_arf_set_force(ctx, alpha, c, n_pulse, rho=None, mask=None, beam_dir=None
     _check(lib().kvs_arf_set_force(ctx, _dptr(A), na, _dptr(Cs), nc, _dptr(R) if R is not None else None, nr,
                                    M.ctypes.data_as(C.POINTER(C.c_uint8)) if M is not None else None,
                                    float(n_pulse), _dptr(d) if d is not None else None), ctx)
+
+
+# ---- acoustic strain ----------------------------------------------------------
+
+def kvs_strain_begin(ctx, K):
+    A, n = _coef(ctx, K)
+    _check(lib().kvs_strain_begin(ctx, _dptr(A), n), ctx)
+
+
+def kvs_strain_accumulate_device(ctx, p_ptr, nsamp, dtype):
+    _check(lib().kvs_strain_accumulate_device(ctx, C.c_void_p(p_ptr), int(nsamp), int(dtype)), ctx)
+
+
+def kvs_strain_get(ctx, shape):
+    """(peak |eps|, peak |grad eps|, nsamp) as [nz][ny][nx] arrays."""
+    shape = _out_shape(ctx, shape)
+    pe, pg = np.empty(shape), np.empty(shape)
+    ns = C.c_int64()
+    _check(lib().kvs_strain_get(ctx, _dptr(pe), _dptr(pg), C.byref(ns)), ctx)
+    return pe, pg, ns.value

@@ -241,3 +241,106 @@ def test_full_size_shell_grid_sampled(kvs):
     S_o = oarf.time_sums_pv(P, V)
     assert np.abs(S_o).max() > 0
     assert np.array_equal(S[:, cells], S_o)
+
+
+def gpu_strain(kvs, grid, K, chunks, p, dtype_code):
+    import torch
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        kvs.kvs_strain_begin(ctx, K)
+        s, keep = 0, []
+        for n in chunks:
+            pt = torch.from_numpy(np.ascontiguousarray(p[s:s + n])).to("cuda")
+            keep.append(pt)
+            kvs.kvs_strain_accumulate_device(ctx, pt.data_ptr(), n, dtype_code)
+            s += n
+        return kvs.kvs_strain_get(ctx, shape_of(grid))
+    finally:
+        kvs.kvs_destroy(ctx)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+def test_strain_peaks_match_oracle(kvs, dtype):
+    """Peak |eps| bit for bit (the same division); peak |grad eps| within
+    1e-13 relative plus 1e-14 of the map's maximum (the kernel forms the
+    neighbour strains with 1/K and scales by 1/(2h): a few roundings per term,
+    amplified where neighbouring strains nearly cancel); per-cell K, samples
+    in chunks (70 spans two launches)."""
+    grid = (33, 30, 47, 2e-4, 2.5e-4, 3e-4)
+    shp = shape_of(grid)
+    say(f"case strain dtype {dtype.__name__}")
+    p, _ = acoustic_beam_samples(grid, 80, per=12, cycles=5, w0=1.2e-3, dtype=dtype)
+    rng = np.random.default_rng(17)
+    K = rng.uniform(2.0e9, 8.0e9, shp)
+    pe, pg, ns = gpu_strain(kvs, grid, K, [5, 70, 5], p, 1 if dtype == np.float32 else 0)
+    pe_o, pg_o = oarf.strain_peaks(grid, p, K)
+    assert ns == 80
+    assert np.array_equal(pe, pe_o)
+    assert np.all(np.abs(pg - pg_o) <= 1e-13 * pg_o + 1e-14 * pg_o.max())
+    assert not pg[0].any() and not pg[:, :, -1].any()
+    pe1, pg1, _ = gpu_strain(kvs, grid, 2.37e9, [80], p, 1 if dtype == np.float32 else 0)
+    pe1_o, pg1_o = oarf.strain_peaks(grid, p, 2.37e9)
+    assert np.array_equal(pe1, pe1_o)
+    assert np.all(np.abs(pg1 - pg1_o) <= 1e-13 * pg1_o + 1e-14 * pg1_o.max())
+
+
+def test_strain_errors(kvs):
+    import ctypes as C
+    grid = GRIDS[1]
+    L = kvs.lib()
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        assert L.kvs_strain_accumulate_device(ctx, C.c_void_p(1), 1, 1) == kvs.KVS_ESTATE
+        assert L.kvs_strain_get(ctx, None, None, None) == kvs.KVS_ESTATE
+        two = np.array([1e9, 1e9])
+        assert L.kvs_strain_begin(ctx, two.ctypes.data_as(C.POINTER(C.c_double)), 2) == kvs.KVS_EINVAL
+        bad = np.array([0.0])
+        assert L.kvs_strain_begin(ctx, bad.ctypes.data_as(C.POINTER(C.c_double)), 1) == kvs.KVS_EINVAL
+        kvs.kvs_strain_begin(ctx, 2e9)
+        assert L.kvs_strain_accumulate_device(ctx, C.c_void_p(1), 0, 1) == kvs.KVS_EINVAL
+        assert L.kvs_strain_accumulate_device(ctx, C.c_void_p(1), 1, 3) == kvs.KVS_EINVAL
+        assert L.kvs_strain_accumulate_device(ctx, None, 1, 1) == kvs.KVS_EINVAL
+    finally:
+        kvs.kvs_destroy(ctx)
+
+
+def test_strain_full_size_shell_grid_boxes(kvs):
+    """512 x 512 x 640, 16 FP32 samples of the focused burst in two launches,
+    K uniform; checked on 10 x 10 x 10 boxes (one touching the grid corner):
+    the oracle's maps of each box equal the GPU's on the box cells whose
+    neighbours lie in the box (all cells for peak |eps|)."""
+    import torch
+    grid = (512, 512, 640, 2e-4, 2e-4, 2e-4)
+    shp = shape_of(grid)
+    K = 1000.0 * 1540.0 ** 2
+    say("case strain full size 512x512x640")
+    rng = np.random.default_rng(5)
+    corners = [(0, 0, 0), (315, 251, 247)] + [tuple(int(v) for v in rng.integers(0, [s - 10 for s in shp]))
+                                              for _ in range(4)]
+    boxes = [[] for _ in corners]
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        kvs.kvs_strain_begin(ctx, K)
+        for s0 in (0, 8):
+            p, _ = acoustic_beam_samples(grid, 8, per=8, cycles=2, s0=s0, focus=(0.0, 0.0, 0.03), xp=torch,
+                                         device="cuda", dtype=torch.float32)
+            torch.cuda.synchronize()
+            kvs.kvs_strain_accumulate_device(ctx, p.data_ptr(), 8, 1)
+            kvs.kvs_synchronize(ctx)
+            for b, (z, y, x) in enumerate(corners):
+                boxes[b].append(p[:, z:z + 10, y:y + 10, x:x + 10].cpu().numpy())
+            del p
+        pe, pg, ns = kvs.kvs_strain_get(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+        torch.cuda.empty_cache()
+    assert ns == 16
+    h = grid[3]
+    for b, (z, y, x) in enumerate(corners):
+        pb = np.concatenate(boxes[b])
+        pe_o, pg_o = oarf.strain_peaks((10, 10, 10, h, h, h), pb, K)
+        assert np.array_equal(pe[z:z + 10, y:y + 10, x:x + 10], pe_o), b
+        g = pg[z + 1:z + 9, y + 1:y + 9, x + 1:x + 9]
+        go = pg_o[1:-1, 1:-1, 1:-1]
+        assert np.all(np.abs(g - go) <= 1e-13 * go + 1e-14 * pg_o.max()), b
+    assert pe.max() > 0 and pg.max() > 0

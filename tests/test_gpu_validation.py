@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from oracle.analysis import arrival_time, fit_speed, rel_l2
-from workloads import curl_wavespeed_case
+from workloads import curl_wavespeed_case, qiba_phantoms
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "curl_wavespeed_180.txt")
@@ -122,3 +122,74 @@ def test_wavespeed_recovery_180(kvs):
     say(f"wavespeed: fit {c_fit:.4f} m/s (oracle {c_g:.4f}), per sensor {w['offsets'] / times}")
     assert abs(c_fit - 2.0) < 0.02
     assert abs(c_fit - c_g) < 1e-4 * c_g
+
+
+QIBA_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "qiba_240x200x200.txt")
+
+
+def load_qiba():
+    """Per phantom: dict(G, dt, speed, lags, traces [steps][3 kept sensors])."""
+    phantoms, offsets, kept, cur = [], None, None, None
+    for line in open(QIBA_GOLDEN):
+        f = line.split()
+        if line.startswith("# offsets_m "):
+            offsets = np.array([float(v) for v in f[2:]])
+        elif line.startswith("# kept_sensors "):
+            kept = [int(v) for v in f[2:]]
+        elif line.startswith("# phantom "):
+            kv = dict(zip(f[2::2], f[3::2]))
+            cur = dict(G=float(kv["G"]), dt=float(kv["dt"]), speed=float(kv["speed"]), rows=[])
+            phantoms.append(cur)
+        elif line.startswith("# lags "):
+            cur["lags"] = np.array([float(v) for v in f[2:]])
+        elif not line.startswith("#") and line.strip():
+            cur["rows"].append([float(v) for v in f])
+    for p in phantoms:
+        p["traces"] = np.array(p.pop("rows"))
+    return offsets, kept, phantoms
+
+
+def test_qiba_phantoms_recover_shear_speed(kvs):
+    """Sec. 4.4: four homogeneous phantoms (G = 1, 2, 5, 10 kPa) on the
+    240 x 200 x 200 grid as one batch sharing one projection of the Gaussian
+    push (Eq. gaussexc), 400 FP32 steps; the group speed from cross-correlated
+    axial velocity traces at 4-14 mm lateral offsets is within 2 % of
+    sqrt(G / rho) and within 1e-3 of the oracle's from the same estimator; the
+    stored oracle traces match to 1e-4 relative L2 (FP32 state, projections
+    to 1e-8 on both sides)."""
+    from oracle.analysis import centred_velocity, group_speed_xcorr
+    w = qiba_phantoms()
+    offsets_g, kept, gold = load_qiba()
+    assert np.allclose(offsets_g, w["offsets"], rtol=1e-15) and len(gold) == len(w["G"])
+    say("case QIBA phantoms 240x200x200")
+    n = len(w["G"])
+    b = kvs.kvs_batch_create([w["grid"]] * n, precision=kvs.KVS_FP32, sponge_cells=8, sponge_sigma_max=-1.0)
+    dts = []
+    try:
+        for i, G in enumerate(w["G"]):
+            ctx = kvs.kvs_batch_instance(b, i)
+            kvs.kvs_set_material_uniform(ctx, G, w["rho"], w["eta"])
+            dt = w["dt_factor"] * kvs.kvs_stable_dt(ctx)
+            kvs.kvs_set_dt(ctx, dt)
+            kvs.kvs_set_envelope(ctx, np.ones(max(1, int(round(w["push_time"] / dt)))))
+            kvs.kvs_batch_set_probes(b, i, w["probes"])
+            dts.append(dt)
+        ctx0 = kvs.kvs_batch_instance(b, 0)
+        kvs.kvs_set_force(ctx0, w["F"])
+        rep = kvs.kvs_project(ctx0, tol=1e-8, max_iter=20000)
+        for i in range(1, n):
+            kvs.kvs_batch_share_projection(b, 0, i)
+        kvs.kvs_batch_set_component(b, w["comp"])
+        kvs.kvs_batch_step(b, w["nsteps"])
+        traces = [kvs.kvs_batch_read_traces(b, i, len(w["probes"])) for i in range(n)]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    assert rep["relres_true"] < 1.1e-8
+    for i, (G, g) in enumerate(zip(w["G"], gold)):
+        assert g["G"] == G and dts[i] == pytest.approx(g["dt"], rel=1e-14)
+        speed, lags = group_speed_xcorr(centred_velocity(traces[i], dts[i]), w["offsets"], dts[i])
+        cs = np.sqrt(G / w["rho"])
+        say(f"QIBA G {G:.0f} Pa: group speed {speed:.4f} m/s (cs {cs:.4f}, oracle {g['speed']:.4f})")
+        assert abs(speed - cs) < 0.02 * cs
+        assert abs(speed - g["speed"]) < 1e-3 * g["speed"]
+        assert rel_l2(traces[i][:, kept], g["traces"]) < 1e-4

@@ -36,3 +36,23 @@ def test_group_speed_from_travelling_pulses():
     even = np.stack([np.exp(-((t - t0 - r / c) / 3e-4) ** 2 / 2) / np.sqrt(r) for r in offsets], axis=1)
     times = [arrival_time(even[:, i], dt) for i in range(len(offsets))]
     assert abs(fit_speed(offsets, times)[0] - c) < 2e-3 * c
+
+
+def test_stored_qiba_speeds_are_within_two_percent():
+    """The oracle's QIBA-like phantoms (Sec. 4.4; stored by
+    tests/golden/make_qiba.py): each group speed is within 2 % of sqrt(G / rho)
+    (the paper reports about 1 % for its runs) and the lags grow with the
+    offset."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "qiba_240x200x200.txt")
+    found = 0
+    for line in open(path):
+        f = line.split()
+        if line.startswith("# phantom "):
+            kv = dict(zip(f[2::2], f[3::2]))
+            cs = np.sqrt(float(kv["G"]) / 1000.0)
+            assert abs(float(kv["speed"]) - cs) < 0.02 * cs
+            found += 1
+        elif line.startswith("# lags "):
+            assert np.all(np.diff([float(v) for v in f[2:]]) > 0)
+    assert found == 4
