@@ -193,3 +193,81 @@ def test_qiba_phantoms_recover_shear_speed(kvs):
         assert abs(speed - cs) < 0.02 * cs
         assert abs(speed - g["speed"]) < 1e-3 * g["speed"]
         assert rel_l2(traces[i][:, kept], g["traces"]) < 1e-4
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_pulsed_protocol_matches_oracle(kvs, precision):
+    """The pulsed protocol's envelope (Sec. 5.2, 50 % duty) compressed to
+    periods of 24 steps, 4 pulses + tail, on a heterogeneous viscous medium
+    with sponge: every on/off switch changes the kernel the step launches;
+    traces of all components match the oracle (FP64 1e-12, FP32 2e-5)."""
+    from workloads import gaussian_push, pulsed_envelope, spherical_inclusions
+    nx, ny, nz = 40, 36, 44
+    h = 0.25e-3
+    grid = (nx, ny, nz, h, h, h)
+    rng = np.random.default_rng(23)
+    G, rho, eta, _ = spherical_inclusions(grid, rng, 4, (2e3, 1000.0, 0.5), (0.8e-3, 2e-3), (1e3, 1e4),
+                                          (1000.0, 1100.0), (0.0, 1.5), 3)
+    F = gaussian_push(grid, 0.8e-3, 2e-3, 1e4)
+    dt = 0.4 * oracle.stable_dt(grid, G, rho, eta)
+    env = pulsed_envelope(dt, on=12 * dt, off=12 * dt, pulses=4)
+    nsteps = len(env) + 30
+    say(f"case pulsed protocol precision {precision}, {nsteps} steps")
+    smax = oracle.default_sigma_max(grid, G, rho, 4)
+    FS_o, _, _ = oracle.project(grid, F, tol=1e-11)
+    probes = np.array([[i, ny // 2, nz // 2] for i in range(0, nx, 3)])
+    _, _, tr_o = oracle.run(grid, G, rho, eta, dt, nsteps, FS=FS_o, env=env, probes=probes, comp=3,
+                            sponge_cells=4, sigma_max=smax)
+    ctx = kvs.kvs_create(grid, precision=precision, sponge_cells=4, sponge_sigma_max=smax)
+    try:
+        kvs.kvs_set_material(ctx, G, rho, eta)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_projected_force(ctx, FS_o)
+        kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_set_probes(ctx, probes, 3)
+        kvs.kvs_step(ctx, nsteps)
+        tr = kvs.kvs_read_traces(ctx, len(probes), 3)
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert env.sum() == 48 and env[11] == 1 and env[12] == 0 and env[24] == 1
+    assert rel_l2(tr, tr_o) < (1e-12 if precision == 0 else 2e-5)
+
+
+def test_pulsed_protocol_full_length(kvs):
+    """The whole protocol (1 ms on / 1 ms off, 25 pulses, 50 ms) on a 192^3
+    brain-like medium (1.5 kPa, 1040 kg/m^3, 0.8 Pa s), h = 0.2 mm, 8-cell
+    sponge, FP32: about 2.2e4 steps stay finite; the focal displacement rises
+    in every on-phase and falls in every off-phase after the first pulses, and
+    the late pulses repeat (peak of the last pulse within 5 % of the one
+    before)."""
+    from workloads import gaussian_push, pulsed_envelope
+    n, h = 192, 0.2e-3
+    grid = (n, n, n, h, h, h)
+    F = gaussian_push(grid, 1e-3, 5e-3, 5e4)
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, sponge_cells=8, sponge_sigma_max=-1.0)
+    try:
+        kvs.kvs_set_material_uniform(ctx, 1.5e3, 1040.0, 0.8)
+        dt = 0.4 * kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        env = pulsed_envelope(dt)
+        say(f"case pulsed protocol 192^3, {len(env)} steps of {dt:.3e} s")
+        kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_set_force(ctx, F)
+        kvs.kvs_project(ctx, tol=1e-8, max_iter=20000)
+        c = n // 2
+        kvs.kvs_set_probes(ctx, [[c, c, c]], 2)
+        kvs.kvs_step(ctx, len(env))
+        tr = kvs.kvs_read_traces(ctx, 1, 1)[:, 0, 0]
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert np.all(np.isfinite(tr)) and len(tr) == len(env)
+    n_per = int(round(2e-3 / dt))
+    n_on = int(round(1e-3 / dt))
+    peaks = []
+    for q in range(2, 25):
+        on = tr[q * n_per:q * n_per + n_on]
+        off = tr[q * n_per + n_on:(q + 1) * n_per]
+        assert on[-1] > on[0] and off[-1] < off[0], q
+        peaks.append(on.max())
+    assert abs(peaks[-1] - peaks[-2]) < 0.05 * peaks[-2]
+    say(f"pulsed: focal u_z peak {peaks[-1]:.3e} m")

@@ -474,3 +474,18 @@ def qiba_phantoms(shape=(240, 200, 200), h=0.25e-3, G=(1e3, 2e3, 5e3, 10e3), rho
     probes = np.array([[i_f, ny // 2 + s, nz // 2] for s in steps], dtype=np.int64)
     return dict(grid=grid, G=tuple(G), rho=rho, eta=0.0, F=F, push_time=push_time, dt_factor=dt_factor,
                 nsteps=nsteps, probes=probes, offsets=np.array(steps) * h, comp=0)
+
+
+def pulsed_envelope(dt, on=1e-3, off=1e-3, pulses=25):
+    """Pulsed forcing protocol of the TIPS demonstration (Sec. 5.2): 50 % duty
+    cycle, `on` seconds on and `off` off, `pulses` pulses (50 ms at the
+    defaults).  Step n is on when t_n = n dt falls in an on-interval, counted
+    in whole steps like the single push (g = 1 for the first round(on / dt)
+    steps of each period of round((on + off) / dt) steps).  Returns g[n] over
+    the whole protocol."""
+    n_on = int(round(on / dt))
+    n_per = int(round((on + off) / dt))
+    g = np.zeros(n_per * pulses)
+    for q in range(pulses):
+        g[q * n_per:q * n_per + n_on] = 1.0
+    return g
