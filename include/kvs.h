@@ -205,6 +205,23 @@ kvs_status kvs_clear_traces(kvs_ctx* ctx);
  * absolute step index n.  get blocks; set resets the outer layer to 0. */
 kvs_status kvs_get_state(const kvs_ctx* ctx, double* u, double* w, int64_t* step);
 kvs_status kvs_set_state(kvs_ctx* ctx, const double* u, const double* w, int64_t step);
+/* Absorbing layer in place of the sponge: a convolutional perfectly matched
+ * layer of `cells` cells next to every Dirichlet face (the absorbing
+ * boundary the paper names for its wall reflections, Sec. 3.5 and Sec. 7).
+ * Each axis is stretched, s = 1 + d / (alpha + i w), in both spatial
+ * derivatives of div(G grad u) and of (eta / dt) lap(w), with memory
+ * variables on the face fluxes and on each axis's cell divergence, updated
+ * recursively once per step (b = exp(-(d + alpha) dt),
+ * c = d / (d + alpha) (b - 1)); d = d0 q^2 over the depth q in the layer,
+ * d0 = 3 c_max ln(1/R) / (2 cells h), c_max the material's largest shear
+ * speed; alpha = alpha_max throughout the layer (alpha_max < 0: pi c_max /
+ * (10 cells h_min), the frequency of a wave ten layer widths long).  cells = 0 switches the layer off.  Needs a context without
+ * sponge and every extent >= 2 cells + 3 (else KVS_EINVAL); R in (0, 1].  The
+ * memory variables (device, state precision, in slabs of cells + 1 nodes on
+ * each side of every axis) belong to the state: kvs_set_state,
+ * kvs_set_state_curl and kvs_reset_state zero them.  Not available to
+ * batched stepping (KVS_ESTATE there). */
+kvs_status kvs_set_pml(kvs_ctx* ctx, int32_t cells, double R, double alpha_max);
 /* Curl-based initial state (Sec. 3.5; the source of the wavespeed validation,
  * Sec. 4.1): an initial velocity v0 = curl_h A, divergence-free by
  * construction, at rest displacement: u = 0 and w = dt v0, where curl_h

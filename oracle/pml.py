@@ -35,7 +35,9 @@ half integers) the depth is q = (L + 1/2 - x) / L or (x - (n - 3/2 - L)) / L
 where positive, d = d0 q^2 with d0 = 3 c_max ln(1/R) / (2 L h) (quadratic
 profile, theoretical normal-incidence reflection R, c_max the largest shear
 speed), alpha = alpha_max inside the layer and 0 elsewhere (default alpha_max =
-pi c_max / (10 h_min), a wave of ten cells per wavelength).  alpha is held
+pi c_max / (10 L h_min): the frequency of a wave ten layer widths long, which
+the layer could not absorb anyway; a larger shift moves more of the band the
+layer does absorb into the unabsorbed part).  alpha is held
 constant across the layer rather than tapered to zero at the wall: at zero
 frequency the stretched flux is alpha / (d + alpha) times the plain one, so a
 vanishing alpha at the wall would cut the interior off from the Dirichlet
@@ -85,8 +87,8 @@ def _along(a, ax, ndim=4):
     return a.reshape(s)
 
 
-def default_alpha_max(grid, cmax):
-    return math.pi * cmax / (10.0 * min(grid[3:6]))
+def default_alpha_max(grid, cmax, L):
+    return math.pi * cmax / (10.0 * L * min(grid[3:6]))
 
 
 def run_pml(grid, G, rho, eta, dt, nsteps, pml_cells, R=1e-5, alpha_max=None, FS=None, env=None, u=None, w=None,
@@ -102,7 +104,7 @@ def run_pml(grid, G, rho, eta, dt, nsteps, pml_cells, R=1e-5, alpha_max=None, FS
     crho = dt * dt / rho
     cmax = float(np.sqrt(np.max(G / rho)))
     if alpha_max is None:
-        alpha_max = default_alpha_max(grid, cmax)
+        alpha_max = default_alpha_max(grid, cmax, max(pml_cells, 1))
     u = np.zeros((3,) + shape) if u is None else np.array(u, dtype=np.float64).reshape((3,) + shape)
     w = np.zeros((3,) + shape) if w is None else np.array(w, dtype=np.float64).reshape((3,) + shape)
     FS = None if FS is None else np.asarray(FS, dtype=np.float64).reshape((3,) + shape)

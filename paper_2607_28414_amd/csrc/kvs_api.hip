@@ -42,6 +42,8 @@ double uniform_dt_max(const kvs_grid& g, double G, double rho, double eta) {
 }
 
 void resolve_sigma(kvs_ctx* c, double cmax) {
+    c->cmax = cmax;
+    c->pml_dirty = true;
     if (c->sponge_cells <= 0) {
         c->sigma_max = 0.0;
         return;
@@ -87,6 +89,8 @@ void release(kvs_ctx* c) {
     dfree(c->arf_sum);
     dfree(c->strain_K);
     dfree(c->strain_peak);
+    dfree(c->pml_tab);
+    dfree(c->pml_mem);
     if (c->cgs_host) (void)hipHostFree(c->cgs_host);
     c->cgs_host = nullptr;
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -376,6 +380,7 @@ kvs_status kvs_set_dt(kvs_ctx* c, double dt) {
                                           std::to_string(c->dt_max));
     c->dt = dt;
     c->have_dt = true;
+    c->pml_dirty = true;
     API_HIP(c, kvs_launch_crho(c));
     return KVS_OK;
 }
@@ -548,6 +553,10 @@ kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
     s = ensure_trace_capacity(c, nsteps);
     if (s != KVS_OK) return s;
     API_HIP(c, hipSetDevice(c->device));
+    if (c->pml_cells > 0 && c->pml_dirty) {
+        API_HIP(c, kvs_pml_build(c));
+        c->pml_dirty = false;
+    }
     for (int64_t q = 0; q < nsteps; ++q) {
         const int64_t n = c->step;
         const double gn = n < n_env ? c->env[(size_t)n] : 0.0;
@@ -561,6 +570,7 @@ kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
         const hipError_t le = kvs_launch_step(c, gn);
         c->launch_ev[0] = c->launch_ev[1] = nullptr;
         API_HIP(c, le);
+        if (c->pml_cells > 0) API_HIP(c, kvs_launch_pml(c, gn));
         c->cur = 1 - c->cur;
         if (c->nprobes > 0) {
             API_HIP(c, kvs_launch_probe_gather(c, c->u[c->cur], c->trace_steps));
@@ -624,6 +634,47 @@ kvs_status kvs_get_state(const kvs_ctx* cc, double* u, double* w, int64_t* step)
     return KVS_OK;
 }
 
+// The layer's memory variables belong to the state: zero them whenever the
+// state is replaced.
+kvs_status clear_pml_memory(kvs_ctx* c) {
+    if (c->pml_mem && c->pml_mem_count > 0) {
+        API_HIP(c, hipMemsetAsync(c->pml_mem, 0, (size_t)c->pml_mem_count * tsize(c), c->stream));
+        API_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return KVS_OK;
+}
+
+kvs_status kvs_set_pml(kvs_ctx* c, int32_t cells, double R, double alpha_max) {
+    if (!c) return KVS_EINVAL;
+    if (cells < 0) return fail(c, KVS_EINVAL, "pml: cells must be >= 0");
+    if (cells > 0) {
+        const kvs_grid& g = c->grid;
+        if (std::min(g.nx, std::min(g.ny, g.nz)) < 2 * (int64_t)cells + 3)
+            return fail(c, KVS_EINVAL, "pml: every extent must be at least 2 cells + 3");
+        if (!(std::isfinite(R) && R > 0.0 && R <= 1.0)) return fail(c, KVS_EINVAL, "pml: R must be in (0, 1]");
+        if (!std::isfinite(alpha_max)) return fail(c, KVS_EINVAL, "pml: alpha_max must be finite");
+        if (c->sponge_cells > 0) return fail(c, KVS_EINVAL, "pml: the context has a sponge; use one or the other");
+    }
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, hipStreamSynchronize(c->stream));
+    dfree(c->pml_tab);
+    dfree(c->pml_mem);
+    c->pml_mem_count = 0;
+    c->pml_cells = 0;
+    if (cells == 0) return KVS_OK;
+    const kvs_grid& g = c->grid;
+    int64_t count = 0;
+    for (int a = 0; a < 3; ++a) count += 9 * kvs_pml_slab_cells(g, cells, a);
+    API_HIP(c, hipMalloc(&c->pml_tab, tsize(c) * 4 * (size_t)(g.nx + g.ny + g.nz)));
+    API_HIP(c, hipMalloc(&c->pml_mem, tsize(c) * (size_t)count));
+    c->pml_mem_count = count;
+    c->pml_cells = cells;
+    c->pml_R = R;
+    c->pml_alpha = alpha_max;
+    c->pml_dirty = true;
+    return clear_pml_memory(c);
+}
+
 kvs_status kvs_set_state(kvs_ctx* c, const double* u, const double* w, int64_t step) {
     if (!c) return KVS_EINVAL;
     if (!u || !w || step < 0) return fail(c, KVS_EINVAL, "bad state");
@@ -642,7 +693,7 @@ kvs_status kvs_set_state(kvs_ctx* c, const double* u, const double* w, int64_t s
     (void)hipFree(tmp);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("set_state: ") + hipGetErrorString(e));
     c->step = step;
-    return KVS_OK;
+    return clear_pml_memory(c);
 }
 
 kvs_status kvs_set_state_curl(kvs_ctx* c, const double* A, int64_t step) {
@@ -659,7 +710,7 @@ kvs_status kvs_set_state_curl(kvs_ctx* c, const double* A, int64_t step) {
     (void)hipFree(tmp);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("curl state: ") + hipGetErrorString(e));
     c->step = step;
-    return KVS_OK;
+    return clear_pml_memory(c);
 }
 
 kvs_status kvs_reset_state(kvs_ctx* c) {
@@ -672,7 +723,7 @@ kvs_status kvs_reset_state(kvs_ctx* c) {
     c->step = 0;
     c->trace_steps = 0;
     if (c->peak) API_HIP(c, hipMemsetAsync(c->peak, 0, (size_t)c->peak_cells * tsize(c), c->stream));
-    return KVS_OK;
+    return clear_pml_memory(c);
 }
 
 kvs_status kvs_set_peak_planes(kvs_ctx* c, const int32_t* axis, const int64_t* index, int32_t n) {
@@ -1188,6 +1239,7 @@ kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
         kvs_ctx* c = b->inst[i];
         const std::string who = "instance " + std::to_string(i) + ": ";
         if (!c->have_material || c->hetero) return bfail(b, KVS_ESTATE, who + "needs a uniform material");
+        if (c->pml_cells > 0) return bfail(b, KVS_ESTATE, who + "absorbing layers are not batched");
         if (!c->have_dt) return bfail(b, KVS_ESTATE, who + "no time step set");
         if (c->step != b->step) return bfail(b, KVS_ESTATE, who + "stepped outside the batch");
         const int64_t n_env = (int64_t)c->env.size();

@@ -132,6 +132,18 @@ struct kvs_ctx {
     double* strain_peak = nullptr;
     int64_t strain_samples = 0;
     bool strain_on = false;
+
+    // absorbing layer (C-PML): cells per face (0 = off), theoretical
+    // reflection, frequency shift (< 0: default); coefficient tables [axis][4][n]
+    // (rebuilt when dt, material or layer change) and the memory variables of
+    // the three axes' slabs [axis][9][slab cells], in the state precision
+    int pml_cells = 0;
+    double pml_R = 1e-5, pml_alpha = -1.0;
+    double cmax = 0.0;  // largest shear speed of the material
+    bool pml_dirty = true;
+    void* pml_tab = nullptr;
+    void* pml_mem = nullptr;
+    int64_t pml_mem_count = 0;
 };
 
 // Plane table handed to the peak kernel by value: axis, index along it, the
@@ -205,6 +217,13 @@ hipError_t kvs_launch_arf_accumulate(kvs_ctx* c, const void* p, const void* v, i
 // peak strain maps (kvs_arf.hip): fold nsamp pressure samples (dtype 0 =
 // double, 1 = float, [nsamp][N]) into c->strain_peak with c->strain_K
 hipError_t kvs_launch_strain(kvs_ctx* c, const void* p, int64_t nsamp, int dtype);
+// absorbing layer (kvs_pml.hip): default frequency shift, slab cells of an
+// axis, coefficient tables from dt and the material, and the layer passes of
+// one step (after kvs_launch_step, before the buffers flip)
+double kvs_pml_default_alpha(const kvs_grid& g, double cmax, int L);
+int64_t kvs_pml_slab_cells(const kvs_grid& g, int L, int axis);
+hipError_t kvs_pml_build(kvs_ctx* c);
+hipError_t kvs_launch_pml(kvs_ctx* c, double gn);
 hipError_t kvs_launch_arf_force(kvs_ctx* c, const double* alpha, int sa, const double* cs, int sc, const double* rho,
                                 int sr, const unsigned char* mask, double n_pulse, const double d[3]);
 // curl-based initial state (kvs_init.hip): u[cur] = 0, w[cur] = dt curl_h A

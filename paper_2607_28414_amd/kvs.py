@@ -88,6 +88,7 @@ SIGNATURES = {
     "kvs_set_state": ([_P, _D, _D, C.c_int64], C.c_int),
     "kvs_reset_state": ([_P], C.c_int),
     "kvs_set_state_curl": ([_P, _D, C.c_int64], C.c_int),
+    "kvs_set_pml": ([_P, C.c_int32, C.c_double, C.c_double], C.c_int),
     "kvs_set_peak_planes": ([_P, C.POINTER(C.c_int32), _I64, C.c_int32], C.c_int),
     "kvs_peak_map": ([_P, C.c_int32, C.c_int64, _D], C.c_int),
     "kvs_enable_kernel_timing": ([_P, C.c_int32], C.c_int),
@@ -342,6 +343,10 @@ def kvs_get_state(ctx, shape):
 def kvs_set_state(ctx, u, w, step):
     u, w = _host(ctx, u, 3), _host(ctx, w, 3)
     _check(lib().kvs_set_state(ctx, _dptr(u), _dptr(w), int(step)), ctx)
+
+
+def kvs_set_pml(ctx, cells, R=1e-5, alpha_max=-1.0):
+    _check(lib().kvs_set_pml(ctx, int(cells), float(R), float(alpha_max)), ctx)
 
 
 def kvs_set_state_curl(ctx, A, step=0):
