@@ -65,9 +65,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["inclusions", "batch", "fpcg", "arf"], default="inclusions",
+    ap.add_argument("--workload", choices=["inclusions", "batch", "fpcg", "arf", "pml"], default="inclusions",
                     help="fpcg: profiling aid, flexible-PCG iterations on the 384 x 384 x 512 grid; "
-                         "arf: the ARF accumulation leg alone")
+                         "arf: the ARF accumulation leg alone; pml: cost of the absorbing layer")
     ap.add_argument("--grid", type=int, default=256, help="cubic grid edge of the inclusion workload")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--cpu-sample-steps", type=int, default=100)
@@ -333,6 +333,50 @@ def arf_workload(args):
     }
 
 
+def run_pml_bench(args):
+    """Cost of the absorbing layer: the 256^3 inclusion medium, push projected
+    by Jacobi-PCG, 500 steps without sponge, once with the Dirichlet walls
+    alone and once with a 10-cell C-PML; HIP events on the context's stream
+    around the steps (step kernel, probe gather, and the layer's passes)."""
+    import torch
+
+    from paper_2607_28414_amd import kvs
+    from workloads import cfg2_inclusions_fp32
+
+    w = cfg2_inclusions_fp32(n=256)
+    out = {}
+    for L in (0, 10):
+        ctx = kvs.kvs_create(w.grid, precision=kvs.KVS_FP32)
+        try:
+            kvs.kvs_set_material(ctx, w.G, w.rho, w.eta)
+            dt = w.dt_factor * kvs.kvs_stable_dt(ctx)
+            kvs.kvs_set_dt(ctx, dt)
+            kvs.kvs_set_envelope(ctx, w.envelope_for(dt))
+            kvs.kvs_set_probes(ctx, w.probes, w.comp)
+            if L:
+                kvs.kvs_set_pml(ctx, L)
+            kvs.kvs_set_force(ctx, w.F)
+            kvs.kvs_project(ctx, tol=w.tol, max_iter=20000)
+            variant, _ = kvs.kvs_autotune_step(ctx, 10)
+            kvs.kvs_step(ctx, 20)
+            kvs.kvs_reset_state(ctx)
+            stream = torch.cuda.ExternalStream(kvs.kvs_stream(ctx))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            kvs.kvs_step(ctx, 500)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out[L] = e0.elapsed_time(e1) / 500
+        finally:
+            kvs.kvs_destroy(ctx)
+    n = 256
+    band = (n - 2) ** 3 - (n - 2 - 20) ** 3
+    return {"workload": "256^3 inclusions, 500 steps, no sponge: Dirichlet walls vs a 10-cell C-PML",
+            "ms_per_step_walls": out[0], "ms_per_step_pml": out[10],
+            "pml_overhead_ms": out[10] - out[0], "layer_cells": band,
+            "layer_fraction": band / (n - 2) ** 3}
+
+
 def shell_workload(args, net):
     """The transcranial-like workload in full (512 x 512 x 640, curved stiff
     shell, 6000-step run window of `shell_steps` steps): one projection of
@@ -571,6 +615,9 @@ def main():
         return
     if args.workload == "arf":
         print(json.dumps(arf_workload(args)), flush=True)
+        return
+    if args.workload == "pml":
+        print(json.dumps(run_pml_bench(args)), flush=True)
         return
     import numpy as np
     import torch

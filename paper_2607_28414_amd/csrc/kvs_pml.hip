@@ -20,12 +20,12 @@
 // drift by a uniform static displacement).
 //
 // The layer is L cells next to every Dirichlet face.  The main step kernel
-// updates every cell with the plain scheme; these kernels then redo the layer
-// cells: pass 1 advances the face memories (psi) of each axis over that
-// axis's two slabs, pass 2 recomputes the layer cells with the stretched
-// derivatives (advancing phi) and overwrites their new state.  Both read only
-// the old state (u, w), so the order after the main kernel is all that is
-// needed.  Memory variables live only in the slabs: along axis a, indices
+// updates every cell with the plain scheme; these kernels then correct the
+// layer cells: pass 1 advances the face memories (psi) of each axis over that
+// axis's two slabs, pass 2 adds to the layer cells' new state the difference
+// the stretched derivatives make (advancing phi).  Both read the old state
+// (u, w); pass 2 also reads and rewrites the new state of the layer cells, so
+// both run after the main kernel, in stream order.  Memory variables live only in the slabs: along axis a, indices
 // [0, T) and [n_a - 1 - T, n_a - 1) with T = L + 1, which hold the faces
 // i + 1/2 and the cells i that the layer uses.
 #include <algorithm>
@@ -59,8 +59,7 @@ struct PmlArgs {
     const T* G;     // [N] or null (uniform G0)
     const T* eta;   // [N] or null (uniform eta_dt0)
     const T* crho;  // [N] or null (uniform crho0)
-    const T* FS;    // [3][N] when gn != 0
-    T G0, eta_dt0, crho0, inv_dt, gn;
+    T G0, eta_dt0, crho0, inv_dt;
     long long N;
     int nx, ny, nz, L, Ts;
     PmlAxis<T> ax[3];
@@ -84,13 +83,24 @@ __global__ __launch_bounds__(256) void pml_face_kernel(const PmlArgs<T> a) {
     const PmlAxis<T>& X = a.ax[A];
     const int Ts = a.Ts;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    // thread order: slab position fastest, then the other two interior coordinates
+    // thread order follows memory: for x faces the slab position (x) fastest,
+    // then y, z; for y and z faces x fastest, then the slab position, then the
+    // remaining axis (rows of the state and of the slab memory stay contiguous)
     const int e1 = A == 0 ? a.ny - 2 : a.nx - 2;  // first other axis (interior extent)
     const long long total = (long long)(2 * Ts) * e1 * (A == 2 ? a.ny - 2 : a.nz - 2);
     if (t >= total) return;
-    const int s = (int)(t % (2 * Ts));
-    const long long r = t / (2 * Ts);
-    const int o1 = 1 + (int)(r % e1), o2 = 1 + (int)(r / e1);
+    int s, o1, o2;
+    if (A == 0) {
+        s = (int)(t % (2 * Ts));
+        const long long r = t / (2 * Ts);
+        o1 = 1 + (int)(r % e1);
+        o2 = 1 + (int)(r / e1);
+    } else {
+        o1 = 1 + (int)(t % e1);
+        const long long r = t / e1;
+        s = (int)(r % (2 * Ts));
+        o2 = 1 + (int)(r / (2 * Ts));
+    }
     const int ia = s < Ts ? s : (X.n - 1 - Ts) + (s - Ts);  // face ia + 1/2
     const T cf = X.tab[3 * X.n + ia];
     if (cf == T(0)) return;
@@ -115,7 +125,13 @@ __global__ __launch_bounds__(256) void pml_face_kernel(const PmlArgs<T> a) {
     }
 }
 
-// Pass 2: the layer cells, enumerated box by box (each cell once).
+// Pass 2: the layer cells, enumerated box by box (each cell once).  With no
+// sponge the plain update is linear in acc (w' = w + (dt^2/rho) acc), so the
+// cell only adds the layer's part to what the step kernel wrote:
+// acc_layer - acc_plain = sum over the axes whose layer holds the cell of
+// (psi differences) / h + phi, where phi advances with that axis's full
+// stretched divergence.  Axes whose layer does not hold the cell are left to
+// the step kernel (there psi = phi = 0).
 template <typename T>
 __global__ __launch_bounds__(256) void pml_cell_kernel(const PmlArgs<T> a) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,53 +150,41 @@ __global__ __launch_bounds__(256) void pml_cell_kernel(const PmlArgs<T> a) {
     const T Gc = a.G ? a.G[cell] : a.G0;
     const T eta_dt = a.eta ? a.eta[cell] * a.inv_dt : a.eta_dt0;
     const T cr = a.crho ? a.crho[cell] : a.crho0;
-    T acc[3] = {T(0), T(0), T(0)};
+    T dacc[3] = {T(0), T(0), T(0)};
 #pragma unroll
     for (int A = 0; A < 3; ++A) {
         const PmlAxis<T>& X = a.ax[A];
+        const int ia = pos[A];
+        if (!(ia <= a.L || ia >= X.n - 1 - a.L)) continue;
         const long long st = strides[A];
         const T Gm = a.G ? harm2<T>(Gc, a.G[cell - st]) : a.G0;
         const T Gp = a.G ? harm2<T>(Gc, a.G[cell + st]) : a.G0;
-        const int ia = pos[A];
-        const bool layer = ia <= a.L || ia >= X.n - 1 - a.L;
-        long long mp = 0, mm = 0;
-        if (layer) {
-            mp = slab_index(A, slab_of(ia, X.n, a.Ts), i, j, k, a.nx, a.ny, a.Ts);      // face ia + 1/2, cell ia
-            mm = slab_index(A, slab_of(ia - 1, X.n, a.Ts), i, j, k, a.nx, a.ny, a.Ts);  // face ia - 1/2
-        }
+        const long long mp = slab_index(A, slab_of(ia, X.n, a.Ts), i, j, k, a.nx, a.ny, a.Ts);      // face ia + 1/2, cell ia
+        const long long mm = slab_index(A, slab_of(ia - 1, X.n, a.Ts), i, j, k, a.nx, a.ny, a.Ts);  // face ia - 1/2
         const T bc = X.tab[ia], cc = X.tab[X.n + ia];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const long long o = c * a.N;
             const T uc = a.u[o + cell], wc = a.w[o + cell];
-            T fp = Gp * ((a.u[o + cell + st] - uc) * X.ih);
-            T fm = Gm * ((uc - a.u[o + cell - st]) * X.ih);
-            T gp = (a.w[o + cell + st] - wc) * X.ih;
-            T gm = (wc - a.w[o + cell - st]) * X.ih;
-            if (layer) {
-                fp += X.mem[c * X.M + mp];
-                fm += X.mem[c * X.M + mm];
-                gp += X.mem[(3 + c) * X.M + mp];
-                gm += X.mem[(3 + c) * X.M + mm];
-            }
-            T D = (fp - fm) * X.ih + eta_dt * ((gp - gm) * X.ih);
-            if (layer) {
-                T* ph = X.mem + (6 + c) * X.M + mp;
-                const T phi = bc * *ph + cc * D;
-                *ph = phi;
-                D += phi;
-            }
-            acc[c] += D;
+            const T pe_p = X.mem[c * X.M + mp], pe_m = X.mem[c * X.M + mm];
+            const T pw_p = X.mem[(3 + c) * X.M + mp], pw_m = X.mem[(3 + c) * X.M + mm];
+            const T fp = Gp * ((a.u[o + cell + st] - uc) * X.ih) + pe_p;
+            const T fm = Gm * ((uc - a.u[o + cell - st]) * X.ih) + pe_m;
+            const T gp = (a.w[o + cell + st] - wc) * X.ih + pw_p;
+            const T gm = (wc - a.w[o + cell - st]) * X.ih + pw_m;
+            const T D = (fp - fm) * X.ih + eta_dt * ((gp - gm) * X.ih);
+            T* ph = X.mem + (6 + c) * X.M + mp;
+            const T phi = bc * *ph + cc * D;
+            *ph = phi;
+            dacc[c] += ((pe_p - pe_m) + eta_dt * (pw_p - pw_m)) * X.ih + phi;
         }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const long long o = c * a.N;
-        T f = acc[c];
-        if (a.gn != T(0)) f += a.gn * a.FS[o + cell];
-        const T wn = a.w[o + cell] + cr * f;
-        a.wn[o + cell] = wn;
-        a.un[o + cell] = a.u[o + cell] + wn;
+        const T d = cr * dacc[c];
+        a.wn[o + cell] += d;
+        a.un[o + cell] += d;
     }
 }
 
@@ -223,7 +227,7 @@ hipError_t build_t(kvs_ctx* c) {
 }
 
 template <typename T>
-hipError_t launch_t(kvs_ctx* c, double gn) {
+hipError_t launch_t(kvs_ctx* c) {
     const kvs_grid& g = c->grid;
     PmlArgs<T> a{};
     const int nb = 1 - c->cur;
@@ -234,12 +238,10 @@ hipError_t launch_t(kvs_ctx* c, double gn) {
     a.G = c->hetero ? static_cast<const T*>(c->G) : nullptr;
     a.eta = c->hetero && c->viscous ? static_cast<const T*>(c->eta) : nullptr;
     a.crho = c->hetero ? static_cast<const T*>(c->crho) : nullptr;
-    a.FS = static_cast<const T*>(c->FS);
     a.G0 = T(c->G0);
     a.eta_dt0 = c->hetero ? T(0) : T(c->eta0 / c->dt);
     a.crho0 = T(c->dt * c->dt / c->rho0);
     a.inv_dt = T(1.0 / c->dt);
-    a.gn = T(gn);
     a.N = (long long)c->N;
     a.nx = (int)g.nx;
     a.ny = (int)g.ny;
@@ -301,5 +303,6 @@ int64_t kvs_pml_slab_cells(const kvs_grid& g, int L, int axis) {
 hipError_t kvs_pml_build(kvs_ctx* c) { return c->prec == KVS_FP32 ? build_t<float>(c) : build_t<double>(c); }
 
 hipError_t kvs_launch_pml(kvs_ctx* c, double gn) {
-    return c->prec == KVS_FP32 ? launch_t<float>(c, gn) : launch_t<double>(c, gn);
+    (void)gn;  // the force term is the step kernel's; the layer changes the stencil terms only
+    return c->prec == KVS_FP32 ? launch_t<float>(c) : launch_t<double>(c);
 }
