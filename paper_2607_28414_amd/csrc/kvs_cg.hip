@@ -143,12 +143,24 @@ __global__ __launch_bounds__(64 * CBY) void cg_init_kernel(const CgGeom g, const
     block_partials<3>(s1, s2, s3, partials, npart);
 }
 
-// Geometry of the two CG sweeps: 64 x SBY tiles, z segments of `kchunk`.
-constexpr int SBY = 8;
-
+// Geometry of the two CG sweeps: TX x BY tiles (TX = 64 WX: WX wavefronts
+// side by side on a row), z segments of `kchunk`.  Wide rows spread the two
+// x-halo columns over more cells: the widest of 256 x 4, 128 x 8 and 64 x 8
+// whose padding of the row stays within 1/8 of it.
 struct SweepGeom {
     int gx, gy, gz, kchunk;
 };
+
+struct SweepShape {
+    int wx, by;
+};
+
+inline SweepShape sweep_shape(int nx) {
+    auto waste_ok = [nx](int tx) { return 8 * (((nx + tx - 1) / tx) * tx - nx) <= nx; };
+    if (waste_ok(256)) return {4, 4};
+    if (waste_ok(128)) return {2, 8};
+    return {1, 8};
+}
 
 // Per-lane tile coordinates and halo slot of a z-marching sweep (same
 // scheme as the FDTD step: wave 0 loads the row below the tile, wave SBY-1
@@ -159,13 +171,15 @@ struct Lane {
     bool act;
 };
 
+template <int WX, int SBY>
 __device__ __forceinline__ Lane sweep_lane(const CgGeom& g, const SweepGeom& s) {
+    constexpr int TX = 64 * WX;
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int B = s.gx * s.gy * s.gz;
     const int t = tile_of(blockIdx.x, B);
     const int bx = t % s.gx, by = (t / s.gx) % s.gy, bz = t / (s.gx * s.gy);
     Lane L;
-    L.i = bx * 64 + tx;
+    L.i = bx * TX + tx;
     L.j = by * SBY + ty;
     L.kb = 1 + bz * s.kchunk;
     L.ke = min(g.nz - 1, L.kb + s.kchunk);
@@ -192,12 +206,12 @@ __device__ __forceinline__ Lane sweep_lane(const CgGeom& g, const SweepGeom& s) 
     } else if (ty == 1 && tx < 2 * SBY) {
         const int row = tx % SBY;
         const bool right = tx >= SBY;
-        const int ii = bx * 64 + (right ? 64 : -1);
+        const int ii = bx * TX + (right ? TX : -1);
         const int jj = by * SBY + row;
         if (ii >= 0 && ii < g.nx && jj < g.ny) {
             L.h_off = ii + g.nx * jj;
             L.h_row = row + 1;
-            L.h_col = right ? 65 : 0;
+            L.h_col = right ? TX + 1 : 0;
             real = true;
         }
     }
@@ -205,21 +219,23 @@ __device__ __forceinline__ Lane sweep_lane(const CgGeom& g, const SweepGeom& s) 
     return L;
 }
 
-// Sum over the block (SBY waves) of up to two values; lane (0,0) writes them
-// to partials[block] and partials[npart + block].
-template <int NS>
+// Sum over the block (WX SBY waves) of up to two values; lane (0,0) writes
+// them to partials[block] and partials[npart + block], in wave order.
+template <int NS, int WX, int SBY>
 __device__ __forceinline__ void sweep_partials(double v0, double v1, double* partials, int npart) {
-    __shared__ double sh[2][SBY];
+    constexpr int NW = WX * SBY;
+    __shared__ double sh[2][NW];
     v0 = wave_sum(v0);
     if (NS > 1) v1 = wave_sum(v1);
-    if (threadIdx.x == 0) {
-        sh[0][threadIdx.y] = v0;
-        if (NS > 1) sh[1][threadIdx.y] = v1;
+    const int wv = threadIdx.y * WX + threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][wv] = v0;
+        if (NS > 1) sh[1][wv] = v1;
     }
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         double a = 0, b = 0;
-        for (int w = 0; w < SBY; ++w) {
+        for (int w = 0; w < NW; ++w) {
             a += sh[0][w];
             if (NS > 1) b += sh[1][w];
         }
@@ -231,12 +247,13 @@ __device__ __forceinline__ void sweep_partials(double v0, double v1, double* par
 // sweep 1: p' = z + beta p, A p' = -lap p', partial p'.Ap'.  z = zs * src
 // with src = r (CG: zs = 1, Jacobi: zs = 1/diag) or, in flexible PCG, the
 // network output zf (zs = 1) unless this iteration fell back to Jacobi.
-__global__ __launch_bounds__(64 * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const double* r_in,
-                                                          const double* zf, const double* p_old, double* p_new,
-                                                          const CgState* st, double* partials, int npart) {
+template <int WX, int SBY>
+__global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const double* r_in,
+                                                               const double* zf, const double* p_old, double* p_new,
+                                                               const CgState* st, double* partials, int npart) {
     if (st->done) return;
-    __shared__ double lds[2][SBY + 3][68];
-    const Lane L = sweep_lane(g, sg);
+    __shared__ double lds[2][SBY + 3][64 * WX + 4];
+    const Lane L = sweep_lane<WX, SBY>(g, sg);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int sxy = g.nx * g.ny;
     const double beta = st->beta;
@@ -270,17 +287,18 @@ __global__ __launch_bounds__(64 * SBY) void cg_dir_kernel(const CgGeom g, const 
         pp = pv(rn, on);
         hc = pv(hrn, hon);
     }
-    sweep_partials<1>(s1, 0.0, partials, npart);
+    sweep_partials<1, WX, SBY>(s1, 0.0, partials, npart);
 }
 
 // sweep 2: A p recomputed, phi += alpha p, r_out = r - alpha A p (r_out may
 // be r itself), partials r.r, r.z
-__global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const SweepGeom sg, double* phi,
-                                                          const double* r, double* r_out, const double* p,
-                                                          const CgState* st, double* partials, int npart) {
+template <int WX, int SBY>
+__global__ __launch_bounds__(64 * WX * SBY) void cg_upd_kernel(const CgGeom g, const SweepGeom sg, double* phi,
+                                                               const double* r, double* r_out, const double* p,
+                                                               const CgState* st, double* partials, int npart) {
     if (st->done) return;
-    __shared__ double lds[2][SBY + 3][68];
-    const Lane L = sweep_lane(g, sg);
+    __shared__ double lds[2][SBY + 3][64 * WX + 4];
+    const Lane L = sweep_lane<WX, SBY>(g, sg);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int sxy = g.nx * g.ny;
     const double alpha = st->alpha;
@@ -318,7 +336,7 @@ __global__ __launch_bounds__(64 * SBY) void cg_upd_kernel(const CgGeom g, const 
         phc = phn;
         rc = rn;
     }
-    sweep_partials<2>(s1, s2, partials, npart);
+    sweep_partials<2, WX, SBY>(s1, s2, partials, npart);
 }
 
 
@@ -511,7 +529,8 @@ kvs_status fail(kvs_ctx* c, kvs_status s, const std::string& msg) {
 
 int64_t kvs_cg_partials_needed(const kvs_grid& gr) {
     CgGeom g = make_geom(gr);
-    const int sweep_xy = ((g.nx + 63) / 64) * ((g.ny + SBY - 1) / SBY);
+    const SweepShape sh = sweep_shape(g.nx);
+    const int sweep_xy = ((g.nx + 64 * sh.wx - 1) / (64 * sh.wx)) * ((g.ny + sh.by - 1) / sh.by);
     return std::max<int64_t>(std::max<int64_t>(nblocks(g), kvs_tiling::max_tiled_blocks(sweep_xy, g.nz - 2)),
                              kvs_unet_out_blocks(gr));
 }
@@ -553,16 +572,42 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3, (int)FIN_INIT, c->cgs);
     CG_HIP(hipGetLastError());
 
+    const SweepShape shp = sweep_shape(g.nx);
     SweepGeom sg{};
-    sg.gx = (g.nx + 63) / 64;
-    sg.gy = (g.ny + SBY - 1) / SBY;
+    sg.gx = (g.nx + 64 * shp.wx - 1) / (64 * shp.wx);
+    sg.gy = (g.ny + shp.by - 1) / shp.by;
     {
-        static const int cap = kvs_tiling::resident_blocks(cg_dir_kernel, 64 * SBY);
+        static const int cap1 = kvs_tiling::resident_blocks(cg_dir_kernel<1, 8>, 512);
+        static const int cap2 = kvs_tiling::resident_blocks(cg_dir_kernel<2, 8>, 1024);
+        static const int cap4 = kvs_tiling::resident_blocks(cg_dir_kernel<4, 4>, 1024);
+        const int cap = shp.wx == 4 ? cap4 : (shp.wx == 2 ? cap2 : cap1);
         sg.kchunk = kvs_tiling::choose_kchunk(sg.gx * sg.gy, g.nz - 2, cap);
         sg.gz = (g.nz - 2 + sg.kchunk - 1) / sg.kchunk;
     }
     const int nbs = sg.gx * sg.gy * sg.gz;
-    const dim3 sblk(64, SBY);
+    const dim3 sblk(64 * shp.wx, shp.by);
+    auto launch_dir = [&](const double* r_in, const double* zf, const double* p_old, double* p_new) {
+        if (shp.wx == 4)
+            hipLaunchKernelGGL((cg_dir_kernel<4, 4>), dim3(nbs), sblk, 0, c->stream, g, sg, r_in, zf, p_old, p_new,
+                               c->cgs, part, npart);
+        else if (shp.wx == 2)
+            hipLaunchKernelGGL((cg_dir_kernel<2, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, r_in, zf, p_old, p_new,
+                               c->cgs, part, npart);
+        else
+            hipLaunchKernelGGL((cg_dir_kernel<1, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, r_in, zf, p_old, p_new,
+                               c->cgs, part, npart);
+    };
+    auto launch_upd = [&](const double* r_in, double* r_out, const double* pv) {
+        if (shp.wx == 4)
+            hipLaunchKernelGGL((cg_upd_kernel<4, 4>), dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, r_in, r_out, pv,
+                               c->cgs, part, npart);
+        else if (shp.wx == 2)
+            hipLaunchKernelGGL((cg_upd_kernel<2, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, r_in, r_out, pv,
+                               c->cgs, part, npart);
+        else
+            hipLaunchKernelGGL((cg_upd_kernel<1, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, r_in, r_out, pv,
+                               c->cgs, part, npart);
+    };
     int pi = 0;  // p[pi] holds the current search direction
     int chunk = flexible ? 2 : 4;
     long long launched = 0;
@@ -586,12 +631,10 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     }
     while (true) {
         for (int m = 0; m < chunk; ++m) {
-            hipLaunchKernelGGL(cg_dir_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, rb[ri], z, c->p[pi], c->p[1 - pi],
-                               c->cgs, part, npart);
+            launch_dir(rb[ri], z, c->p[pi], c->p[1 - pi]);
             hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 1, (int)FIN_ALPHA,
                                c->cgs);
-            hipLaunchKernelGGL(cg_upd_kernel, dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, rb[ri], rb[1 - ri],
-                               c->p[1 - pi], c->cgs, part, npart);
+            launch_upd(rb[ri], rb[1 - ri], c->p[1 - pi]);
             hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 2, (int)FIN_BETA,
                                c->cgs);
             if (flexible) {
