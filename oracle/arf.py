@@ -15,7 +15,7 @@ and handed to the shear solver as a prescribed source.  Two forms:
 * Poynting form, Eq. (arf_poynting): f_i = (2 alpha / c) I_i with the
   time-averaged Poynting vector I_i = <p v_i>, the average normalised the same
   way (sum over the samples divided by the samples in one pulse; Sec. 5.1 uses
-  this form "with pulse normalization corrections").
+  this form with a pulse normalisation it does not write out).
 
 alpha is the absorption in Np/m at the transmit frequency.  Regions outside
 the tissue of interest are masked to zero (Sec. 5.1).  Sec. 6.3 (Table

@@ -422,7 +422,7 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
             st->status = KVS_EBREAKDOWN;
             st->done = 1;
         } else if (s1 == 0.0 || s3 == 0.0) {
-            st->done = 1;  // nothing to solve, or b = 0 (phi is set to 0 by the driver)
+            st->done = 1;  // nothing to solve, or b = 0 (phi is set to 0 by the host)
         } else if (st->fixed_iters <= 0 && !(1.0 >= sqrt(st->tol2))) {
             st->done = 1;  // tol > 1: the initial residual already satisfies the test
         }
@@ -654,7 +654,7 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
         CG_HIP(hipMemcpyAsync(c->cgs_host, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
         CG_HIP(hipStreamSynchronize(c->stream));
         if (c->cgs_host->done) break;
-        if (launched > cap) return fail(c, KVS_EDEVICE, "CG driver: iteration cap passed without a stop flag");
+        if (launched > cap) return fail(c, KVS_EDEVICE, "CG: iteration cap passed without a stop flag");
         chunk = std::min(chunk * 2, flexible ? 8 : 64);
     }
     // b = 0 gives phi = 0, also when a warm start began from an earlier phi
