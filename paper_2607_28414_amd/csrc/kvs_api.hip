@@ -959,9 +959,16 @@ kvs_status kvs_strain_get(const kvs_ctx* cc, double* peak_strain, double* peak_g
     if (peak_strain)
         API_HIP(c, hipMemcpyAsync(peak_strain, c->strain_peak, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToHost,
                                   c->stream));
-    if (peak_gradient)
-        API_HIP(c, hipMemcpyAsync(peak_gradient, c->strain_peak + c->N, sizeof(double) * (size_t)c->N,
-                                  hipMemcpyDeviceToHost, c->stream));
+    if (peak_gradient) {
+        double* roots = nullptr;
+        API_HIP(c, hipMalloc(&roots, sizeof(double) * (size_t)c->N));
+        hipError_t e = kvs_launch_strain_roots(c, roots);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(peak_gradient, roots, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        (void)hipFree(roots);
+        if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("strain: ") + hipGetErrorString(e));
+    }
     API_HIP(c, hipStreamSynchronize(c->stream));
     return KVS_OK;
 }

@@ -127,7 +127,9 @@ __global__ __launch_bounds__(256) void arf_force_kernel(const ForceArgs a) {
 // by FP64 issue (each gradient term differs from the divided form by a few
 // roundings).  The neighbours' p reads hit the caches: concurrent blocks
 // cover adjacent rows and planes.  Running maxima in registers; a NaN, once
-// seen, stays.
+// seen, stays.  The gradient map holds the running maximum of |grad eps|^2:
+// the square root is monotone and correctly rounded, so taking it once when
+// the map is read gives the maximum of the roots exactly.
 template <typename T>
 __global__ __launch_bounds__(256) void strain_kernel(const T* __restrict__ p, long long N, int nsamp, int nx, int ny,
                                                      int nz, const double* __restrict__ K, int sK, double inv_2hx,
@@ -156,8 +158,8 @@ __global__ __launch_bounds__(256) void strain_kernel(const T* __restrict__ p, lo
             const double gx = (en[1] - en[0]) * inv_2hx;
             const double gy = (en[3] - en[2]) * inv_2hy;
             const double gz = (en[5] - en[4]) * inv_2hz;
-            const double g = sqrt(gx * gx + gy * gy + gz * gz);
-            pg = (g > pg || __builtin_isnan(g)) ? g : pg;
+            const double g2 = gx * gx + gy * gy + gz * gz;
+            pg = (g2 > pg || __builtin_isnan(g2)) ? g2 : pg;
         }
     }
     peak[i] = pe;
@@ -228,6 +230,23 @@ hipError_t kvs_launch_strain(kvs_ctx* c, const void* p, int64_t nsamp, int dtype
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+namespace {
+// The gradient map's square roots (the map holds squares while samples are
+// folded in).
+__global__ __launch_bounds__(256) void sqrt_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                   long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = sqrt(in[i]);
+}
+}  // namespace
+
+hipError_t kvs_launch_strain_roots(kvs_ctx* c, double* out) {
+    const long long N = (long long)c->N;
+    const unsigned blocks = (unsigned)std::min<long long>((N + 255) / 256, 16384);
+    hipLaunchKernelGGL(sqrt_kernel, dim3(blocks), dim3(256), 0, c->stream, c->strain_peak + N, out, N);
+    return hipGetLastError();
 }
 
 hipError_t kvs_launch_arf_force(kvs_ctx* c, const double* alpha, int sa, const double* cs, int sc, const double* rho,

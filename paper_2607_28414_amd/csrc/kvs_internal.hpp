@@ -217,6 +217,8 @@ hipError_t kvs_launch_arf_accumulate(kvs_ctx* c, const void* p, const void* v, i
 // peak strain maps (kvs_arf.hip): fold nsamp pressure samples (dtype 0 =
 // double, 1 = float, [nsamp][N]) into c->strain_peak with c->strain_K
 hipError_t kvs_launch_strain(kvs_ctx* c, const void* p, int64_t nsamp, int dtype);
+// square roots of the gradient map (stored as squares) into out (device, N)
+hipError_t kvs_launch_strain_roots(kvs_ctx* c, double* out);
 // absorbing layer (kvs_pml.hip): default frequency shift, slab cells of an
 // axis, coefficient tables from dt and the material, and the layer passes of
 // one step (after kvs_launch_step, before the buffers flip)
