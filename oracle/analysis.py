@@ -110,3 +110,39 @@ def group_speed_xcorr(traces, offsets, dt):
     lags = np.array([xcorr_lag(tr[:, 0], tr[:, i], dt) for i in range(tr.shape[1])])
     speed, _ = fit_speed(offsets, lags)
     return speed, lags
+
+
+def successive_orders(hs, traces):
+    """Self-convergence of traces sampled at common times on levels of
+    spacing hs[0] > hs[1] > ...: d_k = trace_l2(v_k, v_{k+1}) (mean over
+    sensors of the relative L2 difference), then for each pair of successive
+    differences the order p with d_k / d_{k+1} = (h_k^p - h_{k+1}^p) /
+    (h_{k+1}^p - h_{k+2}^p) (the leading error term C h^p), and a global p by
+    least squares of log d_k against log(h_k^p - h_{k+1}^p) over all k.
+    Returns (d, per-interval orders, global order)."""
+    hs = np.asarray(hs, dtype=float)
+    d = np.array([trace_l2(traces[k], traces[k + 1]) for k in range(len(traces) - 1)])
+
+    def ratio(p, k):
+        return (hs[k] ** p - hs[k + 1] ** p) / (hs[k + 1] ** p - hs[k + 2] ** p)
+
+    def solve(target, k):
+        lo, hi = 0.1, 8.0  # the ratio grows with p
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if ratio(mid, k) < target:
+                lo = mid
+            else:
+                hi = mid
+        return 0.5 * (lo + hi)
+
+    per = np.array([solve(d[k] / d[k + 1], k) for k in range(len(d) - 1)])
+
+    def misfit(p):
+        x = np.log(hs[:-1] ** p - hs[1:] ** p)
+        c = np.mean(np.log(d) - x)
+        return np.sum((np.log(d) - x - c) ** 2)
+
+    ps = np.linspace(0.5, 4.0, 3501)
+    glob = float(ps[np.argmin([misfit(p) for p in ps])])
+    return d, per, glob

@@ -4,16 +4,17 @@ Curl-based initial state (Sec. 3.5) and the non-viscous wavespeed recovery
 (Sec. 4.1): the state matches the oracle's exactly (FP64) or to the FP32
 rounding of the same FP64 value; runs from it match the oracle's traces
 (FP64 to 1e-12, FP32 to 2e-5 relative L2); at the paper's 180^3 size the
-FP32 traces match the oracle's stored ones (2e-5) and the peak-arrival fit
-recovers cs = 2 m/s within 1 %."""
+FP32 traces match the oracle's stored ones (2e-5), the peak-arrival fit
+recovers cs = 2 m/s within 1 % (displacement peaks) and 0.1 % (velocity
+peaks); the FP64 grid-convergence study of Sec. 4.2 converges at order 2."""
 import os
 
 import numpy as np
 import pytest
 
 import oracle
-from oracle.analysis import arrival_time, fit_speed, rel_l2
-from workloads import curl_wavespeed_case, qiba_phantoms
+from oracle.analysis import arrival_time, centred_velocity, fit_speed, rel_l2, successive_orders
+from workloads import convergence_level, curl_wavespeed_case, qiba_phantoms
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "curl_wavespeed_180.txt")
@@ -122,6 +123,45 @@ def test_wavespeed_recovery_180(kvs):
     say(f"wavespeed: fit {c_fit:.4f} m/s (oracle {c_g:.4f}), per sensor {w['offsets'] / times}")
     assert abs(c_fit - 2.0) < 0.02
     assert abs(c_fit - c_g) < 1e-4 * c_g
+    # arrivals at the peaks of the centred velocity traces: sqrt(G / rho) within 0.1 %
+    v = centred_velocity(tr, dt)
+    times_v = np.array([arrival_time(v[:, i], dt, t0=dt) for i in range(v.shape[1])])
+    c_v, _ = fit_speed(w["offsets"], times_v)
+    say(f"wavespeed: velocity-peak fit {c_v:.5f} m/s")
+    assert abs(c_v - 2.0) < 1e-3 * 2.0
+
+
+def convergence_traces(kvs, n):
+    """One level of the Sec. 4.2 study on the GPU (FP64): the centred velocity
+    traces at the sensors, sampled at t = m Ts for m = 2 .. nsamp."""
+    w = convergence_level(n)
+    say(f"case convergence level n={n} ({w['nsteps']} steps)")
+    ctx = kvs.kvs_create(w["grid"], precision=kvs.KVS_FP64)
+    try:
+        kvs.kvs_set_material_uniform(ctx, w["G"], w["rho"], w["eta"])
+        kvs.kvs_set_dt(ctx, w["dt"])
+        kvs.kvs_set_state_curl(ctx, w["A"])
+        kvs.kvs_set_probes(ctx, w["probes"], 2)
+        kvs.kvs_step(ctx, w["nsteps"])
+        tr = kvs.kvs_read_traces(ctx, len(w["probes"]), 1)[:, :, 0]
+    finally:
+        kvs.kvs_destroy(ctx)
+    v = centred_velocity(tr, w["dt"])
+    sub = w["sub"]
+    # trace index k holds t = (k + 1) dt
+    return w["grid"][3], v[2 * sub - 1::sub][:w["nsamp"] - 1]
+
+
+def test_self_convergence_second_order(kvs):
+    """Sec. 4.2: five levels of a 36 mm cube (h = 0.6 .. 0.2 mm), the velocity
+    traces at four sensors; successive trace differences (relative L2) fall
+    at order 2 on every interval."""
+    hs, traces = zip(*(convergence_traces(kvs, n) for n in (61, 91, 121, 151, 181)))
+    d, per, glob = successive_orders(hs, traces)
+    say(f"convergence: differences {d}, orders {per}, global {glob:.3f}")
+    assert np.all(np.diff(d) < 0)
+    assert np.all(per >= 1.8), per
+    assert 1.9 <= glob <= 2.2, glob
 
 
 QIBA_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "qiba_240x200x200.txt")

@@ -56,3 +56,21 @@ def test_stored_qiba_speeds_are_within_two_percent():
         elif line.startswith("# lags "):
             assert np.all(np.diff([float(v) for v in f[2:]]) > 0)
     assert found == 4
+
+
+def test_successive_orders_recover_known_orders():
+    """Traces v_h = v + C h^p phi(t) (plus a higher-order term) on levels of
+    uneven refinement give back p per interval and globally (C small, so the
+    finer level's norm in the relative difference stays put)."""
+    from oracle.analysis import successive_orders
+    t = np.linspace(0, 1, 200)
+    v = np.stack([np.sin(5 * t), np.cos(3 * t)], axis=1)
+    phi = np.stack([np.cos(7 * t), np.sin(2 * t)], axis=1)
+    hs = [0.6, 0.4, 0.3, 0.24, 0.2]
+    for p in (1.0, 2.0, 3.0):
+        traces = [v + 1e-4 * h ** p * phi for h in hs]
+        d, per, glob = successive_orders(hs, traces)
+        assert np.allclose(per, p, atol=1e-3) and abs(glob - p) <= 2e-3, (p, per, glob)
+    traces = [v + 1e-4 * h ** 2 * phi + 2e-5 * h ** 4 * phi for h in hs]
+    _, per, glob = successive_orders(hs, traces)
+    assert np.all(np.abs(per - 2) < 0.15) and abs(glob - 2) < 0.1

@@ -489,3 +489,21 @@ def pulsed_envelope(dt, on=1e-3, off=1e-3, pulses=25):
     for q in range(pulses):
         g[q * n_per:q * n_per + n_on] = 1.0
     return g
+
+
+def convergence_level(n, width=36e-3, sigma=3e-3, cs=2.0, rho=1000.0, Ts=120e-6, window=9.6e-3,
+                      offsets_mm=(3.6, 6.0, 8.4, 10.8)):
+    """One level of the grid-convergence study (Sec. 4.2): a cube `width`
+    wide with n nodes (n - 1 a multiple of 30 so that the sensors, at
+    multiples of 1.2 mm from the centre along x, and the centre sit on
+    nodes), the curl source of the wavespeed case with a Gaussian of width
+    sigma, eta = 0, Dirichlet walls; dt = Ts 30 / (n - 1), so that every
+    level samples t = m Ts; `window` long.  Returns the curl_wavespeed_case
+    dict plus dt, nsteps, sub (steps per Ts) and nsamp (samples at m Ts,
+    m = 1 .. nsamp)."""
+    assert (n - 1) % 30 == 0 and n % 2 == 1
+    h = width / (n - 1)
+    w = curl_wavespeed_case(n=n, h=h, cs=cs, rho=rho, sigma=sigma, offsets_mm=offsets_mm)
+    sub = (n - 1) // 30
+    w.update(dt=Ts / sub, sub=sub, nsteps=int(round(window / Ts)) * sub, nsamp=int(round(window / Ts)) - 1)
+    return w
