@@ -8,6 +8,11 @@ subtraction), advance 4000 FDTD steps with the push envelope and the
 lateral-line probe traces, and read the traces back.  The material, force
 pattern and probes are resident in HBM before timing.
 
+--workload kvline: the 1-D harmonic Kelvin-Voigt sweep (16 viscosities as
+one batch of line instances), replay time of the whole sweep; pml, arf and
+fpcg: the cost legs of the absorbing layer, the radiation-force generator and
+the learned preconditioner.
+
 --workload batch: one benchmark step is the 64-instance homogeneous sweep
 (edges 96..192, G and eta from the sweep values): all instances to rest, one
 projection per distinct grid shared by its instances, 2000 steps of every
@@ -65,7 +70,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["inclusions", "batch", "fpcg", "arf", "pml"], default="inclusions",
+    ap.add_argument("--workload", choices=["inclusions", "batch", "fpcg", "arf", "pml", "kvline"], default="inclusions",
                     help="fpcg: profiling aid, flexible-PCG iterations on the 384 x 384 x 512 grid; "
                          "arf: the ARF accumulation leg alone; pml: cost of the absorbing layer")
     ap.add_argument("--grid", type=int, default=256, help="cubic grid edge of the inclusion workload")
@@ -598,6 +603,79 @@ def run_batch(args):
     }
 
 
+def run_kvline_bench(args):
+    """The 1-D harmonic Kelvin-Voigt sweep (Sec. 4.3): the 16 viscosities as
+    one FP32 batch of 301 x 3 x 3 line instances (transverse spacings 1e6 m),
+    a common dt = 0.3 x the most viscous instance's limit, 16 ms of harmonic
+    drive (16071 steps) replayed as one hipGraph; HIP events on the batch's
+    stream around the replay.  The oracle runs the same sweep on the host for
+    the CPU baseline."""
+    import numpy as np
+    import torch
+
+    from paper_2607_28414_amd import kvs
+    from workloads import KV_LINE_ETAS, kv_line_case, kv_line_grid
+
+    torch.cuda.set_device(0)
+    G, rho = 4e3, 1000.0
+    grid = kv_line_grid()
+    n = len(KV_LINE_ETAS)
+    stream = torch.cuda.current_stream()
+    b = kvs.kvs_batch_create([grid] * n, precision=kvs.KVS_FP32, sponge_cells=0, stream=stream.cuda_stream)
+    try:
+        dts = []
+        for i, eta in enumerate(KV_LINE_ETAS):
+            ctx = kvs.kvs_batch_instance(b, i)
+            kvs.kvs_set_material_uniform(ctx, G, rho, eta)
+            dts.append(kvs.kvs_stable_dt(ctx))
+        dt = 0.3 * min(dts)
+        nsteps = int(round(16e-3 / dt))
+        cases = []
+        for i, eta in enumerate(KV_LINE_ETAS):
+            ctx = kvs.kvs_batch_instance(b, i)
+            kvs.kvs_set_dt(ctx, dt)
+            # sensor placement from the expected wave is irrelevant to the cost:
+            # the elastic wavelength and no attenuation for every instance
+            case = kv_line_case(grid, eta, dt, nsteps, 0.0, 2.0)
+            kvs.kvs_set_envelope(ctx, case["env"])
+            kvs.kvs_set_projected_force(ctx, case["FS"])
+            kvs.kvs_batch_set_probes(b, i, case["probes"])
+            cases.append(case)
+        kvs.kvs_batch_set_component(b, 2)
+        log(f"bench: kv line sweep, {n} instances, {nsteps} steps (graph capture)")
+        kvs.kvs_batch_step(b, nsteps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(max(1, args.steps)):
+            kvs.kvs_batch_reset(b)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            kvs.kvs_batch_step(b, nsteps)  # same start, length and trace slot: replay
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        tr = kvs.kvs_batch_read_traces(b, n - 1, len(cases[-1]["probes"]))
+        assert np.all(np.isfinite(tr)), "non-finite traces"
+    finally:
+        kvs.kvs_batch_destroy(b)
+    gpu_ms = float(np.median(ms))
+    res = {"workload": f"1-D harmonic Kelvin-Voigt sweep: {n} viscosities (0-1.5 Pa s) as one FP32 batch of "
+                       f"{grid[0]}x3x3 lines, h 0.1 mm, {nsteps} steps (16 ms), one hipGraph",
+           "ms_per_sweep": gpu_ms, "us_per_step": 1e3 * gpu_ms / nsteps, "instances": n, "fdtd_steps": nsteps,
+           "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        for eta, case in zip(KV_LINE_ETAS, cases):
+            oracle.run(grid, G, rho, eta, dt, nsteps, FS=case["FS"], env=case["env"], probes=case["probes"],
+                       comp=2)
+        cpu_ms = (time.perf_counter() - t0) * 1e3
+        # the oracle splits its loops over z planes: a line has one interior plane
+        res["cpu_baseline"] = {"value": cpu_ms, "unit": "ms per sweep", "cores": 1, "kind": "oracle",
+                               "sample": "the whole sweep, FP64, one thread (one interior z plane)"}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -618,6 +696,9 @@ def main():
         return
     if args.workload == "pml":
         print(json.dumps(run_pml_bench(args)), flush=True)
+        return
+    if args.workload == "kvline":
+        print(json.dumps(run_kvline_bench(args)), flush=True)
         return
     import numpy as np
     import torch

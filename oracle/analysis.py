@@ -6,8 +6,10 @@
 * Trace-L2: relative L2 norm of a velocity-trace difference against a
   reference, averaged over sensors (Sec. 4.2).
 * Relative L2 of two flattened arrays (parity metric).
-* Two-sensor harmonic estimate of (alpha, c) from a complex amplitude ratio
-  (Sec. 4.3 style measurement).
+* Peak lag by cross-correlation and group speed (Sec. 4.4); successive
+  trace differences and the self-convergence order (Sec. 4.2).
+* Harmonic phasors of steady traces and the plane-wave fit of attenuation
+  and phase speed along a line of sensors (Sec. 4.3).
 """
 from __future__ import annotations
 
@@ -59,29 +61,6 @@ def trace_l2(v, v_ref):
     num = np.linalg.norm(v - r, axis=0)
     den = np.linalg.norm(r, axis=0)
     return float(np.mean(num / den))
-
-
-def harmonic_amplitude(trace, dt, omega, n0, n1):
-    """Complex amplitude of exp(-i w t) in trace[n0:n1] by least squares on
-    cos/sin (window chosen as whole periods by the caller)."""
-    t = np.arange(n0, n1) * dt
-    y = np.asarray(trace, dtype=float)[n0:n1]
-    A = np.vstack([np.cos(omega * t), np.sin(omega * t)]).T
-    (a, b), *_ = np.linalg.lstsq(A, y, rcond=None)
-    # y = a cos wt + b sin wt = Re[(a + i b) exp(-i w t)]
-    return complex(a, b)
-
-
-def two_sensor_k(a1, a2, dx, k_guess):
-    """Complex wavenumber from amplitudes a1, a2 at sensors dx apart
-    (a2/a1 = exp(i k dx)); the phase is unwrapped against k_guess."""
-    ratio = a2 / a1
-    alpha = -np.log(abs(ratio)) / dx
-    ph = np.angle(ratio)
-    kr_guess = np.real(k_guess)
-    m = np.round((kr_guess * dx - ph) / (2 * np.pi))
-    kr = (ph + 2 * np.pi * m) / dx
-    return complex(kr, alpha)
 
 
 def xcorr_lag(ref, sig, dt):
@@ -146,3 +125,32 @@ def successive_orders(hs, traces):
     ps = np.linspace(0.5, 4.0, 3501)
     glob = float(ps[np.argmin([misfit(p) for p in ps])])
     return d, per, glob
+
+
+def harmonic_phasors(traces, dt, omega, t_from, t0=None):
+    """Complex amplitudes A of steady harmonic traces (the measurement of the
+    1-D harmonic Kelvin-Voigt benchmark, Sec. 4.3), u(t) = Re(A e^{-i w t})
+    = Re(A) cos(w t) + Im(A) sin(w t): least squares over the samples at
+    t >= t_from with a constant and a linear trend as extra columns (the
+    offset a net impulse leaves on a line).  traces [step][sensor], sample k at
+    t = t0 + k dt (t0 = dt: a trace row holds the state after its step).
+    Returns A [sensor]."""
+    tr = np.asarray(traces, dtype=float)
+    t = (dt if t0 is None else t0) + np.arange(tr.shape[0]) * dt
+    sel = t >= t_from
+    ts = t[sel]
+    M = np.stack([np.cos(omega * ts), np.sin(omega * ts), np.ones_like(ts), ts - ts.mean()], axis=1)
+    coef, *_ = np.linalg.lstsq(M, tr[sel], rcond=None)
+    return coef[0] + 1j * coef[1]
+
+
+def plane_wave_fit(x, A, omega):
+    """Attenuation and phase speed of a plane wave A(x) = A0 exp(i k x),
+    k = k_r + i alpha, from phasors at positions x: alpha = minus the
+    least-squares slope of ln|A| against x, k_r the slope of the unwrapped
+    phase, c = w / k_r.  Returns (alpha [Np/m], c [m/s])."""
+    x = np.asarray(x, dtype=float)
+    A = np.asarray(A)
+    alpha = -np.polyfit(x, np.log(np.abs(A)), 1)[0]
+    kr = np.polyfit(x, np.unwrap(np.angle(A)), 1)[0]
+    return float(alpha), float(omega / kr)

@@ -1,0 +1,106 @@
+"""The 1-D harmonic Kelvin-Voigt benchmark (Sec. 4.3) as one batch on the
+GPU: the 16 viscosities of the sweep as instances of one batch (one launch
+per step over all of them, replayed as a hipGraph), a common dt, through the
+C ABI.  Every instance's sensor traces match the oracle's (FP64 1e-12
+relative L2; FP32 state 2e-5); the attenuation and phase speed measured
+from them match the oracle's measurement and the discrete scheme's closed
+form, and lie within the paper's bars (about 3 % in alpha, < 1 % in c) of the
+continuous Kelvin-Voigt law."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dispersion
+from oracle.analysis import harmonic_phasors, plane_wave_fit, rel_l2
+from workloads import KV_LINE_ETAS, kv_line_case, kv_line_frequency, kv_line_grid
+
+pytestmark = pytest.mark.gpu
+G, RHO = 4e3, 1000.0
+T_RUN = 16e-3
+CHUNK = 4096  # steps per kvs_batch_step call (one captured graph each)
+
+
+@pytest.fixture(scope="module")
+def kvs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2607_28414_amd import kvs as k
+    k.lib()
+    return k
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sweep():
+    """Inputs of the 16 instances and the oracle's traces (FP64)."""
+    grid = kv_line_grid()
+    dt = 0.3 * min(oracle.stable_dt(grid, G, RHO, e) for e in KV_LINE_ETAS)
+    nsteps = int(round(T_RUN / dt))
+    cases, traces = [], []
+    for eta in KV_LINE_ETAS:
+        a_th, c_th = dispersion.kv_attenuation_speed(2 * np.pi * kv_line_frequency(eta), G, RHO, eta)
+        case = kv_line_case(grid, eta, dt, nsteps, float(a_th), float(c_th))
+        _, _, tr = oracle.run(grid, G, RHO, eta, dt, nsteps, FS=case["FS"], env=case["env"],
+                              probes=case["probes"], comp=2)
+        cases.append(case)
+        traces.append(tr[:, :, 0])
+    return grid, dt, nsteps, cases, traces
+
+
+def measure(case, tr, dt):
+    A = harmonic_phasors(tr, dt, case["omega"], case["t_from"])
+    return plane_wave_fit(case["x"], A, case["omega"])
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_kv_line_sweep_batch(kvs, sweep, precision):
+    grid, dt, nsteps, cases, tr_o = sweep
+    n = len(KV_LINE_ETAS)
+    say(f"case kv line sweep precision {precision}: {n} instances of {grid[0]}x3x3, {nsteps} steps")
+    b = kvs.kvs_batch_create([grid] * n, precision=precision, sponge_cells=0)
+    try:
+        for i, eta in enumerate(KV_LINE_ETAS):
+            ctx = kvs.kvs_batch_instance(b, i)
+            kvs.kvs_set_material_uniform(ctx, G, RHO, eta)
+            assert kvs.kvs_stable_dt(ctx) == pytest.approx(oracle.stable_dt(grid, G, RHO, eta), rel=1e-12)
+            kvs.kvs_set_dt(ctx, dt)
+            kvs.kvs_set_envelope(ctx, cases[i]["env"])
+            kvs.kvs_set_projected_force(ctx, cases[i]["FS"])
+            kvs.kvs_batch_set_probes(b, i, cases[i]["probes"])
+        kvs.kvs_batch_set_component(b, 2)
+        t0 = time.perf_counter()
+        done = 0
+        while done < nsteps:
+            m = min(CHUNK, nsteps - done)
+            kvs.kvs_batch_step(b, m)
+            done += m
+        tr = [kvs.kvs_batch_read_traces(b, i, len(cases[i]["probes"])) for i in range(n)]
+        say(f"kv line sweep: {nsteps} steps of {n} instances in {1e3 * (time.perf_counter() - t0):.0f} ms "
+            f"(graph capture included)")
+    finally:
+        kvs.kvs_batch_destroy(b)
+    tol = 1e-12 if precision == 0 else 2e-5
+    for i, eta in enumerate(KV_LINE_ETAS):
+        case = cases[i]
+        err = rel_l2(tr[i], tr_o[i])
+        alpha, c = measure(case, tr[i], dt)
+        alpha_o, c_o = measure(case, tr_o[i], dt)
+        kh = dispersion.discrete_wavenumber(case["omega"], G, RHO, eta, grid[3], dt)
+        a_th, c_th = dispersion.kv_attenuation_speed(case["omega"], G, RHO, eta)
+        say(f"eta {eta:.1f} f0 {case['f0']:.1f}: rel L2 {err:.2e}  alpha {alpha:8.3f} (oracle {alpha_o:8.3f}, "
+            f"scheme {kh.imag:8.3f}, KV {a_th:8.3f})  c {c:.5f} (oracle {c_o:.5f}, scheme "
+            f"{case['omega'] / kh.real:.5f}, KV {c_th:.5f})")
+        assert err < tol, (eta, err)
+        assert c == pytest.approx(c_o, rel=1e-9 if precision == 0 else 1e-5)
+        assert abs(c / c_th - 1) < 0.01
+        if eta > 0:
+            assert alpha == pytest.approx(alpha_o, rel=1e-9 if precision == 0 else 1e-4)
+            assert abs(alpha / a_th - 1) < 0.03
+        else:
+            assert abs(alpha) < (1e-3 if precision == 0 else 0.05)

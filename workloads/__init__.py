@@ -507,3 +507,62 @@ def convergence_level(n, width=36e-3, sigma=3e-3, cs=2.0, rho=1000.0, Ts=120e-6,
     sub = (n - 1) // 30
     w.update(dt=Ts / sub, sub=sub, nsteps=int(round(window / Ts)) * sub, nsamp=int(round(window / Ts)) - 1)
     return w
+
+
+# Viscosity sweep of the 1-D harmonic Kelvin-Voigt benchmark (Sec. 4.3):
+# eta = 0 .. 1.5 Pa s in steps of 0.1.
+KV_LINE_ETAS = tuple(round(0.1 * j, 10) for j in range(16))
+# Drive frequencies [Hz] at the viscosities of the benchmark's table: the ones
+# at which the continuous Kelvin-Voigt law with c_s = 2 m/s (G = 4 kPa,
+# rho = 1000) gives the table's theoretical attenuation; the paper names a
+# smooth schedule f0(eta) without its values.
+KV_LINE_F0_KNOTS = ((0.1, 800.1), (0.3, 789.9), (0.5, 761.0), (1.0, 742.0), (1.5, 742.1))
+
+
+def kv_line_frequency(eta):
+    """Drive frequency [Hz] for viscosity eta: linear between the knots,
+    held at the end values outside them."""
+    k = np.array(KV_LINE_F0_KNOTS)
+    return float(np.interp(eta, k[:, 0], k[:, 1]))
+
+
+def kv_line_grid(nx=301, h=1e-4, transverse=1e6):
+    """A 1-D line of nx nodes (h apart, Dirichlet ends) as an nx x 3 x 3 grid
+    whose y and z spacings are `transverse` metres: the line is the one
+    interior row (j = k = 1), and the y and z terms of the stencil, which see
+    the zero Dirichlet neighbours, scale with 1 / transverse^2 and are below
+    FP64 rounding of the x terms (1e-20 of them at the defaults)."""
+    return (nx, 3, 3, h, transverse, transverse)
+
+
+def kv_line_case(grid, eta, dt, nsteps, alpha_expected, c_expected, amp=1e4, ramp_periods=2.0,
+                 fit_periods=4.0, n_sensors=6, first_mm=0.5, source=1):
+    """Inputs of one instance of the harmonic benchmark on a kv_line_grid:
+    a z-directed point force on line node `source` (next to the x = 0 wall)
+    driven by g^n = r(t_n) sin(w t_n), t_n = n dt, with a raised-cosine
+    ramp r over `ramp_periods` periods (it keeps the start-up transient
+    narrow-band), w = 2 pi f0(eta); n_sensors sensors on the line from
+    first_mm past the source over a span of min(2 wavelengths, 2 e-folding
+    lengths) of the expected wave (alpha_expected [Np/m], c_expected [m/s]:
+    the sensors adapt to the attenuation); the fit window is the last
+    fit_periods periods of the run.  The projected force is the pattern
+    itself: a transverse force uniform over a plane has no divergence.
+    Returns dict(f0, omega, FS [3][3][3][nx], env [nsteps], probes [s][3],
+    x [s] (metres from the wall), t_from)."""
+    nx, h = grid[0], grid[3]
+    f0 = kv_line_frequency(eta)
+    omega = 2.0 * np.pi * f0
+    lam = c_expected / f0
+    span = 2.0 * lam if alpha_expected <= 0 else min(2.0 * lam, 2.0 / alpha_expected)
+    d = first_mm * 1e-3 + np.linspace(0.0, span, n_sensors)
+    ix = source + np.round(d / h).astype(np.int64)
+    assert ix[-1] < nx - 1 and len(set(ix.tolist())) == n_sensors
+    FS = np.zeros((3, 3, 3, nx))
+    FS[2, 1, 1, source] = amp
+    t = np.arange(nsteps) * dt
+    Tr = ramp_periods / f0
+    r = np.where(t < Tr, 0.5 * (1.0 - np.cos(np.pi * t / Tr)), 1.0)
+    env = r * np.sin(omega * t)
+    probes = np.stack([ix, np.ones_like(ix), np.ones_like(ix)], axis=1)
+    return dict(f0=f0, omega=omega, FS=FS, env=env, probes=probes, x=ix * h,
+                t_from=nsteps * dt - fit_periods / f0)
