@@ -184,14 +184,15 @@ def focal_focus_z(grid, epoch, dt, steps_per_epoch=10, speed=1e-3 / 20e-6):
 
 
 def focal_modulated_force(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=10, sigma_l=1e-3, sigma_a=4e-3,
-                          F0=1e4):
+                          F0=1e4, device=None):
     """Non-separable push of the time-varying workload: F_z = F0 exp(-(x^2 +
     y^2) / (2 sigma_l^2) - (z - z_f)^2 / (2 sigma_a^2)) M(x), with the focus
     z_f of `focal_focus_z` and M(x) = 1 + 0.5 / sqrt(8) sum_m cos(k_m . x +
     phi_m): 8 plane waves, |k_m| uniform in [2 pi / 4 mm, 2 pi / 1 mm] with
     random directions (fixed by `seed`), phases phi_m redrawn every epoch
     (seeded by (seed, epoch)).  F is set to 0 where the Gaussian factor is
-    below 1e-16.  Returns [3][nz][ny][nx] FP64."""
+    below 1e-16.  Returns [3][nz][ny][nx] FP64: a numpy array, or with
+    `device` a torch tensor built there (same formula, torch's exp and cos)."""
     nx, ny, nz, hx, hy, hz = grid
     rng = np.random.default_rng(seed)
     kmag = rng.uniform(2 * np.pi / 4e-3, 2 * np.pi / 1e-3, 8)
@@ -205,6 +206,21 @@ def focal_modulated_force(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=
     ix = np.nonzero(np.abs(x) <= cut * sigma_l)[0]
     iy = np.nonzero(np.abs(y) <= cut * sigma_l)[0]
     iz = np.nonzero(np.abs(z - zf) <= cut * sigma_a)[0]
+    if device is not None:
+        import torch
+        F = torch.zeros((3, nz, ny, nx), dtype=torch.float64, device=device)
+        if ix.size == 0 or iy.size == 0 or iz.size == 0:
+            return F
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        Z, Y, X = torch.meshgrid(t(z[iz]), t(y[iy]), t(x[ix]), indexing="ij")
+        g = torch.exp(-(X ** 2 + Y ** 2) / (2 * sigma_l ** 2) - (Z - zf) ** 2 / (2 * sigma_a ** 2))
+        M = torch.ones_like(g)
+        for m in range(8):
+            M += 0.5 / np.sqrt(8) * torch.cos(float(kvec[m, 0]) * X + float(kvec[m, 1]) * Y + float(kvec[m, 2]) * Z
+                                              + float(phases[m]))
+        # ix, iy, iz are contiguous index ranges (|coordinate| below a bound)
+        F[2, iz[0]:iz[-1] + 1, iy[0]:iy[-1] + 1, ix[0]:ix[-1] + 1] = F0 * g * M
+        return F
     F = np.zeros((3, nz, ny, nx))
     if ix.size == 0 or iy.size == 0 or iz.size == 0:
         return F
