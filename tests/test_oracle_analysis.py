@@ -1,7 +1,10 @@
 """Pins of the host-side estimators used by the validation workloads: the
 cross-correlation lag and the group-speed fit recover known delays of
-sampled pulses (closed form: a shifted copy)."""
+sampled pulses (closed form: a shifted copy); the self-convergence order is
+recovered from synthetic errors C h^p; the centred velocity is exact on
+quadratics; the trace-L2 difference is the mean relative difference."""
 import numpy as np
+import pytest
 
 from oracle.analysis import arrival_time, fit_speed, group_speed_xcorr, xcorr_lag
 
@@ -74,3 +77,26 @@ def test_successive_orders_recover_known_orders():
     traces = [v + 1e-4 * h ** 2 * phi + 2e-5 * h ** 4 * phi for h in hs]
     _, per, glob = successive_orders(hs, traces)
     assert np.all(np.abs(per - 2) < 0.15) and abs(glob - 2) < 0.1
+
+
+def test_centred_velocity_is_exact_on_quadratics():
+    """(u(t + dt) - u(t - dt)) / (2 dt) is the exact derivative of a quadratic;
+    the end samples are left at 0."""
+    from oracle.analysis import centred_velocity
+    dt = 2.5e-6
+    t = np.arange(40) * dt
+    u = np.stack([3.0 * t ** 2 - 7.0 * t + 1.0, -2.0 * t ** 2], axis=1)
+    v = centred_velocity(u, dt)
+    exact = np.stack([6.0 * t - 7.0, -4.0 * t], axis=1)
+    assert np.allclose(v[1:-1], exact[1:-1], rtol=1e-9, atol=1e-12)
+    assert not v[0].any() and not v[-1].any()
+
+
+def test_trace_l2_is_the_mean_relative_difference_over_sensors():
+    """Sensor k scaled by (1 + e_k): the per-sensor relative L2 difference is
+    |e_k| whatever the trace's size, and trace_l2 is their mean."""
+    from oracle.analysis import trace_l2
+    rng = np.random.default_rng(5)
+    ref = rng.standard_normal((50, 3)) * np.array([1e-9, 1.0, 1e4])
+    e = np.array([0.01, -0.03, 0.002])
+    assert trace_l2(ref * (1 + e), ref) == pytest.approx(np.mean(np.abs(e)), rel=1e-12)
