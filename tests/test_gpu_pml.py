@@ -122,6 +122,49 @@ def test_pml_absorbs_at_scale(kvs):
     assert e_wall > 0.05 and e_pml < 1e-3 * e_wall
 
 
+def test_pml_full_size_256_matches_oracle(kvs):
+    """The absorbing layer's benchmark configuration: the 256^3 inclusion
+    medium, no sponge, a 10-cell layer, the autotuned tile shape, FP32 state.
+    Two steps from a white-noise state (zero on the Dirichlet layer; every
+    layer cell and face active, the memory variables non-zero after the
+    first step) against the FP64
+    oracle on the whole grid: w within 1e-5 of max|w|, u within that plus
+    one FP32 rounding of max|u|."""
+    from oracle.pml import run_pml
+    from workloads import cfg2_inclusions_fp32
+    wl = cfg2_inclusions_fp32(256)
+    grid = wl.grid
+    shp = (3, grid[2], grid[1], grid[0])
+    rng = np.random.default_rng(77)
+    u0 = (rng.standard_normal(shp) * 1e-6).astype(np.float32).astype(np.float64)
+    w0 = (rng.standard_normal(shp) * 1e-8).astype(np.float32).astype(np.float64)
+    for a in (u0, w0):  # the Dirichlet layer holds zeros (kvs_set_state enforces it)
+        a[:, [0, -1], :, :] = 0.0
+        a[:, :, [0, -1], :] = 0.0
+        a[:, :, :, [0, -1]] = 0.0
+    say("case pml full size 256^3, 10 cells, 2 steps from noise")
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
+    try:
+        kvs.kvs_set_material(ctx, wl.G, wl.rho, wl.eta)
+        dt = wl.dt_factor * kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_pml(ctx, 10)
+        variant, _ = kvs.kvs_autotune_step(ctx, 10)
+        kvs.kvs_set_state(ctx, u0, w0, 0)
+        kvs.kvs_step(ctx, 2)
+        u, w, step = kvs.kvs_get_state(ctx, shp[1:])
+    finally:
+        kvs.kvs_destroy(ctx)
+    say(f"pml full size: variant {variant}, oracle running")
+    u_o, w_o, _ = run_pml(grid, wl.G, wl.rho, wl.eta, dt, 2, 10, u=u0, w=w0)
+    ew = np.abs(w - w_o).max() / np.abs(w_o).max()
+    eu = np.abs(u - u_o).max()
+    say(f"pml full size: max |w - w_o| / max|w_o| {ew:.2e}, max |u - u_o| {eu:.2e} (max|u| {np.abs(u_o).max():.2e})")
+    assert step == 2
+    assert ew < 1e-5
+    assert eu < 1e-5 * np.abs(w_o).max() + 2.0 ** -23 * np.abs(u_o).max()
+
+
 def test_pml_errors(kvs):
     grid = (20, 20, 20, 1e-3, 1e-3, 1e-3)
     ctx = kvs.kvs_create(grid, sponge_cells=4)
