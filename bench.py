@@ -24,7 +24,11 @@ value = interior cell-updates of the timed steps / timed wall time
 roofline: the FDTD step kernel, algorithmic bytes per interior cell-update
           (48 B of FP32 u, w read + written, 12 B of G, eta, dt^2/rho, and
           12 B of f_S on push steps) over its HIP-event-timed launches.
-cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload.
+          copy_gbs / frac_of_copy: a plain device-to-device copy measured in the
+          same run (the practical streaming ceiling) and the kernel against it.
+cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload
+              (all host threads), its host's CPU model, and a shorter sample
+              on one thread.
 projection_learned (default run, outside the timed region): projection time
 to 1e-8 of the learned flexible PCG vs Jacobi-PCG on the time-varying
 workload's 384 x 384 x 512 grid, after training the network by the committed
@@ -124,6 +128,29 @@ def copy_calibration(mib):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4}), flush=True)
+
+
+def measured_copy_gbs(mib=1024, reps=10):
+    """Bandwidth of a plain device-to-device copy on this GPU (the HIP
+    runtime's copy kernel behind a same-type tensor copy of `mib` MiB), read
+    plus write bytes over the median of `reps` HIP-event-timed copies: the
+    practical streaming ceiling next to the 8 TB/s peak."""
+    import numpy as np
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * n * 4 / (float(np.median(ms)) * 1e-3) / 1e9
 
 
 def learned_projection(args, net):
@@ -506,10 +533,31 @@ def cpu_baseline(w, dt, smax, FS_host, nsteps):
                sponge_cells=w.sponge_cells, sigma_max=smax)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same oracle on one thread (OpenMP's runtime shared with the oracle's library)
+    import ctypes
+    one = None
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        n1 = 4
+        t1 = time.perf_counter()
+        oracle.run(w.grid, w.G, w.rho, w.eta, dt, n1, FS=FS_host, env=env, probes=w.probes, comp=2,
+                   sponge_cells=w.sponge_cells, sigma_max=smax)
+        one = w.interior_cells * n1 / (time.perf_counter() - t1) / 1e9
+        gomp.omp_set_num_threads(cores)
+    except OSError:
+        pass
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": w.interior_cells * nsteps / el / 1e9, "unit": "Gcell-updates/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(), "value_one_thread": one,
             "sample": f"{nsteps} FDTD steps of the same {w.grid[0]}^3 workload from rest with the push on "
-                      f"(FP64 C oracle, OpenMP), {el:.1f} s; projection not included"}
+                      f"(FP64 C oracle, OpenMP), {el:.1f} s; projection not included; value_one_thread: "
+                      f"4 steps on one thread"}
 
 
 def run_batch(args):
@@ -774,6 +822,7 @@ def main():
     bytes_total = args.steps * (nsteps * cells * 60 + n_push * cells * 12)
     achieved = bytes_total / (k_ms * 1e-3) / 1e9
     traffic = step_traffic(variant)
+    copy_gbs = measured_copy_gbs()  # after the timed region
     res = {
         "metric": METRIC,
         "value": value,
@@ -809,13 +858,15 @@ def main():
             "kernel_ms_avg": k_ms / max(k_launches, 1),
             "launches": k_launches,
             "variant": variant,
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "fdtd_kernel_gcells": args.steps * nsteps * cells / (k_ms * 1e-3) / 1e9,
         "projection": {"precond": "jacobi", "tol": w.tol, "iters": rep["iters"],
                        "relres_true": rep["relres_true"], "ms": float(np.mean(proj_ms))},
     }
     if not args.no_cpu_baseline:
-        log(f"bench: CPU oracle sample ({args.cpu_sample_steps} steps)")
+        log(f"bench: CPU oracle sample ({args.cpu_sample_steps} steps, then 4 on one thread)")
         res["cpu_baseline"] = cpu_baseline(w, dt, smax, FS_host, args.cpu_sample_steps)
     else:
         res["cpu_baseline"] = None
