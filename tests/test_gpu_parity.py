@@ -135,6 +135,42 @@ def test_hetero_viscous_fp64_parity_ragged_tiles(kvs, shape):
     assert not g["u"][:, 0].any() and not g["u"][:, :, :, -1].any() and not g["w"][:, :, 0].any()
 
 
+def test_cfg2_full_size_traces_within_2e5(kvs):
+    """The 256^3 inclusion workload end to end at its full size, in the
+    benchmark's launch configuration (FP32 state, the GPU's own Jacobi-PCG
+    projection to 1e-8, autotuned tile shape), for the first 200 steps (the
+    37-step push and the start of the wave): the lateral-line traces against
+    the oracle's own projection and run, relative L2 within 2e-5."""
+    w = cfg2_inclusions_fp32(n=256)
+    say("case cfg2 256^3 traces, 200 steps")
+    nsteps = 200
+    dt = w.dt_factor * oracle.stable_dt(w.grid, w.G, w.rho, w.eta)
+    env = w.envelope_for(dt)
+    ctx = kvs.kvs_create(w.grid, precision=kvs.KVS_FP32, sponge_cells=w.sponge_cells, sponge_sigma_max=-1.0)
+    try:
+        kvs.kvs_set_material(ctx, w.G, w.rho, w.eta)
+        kvs.kvs_set_dt(ctx, dt)
+        smax = kvs.kvs_sponge_sigma_max(ctx)
+        kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_set_probes(ctx, w.probes, w.comp)
+        variant, _ = kvs.kvs_autotune_step(ctx, 10)
+        kvs.kvs_set_force(ctx, w.F)
+        rep = kvs.kvs_project(ctx, tol=w.tol, max_iter=20000, precond=kvs.KVS_PC_JACOBI)
+        kvs.kvs_step(ctx, nsteps)
+        tr = kvs.kvs_read_traces(ctx, len(w.probes), 1)
+    finally:
+        kvs.kvs_destroy(ctx)
+    say(f"cfg2 traces: variant {variant}, GPU projection {rep['iters']} iterations; oracle running")
+    assert smax == pytest.approx(oracle.default_sigma_max(w.grid, w.G, w.rho, w.sponge_cells), rel=1e-13)
+    FS_o, _, rep_o = oracle.project(w.grid, w.F, tol=w.tol, max_iter=20000, jacobi=True)
+    _, _, tr_o = oracle.run(w.grid, w.G, w.rho, w.eta, dt, nsteps, FS=FS_o, env=env, probes=w.probes, comp=w.comp,
+                            sponge_cells=w.sponge_cells, sigma_max=smax)
+    err = rel_l2(tr, tr_o)
+    say(f"cfg2 traces: oracle projection {rep_o['iters']} iterations; trace rel L2 {err:.3e}")
+    assert rep["iters"] == rep_o["iters"]
+    assert err <= 2e-5
+
+
 def test_fp32_heterogeneous_traces_within_2e5(kvs):
     """Inclusion workload physics at 64^3 (same h, push widths, dt rule and
     tolerance as the 256^3 case): FP32 state with FP64 projection against
