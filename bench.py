@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=100)
     ap.add_argument("--step-variant", type=int, default=-1,
                     help="pin the step-kernel tile shape (default: autotune); used by the counter runs")
+    ap.add_argument("--unet-bottleneck", type=int, default=4,
+                    help="convolutions in the network's quarter-resolution bottleneck (in, dilated 64->64 ones, out)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-preconditioner projection comparison")
     ap.add_argument("--learned-epochs", type=int, default=4,
@@ -888,7 +890,7 @@ def main():
         res["cpu_baseline"] = None
     res["projection_learned"] = res["time_varying"] = res["shell"] = res["arf"] = None
     if not args.no_learned:
-        net = kvs.kvs_unet_create((16, 32, 64), 4)
+        net = kvs.kvs_unet_create((16, 32, 64), args.unet_bottleneck)
         try:
             res["projection_learned"] = learned_projection(args, net)
             if not args.no_workloads:
