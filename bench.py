@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=100)
     ap.add_argument("--step-variant", type=int, default=-1,
                     help="pin the step-kernel tile shape (default: autotune); used by the counter runs")
+    ap.add_argument("--train-rounds", type=int, default=4,
+                    help="training rounds on the network's own flexible-PCG residuals")
+    ap.add_argument("--train-grid", type=int, default=64, help="edge of the cubic unit training grids")
     ap.add_argument("--unet-bottleneck", type=int, default=4,
                     help="convolutions in the network's quarter-resolution bottleneck (in, dilated 64->64 ones, out)")
     ap.add_argument("--no-learned", action="store_true",
@@ -171,10 +174,11 @@ def learned_projection(args, net):
 
     nx, ny, nz, h = 384, 384, 512, 0.2e-3
     grid = (nx, ny, nz, h, h, h)
-    log("bench: training the preconditioner (64^3 unit grids, 2 rounds on its own residuals)")
+    log(f"bench: training the preconditioner ({args.train_grid}^3 unit grids, {args.train_rounds} rounds on its own "
+        "residuals)")
     ctx = None
     try:
-        tr = train.train_default(net, n=64, seed=0, rounds=2)
+        tr = train.train_default(net, n=args.train_grid, seed=0, rounds=args.train_rounds)
         ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, stream=torch.cuda.current_stream().cuda_stream)
         kvs.kvs_set_preconditioner(ctx, net)
         res = {"jacobi": {"iters": [], "ms": []}, "fpcg": {"iters": [], "ms": [], "fallbacks": []},

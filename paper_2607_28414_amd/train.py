@@ -134,7 +134,7 @@ def init_weights(net, rng, scale=0.3):
     kvs.kvs_unet_set_weights(net, w.astype(np.float32))
 
 
-def train_default(net, n=64, seed=0, rounds=2, lr=2e-3, forces=6, base_steps=200, round_steps=120, log=None):
+def train_default(net, n=64, seed=0, rounds=4, lr=2e-3, forces=6, base_steps=200, round_steps=120, log=None):
     """The training recipe: base samples (`forces` random forces with their
     potentials and the errors after 20 and 60 Jacobi-PCG iterations, 4
     white-noise fields), `base_steps` Adam steps at learning rate lr; then
