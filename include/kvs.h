@@ -102,6 +102,11 @@ typedef struct {
                             PCG with the network set by kvs_set_preconditioner */
     int64_t fixed_iters; /* > 0: run exactly this many iterations, ignore tol (parity mode) */
     int32_t warm_start;  /* != 0: start from the previous phi instead of phi_0 = 0 */
+    int32_t confirm_true; /* != 0: once the recursive residual meets tol, recompute the true residual
+                             ||-b - A phi|| / ||b|| in FP64 and, while it is still >= tol, restart the
+                             iteration from it (iterations keep counting up to max_iter).  Always on
+                             for precond = UNET, whose recursive residual can drift from the true one;
+                             0 keeps the paper's stop rule on the recursive residual alone. */
 } kvs_solve_opts;
 
 typedef struct {

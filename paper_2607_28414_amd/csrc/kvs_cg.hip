@@ -48,7 +48,7 @@ struct CgGeom {
     double dinv;              // 1/diag(A)
 };
 
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3, FIN_FZ0 = 4, FIN_FBETA = 5 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3, FIN_FZ0 = 4, FIN_FBETA = 5, FIN_RESTART = 6 };
 
 using kvs_tiling::tile_of;
 
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(64 * CBY) void grad_subtract_kernel(const CgGeom g,
 // partials[s * stride + q], q < count, s < nsum
 __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials, int count, int stride, int nsum,
                                                           int mode, CgState* st) {
-    if (mode != FIN_INIT && mode != FIN_TRUE && st->done) return;
+    if (mode != FIN_INIT && mode != FIN_TRUE && mode != FIN_RESTART && st->done) return;
     // network scales of the flexible PCG from the current residual
     auto set_net_scales = [&](double rr) {
         const double rms = sqrt(rr / st->n_interior);
@@ -493,6 +493,21 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
             st->status = KVS_ENOTCONV;
             st->done = 1;
         }
+    } else if (mode == FIN_RESTART) {
+        // restart from the true residual r = -b - A phi: the iteration count
+        // and b.b are kept, the direction is rebuilt from z alone (beta = 0)
+        st->rr = s1;
+        st->rz = st->jacobi ? s2 : s1;
+        st->beta = 0.0;
+        st->alpha = 0.0;
+        st->done = 0;
+        if (!isfinite(s1) || !isfinite(st->rz)) {
+            st->status = KVS_EBREAKDOWN;
+            st->done = 1;
+        } else if (s1 == 0.0) {
+            st->done = 1;
+        }
+        set_net_scales(s1);
     } else {  // FIN_TRUE
         st->relres_true2 = s3 > 0.0 ? s1 / s3 : 0.0;
     }
@@ -609,8 +624,6 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
                                c->cgs, part, npart);
     };
     int pi = 0;  // p[pi] holds the current search direction
-    int chunk = flexible ? 2 : 4;
-    long long launched = 0;
     const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
     double* z = c->Ap;  // flexible PCG: the preconditioned residual
     const int* stop = &c->cgs->done;
@@ -629,6 +642,11 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
                            c->cgs);
         CG_HIP(hipGetLastError());
     }
+    // Iterate until the device sets the stop flag (tolerance on the recursive
+    // residual, max_iter, fixed_iters or a breakdown).
+    auto iterate = [&]() -> kvs_status {
+    int chunk = flexible ? 2 : 4;
+    long long launched = 0;
     while (true) {
         for (int m = 0; m < chunk; ++m) {
             launch_dir(rb[ri], z, c->p[pi], c->p[1 - pi]);
@@ -657,14 +675,51 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
         if (launched > cap) return fail(c, KVS_EDEVICE, "CG: iteration cap passed without a stop flag");
         chunk = std::min(chunk * 2, flexible ? 8 : 64);
     }
+    return KVS_OK;
+    };
+    {
+        const kvs_status ist = iterate();
+        if (ist != KVS_OK) return ist;
+    }
     // b = 0 gives phi = 0, also when a warm start began from an earlier phi
     if (warm && c->cgs_host->bb == 0.0) CG_HIP(hipMemsetAsync(c->phi, 0, sizeof(double) * c->N, c->stream));
     // Launches after the stop flag return at once; the host-side flip of pi
-    // may then be off by those, which is harmless: the next solve starts with
-    // beta = 0, which rebuilds the direction from r alone.
+    // may then be off by those, which is harmless: the next solve (or restart)
+    // starts with beta = 0, which rebuilds the direction from z alone.
 
-    hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, part, npart);
-    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3, (int)FIN_TRUE, c->cgs);
+    // Confirmation on the true residual (always for the flexible PCG, whose
+    // recursive residual can drift from the true one when the preconditioner
+    // changes between iterations; on request for CG / Jacobi-PCG): when the
+    // recursive residual met tol but ||-b - A phi|| / ||b|| did not, restart
+    // from the true residual and continue, counting iterations on.
+    const bool confirm = (flexible || o->confirm_true) && o->fixed_iters <= 0;
+    for (int restarts = 0;; ++restarts) {
+        hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, part, npart);
+        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3, (int)FIN_TRUE,
+                           c->cgs);
+        CG_HIP(hipGetLastError());
+        if (!confirm) break;
+        CG_HIP(hipMemcpyAsync(c->cgs_host, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
+        CG_HIP(hipStreamSynchronize(c->stream));
+        const CgState& h = *c->cgs_host;
+        if (h.status != KVS_OK || h.bb == 0.0 || !(h.relres_true2 >= h.tol2) || h.iters >= h.max_iter ||
+            restarts >= 8)
+            break;
+        hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, rb[ri], 1, part, npart);
+        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3,
+                           (int)FIN_RESTART, c->cgs);
+        if (flexible) {
+            const UnetDots dots{nullptr, part, npart};
+            int nbo = 0;
+            CG_HIP(kvs_unet_precondition(c->net, rb[ri], z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop,
+                                         c->stream, &dots, &nbo));
+            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbo, npart, 3,
+                               (int)FIN_FZ0, c->cgs);
+        }
+        CG_HIP(hipGetLastError());
+        const kvs_status ist = iterate();
+        if (ist != KVS_OK) return ist;
+    }
     const int status = c->cgs_host->status;
     if (status != KVS_EBREAKDOWN) {
         if (c->prec == KVS_FP32)

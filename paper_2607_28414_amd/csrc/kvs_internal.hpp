@@ -186,10 +186,13 @@ struct kvs_batch {
     int64_t trace_cap = 0, trace_steps = 0;
     std::vector<double> host_traces;  // host copy of the traces, valid while
     bool host_traces_valid = false;   // no step, reset or probe change happened
-    // cached graph for (start step, nsteps, first trace slot)
+    // cached graph for (start step, nsteps, first trace slot) and the per-step
+    // force switch it was captured with (a step launches the force-reading
+    // kernel when any instance's envelope is non-zero there)
     hipGraphExec_t graph = nullptr;
     bool graph_valid = false;
     int64_t graph_start = -1, graph_steps = 0, graph_trace0 = -1;
+    std::vector<uint8_t> graph_force;
 };
 
 // ---- launchers (kvs_step.hip) -------------------------------------------

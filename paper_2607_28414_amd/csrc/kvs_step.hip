@@ -876,13 +876,27 @@ void launch_batch_step(kvs_batch* b, long long n, int parity) {
     }
 }
 
+// Per step of the run starting at b->step: 1 when any instance's envelope is
+// non-zero there (that step launches the kernel that reads f_S).
+std::vector<uint8_t> batch_force_mask(const kvs_batch* b, int64_t nsteps) {
+    std::vector<uint8_t> m((size_t)nsteps, 0);
+    for (int64_t q = 0; q < nsteps; ++q) {
+        const int64_t n = b->step + q;
+        for (const kvs_ctx* c : b->inst)
+            if (n < (int64_t)c->env.size() && c->env[(size_t)n] != 0.0) {
+                m[(size_t)q] = 1;
+                break;
+            }
+    }
+    return m;
+}
+
 template <typename T>
-hipError_t capture_t(kvs_batch* b, int64_t nsteps) {
+hipError_t capture_t(kvs_batch* b, int64_t nsteps, const std::vector<uint8_t>& force_mask) {
     const int np = (int)b->probe_inst.size();
     for (int64_t q = 0; q < nsteps; ++q) {
         const int64_t n = b->step + q;
-        bool force = false;
-        for (kvs_ctx* c : b->inst) force = force || (n < (int64_t)c->env.size() && c->env[(size_t)n] != 0.0);
+        const bool force = force_mask[(size_t)q] != 0;
         const int parity = (int)(q & 1);
         if (b->viscous)
             force ? launch_batch_step<T, true, true>(b, n, parity) : launch_batch_step<T, true, false>(b, n, parity);
@@ -918,10 +932,12 @@ hipError_t kvs_batch_prepare(kvs_batch* b) {
 
 hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
     // Replay the cached graph when it was captured for the same start step,
-    // step count and trace slot (the parameter table it reads was refreshed
-    // in place by kvs_batch_prepare); otherwise capture a new one.
+    // step count, trace slot and per-step force switch (the parameter table
+    // and envelopes it reads were refreshed in place by kvs_batch_prepare);
+    // otherwise capture a new one.
+    std::vector<uint8_t> force_mask = batch_force_mask(b, nsteps);
     const bool hit = b->graph_valid && b->graph && b->graph_start == b->step && b->graph_steps == nsteps &&
-                     b->graph_trace0 == b->trace_steps;
+                     b->graph_trace0 == b->trace_steps && b->graph_force == force_mask;
     hipError_t e = hipSuccess;
     if (!hit) {
         if (b->graph) (void)hipGraphExecDestroy(b->graph);
@@ -930,7 +946,8 @@ hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t le = b->prec == KVS_FP32 ? capture_t<float>(b, nsteps) : capture_t<double>(b, nsteps);
+            const hipError_t le = b->prec == KVS_FP32 ? capture_t<float>(b, nsteps, force_mask)
+                                                      : capture_t<double>(b, nsteps, force_mask);
             e = hipStreamEndCapture(b->stream, &graph);
             if (e == hipSuccess) e = le;
         }
@@ -941,6 +958,7 @@ hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
         b->graph_start = b->step;
         b->graph_steps = nsteps;
         b->graph_trace0 = b->trace_steps;
+        b->graph_force.swap(force_mask);
     }
     return hipGraphLaunch(b->graph, b->stream);
 }

@@ -41,7 +41,7 @@ class kvs_opts(C.Structure):
 
 class kvs_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precond", C.c_int32),
-                ("fixed_iters", C.c_int64), ("warm_start", C.c_int32)]
+                ("fixed_iters", C.c_int64), ("warm_start", C.c_int32), ("confirm_true", C.c_int32)]
 
 
 class kvs_solve_report(C.Structure):
@@ -276,8 +276,9 @@ def kvs_set_envelope(ctx, g):
 
 
 def kvs_project(ctx, tol=1e-8, max_iter=10000, precond=KVS_PC_JACOBI, fixed_iters=0, warm_start=False,
-                raise_on_status=True):
-    o = kvs_solve_opts(float(tol), int(max_iter), int(precond), int(fixed_iters), int(bool(warm_start)))
+                raise_on_status=True, confirm_true=False):
+    o = kvs_solve_opts(float(tol), int(max_iter), int(precond), int(fixed_iters), int(bool(warm_start)),
+                       int(bool(confirm_true)))
     rep = kvs_solve_report()
     st = lib().kvs_project(ctx, C.byref(o), C.byref(rep))
     if raise_on_status:

@@ -175,3 +175,36 @@ def test_every_batch_tile_shape_matches_oracle(kvs):
                                 sponge_cells=L_SPONGE, sigma_max=800.0)
         for v, tr in results.items():
             assert rel_l2(tr[i], tr_o[:, :, 0]) < 2e-5, (v, i)
+
+
+def test_batch_rerun_with_changed_envelope_matches_oracle(kvs):
+    """A run, a reset, a longer push on one instance and a run of the same
+    length from the same step: the second run must not replay the graph of
+    the first (its steps past the old push read no force), so every
+    instance matches the oracle with its new envelope (FP32 bar); a third
+    run with the envelope switched off entirely matches too."""
+    say("case batch rerun with a changed envelope")
+    b, info = make_batch(kvs, 1)
+    try:
+        kvs.kvs_batch_step(b, NSTEPS)
+        kvs.kvs_batch_reset(b)
+        grid, G, eta, FS_o, dt, env, probes = info[1]
+        long_env = np.ones(len(env) + 25)
+        kvs.kvs_set_envelope(kvs.kvs_batch_instance(b, 1), long_env)
+        kvs.kvs_batch_step(b, NSTEPS)
+        second = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+        kvs.kvs_batch_reset(b)
+        for i in range(len(info)):
+            kvs.kvs_set_envelope(kvs.kvs_batch_instance(b, i), [])
+        kvs.kvs_batch_step(b, NSTEPS)
+        third = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    for i, (grid, G, eta, FS_o, dt, env, probes) in enumerate(info):
+        e = long_env if i == 1 else env
+        _, _, tr_o = oracle.run(grid, G, 1000.0, eta, dt, NSTEPS, FS=FS_o, env=e, probes=probes, comp=2,
+                                sponge_cells=L_SPONGE, sigma_max=800.0)
+        err = rel_l2(second[i], tr_o[:, :, 0])
+        say(f"instance {i}: rel L2 {err:.2e} (push {len(e)} steps)")
+        assert err < 2e-5, (i, err)
+        assert not third[i].any(), i
