@@ -476,6 +476,39 @@ kvs_status kvs_set_step_tuning(kvs_ctx* ctx, int32_t v, int32_t zchunk, int32_t 
 kvs_status kvs_autotune_step(kvs_ctx* ctx, int32_t trial_steps, int32_t* chosen, double* ms_per_launch,
                              int32_t cap);
 
+/* ---- projection without allocation ------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * projection of kvs_project (b = div F, CG or Jacobi-PCG on A phi = -b,
+ * f_S = F - grad phi, FP64 throughout) on caller-owned device buffers, with
+ * the CG vectors, block partials and control block in a fixed device array
+ * of KVS_NOALLOC_SCRATCH_BYTES built into the library (one per device, kept
+ * until the process ends).  No hipMalloc, hipFree or event is created.
+ *   grid   sizes and spacings as for kvs_create; the grid must fit the array:
+ *          about 4 * 8 B per cell, so at most ~2.1e6 cells (129^3); larger
+ *          grids give KVS_EINVAL with a message naming the sizes.
+ *   F      device, 3N doubles [3][nz][ny][nx], read.
+ *   phi    device, N doubles: the potential (written); with
+ *          opts->warm_start != 0 also the initial guess (its outer layer is
+ *          set to 0 first).
+ *   FS     device, 3N doubles: f_S (written, 0 on the outer layer).
+ *   opts   as for kvs_project (NULL: tol 1e-8, max_iter 10000, Jacobi-PCG);
+ *          precond must be KVS_PC_NONE or KVS_PC_JACOBI (else KVS_EINVAL);
+ *          fixed_iters and confirm_true as there.
+ *   device HIP device ordinal (made current); stream: hipStream_t or NULL
+ *          (the null stream); the call returns after the stream's work of
+ *          the projection is done (it polls a device flag, as kvs_project).
+ *   report may be NULL; ms is host wall time.
+ * Returns the solve status as kvs_project does.  Calls on one device share
+ * the array, so calls that overlap on one device (other threads, other
+ * streams) race and must be serialised by the caller.  Error text:
+ * kvs_noalloc_last_error() (per thread). */
+#define KVS_NOALLOC_SCRATCH_BYTES (66u << 20)
+kvs_status kvs_project_noalloc(const kvs_grid* grid, const double* F, double* phi, double* FS,
+                               const kvs_solve_opts* opts, int32_t device, void* stream, kvs_solve_report* report);
+const char* kvs_noalloc_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

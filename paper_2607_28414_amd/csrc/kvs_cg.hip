@@ -28,7 +28,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <mutex>
+#include <string>
 
 #include "kvs_internal.hpp"
 #include "kvs_tiling.hpp"
@@ -535,8 +539,16 @@ CgGeom make_geom(const kvs_grid& gr) {
 
 int nblocks(const CgGeom& g) { return g.gx * g.gy * g.gz; }
 
-kvs_status fail(kvs_ctx* c, kvs_status s, const std::string& msg) {
-    c->err = msg;
+// Error text of the projection driver: a fixed message or a HIP error
+// (the text of a HIP error is a static string); no allocation.
+struct CgErr {
+    const char* what = nullptr;
+    const char* hip = nullptr;
+};
+
+kvs_status cg_fail(CgErr& e, kvs_status s, const char* what, const char* hip = nullptr) {
+    e.what = what;
+    e.hip = hip;
     return s;
 }
 
@@ -550,25 +562,68 @@ int64_t kvs_cg_partials_needed(const kvs_grid& gr) {
                              kvs_unet_out_blocks(gr));
 }
 
-#define CG_HIP(call)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess) return fail(c, KVS_EDEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+#define CG_HIP(call)                                                      \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) return cg_fail(err, KVS_EDEVICE, #call, hipGetErrorString(e_)); \
     } while (0)
 
-kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep) {
-    const CgGeom g = make_geom(c->grid);
+namespace {
+
+// One projection on explicit buffers: b = div F, the CG / Jacobi-PCG /
+// flexible-PCG solve of A phi = -b, f_S = F - grad phi into FS (FP32 or FP64),
+// the FP64 true residual.  Every buffer belongs to the caller; nothing is
+// allocated here.  phi is the initial guess when B.warm (its outer layer must
+// be 0), else it is cleared.  The outer layer of FS is not written.
+struct CgBuffers {
+    kvs_grid grid;
+    hipStream_t stream;
+    const double* F;
+    double* phi;
+    double* r;
+    double* r2;  // flexible PCG only: the previous residual
+    double* p[2];
+    double* Ap;  // flexible PCG: the preconditioned residual z
+    double* partials;
+    int npart;
+    CgState* cgs;       // device control block
+    CgState* cgs_host;  // host mirror (pinned or not)
+    void* FS;
+    int fs_fp32;
+    kvs_unet* net;
+    bool warm;
+    bool use_events;  // time with HIP events (else with the host clock)
+};
+
+__global__ void fill_zero_kernel(double* a, long long n) {
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        a[q] = 0.0;
+}
+
+hipError_t fill_zero(double* a, long long n, hipStream_t s) {
+    const long long b = std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)std::max<long long>(b, 1)), dim3(256), 0, s, a, n);
+    return hipGetLastError();
+}
+
+kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_report* rep, CgErr& err) {
+    const CgGeom g = make_geom(B.grid);
     const int nb = nblocks(g);
     const dim3 blk(64, CBY);
-    double* part = c->partials;
-    const int npart = (int)c->npart;
+    double* part = B.partials;
+    const int npart = B.npart;
+    hipStream_t stream = B.stream;
 
-    hipEvent_t e0, e1;
-    CG_HIP(hipEventCreate(&e0));
-    CG_HIP(hipEventCreate(&e1));
-    CG_HIP(hipEventRecord(e0, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (B.use_events) {
+        CG_HIP(hipEventCreate(&e0));
+        CG_HIP(hipEventCreate(&e1));
+        CG_HIP(hipEventRecord(e0, stream));
+    }
 
     const bool flexible = o->precond == KVS_PC_UNET;
+    if (flexible && (!B.net || !B.r2)) return cg_fail(err, KVS_ESTATE, "flexible PCG needs a network and a second residual buffer");
     CgState init{};
     init.tol2 = o->tol * o->tol;
     init.max_iter = o->max_iter;
@@ -576,15 +631,15 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     init.jacobi = o->precond == KVS_PC_JACOBI ? 1 : 0;
     init.flexible = flexible ? 1 : 0;
     init.dinv = g.dinv;
-    init.h2 = c->grid.hx * c->grid.hx;
+    init.h2 = B.grid.hx * B.grid.hx;
     init.n_interior = (double)(g.nx - 2) * (double)(g.ny - 2) * (double)(g.nz - 2);
-    *c->cgs_host = init;
-    CG_HIP(hipMemcpyAsync(c->cgs, c->cgs_host, sizeof(CgState), hipMemcpyHostToDevice, c->stream));
-    const bool warm = o->warm_start && c->have_phi;
-    if (!warm) CG_HIP(hipMemsetAsync(c->phi, 0, sizeof(double) * c->N, c->stream));
+    *B.cgs_host = init;
+    CG_HIP(hipMemcpyAsync(B.cgs, B.cgs_host, sizeof(CgState), hipMemcpyHostToDevice, stream));
+    const bool warm = B.warm;
+    if (!warm) CG_HIP(fill_zero(B.phi, g.N, stream));
 
-    hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, c->r, warm ? 1 : 0, part, npart);
-    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3, (int)FIN_INIT, c->cgs);
+    hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, stream, g, B.F, B.phi, B.r, warm ? 1 : 0, part, npart);
+    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nb, npart, 3, (int)FIN_INIT, B.cgs);
     CG_HIP(hipGetLastError());
 
     const SweepShape shp = sweep_shape(g.nx);
@@ -603,86 +658,85 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     const dim3 sblk(64 * shp.wx, shp.by);
     auto launch_dir = [&](const double* r_in, const double* zf, const double* p_old, double* p_new) {
         if (shp.wx == 4)
-            hipLaunchKernelGGL((cg_dir_kernel<4, 4>), dim3(nbs), sblk, 0, c->stream, g, sg, r_in, zf, p_old, p_new,
-                               c->cgs, part, npart);
+            hipLaunchKernelGGL((cg_dir_kernel<4, 4>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
+                               B.cgs, part, npart);
         else if (shp.wx == 2)
-            hipLaunchKernelGGL((cg_dir_kernel<2, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, r_in, zf, p_old, p_new,
-                               c->cgs, part, npart);
+            hipLaunchKernelGGL((cg_dir_kernel<2, 8>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
+                               B.cgs, part, npart);
         else
-            hipLaunchKernelGGL((cg_dir_kernel<1, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, r_in, zf, p_old, p_new,
-                               c->cgs, part, npart);
+            hipLaunchKernelGGL((cg_dir_kernel<1, 8>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
+                               B.cgs, part, npart);
     };
     auto launch_upd = [&](const double* r_in, double* r_out, const double* pv) {
         if (shp.wx == 4)
-            hipLaunchKernelGGL((cg_upd_kernel<4, 4>), dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, r_in, r_out, pv,
-                               c->cgs, part, npart);
+            hipLaunchKernelGGL((cg_upd_kernel<4, 4>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
+                               B.cgs, part, npart);
         else if (shp.wx == 2)
-            hipLaunchKernelGGL((cg_upd_kernel<2, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, r_in, r_out, pv,
-                               c->cgs, part, npart);
+            hipLaunchKernelGGL((cg_upd_kernel<2, 8>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
+                               B.cgs, part, npart);
         else
-            hipLaunchKernelGGL((cg_upd_kernel<1, 8>), dim3(nbs), sblk, 0, c->stream, g, sg, c->phi, r_in, r_out, pv,
-                               c->cgs, part, npart);
+            hipLaunchKernelGGL((cg_upd_kernel<1, 8>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
+                               B.cgs, part, npart);
     };
     int pi = 0;  // p[pi] holds the current search direction
     const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
-    double* z = c->Ap;  // flexible PCG: the preconditioned residual
-    const int* stop = &c->cgs->done;
+    double* z = B.Ap;  // flexible PCG: the preconditioned residual
+    const int* stop = &B.cgs->done;
     // flexible PCG keeps the previous residual for beta: the update writes
     // the new residual into the other buffer (rb[ri] is the current one)
-    if (flexible && !c->r2) CG_HIP(hipMalloc(&c->r2, sizeof(double) * c->N));
-    double* rb[2] = {c->r, flexible ? c->r2 : c->r};
+    double* rb[2] = {B.r, flexible ? B.r2 : B.r};
     int ri = 0;
     if (flexible) {
         // z = U(r) and the partial sums of z.r from the network's output kernel
         const UnetDots dots{nullptr, part, npart};
         int nbo = 0;
-        CG_HIP(kvs_unet_precondition(c->net, rb[0], z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop, c->stream,
-                                     &dots, &nbo));
-        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbo, npart, 3, (int)FIN_FZ0,
-                           c->cgs);
+        CG_HIP(kvs_unet_precondition(B.net, rb[0], z, B.grid, &B.cgs->net_in, &B.cgs->net_out, stop, stream, &dots,
+                                     &nbo));
+        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbo, npart, 3, (int)FIN_FZ0,
+                           B.cgs);
         CG_HIP(hipGetLastError());
     }
     // Iterate until the device sets the stop flag (tolerance on the recursive
     // residual, max_iter, fixed_iters or a breakdown).
     auto iterate = [&]() -> kvs_status {
-    int chunk = flexible ? 2 : 4;
-    long long launched = 0;
-    while (true) {
-        for (int m = 0; m < chunk; ++m) {
-            launch_dir(rb[ri], z, c->p[pi], c->p[1 - pi]);
-            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 1, (int)FIN_ALPHA,
-                               c->cgs);
-            launch_upd(rb[ri], rb[1 - ri], c->p[1 - pi]);
-            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbs, npart, 2, (int)FIN_BETA,
-                               c->cgs);
-            if (flexible) {
-                // z = U(r_new) with the partial sums of z.r_new, z.r_old, r_new.r_old
-                const UnetDots dots{rb[ri], part, npart};
-                int nbo = 0;
-                CG_HIP(kvs_unet_precondition(c->net, rb[1 - ri], z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop,
-                                             c->stream, &dots, &nbo));
-                hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbo, npart, 3,
-                                   (int)FIN_FBETA, c->cgs);
-                ri = 1 - ri;
+        int chunk = flexible ? 2 : 4;
+        long long launched = 0;
+        while (true) {
+            for (int m = 0; m < chunk; ++m) {
+                launch_dir(rb[ri], z, B.p[pi], B.p[1 - pi]);
+                hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbs, npart, 1,
+                                   (int)FIN_ALPHA, B.cgs);
+                launch_upd(rb[ri], rb[1 - ri], B.p[1 - pi]);
+                hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbs, npart, 2,
+                                   (int)FIN_BETA, B.cgs);
+                if (flexible) {
+                    // z = U(r_new) with the partial sums of z.r_new, z.r_old, r_new.r_old
+                    const UnetDots dots{rb[ri], part, npart};
+                    int nbo = 0;
+                    CG_HIP(kvs_unet_precondition(B.net, rb[1 - ri], z, B.grid, &B.cgs->net_in, &B.cgs->net_out, stop,
+                                                 stream, &dots, &nbo));
+                    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbo, npart, 3,
+                                       (int)FIN_FBETA, B.cgs);
+                    ri = 1 - ri;
+                }
+                pi = 1 - pi;
             }
-            pi = 1 - pi;
+            CG_HIP(hipGetLastError());
+            launched += chunk;
+            CG_HIP(hipMemcpyAsync(B.cgs_host, B.cgs, sizeof(CgState), hipMemcpyDeviceToHost, stream));
+            CG_HIP(hipStreamSynchronize(stream));
+            if (B.cgs_host->done) break;
+            if (launched > cap) return cg_fail(err, KVS_EDEVICE, "CG: iteration cap passed without a stop flag");
+            chunk = std::min(chunk * 2, flexible ? 8 : 64);
         }
-        CG_HIP(hipGetLastError());
-        launched += chunk;
-        CG_HIP(hipMemcpyAsync(c->cgs_host, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-        CG_HIP(hipStreamSynchronize(c->stream));
-        if (c->cgs_host->done) break;
-        if (launched > cap) return fail(c, KVS_EDEVICE, "CG: iteration cap passed without a stop flag");
-        chunk = std::min(chunk * 2, flexible ? 8 : 64);
-    }
-    return KVS_OK;
+        return KVS_OK;
     };
     {
         const kvs_status ist = iterate();
         if (ist != KVS_OK) return ist;
     }
     // b = 0 gives phi = 0, also when a warm start began from an earlier phi
-    if (warm && c->cgs_host->bb == 0.0) CG_HIP(hipMemsetAsync(c->phi, 0, sizeof(double) * c->N, c->stream));
+    if (warm && B.cgs_host->bb == 0.0) CG_HIP(fill_zero(B.phi, g.N, stream));
     // Launches after the stop flag return at once; the host-side flip of pi
     // may then be off by those, which is harmless: the next solve (or restart)
     // starts with beta = 0, which rebuilds the direction from z alone.
@@ -694,54 +748,54 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     // from the true residual and continue, counting iterations on.
     const bool confirm = (flexible || o->confirm_true) && o->fixed_iters <= 0;
     for (int restarts = 0;; ++restarts) {
-        hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, part, npart);
-        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3, (int)FIN_TRUE,
-                           c->cgs);
+        hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb), blk, 0, stream, g, B.F, B.phi, part, npart);
+        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nb, npart, 3, (int)FIN_TRUE,
+                           B.cgs);
         CG_HIP(hipGetLastError());
         if (!confirm) break;
-        CG_HIP(hipMemcpyAsync(c->cgs_host, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-        CG_HIP(hipStreamSynchronize(c->stream));
-        const CgState& h = *c->cgs_host;
+        CG_HIP(hipMemcpyAsync(B.cgs_host, B.cgs, sizeof(CgState), hipMemcpyDeviceToHost, stream));
+        CG_HIP(hipStreamSynchronize(stream));
+        const CgState& h = *B.cgs_host;
         if (h.status != KVS_OK || h.bb == 0.0 || !(h.relres_true2 >= h.tol2) || h.iters >= h.max_iter ||
             restarts >= 8)
             break;
-        hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, c->stream, g, c->F, c->phi, rb[ri], 1, part, npart);
-        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nb, npart, 3,
-                           (int)FIN_RESTART, c->cgs);
+        hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, stream, g, B.F, B.phi, rb[ri], 1, part, npart);
+        hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nb, npart, 3, (int)FIN_RESTART,
+                           B.cgs);
         if (flexible) {
             const UnetDots dots{nullptr, part, npart};
             int nbo = 0;
-            CG_HIP(kvs_unet_precondition(c->net, rb[ri], z, c->grid, &c->cgs->net_in, &c->cgs->net_out, stop,
-                                         c->stream, &dots, &nbo));
-            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, c->stream, part, nbo, npart, 3,
-                               (int)FIN_FZ0, c->cgs);
+            CG_HIP(kvs_unet_precondition(B.net, rb[ri], z, B.grid, &B.cgs->net_in, &B.cgs->net_out, stop, stream,
+                                         &dots, &nbo));
+            hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbo, npart, 3, (int)FIN_FZ0,
+                               B.cgs);
         }
         CG_HIP(hipGetLastError());
         const kvs_status ist = iterate();
         if (ist != KVS_OK) return ist;
     }
-    const int status = c->cgs_host->status;
+    const int status = B.cgs_host->status;
     if (status != KVS_EBREAKDOWN) {
-        if (c->prec == KVS_FP32)
-            hipLaunchKernelGGL(grad_subtract_kernel<float>, dim3(nb), blk, 0, c->stream, g, c->F, c->phi,
-                               static_cast<float*>(c->FS));
+        if (B.fs_fp32)
+            hipLaunchKernelGGL(grad_subtract_kernel<float>, dim3(nb), blk, 0, stream, g, B.F, B.phi,
+                               static_cast<float*>(B.FS));
         else
-            hipLaunchKernelGGL(grad_subtract_kernel<double>, dim3(nb), blk, 0, c->stream, g, c->F, c->phi,
-                               static_cast<double*>(c->FS));
+            hipLaunchKernelGGL(grad_subtract_kernel<double>, dim3(nb), blk, 0, stream, g, B.F, B.phi,
+                               static_cast<double*>(B.FS));
     }
     CG_HIP(hipGetLastError());
-    CG_HIP(hipEventRecord(e1, c->stream));
-    CG_HIP(hipMemcpyAsync(c->cgs_host, c->cgs, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-    CG_HIP(hipStreamSynchronize(c->stream));
+    if (B.use_events) CG_HIP(hipEventRecord(e1, stream));
+    CG_HIP(hipMemcpyAsync(B.cgs_host, B.cgs, sizeof(CgState), hipMemcpyDeviceToHost, stream));
+    CG_HIP(hipStreamSynchronize(stream));
     float ms = 0.f;
-    CG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-
-    const CgState& s = *c->cgs_host;
-    c->have_phi = true;
-    if (s.status != KVS_EBREAKDOWN) c->fs_current = true;
-    c->last_fallbacks = s.fallbacks;
+    if (B.use_events) {
+        CG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } else {
+        ms = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    const CgState& s = *B.cgs_host;
     if (rep) {
         rep->iters = s.iters;
         rep->relres_recursive = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
@@ -749,8 +803,208 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
         rep->ms = ms;
         rep->status = s.status;
     }
-    if (s.status != KVS_OK)
-        c->err = s.status == KVS_ENOTCONV ? "projection: CG reached max_iter above tolerance"
-                                          : "projection: CG breakdown (p.Ap <= 0 or non-finite inner product)";
+    if (s.status == KVS_ENOTCONV) return cg_fail(err, KVS_ENOTCONV, "projection: CG reached max_iter above tolerance");
+    if (s.status == KVS_EBREAKDOWN)
+        return cg_fail(err, KVS_EBREAKDOWN, "projection: CG breakdown (p.Ap <= 0 or non-finite inner product)");
     return (kvs_status)s.status;
 }
+
+std::string cg_message(const CgErr& e) {
+    std::string m = e.what ? e.what : "";
+    if (e.hip) m += std::string(": ") + e.hip;
+    return m;
+}
+
+}  // namespace
+
+kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep) {
+    if (o->precond == KVS_PC_UNET && !c->r2) {
+        const hipError_t e = hipMalloc(&c->r2, sizeof(double) * c->N);
+        if (e != hipSuccess) {
+            c->err = std::string("hipMalloc (second residual): ") + hipGetErrorString(e);
+            return KVS_ENOMEM;
+        }
+    }
+    CgBuffers B{};
+    B.grid = c->grid;
+    B.stream = c->stream;
+    B.F = c->F;
+    B.phi = c->phi;
+    B.r = c->r;
+    B.r2 = c->r2;
+    B.p[0] = c->p[0];
+    B.p[1] = c->p[1];
+    B.Ap = c->Ap;
+    B.partials = c->partials;
+    B.npart = (int)c->npart;
+    B.cgs = c->cgs;
+    B.cgs_host = c->cgs_host;
+    B.FS = c->FS;
+    B.fs_fp32 = c->prec == KVS_FP32;
+    B.net = c->net;
+    B.warm = o->warm_start && c->have_phi;
+    B.use_events = true;
+    CgErr err;
+    const kvs_status st = cg_project(B, o, rep, err);
+    if (st == KVS_EDEVICE && err.hip) {  // a HIP failure: the solve did not finish
+        c->err = cg_message(err);
+        return st;
+    }
+    if (st != KVS_OK && st != KVS_ENOTCONV && st != KVS_EBREAKDOWN) {
+        c->err = cg_message(err);
+        return st;
+    }
+    const CgState& s = *c->cgs_host;
+    c->have_phi = true;
+    if (s.status != KVS_EBREAKDOWN) c->fs_current = true;
+    c->last_fallbacks = s.fallbacks;
+    if (st != KVS_OK) c->err = cg_message(err);
+    return st;
+}
+
+// ---- projection without allocation ------------------------------------------
+//
+// The CG work vectors, block partials and control block of
+// kvs_project_noalloc live in one file-scope device array, `scratch`, of
+// KVS_NOALLOC_SCRATCH_BYTES.  Each device holds its own copy; its address is
+// taken once per device with hipGetSymbolAddress (the array's name is a host
+// stand-in, never a device pointer) and every later use goes through that
+// address.  Calls on one device share the array: calls that overlap on one
+// device race.  Layout: CgState | partials (3 npart) | r | p0 | p1 | Ap.
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[KVS_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+thread_local char g_noalloc_err[256] = "";
+
+kvs_status noalloc_fail(kvs_status s, const char* what, const char* detail = nullptr) {
+    std::snprintf(g_noalloc_err, sizeof(g_noalloc_err), "%s%s%s", what, detail ? ": " : "", detail ? detail : "");
+    return s;
+}
+
+// The device address of this device's scratch array (looked up once per
+// device with the device current).
+kvs_status scratch_address(int device, unsigned char** out) {
+    if (device < 0 || device >= kMaxDevices) return noalloc_fail(KVS_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return noalloc_fail(KVS_EDEVICE, "hipGetSymbolAddress(scratch)", hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+    return KVS_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of scratch a projection of `g` needs.
+size_t noalloc_bytes(const kvs_grid& g, int64_t npart) {
+    const size_t N = (size_t)g.nx * (size_t)g.ny * (size_t)g.nz;
+    return align256(sizeof(CgState)) + align256(3 * (size_t)npart * sizeof(double)) + 4 * align256(N * sizeof(double));
+}
+
+// Zero the outer layer of `ncomp` consecutive scalar fields of double.
+__global__ void zero_outer_kernel(double* f, int nx, int ny, int nz, int ncomp) {
+    const long long N = (long long)nx * ny * nz;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < N * ncomp;
+         q += (long long)gridDim.x * blockDim.x) {
+        const long long c = q % N;
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((long long)nx * ny));
+        if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1 || k == 0 || k == nz - 1) f[q] = 0.0;
+    }
+}
+
+}  // namespace
+
+kvs_status kvs_project_noalloc(const kvs_grid* grid, const double* F, double* phi, double* FS,
+                               const kvs_solve_opts* opts, int32_t device, void* stream, kvs_solve_report* rep) {
+    g_noalloc_err[0] = 0;
+    if (!grid || !F || !phi || !FS) return noalloc_fail(KVS_EINVAL, "grid, F, phi and FS must be non-NULL");
+    const kvs_grid& g = *grid;
+    if (g.nx < 3 || g.ny < 3 || g.nz < 3 || !(g.hx > 0) || !(g.hy > 0) || !(g.hz > 0) || !std::isfinite(g.hx) ||
+        !std::isfinite(g.hy) || !std::isfinite(g.hz))
+        return noalloc_fail(KVS_EINVAL, "grid needs n >= 3 per axis and finite spacings > 0");
+    kvs_solve_opts o{};
+    o.tol = 1e-8;
+    o.max_iter = 10000;
+    o.precond = KVS_PC_JACOBI;
+    if (opts) o = *opts;
+    if (o.fixed_iters < 0) return noalloc_fail(KVS_EINVAL, "fixed_iters < 0");
+    if (o.fixed_iters == 0 && !(o.tol > 0.0 && std::isfinite(o.tol))) return noalloc_fail(KVS_EINVAL, "tol must be > 0");
+    if (o.max_iter <= 0) return noalloc_fail(KVS_EINVAL, "max_iter must be > 0");
+    if (o.precond != KVS_PC_NONE && o.precond != KVS_PC_JACOBI)
+        return noalloc_fail(KVS_EINVAL, "the allocation-free projection runs CG or Jacobi-PCG only");
+    const int64_t npart = std::max<int64_t>(kvs_cg_partials_needed(g), 2048);
+    const size_t need = noalloc_bytes(g, npart);
+    if ((double)g.nx * (double)g.ny * (double)g.nz > 2.0e9 || need > (size_t)KVS_NOALLOC_SCRATCH_BYTES) {
+        char detail[160];
+        std::snprintf(detail, sizeof(detail), "grid %lldx%lldx%lld needs %zu bytes of scratch, the maximum is %zu",
+                      (long long)g.nx, (long long)g.ny, (long long)g.nz, need, (size_t)KVS_NOALLOC_SCRATCH_BYTES);
+        return noalloc_fail(KVS_EINVAL, "grid too large for the allocation-free projection", detail);
+    }
+    {
+        const hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess) return noalloc_fail(KVS_EDEVICE, "hipSetDevice", hipGetErrorString(e));
+    }
+    unsigned char* base = nullptr;
+    {
+        const kvs_status st = scratch_address(device, &base);
+        if (st != KVS_OK) return st;
+    }
+    const size_t N = (size_t)g.nx * (size_t)g.ny * (size_t)g.nz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* q = base + off;
+        off += align256(bytes);
+        return q;
+    };
+    CgState host_state{};
+    CgBuffers B{};
+    B.grid = g;
+    B.stream = static_cast<hipStream_t>(stream);
+    B.F = F;
+    B.phi = phi;
+    B.cgs = reinterpret_cast<CgState*>(take(sizeof(CgState)));
+    B.partials = reinterpret_cast<double*>(take(3 * (size_t)npart * sizeof(double)));
+    B.npart = (int)npart;
+    B.r = reinterpret_cast<double*>(take(N * sizeof(double)));
+    B.p[0] = reinterpret_cast<double*>(take(N * sizeof(double)));
+    B.p[1] = reinterpret_cast<double*>(take(N * sizeof(double)));
+    B.Ap = reinterpret_cast<double*>(take(N * sizeof(double)));
+    B.r2 = nullptr;
+    B.cgs_host = &host_state;
+    B.FS = FS;
+    B.fs_fp32 = 0;
+    B.net = nullptr;
+    B.warm = o.warm_start != 0;
+    B.use_events = false;
+    // The sweeps read the outer layer of r and of both directions (never
+    // written there, 0 in a context since its creation): the shared array
+    // holds whatever the last call left, so clear them on every call.
+    for (double* v : {B.r, B.p[0], B.p[1]}) {
+        const hipError_t e = fill_zero(v, (long long)N, B.stream);
+        if (e != hipSuccess) return noalloc_fail(KVS_EDEVICE, "fill_zero_kernel", hipGetErrorString(e));
+    }
+    // outer layers: phi (a warm start's guess) and FS are 0 there
+    const unsigned nbz = (unsigned)std::min<size_t>((3 * N + 255) / 256, 4096);
+    if (B.warm) hipLaunchKernelGGL(zero_outer_kernel, dim3(nbz), dim3(256), 0, B.stream, phi, (int)g.nx, (int)g.ny,
+                                   (int)g.nz, 1);
+    hipLaunchKernelGGL(zero_outer_kernel, dim3(nbz), dim3(256), 0, B.stream, FS, (int)g.nx, (int)g.ny, (int)g.nz, 3);
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return noalloc_fail(KVS_EDEVICE, "zero_outer_kernel", hipGetErrorString(e));
+    }
+    CgErr err;
+    const kvs_status st = cg_project(B, &o, rep, err);
+    if (st != KVS_OK) noalloc_fail(st, err.what ? err.what : "projection failed", err.hip);
+    return st;
+}
+
+const char* kvs_noalloc_last_error(void) { return g_noalloc_err; }

@@ -74,6 +74,9 @@ SIGNATURES = {
     "kvs_get_force": ([_P, _D], C.c_int),
     "kvs_set_envelope": ([_P, _D, C.c_int64], C.c_int),
     "kvs_project": ([_P, C.POINTER(kvs_solve_opts), C.POINTER(kvs_solve_report)], C.c_int),
+    "kvs_project_noalloc": ([C.POINTER(kvs_grid), C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(kvs_solve_opts),
+                             C.c_int32, C.c_void_p, C.POINTER(kvs_solve_report)], C.c_int),
+    "kvs_noalloc_last_error": ([], C.c_char_p),
     "kvs_set_projected_force": ([_P, _D], C.c_int),
     "kvs_set_preconditioner": ([_P, _P], C.c_int),
     "kvs_last_fallbacks": ([_P, _I64], C.c_int),
@@ -285,6 +288,29 @@ def kvs_project(ctx, tol=1e-8, max_iter=10000, precond=KVS_PC_JACOBI, fixed_iter
         _check(st, ctx)
     return dict(iters=rep.iters, relres_recursive=rep.relres_recursive, relres_true=rep.relres_true,
                 ms=rep.ms, status=rep.status, return_status=st)
+
+
+def kvs_project_noalloc(grid, F_ptr, phi_ptr, FS_ptr, tol=1e-8, max_iter=10000, precond=KVS_PC_JACOBI,
+                        fixed_iters=0, warm_start=False, confirm_true=False, device=0, stream=None,
+                        raise_on_status=True):
+    """Projection on caller-owned device buffers with the library's fixed
+    scratch array (no allocation): F (3N doubles) read, phi (N doubles) and
+    FS (3N doubles) written; addresses as integers (e.g. tensor.data_ptr())."""
+    nx, ny, nz, hx, hy, hz = grid
+    g = kvs_grid(int(nx), int(ny), int(nz), float(hx), float(hy), float(hz))
+    o = kvs_solve_opts(float(tol), int(max_iter), int(precond), int(fixed_iters), int(bool(warm_start)),
+                       int(bool(confirm_true)))
+    rep = kvs_solve_report()
+    st = lib().kvs_project_noalloc(C.byref(g), F_ptr, phi_ptr, FS_ptr, C.byref(o), int(device), stream or None,
+                                   C.byref(rep))
+    if raise_on_status and st != KVS_OK:
+        msg = lib().kvs_noalloc_last_error()
+        raise KvsError(st, msg.decode() if msg else "")
+    return dict(iters=rep.iters, relres_recursive=rep.relres_recursive, relres_true=rep.relres_true,
+                ms=rep.ms, status=rep.status, return_status=st)
+
+
+KVS_NOALLOC_SCRATCH_BYTES = 66 << 20
 
 
 def kvs_set_projected_force(ctx, FS):
