@@ -208,3 +208,48 @@ def test_batch_rerun_with_changed_envelope_matches_oracle(kvs):
         say(f"instance {i}: rel L2 {err:.2e} (push {len(e)} steps)")
         assert err < 2e-5, (i, err)
         assert not third[i].any(), i
+
+
+def test_batch_sweep_edges_96_and_160_match_oracle(kvs):
+    """Instances of the 64-instance sweep's shape with edges that are not
+    multiples of the tile width (96 and 160 cells: several x tiles with a
+    partial last one), in the sweep's launch configuration (autotuned tile
+    shape and z chunk, 8-cell sponge of default strength, 100 us push, dt =
+    0.4 x the stable limit): lateral-line u_z traces over 200 steps against
+    the oracle's run from the oracle's own projection, relative L2 within
+    2e-5 per instance."""
+    say("case batch edges 96 and 160")
+    h = 0.25e-3
+    draws = [(96, 10 ** (3 + 4 / 9), 0.7), (160, 10 ** (3 + 7 / 9), 1.2)]
+    grids = [(e, e, e, h, h, h) for e, _, _ in draws]
+    nsteps = 200
+    b = kvs.kvs_batch_create(grids, precision=1, sponge_cells=8, sponge_sigma_max=-1.0)
+    info = []
+    try:
+        for i, ((e, G, eta), grid) in enumerate(zip(draws, grids)):
+            ctx = kvs.kvs_batch_instance(b, i)
+            kvs.kvs_set_material_uniform(ctx, G, 1000.0, eta)
+            dt = 0.4 * kvs.kvs_stable_dt(ctx)
+            kvs.kvs_set_dt(ctx, dt)
+            env = np.ones(int(round(100e-6 / dt)))
+            kvs.kvs_set_envelope(ctx, env)
+            F = gaussian_push(grid, 1e-3, 4e-3, 1e4)
+            FS_o, _, rep_o = oracle.project(grid, F, tol=1e-8, jacobi=True)
+            kvs.kvs_set_projected_force(ctx, FS_o)
+            probes = x_line_probes(grid)
+            kvs.kvs_batch_set_probes(b, i, probes)
+            smax = kvs.kvs_sponge_sigma_max(ctx)
+            info.append((grid, G, eta, dt, env, FS_o, probes, smax))
+        kvs.kvs_batch_set_component(b, 2)
+        v, z, _ = kvs.kvs_batch_autotune(b, 3)
+        kvs.kvs_batch_step(b, nsteps)
+        traces = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    for i, (grid, G, eta, dt, env, FS_o, probes, smax) in enumerate(info):
+        assert smax == pytest.approx(oracle.default_sigma_max(grid, G, 1000.0, 8), rel=1e-13)
+        _, _, tr_o = oracle.run(grid, G, 1000.0, eta, dt, nsteps, FS=FS_o, env=env, probes=probes, comp=2,
+                                sponge_cells=8, sigma_max=smax)
+        err = rel_l2(traces[i], tr_o[:, :, 0])
+        say(f"edge {grid[0]}: tile variant {v}, z {z}, rel L2 {err:.2e}")
+        assert err < 2e-5, (grid[0], err)

@@ -169,6 +169,54 @@ def test_cfg2_full_size_traces_within_2e5(kvs, cfg2_oracle):
     assert err <= 2e-5
 
 
+def test_cfg2_full_length_traces_against_stored_oracle_run(kvs):
+    """The 256^3 inclusion workload over all 4000 steps in the benchmark's
+    launch configuration (force from device memory, the GPU's own Jacobi-PCG
+    projection to 1e-8, autotuned tile shape, all 256 lateral-line probes):
+    u_z traces of 32 of the probes against the oracle's own end-to-end FP64
+    run (tests/golden/make_cfg2.py), relative L2 within 2e-5 over the whole
+    run and within each 1000-step window; the stable dt, sponge strength,
+    push length and projection iteration count equal the oracle's."""
+    import os
+
+    import torch
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "cfg2_256_traces.npz"))
+    w = cfg2_inclusions_fp32(n=256)
+    say("case cfg2 256^3 full length (4000 steps) against the stored oracle run")
+    ctx = kvs.kvs_create(w.grid, precision=kvs.KVS_FP32, sponge_cells=w.sponge_cells, sponge_sigma_max=-1.0,
+                         stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        kvs.kvs_set_material(ctx, w.G, w.rho, w.eta)
+        dt = w.dt_factor * kvs.kvs_stable_dt(ctx)
+        kvs.kvs_set_dt(ctx, dt)
+        env = w.envelope_for(dt)
+        kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_set_probes(ctx, w.probes, w.comp)
+        variant, _ = kvs.kvs_autotune_step(ctx, 20)
+        F_dev = torch.from_numpy(np.ascontiguousarray(w.F)).to("cuda")
+        kvs.kvs_set_force_device(ctx, F_dev.data_ptr(), 0)
+        rep = kvs.kvs_project(ctx, tol=w.tol, max_iter=20000, precond=kvs.KVS_PC_JACOBI)
+        kvs.kvs_step(ctx, w.nsteps)
+        tr = kvs.kvs_read_traces(ctx, len(w.probes), 1)[:, :, 0]
+        smax = kvs.kvs_sponge_sigma_max(ctx)
+    finally:
+        kvs.kvs_destroy(ctx)
+    ref = gold["traces"]
+    got = tr[:, gold["probes"][:, 0]]
+    assert got.shape == ref.shape == (4000, 32)
+    assert dt == pytest.approx(float(gold["dt"]), rel=1e-13)
+    assert smax == pytest.approx(float(gold["sigma_max"]), rel=1e-13)
+    assert len(env) == int(gold["n_push"])
+    err = rel_l2(got, ref)
+    windows = [rel_l2(got[q:q + 1000], ref[q:q + 1000]) for q in range(0, 4000, 1000)]
+    say(f"cfg2 full length: variant {variant}, projection {rep['iters']} iterations (oracle "
+        f"{int(gold['projection_iters'])}), trace rel L2 {err:.3e}, per 1000 steps "
+        + ", ".join(f"{e:.2e}" for e in windows))
+    assert rep["iters"] == int(gold["projection_iters"])
+    assert err <= 2e-5
+    assert max(windows) <= 2e-5
+
+
 def test_fp32_heterogeneous_traces_within_2e5(kvs):
     """Inclusion workload physics at 64^3 (same h, push widths, dt rule and
     tolerance as the 256^3 case): FP32 state with FP64 projection against

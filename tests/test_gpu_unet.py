@@ -86,7 +86,10 @@ def test_network_forward_matches_oracle(kvs):
     err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
     say(f"forward rel L2 {err:.2e}")
     assert not z[0].any() and not z[:, 0].any() and np.isfinite(z).all()
-    assert err < 2e-2
+    # measured 2.2e-4: one-ulp BF16 flips of activations where the FP32 sums
+    # of the two sides straddle a rounding boundary; a wiring mistake in a
+    # skip or upsampling path moves z by far more than 2e-3
+    assert err < 2e-3
 
 
 @pytest.mark.parametrize("dims", [(70, 19, 23), (130, 9, 41), (5, 4, 3)])
@@ -135,9 +138,11 @@ def random_weights(rng, nbott=4, scale=1.0):
 
 def test_backward_matches_oracle(kvs):
     """Weight gradients of the GPU backward pass against the oracle's, which
-    rounds to BF16 at the same points; per layer within 2e-2 relative L2
-    (the residue is BF16 rounding flips of activation gradients where the
-    FP32 sums of the two sides straddle a rounding boundary)."""
+    rounds to BF16 at the same points; per layer within 5e-3 relative L2
+    (measured 2e-7 to 1.2e-3, largest for the pointwise projection that sees
+    every flip upstream of it: the residue is BF16 rounding flips of
+    activation gradients where the FP32 sums of the two sides straddle a
+    rounding boundary)."""
     import torch
     say("case unet backward")
     rng = np.random.default_rng(21)
@@ -164,7 +169,7 @@ def test_backward_matches_oracle(kvs):
         n = unet.layer_size(ci, co, dl)
         err = np.linalg.norm(g[off:off + n] - go[off:off + n]) / np.linalg.norm(go[off:off + n])
         say(f"layer {li} ({ci}->{co}): grad rel L2 {err:.2e}")
-        assert err < 2e-2, (li, err)
+        assert err < 5e-3, (li, err)
         off += n
 
 

@@ -168,11 +168,14 @@ QIBA_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "qiba_240x200x20
 
 
 def load_qiba():
-    """Per phantom: dict(G, dt, speed, lags, traces [steps][3 kept sensors])."""
+    """Per phantom: dict(G, dt, speed, lags, traces [steps][3 kept sensors]);
+    also the oracle projection's iteration count (load_qiba.projection_iters)."""
     phantoms, offsets, kept, cur = [], None, None, None
     for line in open(QIBA_GOLDEN):
         f = line.split()
-        if line.startswith("# offsets_m "):
+        if line.startswith("# projection_iters "):
+            load_qiba.projection_iters = int(f[2])
+        elif line.startswith("# offsets_m "):
             offsets = np.array([float(v) for v in f[2:]])
         elif line.startswith("# kept_sensors "):
             kept = [int(v) for v in f[2:]]
@@ -195,8 +198,9 @@ def test_qiba_phantoms_recover_shear_speed(kvs):
     push (Eq. gaussexc), 400 FP32 steps; the group speed from cross-correlated
     axial velocity traces at 4-14 mm lateral offsets is within 2 % of
     sqrt(G / rho) and within 1e-3 of the oracle's from the same estimator; the
-    stored oracle traces match to 1e-4 relative L2 (FP32 state, projections
-    to 1e-8 on both sides)."""
+    stored oracle traces match to 2e-5 relative L2 (FP32 state; the GPU
+    projection runs the oracle's iteration count at 1e-8, as the other parity
+    runs do, so that both sides subtract the same gradient up to rounding)."""
     from oracle.analysis import centred_velocity, group_speed_xcorr
     w = qiba_phantoms()
     offsets_g, kept, gold = load_qiba()
@@ -216,7 +220,7 @@ def test_qiba_phantoms_recover_shear_speed(kvs):
             dts.append(dt)
         ctx0 = kvs.kvs_batch_instance(b, 0)
         kvs.kvs_set_force(ctx0, w["F"])
-        rep = kvs.kvs_project(ctx0, tol=1e-8, max_iter=20000)
+        rep = kvs.kvs_project(ctx0, tol=1e-8, max_iter=20000, fixed_iters=load_qiba.projection_iters)
         for i in range(1, n):
             kvs.kvs_batch_share_projection(b, 0, i)
         kvs.kvs_batch_set_component(b, w["comp"])
@@ -232,7 +236,9 @@ def test_qiba_phantoms_recover_shear_speed(kvs):
         say(f"QIBA G {G:.0f} Pa: group speed {speed:.4f} m/s (cs {cs:.4f}, oracle {g['speed']:.4f})")
         assert abs(speed - cs) < 0.02 * cs
         assert abs(speed - g["speed"]) < 1e-3 * g["speed"]
-        assert rel_l2(traces[i][:, kept], g["traces"]) < 1e-4
+        err = rel_l2(traces[i][:, kept], g["traces"])
+        say(f"QIBA G {G:.0f} Pa: stored traces rel L2 {err:.2e}")
+        assert err < 2e-5
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
