@@ -48,8 +48,9 @@
  *   - "*_device" pointers are device memory owned by the caller, read
  *     asynchronously on the context's stream; the caller keeps them alive
  *     until kvs_synchronize() returns.
- *   - The context owns every device buffer it allocates (hipMalloc) and
- *     releases them in kvs_destroy().
+ *   - The context owns every device buffer it allocates (through the
+ *     allocator named in kvs_opts, else hipMalloc) and releases them in
+ *     kvs_destroy().
  *   - A context is not thread-safe; distinct contexts are independent.
  *     All GPU work of a context is ordered on its stream.
  */
@@ -92,6 +93,16 @@ typedef struct {
                                 the one-way amplitude factor through the ramp about 10^-1.5 */
     int32_t device;          /* HIP device ordinal */
     void* stream;            /* hipStream_t to run on, or NULL: the context creates its own */
+    /* Device-memory allocator for every buffer the context (or batch) owns, e.g. a framework's
+     * caching allocator; NULL (both) selects hipMalloc / hipFree.  alloc(bytes, alloc_user)
+     * returns device memory of the opts' device (NULL: KVS_ENOMEM); free(ptr, alloc_user) takes
+     * back exactly what alloc returned, on the creating thread's calls, after the library has
+     * synchronised its stream; every buffer is returned by kvs_destroy at the latest.  Must
+     * stay callable until then.  Only one of the two set: KVS_EINVAL.  The network of
+     * kvs_unet_create keeps its own buffers (hipMalloc). */
+    void* (*alloc)(size_t bytes, void* user);
+    void (*free)(void* ptr, void* user);
+    void* alloc_user;
 } kvs_opts;
 
 typedef struct {

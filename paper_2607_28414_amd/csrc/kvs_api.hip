@@ -57,8 +57,8 @@ void resolve_sigma(kvs_ctx* c, double cmax) {
 }
 
 template <typename P>
-void dfree(P*& p) {
-    if (p) (void)hipFree((void*)p);
+void dfree(const KvsMem& m, P*& p) {
+    m.put((void*)p);
     p = nullptr;
 }
 
@@ -67,30 +67,30 @@ void release(kvs_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (int b = 0; b < 2; ++b) {
-        dfree(c->u[b]);
-        dfree(c->w[b]);
-        dfree(c->p[b]);
+        dfree(c->mem, c->u[b]);
+        dfree(c->mem, c->w[b]);
+        dfree(c->mem, c->p[b]);
     }
-    dfree(c->G);
-    dfree(c->eta);
-    dfree(c->rho_t);
-    dfree(c->crho);
-    dfree(c->F);
-    dfree(c->FS);
-    dfree(c->phi);
-    dfree(c->r);
-    dfree(c->r2);
-    dfree(c->Ap);
-    dfree(c->partials);
-    dfree(c->cgs);
-    dfree(c->probe_cells);
-    dfree(c->traces);
-    dfree(c->peak);
-    dfree(c->arf_sum);
-    dfree(c->strain_K);
-    dfree(c->strain_peak);
-    dfree(c->pml_tab);
-    dfree(c->pml_mem);
+    dfree(c->mem, c->G);
+    dfree(c->mem, c->eta);
+    dfree(c->mem, c->rho_t);
+    dfree(c->mem, c->crho);
+    dfree(c->mem, c->F);
+    dfree(c->mem, c->FS);
+    dfree(c->mem, c->phi);
+    dfree(c->mem, c->r);
+    dfree(c->mem, c->r2);
+    dfree(c->mem, c->Ap);
+    dfree(c->mem, c->partials);
+    dfree(c->mem, c->cgs);
+    dfree(c->mem, c->probe_cells);
+    dfree(c->mem, c->traces);
+    dfree(c->mem, c->peak);
+    dfree(c->mem, c->arf_sum);
+    dfree(c->mem, c->strain_K);
+    dfree(c->mem, c->strain_peak);
+    dfree(c->mem, c->pml_tab);
+    dfree(c->mem, c->pml_mem);
     if (c->cgs_host) (void)hipHostFree(c->cgs_host);
     c->cgs_host = nullptr;
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
@@ -112,12 +112,12 @@ kvs_status ensure_trace_capacity(kvs_ctx* c, int64_t more) {
     int64_t cap = std::max<int64_t>(need, std::max<int64_t>(2 * c->trace_cap, 1024));
     const int64_t per = c->nprobes * ncomp_of(c->probe_comp);
     double* nb = nullptr;
-    API_HIP(c, hipMalloc(&nb, sizeof(double) * per * cap));
+    API_HIP(c, c->mem.get(&nb, sizeof(double) * per * cap));
     if (c->traces && c->trace_steps > 0)
         API_HIP(c, hipMemcpyAsync(nb, c->traces, sizeof(double) * per * c->trace_steps, hipMemcpyDeviceToDevice,
                                   c->stream));
     API_HIP(c, hipStreamSynchronize(c->stream));
-    dfree(c->traces);
+    dfree(c->mem, c->traces);
     c->traces = nb;
     c->trace_cap = cap;
     return KVS_OK;
@@ -194,6 +194,8 @@ kvs_status kvs_create(const kvs_grid* grid, const kvs_opts* opts, kvs_ctx** out)
     if (o.precision != KVS_FP64 && o.precision != KVS_FP32) return fail(nullptr, KVS_EINVAL, "unknown precision");
     if (o.sponge_cells < 0) return fail(nullptr, KVS_EINVAL, "sponge_cells < 0");
     if (std::isnan(o.sponge_sigma_max)) return fail(nullptr, KVS_EINVAL, "sponge_sigma_max is NaN");
+    if ((o.alloc == nullptr) != (o.free == nullptr))
+        return fail(nullptr, KVS_EINVAL, "alloc and free must be given together");
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, KVS_EDEVICE, "no HIP device");
@@ -222,22 +224,26 @@ kvs_status kvs_create(const kvs_grid* grid, const kvs_opts* opts, kvs_ctx** out)
         }
         c->own_stream = true;
     }
+    c->mem.alloc = o.alloc;
+    c->mem.release = o.free;
+    c->mem.user = o.alloc_user;
+    c->mem.stream = c->stream;
     const size_t ts = tsize(c);
     const size_t N = (size_t)c->N;
     c->npart = kvs_cg_partials_needed(g);
     bool ok = true;
     for (int b = 0; b < 2 && ok; ++b) {
-        ok = ok && hipMalloc(&c->u[b], 3 * N * ts) == hipSuccess;
-        ok = ok && hipMalloc(&c->w[b], 3 * N * ts) == hipSuccess;
-        ok = ok && hipMalloc(&c->p[b], N * sizeof(double)) == hipSuccess;
+        ok = ok && c->mem.get(&c->u[b], 3 * N * ts) == hipSuccess;
+        ok = ok && c->mem.get(&c->w[b], 3 * N * ts) == hipSuccess;
+        ok = ok && c->mem.get(&c->p[b], N * sizeof(double)) == hipSuccess;
     }
-    ok = ok && hipMalloc(&c->F, 3 * N * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&c->FS, 3 * N * ts) == hipSuccess;
-    ok = ok && hipMalloc(&c->phi, N * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&c->r, N * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&c->Ap, N * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&c->partials, 3 * (size_t)std::max<int64_t>(c->npart, 2048) * sizeof(double)) == hipSuccess;
-    ok = ok && hipMalloc(&c->cgs, sizeof(CgState)) == hipSuccess;
+    ok = ok && c->mem.get(&c->F, 3 * N * sizeof(double)) == hipSuccess;
+    ok = ok && c->mem.get(&c->FS, 3 * N * ts) == hipSuccess;
+    ok = ok && c->mem.get(&c->phi, N * sizeof(double)) == hipSuccess;
+    ok = ok && c->mem.get(&c->r, N * sizeof(double)) == hipSuccess;
+    ok = ok && c->mem.get(&c->Ap, N * sizeof(double)) == hipSuccess;
+    ok = ok && c->mem.get(&c->partials, 3 * (size_t)std::max<int64_t>(c->npart, 2048) * sizeof(double)) == hipSuccess;
+    ok = ok && c->mem.get(&c->cgs, sizeof(CgState)) == hipSuccess;
     ok = ok && hipHostMalloc(&c->cgs_host, sizeof(CgState), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         release(c);
@@ -290,13 +296,13 @@ kvs_status kvs_set_material(kvs_ctx* c, const double* G, const double* rho, cons
     }
     API_HIP(c, hipSetDevice(c->device));
     const size_t ts = tsize(c);
-    if (!c->G) API_HIP(c, hipMalloc(&c->G, N * ts));
-    if (!c->eta) API_HIP(c, hipMalloc(&c->eta, N * ts));
-    if (!c->rho_t) API_HIP(c, hipMalloc(&c->rho_t, N * ts));
-    if (!c->crho) API_HIP(c, hipMalloc(&c->crho, N * ts));
+    if (!c->G) API_HIP(c, c->mem.get(&c->G, N * ts));
+    if (!c->eta) API_HIP(c, c->mem.get(&c->eta, N * ts));
+    if (!c->rho_t) API_HIP(c, c->mem.get(&c->rho_t, N * ts));
+    if (!c->crho) API_HIP(c, c->mem.get(&c->crho, N * ts));
     double* tmp = nullptr;
     const int64_t npart = 2 * 1024;
-    API_HIP(c, hipMalloc(&tmp, sizeof(double) * (3 * N + npart + 2)));
+    API_HIP(c, c->mem.get(&tmp, sizeof(double) * (3 * N + npart + 2)));
     double* dG = tmp;
     double* drho = tmp + N;
     double* deta = tmp + 2 * N;
@@ -314,7 +320,7 @@ kvs_status kvs_set_material(kvs_ctx* c, const double* G, const double* rho, cons
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) st = fail(c, KVS_EDEVICE, std::string("set_material: ") + hipGetErrorString(e));
     } while (false);
-    (void)hipFree(tmp);
+    c->mem.put(tmp);
     if (st != KVS_OK) return st;
     c->hetero = true;
     c->viscous = visc;
@@ -474,11 +480,11 @@ kvs_status kvs_set_projected_force(kvs_ctx* c, const double* FS) {
         API_HIP(c, hipStreamSynchronize(c->stream));
     } else {
         double* tmp = nullptr;
-        API_HIP(c, hipMalloc(&tmp, bytes));
+        API_HIP(c, c->mem.get(&tmp, bytes));
         hipError_t e = hipMemcpyAsync(tmp, FS, bytes, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = kvs_launch_cast(c, tmp, c->FS, 3 * c->N);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        (void)hipFree(tmp);
+        c->mem.put(tmp);
         if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("set_projected_force: ") + hipGetErrorString(e));
     }
     c->fs_current = true;
@@ -496,11 +502,11 @@ kvs_status kvs_get_projected_force(const kvs_ctx* cc, double* FS) {
         return KVS_OK;
     }
     double* tmp = nullptr;
-    API_HIP(c, hipMalloc(&tmp, bytes));
+    API_HIP(c, c->mem.get(&tmp, bytes));
     hipError_t e = kvs_launch_widen(c, c->FS, tmp, 3 * c->N);
     if (e == hipSuccess) e = hipMemcpyAsync(FS, tmp, bytes, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(tmp);
+    c->mem.put(tmp);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("get_projected_force: ") + hipGetErrorString(e));
     return KVS_OK;
 }
@@ -527,14 +533,14 @@ kvs_status kvs_set_probes(kvs_ctx* c, const int64_t* ijk, int64_t n, int32_t com
         flat[(size_t)p] = i + g.nx * (j + g.ny * k);
     }
     API_HIP(c, hipStreamSynchronize(c->stream));
-    dfree(c->probe_cells);
-    dfree(c->traces);
+    dfree(c->mem, c->probe_cells);
+    dfree(c->mem, c->traces);
     c->trace_cap = 0;
     c->trace_steps = 0;
     c->nprobes = n;
     c->probe_comp = comp;
     if (n > 0) {
-        API_HIP(c, hipMalloc(&c->probe_cells, sizeof(int64_t) * n));
+        API_HIP(c, c->mem.get(&c->probe_cells, sizeof(int64_t) * n));
         API_HIP(c, hipMemcpyAsync(c->probe_cells, flat.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
         API_HIP(c, hipStreamSynchronize(c->stream));
     }
@@ -613,7 +619,7 @@ kvs_status kvs_get_state(const kvs_ctx* cc, double* u, double* w, int64_t* step)
     if (!c) return KVS_EINVAL;
     const size_t bytes = sizeof(double) * 3 * c->N;
     double* tmp = nullptr;
-    if (c->prec == KVS_FP32) API_HIP(c, hipMalloc(&tmp, bytes));
+    if (c->prec == KVS_FP32) API_HIP(c, c->mem.get(&tmp, bytes));
     hipError_t e = hipSuccess;
     void* src[2] = {c->u[c->cur], c->w[c->cur]};
     double* dst[2] = {u, w};
@@ -628,7 +634,7 @@ kvs_status kvs_get_state(const kvs_ctx* cc, double* u, double* w, int64_t* step)
         }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (tmp) (void)hipFree(tmp);
+    if (tmp) c->mem.put(tmp);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("get_state: ") + hipGetErrorString(e));
     if (step) *step = c->step;
     return KVS_OK;
@@ -657,16 +663,16 @@ kvs_status kvs_set_pml(kvs_ctx* c, int32_t cells, double R, double alpha_max) {
     }
     API_HIP(c, hipSetDevice(c->device));
     API_HIP(c, hipStreamSynchronize(c->stream));
-    dfree(c->pml_tab);
-    dfree(c->pml_mem);
+    dfree(c->mem, c->pml_tab);
+    dfree(c->mem, c->pml_mem);
     c->pml_mem_count = 0;
     c->pml_cells = 0;
     if (cells == 0) return KVS_OK;
     const kvs_grid& g = c->grid;
     int64_t count = 0;
     for (int a = 0; a < 3; ++a) count += 9 * kvs_pml_slab_cells(g, cells, a);
-    API_HIP(c, hipMalloc(&c->pml_tab, tsize(c) * 4 * (size_t)(g.nx + g.ny + g.nz)));
-    API_HIP(c, hipMalloc(&c->pml_mem, tsize(c) * (size_t)count));
+    API_HIP(c, c->mem.get(&c->pml_tab, tsize(c) * 4 * (size_t)(g.nx + g.ny + g.nz)));
+    API_HIP(c, c->mem.get(&c->pml_mem, tsize(c) * (size_t)count));
     c->pml_mem_count = count;
     c->pml_cells = cells;
     c->pml_R = R;
@@ -680,7 +686,7 @@ kvs_status kvs_set_state(kvs_ctx* c, const double* u, const double* w, int64_t s
     if (!u || !w || step < 0) return fail(c, KVS_EINVAL, "bad state");
     const size_t bytes = sizeof(double) * 3 * c->N;
     double* tmp = nullptr;
-    API_HIP(c, hipMalloc(&tmp, bytes));
+    API_HIP(c, c->mem.get(&tmp, bytes));
     hipError_t e = hipSuccess;
     const double* src[2] = {u, w};
     void* dst[2] = {c->u[c->cur], c->w[c->cur]};
@@ -690,7 +696,7 @@ kvs_status kvs_set_state(kvs_ctx* c, const double* u, const double* w, int64_t s
         if (e == hipSuccess) e = kvs_launch_zero_boundary(c, dst[q]);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
-    (void)hipFree(tmp);
+    c->mem.put(tmp);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("set_state: ") + hipGetErrorString(e));
     c->step = step;
     return clear_pml_memory(c);
@@ -703,11 +709,11 @@ kvs_status kvs_set_state_curl(kvs_ctx* c, const double* A, int64_t step) {
     const size_t bytes = sizeof(double) * 3 * c->N;
     API_HIP(c, hipSetDevice(c->device));
     double* tmp = nullptr;
-    API_HIP(c, hipMalloc(&tmp, bytes));
+    API_HIP(c, c->mem.get(&tmp, bytes));
     hipError_t e = hipMemcpyAsync(tmp, A, bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = kvs_launch_curl_state(c, tmp);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(tmp);
+    c->mem.put(tmp);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("curl state: ") + hipGetErrorString(e));
     c->step = step;
     return clear_pml_memory(c);
@@ -745,11 +751,11 @@ kvs_status kvs_set_peak_planes(kvs_ctx* c, const int32_t* axis, const int64_t* i
     }
     API_HIP(c, hipSetDevice(c->device));
     API_HIP(c, hipStreamSynchronize(c->stream));
-    dfree(c->peak);
+    dfree(c->mem, c->peak);
     c->npeak = 0;
     c->peak_cells = 0;
     if (n == 0) return KVS_OK;
-    API_HIP(c, hipMalloc(&c->peak, (size_t)total * tsize(c)));
+    API_HIP(c, c->mem.get(&c->peak, (size_t)total * tsize(c)));
     API_HIP(c, hipMemsetAsync(c->peak, 0, (size_t)total * tsize(c), c->stream));
     for (int p = 0; p < n; ++p) {
         c->peak_axis[p] = axis[p];
@@ -796,10 +802,10 @@ kvs_status kvs_arf_begin(kvs_ctx* c, int32_t mode) {
     API_HIP(c, hipSetDevice(c->device));
     if (c->arf_sum_cap < need) {
         API_HIP(c, hipStreamSynchronize(c->stream));
-        dfree(c->arf_sum);
+        dfree(c->mem, c->arf_sum);
         c->arf_sum_cap = 0;
         c->arf_mode = 0;
-        API_HIP(c, hipMalloc(&c->arf_sum, sizeof(double) * (size_t)need));
+        API_HIP(c, c->mem.get(&c->arf_sum, sizeof(double) * (size_t)need));
         c->arf_sum_cap = need;
     }
     API_HIP(c, hipMemsetAsync(c->arf_sum, 0, sizeof(double) * (size_t)need, c->stream));
@@ -833,7 +839,7 @@ kvs_status kvs_arf_accumulate(kvs_ctx* c, const double* p, const double* v, int6
     // stage one sample at a time (p, then v) through one device buffer
     const int64_t per = (v ? 4 : 1) * c->N;
     double* stage = nullptr;
-    API_HIP(c, hipMalloc(&stage, sizeof(double) * (size_t)per));
+    API_HIP(c, c->mem.get(&stage, sizeof(double) * (size_t)per));
     hipError_t e = hipSuccess;
     for (int64_t s = 0; s < nsamp && e == hipSuccess; ++s) {
         e = hipMemcpyAsync(stage, p + s * c->N, sizeof(double) * (size_t)c->N, hipMemcpyHostToDevice, c->stream);
@@ -843,7 +849,7 @@ kvs_status kvs_arf_accumulate(kvs_ctx* c, const double* p, const double* v, int6
         if (e == hipSuccess) e = kvs_launch_arf_accumulate(c, stage, v ? stage + c->N : nullptr, 1, 0);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
-    (void)hipFree(stage);
+    c->mem.put(stage);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("arf accumulate: ") + hipGetErrorString(e));
     c->arf_samples += nsamp;
     return KVS_OK;
@@ -895,7 +901,7 @@ kvs_status kvs_arf_set_force(kvs_ctx* c, const double* alpha, int64_t n_alpha, c
     const size_t doubles = (size_t)(n_alpha + n_c + nr);
     const size_t bytes = sizeof(double) * doubles + (mask ? (size_t)c->N : 0);
     char* tmp = nullptr;
-    API_HIP(c, hipMalloc(&tmp, bytes));
+    API_HIP(c, c->mem.get(&tmp, bytes));
     double* dA = reinterpret_cast<double*>(tmp);
     double* dC = dA + n_alpha;
     double* dR = plane ? dC + n_c : nullptr;
@@ -908,7 +914,7 @@ kvs_status kvs_arf_set_force(kvs_ctx* c, const double* alpha, int64_t n_alpha, c
         e = kvs_launch_arf_force(c, dA, n_alpha == 1 ? 0 : 1, dC, n_c == 1 ? 0 : 1, dR, n_rho == 1 ? 0 : 1, dM,
                                  n_pulse, d);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(tmp);
+    c->mem.put(tmp);
     if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("arf force: ") + hipGetErrorString(e));
     c->have_force = true;
     c->fs_current = false;
@@ -922,11 +928,11 @@ kvs_status kvs_strain_begin(kvs_ctx* c, const double* K, int64_t n_K) {
         if (!finite_pos(K[q])) return fail(c, KVS_EINVAL, "strain: K must be finite, > 0");
     API_HIP(c, hipSetDevice(c->device));
     API_HIP(c, hipStreamSynchronize(c->stream));
-    if (!c->strain_peak) API_HIP(c, hipMalloc(&c->strain_peak, sizeof(double) * 2 * (size_t)c->N));
+    if (!c->strain_peak) API_HIP(c, c->mem.get(&c->strain_peak, sizeof(double) * 2 * (size_t)c->N));
     if (c->strain_K_cap < n_K) {
-        dfree(c->strain_K);
+        dfree(c->mem, c->strain_K);
         c->strain_K_cap = 0;
-        API_HIP(c, hipMalloc(&c->strain_K, sizeof(double) * (size_t)n_K));
+        API_HIP(c, c->mem.get(&c->strain_K, sizeof(double) * (size_t)n_K));
         c->strain_K_cap = n_K;
     }
     API_HIP(c, hipMemcpyAsync(c->strain_K, K, sizeof(double) * (size_t)n_K, hipMemcpyHostToDevice, c->stream));
@@ -961,12 +967,12 @@ kvs_status kvs_strain_get(const kvs_ctx* cc, double* peak_strain, double* peak_g
                                   c->stream));
     if (peak_gradient) {
         double* roots = nullptr;
-        API_HIP(c, hipMalloc(&roots, sizeof(double) * (size_t)c->N));
+        API_HIP(c, c->mem.get(&roots, sizeof(double) * (size_t)c->N));
         hipError_t e = kvs_launch_strain_roots(c, roots);
         if (e == hipSuccess)
             e = hipMemcpyAsync(peak_gradient, roots, sizeof(double) * (size_t)c->N, hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        (void)hipFree(roots);
+        c->mem.put(roots);
         if (e != hipSuccess) return fail(c, KVS_EDEVICE, std::string("strain: ") + hipGetErrorString(e));
     }
     API_HIP(c, hipStreamSynchronize(c->stream));
@@ -1092,10 +1098,10 @@ static void batch_release(kvs_batch* b) {
     b->inst.clear();
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
-    dfree(b->dev_params);
-    dfree(b->dev_work);
-    dfree(b->dev_probes);
-    dfree(b->traces);
+    dfree(b->mem, b->dev_params);
+    dfree(b->mem, b->dev_work);
+    dfree(b->mem, b->dev_probes);
+    dfree(b->mem, b->traces);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     b->stream = nullptr;
 }
@@ -1112,6 +1118,10 @@ kvs_status kvs_batch_create(const kvs_grid* grids, int32_t n, const kvs_opts* op
     if (hipSetDevice(o.device) != hipSuccess) return bfail(nullptr, KVS_EDEVICE, "hipSetDevice failed");
     kvs_batch* b = new (std::nothrow) kvs_batch();
     if (!b) return bfail(nullptr, KVS_ENOMEM, "host allocation failed");
+    if ((o.alloc == nullptr) != (o.free == nullptr)) {
+        delete b;
+        return bfail(nullptr, KVS_EINVAL, "alloc and free must be given together");
+    }
     b->device = o.device;
     b->prec = o.precision;
     if (o.stream) {
@@ -1124,6 +1134,10 @@ kvs_status kvs_batch_create(const kvs_grid* grids, int32_t n, const kvs_opts* op
         b->own_stream = true;
     }
     o.stream = b->stream;
+    b->mem.alloc = o.alloc;
+    b->mem.release = o.free;
+    b->mem.user = o.alloc_user;
+    b->mem.stream = b->stream;
     for (int32_t i = 0; i < n; ++i) {
         kvs_ctx* c = nullptr;
         kvs_status st = kvs_create(&grids[i], &o, &c);
@@ -1171,8 +1185,8 @@ kvs_status kvs_batch_share_projection(kvs_batch* b, int32_t src, int32_t dst) {
 
 static kvs_status batch_upload_probes(kvs_batch* b) {
     const size_t np = b->probe_inst.size();
-    dfree(b->dev_probes);
-    dfree(b->traces);
+    dfree(b->mem, b->dev_probes);
+    dfree(b->mem, b->traces);
     b->trace_cap = 0;
     b->trace_steps = 0;
     b->graph_valid = false;
@@ -1183,7 +1197,7 @@ static kvs_status batch_upload_probes(kvs_batch* b) {
         flat[2 * p] = b->probe_inst[p];
         flat[2 * p + 1] = b->probe_cell[p];
     }
-    BATCH_HIP(b, hipMalloc(&b->dev_probes, sizeof(int64_t) * flat.size()));
+    BATCH_HIP(b, b->mem.get(&b->dev_probes, sizeof(int64_t) * flat.size()));
     BATCH_HIP(b, hipMemcpyAsync(b->dev_probes, flat.data(), sizeof(int64_t) * flat.size(), hipMemcpyHostToDevice,
                                 b->stream));
     BATCH_HIP(b, hipStreamSynchronize(b->stream));
@@ -1259,12 +1273,12 @@ kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
     if (np > 0 && b->trace_steps + nsteps > b->trace_cap) {
         const int64_t cap = std::max<int64_t>(b->trace_steps + nsteps, 2 * b->trace_cap);
         double* nb = nullptr;
-        BATCH_HIP(b, hipMalloc(&nb, sizeof(double) * np * cap));
+        BATCH_HIP(b, b->mem.get(&nb, sizeof(double) * np * cap));
         if (b->traces && b->trace_steps > 0)
             BATCH_HIP(b, hipMemcpyAsync(nb, b->traces, sizeof(double) * np * b->trace_steps, hipMemcpyDeviceToDevice,
                                         b->stream));
         BATCH_HIP(b, hipStreamSynchronize(b->stream));
-        dfree(b->traces);
+        dfree(b->mem, b->traces);
         b->traces = nb;
         b->trace_cap = cap;
         b->graph_valid = false;
@@ -1282,7 +1296,7 @@ kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
 }
 
 static void batch_retile(kvs_batch* b) {
-    dfree(b->dev_work);  // rebuilt for the new tile shape by the next prepare
+    dfree(b->mem, b->dev_work);  // rebuilt for the new tile shape by the next prepare
     b->nwork = 0;
     b->graph_valid = false;
 }

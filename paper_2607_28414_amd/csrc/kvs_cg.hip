@@ -819,9 +819,9 @@ std::string cg_message(const CgErr& e) {
 
 kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_report* rep) {
     if (o->precond == KVS_PC_UNET && !c->r2) {
-        const hipError_t e = hipMalloc(&c->r2, sizeof(double) * c->N);
+        const hipError_t e = c->mem.get(&c->r2, sizeof(double) * c->N);
         if (e != hipSuccess) {
-            c->err = std::string("hipMalloc (second residual): ") + hipGetErrorString(e);
+            c->err = std::string("device allocation (second residual): ") + hipGetErrorString(e);
             return KVS_ENOMEM;
         }
     }

@@ -29,8 +29,43 @@ struct CgState {
     int fallbacks;          // number of Jacobi fallbacks taken
 };
 
+// Device memory of a context or batch: the caller's allocator when kvs_opts
+// names one, else hipMalloc / hipFree.  Before handing a buffer back to the
+// caller's allocator the stream is synchronised, so that no queued kernel
+// still uses it whatever the allocator's stream semantics (hipFree
+// synchronises by itself).
+struct KvsMem {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* user = nullptr;
+    hipStream_t stream = nullptr;
+
+    hipError_t get(void** p, size_t bytes) const {
+        if (!alloc) return hipMalloc(p, bytes);
+        *p = bytes ? alloc(bytes, user) : nullptr;
+        return (*p || !bytes) ? hipSuccess : hipErrorOutOfMemory;
+    }
+    template <typename P>
+    hipError_t get(P** p, size_t bytes) const {
+        void* q = nullptr;
+        const hipError_t e = get(&q, bytes);
+        *p = static_cast<P*>(q);
+        return e;
+    }
+    void put(void* p) const {
+        if (!p) return;
+        if (!alloc) {
+            (void)hipFree(p);
+            return;
+        }
+        if (stream) (void)hipStreamSynchronize(stream);
+        release(p, user);
+    }
+};
+
 struct kvs_ctx {
     kvs_grid grid{};
+    KvsMem mem;  // where the context's device buffers come from
     int64_t N = 0;
     int prec = KVS_FP64;
     int device = 0;
@@ -162,6 +197,7 @@ inline int ncomp_of(int comp) { return comp == 3 ? 3 : 1; }
 // covering every instance's tiles, the step loop replayed as a hipGraph).
 struct kvs_batch {
     std::vector<kvs_ctx*> inst;
+    KvsMem mem;  // where the batch's own device tables come from
     int device = 0;
     int prec = KVS_FP32;
     hipStream_t stream = nullptr;

@@ -803,9 +803,9 @@ hipError_t prepare_t(kvs_batch* b) {
     const size_t ebytes = sizeof(double) * std::max<size_t>(env_total, 1);
     hipError_t e = hipSuccess;
     if (!b->dev_params || b->params_bytes < pbytes + ebytes) {
-        if (b->dev_params) e = hipFree(b->dev_params);
+        b->mem.put(b->dev_params);  // after the stream's earlier steps (put synchronises)
         b->dev_params = nullptr;
-        if (e == hipSuccess) e = hipMalloc(&b->dev_params, pbytes + ebytes);
+        e = b->mem.get(&b->dev_params, pbytes + ebytes);
         if (e != hipSuccess) return e;
         b->params_bytes = pbytes + ebytes;
         b->graph_valid = false;  // the graph holds the old table's address
@@ -834,7 +834,7 @@ hipError_t prepare_t(kvs_batch* b) {
     e = hipMemcpyAsync(b->dev_params, params.data(), pbytes, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(env_dev, env_host.data(), ebytes, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && !b->dev_work) {
-        e = hipMalloc(&b->dev_work, sizeof(int4) * work.size());
+        e = b->mem.get(&b->dev_work, sizeof(int4) * work.size());
         if (e == hipSuccess)
             e = hipMemcpyAsync(b->dev_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice,
                                b->stream);

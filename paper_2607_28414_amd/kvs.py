@@ -34,9 +34,53 @@ class kvs_grid(C.Structure):
                 ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class kvs_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("sponge_cells", C.c_int32), ("sponge_sigma_max", C.c_double),
-                ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """kvs_opts allocator callbacks backed by torch's caching allocator on
+    one device and stream (the stream the context runs on, so that the
+    allocator's stream ordering matches the library's).  Counts the calls
+    and the bytes in use."""
+
+    def __init__(self, device, stream):
+        import torch
+        self._torch = torch
+        self.device, self.stream = int(device), int(stream or 0)
+        self.allocs = self.frees = self.live_bytes = 0
+        self._sizes = {}
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _user):
+        ptr = self._torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        self.allocs += 1
+        self.live_bytes += int(nbytes)
+        self._sizes[ptr] = int(nbytes)
+        return ptr
+
+    def _free(self, ptr, _user):
+        self._torch.cuda.caching_allocator_delete(ptr)
+        self.frees += 1
+        self.live_bytes -= self._sizes.pop(ptr, 0)
+
+
+# allocators in use, kept alive while their context or batch lives
+_ALLOCATORS = {}
+
+
+def _opts(precision, sponge_cells, sponge_sigma_max, device, stream, allocator):
+    o = kvs_opts(int(precision), int(sponge_cells), float(sponge_sigma_max), int(device), stream or None)
+    if allocator is not None:
+        o.alloc, o.free = allocator.alloc_fn, allocator.free_fn
+    return o
 
 
 class kvs_solve_opts(C.Structure):
@@ -211,17 +255,24 @@ def _out_shape(ctx, shape):
     return tuple(shape)
 
 
-def kvs_create(grid, precision=KVS_FP64, sponge_cells=0, sponge_sigma_max=-1.0, device=0, stream=None):
+def kvs_create(grid, precision=KVS_FP64, sponge_cells=0, sponge_sigma_max=-1.0, device=0, stream=None,
+               allocator=None):
+    """allocator: None (hipMalloc inside the library) or a TorchAllocator for
+    this device (best built for the same `stream`: the library synchronises
+    its stream before it hands a buffer back, so any stream is safe)."""
     nx, ny, nz, hx, hy, hz = grid
     g = kvs_grid(int(nx), int(ny), int(nz), float(hx), float(hy), float(hz))
-    o = kvs_opts(int(precision), int(sponge_cells), float(sponge_sigma_max), int(device), stream or None)
+    o = _opts(precision, sponge_cells, sponge_sigma_max, device, stream, allocator)
     out = C.c_void_p()
     _check(lib().kvs_create(C.byref(g), C.byref(o), C.byref(out)))
+    if allocator is not None:
+        _ALLOCATORS[out.value] = allocator
     return out
 
 
 def kvs_destroy(ctx):
     lib().kvs_destroy(ctx)
+    _ALLOCATORS.pop(ctx.value if isinstance(ctx, C.c_void_p) else ctx, None)
 
 
 def kvs_synchronize(ctx):
@@ -444,17 +495,21 @@ def _bcheck(status, b):
         raise KvsError(status, msg.decode() if msg else "")
 
 
-def kvs_batch_create(grids, precision=KVS_FP32, sponge_cells=0, sponge_sigma_max=-1.0, device=0, stream=None):
+def kvs_batch_create(grids, precision=KVS_FP32, sponge_cells=0, sponge_sigma_max=-1.0, device=0, stream=None,
+                     allocator=None):
     arr = (kvs_grid * len(grids))(*[kvs_grid(int(g[0]), int(g[1]), int(g[2]), float(g[3]), float(g[4]), float(g[5]))
                                     for g in grids])
-    o = kvs_opts(int(precision), int(sponge_cells), float(sponge_sigma_max), int(device), stream or None)
+    o = _opts(precision, sponge_cells, sponge_sigma_max, device, stream, allocator)
     out = C.c_void_p()
     _bcheck(lib().kvs_batch_create(arr, len(grids), C.byref(o), C.byref(out)), None)
+    if allocator is not None:
+        _ALLOCATORS[out.value] = allocator
     return out
 
 
 def kvs_batch_destroy(b):
     lib().kvs_batch_destroy(b)
+    _ALLOCATORS.pop(b.value if isinstance(b, C.c_void_p) else b, None)
 
 
 def kvs_batch_instance(b, i):

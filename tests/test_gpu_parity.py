@@ -555,3 +555,99 @@ def test_peak_plane_and_buffer_errors(kvs):
             kvs.kvs_peak_map(ctx, 2, 10, grid)
     finally:
         kvs.kvs_destroy(ctx)
+
+
+def test_torch_allocator_context_and_batch(kvs):
+    """A context and a batch whose device buffers come from torch's caching
+    allocator through the kvs_opts callbacks: every byte of device memory
+    they take is accounted for by torch's reserved memory (so the library
+    made no hipMalloc of its own), every buffer comes back by destroy, and
+    the traces equal, bit for bit, those of the same runs on hipMalloc'd
+    buffers (heterogeneous FP32 context with projection, probes, peak maps
+    and a re-registration; a two-instance batch)."""
+    import torch
+    say("case torch allocator")
+    grid, G, rho, eta, F = hetero_case((61, 37, 45), 41)
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    probes = np.array([[i, 18, 22] for i in range(61)])
+    env = np.ones(9)
+
+    def run_ctx(allocator, stream):
+        ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, sponge_cells=3, stream=stream, allocator=allocator)
+        try:
+            kvs.kvs_set_material(ctx, G, rho, eta)
+            kvs.kvs_set_dt(ctx, dt)
+            kvs.kvs_set_force(ctx, F)
+            kvs.kvs_set_envelope(ctx, env)
+            kvs.kvs_project(ctx, tol=1e-10)
+            kvs.kvs_set_probes(ctx, probes, 3)
+            kvs.kvs_set_peak_planes(ctx, [(0, 30), (2, 20)])
+            kvs.kvs_step(ctx, 40)
+            kvs.kvs_set_peak_planes(ctx, [(1, 18)])
+            kvs.kvs_step(ctx, 30)
+            return kvs.kvs_read_traces(ctx, len(probes), 3), kvs.kvs_peak_map(ctx, 1, 18, grid)
+        finally:
+            kvs.kvs_destroy(ctx)
+
+    s = torch.cuda.Stream()
+    ref_tr, ref_map = run_ctx(None, s.cuda_stream)
+    alloc = kvs.TorchAllocator(0, s.cuda_stream)
+    torch.cuda.synchronize()
+    free0, res0 = torch.cuda.mem_get_info()[0], torch.cuda.memory_reserved()
+    ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, sponge_cells=3, stream=s.cuda_stream, allocator=alloc)
+    try:
+        kvs.kvs_set_material(ctx, G, rho, eta)
+        kvs.kvs_set_dt(ctx, dt)
+        kvs.kvs_set_force(ctx, F)
+        kvs.kvs_set_envelope(ctx, env)
+        kvs.kvs_project(ctx, tol=1e-10)
+        kvs.kvs_set_probes(ctx, probes, 3)
+        kvs.kvs_set_peak_planes(ctx, [(0, 30), (2, 20)])
+        kvs.kvs_step(ctx, 40)
+        kvs.kvs_set_peak_planes(ctx, [(1, 18)])
+        kvs.kvs_step(ctx, 30)
+        tr, pm = kvs.kvs_read_traces(ctx, len(probes), 3), kvs.kvs_peak_map(ctx, 1, 18, grid)
+        torch.cuda.synchronize()
+        taken = free0 - torch.cuda.mem_get_info()[0]
+        grown = torch.cuda.memory_reserved() - res0
+        live = alloc.live_bytes
+    finally:
+        kvs.kvs_destroy(ctx)
+    say(f"torch allocator: {alloc.allocs} allocations, {live} B live, device memory taken {taken} B, "
+        f"torch reserve grew {grown} B")
+    assert alloc.allocs > 10 and live > 3 * 61 * 37 * 45 * 4
+    assert taken == grown  # nothing outside torch's pool
+    assert alloc.frees == alloc.allocs and alloc.live_bytes == 0
+    assert np.array_equal(tr, ref_tr) and np.array_equal(pm, ref_map)
+
+    # batch: instances and the batch's own tables through the allocator
+    grids = [(24, 20, 22, 0.25e-3, 0.25e-3, 0.25e-3), (30, 26, 28, 0.25e-3, 0.25e-3, 0.25e-3)]
+
+    def run_batch(allocator):
+        b = kvs.kvs_batch_create(grids, precision=1, sponge_cells=3, stream=s.cuda_stream, allocator=allocator)
+        try:
+            for i, g in enumerate(grids):
+                c = kvs.kvs_batch_instance(b, i)
+                kvs.kvs_set_material_uniform(c, 2e3 * (i + 1), 1000.0, 0.4)
+                kvs.kvs_set_dt(c, 0.4 * kvs.kvs_stable_dt(c))
+                kvs.kvs_set_force(c, gaussian_push(g, 0.75e-3, 1.5e-3, 1e4))
+                kvs.kvs_project(c, tol=1e-10)
+                kvs.kvs_set_envelope(c, np.ones(4))
+                kvs.kvs_batch_set_probes(b, i, x_line_probes(g))
+            kvs.kvs_batch_step(b, 50)
+            return [kvs.kvs_batch_read_traces(b, i, g[0]) for i, g in enumerate(grids)]
+        finally:
+            kvs.kvs_batch_destroy(b)
+
+    ref = run_batch(None)
+    balloc = kvs.TorchAllocator(0, s.cuda_stream)
+    got = run_batch(balloc)
+    assert balloc.allocs > 0 and balloc.frees == balloc.allocs and balloc.live_bytes == 0
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    with pytest.raises(kvs.KvsError) as e:
+        o = kvs.kvs_opts(1, 0, -1.0, 0, None)
+        o.alloc = alloc.alloc_fn  # free missing
+        out = kvs.C.c_void_p()
+        kvs._check(kvs.lib().kvs_create(kvs.C.byref(kvs.kvs_grid(8, 8, 8, 1e-3, 1e-3, 1e-3)), kvs.C.byref(o),
+                                        kvs.C.byref(out)))
+    assert e.value.status == kvs.KVS_EINVAL
