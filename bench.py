@@ -96,6 +96,10 @@ def parse():
     ap.add_argument("--tv-epochs", type=int, default=4, help="epochs of the time-varying workload window")
     ap.add_argument("--shell-steps", type=int, default=300, help="steps of the shell workload window")
     ap.add_argument("--arf-repeats", type=int, default=8, help="accumulate launches of the ARF leg")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed sweeps of the batched leg in the default run")
+    ap.add_argument("--batch-warmup", type=int, default=1, help="untimed sweeps of the batched leg in the default run")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="skip the 48^3 FP64, batched-sweep, KV-line and streaming-reference legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (HBM counter calibration)")
     return ap.parse_args()
@@ -170,7 +174,7 @@ def learned_projection(args, net):
     import torch
 
     from paper_2607_28414_amd import kvs, train
-    from workloads import focal_modulated_force
+    from workloads import focal_modulated_params
 
     nx, ny, nz, h = 384, 384, 512, 0.2e-3
     grid = (nx, ny, nz, h, h, h)
@@ -185,13 +189,10 @@ def learned_projection(args, net):
                "fpcg": {"iters": [], "ms": [], "fallbacks": [], "relres_true": []},
                "jacobi_warm": {"iters": [], "ms": [], "relres_true": []},
                "fpcg_warm": {"iters": [], "ms": [], "relres_true": []}}
-        F_dev = None
         for e in range(args.learned_epochs):
-            F = focal_modulated_force(grid, epoch=e)
-            F_dev = torch.from_numpy(F).to("cuda")
-            del F
+            push = focal_modulated_params(grid, epoch=e)
             for name, pc in (("jacobi", kvs.KVS_PC_JACOBI), ("fpcg", kvs.KVS_PC_UNET)):
-                kvs.kvs_set_force_device(ctx, F_dev.data_ptr(), 0)
+                kvs.kvs_set_force_pattern(ctx, **push)  # generated on the device
                 # both methods stop only when the FP64 true residual is below 1e-8
                 rep = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=pc, confirm_true=True)
                 res[name]["iters"].append(rep["iters"])
@@ -205,8 +206,7 @@ def learned_projection(args, net):
         # warm-started: consecutive epochs, phi kept from the previous solve of the same method
         for name, pc in (("jacobi_warm", kvs.KVS_PC_JACOBI), ("fpcg_warm", kvs.KVS_PC_UNET)):
             for e in range(args.learned_epochs):
-                F_dev = torch.from_numpy(focal_modulated_force(grid, epoch=e)).to("cuda")
-                kvs.kvs_set_force_device(ctx, F_dev.data_ptr(), 0)
+                kvs.kvs_set_force_pattern(ctx, **focal_modulated_params(grid, epoch=e))
                 rep = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=pc, warm_start=e > 0,
                                       confirm_true=True)
                 assert rep["status"] == 0 and rep["relres_true"] < 1e-8, rep
@@ -254,7 +254,7 @@ def time_varying_window(args, net):
     import torch
 
     from paper_2607_28414_amd import kvs
-    from workloads import cfg4_grf_material, focal_modulated_force
+    from workloads import cfg4_grf_material, focal_modulated_params
 
     log("bench: time-varying workload 384x384x512 (random medium, F_S always on)")
     grid, G, rho, eta = cfg4_grf_material()
@@ -274,17 +274,16 @@ def time_varying_window(args, net):
         kvs.kvs_enable_kernel_timing(ctx, True)
         for e in range(args.tv_epochs):
             # the epoch's force (standing in for the acoustic solver's output) is
-            # built on the GPU before the epoch's timing starts
-            force = focal_modulated_force(grid, epoch=e, dt=dt, device="cuda")
+            # generated by the library's pattern kernel inside the epoch
+            push = focal_modulated_params(grid, epoch=e, dt=dt)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            kvs.kvs_set_force_device(ctx, force.data_ptr(), 0)
+            kvs.kvs_set_force_pattern(ctx, **push)
             rep = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=kvs.KVS_PC_UNET, warm_start=e > 0,
                                   confirm_true=True)
             kvs.kvs_step(ctx, 10)
             torch.cuda.synchronize()
             ems.append((time.perf_counter() - t0) * 1e3)
-            del force
             if (e + 1) % 50 == 0:
                 log(f"bench: time-varying epoch {e + 1} of {args.tv_epochs}")
             assert rep["status"] == 0 and rep["relres_true"] < 1e-8, rep
@@ -524,7 +523,7 @@ def run_fpcg_profile(args):
     import torch
 
     from paper_2607_28414_amd import kvs, train
-    from workloads import focal_modulated_force
+    from workloads import focal_modulated_params
 
     g = (384, 384, 512, 0.2e-3, 0.2e-3, 0.2e-3)
     net = kvs.kvs_unet_create((16, 32, 64), 4)
@@ -532,7 +531,7 @@ def run_fpcg_profile(args):
     try:
         train.init_weights(net, np.random.default_rng(0))
         ctx = kvs.kvs_create(g, precision=kvs.KVS_FP32, stream=torch.cuda.current_stream().cuda_stream)
-        kvs.kvs_set_force(ctx, focal_modulated_force(g, epoch=0))
+        kvs.kvs_set_force_pattern(ctx, **focal_modulated_params(g, epoch=0))
         kvs.kvs_set_preconditioner(ctx, net)
         ms = [kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_UNET, fixed_iters=10)["ms"] for _ in range(2)]
     finally:
@@ -542,9 +541,13 @@ def run_fpcg_profile(args):
     return {"profiling_aid": "flexible PCG, 10 fixed iterations, 384x384x512, untrained network", "solve_ms": ms}
 
 
-def cpu_baseline(w, dt, smax, FS_host, nsteps):
-    """The FP64 oracle, as it stands, on `nsteps` FDTD steps of the workload
-    (from rest, push on), timed on the host cores."""
+def cpu_baseline(w, dt, smax, FS_host, nsteps, proj_iters, cg_sample=40):
+    """The FP64 oracle, as it stands, on a bounded sample of the whole
+    workload, timed on the host cores: `nsteps` FDTD steps (from rest, push
+    on) and `cg_sample` Jacobi-PCG iterations of the projection (with its
+    divergence and gradient subtraction).  value = the whole job (the
+    projection's `proj_iters` iterations and the workload's steps) at the
+    sampled per-step and per-iteration times, in the metric's unit."""
     import numpy as np
 
     import oracle
@@ -554,6 +557,11 @@ def cpu_baseline(w, dt, smax, FS_host, nsteps):
     oracle.run(w.grid, w.G, w.rho, w.eta, dt, nsteps, FS=FS_host, env=env, probes=w.probes, comp=2,
                sponge_cells=w.sponge_cells, sigma_max=smax)
     el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.project(w.grid, w.F, fixed_iters=cg_sample, jacobi=True)
+    el_cg = time.perf_counter() - t1
+    t_step, t_iter = el / nsteps, el_cg / cg_sample
+    t_job = proj_iters * t_iter + w.nsteps * t_step
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     # the same oracle on one thread (OpenMP's runtime shared with the oracle's library)
     import ctypes
@@ -562,10 +570,10 @@ def cpu_baseline(w, dt, smax, FS_host, nsteps):
         gomp = ctypes.CDLL("libgomp.so.1")
         gomp.omp_set_num_threads(1)
         n1 = 4
-        t1 = time.perf_counter()
+        t2 = time.perf_counter()
         oracle.run(w.grid, w.G, w.rho, w.eta, dt, n1, FS=FS_host, env=env, probes=w.probes, comp=2,
                    sponge_cells=w.sponge_cells, sigma_max=smax)
-        one = w.interior_cells * n1 / (time.perf_counter() - t1) / 1e9
+        one = w.interior_cells * n1 / (time.perf_counter() - t2) / 1e9
         gomp.omp_set_num_threads(cores)
     except OSError:
         pass
@@ -575,15 +583,86 @@ def cpu_baseline(w, dt, smax, FS_host, nsteps):
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
     except OSError:
         pass
-    return {"value": w.interior_cells * nsteps / el / 1e9, "unit": "Gcell-updates/s", "cores": cores,
-            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(), "value_one_thread": one,
-            "sample": f"{nsteps} FDTD steps of the same {w.grid[0]}^3 workload from rest with the push on "
-                      f"(FP64 C oracle, OpenMP), {el:.1f} s; projection not included; value_one_thread: "
-                      f"4 steps on one thread"}
+    return {"value": w.interior_cells * w.nsteps / t_job / 1e9, "unit": "Gcell-updates/s", "cores": cores,
+            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
+            "fdtd_only": w.interior_cells * nsteps / el / 1e9, "s_per_step": t_step, "s_per_cg_iteration": t_iter,
+            "whole_job_s": t_job, "value_one_thread_fdtd": one,
+            "sample": f"{nsteps} FDTD steps of the same {w.grid[0]}^3 workload from rest with the push on ({el:.1f} s) "
+                      f"and {cg_sample} Jacobi-PCG iterations of its projection with divergence and gradient "
+                      f"subtraction ({el_cg:.1f} s), FP64 C oracle, OpenMP; value = the whole job ({proj_iters} "
+                      f"iterations + {w.nsteps} steps) at the sampled rates; value_one_thread_fdtd: 4 steps on one "
+                      f"thread"}
 
 
-def run_batch(args):
-    """The 64-instance batched sweep; returns the result line."""
+def run_config1(args):
+    """The plain method at CPU size (48^3 FP64 homogeneous, Jacobi-PCG to
+    1e-10, 200 steps, u_z on the lateral line): the whole simulation on the
+    GPU (force resident in HBM, timed over repeats) and the oracle's whole
+    run on the host cores; both traces compared."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle.analysis import rel_l2
+    from paper_2607_28414_amd import kvs
+    from workloads import cfg1_homogeneous_fp64
+
+    w = cfg1_homogeneous_fp64()
+    log("bench: 48^3 FP64 workload")
+    stream = torch.cuda.current_stream()
+    ctx = kvs.kvs_create(w.grid, precision=kvs.KVS_FP64, sponge_cells=w.sponge_cells, sponge_sigma_max=-1.0,
+                         stream=stream.cuda_stream)
+    try:
+        kvs.kvs_set_material_uniform(ctx, w.G, w.rho, w.eta)
+        kvs.kvs_set_dt(ctx, w.dt)
+        kvs.kvs_set_envelope(ctx, w.env)
+        kvs.kvs_set_probes(ctx, w.probes, w.comp)
+        kvs.kvs_autotune_step(ctx, 5)
+        F_dev = torch.from_numpy(np.ascontiguousarray(w.F)).to("cuda")
+
+        def sim():
+            kvs.kvs_reset_state(ctx)
+            kvs.kvs_set_force_device(ctx, F_dev.data_ptr(), 0)
+            rep = kvs.kvs_project(ctx, tol=w.tol, precond=kvs.KVS_PC_JACOBI)
+            kvs.kvs_step(ctx, w.nsteps)
+            return rep, kvs.kvs_read_traces(ctx, len(w.probes), 1)
+
+        sim()
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rep, tr = sim()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        smax = kvs.kvs_sponge_sigma_max(ctx)
+    finally:
+        kvs.kvs_destroy(ctx)
+    cells = w.interior_cells
+    out = {"workload": "homogeneous 48^3 FP64, h 0.5 mm, G 3 kPa, 8-cell sponge, Gaussian push 100 us, Jacobi-PCG "
+                       "to 1e-10, dt 5e-5 s, 200 steps, u_z on the lateral line (cache-resident: no roofline)",
+           "value": cells * w.nsteps / el / 1e9, "unit": "Gcell-updates/s", "ms_per_simulation": el * 1e3,
+           "projection_iters": rep["iters"], "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        oracle.lib()
+        t1 = time.perf_counter()
+        FS_o, _, rep_o = oracle.project(w.grid, w.F, tol=w.tol, jacobi=True)
+        _, _, tr_o = oracle.run(w.grid, w.G, w.rho, w.eta, w.dt, w.nsteps, FS=FS_o, env=w.env, probes=w.probes,
+                                comp=w.comp, sponge_cells=w.sponge_cells, sigma_max=smax)
+        el_o = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": cells * w.nsteps / el_o / 1e9, "unit": "Gcell-updates/s",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle", "sample": f"the whole simulation (projection {rep_o['iters']} "
+                                                           f"iterations + 200 steps), {el_o:.2f} s"}
+        out["trace_rel_l2_vs_oracle"] = rel_l2(tr, tr_o)
+    return out
+
+
+def run_batch(args, steps=None, warmup=None):
+    """The 64-instance batched sweep; returns the result line (steps and
+    warmup default to the command line's)."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     import numpy as np
     import torch
 
@@ -633,13 +712,13 @@ def run_batch(args):
             tr = [kvs.kvs_batch_read_traces(b, i, grids[i][0]) for i in range(len(draws))]
             return reps, tr
 
-        for q in range(args.warmup):
+        for q in range(warmup):
             log(f"bench: warmup step {q} (graph capture)")
             one_step()
         torch.cuda.synchronize()
-        log(f"bench: timing {args.steps} steps")
+        log(f"bench: timing {steps} steps")
         t0 = time.perf_counter()
-        for q in range(args.steps):
+        for q in range(steps):
             reps, tr = one_step()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
@@ -654,12 +733,12 @@ def run_batch(args):
     finally:
         kvs.kvs_batch_destroy(b)
     total = sum(cells) * nsteps
-    value = args.steps * total / el / 1e9
+    value = steps * total / el / 1e9
     bytes_total = 48.0 * total + 12.0 * sum(c * p for c, p in zip(cells, n_push))
     achieved = bytes_total / (step_ms * 1e-3) / 1e9
     return {
-        "metric": METRIC, "value": value, "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": value, "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": el / steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched sweep: 64 homogeneous instances, edges 96-192 (cubic), G 1-10 kPa, "
                                "eta 0-1.5 Pa s, rho 1000, dx 0.25 mm, 8-cell sponge, Gaussian push 100 us, "
@@ -673,8 +752,46 @@ def run_batch(args):
                      "variant": bv, "zchunk": bz},
         "projection": {"precond": "jacobi", "tol": 1e-8,
                        "per_grid": {str(e): {"iters": r["iters"], "ms": r["ms"]} for e, r in reps.items()}},
-        "cpu_baseline": None,
+        "cpu_baseline": batch_cpu_window(draws, {e: r["iters"] for e, r in reps.items()}, nsteps)
+        if not args.no_cpu_baseline else None,
     }
+
+
+def batch_cpu_window(draws, proj_iters, nsteps, steps_sample=6, cg_sample=20):
+    """The FP64 oracle on a window of the batched sweep: for each distinct
+    edge, `steps_sample` steps of one of its instances (from rest, push on)
+    and `cg_sample` Jacobi-PCG iterations of its grid's projection; value =
+    the whole sweep (every instance's `nsteps` steps and one projection per
+    distinct grid at the GPU's iteration counts) at the sampled rates."""
+    import numpy as np
+
+    import oracle
+    from workloads import gaussian_push, x_line_probes
+    h = 0.25e-3
+    oracle.lib()
+    t_step, t_iter, spent = {}, {}, 0.0
+    for e in sorted(proj_iters):
+        _, G, rho, eta = next(d for d in draws if d[0] == e)
+        grid = (e, e, e, h, h, h)
+        F = gaussian_push(grid, 1e-3, 4e-3, 1e4)
+        t0 = time.perf_counter()
+        FS, _, _ = oracle.project(grid, F, fixed_iters=cg_sample, jacobi=True)
+        t_iter[e] = (time.perf_counter() - t0) / cg_sample
+        dt = 0.4 * oracle.stable_dt(grid, G, rho, eta)
+        smax = oracle.default_sigma_max(grid, G, rho, 8)
+        t1 = time.perf_counter()
+        oracle.run(grid, G, rho, eta, dt, steps_sample, FS=FS, env=np.ones(steps_sample), probes=x_line_probes(grid),
+                   comp=2, sponge_cells=8, sigma_max=smax)
+        t_step[e] = (time.perf_counter() - t1) / steps_sample
+        spent += time.perf_counter() - t0
+    t_job = sum(nsteps * t_step[d[0]] for d in draws) + sum(proj_iters[e] * t_iter[e] for e in proj_iters)
+    updates = nsteps * sum((d[0] - 2) ** 3 for d in draws)
+    return {"value": updates / t_job / 1e9, "unit": "Gcell-updates/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "kind": "oracle",
+            "whole_sweep_s": t_job,
+            "sample": f"per distinct edge ({', '.join(str(e) for e in sorted(proj_iters))}): {steps_sample} steps of "
+                      f"one instance and {cg_sample} Jacobi-PCG iterations of its projection, {spent:.1f} s in all; "
+                      f"value = the whole 64-instance sweep at the sampled rates"}
 
 
 def run_kvline_bench(args):
@@ -857,6 +974,7 @@ def main():
     achieved = bytes_total / (k_ms * 1e-3) / 1e9
     traffic = step_traffic(variant)
     copy_gbs = measured_copy_gbs()  # after the timed region
+    stream_gbs = kvs.kvs_measure_stream(cells, 10) if not args.no_extra_legs else None
     res = {
         "metric": METRIC,
         "value": value,
@@ -894,6 +1012,10 @@ def main():
             "variant": variant,
             "copy_gbs": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
+            "stream_gbs": stream_gbs,
+            "frac_of_stream": achieved / stream_gbs if stream_gbs else None,
+            "stream_note": "kvs_measure_stream: the step's 9 FP32 reads + 6 writes per cell (60 B) with no stencil, "
+                           "over the interior cell count",
         },
         "fdtd_kernel_gcells": args.steps * nsteps * cells / (k_ms * 1e-3) / 1e9,
         "pcie_inclusive": {"value": nsteps * cells / (pcie_ms * 1e-3) / 1e9, "unit": "Gcell-updates/s",
@@ -905,9 +1027,14 @@ def main():
     }
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle sample ({args.cpu_sample_steps} steps, then 4 on one thread)")
-        res["cpu_baseline"] = cpu_baseline(w, dt, smax, FS_host, args.cpu_sample_steps)
+        res["cpu_baseline"] = cpu_baseline(w, dt, smax, FS_host, args.cpu_sample_steps, rep["iters"])
     else:
         res["cpu_baseline"] = None
+    res["config1"] = res["batch"] = res["kvline"] = None
+    if not args.no_extra_legs:
+        res["config1"] = run_config1(args)
+        res["batch"] = run_batch(args, steps=args.batch_steps, warmup=args.batch_warmup)
+        res["kvline"] = run_kvline_bench(args)
     res["projection_learned"] = res["time_varying"] = res["shell"] = res["arf"] = None
     if not args.no_learned:
         net = kvs.kvs_unet_create((16, 32, 64), args.unet_bottleneck)

@@ -173,6 +173,36 @@ kvs_status kvs_set_force(kvs_ctx* ctx, const double* F);
 /* Same from device memory: dtype 0 = double, 1 = float; copied on the
  * context's stream. */
 kvs_status kvs_set_force_device(kvs_ctx* ctx, const void* F, int32_t dtype);
+/* Force pattern from its closed form, generated on the device (replaces the
+ * force and marks the projected force stale, like kvs_set_force): the focused
+ * Gaussian push of a separable source (Sec. 3.3; the Gaussian excitation of
+ * Sec. 4.4) and, with plane-wave modes, a modulated push whose parameters
+ * change between re-projections (a general time-varying source f^n):
+ *   F_axis = F0 exp(-lat^2 / (2 sigma_lateral^2) - ax^2 / (2 sigma_axial^2)) M,
+ *   M = 1 + mod_amp sum_{m < n_modes} cos(k_m . x + phase_m),
+ * other components 0; x = ((i - nx/2) hx, (j - ny/2) hy, (k - nz/2) hz) are
+ * the node coordinates [m] (integer division nx/2), ax = x_axis - centre_axis,
+ * lat^2 the sum of the squared offsets x_a - centre_a over the other two axes.
+ * box_lateral >= 0: F = 0 where some lateral offset exceeds it in magnitude;
+ * box_axial >= 0: likewise |ax|; < 0: no box.  FP64, evaluated in this order
+ * without fused multiply-adds.  axis 0..2, sigmas > 0, 0 <= n_modes <=
+ * KVS_MAX_FORCE_MODES, every value finite, else KVS_EINVAL.  Asynchronous on
+ * the context's stream. */
+#define KVS_MAX_FORCE_MODES 16
+typedef struct {
+    int32_t axis;          /* force component and beam axis, 0..2 */
+    double F0;             /* peak [N/m^3] */
+    double centre[3];      /* focus [m], node coordinates */
+    double sigma_lateral;  /* [m] */
+    double sigma_axial;    /* [m] */
+    double box_lateral;    /* [m], < 0: none */
+    double box_axial;      /* [m], < 0: none */
+    int32_t n_modes;       /* plane-wave modulation modes */
+    double mod_amp;        /* a in M = 1 + a sum cos(...) */
+    double k[KVS_MAX_FORCE_MODES][3]; /* wave vectors [rad/m] */
+    double phase[KVS_MAX_FORCE_MODES]; /* [rad] */
+} kvs_force_pattern;
+kvs_status kvs_set_force_pattern(kvs_ctx* ctx, const kvs_force_pattern* p);
 /* Read back the force pattern (host, 3*N doubles).  No force: KVS_ESTATE.
  * Blocks. */
 kvs_status kvs_get_force(const kvs_ctx* ctx, double* F);
@@ -340,6 +370,13 @@ kvs_status kvs_strain_get(const kvs_ctx* ctx, double* peak_strain, double* peak_
  * the launch count since timing was switched on. */
 kvs_status kvs_enable_kernel_timing(kvs_ctx* ctx, int32_t on);
 kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* launches);
+/* Streaming reference for the roofline of the FDTD step: a kernel with the
+ * step's memory pattern and no stencil (per cell 9 FP32 values read, 6
+ * written: 60 B; 15 contiguous streams of n floats, 16-byte accesses) run
+ * reps times on `device` after one untimed launch; *gbs = 60 n bytes over
+ * the median launch time (HIP events).  Allocates and frees its 15 buffers
+ * (60 n bytes).  n >= 1024, reps >= 1, else KVS_EINVAL. */
+kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* gbs);
 
 /* ---- batched parameter sweeps ----------------------------------------------- */
 

@@ -401,6 +401,27 @@ kvs_status kvs_set_force(kvs_ctx* c, const double* F) {
     return KVS_OK;
 }
 
+kvs_status kvs_set_force_pattern(kvs_ctx* c, const kvs_force_pattern* p) {
+    if (!c) return KVS_EINVAL;
+    if (!p) return fail(c, KVS_EINVAL, "pattern is NULL");
+    if (p->axis < 0 || p->axis > 2) return fail(c, KVS_EINVAL, "axis must be 0..2");
+    if (!finite_pos(p->sigma_lateral) || !finite_pos(p->sigma_axial))
+        return fail(c, KVS_EINVAL, "sigmas must be finite and > 0");
+    if (p->n_modes < 0 || p->n_modes > KVS_MAX_FORCE_MODES) return fail(c, KVS_EINVAL, "n_modes out of range");
+    bool ok = std::isfinite(p->F0) && std::isfinite(p->box_lateral) && std::isfinite(p->box_axial) &&
+              std::isfinite(p->mod_amp);
+    for (int d = 0; d < 3; ++d) ok = ok && std::isfinite(p->centre[d]);
+    for (int m = 0; m < p->n_modes; ++m)
+        ok = ok && std::isfinite(p->k[m][0]) && std::isfinite(p->k[m][1]) && std::isfinite(p->k[m][2]) &&
+             std::isfinite(p->phase[m]);
+    if (!ok) return fail(c, KVS_EINVAL, "pattern value not finite");
+    API_HIP(c, hipSetDevice(c->device));
+    API_HIP(c, kvs_launch_force_pattern(c, p));
+    c->have_force = true;
+    c->fs_current = false;
+    return KVS_OK;
+}
+
 kvs_status kvs_set_force_device(kvs_ctx* c, const void* F, int32_t dtype) {
     if (!c) return KVS_EINVAL;
     if (!F) return fail(c, KVS_EINVAL, "F is NULL");

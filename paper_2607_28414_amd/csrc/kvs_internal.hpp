@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -230,6 +231,10 @@ struct kvs_batch {
     int64_t graph_start = -1, graph_steps = 0, graph_trace0 = -1;
     std::vector<uint8_t> graph_force;
 };
+
+// ---- launchers (kvs_force.hip) ------------------------------------------
+// Write the closed-form force pattern into c->F (3N doubles) on c's stream.
+hipError_t kvs_launch_force_pattern(kvs_ctx* c, const kvs_force_pattern* p);
 
 // ---- launchers (kvs_step.hip) -------------------------------------------
 // One FDTD step from (u[cur], w[cur]) into (u[1-cur], w[1-cur]) with source

@@ -83,6 +83,16 @@ def _opts(precision, sponge_cells, sponge_sigma_max, device, stream, allocator):
     return o
 
 
+KVS_MAX_FORCE_MODES = 16
+
+
+class kvs_force_pattern(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("F0", C.c_double), ("centre", C.c_double * 3),
+                ("sigma_lateral", C.c_double), ("sigma_axial", C.c_double), ("box_lateral", C.c_double),
+                ("box_axial", C.c_double), ("n_modes", C.c_int32), ("mod_amp", C.c_double),
+                ("k", (C.c_double * 3) * KVS_MAX_FORCE_MODES), ("phase", C.c_double * KVS_MAX_FORCE_MODES)]
+
+
 class kvs_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precond", C.c_int32),
                 ("fixed_iters", C.c_int64), ("warm_start", C.c_int32), ("confirm_true", C.c_int32)]
@@ -115,6 +125,7 @@ SIGNATURES = {
     "kvs_set_dt": ([_P, C.c_double], C.c_int),
     "kvs_set_force": ([_P, _D], C.c_int),
     "kvs_set_force_device": ([_P, C.c_void_p, C.c_int32], C.c_int),
+    "kvs_set_force_pattern": ([_P, C.POINTER(kvs_force_pattern)], C.c_int),
     "kvs_get_force": ([_P, _D], C.c_int),
     "kvs_set_envelope": ([_P, _D, C.c_int64], C.c_int),
     "kvs_project": ([_P, C.POINTER(kvs_solve_opts), C.POINTER(kvs_solve_report)], C.c_int),
@@ -180,6 +191,7 @@ SIGNATURES = {
     "kvs_set_step_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
+    "kvs_measure_stream": ([C.c_int32, C.c_int64, C.c_int32, _D], C.c_int),
     "kvs_arf_begin": ([_P, C.c_int32], C.c_int),
     "kvs_strain_begin": ([_P, _D, C.c_int64], C.c_int),
     "kvs_strain_accumulate_device": ([_P, C.c_void_p, C.c_int64, C.c_int32], C.c_int),
@@ -312,6 +324,36 @@ def kvs_set_dt(ctx, dt):
 def kvs_set_force(ctx, F):
     F = _host(ctx, F, 3)
     _check(lib().kvs_set_force(ctx, _dptr(F)), ctx)
+
+
+def kvs_measure_stream(n, reps=10, device=0):
+    """GB/s of the streaming reference kernel (the FDTD step's 9-read /
+    6-write FP32 pattern) over n cells."""
+    out = C.c_double()
+    _check(lib().kvs_measure_stream(int(device), int(n), int(reps), C.byref(out)))
+    return out.value
+
+
+def kvs_set_force_pattern(ctx, axis, F0, centre, sigma_lateral, sigma_axial, box_lateral=-1.0, box_axial=-1.0,
+                          k=(), phase=(), mod_amp=0.0):
+    """Closed-form force pattern generated by the library (marshalling only):
+    the parameters of workloads' pattern dicts."""
+    k = np.asarray(k, dtype=np.float64).reshape(-1, 3)
+    phase = np.asarray(phase, dtype=np.float64).reshape(-1)
+    if len(k) != len(phase) or len(k) > KVS_MAX_FORCE_MODES:
+        raise ValueError("k and phase need the same number of modes, at most KVS_MAX_FORCE_MODES")
+    p = kvs_force_pattern()
+    p.axis, p.F0 = int(axis), float(F0)
+    for d in range(3):
+        p.centre[d] = float(centre[d])
+    p.sigma_lateral, p.sigma_axial = float(sigma_lateral), float(sigma_axial)
+    p.box_lateral, p.box_axial = float(box_lateral), float(box_axial)
+    p.n_modes, p.mod_amp = len(k), float(mod_amp)
+    for m in range(len(k)):
+        for d in range(3):
+            p.k[m][d] = float(k[m, d])
+        p.phase[m] = float(phase[m])
+    _check(lib().kvs_set_force_pattern(ctx, C.byref(p)), ctx)
 
 
 def kvs_set_force_device(ctx, ptr, dtype):

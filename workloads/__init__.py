@@ -65,20 +65,55 @@ def coords(n, h):
     return (np.arange(n) - n // 2) * h
 
 
+def gaussian_push_params(sigma_l, sigma_a, F0, centre=(0.0, 0.0, 0.0), axis=2):
+    """Parameters of the focused Gaussian push (a pattern dict, see
+    force_from_params): no box, no modulation."""
+    return dict(axis=int(axis), F0=float(F0), centre=tuple(float(c) for c in centre), sigma_lateral=float(sigma_l),
+                sigma_axial=float(sigma_a), box_lateral=-1.0, box_axial=-1.0, k=np.zeros((0, 3)),
+                phase=np.zeros(0), mod_amp=0.0)
+
+
+def force_from_params(grid, p):
+    """[3][nz][ny][nx] force of a pattern dict: F_axis = F0 exp(-lat^2 /
+    (2 s_l^2) - ax^2 / (2 s_a^2)) M with M = 1 + a sum_m cos(k_m . x +
+    phi_m), x the node coordinates, ax and lat^2 the axial and lateral
+    offsets from the focus; 0 outside the box (when given).  Evaluated term
+    by term in the order written."""
+    nx, ny, nz, hx, hy, hz = grid
+    axis = p["axis"]
+    x = [coords(nx, hx), coords(ny, hy), coords(nz, hz)]
+    off = [x[d] - p["centre"][d] for d in range(3)]
+    keep = []
+    for d in range(3):
+        box = p["box_axial"] if d == axis else p["box_lateral"]
+        keep.append(np.nonzero(np.abs(off[d]) <= box)[0] if box >= 0 else np.arange(len(off[d])))
+    F = np.zeros((3, nz, ny, nx))
+    ix, iy, iz = keep
+    if ix.size == 0 or iy.size == 0 or iz.size == 0:
+        return F
+    Z, Y, X = np.meshgrid(off[2][iz], off[1][iy], off[0][ix], indexing="ij")
+    O = [X, Y, Z]
+    lat2 = None
+    for d in range(3):
+        if d != axis:
+            lat2 = O[d] * O[d] if lat2 is None else lat2 + O[d] * O[d]
+    ax = O[axis]
+    g = np.exp(-lat2 / (2.0 * (p["sigma_lateral"] * p["sigma_lateral"]))
+               - ax * ax / (2.0 * (p["sigma_axial"] * p["sigma_axial"])))
+    M = np.ones_like(g)
+    if len(p["phase"]):
+        Za, Ya, Xa = np.meshgrid(x[2][iz], x[1][iy], x[0][ix], indexing="ij")
+        for m in range(len(p["phase"])):
+            k = p["k"][m]
+            M = M + p["mod_amp"] * np.cos(k[0] * Xa + k[1] * Ya + k[2] * Za + p["phase"][m])
+    F[axis][np.ix_(iz, iy, ix)] = p["F0"] * g * M
+    return F
+
+
 def gaussian_push(grid, sigma_l, sigma_a, F0, centre=(0.0, 0.0, 0.0), axis=2):
     """F along `axis` = F0 exp(-(lateral^2)/(2 sigma_l^2) - (axial - c)^2/(2 sigma_a^2)).
     Returns the [3][nz][ny][nx] force with only component `axis` non-zero."""
-    nx, ny, nz, hx, hy, hz = grid
-    x = coords(nx, hx) - centre[0]
-    y = coords(ny, hy) - centre[1]
-    z = coords(nz, hz) - centre[2]
-    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
-    pos = [X, Y, Z]
-    axial = pos[axis]
-    lat2 = sum(pos[a] ** 2 for a in range(3) if a != axis)
-    F = np.zeros((3, nz, ny, nx))
-    F[axis] = F0 * np.exp(-lat2 / (2.0 * sigma_l ** 2) - axial ** 2 / (2.0 * sigma_a ** 2))
-    return F
+    return force_from_params(grid, gaussian_push_params(sigma_l, sigma_a, F0, centre, axis))
 
 
 def x_line_probes(grid, j=None, k=None):
@@ -183,17 +218,15 @@ def focal_focus_z(grid, epoch, dt, steps_per_epoch=10, speed=1e-3 / 20e-6):
     return lo + (s if s <= L else 2 * L - s)
 
 
-def focal_modulated_force(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=10, sigma_l=1e-3, sigma_a=4e-3,
-                          F0=1e4, device=None):
-    """Non-separable push of the time-varying workload: F_z = F0 exp(-(x^2 +
-    y^2) / (2 sigma_l^2) - (z - z_f)^2 / (2 sigma_a^2)) M(x), with the focus
-    z_f of `focal_focus_z` and M(x) = 1 + 0.5 / sqrt(8) sum_m cos(k_m . x +
-    phi_m): 8 plane waves, |k_m| uniform in [2 pi / 4 mm, 2 pi / 1 mm] with
-    random directions (fixed by `seed`), phases phi_m redrawn every epoch
-    (seeded by (seed, epoch)).  F is set to 0 where the Gaussian factor is
-    below 1e-16.  Returns [3][nz][ny][nx] FP64: a numpy array, or with
-    `device` a torch tensor built there (same formula, torch's exp and cos)."""
-    nx, ny, nz, hx, hy, hz = grid
+def focal_modulated_params(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=10, sigma_l=1e-3, sigma_a=4e-3,
+                           F0=1e4):
+    """Pattern dict of the time-varying workload's push at `epoch`: a z
+    Gaussian (sigma_l lateral, sigma_a axial) on the lateral centre line
+    focused at the z of `focal_focus_z`, times M(x) = 1 + 0.5 / sqrt(8)
+    sum_m cos(k_m . x + phi_m) with 8 plane waves, |k_m| uniform in
+    [2 pi / 4 mm, 2 pi / 1 mm] with random directions (fixed by `seed`) and
+    phases redrawn every epoch (seeded by (seed, epoch)); F = 0 outside the
+    box where the Gaussian factor is above 1e-16 along each axis."""
     rng = np.random.default_rng(seed)
     kmag = rng.uniform(2 * np.pi / 4e-3, 2 * np.pi / 1e-3, 8)
     dirs = rng.standard_normal((8, 3))
@@ -201,36 +234,17 @@ def focal_modulated_force(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=
     kvec = kmag[:, None] * dirs
     phases = np.random.default_rng([seed, epoch]).uniform(0, 2 * np.pi, 8)
     zf = focal_focus_z(grid, epoch, dt, steps_per_epoch)
-    x, y, z = coords(nx, hx), coords(ny, hy), coords(nz, hz)
     cut = np.sqrt(2 * np.log(1e16))
-    ix = np.nonzero(np.abs(x) <= cut * sigma_l)[0]
-    iy = np.nonzero(np.abs(y) <= cut * sigma_l)[0]
-    iz = np.nonzero(np.abs(z - zf) <= cut * sigma_a)[0]
-    if device is not None:
-        import torch
-        F = torch.zeros((3, nz, ny, nx), dtype=torch.float64, device=device)
-        if ix.size == 0 or iy.size == 0 or iz.size == 0:
-            return F
-        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
-        Z, Y, X = torch.meshgrid(t(z[iz]), t(y[iy]), t(x[ix]), indexing="ij")
-        g = torch.exp(-(X ** 2 + Y ** 2) / (2 * sigma_l ** 2) - (Z - zf) ** 2 / (2 * sigma_a ** 2))
-        M = torch.ones_like(g)
-        for m in range(8):
-            M += 0.5 / np.sqrt(8) * torch.cos(float(kvec[m, 0]) * X + float(kvec[m, 1]) * Y + float(kvec[m, 2]) * Z
-                                              + float(phases[m]))
-        # ix, iy, iz are contiguous index ranges (|coordinate| below a bound)
-        F[2, iz[0]:iz[-1] + 1, iy[0]:iy[-1] + 1, ix[0]:ix[-1] + 1] = F0 * g * M
-        return F
-    F = np.zeros((3, nz, ny, nx))
-    if ix.size == 0 or iy.size == 0 or iz.size == 0:
-        return F
-    Z, Y, X = np.meshgrid(z[iz], y[iy], x[ix], indexing="ij")
-    g = np.exp(-(X ** 2 + Y ** 2) / (2 * sigma_l ** 2) - (Z - zf) ** 2 / (2 * sigma_a ** 2))
-    M = np.ones_like(g)
-    for m in range(8):
-        M += 0.5 / np.sqrt(8) * np.cos(kvec[m, 0] * X + kvec[m, 1] * Y + kvec[m, 2] * Z + phases[m])
-    F[2][np.ix_(iz, iy, ix)] = F0 * g * M
-    return F
+    return dict(axis=2, F0=float(F0), centre=(0.0, 0.0, float(zf)), sigma_lateral=float(sigma_l),
+                sigma_axial=float(sigma_a), box_lateral=float(cut * sigma_l), box_axial=float(cut * sigma_a),
+                k=kvec, phase=phases, mod_amp=0.5 / np.sqrt(8))
+
+
+def focal_modulated_force(grid, seed=1004, epoch=0, dt=1.75e-6, steps_per_epoch=10, sigma_l=1e-3, sigma_a=4e-3,
+                          F0=1e4):
+    """Non-separable push of the time-varying workload (focal_modulated_params)
+    as a [3][nz][ny][nx] FP64 numpy array."""
+    return force_from_params(grid, focal_modulated_params(grid, seed, epoch, dt, steps_per_epoch, sigma_l, sigma_a, F0))
 
 
 def gaussian_random_field(shape, h, corr_len, rng):
