@@ -833,16 +833,21 @@ def run_kvline_bench(args):
             kvs.kvs_batch_set_probes(b, i, case["probes"])
             cases.append(case)
         kvs.kvs_batch_set_component(b, 2)
-        log(f"bench: kv line sweep, {n} instances, {nsteps} steps (graph capture)")
+        persistent = kvs.kvs_batch_uses_persistent(b)
+        log(f"bench: kv line sweep, {n} instances, {nsteps} steps ("
+            + ("one persistent launch" if persistent else "graph capture") + ")")
         kvs.kvs_batch_step(b, nsteps)
+        # events on the batch's own stream (the library makes one when it is
+        # handed the null stream)
+        lib_stream = torch.cuda.ExternalStream(kvs.kvs_stream(kvs.kvs_batch_instance(b, 0)))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ms = []
         for _ in range(max(1, args.steps)):
             kvs.kvs_batch_reset(b)
             torch.cuda.synchronize()
-            e0.record(stream)
-            kvs.kvs_batch_step(b, nsteps)  # same start, length and trace slot: replay
-            e1.record(stream)
+            e0.record(lib_stream)
+            kvs.kvs_batch_step(b, nsteps)
+            e1.record(lib_stream)
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         tr = kvs.kvs_batch_read_traces(b, n - 1, len(cases[-1]["probes"]))
@@ -851,7 +856,9 @@ def run_kvline_bench(args):
         kvs.kvs_batch_destroy(b)
     gpu_ms = float(np.median(ms))
     res = {"workload": f"1-D harmonic Kelvin-Voigt sweep: {n} viscosities (0-1.5 Pa s) as one FP32 batch of "
-                       f"{grid[0]}x3x3 lines, h 0.1 mm, {nsteps} steps (16 ms), one hipGraph",
+                       f"{grid[0]}x3x3 lines, h 0.1 mm, {nsteps} steps (16 ms), "
+                       + ("one persistent launch (state in LDS, one workgroup per line)" if persistent
+                          else "one hipGraph of per-step launches"),
            "ms_per_sweep": gpu_ms, "us_per_step": 1e3 * gpu_ms / nsteps, "instances": n, "fdtd_steps": nsteps,
            "cpu_baseline": None}
     if not args.no_cpu_baseline:

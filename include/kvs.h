@@ -413,6 +413,15 @@ kvs_status kvs_batch_trace_count(const kvs_batch* b, int64_t* nsteps_recorded);
 /* Traces of instance i, [step][probe] doubles, into out (cap doubles). */
 kvs_status kvs_batch_read_traces(kvs_batch* b, int32_t i, double* out, int64_t cap, int64_t* n_written);
 
+/* Persistent runs of small instances (on by default): when every instance's
+ * whole state (u and w, 24 B per node in FP32, 48 B in FP64) fits in 150 KB,
+ * a kvs_batch_step run is one launch with one workgroup per instance that
+ * keeps the state in LDS and advances it through all the steps (two
+ * workgroup barriers per step, probes written after every step), instead of
+ * one launch per step.  on = 0 keeps the per-step launches.
+ * kvs_batch_uses_persistent reports whether the next run takes that path. */
+kvs_status kvs_batch_set_persistent(kvs_batch* b, int32_t on);
+kvs_status kvs_batch_uses_persistent(const kvs_batch* b, int32_t* on);
 /* Batch tile shape (a step-kernel variant, as for kvs_set_step_variant) and
  * z planes per block (>= 1). */
 kvs_status kvs_batch_set_tuning(kvs_batch* b, int32_t variant, int32_t zchunk);

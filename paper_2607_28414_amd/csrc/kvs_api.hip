@@ -1213,11 +1213,14 @@ static kvs_status batch_upload_probes(kvs_batch* b) {
     b->graph_valid = false;
     b->host_traces_valid = false;
     if (np == 0) return KVS_OK;
-    std::vector<int64_t> flat(2 * np);
+    // (instance, cell) pairs, then the first probe of every instance (n + 1
+    // entries: the persistent path finds its instance's probes there)
+    std::vector<int64_t> flat(2 * np + b->probe_first.size());
     for (size_t p = 0; p < np; ++p) {
         flat[2 * p] = b->probe_inst[p];
         flat[2 * p + 1] = b->probe_cell[p];
     }
+    std::copy(b->probe_first.begin(), b->probe_first.end(), flat.begin() + 2 * np);
     BATCH_HIP(b, b->mem.get(&b->dev_probes, sizeof(int64_t) * flat.size()));
     BATCH_HIP(b, hipMemcpyAsync(b->dev_probes, flat.data(), sizeof(int64_t) * flat.size(), hipMemcpyHostToDevice,
                                 b->stream));
@@ -1313,6 +1316,19 @@ kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
     b->step += nsteps;
     if (np > 0) b->trace_steps += nsteps;
     b->host_traces_valid = false;
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_set_persistent(kvs_batch* b, int32_t on) {
+    if (!b) return KVS_EINVAL;
+    b->small_ok = on != 0;
+    b->graph_valid = false;
+    return KVS_OK;
+}
+
+kvs_status kvs_batch_uses_persistent(const kvs_batch* b, int32_t* on) {
+    if (!b || !on) return KVS_EINVAL;
+    *on = kvs_batch_small_path(b) ? 1 : 0;
     return KVS_OK;
 }
 

@@ -206,6 +206,7 @@ struct kvs_batch {
     std::string err;
     int comp = 2;
     int64_t step = 0;  // common step index of all instances
+    bool small_ok = true;  // use the persistent one-block-per-instance run when every instance fits
     int variant = 1;   // tile shape (index into the step-kernel variants)
     int zchunk = 32;   // z planes per block
 
@@ -283,6 +284,9 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
 hipError_t kvs_batch_prepare(kvs_batch* b);
 hipError_t kvs_batch_trial_launch(kvs_batch* b);
 hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps);
+// True when kvs_batch_run takes the persistent path (every instance's state
+// fits one workgroup's LDS and the path is enabled).
+bool kvs_batch_small_path(const kvs_batch* b);
 
 // ---- learned preconditioner (kvs_unet.hip) ---------------------------------
 // Inner products the flexible PCG needs from the preconditioned residual z,

@@ -911,7 +911,239 @@ hipError_t capture_t(kvs_batch* b, int64_t nsteps, const std::vector<uint8_t>& f
     return hipGetLastError();
 }
 
+// ---- persistent path for small instances -----------------------------------
+//
+// When every instance's whole state (u and w, three components each) fits in
+// one workgroup's LDS, a batch run is one launch of one block per instance
+// that advances its instance through all the steps in the kernel: the state
+// lives in LDS for the whole run, the block's threads own fixed interior
+// cells, and two block barriers per step separate reading the old state from
+// writing the new one; probe values are written after every step.  The
+// per-cell arithmetic is the step kernel's (same operand order, sponge
+// factors and FP32 reciprocal), so one launch replaces two launches per step
+// and the run is bound by the latency of a step, not by launches.
+constexpr int kSmallMaxThreads = 1024;
+constexpr int kSmallChunk = 64;  // steps whose envelope and probe values are staged in LDS at a time
+constexpr size_t kSmallMaxLds = 150 * 1024;
+
+// LINE: every instance is a line (ny = nz = 3): the y and z neighbours of an
+// interior node lie on the Dirichlet layer and are exactly 0, so they are
+// taken as the constant 0 instead of read (the same arithmetic).
+template <typename T, bool VISC, int CPT, bool LINE>
+__global__ __launch_bounds__(kSmallMaxThreads) void batch_small_kernel(const BatchInst<T>* inst, const long long* probes,
+                                                                       const long long* probe_first, int np, int comp,
+                                                                       double* traces, long long step0,
+                                                                       long long nsteps) {
+    extern __shared__ __align__(16) unsigned char small_lds[];
+    const int nthr = blockDim.x;
+    // everything the step loop needs is read once: the loop's stores to the
+    // traces would otherwise make the compiler re-read it every step
+    const StepArgs<T> a = inst[blockIdx.x].a[0];  // parity 0: the buffers current at the start of the run
+    // the envelope through a global-memory pointer: a generic (flat) load
+    // could alias LDS, which would order every LDS access behind it
+    typedef const __attribute__((address_space(1))) double* genv_t;
+    const genv_t env = (genv_t)inst[blockIdx.x].env;
+    const long long n_env = inst[blockIdx.x].n_env;
+    const int N = (int)a.N;
+    T* su = reinterpret_cast<T*>(small_lds);  // [3][N]
+    T* sw = su + 3 * N;                        // [3][N]
+    T* senv = sw + 3 * N;                      // [kSmallChunk]: the chunk's envelope values
+    const long long pf = np > 0 ? probe_first[blockIdx.x] : 0;
+    const int npi = np > 0 ? (int)(probe_first[blockIdx.x + 1] - pf) : 0;
+    T* strace = senv + kSmallChunk;                                     // [kSmallChunk][npi]: probe values
+    int* sprobe = reinterpret_cast<int*>(strace + kSmallChunk * npi);  // this instance's probe cells
+    for (int q = threadIdx.x; q < 3 * N; q += nthr) {
+        su[q] = a.u[q];
+        sw[q] = a.w[q];
+    }
+    for (int p = threadIdx.x; p < npi; p += nthr) sprobe[p] = comp * N + (int)probes[2 * (pf + p) + 1];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nxi = nx - 2, nyi = ny - 2, nint = nxi * nyi * (nz - 2);
+    const int sy = nx, sz = nx * ny;
+    // owned cells: their index, sponge factors, f_S and own u, w (registers)
+    int cell[CPT];
+    T a1[CPT], a2[CPT], fs[CPT][3], ur[CPT][3], wr[CPT][3];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int t = threadIdx.x + m * nthr;
+        cell[m] = -1;
+        a1[m] = a2[m] = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fs[m][c] = ur[m][c] = wr[m][c] = T(0);
+        if (t < nint) {
+            const int i = 1 + t % nxi, j = 1 + (t / nxi) % nyi, k = 1 + t / (nxi * nyi);
+            const int q = i + nx * (j + ny * k);
+            cell[m] = q;
+            const T r = a.L > 0 ? max(max(ramp<T>(i, nx, a.L, a.invL), ramp<T>(j, ny, a.L, a.invL)),
+                                      ramp<T>(k, nz, a.L, a.invL))
+                                : T(0);
+            const T s = a.half_dt_smax * r;
+            const T inv1ps = rcp_fast<T>(T(1) + s);
+            a1[m] = (T(1) - s) * inv1ps;
+            a2[m] = a.crho0 * inv1ps;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fs[m][c] = a.FS[c * a.N + q];
+                ur[m][c] = a.u[c * a.N + q];
+                wr[m][c] = a.w[c * a.N + q];
+            }
+        }
+    }
+    const T gx = a.G0 * a.ihx2, gy = a.G0 * a.ihy2, gz = a.G0 * a.ihz2;
+    const T ihx2 = a.ihx2, ihy2 = a.ihy2, ihz2 = a.ihz2, eta_dt = a.eta_dt0;
+    for (long long st0 = 0; st0 < nsteps; st0 += kSmallChunk) {
+        const int cn = (int)min((long long)kSmallChunk, nsteps - st0);
+        // the chunk's envelope values: global memory is touched only here and
+        // in the flush of the chunk's probe values below, so the step loop
+        // itself waits on LDS alone
+        for (int q = threadIdx.x; q < cn; q += nthr) {
+            const long long n = step0 + st0 + q;
+            senv[q] = n < n_env ? T(env[n]) : T(0);
+        }
+        lds_barrier();
+        for (int sc = 0; sc < cn; ++sc) {
+            const T gn = senv[sc];
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                if (cell[m] < 0) continue;
+                const int c0 = cell[m];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T* u = su + c * N;
+                    const T uc = ur[m][c];
+                    const T uyp = LINE ? T(0) : u[c0 + sy], uym = LINE ? T(0) : u[c0 - sy];
+                    const T uzp = LINE ? T(0) : u[c0 + sz], uzm = LINE ? T(0) : u[c0 - sz];
+                    T acc = gx * (u[c0 + 1] - uc) - gx * (uc - u[c0 - 1]) + gy * (uyp - uc) - gy * (uc - uym)
+                          + gz * (uzp - uc) - gz * (uc - uzm);
+                    const T wc = wr[m][c];
+                    if constexpr (VISC) {
+                        const T* w = sw + c * N;
+                        const T wyp = LINE ? T(0) : w[c0 + sy], wym = LINE ? T(0) : w[c0 - sy];
+                        const T wzp = LINE ? T(0) : w[c0 + sz], wzm = LINE ? T(0) : w[c0 - sz];
+                        const T lw = (w[c0 + 1] + w[c0 - 1] - T(2) * wc) * ihx2 + (wyp + wym - T(2) * wc) * ihy2
+                                   + (wzp + wzm - T(2) * wc) * ihz2;
+                        acc += eta_dt * lw;
+                    }
+                    if (gn != T(0)) acc += gn * fs[m][c];
+                    const T wnew = a1[m] * wc + a2[m] * acc;
+                    wr[m][c] = wnew;
+                    ur[m][c] = uc + wnew;
+                }
+            }
+            lds_barrier();  // every read of the old state is done
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (cell[m] >= 0)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        su[c * N + cell[m]] = ur[m][c];
+                        if constexpr (VISC) sw[c * N + cell[m]] = wr[m][c];
+                    }
+            lds_barrier();  // the new state is complete
+            for (int p = threadIdx.x; p < npi; p += nthr) strace[sc * npi + p] = su[sprobe[p]];
+        }
+        lds_barrier();  // the chunk's probe values are complete
+        for (int q = threadIdx.x; q < cn * npi; q += nthr)
+            traces[(st0 + q / npi) * (long long)np + pf + q % npi] = (double)strace[q];
+        // the next chunk writes senv and strace only after the barrier that
+        // follows its envelope load, i.e. after these reads
+    }
+    // the run leaves the instance's state in the buffers current after nsteps
+    // (w in LDS is stale without viscosity: the registers hold it)
+    T* du = (nsteps & 1) ? a.un : const_cast<T*>(a.u);
+    T* dw = (nsteps & 1) ? a.wn : const_cast<T*>(a.w);
+#pragma unroll
+    for (int m = 0; m < CPT; ++m)
+        if (cell[m] >= 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sw[c * N + cell[m]] = wr[m][c];
+    lds_barrier();
+    for (int q = threadIdx.x; q < 3 * N; q += nthr) {
+        du[q] = su[q];
+        dw[q] = sw[q];
+    }
+}
+
+// LDS of the persistent kernel: the state (6 N values), a chunk's envelope
+// and probe values, and the probe cells, for the instance with the most
+// probes.
+template <typename T>
+size_t small_lds_bytes(const kvs_batch* b, const kvs_ctx* c) {
+    int64_t most = 0;
+    for (size_t i = 0; i + 1 < b->probe_first.size(); ++i)
+        most = std::max<int64_t>(most, b->probe_first[i + 1] - b->probe_first[i]);
+    return (6 * (size_t)c->N + kSmallChunk * (1 + (size_t)most)) * sizeof(T) + sizeof(int) * (size_t)most;
+}
+
+// Threads per workgroup (a multiple of 64, at most 1024, enough for one
+// interior cell each where possible) and cells per thread.
+template <typename T>
+bool small_fits(const kvs_batch* b, int* cpt, int* threads) {
+    long long most = 1;
+    for (const kvs_ctx* c : b->inst) {
+        const kvs_grid& g = c->grid;
+        if (small_lds_bytes<T>(b, c) > kSmallMaxLds) return false;
+        most = std::max<long long>(most, (g.nx - 2) * (g.ny - 2) * (g.nz - 2));
+    }
+    const int thr = (int)std::min<long long>(kSmallMaxThreads, 64 * ((most + 63) / 64));
+    const long long need = (most + thr - 1) / thr;
+    if (need > 8) return false;
+    *threads = thr;
+    *cpt = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+    return true;
+}
+
+template <typename T, bool VISC, int CPT, bool LINE>
+hipError_t launch_small_shape(kvs_batch* b, int64_t nsteps, int threads) {
+    size_t lds = 0;
+    for (const kvs_ctx* c : b->inst) lds = std::max(lds, small_lds_bytes<T>(b, c));
+    static bool attr_set = false;  // one attribute call per instantiation
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)batch_small_kernel<T, VISC, CPT, LINE>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallMaxLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int np = (int)b->probe_inst.size();
+    const long long* pr = static_cast<const long long*>(b->dev_probes);
+    double* tr = np > 0 ? b->traces + b->trace_steps * np : nullptr;
+    hipLaunchKernelGGL((batch_small_kernel<T, VISC, CPT, LINE>), dim3((unsigned)b->inst.size()), dim3(threads), lds,
+                       b->stream, static_cast<const BatchInst<T>*>(b->dev_params), pr, np > 0 ? pr + 2 * np : nullptr,
+                       np, b->comp, tr, (long long)b->step, (long long)nsteps);
+    return hipGetLastError();
+}
+
+template <typename T, bool VISC>
+hipError_t launch_small(kvs_batch* b, int64_t nsteps, int cpt, int threads) {
+    bool line = true;
+    for (const kvs_ctx* c : b->inst) line = line && c->grid.ny == 3 && c->grid.nz == 3;
+    if (line) {
+        switch (cpt) {
+            case 1: return launch_small_shape<T, VISC, 1, true>(b, nsteps, threads);
+            case 2: return launch_small_shape<T, VISC, 2, true>(b, nsteps, threads);
+            case 4: return launch_small_shape<T, VISC, 4, true>(b, nsteps, threads);
+            default: return launch_small_shape<T, VISC, 8, true>(b, nsteps, threads);
+        }
+    }
+    switch (cpt) {
+        case 1: return launch_small_shape<T, VISC, 1, false>(b, nsteps, threads);
+        case 2: return launch_small_shape<T, VISC, 2, false>(b, nsteps, threads);
+        case 4: return launch_small_shape<T, VISC, 4, false>(b, nsteps, threads);
+        default: return launch_small_shape<T, VISC, 8, false>(b, nsteps, threads);
+    }
+}
+
+template <typename T>
+hipError_t run_small_t(kvs_batch* b, int64_t nsteps, int cpt, int threads) {
+    return b->viscous ? launch_small<T, true>(b, nsteps, cpt, threads) : launch_small<T, false>(b, nsteps, cpt, threads);
+}
+
 }  // namespace
+
+bool kvs_batch_small_path(const kvs_batch* b) {
+    int cpt = 0, thr = 0;
+    return b->small_ok && (b->prec == KVS_FP32 ? small_fits<float>(b, &cpt, &thr) : small_fits<double>(b, &cpt, &thr));
+}
 
 // One uncaptured step launch that only rewrites the next buffers (parity 0,
 // no force): used to time tile shapes without advancing the state.
@@ -931,6 +1163,9 @@ hipError_t kvs_batch_prepare(kvs_batch* b) {
 }
 
 hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
+    int cpt = 0, thr = 0;
+    if (b->small_ok && (b->prec == KVS_FP32 ? small_fits<float>(b, &cpt, &thr) : small_fits<double>(b, &cpt, &thr)))
+        return b->prec == KVS_FP32 ? run_small_t<float>(b, nsteps, cpt, thr) : run_small_t<double>(b, nsteps, cpt, thr);
     // Replay the cached graph when it was captured for the same start step,
     // step count, trace slot and per-step force switch (the parameter table
     // and envelopes it reads were refreshed in place by kvs_batch_prepare);

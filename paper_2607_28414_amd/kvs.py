@@ -163,6 +163,8 @@ SIGNATURES = {
     "kvs_batch_trace_count": ([_P, _I64], C.c_int),
     "kvs_batch_read_traces": ([_P, C.c_int32, _D, C.c_int64, _I64], C.c_int),
     "kvs_batch_set_tuning": ([_P, C.c_int32, C.c_int32], C.c_int),
+    "kvs_batch_set_persistent": ([_P, C.c_int32], C.c_int),
+    "kvs_batch_uses_persistent": ([_P, C.POINTER(C.c_int32)], C.c_int),
     "kvs_unet_create": ([C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_void_p)], C.c_int),
     "kvs_unet_destroy": ([_P], None),
     "kvs_unet_last_error": ([_P], C.c_char_p),
@@ -547,6 +549,16 @@ def kvs_batch_create(grids, precision=KVS_FP32, sponge_cells=0, sponge_sigma_max
     if allocator is not None:
         _ALLOCATORS[out.value] = allocator
     return out
+
+
+def kvs_batch_set_persistent(b, on):
+    _bcheck(lib().kvs_batch_set_persistent(b, int(bool(on))), b)
+
+
+def kvs_batch_uses_persistent(b):
+    out = C.c_int32()
+    _bcheck(lib().kvs_batch_uses_persistent(b, C.byref(out)), b)
+    return bool(out.value)
 
 
 def kvs_batch_destroy(b):

@@ -253,3 +253,83 @@ def test_batch_sweep_edges_96_and_160_match_oracle(kvs):
         err = rel_l2(traces[i], tr_o[:, :, 0])
         say(f"edge {grid[0]}: tile variant {v}, z {z}, rel L2 {err:.2e}")
         assert err < 2e-5, (grid[0], err)
+
+
+SMALL = [  # (nx, ny, nz), G, eta: every state fits one workgroup's LDS (FP64: 48 B per node, <= 3200 nodes)
+    ((13, 14, 15), 2e3, 0.0),
+    ((12, 18, 9), 5e3, 0.7),
+    ((17, 11, 13), 1e3, 1.5),
+    ((9, 9, 9), 8e3, 0.2),
+]
+
+
+def make_small_batch(kvs, precision, cases=SMALL, L=2):
+    grids = [tuple(s) + (H, H, H) for s, _, _ in cases]
+    b = kvs.kvs_batch_create(grids, precision=precision, sponge_cells=L, sponge_sigma_max=800.0)
+    info = []
+    for i, (_, G, eta) in enumerate(cases):
+        grid = grids[i]
+        ctx = kvs.kvs_batch_instance(b, i)
+        F = gaussian_push(grid, 0.5e-3, 1.0e-3, 1e4) + 30.0 * np.random.default_rng(i).standard_normal(
+            (3, grid[2], grid[1], grid[0]))
+        FS_o, _, _ = oracle.project(grid, F, tol=1e-12)
+        dt, env = setup_instance(kvs, ctx, grid, G, eta, F, FS=FS_o)
+        env = np.concatenate([env, [0.0, 0.5, 0.0, 1.0]])  # switches on and off
+        kvs.kvs_set_envelope(ctx, env)
+        probes = np.array([[ii, grid[1] // 2, grid[2] // 2] for ii in range(grid[0])])
+        kvs.kvs_batch_set_probes(b, i, probes)
+        info.append((grid, G, eta, FS_o, dt, env, probes))
+    kvs.kvs_batch_set_component(b, 1)
+    return b, info
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_small_batch_matches_oracle(kvs, precision):
+    """Small instances take the persistent path (one launch for the whole run,
+    state in LDS): traces of the y component against the oracle (FP64 1e-12,
+    FP32 2e-5) over a run split at an odd step, the final state equal to the
+    oracle's; the per-step path gives the same traces to the bar."""
+    say(f"case persistent small batch precision {precision}")
+    b, info = make_small_batch(kvs, precision)
+    try:
+        assert kvs.kvs_batch_uses_persistent(b)
+        kvs.kvs_batch_step(b, 37)
+        kvs.kvs_batch_step(b, 53)
+        traces = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+        states = [kvs.kvs_get_state(kvs.kvs_batch_instance(b, i), (g[2], g[1], g[0])) for i, (g, *_) in
+                  enumerate(info)]
+        kvs.kvs_batch_reset(b)
+        kvs.kvs_batch_set_persistent(b, False)
+        assert not kvs.kvs_batch_uses_persistent(b)
+        kvs.kvs_batch_step(b, 90)
+        tiled = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    bar = 1e-12 if precision == 0 else 2e-5
+    for i, (grid, G, eta, FS_o, dt, env, probes) in enumerate(info):
+        u_o, w_o, tr_o = oracle.run(grid, G, 1000.0, eta, dt, 90, FS=FS_o, env=env, probes=probes, comp=1,
+                                    sponge_cells=2, sigma_max=800.0)
+        err = rel_l2(traces[i], tr_o[:, :, 0])
+        say(f"instance {i} {grid[:3]}: persistent rel L2 {err:.2e}, per-step {rel_l2(tiled[i], tr_o[:, :, 0]):.2e}")
+        assert err < bar and rel_l2(tiled[i], tr_o[:, :, 0]) < bar, (i, err)
+        u, w, step = states[i]
+        assert step == 90
+        assert rel_l2(u, u_o) < bar and rel_l2(w, w_o) < bar
+
+
+def test_persistent_path_needs_every_instance_to_fit(kvs):
+    """One instance too large for a workgroup's LDS sends the whole batch to
+    the per-step launches; the small instances still match the oracle."""
+    say("case persistent fallback")
+    cases = SMALL[:2] + [((30, 28, 26), 5e3, 0.7)]
+    b, info = make_small_batch(kvs, 1, cases=cases)
+    try:
+        assert not kvs.kvs_batch_uses_persistent(b)
+        kvs.kvs_batch_step(b, 40)
+        traces = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    for i, (grid, G, eta, FS_o, dt, env, probes) in enumerate(info):
+        _, _, tr_o = oracle.run(grid, G, 1000.0, eta, dt, 40, FS=FS_o, env=env, probes=probes, comp=1,
+                                sponge_cells=2, sigma_max=800.0)
+        assert rel_l2(traces[i], tr_o[:, :, 0]) < 2e-5

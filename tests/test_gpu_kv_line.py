@@ -19,7 +19,7 @@ from workloads import KV_LINE_ETAS, kv_line_case, kv_line_frequency, kv_line_gri
 pytestmark = pytest.mark.gpu
 G, RHO = 4e3, 1000.0
 T_RUN = 16e-3
-CHUNK = 4096  # steps per kvs_batch_step call (one captured graph each)
+CHUNK = 4096  # steps per kvs_batch_step call
 
 
 @pytest.fixture(scope="module")
@@ -74,6 +74,7 @@ def test_kv_line_sweep_batch(kvs, sweep, precision):
             kvs.kvs_set_projected_force(ctx, cases[i]["FS"])
             kvs.kvs_batch_set_probes(b, i, cases[i]["probes"])
         kvs.kvs_batch_set_component(b, 2)
+        assert kvs.kvs_batch_uses_persistent(b)  # line instances run as one launch per call
         t0 = time.perf_counter()
         done = 0
         while done < nsteps:
@@ -81,8 +82,7 @@ def test_kv_line_sweep_batch(kvs, sweep, precision):
             kvs.kvs_batch_step(b, m)
             done += m
         tr = [kvs.kvs_batch_read_traces(b, i, len(cases[i]["probes"])) for i in range(n)]
-        say(f"kv line sweep: {nsteps} steps of {n} instances in {1e3 * (time.perf_counter() - t0):.0f} ms "
-            f"(graph capture included)")
+        say(f"kv line sweep: {nsteps} steps of {n} instances in {1e3 * (time.perf_counter() - t0):.0f} ms")
     finally:
         kvs.kvs_batch_destroy(b)
     tol = 1e-12 if precision == 0 else 2e-5
