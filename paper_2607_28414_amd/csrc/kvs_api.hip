@@ -584,9 +584,14 @@ kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
         API_HIP(c, kvs_pml_build(c));
         c->pml_dirty = false;
     }
+    // The probe values of a step's result are recorded by extra blocks of the
+    // next step's launch, which read that launch's input state: one launch
+    // per step, and one gather after the last step of the call.
+    const int64_t per_slot = c->nprobes * ncomp_of(c->probe_comp);
     for (int64_t q = 0; q < nsteps; ++q) {
         const int64_t n = c->step;
         const double gn = n < n_env ? c->env[(size_t)n] : 0.0;
+        if (c->nprobes > 0 && q > 0) c->probe_fused_out = c->traces + (c->trace_steps - 1) * per_slot;
         if (c->timing) {
             hipEvent_t ea = nullptr, eb = nullptr;
             s = next_event_pair(c, &ea, &eb);
@@ -596,16 +601,15 @@ kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
         }
         const hipError_t le = kvs_launch_step(c, gn);
         c->launch_ev[0] = c->launch_ev[1] = nullptr;
+        c->probe_fused_out = nullptr;
         API_HIP(c, le);
         if (c->pml_cells > 0) API_HIP(c, kvs_launch_pml(c, gn));
         c->cur = 1 - c->cur;
-        if (c->nprobes > 0) {
-            API_HIP(c, kvs_launch_probe_gather(c, c->u[c->cur], c->trace_steps));
-            c->trace_steps += 1;
-        }
+        if (c->nprobes > 0) c->trace_steps += 1;  // slot filled by the next launch or the gather below
         if (c->npeak > 0) API_HIP(c, kvs_launch_peak_update(c, c->u[c->cur]));
         c->step += 1;
     }
+    if (c->nprobes > 0 && nsteps > 0) API_HIP(c, kvs_launch_probe_gather(c, c->u[c->cur], c->trace_steps - 1));
     return KVS_OK;
 }
 

@@ -120,6 +120,9 @@ struct kvs_ctx {
     int64_t* probe_cells = nullptr;
     int64_t nprobes = 0;
     int probe_comp = 2;
+    // trace slot that the probe blocks of the step launch being issued fill
+    // with the launch's input state (null: no probe blocks)
+    double* probe_fused_out = nullptr;
     double* traces = nullptr;
     int64_t trace_cap = 0;    // steps of capacity
     int64_t trace_steps = 0;  // steps recorded

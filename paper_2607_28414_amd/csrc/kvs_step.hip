@@ -54,6 +54,14 @@ struct StepArgs {
     T gn;
     T half_dt_smax;  // sigma_max * dt / 2
     int remap;       // 1: XCD-contiguous tile order
+    // probe blocks: the first pblocks blocks of a launch copy the input state
+    // (the previous step's result) at the probe cells into pout (probe p of
+    // component pcomp at pout[p], or all components at pout[3 p + c]); the
+    // remaining blocks are the tiles
+    const long long* pcells;
+    double* pout;
+    long long np;
+    int pcomp, pblocks;
 };
 
 template <typename T>
@@ -376,8 +384,23 @@ __device__ __forceinline__ void step_tile(const StepArgs<T>& a, int bx, int by, 
 template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WX, int WPE>
 __global__ __launch_bounds__(64 * WX * BY) __attribute__((amdgpu_waves_per_eu(WPE))) void step_kernel(
     const StepArgs<T> a) {
+    if ((int)blockIdx.x < a.pblocks) {
+        const long long p = (long long)blockIdx.x * (64 * WX * BY) + threadIdx.y * (64 * WX) + threadIdx.x;
+        if (p < a.np) {
+            const long long q = a.pcells[p];
+            if (a.pcomp == 3) {
+                a.pout[3 * p] = (double)a.u[q];
+                a.pout[3 * p + 1] = (double)a.u[a.N + q];
+                a.pout[3 * p + 2] = (double)a.u[2 * a.N + q];
+            } else {
+                a.pout[p] = (double)a.u[a.pcomp * a.N + q];
+            }
+        }
+        return;
+    }
     const int B = a.gx * a.gy * a.gz;
-    const int t = a.remap ? tile_of(blockIdx.x, B) : (int)blockIdx.x;
+    const int b = (int)blockIdx.x - a.pblocks;
+    const int t = a.remap ? tile_of(b, B) : b;
     step_tile<T, HET, VISC, FORCE, BY, VEC, WX>(a, t % a.gx, (t / a.gx) % a.gy, t / (a.gx * a.gy));
 }
 
@@ -435,7 +458,8 @@ hipError_t launch_shape(kvs_ctx* c, StepArgs<T> a) {
     a.gy = (a.ny + BY - 1) / BY;
     a.kchunk = c->step_zchunk > 0 ? std::min(c->step_zchunk, a.nz - 2) : choose_kchunk(a.gx * a.gy, a.nz - 2, cap);
     a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
-    const int blocks = a.gx * a.gy * a.gz;
+    a.pblocks = a.pout ? (int)((a.np + 64 * WX * BY - 1) / (64 * WX * BY)) : 0;
+    const int blocks = a.gx * a.gy * a.gz + a.pblocks;
     if (c->launch_ev[0])
         hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(64 * WX, BY), 0, c->stream, c->launch_ev[0],
                               c->launch_ev[1], 0, a);
@@ -496,6 +520,12 @@ hipError_t launch_step_t(kvs_ctx* c, double gn, int variant) {
     a.gn = T(gn);
     a.half_dt_smax = T(0.5 * c->sigma_max * c->dt);
     a.remap = c->step_remap;
+    if (c->probe_fused_out) {
+        a.pcells = reinterpret_cast<const long long*>(c->probe_cells);
+        a.pout = c->probe_fused_out;
+        a.np = c->nprobes;
+        a.pcomp = c->probe_comp;
+    }
     const bool F = gn != 0.0;
     if (c->hetero) {
         if (c->viscous)

@@ -651,3 +651,42 @@ def test_torch_allocator_context_and_batch(kvs):
         kvs._check(kvs.lib().kvs_create(kvs.C.byref(kvs.kvs_grid(8, 8, 8, 1e-3, 1e-3, 1e-3)), kvs.C.byref(o),
                                         kvs.C.byref(out)))
     assert e.value.status == kvs.KVS_EINVAL
+
+
+@pytest.mark.parametrize("comp", [1, 3])
+def test_probes_recorded_by_the_next_step_launch(kvs, comp):
+    """Probe values of a step's result are recorded by extra blocks of the
+    next step's launch (from its input state) and, after the last step of a
+    call, by one gather: probes on the Dirichlet faces i = 0, nx - 1, j = 0,
+    ny - 1 and (second pass) z = 0, a repeated cell, cells of several tiles and
+    planes, two calls with a change of tile shape between them - FP64 traces
+    equal to the oracle's to 1e-12."""
+    grid, G, rho, eta, F = hetero_case((70, 21, 37), 43)
+    nx, ny, nz = grid[:3]
+    dt = 0.5 * oracle.stable_dt(grid, G, rho, eta)
+    FS_o, _, _ = oracle.project(grid, F, tol=1e-12)
+    env = np.array([1.0, 0.5, 1.0])
+    pts = [[0, 10, 18], [nx - 1, 10, 18], [5, 0, 3], [6, ny - 1, nz - 2], [33, 10, 18], [33, 10, 18], [64, 20, 1],
+           [65, 7, 30], [1, 1, 1], [68, 19, 35], [12, 9, 18], [12, 9, 19]]
+    for extra in ([], [[4, 4, 0]]):
+        say(f"case fused probes comp {comp}, extra {extra}")
+        probes = np.array(pts + extra)
+        _, _, tr_o = oracle.run(grid, G, rho, eta, dt, 50, FS=FS_o, env=env, probes=probes, comp=comp, sponge_cells=3,
+                                sigma_max=1500.0)
+        ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP64, sponge_cells=3, sponge_sigma_max=1500.0)
+        try:
+            kvs.kvs_set_material(ctx, G, rho, eta)
+            kvs.kvs_set_dt(ctx, dt)
+            kvs.kvs_set_projected_force(ctx, FS_o)
+            kvs.kvs_set_envelope(ctx, env)
+            kvs.kvs_set_probes(ctx, probes, comp)
+            kvs.kvs_set_step_variant(ctx, 1)
+            kvs.kvs_step(ctx, 23)
+            kvs.kvs_set_step_variant(ctx, 5)  # another tile shape from step 23 on
+            kvs.kvs_step(ctx, 27)
+            tr = kvs.kvs_read_traces(ctx, len(probes), 3 if comp == 3 else 1)
+        finally:
+            kvs.kvs_destroy(ctx)
+        assert tr.shape == tr_o.shape
+        assert rel_l2(tr, tr_o) < 1e-12, rel_l2(tr, tr_o)
+        assert not tr[:, :4].any() and not tr[:, -1].any() if extra else not tr[:, :4].any()
