@@ -323,14 +323,15 @@ def arf_workload(args):
     import torch
 
     from paper_2607_28414_amd import kvs
-    from workloads import acoustic_beam_samples
+    from workloads.gpu import beam_samples_device
 
     grid = (512, 512, 640, 0.2e-3, 0.2e-3, 0.2e-3)
     N = 512 * 512 * 640
     ns = 8
     log("bench: ARF accumulation 512x512x640")
-    p, v = acoustic_beam_samples(grid, ns, per=8, cycles=2, focus=(0.0, 0.0, 0.03), xp=torch, device="cuda",
-                                 dtype=torch.float32)
+    # synthetic samples standing in for an acoustic solver's output, drawn on
+    # the device by the input generator's kernel
+    p, v = beam_samples_device(grid, ns, per=8, cycles=2, focus=(0.0, 0.0, 0.03))
     torch.cuda.synchronize()
     ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32)
     try:

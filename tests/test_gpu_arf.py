@@ -13,6 +13,7 @@ import oracle
 from oracle import arf as oarf
 from oracle.analysis import rel_l2
 from workloads import acoustic_beam_samples
+from workloads.gpu import beam_samples_device
 
 pytestmark = pytest.mark.gpu
 
@@ -217,8 +218,7 @@ def test_full_size_shell_grid_sampled(kvs):
     try:
         kvs.kvs_arf_begin(ctx, 2)
         for s0 in (0, 8):
-            p, v = acoustic_beam_samples(grid, 8, per=8, cycles=2, s0=s0, focus=(0.0, 0.0, 0.03),
-                                         xp=torch, device="cuda", dtype=torch.float32)
+            p, v = beam_samples_device(grid, 8, per=8, cycles=2, s0=s0, focus=(0.0, 0.0, 0.03))
             # the samples are written on torch's stream; the library reads
             # them on its own stream
             torch.cuda.synchronize()
@@ -322,8 +322,7 @@ def test_strain_full_size_shell_grid_boxes(kvs):
     try:
         kvs.kvs_strain_begin(ctx, K)
         for s0 in (0, 8):
-            p, _ = acoustic_beam_samples(grid, 8, per=8, cycles=2, s0=s0, focus=(0.0, 0.0, 0.03), xp=torch,
-                                         device="cuda", dtype=torch.float32)
+            p, _ = beam_samples_device(grid, 8, per=8, cycles=2, s0=s0, focus=(0.0, 0.0, 0.03), with_v=False)
             torch.cuda.synchronize()
             kvs.kvs_strain_accumulate_device(ctx, p.data_ptr(), 8, 1)
             kvs.kvs_synchronize(ctx)
@@ -344,3 +343,22 @@ def test_strain_full_size_shell_grid_boxes(kvs):
         go = pg_o[1:-1, 1:-1, 1:-1]
         assert np.all(np.abs(g - go) <= 1e-13 * go + 1e-14 * pg_o.max()), b
     assert pe.max() > 0 and pg.max() > 0
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_device_beam_samples_match_numpy_generator(kvs, dtype):
+    """The device generator of the synthetic acoustic samples (input drawing
+    for the full-size runs) against the numpy generator: FP64 within 1e-13
+    of the peak, FP32 within one rounding of the FP64 value (exp, cos and
+    atan may differ by an ulp or so between the two sides)."""
+    grid = (37, 29, 45, 2e-4, 2.5e-4, 3e-4)
+    say(f"case device beam samples {np.dtype(dtype).name}")
+    p_d, v_d = beam_samples_device(grid, 11, per=8, cycles=1, s0=3, focus=(1e-3, -0.5e-3, 2e-3),
+                                   dtype="float32" if dtype == np.float32 else "float64")
+    p_d, v_d = p_d.cpu().numpy(), v_d.cpu().numpy()
+    p_n, v_n = acoustic_beam_samples(grid, 11, per=8, cycles=1, s0=3, focus=(1e-3, -0.5e-3, 2e-3), dtype=dtype)
+    assert p_d.shape == p_n.shape and v_d.shape == v_n.shape
+    assert not p_n[5:].any() and not p_d[5:].any()  # silent after one period
+    for a, b in ((p_d, p_n), (v_d, v_n)):
+        tol = 1e-13 if dtype == np.float64 else 2.0 ** -23
+        assert np.all(np.abs(a.astype(np.float64) - b) <= tol * np.abs(b) + 1e-13 * np.abs(b).max())

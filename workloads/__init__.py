@@ -400,8 +400,7 @@ def cfg5_shell(n=(512, 512, 640), h=0.2e-3, seed=1005):
 
 
 def acoustic_beam_samples(grid, samples, f0=1.0e6, c=1540.0, rho=1000.0, alpha=5.8, p0=1.5e6, w0=1.5e-3,
-                          focus=(0.0, 0.0, 0.0), per=20, cycles=10, s0=0, xp=np, device=None,
-                          dtype=np.float32):
+                          focus=(0.0, 0.0, 0.0), per=20, cycles=10, s0=0, dtype=np.float32):
     """A synthetic focused tone burst standing in for an acoustic solver's
     output (the paper's Fullwave fields are not available): a Gaussian beam
     along +z focused at `focus` (waist w0, wavelength c/f0, attenuated by
@@ -410,18 +409,14 @@ def acoustic_beam_samples(grid, samples, f0=1.0e6, c=1540.0, rho=1000.0, alpha=5
     (x/R, y/R, 1), normalised.
 
     Returns (p, v): p [samples][nz][ny][nx], v [samples][3][nz][ny][nx] for
-    sample indices s0 .. s0 + samples - 1, built with `xp` (numpy, or torch
-    with `device`) in FP64 and cast to `dtype`.
+    sample indices s0 .. s0 + samples - 1, built in FP64 and cast to `dtype`
+    (workloads.gpu.beam_samples_device draws the same samples on the device).
     """
     nx, ny, nz, hx, hy, hz = grid
-    if xp is np:
-        arange = lambda n, h: (np.arange(n) - n // 2) * h
-        zeros = lambda shape: np.zeros(shape)
-        cast = lambda a: a.astype(dtype)
-    else:
-        arange = lambda n, h: (xp.arange(n, device=device, dtype=xp.float64) - n // 2) * h
-        zeros = lambda shape: xp.zeros(shape, device=device, dtype=xp.float64)
-        cast = lambda a: a.to(dtype)
+    xp = np
+    arange = lambda n, h: (np.arange(n) - n // 2) * h
+    zeros = lambda shape: np.zeros(shape)
+    cast = lambda a: a.astype(dtype)
     x = arange(nx, hx)[None, None, :] - focus[0]
     y = arange(ny, hy)[None, :, None] - focus[1]
     z = arange(nz, hz)[:, None, None]
