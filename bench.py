@@ -54,16 +54,16 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what it reads for a plain copy of known size (--copy-calibration):
 # FETCH_SIZE reports half of the bytes a copy reads, WRITE_SIZE all of the
 # bytes it writes.  A changed source voids the figures (traffic -> null).
-STEP_SOURCE_SHA = "42b370af991bffd010e37941b167d614ad27d9238bbbf04ca4b0702a60451c26"
+STEP_SOURCE_SHA = "5712d124a31a7424d760876a4dab29d6514332065b861e6b9bcfae6ac76de5bd"
 STEP_COUNTERS_KIB = {  # variant -> (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
-    0: (423806.7, 390144.0),
-    1: (399461.0, 390144.0),
-    2: (323416.5, 390144.0),
-    3: (302655.7, 390146.2),
-    4: (355036.2, 390144.0),
-    5: (332955.7, 390144.0),
-    6: (304283.6, 390144.1),
-    7: (304442.5, 390144.8),
+    0: (423983.2, 390146.0),
+    1: (400448.2, 390146.0),
+    2: (322676.2, 390146.0),
+    3: (302672.6, 390146.3),
+    4: (361179.7, 390146.0),
+    5: (331166.7, 390146.0),
+    6: (304537.1, 390146.4),
+    7: (304696.8, 390146.7),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 METRIC = "FDTD Gcell-updates/s (% HBM roofline); projection time, learned-FPCG vs PCG @1e-8"
