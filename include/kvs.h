@@ -377,6 +377,12 @@ kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* launches);
  * the median launch time (HIP events).  Allocates and frees its 15 buffers
  * (60 n bytes).  n >= 1024, reps >= 1, else KVS_EINVAL. */
 kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* gbs);
+/* The same with the read/write mix of a chosen step kernel: (reads, writes)
+ * = (9, 6), the heterogeneous step, or (6, 6), the homogeneous batched step
+ * (u and w only, 48 B per cell); other mixes give KVS_EINVAL.  *gbs counts
+ * 4 (reads + writes) n bytes; allocates and frees reads + writes buffers. */
+kvs_status kvs_measure_stream_rw(int32_t device, int64_t n, int32_t reads, int32_t writes, int32_t reps,
+                                 double* gbs);
 
 /* ---- batched parameter sweeps ----------------------------------------------- */
 
@@ -422,13 +428,18 @@ kvs_status kvs_batch_read_traces(kvs_batch* b, int32_t i, double* out, int64_t c
  * kvs_batch_uses_persistent reports whether the next run takes that path. */
 kvs_status kvs_batch_set_persistent(kvs_batch* b, int32_t on);
 kvs_status kvs_batch_uses_persistent(const kvs_batch* b, int32_t* on);
-/* Batch tile shape (a step-kernel variant, as for kvs_set_step_variant) and
- * z planes per block (>= 1). */
+/* Batch tile shape (a step-kernel variant, as for kvs_set_step_variant, or
+ * KVS_BATCH_FIT_ROWS) and z planes per block (>= 1).  KVS_BATCH_FIT_ROWS gives
+ * each instance the narrowest tile that spans its x rows (64 x 8, 128 x 8,
+ * 192 x 4 or 256 x 4 cells; wider rows take several 256 x 4 tiles; FP64:
+ * 64 x 8 or 128 x 4), so no tile re-reads x-halo columns of a neighbour;
+ * instances of one shape share a launch (one launch per shape per step). */
+#define KVS_BATCH_FIT_ROWS (-1)
 kvs_status kvs_batch_set_tuning(kvs_batch* b, int32_t variant, int32_t zchunk);
-/* Time every (variant, z planes in {16, 32, 64}) with trial_steps launches
- * that do not advance the state, keep the fastest, return it.  Needs every
- * instance's material and dt.  ms_per_launch (cap entries, one per variant,
- * best z) may be NULL. */
+/* Time every (variant, z planes in {16, 32, 64}), KVS_BATCH_FIT_ROWS included,
+ * with trial_steps launches that do not advance the state, keep the fastest,
+ * return it.  Needs every instance's material and dt.  ms_per_launch (cap
+ * entries: one per variant, best z, then the row-fitted tiling) may be NULL. */
 kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* variant, int32_t* zchunk,
                               double* ms_per_launch, int32_t cap);
 

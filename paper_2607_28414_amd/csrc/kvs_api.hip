@@ -1344,7 +1344,8 @@ static void batch_retile(kvs_batch* b) {
 
 kvs_status kvs_batch_set_tuning(kvs_batch* b, int32_t variant, int32_t zchunk) {
     if (!b) return KVS_EINVAL;
-    if (variant < 0 || variant >= kvs_step_variant_count()) return bfail(b, KVS_EINVAL, "no such variant");
+    if ((variant < 0 || variant >= kvs_step_variant_count()) && variant != KVS_BATCH_FIT_ROWS)
+        return bfail(b, KVS_EINVAL, "no such variant");
     if (zchunk < 1) return bfail(b, KVS_EINVAL, "zchunk < 1");
     b->variant = variant;
     b->zchunk = zchunk;
@@ -1370,7 +1371,9 @@ kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* varian
     int best_v = b->variant, best_z = b->zchunk;
     double best = 1e300;
     hipError_t e = hipSuccess;
-    for (int v = 0; v < nv && e == hipSuccess; ++v) {
+    // candidates: every variant for all instances, then the row-fitted tiling
+    for (int vi = 0; vi <= nv && e == hipSuccess; ++vi) {
+        const int v = vi < nv ? vi : KVS_BATCH_FIT_ROWS;
         double vbest = 1e300;
         for (int zi = 0; zi < 3 && e == hipSuccess; ++zi) {
             b->variant = v;
@@ -1392,7 +1395,7 @@ kvs_status kvs_batch_autotune(kvs_batch* b, int32_t trial_steps, int32_t* varian
                 best_z = zs[zi];
             }
         }
-        if (ms_per_launch && v < cap) ms_per_launch[v] = vbest;
+        if (ms_per_launch && vi < cap) ms_per_launch[vi] = vbest;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

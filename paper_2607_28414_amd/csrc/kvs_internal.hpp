@@ -210,14 +210,20 @@ struct kvs_batch {
     int comp = 2;
     int64_t step = 0;  // common step index of all instances
     bool small_ok = true;  // use the persistent one-block-per-instance run when every instance fits
-    int variant = 1;   // tile shape (index into the step-kernel variants)
+    int variant = 1;   // tile shape (index into the step-kernel variants), or
+                       // KVS_BATCH_FIT_ROWS: each instance's tile fitted to its x rows
     int zchunk = 32;   // z planes per block
 
     // device tables (rebuilt when the instances' parameters change)
     void* dev_params = nullptr;  // BatchInst<T>[n], then the envelopes
     size_t params_bytes = 0;
-    void* dev_work = nullptr;    // int4[nwork]
+    void* dev_work = nullptr;    // int4[nwork], instances grouped by tile shape
     int nwork = 0;
+    // one launch per group: tile shape id and the group's slice of the work list
+    struct Group {
+        int shape, off, count;
+    };
+    std::vector<Group> groups;
     bool viscous = false;
     // probes: flat (instance, cell) list and traces [slot][nprobes] doubles
     std::vector<int64_t> probe_inst, probe_cell;

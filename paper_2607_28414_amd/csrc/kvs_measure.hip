@@ -1,12 +1,14 @@
-// Streaming reference for the FDTD step's roofline: a kernel with the step's
-// memory pattern and no stencil, i.e. per cell 9 FP32 values read (three
-// components each of u and w, and the three per-cell material values) and 6
-// written (the new u and w), 60 B, each stream contiguous, 16-byte vector
-// accesses with non-temporal loads and stores (the fastest of the simple
-// forms measured: plain accesses, one or several vectors per thread, 4 to 32
-// blocks per CU), grid-stride over 16 blocks per CU.  Its bandwidth is the practical ceiling for a
-// kernel that moves the step's bytes once; the step kernel's fraction of it
-// separates stencil and tiling losses from what HBM delivers to this pattern.
+// Streaming references for the FDTD step kernels' rooflines: kernels with a
+// step's memory pattern and no stencil.  The heterogeneous step reads 9 FP32
+// values per cell (three components each of u and w, and the three per-cell
+// material values) and writes 6 (the new u and w), 60 B; the homogeneous
+// batched step reads 6 and writes 6, 48 B.  Each stream is contiguous, with
+// 16-byte non-temporal loads and stores (the fastest of the simple forms
+// measured: plain accesses, one or several vectors per thread, 4 to 32 blocks
+// per CU), grid-stride over 16 blocks per CU.  The bandwidth is the practical
+// ceiling for a kernel that moves a step's bytes once; a step kernel's
+// fraction of it separates stencil and tiling losses from what HBM delivers
+// to that read/write mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,25 +26,32 @@ struct StreamPtrs {
     long long n4;
 };
 
+// R reads and W writes per element (W <= R): every output mixes three inputs
+// so that no load is dead.
+template <int R, int W>
 __global__ __launch_bounds__(256) void stream_kernel(const StreamPtrs s) {
+    static_assert(W <= R && R <= 9 && W <= 6 && R <= W + 3, "every input feeds an output");
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < s.n4; q += stride) {
-        f4 v[9];
+        f4 v[R];
 #pragma unroll
-        for (int a = 0; a < 9; ++a) v[a] = __builtin_nontemporal_load(&s.in[a][q]);
-        // six outputs from the nine inputs, so that no load is dead
+        for (int a = 0; a < R; ++a) v[a] = __builtin_nontemporal_load(&s.in[a][q]);
 #pragma unroll
-        for (int b = 0; b < 6; ++b) __builtin_nontemporal_store(v[b] + v[(b + 3) % 9] * v[6 + b % 3], &s.out[b][q]);
+        for (int b = 0; b < W; ++b)
+            __builtin_nontemporal_store(v[b] + v[(b + 3) % R] * v[(R - 3 + b % 3) % R], &s.out[b][q]);
     }
 }
 
 }  // namespace
 
-kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* gbs) {
+kvs_status kvs_measure_stream_rw(int32_t device, int64_t n, int32_t reads, int32_t writes, int32_t reps,
+                                 double* gbs) {
     if (!gbs || n < 1024 || reps < 1) return KVS_EINVAL;
+    if (!((reads == 9 && writes == 6) || (reads == 6 && writes == 6))) return KVS_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return KVS_EDEVICE;
     const long long n4 = (n + 3) / 4;
-    std::vector<void*> bufs(15, nullptr);
+    const int nbuf = reads + writes;
+    std::vector<void*> bufs((size_t)nbuf, nullptr);
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     kvs_status ret = KVS_OK;
@@ -57,8 +66,8 @@ kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* g
     }
     if (ret == KVS_OK) {
         StreamPtrs s{};
-        for (int a = 0; a < 9; ++a) s.in[a] = static_cast<const f4*>(bufs[(size_t)a]);
-        for (int b = 0; b < 6; ++b) s.out[b] = static_cast<f4*>(bufs[(size_t)(9 + b)]);
+        for (int a = 0; a < reads; ++a) s.in[a] = static_cast<const f4*>(bufs[(size_t)a]);
+        for (int b = 0; b < writes; ++b) s.out[b] = static_cast<f4*>(bufs[(size_t)(reads + b)]);
         s.n4 = n4;
         hipDeviceProp_t prop;
         (void)hipGetDeviceProperties(&prop, device);
@@ -66,7 +75,10 @@ kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* g
         std::vector<float> ms;
         for (int r = 0; r <= reps && ret == KVS_OK; ++r) {  // the first launch is not timed
             (void)hipEventRecord(e0, st);
-            hipLaunchKernelGGL(stream_kernel, dim3(blocks), dim3(256), 0, st, s);
+            if (reads == 9)
+                hipLaunchKernelGGL((stream_kernel<9, 6>), dim3(blocks), dim3(256), 0, st, s);
+            else
+                hipLaunchKernelGGL((stream_kernel<6, 6>), dim3(blocks), dim3(256), 0, st, s);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) ret = KVS_EDEVICE;
             float t = 0.f;
@@ -76,7 +88,7 @@ kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* g
         if (ret == KVS_OK) {
             std::sort(ms.begin(), ms.end());
             const double med = ms[ms.size() / 2];
-            *gbs = 15.0 * 16.0 * (double)n4 / (med * 1e-3) / 1e9;
+            *gbs = (double)nbuf * 16.0 * (double)n4 / (med * 1e-3) / 1e9;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -85,4 +97,8 @@ kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* g
     for (auto b : bufs)
         if (b) (void)hipFree(b);
     return ret;
+}
+
+kvs_status kvs_measure_stream(int32_t device, int64_t n, int32_t reps, double* gbs) {
+    return kvs_measure_stream_rw(device, n, 9, 6, reps, gbs);
 }

@@ -802,6 +802,35 @@ StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int wx, int zchu
     return a;
 }
 
+// Batch tile shapes: ids 0 .. kNumVariants-1 are the step-kernel variants;
+// kShape192 is a 192 x 4 tile (three wavefronts per row), used only by the
+// row-fitted tiling.
+constexpr int kShape192 = kNumVariants;
+
+void batch_shape_dims(int shape, int* by, int* vec, int* wx) {
+    if (shape == kShape192) {
+        *by = 4;
+        *vec = 1;
+        *wx = 3;
+        return;
+    }
+    *by = kVariants[shape].by;
+    *vec = kVariants[shape].vec;
+    *wx = kVariants[shape].wx;
+}
+
+// The narrowest tile spanning an x row of nx cells: the row is then loaded
+// once per tile with its Dirichlet ends as the x halo, instead of each tile
+// re-reading two halo columns of its neighbours.  FP64 stays within the
+// shapes whose two buffered planes fit the LDS (64 x 8, 128 x 4).
+int fit_shape(int nx, bool fp64) {
+    if (nx <= 64) return 1;  // 64 x 8
+    if (fp64) return 5;      // 128 x 4
+    if (nx <= 128) return 6; // 128 x 8
+    if (nx <= 192) return kShape192;
+    return 7;                // 256 x 4 (several per row beyond 256)
+}
+
 // The batch's tile shape, narrowed like the single-context launch (two
 // cells per lane need every instance's nx even).
 int batch_variant(const kvs_batch* b) {
@@ -810,6 +839,12 @@ int batch_variant(const kvs_batch* b) {
     bool even = true;
     for (const kvs_ctx* c : b->inst) even = even && (c->grid.nx % 2 == 0);
     return effective_variant(v, b->prec == KVS_FP64, !even);
+}
+
+// Tile shape of instance c in batch b.
+int instance_shape(const kvs_batch* b, const kvs_ctx* c) {
+    if (b->variant == KVS_BATCH_FIT_ROWS) return fit_shape((int)c->grid.nx, b->prec == KVS_FP64);
+    return batch_variant(b);
 }
 
 template <typename T>
@@ -843,10 +878,12 @@ hipError_t prepare_t(kvs_batch* b) {
     double* env_dev = reinterpret_cast<double*>(static_cast<char*>(b->dev_params) + pbytes);
     std::vector<double> env_host(std::max<size_t>(env_total, 1), 0.0);
     size_t off = 0;
-    const int v = batch_variant(b);
-    const int by = kVariants[v].by, vec = kVariants[v].vec, wx = kVariants[v].wx;
+    std::vector<int> shape((size_t)n);
     for (int i = 0; i < n; ++i) {
         kvs_ctx* c = b->inst[(size_t)i];
+        shape[(size_t)i] = instance_shape(b, c);
+        int by = 0, vec = 0, wx = 0;
+        batch_shape_dims(shape[(size_t)i], &by, &vec, &wx);
         params[(size_t)i].a[0] = instance_args<T>(c, c->cur, by, vec, wx, b->zchunk);
         params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur, by, vec, wx, b->zchunk);
         params[(size_t)i].env = env_dev + off;
@@ -854,11 +891,20 @@ hipError_t prepare_t(kvs_batch* b) {
         std::copy(c->env.begin(), c->env.end(), env_host.begin() + off);
         off += c->env.size();
         visc = visc || c->viscous;
-        if (!b->dev_work) {
-            const StepArgs<T>& a = params[(size_t)i].a[0];
-            for (int bz = 0; bz < a.gz; ++bz)
-                for (int by = 0; by < a.gy; ++by)
-                    for (int bx = 0; bx < a.gx; ++bx) work.push_back(make_int4(i, bx, by, bz));
+    }
+    if (!b->dev_work) {
+        // the work list grouped by tile shape: one launch per group
+        b->groups.clear();
+        for (int sh = 0; sh <= kShape192; ++sh) {
+            const int first = (int)work.size();
+            for (int i = 0; i < n; ++i) {
+                if (shape[(size_t)i] != sh) continue;
+                const StepArgs<T>& a = params[(size_t)i].a[0];
+                for (int bz = 0; bz < a.gz; ++bz)
+                    for (int by = 0; by < a.gy; ++by)
+                        for (int bx = 0; bx < a.gx; ++bx) work.push_back(make_int4(i, bx, by, bz));
+            }
+            if ((int)work.size() > first) b->groups.push_back({sh, first, (int)work.size() - first});
         }
     }
     e = hipMemcpyAsync(b->dev_params, params.data(), pbytes, hipMemcpyHostToDevice, b->stream);
@@ -877,31 +923,35 @@ hipError_t prepare_t(kvs_batch* b) {
 }
 
 template <typename T, bool VISC, bool FORCE, int BY, int VEC, int WX>
-void launch_batch_shape(kvs_batch* b, long long n, int parity) {
-    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, BY, VEC, WX>), dim3(b->nwork), dim3(64 * WX, BY), 0,
-                       b->stream,
-                       static_cast<const BatchInst<T>*>(b->dev_params), static_cast<const int4*>(b->dev_work),
-                       b->nwork, n, parity);
+void launch_batch_shape(kvs_batch* b, long long n, int parity, const kvs_batch::Group& g) {
+    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, BY, VEC, WX>), dim3(g.count), dim3(64 * WX, BY), 0,
+                       b->stream, static_cast<const BatchInst<T>*>(b->dev_params),
+                       static_cast<const int4*>(b->dev_work) + g.off, g.count, n, parity);
 }
 
+// One launch per tile-shape group (a single group unless the tiling is
+// fitted to each instance's rows).
 template <typename T, bool VISC, bool FORCE>
 void launch_batch_step(kvs_batch* b, long long n, int parity) {
-    if constexpr (sizeof(T) == 8) {
-        switch (batch_variant(b)) {
-            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity);
-            case 5: return launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity);
-            default: return launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity);
-        }
-    } else {
-        switch (batch_variant(b)) {
-            case 1: return launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity);
-            case 2: return launch_batch_shape<T, VISC, FORCE, 4, 2, 1>(b, n, parity);
-            case 3: return launch_batch_shape<T, VISC, FORCE, 8, 2, 1>(b, n, parity);
-            case 4: return launch_batch_shape<T, VISC, FORCE, 16, 1, 1>(b, n, parity);
-            case 5: return launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity);
-            case 6: return launch_batch_shape<T, VISC, FORCE, 8, 1, 2>(b, n, parity);
-            case 7: return launch_batch_shape<T, VISC, FORCE, 4, 1, 4>(b, n, parity);
-            default: return launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity);
+    for (const kvs_batch::Group& g : b->groups) {
+        if constexpr (sizeof(T) == 8) {
+            switch (g.shape) {
+                case 1: launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity, g); break;
+                case 5: launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity, g); break;
+                default: launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity, g); break;
+            }
+        } else {
+            switch (g.shape) {
+                case 1: launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity, g); break;
+                case 2: launch_batch_shape<T, VISC, FORCE, 4, 2, 1>(b, n, parity, g); break;
+                case 3: launch_batch_shape<T, VISC, FORCE, 8, 2, 1>(b, n, parity, g); break;
+                case 4: launch_batch_shape<T, VISC, FORCE, 16, 1, 1>(b, n, parity, g); break;
+                case 5: launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity, g); break;
+                case 6: launch_batch_shape<T, VISC, FORCE, 8, 1, 2>(b, n, parity, g); break;
+                case 7: launch_batch_shape<T, VISC, FORCE, 4, 1, 4>(b, n, parity, g); break;
+                case kShape192: launch_batch_shape<T, VISC, FORCE, 4, 1, 3>(b, n, parity, g); break;
+                default: launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity, g); break;
+            }
         }
     }
 }

@@ -194,6 +194,7 @@ SIGNATURES = {
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
     "kvs_measure_stream": ([C.c_int32, C.c_int64, C.c_int32, _D], C.c_int),
+    "kvs_measure_stream_rw": ([C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _D], C.c_int),
     "kvs_arf_begin": ([_P, C.c_int32], C.c_int),
     "kvs_strain_begin": ([_P, _D, C.c_int64], C.c_int),
     "kvs_strain_accumulate_device": ([_P, C.c_void_p, C.c_int64, C.c_int32], C.c_int),
@@ -328,11 +329,15 @@ def kvs_set_force(ctx, F):
     _check(lib().kvs_set_force(ctx, _dptr(F)), ctx)
 
 
-def kvs_measure_stream(n, reps=10, device=0):
-    """GB/s of the streaming reference kernel (the FDTD step's 9-read /
-    6-write FP32 pattern) over n cells."""
+def kvs_measure_stream(n, reps=10, device=0, reads=9, writes=6):
+    """GB/s of the streaming reference kernel over n cells: the
+    heterogeneous FDTD step's 9-read / 6-write FP32 pattern, or with
+    reads=6 the homogeneous batched step's 6 / 6."""
     out = C.c_double()
-    _check(lib().kvs_measure_stream(int(device), int(n), int(reps), C.byref(out)))
+    if (reads, writes) == (9, 6):
+        _check(lib().kvs_measure_stream(int(device), int(n), int(reps), C.byref(out)))
+    else:
+        _check(lib().kvs_measure_stream_rw(int(device), int(n), int(reads), int(writes), int(reps), C.byref(out)))
     return out.value
 
 
@@ -613,8 +618,13 @@ def kvs_batch_set_tuning(b, variant, zchunk):
     _bcheck(lib().kvs_batch_set_tuning(b, int(variant), int(zchunk)), b)
 
 
+KVS_BATCH_FIT_ROWS = -1
+
+
 def kvs_batch_autotune(b, trial_steps=5):
-    n = kvs_num_step_variants()
+    """Returns (variant, z planes, ms per launch of each candidate: the
+    variants, then the row-fitted tiling); variant may be KVS_BATCH_FIT_ROWS."""
+    n = kvs_num_step_variants() + 1
     ms = np.zeros(n)
     v, z = C.c_int32(), C.c_int32()
     _bcheck(lib().kvs_batch_autotune(b, int(trial_steps), C.byref(v), C.byref(z), _dptr(ms), n), b)

@@ -125,6 +125,65 @@ def test_batch_equals_single_context_bitwise_and_replays(kvs):
         assert np.array_equal(tr, first[i]), i
 
 
+WIDE = [  # (nx, ny, nz), G, eta: x rows that take each row-fitted tile width
+    ((40, 30, 20), 2e3, 0.0),     # 64 x 8
+    ((100, 20, 18), 5e3, 0.7),    # 128 x 8 (FP64: 128 x 4)
+    ((150, 16, 20), 1e3, 1.5),    # 192 x 4 (FP64: 128 x 4, two per row)
+    ((210, 14, 12), 8e3, 0.2),    # 256 x 4 (FP64: 128 x 4, two per row)
+    ((300, 10, 10), 3e3, 0.0),    # two 256 x 4 tiles per row (FP64: three 128 x 4)
+]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_row_fitted_batch_tiles_match_oracle_and_single_contexts(kvs, precision):
+    """The row-fitted batch tiling (one launch per tile width per step) on
+    instances whose x rows take every width, a ragged last tile and two
+    tiles per row: traces against the oracle (FP64 1e-12, FP32 2e-5) and,
+    in FP32, bitwise against each instance stepped alone with the same tile
+    shape."""
+    say(f"case row-fitted batch tiles precision {precision}")
+    grids = [tuple(sh) + (H, H, H) for sh, _, _ in WIDE]
+    b = kvs.kvs_batch_create(grids, precision=precision, sponge_cells=L_SPONGE, sponge_sigma_max=800.0)
+    info = []
+    try:
+        for i, (sh, G, eta) in enumerate(WIDE):
+            grid = grids[i]
+            F = gaussian_push(grid, 0.75e-3, 1.5e-3, 1e4)
+            FS_o, _, _ = oracle.project(grid, F, tol=1e-12)
+            dt, env = setup_instance(kvs, kvs.kvs_batch_instance(b, i), grid, G, eta, F, FS=FS_o)
+            probes = x_line_probes(grid)
+            kvs.kvs_batch_set_probes(b, i, probes)
+            info.append((grid, G, eta, FS_o, dt, env, probes))
+        kvs.kvs_batch_set_component(b, 2)
+        kvs.kvs_batch_set_tuning(b, kvs.KVS_BATCH_FIT_ROWS, 16)
+        kvs.kvs_batch_step(b, NSTEPS)
+        traces = [kvs.kvs_batch_read_traces(b, i, len(info[i][6])) for i in range(len(info))]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    for i, (grid, G, eta, FS_o, dt, env, probes) in enumerate(info):
+        _, _, tr_o = oracle.run(grid, G, 1000.0, eta, dt, NSTEPS, FS=FS_o, env=env, probes=probes, comp=2,
+                                sponge_cells=L_SPONGE, sigma_max=800.0)
+        err = rel_l2(traces[i], tr_o[:, :, 0])
+        say(f"instance {i} nx {grid[0]}: rel L2 {err:.2e}")
+        assert err < (1e-12 if precision == 0 else 2e-5), (i, err)
+    if precision == 1:
+        # single-context variants of the same tile shapes (64 x 8, 128 x 8,
+        # 256 x 4); the 192 x 4 tile has no single-context variant
+        same_shape = {0: 1, 1: 6, 3: 7, 4: 7}
+        for i, v in same_shape.items():
+            grid, G, eta, FS_o, dt, env, probes = info[i]
+            ctx = kvs.kvs_create(grid, precision=1, sponge_cells=L_SPONGE, sponge_sigma_max=800.0)
+            try:
+                setup_instance(kvs, ctx, grid, G, eta, None, FS=FS_o)
+                kvs.kvs_set_probes(ctx, probes, 2)
+                kvs.kvs_set_step_tuning(ctx, v, 16, 1)
+                kvs.kvs_step(ctx, NSTEPS)
+                tr = kvs.kvs_read_traces(ctx, len(probes), 1)[:, :, 0]
+            finally:
+                kvs.kvs_destroy(ctx)
+            assert np.array_equal(tr, traces[i]), i
+
+
 def test_batch_shared_projection_and_call_order(kvs):
     say("case batch share projection / call order")
     grid = (32, 32, 32, H, H, H)
@@ -157,12 +216,13 @@ def test_every_batch_tile_shape_matches_oracle(kvs):
     b, info = make_batch(kvs, 1)
     try:
         v0, z0, ms = kvs.kvs_batch_autotune(b, 2)
-        assert 0 <= v0 < len(ms) and z0 in (16, 32, 64)
+        assert len(ms) == kvs.kvs_num_step_variants() + 1 and np.all(ms > 0)
+        assert (v0 == kvs.KVS_BATCH_FIT_ROWS or 0 <= v0 < len(ms) - 1) and z0 in (16, 32, 64)
         for i in range(len(info)):
             u, w, s = kvs.kvs_get_state(kvs.kvs_batch_instance(b, i), (info[i][0][2], info[i][0][1], info[i][0][0]))
             assert s == 0 and not u.any() and not w.any()
         results = {}
-        for v in range(kvs.kvs_num_step_variants()):
+        for v in list(range(kvs.kvs_num_step_variants())) + [kvs.KVS_BATCH_FIT_ROWS]:
             say(f"case batch shape {v}")
             kvs.kvs_batch_reset(b)
             kvs.kvs_batch_set_tuning(b, v, 16)
