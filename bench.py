@@ -50,11 +50,11 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the FDTD step kernel from rocprofv3 counter runs of this
 # benchmark (256^3 inclusion workload, one launch without force): FETCH_SIZE
 # and WRITE_SIZE in KiB per dispatch, per tile-shape variant, taken on the
-# step-kernel source whose SHA-256 is STEP_SOURCE_SHA.  Each counter is
+# step-kernel sources (STEP_SOURCES) whose SHA-256 is STEP_SOURCE_SHA.  Each counter is
 # scaled by what it reads for a plain copy of known size (--copy-calibration):
 # FETCH_SIZE reports half of the bytes a copy reads, WRITE_SIZE all of the
 # bytes it writes.  A changed source voids the figures (traffic -> null).
-STEP_SOURCE_SHA = "5712d124a31a7424d760876a4dab29d6514332065b861e6b9bcfae6ac76de5bd"
+STEP_SOURCE_SHA = "f26c91bb5db918abca9fc803284f993aa0fe815a66b95bb68a2d2f50a855e0e9"
 STEP_COUNTERS_KIB = {  # variant -> (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
     0: (423983.2, 390146.0),
     1: (400448.2, 390146.0),
@@ -109,11 +109,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+STEP_SOURCES = ("kvs_step_tile.hpp", "kvs_step.hip", "kvs_tiling.hpp")
+
+
 def step_source_sha():
+    """SHA-256 over the step kernel's sources (tile code, kernel and launch
+    shapes, tile order), in that order."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2607_28414_amd", "csrc", "kvs_step.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2607_28414_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def step_traffic(variant):

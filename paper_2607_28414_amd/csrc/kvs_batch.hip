@@ -1,0 +1,538 @@
+// Batched sweeps: many homogeneous instances advanced together, either one
+// launch per step over every instance's tiles (captured once as a hipGraph
+// and replayed), or, when every instance's state fits one workgroup's LDS,
+// one persistent launch for the whole run.
+#include "kvs_step_tile.hpp"
+
+namespace {
+
+// Batched homogeneous instances: one launch covers every instance's tiles
+// through a work list (instance, bx, by, bz).  `parity` (steps since the
+// table was built, mod 2) selects which ping-pong buffers are current; the
+// absolute step n indexes each instance's envelope.
+template <typename T>
+struct BatchInst {
+    StepArgs<T> a[2];  // [parity]: u, w current / next swapped
+    const double* env;
+    long long n_env;
+};
+
+template <typename T, bool VISC, bool FORCE, int BY, int VEC, int WX>
+__global__ __launch_bounds__(64 * WX * BY) void batch_step_kernel(const BatchInst<T>* inst, const int4* work,
+                                                                  int nwork, long long n, int parity) {
+    const int t = tile_of(blockIdx.x, nwork);
+    const int4 wi = work[t];
+    const BatchInst<T>& bi = inst[wi.x];
+    StepArgs<T> a = bi.a[parity];
+    a.gn = n < bi.n_env ? T(bi.env[n]) : T(0);
+    step_tile<T, false, VISC, FORCE, BY, VEC, WX>(a, wi.y, wi.z, wi.w);
+}
+
+
+template <typename T>
+StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int wx, int zchunk) {
+    const kvs_grid& g = c->grid;
+    StepArgs<T> a{};
+    a.u = static_cast<const T*>(c->u[cur]);
+    a.w = static_cast<const T*>(c->w[cur]);
+    a.un = static_cast<T*>(c->u[1 - cur]);
+    a.wn = static_cast<T*>(c->w[1 - cur]);
+    a.FS = static_cast<const T*>(c->FS);
+    a.N = c->N;
+    a.nx = (int)g.nx;
+    a.ny = (int)g.ny;
+    a.nz = (int)g.nz;
+    a.gx = (a.nx + 64 * wx * vec - 1) / (64 * wx * vec);
+    a.gy = (a.ny + by - 1) / by;
+    a.kchunk = std::min(zchunk, a.nz - 2);
+    a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
+    a.L = c->sponge_cells;
+    a.invL = a.L > 0 ? T(1.0 / a.L) : T(0);
+    a.ihx2 = T(1.0 / (g.hx * g.hx));
+    a.ihy2 = T(1.0 / (g.hy * g.hy));
+    a.ihz2 = T(1.0 / (g.hz * g.hz));
+    a.G0 = T(c->G0);
+    a.eta_dt0 = T(c->eta0 / c->dt);
+    a.crho0 = T(c->dt * c->dt / c->rho0);
+    a.inv_dt = T(1.0 / c->dt);
+    a.gn = T(0);
+    a.half_dt_smax = T(0.5 * c->sigma_max * c->dt);
+    a.remap = 1;
+    return a;
+}
+
+// Batch tile shapes: ids 0 .. kNumVariants-1 are the step-kernel variants;
+// kShape192 is a 192 x 4 tile (three wavefronts per row), used only by the
+// row-fitted tiling.
+constexpr int kShape192 = kNumVariants;
+
+void batch_shape_dims(int shape, int* by, int* vec, int* wx) {
+    if (shape == kShape192) {
+        *by = 4;
+        *vec = 1;
+        *wx = 3;
+        return;
+    }
+    *by = kVariants[shape].by;
+    *vec = kVariants[shape].vec;
+    *wx = kVariants[shape].wx;
+}
+
+// The narrowest tile spanning an x row of nx cells: the row is then loaded
+// once per tile with its Dirichlet ends as the x halo, instead of each tile
+// re-reading two halo columns of its neighbours.  FP64 stays within the
+// shapes whose two buffered planes fit the LDS (64 x 8, 128 x 4).
+int fit_shape(int nx, bool fp64) {
+    if (nx <= 64) return 1;  // 64 x 8
+    if (fp64) return 5;      // 128 x 4
+    if (nx <= 128) return 6; // 128 x 8
+    if (nx <= 192) return kShape192;
+    return 7;                // 256 x 4 (several per row beyond 256)
+}
+
+// The batch's tile shape, narrowed like the single-context launch (two
+// cells per lane need every instance's nx even).
+int batch_variant(const kvs_batch* b) {
+    int v = b->variant;
+    if (v < 0 || v >= kNumVariants) v = 1;
+    bool even = true;
+    for (const kvs_ctx* c : b->inst) even = even && (c->grid.nx % 2 == 0);
+    return effective_variant(v, b->prec == KVS_FP64, !even);
+}
+
+// Tile shape of instance c in batch b.
+int instance_shape(const kvs_batch* b, const kvs_ctx* c) {
+    if (b->variant == KVS_BATCH_FIT_ROWS) return fit_shape((int)c->grid.nx, b->prec == KVS_FP64);
+    return batch_variant(b);
+}
+
+template <typename T>
+__global__ void batch_probe_kernel(const BatchInst<T>* inst, const long long* probes, int np, int comp, int parity,
+                                   double* out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const StepArgs<T>& a = inst[probes[2 * p]].a[parity];
+    out[p] = (double)a.un[comp * a.N + probes[2 * p + 1]];  // u after the step
+}
+
+template <typename T>
+hipError_t prepare_t(kvs_batch* b) {
+    const int n = (int)b->inst.size();
+    std::vector<BatchInst<T>> params((size_t)n);
+    std::vector<int4> work;
+    bool visc = false;
+    size_t env_total = 0;
+    for (int i = 0; i < n; ++i) env_total += b->inst[(size_t)i]->env.size();
+    const size_t pbytes = sizeof(BatchInst<T>) * (size_t)n;
+    const size_t ebytes = sizeof(double) * std::max<size_t>(env_total, 1);
+    hipError_t e = hipSuccess;
+    if (!b->dev_params || b->params_bytes < pbytes + ebytes) {
+        b->mem.put(b->dev_params);  // after the stream's earlier steps (put synchronises)
+        b->dev_params = nullptr;
+        e = b->mem.get(&b->dev_params, pbytes + ebytes);
+        if (e != hipSuccess) return e;
+        b->params_bytes = pbytes + ebytes;
+        b->graph_valid = false;  // the graph holds the old table's address
+    }
+    double* env_dev = reinterpret_cast<double*>(static_cast<char*>(b->dev_params) + pbytes);
+    std::vector<double> env_host(std::max<size_t>(env_total, 1), 0.0);
+    size_t off = 0;
+    std::vector<int> shape((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        kvs_ctx* c = b->inst[(size_t)i];
+        shape[(size_t)i] = instance_shape(b, c);
+        int by = 0, vec = 0, wx = 0;
+        batch_shape_dims(shape[(size_t)i], &by, &vec, &wx);
+        params[(size_t)i].a[0] = instance_args<T>(c, c->cur, by, vec, wx, b->zchunk);
+        params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur, by, vec, wx, b->zchunk);
+        params[(size_t)i].env = env_dev + off;
+        params[(size_t)i].n_env = (long long)c->env.size();
+        std::copy(c->env.begin(), c->env.end(), env_host.begin() + off);
+        off += c->env.size();
+        visc = visc || c->viscous;
+    }
+    if (!b->dev_work) {
+        // the work list grouped by tile shape: one launch per group
+        b->groups.clear();
+        for (int sh = 0; sh <= kShape192; ++sh) {
+            const int first = (int)work.size();
+            for (int i = 0; i < n; ++i) {
+                if (shape[(size_t)i] != sh) continue;
+                const StepArgs<T>& a = params[(size_t)i].a[0];
+                for (int bz = 0; bz < a.gz; ++bz)
+                    for (int by = 0; by < a.gy; ++by)
+                        for (int bx = 0; bx < a.gx; ++bx) work.push_back(make_int4(i, bx, by, bz));
+            }
+            if ((int)work.size() > first) b->groups.push_back({sh, first, (int)work.size() - first});
+        }
+    }
+    e = hipMemcpyAsync(b->dev_params, params.data(), pbytes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(env_dev, env_host.data(), ebytes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !b->dev_work) {
+        e = b->mem.get(&b->dev_work, sizeof(int4) * work.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->dev_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice,
+                               b->stream);
+        b->nwork = (int)work.size();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (visc != b->viscous) b->graph_valid = false;
+    b->viscous = visc;
+    return e;
+}
+
+template <typename T, bool VISC, bool FORCE, int BY, int VEC, int WX>
+void launch_batch_shape(kvs_batch* b, long long n, int parity, const kvs_batch::Group& g) {
+    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, BY, VEC, WX>), dim3(g.count), dim3(64 * WX, BY), 0,
+                       b->stream, static_cast<const BatchInst<T>*>(b->dev_params),
+                       static_cast<const int4*>(b->dev_work) + g.off, g.count, n, parity);
+}
+
+// One launch per tile-shape group (a single group unless the tiling is
+// fitted to each instance's rows).
+template <typename T, bool VISC, bool FORCE>
+void launch_batch_step(kvs_batch* b, long long n, int parity) {
+    for (const kvs_batch::Group& g : b->groups) {
+        if constexpr (sizeof(T) == 8) {
+            switch (g.shape) {
+                case 1: launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity, g); break;
+                case 5: launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity, g); break;
+                default: launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity, g); break;
+            }
+        } else {
+            switch (g.shape) {
+                case 1: launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity, g); break;
+                case 2: launch_batch_shape<T, VISC, FORCE, 4, 2, 1>(b, n, parity, g); break;
+                case 3: launch_batch_shape<T, VISC, FORCE, 8, 2, 1>(b, n, parity, g); break;
+                case 4: launch_batch_shape<T, VISC, FORCE, 16, 1, 1>(b, n, parity, g); break;
+                case 5: launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity, g); break;
+                case 6: launch_batch_shape<T, VISC, FORCE, 8, 1, 2>(b, n, parity, g); break;
+                case 7: launch_batch_shape<T, VISC, FORCE, 4, 1, 4>(b, n, parity, g); break;
+                case kShape192: launch_batch_shape<T, VISC, FORCE, 4, 1, 3>(b, n, parity, g); break;
+                default: launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity, g); break;
+            }
+        }
+    }
+}
+
+// Per step of the run starting at b->step: 1 when any instance's envelope is
+// non-zero there (that step launches the kernel that reads f_S).
+std::vector<uint8_t> batch_force_mask(const kvs_batch* b, int64_t nsteps) {
+    std::vector<uint8_t> m((size_t)nsteps, 0);
+    for (int64_t q = 0; q < nsteps; ++q) {
+        const int64_t n = b->step + q;
+        for (const kvs_ctx* c : b->inst)
+            if (n < (int64_t)c->env.size() && c->env[(size_t)n] != 0.0) {
+                m[(size_t)q] = 1;
+                break;
+            }
+    }
+    return m;
+}
+
+template <typename T>
+hipError_t capture_t(kvs_batch* b, int64_t nsteps, const std::vector<uint8_t>& force_mask) {
+    const int np = (int)b->probe_inst.size();
+    for (int64_t q = 0; q < nsteps; ++q) {
+        const int64_t n = b->step + q;
+        const bool force = force_mask[(size_t)q] != 0;
+        const int parity = (int)(q & 1);
+        if (b->viscous)
+            force ? launch_batch_step<T, true, true>(b, n, parity) : launch_batch_step<T, true, false>(b, n, parity);
+        else
+            force ? launch_batch_step<T, false, true>(b, n, parity) : launch_batch_step<T, false, false>(b, n, parity);
+        if (np > 0)
+            hipLaunchKernelGGL(batch_probe_kernel<T>, dim3((np + 255) / 256), dim3(256), 0, b->stream,
+                               static_cast<const BatchInst<T>*>(b->dev_params),
+                               static_cast<const long long*>(b->dev_probes), np, b->comp, parity,
+                               b->traces + (b->trace_steps + q) * np);
+    }
+    return hipGetLastError();
+}
+
+// ---- persistent path for small instances -----------------------------------
+//
+// When every instance's whole state (u and w, three components each) fits in
+// one workgroup's LDS, a batch run is one launch of one block per instance
+// that advances its instance through all the steps in the kernel: the state
+// lives in LDS for the whole run, the block's threads own fixed interior
+// cells, and two block barriers per step separate reading the old state from
+// writing the new one; probe values are written after every step.  The
+// per-cell arithmetic is the step kernel's (same operand order, sponge
+// factors and FP32 reciprocal), so one launch replaces two launches per step
+// and the run is bound by the latency of a step, not by launches.
+constexpr int kSmallMaxThreads = 1024;
+constexpr int kSmallChunk = 64;  // steps whose envelope and probe values are staged in LDS at a time
+constexpr size_t kSmallMaxLds = 150 * 1024;
+
+// LINE: every instance is a line (ny = nz = 3): the y and z neighbours of an
+// interior node lie on the Dirichlet layer and are exactly 0, so they are
+// taken as the constant 0 instead of read (the same arithmetic).
+template <typename T, bool VISC, int CPT, bool LINE>
+__global__ __launch_bounds__(kSmallMaxThreads) void batch_small_kernel(const BatchInst<T>* inst, const long long* probes,
+                                                                       const long long* probe_first, int np, int comp,
+                                                                       double* traces, long long step0,
+                                                                       long long nsteps) {
+    extern __shared__ __align__(16) unsigned char small_lds[];
+    const int nthr = blockDim.x;
+    // everything the step loop needs is read once: the loop's stores to the
+    // traces would otherwise make the compiler re-read it every step
+    const StepArgs<T> a = inst[blockIdx.x].a[0];  // parity 0: the buffers current at the start of the run
+    // the envelope through a global-memory pointer: a generic (flat) load
+    // could alias LDS, which would order every LDS access behind it
+    typedef const __attribute__((address_space(1))) double* genv_t;
+    const genv_t env = (genv_t)inst[blockIdx.x].env;
+    const long long n_env = inst[blockIdx.x].n_env;
+    const int N = (int)a.N;
+    T* su = reinterpret_cast<T*>(small_lds);  // [3][N]
+    T* sw = su + 3 * N;                        // [3][N]
+    T* senv = sw + 3 * N;                      // [kSmallChunk]: the chunk's envelope values
+    const long long pf = np > 0 ? probe_first[blockIdx.x] : 0;
+    const int npi = np > 0 ? (int)(probe_first[blockIdx.x + 1] - pf) : 0;
+    T* strace = senv + kSmallChunk;                                     // [kSmallChunk][npi]: probe values
+    int* sprobe = reinterpret_cast<int*>(strace + kSmallChunk * npi);  // this instance's probe cells
+    for (int q = threadIdx.x; q < 3 * N; q += nthr) {
+        su[q] = a.u[q];
+        sw[q] = a.w[q];
+    }
+    for (int p = threadIdx.x; p < npi; p += nthr) sprobe[p] = comp * N + (int)probes[2 * (pf + p) + 1];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nxi = nx - 2, nyi = ny - 2, nint = nxi * nyi * (nz - 2);
+    const int sy = nx, sz = nx * ny;
+    // owned cells: their index, sponge factors, f_S and own u, w (registers)
+    int cell[CPT];
+    T a1[CPT], a2[CPT], fs[CPT][3], ur[CPT][3], wr[CPT][3];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int t = threadIdx.x + m * nthr;
+        cell[m] = -1;
+        a1[m] = a2[m] = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fs[m][c] = ur[m][c] = wr[m][c] = T(0);
+        if (t < nint) {
+            const int i = 1 + t % nxi, j = 1 + (t / nxi) % nyi, k = 1 + t / (nxi * nyi);
+            const int q = i + nx * (j + ny * k);
+            cell[m] = q;
+            const T r = a.L > 0 ? max(max(ramp<T>(i, nx, a.L, a.invL), ramp<T>(j, ny, a.L, a.invL)),
+                                      ramp<T>(k, nz, a.L, a.invL))
+                                : T(0);
+            const T s = a.half_dt_smax * r;
+            const T inv1ps = rcp_fast<T>(T(1) + s);
+            a1[m] = (T(1) - s) * inv1ps;
+            a2[m] = a.crho0 * inv1ps;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fs[m][c] = a.FS[c * a.N + q];
+                ur[m][c] = a.u[c * a.N + q];
+                wr[m][c] = a.w[c * a.N + q];
+            }
+        }
+    }
+    const T gx = a.G0 * a.ihx2, gy = a.G0 * a.ihy2, gz = a.G0 * a.ihz2;
+    const T ihx2 = a.ihx2, ihy2 = a.ihy2, ihz2 = a.ihz2, eta_dt = a.eta_dt0;
+    for (long long st0 = 0; st0 < nsteps; st0 += kSmallChunk) {
+        const int cn = (int)min((long long)kSmallChunk, nsteps - st0);
+        // the chunk's envelope values: global memory is touched only here and
+        // in the flush of the chunk's probe values below, so the step loop
+        // itself waits on LDS alone
+        for (int q = threadIdx.x; q < cn; q += nthr) {
+            const long long n = step0 + st0 + q;
+            senv[q] = n < n_env ? T(env[n]) : T(0);
+        }
+        lds_barrier();
+        for (int sc = 0; sc < cn; ++sc) {
+            const T gn = senv[sc];
+#pragma unroll
+            for (int m = 0; m < CPT; ++m) {
+                if (cell[m] < 0) continue;
+                const int c0 = cell[m];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T* u = su + c * N;
+                    const T uc = ur[m][c];
+                    const T uyp = LINE ? T(0) : u[c0 + sy], uym = LINE ? T(0) : u[c0 - sy];
+                    const T uzp = LINE ? T(0) : u[c0 + sz], uzm = LINE ? T(0) : u[c0 - sz];
+                    T acc = gx * (u[c0 + 1] - uc) - gx * (uc - u[c0 - 1]) + gy * (uyp - uc) - gy * (uc - uym)
+                          + gz * (uzp - uc) - gz * (uc - uzm);
+                    const T wc = wr[m][c];
+                    if constexpr (VISC) {
+                        const T* w = sw + c * N;
+                        const T wyp = LINE ? T(0) : w[c0 + sy], wym = LINE ? T(0) : w[c0 - sy];
+                        const T wzp = LINE ? T(0) : w[c0 + sz], wzm = LINE ? T(0) : w[c0 - sz];
+                        const T lw = (w[c0 + 1] + w[c0 - 1] - T(2) * wc) * ihx2 + (wyp + wym - T(2) * wc) * ihy2
+                                   + (wzp + wzm - T(2) * wc) * ihz2;
+                        acc += eta_dt * lw;
+                    }
+                    if (gn != T(0)) acc += gn * fs[m][c];
+                    const T wnew = a1[m] * wc + a2[m] * acc;
+                    wr[m][c] = wnew;
+                    ur[m][c] = uc + wnew;
+                }
+            }
+            lds_barrier();  // every read of the old state is done
+#pragma unroll
+            for (int m = 0; m < CPT; ++m)
+                if (cell[m] >= 0)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        su[c * N + cell[m]] = ur[m][c];
+                        if constexpr (VISC) sw[c * N + cell[m]] = wr[m][c];
+                    }
+            lds_barrier();  // the new state is complete
+            for (int p = threadIdx.x; p < npi; p += nthr) strace[sc * npi + p] = su[sprobe[p]];
+        }
+        lds_barrier();  // the chunk's probe values are complete
+        for (int q = threadIdx.x; q < cn * npi; q += nthr)
+            traces[(st0 + q / npi) * (long long)np + pf + q % npi] = (double)strace[q];
+        // the next chunk writes senv and strace only after the barrier that
+        // follows its envelope load, i.e. after these reads
+    }
+    // the run leaves the instance's state in the buffers current after nsteps
+    // (w in LDS is stale without viscosity: the registers hold it)
+    T* du = (nsteps & 1) ? a.un : const_cast<T*>(a.u);
+    T* dw = (nsteps & 1) ? a.wn : const_cast<T*>(a.w);
+#pragma unroll
+    for (int m = 0; m < CPT; ++m)
+        if (cell[m] >= 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sw[c * N + cell[m]] = wr[m][c];
+    lds_barrier();
+    for (int q = threadIdx.x; q < 3 * N; q += nthr) {
+        du[q] = su[q];
+        dw[q] = sw[q];
+    }
+}
+
+// LDS of the persistent kernel: the state (6 N values), a chunk's envelope
+// and probe values, and the probe cells, for the instance with the most
+// probes.
+template <typename T>
+size_t small_lds_bytes(const kvs_batch* b, const kvs_ctx* c) {
+    int64_t most = 0;
+    for (size_t i = 0; i + 1 < b->probe_first.size(); ++i)
+        most = std::max<int64_t>(most, b->probe_first[i + 1] - b->probe_first[i]);
+    return (6 * (size_t)c->N + kSmallChunk * (1 + (size_t)most)) * sizeof(T) + sizeof(int) * (size_t)most;
+}
+
+// Threads per workgroup (a multiple of 64, at most 1024, enough for one
+// interior cell each where possible) and cells per thread.
+template <typename T>
+bool small_fits(const kvs_batch* b, int* cpt, int* threads) {
+    long long most = 1;
+    for (const kvs_ctx* c : b->inst) {
+        const kvs_grid& g = c->grid;
+        if (small_lds_bytes<T>(b, c) > kSmallMaxLds) return false;
+        most = std::max<long long>(most, (g.nx - 2) * (g.ny - 2) * (g.nz - 2));
+    }
+    const int thr = (int)std::min<long long>(kSmallMaxThreads, 64 * ((most + 63) / 64));
+    const long long need = (most + thr - 1) / thr;
+    if (need > 8) return false;
+    *threads = thr;
+    *cpt = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+    return true;
+}
+
+template <typename T, bool VISC, int CPT, bool LINE>
+hipError_t launch_small_shape(kvs_batch* b, int64_t nsteps, int threads) {
+    size_t lds = 0;
+    for (const kvs_ctx* c : b->inst) lds = std::max(lds, small_lds_bytes<T>(b, c));
+    static bool attr_set = false;  // one attribute call per instantiation
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)batch_small_kernel<T, VISC, CPT, LINE>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallMaxLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int np = (int)b->probe_inst.size();
+    const long long* pr = static_cast<const long long*>(b->dev_probes);
+    double* tr = np > 0 ? b->traces + b->trace_steps * np : nullptr;
+    hipLaunchKernelGGL((batch_small_kernel<T, VISC, CPT, LINE>), dim3((unsigned)b->inst.size()), dim3(threads), lds,
+                       b->stream, static_cast<const BatchInst<T>*>(b->dev_params), pr, np > 0 ? pr + 2 * np : nullptr,
+                       np, b->comp, tr, (long long)b->step, (long long)nsteps);
+    return hipGetLastError();
+}
+
+template <typename T, bool VISC>
+hipError_t launch_small(kvs_batch* b, int64_t nsteps, int cpt, int threads) {
+    bool line = true;
+    for (const kvs_ctx* c : b->inst) line = line && c->grid.ny == 3 && c->grid.nz == 3;
+    if (line) {
+        switch (cpt) {
+            case 1: return launch_small_shape<T, VISC, 1, true>(b, nsteps, threads);
+            case 2: return launch_small_shape<T, VISC, 2, true>(b, nsteps, threads);
+            case 4: return launch_small_shape<T, VISC, 4, true>(b, nsteps, threads);
+            default: return launch_small_shape<T, VISC, 8, true>(b, nsteps, threads);
+        }
+    }
+    switch (cpt) {
+        case 1: return launch_small_shape<T, VISC, 1, false>(b, nsteps, threads);
+        case 2: return launch_small_shape<T, VISC, 2, false>(b, nsteps, threads);
+        case 4: return launch_small_shape<T, VISC, 4, false>(b, nsteps, threads);
+        default: return launch_small_shape<T, VISC, 8, false>(b, nsteps, threads);
+    }
+}
+
+template <typename T>
+hipError_t run_small_t(kvs_batch* b, int64_t nsteps, int cpt, int threads) {
+    return b->viscous ? launch_small<T, true>(b, nsteps, cpt, threads) : launch_small<T, false>(b, nsteps, cpt, threads);
+}
+
+}  // namespace
+
+bool kvs_batch_small_path(const kvs_batch* b) {
+    int cpt = 0, thr = 0;
+    return b->small_ok && (b->prec == KVS_FP32 ? small_fits<float>(b, &cpt, &thr) : small_fits<double>(b, &cpt, &thr));
+}
+
+// One uncaptured step launch that only rewrites the next buffers (parity 0,
+// no force): used to time tile shapes without advancing the state.
+hipError_t kvs_batch_trial_launch(kvs_batch* b) {
+    if (b->prec == KVS_FP32) {
+        b->viscous ? launch_batch_step<float, true, false>(b, b->step, 0)
+                   : launch_batch_step<float, false, false>(b, b->step, 0);
+    } else {
+        b->viscous ? launch_batch_step<double, true, false>(b, b->step, 0)
+                   : launch_batch_step<double, false, false>(b, b->step, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t kvs_batch_prepare(kvs_batch* b) {
+    return b->prec == KVS_FP32 ? prepare_t<float>(b) : prepare_t<double>(b);
+}
+
+hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
+    int cpt = 0, thr = 0;
+    if (b->small_ok && (b->prec == KVS_FP32 ? small_fits<float>(b, &cpt, &thr) : small_fits<double>(b, &cpt, &thr)))
+        return b->prec == KVS_FP32 ? run_small_t<float>(b, nsteps, cpt, thr) : run_small_t<double>(b, nsteps, cpt, thr);
+    // Replay the cached graph when it was captured for the same start step,
+    // step count, trace slot and per-step force switch (the parameter table
+    // and envelopes it reads were refreshed in place by kvs_batch_prepare);
+    // otherwise capture a new one.
+    std::vector<uint8_t> force_mask = batch_force_mask(b, nsteps);
+    const bool hit = b->graph_valid && b->graph && b->graph_start == b->step && b->graph_steps == nsteps &&
+                     b->graph_trace0 == b->trace_steps && b->graph_force == force_mask;
+    hipError_t e = hipSuccess;
+    if (!hit) {
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        b->graph_valid = false;
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t le = b->prec == KVS_FP32 ? capture_t<float>(b, nsteps, force_mask)
+                                                      : capture_t<double>(b, nsteps, force_mask);
+            e = hipStreamEndCapture(b->stream, &graph);
+            if (e == hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        b->graph_valid = true;
+        b->graph_start = b->step;
+        b->graph_steps = nsteps;
+        b->graph_trace0 = b->trace_steps;
+        b->graph_force.swap(force_mask);
+    }
+    return hipGraphLaunch(b->graph, b->stream);
+}

@@ -1,384 +1,11 @@
-// FDTD step of the reduced Kelvin-Voigt shear equation on gfx950, plus the
-// small per-cell helper kernels (material casts, dt^2/rho, stable dt,
-// probe gather).
-//
-// Update (Sec. 3.1 leapfrog in summed form, Sec. 3.3 separable source,
-// Sec. 3.5 Dirichlet layer), per interior cell and component c:
-//   acc = div(G grad u_c) + (eta/dt) lap(w_c) + g_n f_S,c
-//   w'  = a1 w_c + a2 acc,  a1 = (1-s)/(1+s), a2 = (dt^2/rho)/(1+s)
-//   u'  = u_c + w'
-// with s = sigma dt / 2 from the linear sponge ramp and harmonic face moduli.
-//
-// Kernel layout ("2.5-D" blocking).  A block of 64 WX x BY threads owns a
-// TX x BY column tile in the xy plane (TX = 64 WX VEC) and marches over a
-// chunk of z planes.  One 64-lane wavefront covers 64 VEC consecutive cells of
-// an x row, so every global access is a fully coalesced row segment; WX > 1
-// puts several wavefronts side by side on a row, which spreads the two x-halo
-// columns over a wider tile without more registers per lane.  Per plane the block stages the
-// fields that are needed at xy neighbours (u, plus w when eta != 0, plus G
-// when heterogeneous) in LDS with a one-cell halo; z neighbours live in a
-// per-thread register queue (k-1, k, k+1, with k+2 prefetched).  Each cell's
-// state is therefore read from HBM once per step; halo rows of adjacent tiles
-// are served by L2 because tiles are issued XCD-contiguously (see tile_of).
+// FDTD step kernel of one context (tile code in kvs_step_tile.hpp), its
+// launch shapes, and the small per-cell helper kernels (material casts,
+// dt^2/rho, stable dt, probe gather).
 #include <hip/hip_ext.h>
 
-#include "kvs_internal.hpp"
-#include "kvs_tiling.hpp"
+#include "kvs_step_tile.hpp"
 
 namespace {
-
-using kvs_tiling::choose_kchunk;
-using kvs_tiling::lds_barrier;
-using kvs_tiling::resident_blocks;
-using kvs_tiling::tile_of;
-
-template <typename T>
-struct StepArgs {
-    const T* u;     // [3][N] current u^n
-    const T* w;     // [3][N] current w^n
-    T* un;          // [3][N] u^{n+1}
-    T* wn;          // [3][N] w^{n+1}
-    const T* G;     // [N] (heterogeneous)
-    const T* eta;   // [N] (heterogeneous)
-    const T* crho;  // [N] dt^2/rho (heterogeneous)
-    const T* FS;    // [3][N] projected force (when gn != 0)
-    long long N;
-    int nx, ny, nz;
-    int gx, gy, gz;  // tiles per axis
-    int kchunk;
-    int L;           // sponge cells
-    T invL;
-    T ihx2, ihy2, ihz2;
-    T G0, eta_dt0, crho0;  // homogeneous medium
-    T inv_dt;
-    T gn;
-    T half_dt_smax;  // sigma_max * dt / 2
-    int remap;       // 1: XCD-contiguous tile order
-    // probe blocks: the first pblocks blocks of a launch copy the input state
-    // (the previous step's result) at the probe cells into pout (probe p of
-    // component pcomp at pout[p], or all components at pout[3 p + c]); the
-    // remaining blocks are the tiles
-    const long long* pcells;
-    double* pout;
-    long long np;
-    int pcomp, pblocks;
-};
-
-template <typename T>
-__device__ __forceinline__ T harm(T a, T b);
-template <>
-__device__ __forceinline__ float harm<float>(float a, float b) {
-    return 2.0f * a * b * __builtin_amdgcn_rcpf(a + b);
-}
-template <>
-__device__ __forceinline__ double harm<double>(double a, double b) {
-    return 2.0 * a * b / (a + b);
-}
-
-template <typename T>
-__device__ __forceinline__ T ramp(int idx, int n, int L, T invL) {
-    const int d = min(idx, n - 1 - idx);
-    return d < L ? T(L - d) * invL : T(0);
-}
-
-template <typename T>
-__device__ __forceinline__ T rcp_fast(T x);
-template <>
-__device__ __forceinline__ float rcp_fast<float>(float x) {
-    return __builtin_amdgcn_rcpf(x);
-}
-template <>
-__device__ __forceinline__ double rcp_fast<double>(double x) {
-    return 1.0 / x;
-}
-
-// Vector of VEC consecutive x cells held by one lane.
-template <typename T, int V>
-struct VecT {
-    typedef T type __attribute__((ext_vector_type(V)));
-};
-template <typename T>
-struct VecT<T, 1> {
-    typedef T type;
-};
-
-template <typename T, int V>
-__device__ __forceinline__ void vload(const T* p, T (&o)[V]) {
-    if constexpr (V == 1) {
-        o[0] = *p;
-    } else {
-        const typename VecT<T, V>::type x = *reinterpret_cast<const typename VecT<T, V>::type*>(p);
-#pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = x[v];
-    }
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void vload_nt(const T* p, T (&o)[V]) {
-    if constexpr (V == 1) {
-        o[0] = __builtin_nontemporal_load(p);
-    } else {
-        const typename VecT<T, V>::type x =
-            __builtin_nontemporal_load(reinterpret_cast<const typename VecT<T, V>::type*>(p));
-#pragma unroll
-        for (int v = 0; v < V; ++v) o[v] = x[v];
-    }
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void vstore_nt(T* p, const T (&a)[V]) {
-    if constexpr (V == 1) {
-        __builtin_nontemporal_store(a[0], p);
-    } else {
-        typename VecT<T, V>::type x;
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[v] = a[v];
-        __builtin_nontemporal_store(x, reinterpret_cast<typename VecT<T, V>::type*>(p));
-    }
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void vlds_write(T* p, const T (&a)[V]) {
-    if constexpr (V == 1) {
-        *p = a[0];
-    } else {
-        typename VecT<T, V>::type x;
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[v] = a[v];
-        *reinterpret_cast<typename VecT<T, V>::type*>(p) = x;
-    }
-}
-
-// The loop body is straight-line on purpose: every lane issues every load
-// (addresses clamped in bounds), writes LDS unconditionally (lanes without
-// halo work into a dummy row) and stores unconditionally (values of cells
-// that are not interior are 0, written into boundary cells that hold 0).
-// Branch-free memory code lets the compiler count outstanding loads exactly,
-// so the plane-ahead prefetch stays in flight across the barrier instead of
-// being drained every plane.
-//
-// A lane owns VEC consecutive x cells (one dword or dwordx2 access per
-// field); WX wavefronts cover TX = 64 WX VEC cells of one x row, a block BY
-// rows.
-// LDS row layout: [pad][left halo][TX cells][right halo][pad], so that every
-// lane's VEC-wide write is naturally aligned, including the halo writes.
-template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WX>
-__device__ __forceinline__ void step_tile(const StepArgs<T>& a, int bx, int by, int bz) {
-    static_assert(BY >= 3 && 2 * BY <= 64, "halo lane assignment needs 3 <= BY <= 32");
-    static_assert(64 * WX * BY <= 1024, "at most 1024 threads per block");
-    constexpr int NQ = 3 + (VISC ? 3 : 0) + (HET ? 1 : 0);
-    constexpr int QG = VISC ? 6 : 3;
-    constexpr int TX = 64 * WX * VEC;
-    constexpr int W = TX + 4;
-    constexpr int DUMMY = BY + 2;
-    __shared__ T lds[2][NQ][BY + 3][W];
-
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int nx = a.nx, ny = a.ny;
-    const int i0 = bx * TX + VEC * tx;  // first of this lane's cells
-    const int j = by * BY + ty;
-    const int kb = 1 + bz * a.kchunk;
-    const int ke = min(a.nz - 1, kb + a.kchunk);  // planes kb .. ke-1
-    const bool inb = i0 < nx && j < ny;          // VEC > 1 needs nx % VEC == 0
-    bool act[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) act[v] = i0 + v >= 1 && i0 + v <= nx - 2 && j >= 1 && j <= ny - 2;
-    const int sxy = nx * ny;
-    const int col = inb ? i0 + nx * j : 0;
-    // store column: the lane's own cells; lanes outside the grid store zeros
-    // into boundary row ny-1
-    const int scol = inb ? col : min(i0, nx - VEC) + nx * (ny - 1);
-    const int lcol = 2 + VEC * tx;  // LDS column of the lane's first cell
-
-    // one halo slot per lane: wave 0 loads the row below the tile, wave BY-1
-    // the row above, lanes 0..2BY-1 of wave 1 the VEC-wide pieces whose
-    // last / first element is the left / right halo column of each row
-    int h_off = col, h_row = DUMMY, h_col = lcol;
-    bool h_real = true;
-    if (ty == 0) {
-        if (j >= 1 && i0 < nx) {
-            h_off = col - nx;
-            h_row = 0;
-        }
-    } else if (ty == BY - 1) {
-        if (j + 1 < ny && i0 < nx) {
-            h_off = col + nx;
-            h_row = BY + 1;
-        }
-    } else if (ty == 1 && tx < 2 * BY) {
-        h_real = false;
-        const int row = tx % BY;
-        const bool right = tx >= BY;
-        const int ii = bx * TX + (right ? TX : -VEC);
-        const int jj = by * BY + row;
-        if (ii >= 0 && ii < nx && jj < ny) {
-            h_off = ii + nx * jj;
-            h_row = row + 1;
-            h_col = right ? TX + 2 : 2 - VEC;
-            h_real = true;
-        }
-    } else {
-        h_real = false;
-    }
-    if (h_row == DUMMY) h_real = false;
-    // a lane without halo work re-reads its own prefetch address (plane k+2)
-    const int h_dz = h_real ? 1 : 2;
-
-    const T* fp[NQ];
-    fp[0] = a.u;
-    fp[1] = a.u + a.N;
-    fp[2] = a.u + 2 * a.N;
-    if constexpr (VISC) {
-        fp[3] = a.w;
-        fp[4] = a.w + a.N;
-        fp[5] = a.w + 2 * a.N;
-    }
-    if constexpr (HET) fp[QG] = a.G;
-
-    // z register queue (k-1, k, k+1, prefetched k+2), halo of plane k (and
-    // k+1 prefetched), per-cell values of plane k (and k+1 prefetched)
-    T zm[NQ][VEC], zc[NQ][VEC], zp[NQ][VEC], zn[NQ][VEC], hc[NQ][VEC], hn[NQ][VEC];
-    T wo_c[3][VEC], wo_n[3][VEC], fs_c[3][VEC], fs_n[3][VEC];
-    T crho_c[VEC], crho_n[VEC], eta_c[VEC], eta_n[VEC];
-#pragma unroll
-    for (int f = 0; f < NQ; ++f) {
-        vload<T, VEC>(fp[f] + (kb - 1) * sxy + col, zm[f]);
-        vload<T, VEC>(fp[f] + kb * sxy + col, zc[f]);
-        vload<T, VEC>(fp[f] + (kb + 1) * sxy + col, zp[f]);
-        vload<T, VEC>(fp[f] + kb * sxy + h_off, hc[f]);
-    }
-    {
-        const int q = kb * sxy + col;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                wo_c[c][v] = wo_n[c][v] = T(0);
-                fs_c[c][v] = fs_n[c][v] = T(0);
-            }
-            if constexpr (!VISC) vload<T, VEC>(a.w + c * a.N + q, wo_c[c]);
-            if constexpr (FORCE) vload<T, VEC>(a.FS + c * a.N + q, fs_c[c]);
-        }
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            crho_c[v] = crho_n[v] = a.crho0;
-            eta_c[v] = eta_n[v] = T(0);
-        }
-        if constexpr (HET) {
-            vload<T, VEC>(a.crho + q, crho_c);
-            if constexpr (VISC) vload<T, VEC>(a.eta + q, eta_c);
-        }
-    }
-
-    T rxy[VEC];
-#pragma unroll
-    for (int v = 0; v < VEC; ++v)
-        rxy[v] = a.L > 0 ? max(ramp<T>(i0 + v, nx, a.L, a.invL), ramp<T>(j, ny, a.L, a.invL)) : T(0);
-    const T ihx2 = a.ihx2, ihy2 = a.ihy2, ihz2 = a.ihz2;
-
-    for (int k = kb; k < ke; ++k) {
-        const int buf = k & 1;
-#pragma unroll
-        for (int f = 0; f < NQ; ++f) {
-            vlds_write<T, VEC>(&lds[buf][f][ty + 1][lcol], zc[f]);
-            vlds_write<T, VEC>(&lds[buf][f][h_row][h_col], hc[f]);
-        }
-        // prefetch: centre of plane k+2, halo and per-cell values of k+1
-        // (clamped to planes that exist; the clamped values go unused)
-        const int k2 = min(k + 2, ke);
-        const int k1 = min(k + 1, ke - 1);
-#pragma unroll
-        for (int f = 0; f < NQ; ++f) {
-            vload<T, VEC>(fp[f] + k2 * sxy + col, zn[f]);
-            vload<T, VEC>(fp[f] + min(k + h_dz, ke) * sxy + h_off, hn[f]);
-        }
-        {
-            const int q = k1 * sxy + col;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if constexpr (!VISC) vload<T, VEC>(a.w + c * a.N + q, wo_n[c]);
-                if constexpr (FORCE) vload_nt<T, VEC>(a.FS + c * a.N + q, fs_n[c]);
-            }
-            if constexpr (HET) {
-                vload_nt<T, VEC>(a.crho + q, crho_n);
-                if constexpr (VISC) vload_nt<T, VEC>(a.eta + q, eta_n);
-            }
-        }
-        lds_barrier();
-
-        const T rz = a.L > 0 ? ramp<T>(k, a.nz, a.L, a.invL) : T(0);
-        T uo[3][VEC], wo[3][VEC];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            const int lc = lcol + v;
-            const T s = a.half_dt_smax * max(rxy[v], rz);
-            const T inv1ps = rcp_fast<T>(T(1) + s);
-            const T a1 = (T(1) - s) * inv1ps;
-            const T a2 = crho_c[v] * inv1ps;
-            const T eta_dt = HET ? eta_c[v] * a.inv_dt : a.eta_dt0;
-            T gxm, gxp, gym, gyp, gzm, gzp;
-            if constexpr (HET) {
-                const T Gc = zc[QG][v];
-                gxm = harm<T>(Gc, lds[buf][QG][ty + 1][lc - 1]) * ihx2;
-                gxp = harm<T>(Gc, lds[buf][QG][ty + 1][lc + 1]) * ihx2;
-                gym = harm<T>(Gc, lds[buf][QG][ty][lc]) * ihy2;
-                gyp = harm<T>(Gc, lds[buf][QG][ty + 2][lc]) * ihy2;
-                gzm = harm<T>(Gc, zm[QG][v]) * ihz2;
-                gzp = harm<T>(Gc, zp[QG][v]) * ihz2;
-            } else {
-                gxm = gxp = a.G0 * ihx2;
-                gym = gyp = a.G0 * ihy2;
-                gzm = gzp = a.G0 * ihz2;
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T uc = zc[c][v];
-                T acc = gxp * (lds[buf][c][ty + 1][lc + 1] - uc) - gxm * (uc - lds[buf][c][ty + 1][lc - 1])
-                      + gyp * (lds[buf][c][ty + 2][lc] - uc) - gym * (uc - lds[buf][c][ty][lc])
-                      + gzp * (zp[c][v] - uc) - gzm * (uc - zm[c][v]);
-                T wc;
-                if constexpr (VISC) {
-                    wc = zc[3 + c][v];
-                    const T lw = (lds[buf][3 + c][ty + 1][lc + 1] + lds[buf][3 + c][ty + 1][lc - 1] - T(2) * wc) * ihx2
-                               + (lds[buf][3 + c][ty + 2][lc] + lds[buf][3 + c][ty][lc] - T(2) * wc) * ihy2
-                               + (zp[3 + c][v] + zm[3 + c][v] - T(2) * wc) * ihz2;
-                    acc += eta_dt * lw;
-                } else {
-                    wc = wo_c[c][v];
-                }
-                if constexpr (FORCE) acc += a.gn * fs_c[c][v];
-                const T wnew = a1 * wc + a2 * acc;
-                wo[c][v] = act[v] ? wnew : T(0);
-                uo[c][v] = act[v] ? uc + wnew : T(0);
-            }
-        }
-        const int sidx = k * sxy + scol;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            vstore_nt<T, VEC>(a.wn + c * a.N + sidx, wo[c]);
-            vstore_nt<T, VEC>(a.un + c * a.N + sidx, uo[c]);
-        }
-#pragma unroll
-        for (int f = 0; f < NQ; ++f)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                zm[f][v] = zc[f][v];
-                zc[f][v] = zp[f][v];
-                zp[f][v] = zn[f][v];
-                hc[f][v] = hn[f][v];
-            }
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                wo_c[c][v] = wo_n[c][v];
-                fs_c[c][v] = fs_n[c][v];
-            }
-            crho_c[v] = crho_n[v];
-            eta_c[v] = eta_n[v];
-        }
-    }
-}
 
 // One context: tile from the block index (XCD-contiguous order when remap).
 template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WX, int WPE>
@@ -402,52 +29,6 @@ __global__ __launch_bounds__(64 * WX * BY) __attribute__((amdgpu_waves_per_eu(WP
     const int b = (int)blockIdx.x - a.pblocks;
     const int t = a.remap ? tile_of(b, B) : b;
     step_tile<T, HET, VISC, FORCE, BY, VEC, WX>(a, t % a.gx, (t / a.gx) % a.gy, t / (a.gx * a.gy));
-}
-
-// Batched homogeneous instances: one launch covers every instance's tiles
-// through a work list (instance, bx, by, bz).  `parity` (steps since the
-// table was built, mod 2) selects which ping-pong buffers are current; the
-// absolute step n indexes each instance's envelope.
-template <typename T>
-struct BatchInst {
-    StepArgs<T> a[2];  // [parity]: u, w current / next swapped
-    const double* env;
-    long long n_env;
-};
-
-template <typename T, bool VISC, bool FORCE, int BY, int VEC, int WX>
-__global__ __launch_bounds__(64 * WX * BY) void batch_step_kernel(const BatchInst<T>* inst, const int4* work,
-                                                                  int nwork, long long n, int parity) {
-    const int t = tile_of(blockIdx.x, nwork);
-    const int4 wi = work[t];
-    const BatchInst<T>& bi = inst[wi.x];
-    StepArgs<T> a = bi.a[parity];
-    a.gn = n < bi.n_env ? T(bi.env[n]) : T(0);
-    step_tile<T, false, VISC, FORCE, BY, VEC, WX>(a, wi.y, wi.z, wi.w);
-}
-
-// Step-kernel variants (tile rows BY, cells per lane VEC, wavefronts per row
-// WX) chosen by kvs_autotune_step; variant 0 is the default.
-struct StepVariant {
-    int by, vec, wx, wpe;
-};
-// wpe: minimum waves per SIMD asked of the register allocator (1 = free)
-constexpr StepVariant kVariants[] = {{4, 1, 1, 1}, {8, 1, 1, 1}, {4, 2, 1, 1}, {8, 2, 1, 1},
-                                     {16, 1, 1, 1}, {4, 1, 2, 1}, {8, 1, 2, 1}, {4, 1, 4, 1}};
-constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-
-// The shape a launch actually uses.  VEC = 2 needs an even nx so that every
-// lane's pair is aligned and whole.  FP64 (the parity mode) uses one cell per
-// lane and tiles of at most 8 rows and 128 columns: larger FP64 tiles spill
-// registers or exceed the 160 KB of LDS (two buffered planes of 7 fields).
-int effective_variant(int v, bool fp64, bool odd_nx) {
-    if (v < 0 || v >= kNumVariants) v = 0;
-    if (kVariants[v].vec == 2 && (fp64 || odd_nx)) v = kVariants[v].by == 8 ? 1 : 0;
-    if (fp64) {
-        if (v == 4) v = 1;
-        if (v == 6 || v == 7) v = 5;
-    }
-    return v;
 }
 
 template <typename T, bool HET, bool VISC, bool FORCE, int BY, int VEC, int WX, int WPE = 1>
@@ -764,516 +345,4 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
                        (int)g.nz, S, partial, partial + nb);
     hipLaunchKernelGGL(minmax_finalize_kernel, dim3(1), dim3(256), 0, c->stream, partial, partial + nb, nb, out);
     return hipGetLastError();
-}
-
-// ---- batched stepping -------------------------------------------------------
-
-namespace {
-
-template <typename T>
-StepArgs<T> instance_args(kvs_ctx* c, int cur, int by, int vec, int wx, int zchunk) {
-    const kvs_grid& g = c->grid;
-    StepArgs<T> a{};
-    a.u = static_cast<const T*>(c->u[cur]);
-    a.w = static_cast<const T*>(c->w[cur]);
-    a.un = static_cast<T*>(c->u[1 - cur]);
-    a.wn = static_cast<T*>(c->w[1 - cur]);
-    a.FS = static_cast<const T*>(c->FS);
-    a.N = c->N;
-    a.nx = (int)g.nx;
-    a.ny = (int)g.ny;
-    a.nz = (int)g.nz;
-    a.gx = (a.nx + 64 * wx * vec - 1) / (64 * wx * vec);
-    a.gy = (a.ny + by - 1) / by;
-    a.kchunk = std::min(zchunk, a.nz - 2);
-    a.gz = (a.nz - 2 + a.kchunk - 1) / a.kchunk;
-    a.L = c->sponge_cells;
-    a.invL = a.L > 0 ? T(1.0 / a.L) : T(0);
-    a.ihx2 = T(1.0 / (g.hx * g.hx));
-    a.ihy2 = T(1.0 / (g.hy * g.hy));
-    a.ihz2 = T(1.0 / (g.hz * g.hz));
-    a.G0 = T(c->G0);
-    a.eta_dt0 = T(c->eta0 / c->dt);
-    a.crho0 = T(c->dt * c->dt / c->rho0);
-    a.inv_dt = T(1.0 / c->dt);
-    a.gn = T(0);
-    a.half_dt_smax = T(0.5 * c->sigma_max * c->dt);
-    a.remap = 1;
-    return a;
-}
-
-// Batch tile shapes: ids 0 .. kNumVariants-1 are the step-kernel variants;
-// kShape192 is a 192 x 4 tile (three wavefronts per row), used only by the
-// row-fitted tiling.
-constexpr int kShape192 = kNumVariants;
-
-void batch_shape_dims(int shape, int* by, int* vec, int* wx) {
-    if (shape == kShape192) {
-        *by = 4;
-        *vec = 1;
-        *wx = 3;
-        return;
-    }
-    *by = kVariants[shape].by;
-    *vec = kVariants[shape].vec;
-    *wx = kVariants[shape].wx;
-}
-
-// The narrowest tile spanning an x row of nx cells: the row is then loaded
-// once per tile with its Dirichlet ends as the x halo, instead of each tile
-// re-reading two halo columns of its neighbours.  FP64 stays within the
-// shapes whose two buffered planes fit the LDS (64 x 8, 128 x 4).
-int fit_shape(int nx, bool fp64) {
-    if (nx <= 64) return 1;  // 64 x 8
-    if (fp64) return 5;      // 128 x 4
-    if (nx <= 128) return 6; // 128 x 8
-    if (nx <= 192) return kShape192;
-    return 7;                // 256 x 4 (several per row beyond 256)
-}
-
-// The batch's tile shape, narrowed like the single-context launch (two
-// cells per lane need every instance's nx even).
-int batch_variant(const kvs_batch* b) {
-    int v = b->variant;
-    if (v < 0 || v >= kNumVariants) v = 1;
-    bool even = true;
-    for (const kvs_ctx* c : b->inst) even = even && (c->grid.nx % 2 == 0);
-    return effective_variant(v, b->prec == KVS_FP64, !even);
-}
-
-// Tile shape of instance c in batch b.
-int instance_shape(const kvs_batch* b, const kvs_ctx* c) {
-    if (b->variant == KVS_BATCH_FIT_ROWS) return fit_shape((int)c->grid.nx, b->prec == KVS_FP64);
-    return batch_variant(b);
-}
-
-template <typename T>
-__global__ void batch_probe_kernel(const BatchInst<T>* inst, const long long* probes, int np, int comp, int parity,
-                                   double* out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const StepArgs<T>& a = inst[probes[2 * p]].a[parity];
-    out[p] = (double)a.un[comp * a.N + probes[2 * p + 1]];  // u after the step
-}
-
-template <typename T>
-hipError_t prepare_t(kvs_batch* b) {
-    const int n = (int)b->inst.size();
-    std::vector<BatchInst<T>> params((size_t)n);
-    std::vector<int4> work;
-    bool visc = false;
-    size_t env_total = 0;
-    for (int i = 0; i < n; ++i) env_total += b->inst[(size_t)i]->env.size();
-    const size_t pbytes = sizeof(BatchInst<T>) * (size_t)n;
-    const size_t ebytes = sizeof(double) * std::max<size_t>(env_total, 1);
-    hipError_t e = hipSuccess;
-    if (!b->dev_params || b->params_bytes < pbytes + ebytes) {
-        b->mem.put(b->dev_params);  // after the stream's earlier steps (put synchronises)
-        b->dev_params = nullptr;
-        e = b->mem.get(&b->dev_params, pbytes + ebytes);
-        if (e != hipSuccess) return e;
-        b->params_bytes = pbytes + ebytes;
-        b->graph_valid = false;  // the graph holds the old table's address
-    }
-    double* env_dev = reinterpret_cast<double*>(static_cast<char*>(b->dev_params) + pbytes);
-    std::vector<double> env_host(std::max<size_t>(env_total, 1), 0.0);
-    size_t off = 0;
-    std::vector<int> shape((size_t)n);
-    for (int i = 0; i < n; ++i) {
-        kvs_ctx* c = b->inst[(size_t)i];
-        shape[(size_t)i] = instance_shape(b, c);
-        int by = 0, vec = 0, wx = 0;
-        batch_shape_dims(shape[(size_t)i], &by, &vec, &wx);
-        params[(size_t)i].a[0] = instance_args<T>(c, c->cur, by, vec, wx, b->zchunk);
-        params[(size_t)i].a[1] = instance_args<T>(c, 1 - c->cur, by, vec, wx, b->zchunk);
-        params[(size_t)i].env = env_dev + off;
-        params[(size_t)i].n_env = (long long)c->env.size();
-        std::copy(c->env.begin(), c->env.end(), env_host.begin() + off);
-        off += c->env.size();
-        visc = visc || c->viscous;
-    }
-    if (!b->dev_work) {
-        // the work list grouped by tile shape: one launch per group
-        b->groups.clear();
-        for (int sh = 0; sh <= kShape192; ++sh) {
-            const int first = (int)work.size();
-            for (int i = 0; i < n; ++i) {
-                if (shape[(size_t)i] != sh) continue;
-                const StepArgs<T>& a = params[(size_t)i].a[0];
-                for (int bz = 0; bz < a.gz; ++bz)
-                    for (int by = 0; by < a.gy; ++by)
-                        for (int bx = 0; bx < a.gx; ++bx) work.push_back(make_int4(i, bx, by, bz));
-            }
-            if ((int)work.size() > first) b->groups.push_back({sh, first, (int)work.size() - first});
-        }
-    }
-    e = hipMemcpyAsync(b->dev_params, params.data(), pbytes, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(env_dev, env_host.data(), ebytes, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess && !b->dev_work) {
-        e = b->mem.get(&b->dev_work, sizeof(int4) * work.size());
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->dev_work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice,
-                               b->stream);
-        b->nwork = (int)work.size();
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (visc != b->viscous) b->graph_valid = false;
-    b->viscous = visc;
-    return e;
-}
-
-template <typename T, bool VISC, bool FORCE, int BY, int VEC, int WX>
-void launch_batch_shape(kvs_batch* b, long long n, int parity, const kvs_batch::Group& g) {
-    hipLaunchKernelGGL((batch_step_kernel<T, VISC, FORCE, BY, VEC, WX>), dim3(g.count), dim3(64 * WX, BY), 0,
-                       b->stream, static_cast<const BatchInst<T>*>(b->dev_params),
-                       static_cast<const int4*>(b->dev_work) + g.off, g.count, n, parity);
-}
-
-// One launch per tile-shape group (a single group unless the tiling is
-// fitted to each instance's rows).
-template <typename T, bool VISC, bool FORCE>
-void launch_batch_step(kvs_batch* b, long long n, int parity) {
-    for (const kvs_batch::Group& g : b->groups) {
-        if constexpr (sizeof(T) == 8) {
-            switch (g.shape) {
-                case 1: launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity, g); break;
-                case 5: launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity, g); break;
-                default: launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity, g); break;
-            }
-        } else {
-            switch (g.shape) {
-                case 1: launch_batch_shape<T, VISC, FORCE, 8, 1, 1>(b, n, parity, g); break;
-                case 2: launch_batch_shape<T, VISC, FORCE, 4, 2, 1>(b, n, parity, g); break;
-                case 3: launch_batch_shape<T, VISC, FORCE, 8, 2, 1>(b, n, parity, g); break;
-                case 4: launch_batch_shape<T, VISC, FORCE, 16, 1, 1>(b, n, parity, g); break;
-                case 5: launch_batch_shape<T, VISC, FORCE, 4, 1, 2>(b, n, parity, g); break;
-                case 6: launch_batch_shape<T, VISC, FORCE, 8, 1, 2>(b, n, parity, g); break;
-                case 7: launch_batch_shape<T, VISC, FORCE, 4, 1, 4>(b, n, parity, g); break;
-                case kShape192: launch_batch_shape<T, VISC, FORCE, 4, 1, 3>(b, n, parity, g); break;
-                default: launch_batch_shape<T, VISC, FORCE, 4, 1, 1>(b, n, parity, g); break;
-            }
-        }
-    }
-}
-
-// Per step of the run starting at b->step: 1 when any instance's envelope is
-// non-zero there (that step launches the kernel that reads f_S).
-std::vector<uint8_t> batch_force_mask(const kvs_batch* b, int64_t nsteps) {
-    std::vector<uint8_t> m((size_t)nsteps, 0);
-    for (int64_t q = 0; q < nsteps; ++q) {
-        const int64_t n = b->step + q;
-        for (const kvs_ctx* c : b->inst)
-            if (n < (int64_t)c->env.size() && c->env[(size_t)n] != 0.0) {
-                m[(size_t)q] = 1;
-                break;
-            }
-    }
-    return m;
-}
-
-template <typename T>
-hipError_t capture_t(kvs_batch* b, int64_t nsteps, const std::vector<uint8_t>& force_mask) {
-    const int np = (int)b->probe_inst.size();
-    for (int64_t q = 0; q < nsteps; ++q) {
-        const int64_t n = b->step + q;
-        const bool force = force_mask[(size_t)q] != 0;
-        const int parity = (int)(q & 1);
-        if (b->viscous)
-            force ? launch_batch_step<T, true, true>(b, n, parity) : launch_batch_step<T, true, false>(b, n, parity);
-        else
-            force ? launch_batch_step<T, false, true>(b, n, parity) : launch_batch_step<T, false, false>(b, n, parity);
-        if (np > 0)
-            hipLaunchKernelGGL(batch_probe_kernel<T>, dim3((np + 255) / 256), dim3(256), 0, b->stream,
-                               static_cast<const BatchInst<T>*>(b->dev_params),
-                               static_cast<const long long*>(b->dev_probes), np, b->comp, parity,
-                               b->traces + (b->trace_steps + q) * np);
-    }
-    return hipGetLastError();
-}
-
-// ---- persistent path for small instances -----------------------------------
-//
-// When every instance's whole state (u and w, three components each) fits in
-// one workgroup's LDS, a batch run is one launch of one block per instance
-// that advances its instance through all the steps in the kernel: the state
-// lives in LDS for the whole run, the block's threads own fixed interior
-// cells, and two block barriers per step separate reading the old state from
-// writing the new one; probe values are written after every step.  The
-// per-cell arithmetic is the step kernel's (same operand order, sponge
-// factors and FP32 reciprocal), so one launch replaces two launches per step
-// and the run is bound by the latency of a step, not by launches.
-constexpr int kSmallMaxThreads = 1024;
-constexpr int kSmallChunk = 64;  // steps whose envelope and probe values are staged in LDS at a time
-constexpr size_t kSmallMaxLds = 150 * 1024;
-
-// LINE: every instance is a line (ny = nz = 3): the y and z neighbours of an
-// interior node lie on the Dirichlet layer and are exactly 0, so they are
-// taken as the constant 0 instead of read (the same arithmetic).
-template <typename T, bool VISC, int CPT, bool LINE>
-__global__ __launch_bounds__(kSmallMaxThreads) void batch_small_kernel(const BatchInst<T>* inst, const long long* probes,
-                                                                       const long long* probe_first, int np, int comp,
-                                                                       double* traces, long long step0,
-                                                                       long long nsteps) {
-    extern __shared__ __align__(16) unsigned char small_lds[];
-    const int nthr = blockDim.x;
-    // everything the step loop needs is read once: the loop's stores to the
-    // traces would otherwise make the compiler re-read it every step
-    const StepArgs<T> a = inst[blockIdx.x].a[0];  // parity 0: the buffers current at the start of the run
-    // the envelope through a global-memory pointer: a generic (flat) load
-    // could alias LDS, which would order every LDS access behind it
-    typedef const __attribute__((address_space(1))) double* genv_t;
-    const genv_t env = (genv_t)inst[blockIdx.x].env;
-    const long long n_env = inst[blockIdx.x].n_env;
-    const int N = (int)a.N;
-    T* su = reinterpret_cast<T*>(small_lds);  // [3][N]
-    T* sw = su + 3 * N;                        // [3][N]
-    T* senv = sw + 3 * N;                      // [kSmallChunk]: the chunk's envelope values
-    const long long pf = np > 0 ? probe_first[blockIdx.x] : 0;
-    const int npi = np > 0 ? (int)(probe_first[blockIdx.x + 1] - pf) : 0;
-    T* strace = senv + kSmallChunk;                                     // [kSmallChunk][npi]: probe values
-    int* sprobe = reinterpret_cast<int*>(strace + kSmallChunk * npi);  // this instance's probe cells
-    for (int q = threadIdx.x; q < 3 * N; q += nthr) {
-        su[q] = a.u[q];
-        sw[q] = a.w[q];
-    }
-    for (int p = threadIdx.x; p < npi; p += nthr) sprobe[p] = comp * N + (int)probes[2 * (pf + p) + 1];
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int nxi = nx - 2, nyi = ny - 2, nint = nxi * nyi * (nz - 2);
-    const int sy = nx, sz = nx * ny;
-    // owned cells: their index, sponge factors, f_S and own u, w (registers)
-    int cell[CPT];
-    T a1[CPT], a2[CPT], fs[CPT][3], ur[CPT][3], wr[CPT][3];
-#pragma unroll
-    for (int m = 0; m < CPT; ++m) {
-        const int t = threadIdx.x + m * nthr;
-        cell[m] = -1;
-        a1[m] = a2[m] = T(0);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) fs[m][c] = ur[m][c] = wr[m][c] = T(0);
-        if (t < nint) {
-            const int i = 1 + t % nxi, j = 1 + (t / nxi) % nyi, k = 1 + t / (nxi * nyi);
-            const int q = i + nx * (j + ny * k);
-            cell[m] = q;
-            const T r = a.L > 0 ? max(max(ramp<T>(i, nx, a.L, a.invL), ramp<T>(j, ny, a.L, a.invL)),
-                                      ramp<T>(k, nz, a.L, a.invL))
-                                : T(0);
-            const T s = a.half_dt_smax * r;
-            const T inv1ps = rcp_fast<T>(T(1) + s);
-            a1[m] = (T(1) - s) * inv1ps;
-            a2[m] = a.crho0 * inv1ps;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                fs[m][c] = a.FS[c * a.N + q];
-                ur[m][c] = a.u[c * a.N + q];
-                wr[m][c] = a.w[c * a.N + q];
-            }
-        }
-    }
-    const T gx = a.G0 * a.ihx2, gy = a.G0 * a.ihy2, gz = a.G0 * a.ihz2;
-    const T ihx2 = a.ihx2, ihy2 = a.ihy2, ihz2 = a.ihz2, eta_dt = a.eta_dt0;
-    for (long long st0 = 0; st0 < nsteps; st0 += kSmallChunk) {
-        const int cn = (int)min((long long)kSmallChunk, nsteps - st0);
-        // the chunk's envelope values: global memory is touched only here and
-        // in the flush of the chunk's probe values below, so the step loop
-        // itself waits on LDS alone
-        for (int q = threadIdx.x; q < cn; q += nthr) {
-            const long long n = step0 + st0 + q;
-            senv[q] = n < n_env ? T(env[n]) : T(0);
-        }
-        lds_barrier();
-        for (int sc = 0; sc < cn; ++sc) {
-            const T gn = senv[sc];
-#pragma unroll
-            for (int m = 0; m < CPT; ++m) {
-                if (cell[m] < 0) continue;
-                const int c0 = cell[m];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const T* u = su + c * N;
-                    const T uc = ur[m][c];
-                    const T uyp = LINE ? T(0) : u[c0 + sy], uym = LINE ? T(0) : u[c0 - sy];
-                    const T uzp = LINE ? T(0) : u[c0 + sz], uzm = LINE ? T(0) : u[c0 - sz];
-                    T acc = gx * (u[c0 + 1] - uc) - gx * (uc - u[c0 - 1]) + gy * (uyp - uc) - gy * (uc - uym)
-                          + gz * (uzp - uc) - gz * (uc - uzm);
-                    const T wc = wr[m][c];
-                    if constexpr (VISC) {
-                        const T* w = sw + c * N;
-                        const T wyp = LINE ? T(0) : w[c0 + sy], wym = LINE ? T(0) : w[c0 - sy];
-                        const T wzp = LINE ? T(0) : w[c0 + sz], wzm = LINE ? T(0) : w[c0 - sz];
-                        const T lw = (w[c0 + 1] + w[c0 - 1] - T(2) * wc) * ihx2 + (wyp + wym - T(2) * wc) * ihy2
-                                   + (wzp + wzm - T(2) * wc) * ihz2;
-                        acc += eta_dt * lw;
-                    }
-                    if (gn != T(0)) acc += gn * fs[m][c];
-                    const T wnew = a1[m] * wc + a2[m] * acc;
-                    wr[m][c] = wnew;
-                    ur[m][c] = uc + wnew;
-                }
-            }
-            lds_barrier();  // every read of the old state is done
-#pragma unroll
-            for (int m = 0; m < CPT; ++m)
-                if (cell[m] >= 0)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        su[c * N + cell[m]] = ur[m][c];
-                        if constexpr (VISC) sw[c * N + cell[m]] = wr[m][c];
-                    }
-            lds_barrier();  // the new state is complete
-            for (int p = threadIdx.x; p < npi; p += nthr) strace[sc * npi + p] = su[sprobe[p]];
-        }
-        lds_barrier();  // the chunk's probe values are complete
-        for (int q = threadIdx.x; q < cn * npi; q += nthr)
-            traces[(st0 + q / npi) * (long long)np + pf + q % npi] = (double)strace[q];
-        // the next chunk writes senv and strace only after the barrier that
-        // follows its envelope load, i.e. after these reads
-    }
-    // the run leaves the instance's state in the buffers current after nsteps
-    // (w in LDS is stale without viscosity: the registers hold it)
-    T* du = (nsteps & 1) ? a.un : const_cast<T*>(a.u);
-    T* dw = (nsteps & 1) ? a.wn : const_cast<T*>(a.w);
-#pragma unroll
-    for (int m = 0; m < CPT; ++m)
-        if (cell[m] >= 0)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sw[c * N + cell[m]] = wr[m][c];
-    lds_barrier();
-    for (int q = threadIdx.x; q < 3 * N; q += nthr) {
-        du[q] = su[q];
-        dw[q] = sw[q];
-    }
-}
-
-// LDS of the persistent kernel: the state (6 N values), a chunk's envelope
-// and probe values, and the probe cells, for the instance with the most
-// probes.
-template <typename T>
-size_t small_lds_bytes(const kvs_batch* b, const kvs_ctx* c) {
-    int64_t most = 0;
-    for (size_t i = 0; i + 1 < b->probe_first.size(); ++i)
-        most = std::max<int64_t>(most, b->probe_first[i + 1] - b->probe_first[i]);
-    return (6 * (size_t)c->N + kSmallChunk * (1 + (size_t)most)) * sizeof(T) + sizeof(int) * (size_t)most;
-}
-
-// Threads per workgroup (a multiple of 64, at most 1024, enough for one
-// interior cell each where possible) and cells per thread.
-template <typename T>
-bool small_fits(const kvs_batch* b, int* cpt, int* threads) {
-    long long most = 1;
-    for (const kvs_ctx* c : b->inst) {
-        const kvs_grid& g = c->grid;
-        if (small_lds_bytes<T>(b, c) > kSmallMaxLds) return false;
-        most = std::max<long long>(most, (g.nx - 2) * (g.ny - 2) * (g.nz - 2));
-    }
-    const int thr = (int)std::min<long long>(kSmallMaxThreads, 64 * ((most + 63) / 64));
-    const long long need = (most + thr - 1) / thr;
-    if (need > 8) return false;
-    *threads = thr;
-    *cpt = need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
-    return true;
-}
-
-template <typename T, bool VISC, int CPT, bool LINE>
-hipError_t launch_small_shape(kvs_batch* b, int64_t nsteps, int threads) {
-    size_t lds = 0;
-    for (const kvs_ctx* c : b->inst) lds = std::max(lds, small_lds_bytes<T>(b, c));
-    static bool attr_set = false;  // one attribute call per instantiation
-    if (!attr_set) {
-        const hipError_t e = hipFuncSetAttribute((const void*)batch_small_kernel<T, VISC, CPT, LINE>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallMaxLds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    const int np = (int)b->probe_inst.size();
-    const long long* pr = static_cast<const long long*>(b->dev_probes);
-    double* tr = np > 0 ? b->traces + b->trace_steps * np : nullptr;
-    hipLaunchKernelGGL((batch_small_kernel<T, VISC, CPT, LINE>), dim3((unsigned)b->inst.size()), dim3(threads), lds,
-                       b->stream, static_cast<const BatchInst<T>*>(b->dev_params), pr, np > 0 ? pr + 2 * np : nullptr,
-                       np, b->comp, tr, (long long)b->step, (long long)nsteps);
-    return hipGetLastError();
-}
-
-template <typename T, bool VISC>
-hipError_t launch_small(kvs_batch* b, int64_t nsteps, int cpt, int threads) {
-    bool line = true;
-    for (const kvs_ctx* c : b->inst) line = line && c->grid.ny == 3 && c->grid.nz == 3;
-    if (line) {
-        switch (cpt) {
-            case 1: return launch_small_shape<T, VISC, 1, true>(b, nsteps, threads);
-            case 2: return launch_small_shape<T, VISC, 2, true>(b, nsteps, threads);
-            case 4: return launch_small_shape<T, VISC, 4, true>(b, nsteps, threads);
-            default: return launch_small_shape<T, VISC, 8, true>(b, nsteps, threads);
-        }
-    }
-    switch (cpt) {
-        case 1: return launch_small_shape<T, VISC, 1, false>(b, nsteps, threads);
-        case 2: return launch_small_shape<T, VISC, 2, false>(b, nsteps, threads);
-        case 4: return launch_small_shape<T, VISC, 4, false>(b, nsteps, threads);
-        default: return launch_small_shape<T, VISC, 8, false>(b, nsteps, threads);
-    }
-}
-
-template <typename T>
-hipError_t run_small_t(kvs_batch* b, int64_t nsteps, int cpt, int threads) {
-    return b->viscous ? launch_small<T, true>(b, nsteps, cpt, threads) : launch_small<T, false>(b, nsteps, cpt, threads);
-}
-
-}  // namespace
-
-bool kvs_batch_small_path(const kvs_batch* b) {
-    int cpt = 0, thr = 0;
-    return b->small_ok && (b->prec == KVS_FP32 ? small_fits<float>(b, &cpt, &thr) : small_fits<double>(b, &cpt, &thr));
-}
-
-// One uncaptured step launch that only rewrites the next buffers (parity 0,
-// no force): used to time tile shapes without advancing the state.
-hipError_t kvs_batch_trial_launch(kvs_batch* b) {
-    if (b->prec == KVS_FP32) {
-        b->viscous ? launch_batch_step<float, true, false>(b, b->step, 0)
-                   : launch_batch_step<float, false, false>(b, b->step, 0);
-    } else {
-        b->viscous ? launch_batch_step<double, true, false>(b, b->step, 0)
-                   : launch_batch_step<double, false, false>(b, b->step, 0);
-    }
-    return hipGetLastError();
-}
-
-hipError_t kvs_batch_prepare(kvs_batch* b) {
-    return b->prec == KVS_FP32 ? prepare_t<float>(b) : prepare_t<double>(b);
-}
-
-hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
-    int cpt = 0, thr = 0;
-    if (b->small_ok && (b->prec == KVS_FP32 ? small_fits<float>(b, &cpt, &thr) : small_fits<double>(b, &cpt, &thr)))
-        return b->prec == KVS_FP32 ? run_small_t<float>(b, nsteps, cpt, thr) : run_small_t<double>(b, nsteps, cpt, thr);
-    // Replay the cached graph when it was captured for the same start step,
-    // step count, trace slot and per-step force switch (the parameter table
-    // and envelopes it reads were refreshed in place by kvs_batch_prepare);
-    // otherwise capture a new one.
-    std::vector<uint8_t> force_mask = batch_force_mask(b, nsteps);
-    const bool hit = b->graph_valid && b->graph && b->graph_start == b->step && b->graph_steps == nsteps &&
-                     b->graph_trace0 == b->trace_steps && b->graph_force == force_mask;
-    hipError_t e = hipSuccess;
-    if (!hit) {
-        if (b->graph) (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-        b->graph_valid = false;
-        hipGraph_t graph = nullptr;
-        e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            const hipError_t le = b->prec == KVS_FP32 ? capture_t<float>(b, nsteps, force_mask)
-                                                      : capture_t<double>(b, nsteps, force_mask);
-            e = hipStreamEndCapture(b->stream, &graph);
-            if (e == hipSuccess) e = le;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return e;
-        b->graph_valid = true;
-        b->graph_start = b->step;
-        b->graph_steps = nsteps;
-        b->graph_trace0 = b->trace_steps;
-        b->graph_force.swap(force_mask);
-    }
-    return hipGraphLaunch(b->graph, b->stream);
 }
