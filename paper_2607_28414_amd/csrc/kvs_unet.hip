@@ -279,6 +279,174 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     }
 }
 
+// Convolution on sub-lattice bricks (any dilation; 32 or 64 input channels,
+// the 1/4-resolution bottleneck): a convolution with dilation d is d^3
+// independent undilated convolutions on the sub-lattices x = a + d i,
+// y = b + d j, z = c + d k.  A block owns an 8 x 8 x 4 brick of one
+// sub-lattice (256 output voxels, all CO channels) and stages the brick's
+// input with its one-voxel halo (10 x 10 x 6 voxels, zeros outside the grid)
+// in LDS, 32 input channels per pass; wavefront w computes z layer w of the
+// brick, 4 groups of 16 voxels (two 8-voxel rows each) x CO channels, with
+// both MFMA operands read from LDS: every staged activation serves the 27
+// taps of up to 27 outputs from LDS instead of 27 gathers through the L1.
+// The weights of three taps at a time are staged in LDS, the next three
+// loaded into registers while the current ones are used.  Same sum as
+// conv3_mfma in another order (taps of the first 32 channels, then of the
+// next 32), FP32 accumulation, one rounding of the output.
+constexpr int SB_X = 8, SB_Y = 8, SB_Z = 4;                        // output brick (sub-lattice voxels)
+constexpr int SH_X = SB_X + 2, SH_Y = SB_Y + 2, SH_Z = SB_Z + 2;    // staged brick with halo
+constexpr int SH_V = SH_X * SH_Y * SH_Z;                            // 600 staged voxels
+constexpr int SVS = 32;            // LDS voxel stride (bf16; padding to 40 or 48 measured no faster)
+constexpr int STAPS = 3;           // taps per weight slab
+constexpr int SWROW = 32 * STAPS + 8;  // bf16 per output-channel row of a slab (padded)
+
+struct SubBricks {
+    int bx, by, bz;  // bricks per sub-lattice axis
+};
+
+template <int CI, int CO, typename OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3_sub(
+    const bf16* __restrict__ A, Dims d, int dil, SubBricks sb, const bf16* __restrict__ W, OUT* __restrict__ out,
+    const int* stop) {
+    static_assert(CI % 32 == 0 && CO % 16 == 0 && CO <= 64, "channel counts");
+    constexpr int NH = CI / 32;      // passes of 32 input channels
+    constexpr int MT = CO / 16;      // output-channel tiles
+    constexpr int KP = 27 * CI;      // weight row length (a multiple of 32)
+    constexpr int NSL = 27 / STAPS;  // weight slabs per pass
+    constexpr int WITEMS = CO * STAPS * 4;  // 16-byte pieces per slab
+    constexpr int WIPT = (WITEMS + 255) / 256;
+    constexpr int XITEMS = SH_V * 4;        // 16-byte pieces of a staged pass
+    constexpr int XIPT = (XITEMS + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 xs[SH_V * SVS];
+    __shared__ __attribute__((aligned(16))) bf16 ws[2][CO * SWROW];
+    if (stop && *stop) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int vl = lane & 15, kg = lane >> 4;
+    int q = kvs_tiling::tile_of((int)blockIdx.x, (int)gridDim.x);
+    const int bi = q % sb.bx;
+    q /= sb.bx;
+    const int bj = q % sb.by;
+    q /= sb.by;
+    const int bk = q % sb.bz;
+    q /= sb.bz;
+    const int sa = q % dil, sbb = (q / dil) % dil, sc = q / (dil * dil);  // sub-lattice
+    const int i0 = bi * SB_X, j0 = bj * SB_Y, k0 = bk * SB_Z;
+
+    // staged pieces of this thread: source offset (elements, channel 0) or -1
+    int xsrc[XIPT];
+#pragma unroll
+    for (int h = 0; h < XIPT; ++h) {
+        const int p = t + 256 * h;
+        xsrc[h] = -1;
+        if (p < XITEMS) {
+            const int v = p >> 2, hx = v % SH_X, hy = (v / SH_X) % SH_Y, hz = v / (SH_X * SH_Y);
+            const int gx = sa + dil * (i0 + hx - 1), gy = sbb + dil * (j0 + hy - 1), gz = sc + dil * (k0 + hz - 1);
+            if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+                xsrc[h] = (gx + d.nx * (gy + d.ny * gz)) * CI + 8 * (p & 3);
+        }
+    }
+    // the pieces of one pass, loaded into registers (the next pass's while
+    // the current one runs), then written to LDS
+    bf16x8 xn[XIPT];
+    auto xload = [&](int pass) {
+#pragma unroll
+        for (int h = 0; h < XIPT; ++h) {
+            bf16x8 v = {};
+            if (xsrc[h] >= 0) v = *reinterpret_cast<const bf16x8*>(A + xsrc[h] + 32 * pass);
+            xn[h] = v;
+        }
+    };
+    auto xstore = [&]() {
+#pragma unroll
+        for (int h = 0; h < XIPT; ++h) {
+            const int p = t + 256 * h;
+            if (p >= XITEMS) break;
+            *reinterpret_cast<bf16x8*>(&xs[(p >> 2) * SVS + 8 * (p & 3)]) = xn[h];
+        }
+    };
+    // weight slab (pass, slab): rows co, taps 3 slab .. 3 slab + 2, channels 32 pass .. + 31
+    bf16x8 wreg[WIPT];
+    auto wload = [&](int pass, int sl) {
+#pragma unroll
+        for (int h = 0; h < WIPT; ++h) {
+            const int it = min(t + 256 * h, WITEMS - 1);
+            const int co = it / (4 * STAPS), r = it % (4 * STAPS), tt = r >> 2, pc = r & 3;
+            wreg[h] = *reinterpret_cast<const bf16x8*>(W + (size_t)co * KP + (STAPS * sl + tt) * CI + 32 * pass + 8 * pc);
+        }
+    };
+    auto wstore = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < WIPT; ++h) {
+            const int it = t + 256 * h;
+            if (it >= WITEMS) break;
+            const int co = it / (4 * STAPS), r = it % (4 * STAPS);
+            *reinterpret_cast<bf16x8*>(&ws[buf][co * SWROW + 8 * r]) = wreg[h];
+        }
+    };
+
+    f32x4 acc[4][MT];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // staged voxel of group g at tap offset (0, 0, 0): x = vl % 8, y = 2 g + vl / 8, z = wv
+    int xv[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) xv[g] = (vl & 7) + SH_X * (2 * g + (vl >> 3) + SH_Y * wv);
+
+#pragma unroll 1
+    for (int pass = 0; pass < NH; ++pass) {
+        // (the barrier that ends the previous pass's last slab: every
+        // wavefront is done with xs and both weight buffers)
+        if (pass == 0) xload(0);
+        xstore();
+        if (pass + 1 < NH) xload(pass + 1);
+        wload(pass, 0);
+        wstore(0);
+        kvs_tiling::lds_barrier();
+#pragma unroll 1
+        for (int sl = 0; sl < NSL; ++sl) {
+            if (sl + 1 < NSL) wload(pass, sl + 1);
+            const bf16* wb = ws[sl & 1];
+#pragma unroll
+            for (int tt = 0; tt < STAPS; ++tt) {
+                const int tap = STAPS * sl + tt;
+                const int off = tap % 3 + SH_X * ((tap / 3) % 3 + SH_Y * (tap / 9));
+                bf16x8 xf[4], wf[MT];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) xf[g] = *reinterpret_cast<const bf16x8*>(&xs[(xv[g] + off) * SVS + 8 * kg]);
+#pragma unroll
+                for (int m = 0; m < MT; ++m)
+                    wf[m] = *reinterpret_cast<const bf16x8*>(&wb[(16 * m + vl) * SWROW + 32 * tt + 8 * kg]);
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], xf[g], acc[g][m]);
+            }
+            if (sl + 1 < NSL) wstore((sl + 1) & 1);
+            kvs_tiling::lds_barrier();
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int x = i0 + (vl & 7), y = j0 + 2 * g + (vl >> 3), z = k0 + wv;
+        const int gx = sa + dil * x, gy = sbb + dil * y, gz = sc + dil * z;
+        if (gx >= d.nx || gy >= d.ny || gz >= d.nz) continue;
+        const size_t v = (size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz);
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            if constexpr (sizeof(OUT) == 2) {
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = (bf16)acc[g][m][i];
+                *reinterpret_cast<bf16x4*>(out + v * CO + 16 * m + 4 * kg) = o;
+            } else {
+                *reinterpret_cast<f32x4*>(out + v * CO + 16 * m + 4 * kg) = acc[g][m];
+            }
+        }
+    }
+}
+
 // Convolution with dilation 1 as an LDS-staged z-march (same result as
 // conv3_mfma).  A block owns a 32 x TY column of output voxels and marches up
 // a z segment; the haloed input planes z - 1, z, z + 1 (34 x (TY + 2) voxels,
@@ -960,7 +1128,9 @@ hipError_t launch_zm(const bf16* A, Dims d, const bf16* W, OUT* out, const float
 
 // dispatch of the MFMA conv over the channel pairs this network uses:
 // dilation 1 with up to 32 channels -> LDS z-march; dilated or 64-channel
-// layers (the 1/4-resolution bottleneck) -> gathering kernel
+// layers (the 1/4-resolution bottleneck, 32 or 64 input channels) ->
+// sub-lattice bricks; the gathering kernel for the rest (fewer than 32 input
+// channels with dilation or 64 output channels)
 template <typename OUT>
 hipError_t launch_conv(int ci, int co, const bf16* A, Dims d, int dil, const bf16* W, OUT* out, hipStream_t s,
                        const int* stop = nullptr) {
@@ -968,6 +1138,17 @@ hipError_t launch_conv(int ci, int co, const bf16* A, Dims d, int dil, const bf1
     if (ci == CI_ && co == CO_) {                                                                              \
         if constexpr (CI_ <= 32 && CO_ <= 32) {                                                                \
             if (dil == 1) return launch_zm<CI_, CO_, false, OUT>(A, d, W, out, nullptr, nullptr, s, stop);     \
+        }                                                                                                      \
+        if constexpr (CI_ % 32 == 0) {                                                                         \
+            if (d.n() * CI_ < (1LL << 31)) {                                                                   \
+                const int ex = (d.nx + dil - 1) / dil, ey = (d.ny + dil - 1) / dil, ez = (d.nz + dil - 1) / dil; \
+                const SubBricks sb{(ex + SB_X - 1) / SB_X, (ey + SB_Y - 1) / SB_Y, (ez + SB_Z - 1) / SB_Z};      \
+                const long long nsb = (long long)dil * dil * dil * sb.bx * sb.by * sb.bz;                     \
+                if (nsb >= (1LL << 31)) return hipErrorInvalidValue;                                           \
+                hipLaunchKernelGGL((conv3_sub<CI_, CO_, OUT>), dim3((unsigned)nsb), dim3(256), 0, s, A, d, dil, sb, \
+                                   W, out, stop);                                                              \
+                return hipGetLastError();                                                                      \
+            }                                                                                                  \
         }                                                                                                      \
         constexpr int NV = conv_nv(CI_, CO_);                                                                  \
         /* bricks for dilation 1 (measured faster there; with dilation the       \
