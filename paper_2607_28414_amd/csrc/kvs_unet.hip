@@ -282,20 +282,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
 // Convolution on sub-lattice bricks (any dilation; 32 or 64 input channels,
 // the 1/4-resolution bottleneck): a convolution with dilation d is d^3
 // independent undilated convolutions on the sub-lattices x = a + d i,
-// y = b + d j, z = c + d k.  A block owns an 8 x 8 x 4 brick of one
-// sub-lattice (256 output voxels, all CO channels) and stages the brick's
-// input with its one-voxel halo (10 x 10 x 6 voxels, zeros outside the grid)
-// in LDS, 32 input channels per pass; wavefront w computes z layer w of the
-// brick, 4 groups of 16 voxels (two 8-voxel rows each) x CO channels, with
+// y = b + d j, z = c + d k.  A block owns an 8 x 8 x 4 LZ brick of one
+// sub-lattice (all CO channels) and stages the brick's input with its
+// one-voxel halo (10 x 10 x (4 LZ + 2) voxels, zeros outside the grid) in
+// LDS, 32 input channels per pass; wavefront w computes z layers LZ w ..
+// LZ w + LZ - 1 of the brick, 4 LZ groups of 16 voxels (two 8-voxel rows
+// each) x CO channels, with
 // both MFMA operands read from LDS: every staged activation serves the 27
 // taps of up to 27 outputs from LDS instead of 27 gathers through the L1.
 // The weights of three taps at a time are staged in LDS, the next three
 // loaded into registers while the current ones are used.  Same sum as
 // conv3_mfma in another order (taps of the first 32 channels, then of the
 // next 32), FP32 accumulation, one rounding of the output.
-constexpr int SB_X = 8, SB_Y = 8, SB_Z = 4;                        // output brick (sub-lattice voxels)
-constexpr int SH_X = SB_X + 2, SH_Y = SB_Y + 2, SH_Z = SB_Z + 2;    // staged brick with halo
-constexpr int SH_V = SH_X * SH_Y * SH_Z;                            // 600 staged voxels
+constexpr int SB_X = 8, SB_Y = 8;         // output brick (sub-lattice voxels): 8 x 8 x 4 LZ
+constexpr int SH_X = SB_X + 2, SH_Y = SB_Y + 2;  // staged brick with halo: 10 x 10 x (4 LZ + 2)
+// z layers of the brick per wavefront: 2 for up to 32 output channels (the
+// weight slabs are small enough for a 10 x 10 x 10 staged brick at two blocks
+// per CU, and each weight fragment then serves 8 voxel groups), else 1
+constexpr int sub_lz(int co) { return co <= 32 ? 2 : 1; }
 constexpr int SVS = 32;            // LDS voxel stride (bf16; padding to 40 or 48 measured no faster)
 constexpr int STAPS = 3;           // taps per weight slab
 constexpr int SWROW = 32 * STAPS + 8;  // bf16 per output-channel row of a slab (padded)
@@ -309,6 +313,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     const bf16* __restrict__ A, Dims d, int dil, SubBricks sb, const bf16* __restrict__ W, OUT* __restrict__ out,
     const int* stop) {
     static_assert(CI % 32 == 0 && CO % 16 == 0 && CO <= 64, "channel counts");
+    constexpr int LZ = sub_lz(CO), NG = 4 * LZ;  // z layers per wavefront, voxel groups per wavefront
+    constexpr int SB_Z = 4 * LZ, SH_Z = SB_Z + 2, SH_V = SH_X * SH_Y * SH_Z;
     constexpr int NH = CI / 32;      // passes of 32 input channels
     constexpr int MT = CO / 16;      // output-channel tiles
     constexpr int KP = 27 * CI;      // weight row length (a multiple of 32)
@@ -389,15 +395,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         }
     };
 
-    f32x4 acc[4][MT];
+    f32x4 acc[NG][MT];
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
         for (int m = 0; m < MT; ++m) acc[g][m] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // staged voxel of group g at tap offset (0, 0, 0): x = vl % 8, y = 2 g + vl / 8, z = wv
-    int xv[4];
+    // staged voxel of group g at tap offset (0, 0, 0): x = vl % 8,
+    // y = 2 (g % 4) + vl / 8, z = LZ wv + g / 4
+    int xv[NG];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) xv[g] = (vl & 7) + SH_X * (2 * g + (vl >> 3) + SH_Y * wv);
+    for (int g = 0; g < NG; ++g) xv[g] = (vl & 7) + SH_X * (2 * (g & 3) + (vl >> 3) + SH_Y * (LZ * wv + (g >> 2)));
 
 #pragma unroll 1
     for (int pass = 0; pass < NH; ++pass) {
@@ -419,14 +426,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
             for (int tt = 0; tt < STAPS; ++tt) {
                 const int tap = STAPS * sl + tt;
                 const int off = tap % 3 + SH_X * ((tap / 3) % 3 + SH_Y * (tap / 9));
-                bf16x8 xf[4], wf[MT];
+                bf16x8 xf[NG], wf[MT];
 #pragma unroll
-                for (int g = 0; g < 4; ++g) xf[g] = *reinterpret_cast<const bf16x8*>(&xs[(xv[g] + off) * SVS + 8 * kg]);
+                for (int g = 0; g < NG; ++g) xf[g] = *reinterpret_cast<const bf16x8*>(&xs[(xv[g] + off) * SVS + 8 * kg]);
 #pragma unroll
                 for (int m = 0; m < MT; ++m)
                     wf[m] = *reinterpret_cast<const bf16x8*>(&wb[(16 * m + vl) * SWROW + 32 * tt + 8 * kg]);
 #pragma unroll
-                for (int g = 0; g < 4; ++g)
+                for (int g = 0; g < NG; ++g)
 #pragma unroll
                     for (int m = 0; m < MT; ++m) acc[g][m] = mfma32(wf[m], xf[g], acc[g][m]);
             }
@@ -435,8 +442,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         }
     }
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int x = i0 + (vl & 7), y = j0 + 2 * g + (vl >> 3), z = k0 + wv;
+    for (int g = 0; g < NG; ++g) {
+        const int x = i0 + (vl & 7), y = j0 + 2 * (g & 3) + (vl >> 3), z = k0 + LZ * wv + (g >> 2);
         const int gx = sa + dil * x, gy = sbb + dil * y, gz = sc + dil * z;
         if (gx >= d.nx || gy >= d.ny || gz >= d.nz) continue;
         const size_t v = (size_t)gx + (size_t)d.nx * (gy + (size_t)d.ny * gz);
@@ -1149,7 +1156,8 @@ hipError_t launch_conv(int ci, int co, const bf16* A, Dims d, int dil, const bf1
         if constexpr (CI_ % 32 == 0) {                                                                         \
             if (d.n() * CI_ < (1LL << 31)) {                                                                   \
                 const int ex = (d.nx + dil - 1) / dil, ey = (d.ny + dil - 1) / dil, ez = (d.nz + dil - 1) / dil; \
-                const SubBricks sb{(ex + SB_X - 1) / SB_X, (ey + SB_Y - 1) / SB_Y, (ez + SB_Z - 1) / SB_Z};      \
+                constexpr int SBZ = 4 * sub_lz(CO_);                                                           \
+                const SubBricks sb{(ex + SB_X - 1) / SB_X, (ey + SB_Y - 1) / SB_Y, (ez + SBZ - 1) / SBZ};        \
                 const long long nsb = (long long)dil * dil * dil * sb.bx * sb.by * sb.bz;                     \
                 if (nsb >= (1LL << 31)) return hipErrorInvalidValue;                                           \
                 hipLaunchKernelGGL((conv3_sub<CI_, CO_, OUT>), dim3((unsigned)nsb), dim3(256), 0, s, A, d, dil, sb, \
