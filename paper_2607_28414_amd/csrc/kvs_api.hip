@@ -695,7 +695,9 @@ kvs_status kvs_set_pml(kvs_ctx* c, int32_t cells, double R, double alpha_max) {
     if (cells == 0) return KVS_OK;
     const kvs_grid& g = c->grid;
     int64_t count = 0;
-    for (int a = 0; a < 3; ++a) count += 9 * kvs_pml_slab_cells(g, cells, a);
+    // per axis: two buffers of the 6 face memories (one read, the other
+    // written each step) and the 3 divergence memories
+    for (int a = 0; a < 3; ++a) count += 15 * kvs_pml_slab_cells(g, cells, a);
     API_HIP(c, c->mem.get(&c->pml_tab, tsize(c) * 4 * (size_t)(g.nx + g.ny + g.nz)));
     API_HIP(c, c->mem.get(&c->pml_mem, tsize(c) * (size_t)count));
     c->pml_mem_count = count;

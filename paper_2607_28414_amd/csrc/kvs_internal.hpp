@@ -274,7 +274,7 @@ hipError_t kvs_launch_strain(kvs_ctx* c, const void* p, int64_t nsamp, int dtype
 // square roots of the gradient map (stored as squares) into out (device, N)
 hipError_t kvs_launch_strain_roots(kvs_ctx* c, double* out);
 // absorbing layer (kvs_pml.hip): default frequency shift, slab cells of an
-// axis, coefficient tables from dt and the material, and the layer passes of
+// axis, coefficient tables from dt and the material, and the layer pass of
 // one step (after kvs_launch_step, before the buffers flip)
 double kvs_pml_default_alpha(const kvs_grid& g, double cmax, int L);
 int64_t kvs_pml_slab_cells(const kvs_grid& g, int L, int axis);

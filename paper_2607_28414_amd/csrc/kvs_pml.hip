@@ -20,14 +20,16 @@
 // drift by a uniform static displacement).
 //
 // The layer is L cells next to every Dirichlet face.  The main step kernel
-// updates every cell with the plain scheme; these kernels then correct the
-// layer cells: pass 1 advances the face memories (psi) of each axis over that
-// axis's two slabs, pass 2 adds to the layer cells' new state the difference
-// the stretched derivatives make (advancing phi).  Both read the old state
-// (u, w); pass 2 also reads and rewrites the new state of the layer cells, so
-// both run after the main kernel, in stream order.  Memory variables live only in the slabs: along axis a, indices
-// [0, T) and [n_a - 1 - T, n_a - 1) with T = L + 1, which hold the faces
-// i + 1/2 and the cells i that the layer uses.
+// updates every cell with the plain scheme; one layer pass per step then
+// corrects the layer cells: for each axis whose layer holds the cell it
+// advances the memories of the cell's two faces from the old state (read
+// from one buffer; the cell writes the face towards the wall into the other
+// buffer, so every face is written once, and the buffers swap every step),
+// advances the cell's divergence memory phi and adds to the new state the
+// difference the stretched derivatives make.  Memory variables live only in
+// the slabs: along axis a, indices [0, T) and [n_a - 1 - T, n_a - 1) with
+// T = L + 1, which hold the faces i + 1/2 and the cells i that the layer
+// uses.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -43,11 +45,13 @@ __device__ __forceinline__ T harm2(T a, T b) {
 
 template <typename T>
 struct PmlAxis {
-    const T* tab;  // [4][n]: b at cells, c at cells, b at faces (i + 1/2), c at faces
-    T* mem;        // [9][M]: psi_el (3 components), psi_w (3), phi (3)
-    long long M;   // slab cells of this axis
-    int n;         // extent
-    T ih;          // 1 / h
+    const T* tab;     // [4][n]: b at cells, c at cells, b at faces (i + 1/2), c at faces
+    const T* psin;    // [6][M]: face memories psi_el (3 components), psi_w (3), this step's
+    T* psout;         // [6][M]: the same, next step's
+    T* phi;           // [3][M]: divergence memories (updated in place)
+    long long M;      // slab cells of this axis
+    int n;            // extent
+    T ih;             // 1 / h
 };
 
 template <typename T>
@@ -77,61 +81,16 @@ __device__ __forceinline__ long long slab_index(int a, int s, int i, int j, int 
     return i + (long long)nx * (j + (long long)ny * s);
 }
 
-// Pass 1: face memories of axis A over its two slabs, interior rows only.
-template <typename T, int A>
-__global__ __launch_bounds__(256) void pml_face_kernel(const PmlArgs<T> a) {
-    const PmlAxis<T>& X = a.ax[A];
-    const int Ts = a.Ts;
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    // thread order follows memory: for x faces the slab position (x) fastest,
-    // then y, z; for y and z faces x fastest, then the slab position, then the
-    // remaining axis (rows of the state and of the slab memory stay contiguous)
-    const int e1 = A == 0 ? a.ny - 2 : a.nx - 2;  // first other axis (interior extent)
-    const long long total = (long long)(2 * Ts) * e1 * (A == 2 ? a.ny - 2 : a.nz - 2);
-    if (t >= total) return;
-    int s, o1, o2;
-    if (A == 0) {
-        s = (int)(t % (2 * Ts));
-        const long long r = t / (2 * Ts);
-        o1 = 1 + (int)(r % e1);
-        o2 = 1 + (int)(r / e1);
-    } else {
-        o1 = 1 + (int)(t % e1);
-        const long long r = t / e1;
-        s = (int)(r % (2 * Ts));
-        o2 = 1 + (int)(r / (2 * Ts));
-    }
-    const int ia = s < Ts ? s : (X.n - 1 - Ts) + (s - Ts);  // face ia + 1/2
-    const T cf = X.tab[3 * X.n + ia];
-    if (cf == T(0)) return;
-    const T bf = X.tab[2 * X.n + ia];
-    int i, j, k;
-    long long stride;
-    if (A == 0) { i = ia; j = o1; k = o2; stride = 1; }
-    else if (A == 1) { i = o1; j = ia; k = o2; stride = a.nx; }
-    else { i = o1; j = o2; k = ia; stride = (long long)a.nx * a.ny; }
-    const long long p = i + (long long)a.nx * (j + (long long)a.ny * k), q = p + stride;
-    const T Gf = a.G ? harm2<T>(a.G[p], a.G[q]) : a.G0;
-    const long long m = slab_index(A, s, i, j, k, a.nx, a.ny, Ts);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const long long o = c * a.N;
-        const T Fel = Gf * ((a.u[o + q] - a.u[o + p]) * X.ih);
-        const T Fw = (a.w[o + q] - a.w[o + p]) * X.ih;
-        T* pe = X.mem + c * X.M + m;
-        T* pw = X.mem + (3 + c) * X.M + m;
-        *pe = bf * *pe + cf * Fel;
-        *pw = bf * *pw + cf * Fw;
-    }
-}
-
-// Pass 2: the layer cells, enumerated box by box (each cell once).  With no
-// sponge the plain update is linear in acc (w' = w + (dt^2/rho) acc), so the
-// cell only adds the layer's part to what the step kernel wrote:
+// The layer pass: the layer cells, enumerated box by box (each cell once).
+// With no sponge the plain update is linear in acc (w' = w + (dt^2/rho) acc),
+// so the cell only adds the layer's part to what the step kernel wrote:
 // acc_layer - acc_plain = sum over the axes whose layer holds the cell of
-// (psi differences) / h + phi, where phi advances with that axis's full
-// stretched divergence.  Axes whose layer does not hold the cell are left to
-// the step kernel (there psi = phi = 0).
+// (psi differences) / h + phi, where psi on the cell's two faces and phi
+// advance with that axis's fluxes and full stretched divergence.  Axes whose
+// layer does not hold the cell are left to the step kernel (there psi = phi
+// = 0).  The face towards the wall is the cell's to write (in the low layer
+// its face i - 1/2, in the high layer i + 1/2); the face at the layer's
+// inner edge has c = 0 and keeps its zero.
 template <typename T>
 __global__ __launch_bounds__(256) void pml_cell_kernel(const PmlArgs<T> a) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -156,24 +115,29 @@ __global__ __launch_bounds__(256) void pml_cell_kernel(const PmlArgs<T> a) {
         const PmlAxis<T>& X = a.ax[A];
         const int ia = pos[A];
         if (!(ia <= a.L || ia >= X.n - 1 - a.L)) continue;
+        const bool low = ia <= a.L;
         const long long st = strides[A];
         const T Gm = a.G ? harm2<T>(Gc, a.G[cell - st]) : a.G0;
         const T Gp = a.G ? harm2<T>(Gc, a.G[cell + st]) : a.G0;
         const long long mp = slab_index(A, slab_of(ia, X.n, a.Ts), i, j, k, a.nx, a.ny, a.Ts);      // face ia + 1/2, cell ia
         const long long mm = slab_index(A, slab_of(ia - 1, X.n, a.Ts), i, j, k, a.nx, a.ny, a.Ts);  // face ia - 1/2
+        const long long mo = low ? mm : mp;                                                            // the face this cell writes
         const T bc = X.tab[ia], cc = X.tab[X.n + ia];
+        const T bfm = X.tab[2 * X.n + ia - 1], cfm = X.tab[3 * X.n + ia - 1];
+        const T bfp = X.tab[2 * X.n + ia], cfp = X.tab[3 * X.n + ia];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const long long o = c * a.N;
             const T uc = a.u[o + cell], wc = a.w[o + cell];
-            const T pe_p = X.mem[c * X.M + mp], pe_m = X.mem[c * X.M + mm];
-            const T pw_p = X.mem[(3 + c) * X.M + mp], pw_m = X.mem[(3 + c) * X.M + mm];
-            const T fp = Gp * ((a.u[o + cell + st] - uc) * X.ih) + pe_p;
-            const T fm = Gm * ((uc - a.u[o + cell - st]) * X.ih) + pe_m;
-            const T gp = (a.w[o + cell + st] - wc) * X.ih + pw_p;
-            const T gm = (wc - a.w[o + cell - st]) * X.ih + pw_m;
-            const T D = (fp - fm) * X.ih + eta_dt * ((gp - gm) * X.ih);
-            T* ph = X.mem + (6 + c) * X.M + mp;
+            const T Fp = Gp * ((a.u[o + cell + st] - uc) * X.ih), Fm = Gm * ((uc - a.u[o + cell - st]) * X.ih);
+            const T Wp = (a.w[o + cell + st] - wc) * X.ih, Wm = (wc - a.w[o + cell - st]) * X.ih;
+            const T pe_p = bfp * X.psin[c * X.M + mp] + cfp * Fp, pe_m = bfm * X.psin[c * X.M + mm] + cfm * Fm;
+            const T pw_p = bfp * X.psin[(3 + c) * X.M + mp] + cfp * Wp;
+            const T pw_m = bfm * X.psin[(3 + c) * X.M + mm] + cfm * Wm;
+            X.psout[c * X.M + mo] = low ? pe_m : pe_p;
+            X.psout[(3 + c) * X.M + mo] = low ? pw_m : pw_p;
+            const T D = ((Fp + pe_p) - (Fm + pe_m)) * X.ih + eta_dt * (((Wp + pw_p) - (Wm + pw_m)) * X.ih);
+            T* ph = X.phi + c * X.M + mp;
             const T phi = bc * *ph + cc * D;
             *ph = phi;
             dacc[c] += ((pe_p - pe_m) + eta_dt * (pw_p - pw_m)) * X.ih + phi;
@@ -250,16 +214,21 @@ hipError_t launch_t(kvs_ctx* c) {
     a.Ts = c->pml_cells + 1;
     const int ext[3] = {a.nx, a.ny, a.nz};
     const double hh[3] = {g.hx, g.hy, g.hz};
+    // memory per axis: face-memory buffers 0 and 1 (6 slabs each), then phi
+    // (3 slabs); this step reads the buffer of the state's parity
     const T* tab = static_cast<const T*>(c->pml_tab);
     T* mem = static_cast<T*>(c->pml_mem);
     for (int A = 0; A < 3; ++A) {
+        const long long M = kvs_pml_slab_cells(g, c->pml_cells, A);
         a.ax[A].tab = tab;
-        a.ax[A].mem = mem;
+        a.ax[A].psin = mem + (c->cur ? 6 * M : 0);
+        a.ax[A].psout = mem + (c->cur ? 0 : 6 * M);
+        a.ax[A].phi = mem + 12 * M;
         a.ax[A].n = ext[A];
         a.ax[A].ih = T(1.0 / hh[A]);
-        a.ax[A].M = kvs_pml_slab_cells(g, c->pml_cells, A);
+        a.ax[A].M = M;
         tab += 4 * ext[A];
-        mem += 9 * a.ax[A].M;
+        mem += 15 * M;
     }
     const int L = a.L, nx = a.nx, ny = a.ny, nz = a.nz;
     const int boxes[6][6] = {
@@ -277,12 +246,6 @@ hipError_t launch_t(kvs_ctx* c) {
                             (boxes[b][5] - boxes[b][4] + 1);
         a.start[b + 1] = a.start[b] + v;
     }
-    const long long f0 = (long long)(2 * a.Ts) * (ny - 2) * (nz - 2);
-    const long long f1 = (long long)(2 * a.Ts) * (nx - 2) * (nz - 2);
-    const long long f2 = (long long)(2 * a.Ts) * (nx - 2) * (ny - 2);
-    hipLaunchKernelGGL((pml_face_kernel<T, 0>), dim3((unsigned)((f0 + 255) / 256)), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL((pml_face_kernel<T, 1>), dim3((unsigned)((f1 + 255) / 256)), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL((pml_face_kernel<T, 2>), dim3((unsigned)((f2 + 255) / 256)), dim3(256), 0, c->stream, a);
     hipLaunchKernelGGL(pml_cell_kernel<T>, dim3((unsigned)((a.start[6] + 255) / 256)), dim3(256), 0, c->stream, a);
     return hipGetLastError();
 }
