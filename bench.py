@@ -271,7 +271,6 @@ def time_varying_window(args, net):
                          stream=stream.cuda_stream)
     try:
         kvs.kvs_set_material(ctx, G, rho, eta)
-        del G, eta
         dt = 0.4 * kvs.kvs_stable_dt(ctx)
         kvs.kvs_set_dt(ctx, dt)
         kvs.kvs_set_envelope(ctx, np.ones(3000))
@@ -306,6 +305,13 @@ def time_varying_window(args, net):
         kvs.kvs_destroy(ctx)
     per = k_ms / k_launches
     achieved = cells * 72 / (per * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        from workloads import force_from_params
+        log("bench: oracle window of the time-varying workload")
+        cpu = oracle_window(grid, G, rho, eta, dt, force_from_params(grid, focal_modulated_params(grid, epoch=0, dt=dt)),
+                            3, 10, 8, proj_iters=1593)
+    del G, eta
     return {
         "workload": f"384x384x512, h 0.2 mm, G = 10^(3 + Phi(xi)) Pa and eta = 1.5 Phi(xi') Pa s (3 mm random "
                     f"fields), rho 1000, 8-cell sponge, dt {dt:.3e} s (0.4 x stable limit), epochs 0-"
@@ -316,6 +322,7 @@ def time_varying_window(args, net):
                      "algorithmic_bytes_per_cell_update": 72, "launches": k_launches, "variant": variant},
         "projection_iters": iters, "projection_ms": pms, "fallbacks": fbs, "projection_relres_true": rts,
         "epoch_ms": ems, "epoch_ms_mean_after_first": float(np.mean(ems[1:])) if len(ems) > 1 else None,
+        "cpu_baseline": cpu,
     }
 
 
@@ -462,14 +469,12 @@ def shell_workload(args, net):
                          stream=stream.cuda_stream)
     try:
         kvs.kvs_set_material(ctx, w.G, w.rho, w.eta)
-        w.G = w.rho = w.eta = None
         dt = w.dt_factor * kvs.kvs_stable_dt(ctx)
         kvs.kvs_set_dt(ctx, dt)
         env = w.envelope_for(dt)
         kvs.kvs_set_envelope(ctx, env)
         variant, _ = kvs.kvs_autotune_step(ctx, 10)
         kvs.kvs_set_force(ctx, w.F)
-        w.F = None
         kvs.kvs_set_preconditioner(ctx, net)
         rj = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=kvs.KVS_PC_JACOBI, confirm_true=True)
         rf = kvs.kvs_project(ctx, tol=1e-8, max_iter=20000, precond=kvs.KVS_PC_UNET, confirm_true=True)
@@ -502,6 +507,11 @@ def shell_workload(args, net):
     n_push = min(len(env), args.shell_steps)
     bytes_total = cells * (60 * args.shell_steps + 12 * n_push)
     achieved = bytes_total / (k_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: oracle window of the shell workload")
+        cpu = oracle_window(w.grid, w.G, w.rho, w.eta, dt, w.F, 2, 8, w.sponge_cells, proj_iters=rj["iters"])
+    w.G = w.rho = w.eta = w.F = None
     return {
         "workload": f"512x512x640, h 0.2 mm, curved shell 5-8 mm (100 kPa, 1900, 2 Pa s) over soft tissue "
                     f"(1.5 kPa, 1040, 0.8 Pa s), 8-cell sponge, push 20 mm below the shell (1 mm / 5 mm, 5e4 "
@@ -518,6 +528,7 @@ def shell_workload(args, net):
         "stepping_ms_per_step": all_ms / args.shell_steps,
         "sensor_overhead_ms_per_step": all_ms / args.shell_steps - per,
         "peak_u_m": peak,
+        "cpu_baseline": cpu,
     }
 
 
@@ -600,6 +611,37 @@ def cpu_baseline(w, dt, smax, FS_host, nsteps, proj_iters, cg_sample=40):
                       f"subtraction ({el_cg:.1f} s), FP64 C oracle, OpenMP; value = the whole job ({proj_iters} "
                       f"iterations + {w.nsteps} steps) at the sampled rates; value_one_thread_fdtd: 4 steps on one "
                       f"thread"}
+
+
+def oracle_window(grid, G, rho, eta, dt, F, nsteps, cg_iters, sponge_cells, proj_iters=None):
+    """The FP64 oracle, as it stands, on a stated window of a full-size
+    workload (the whole run would take hours on the host): `nsteps` FDTD steps
+    from rest with the force on (the force itself in place of its projection:
+    a step's cost does not depend on the values) and one Jacobi-PCG
+    projection of `cg_iters` fixed iterations with its divergence and
+    gradient subtraction, timed on the host cores.  Reports Gcell-updates/s of
+    the steps and seconds per CG iteration; with proj_iters, the seconds one
+    projection at that iteration count would take at the sampled rate."""
+    import oracle
+    oracle.lib()
+    cells = (grid[0] - 2) * (grid[1] - 2) * (grid[2] - 2)
+    smax = oracle.default_sigma_max(grid, G, rho, sponge_cells)
+    t0 = time.perf_counter()
+    oracle.run(grid, G, rho, eta, dt, nsteps, FS=F, env=[1.0] * nsteps, sponge_cells=sponge_cells, sigma_max=smax)
+    el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.project(grid, F, fixed_iters=cg_iters, jacobi=True)
+    el_cg = time.perf_counter() - t1
+    out = {"value": cells * nsteps / el / 1e9, "unit": "Gcell-updates/s", "kind": "oracle",
+           "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+           "s_per_step": el / nsteps, "s_per_cg_iteration": el_cg / cg_iters,
+           "sample": f"{nsteps} FDTD steps from rest with the force on ({el:.1f} s) and one Jacobi-PCG projection "
+                     f"of {cg_iters} fixed iterations with divergence and gradient subtraction ({el_cg:.1f} s), "
+                     f"FP64 C oracle, OpenMP"}
+    if proj_iters:
+        out["s_per_projection_at_gpu_iters"] = proj_iters * el_cg / cg_iters
+        out["gpu_projection_iters"] = proj_iters
+    return out
 
 
 def run_config1(args):
