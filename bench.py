@@ -9,28 +9,35 @@ lateral-line probe traces, and read the traces back.  The material, force
 pattern and probes are resident in HBM before timing.
 
 --workload kvline: the 1-D harmonic Kelvin-Voigt sweep (16 viscosities as
-one batch of line instances), replay time of the whole sweep; pml, arf and
-fpcg: the cost legs of the absorbing layer, the radiation-force generator and
-the learned preconditioner.
+one batch of line instances, one persistent launch), time of the whole
+sweep; pml, arf and fpcg: the cost legs of the absorbing layer, the
+radiation-force generator and the learned preconditioner.
 
 --workload batch: one benchmark step is the 64-instance homogeneous sweep
 (edges 96..192, G and eta from the sweep values): all instances to rest, one
 projection per distinct grid shared by its instances, 2000 steps of every
-instance as one replayed hipGraph (one launch per step over all instances),
-lateral-line traces read back.
+instance as one replayed hipGraph (one launch per step and tile width over
+all instances), lateral-line traces read back.
 
 value = interior cell-updates of the timed steps / timed wall time
         (whole job, projection included), in Gcell-updates/s.
 roofline: the FDTD step kernel, algorithmic bytes per interior cell-update
           (48 B of FP32 u, w read + written, 12 B of G, eta, dt^2/rho, and
-          12 B of f_S on push steps) over its HIP-event-timed launches.
-          copy_gbs / frac_of_copy: a plain device-to-device copy measured in the
-          same run (the practical streaming ceiling) and the kernel against it.
+          12 B of f_S on push steps) over its HIP-event-timed launches;
+          traffic: HBM bytes per launch from the rocprofv3 counter runs of
+          the same kernel source (null when the source differs).
+          stream_gbs / frac_of_stream: a stream with the step's own 9 reads
+          and 6 writes per cell and no stencil, measured in the same run
+          (the practical ceiling), and the kernel against it; copy_gbs /
+          frac_of_copy: the same for a plain device-to-device copy.
 cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload
-              (all host threads), its host's CPU model, and a shorter sample
-              on one thread.
-projection_learned (default run, outside the timed region): projection time
-to 1e-8 of the learned flexible PCG vs Jacobi-PCG on the time-varying
+              (all host threads; steps and projection iterations, scaled to
+              the whole job), its host's CPU model, and a shorter sample on
+              one thread.
+The same line carries the other configurations as legs (config1, batch,
+kvline, time_varying, shell, arf), each with its own oracle timing, and
+projection_learned (outside the timed region): projection time to a true
+1e-8 of the learned flexible PCG vs Jacobi-PCG on the time-varying
 workload's 384 x 384 x 512 grid, after training the network by the committed
 recipe (training time reported separately).
 """
