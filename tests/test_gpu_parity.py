@@ -616,7 +616,11 @@ def test_torch_allocator_context_and_batch(kvs):
     say(f"torch allocator: {alloc.allocs} allocations, {live} B live, device memory taken {taken} B, "
         f"torch reserve grew {grown} B")
     assert alloc.allocs > 10 and live > 3 * 61 * 37 * 45 * 4
-    assert taken == grown  # nothing outside torch's pool
+    # nothing outside torch's pool: a device allocation of the library's own
+    # would make taken exceed grown (taken can fall short of it when the
+    # runtime hands back memory freed before the window, e.g. the chunk that
+    # held small buffers of the hipMalloc'd reference run)
+    assert taken <= grown
     assert alloc.frees == alloc.allocs and alloc.live_bytes == 0
     assert np.array_equal(tr, ref_tr) and np.array_equal(pm, ref_map)
 
