@@ -21,15 +21,24 @@ all instances), lateral-line traces read back.
 
 value = interior cell-updates of the timed steps / timed wall time
         (whole job, projection included), in Gcell-updates/s.
-roofline: the FDTD step kernel, algorithmic bytes per interior cell-update
-          (48 B of FP32 u, w read + written, 12 B of G, eta, dt^2/rho, and
-          12 B of f_S on push steps) over its HIP-event-timed launches;
+roofline: the dominant FDTD kernel over its HIP-event-timed launches.  By
+          default that is the two-step kernel (two steps per launch, bound by
+          vector-ALU issue): bound "alu", algorithmic FP32 flop (147 per
+          cell-update, two updates per cell and launch) over its mean launch
+          duration against the 78.6 TFLOP/s FMA peak without packed FP32;
+          hbm_model: cell-updates per second x 60 B against 8 TB/s (the
+          metric's % of the HBM roofline); the one-step push launches beside
+          it.  With --step-blocking 1: the one-step kernel, algorithmic bytes
+          per interior cell-update (48 B of FP32 u, w read + written, 12 B of
+          G, eta, dt^2/rho, and 12 B of f_S on push steps), with stream_gbs /
+          frac_of_stream (a stream with the step's own 9 reads and 6 writes
+          per cell and no stencil, measured in the same run) and copy_gbs /
+          frac_of_copy (a plain device-to-device copy).
           traffic: HBM bytes per launch from the rocprofv3 counter runs of
           the same kernel source (null when the source differs).
-          stream_gbs / frac_of_stream: a stream with the step's own 9 reads
-          and 6 writes per cell and no stencil, measured in the same run
-          (the practical ceiling), and the kernel against it; copy_gbs /
-          frac_of_copy: the same for a plain device-to-device copy.
+one_step_kernel: the one-step kernel alone after the timed region (200
+          launches without force): us per launch, fraction of 8 TB/s,
+          traffic.
 cpu_baseline: the FP64 CPU oracle on a bounded sample of the same workload
               (all host threads; steps and projection iterations, scaled to
               the whole job), its host's CPU model, and a shorter sample on
@@ -73,6 +82,22 @@ STEP_COUNTERS_KIB = {  # variant -> (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatch
     7: (304696.8, 390146.7),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+# The same counters for the two-step kernel (step2_kernel, one launch = two
+# steps without force), taken on STEP2_SOURCES with SHA-256 STEP2_SOURCE_SHA.
+STEP2_SOURCE_SHA = "5790dfd03989459253496200a6ba84abc02709fa4ce3a8c1c0333225a0eebe53"
+STEP2_COUNTERS_KIB = (355157.9, 390148.0)  # (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
+# Algorithmic FP32 arithmetic of one heterogeneous viscous cell-update of the
+# summed-form leapfrog (Sec. 3.1), an FMA counted as two: six harmonic face
+# moduli 2 G G' / (G + G') / h^2 (5 each, 30); the sponge factors s,
+# (1 - s) / (1 + s), (dt^2 / rho) / (1 + s) and eta / dt (6); per component
+# the flux divergence of G grad u (6 differences, 6 products, 5 sums: 17), the
+# Laplacian of w (4 per axis and 2 sums: 14), acc += (eta / dt) lap w (2),
+# w' = a1 w + a2 acc (3) and u' = u + w' (1): 37 x 3 = 111.  Total 147.
+FLOP_PER_CELL_UPDATE = 147
+# FP32 vector peak of the MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2
+# (FMA) = 78.6 TFLOP/s without packed FP32 instructions (which this build does
+# not emit), 157.3 TFLOP/s with them (the published figure).
+FP32_PEAK_TFLOPS, FP32_PACKED_PEAK_TFLOPS = 78.6, 157.3
 METRIC = "FDTD Gcell-updates/s (% HBM roofline); projection time, learned-FPCG vs PCG @1e-8"
 
 
@@ -89,6 +114,8 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=100)
     ap.add_argument("--step-variant", type=int, default=-1,
                     help="pin the step-kernel tile shape (default: autotune); used by the counter runs")
+    ap.add_argument("--step-blocking", type=int, default=2, choices=[1, 2],
+                    help="FDTD steps per step-kernel launch in the main leg (2: the two-step kernel)")
     ap.add_argument("--train-rounds", type=int, default=4,
                     help="training rounds on the network's own flexible-PCG residuals")
     ap.add_argument("--train-grid", type=int, default=64, help="edge of the cubic unit training grids")
@@ -117,17 +144,27 @@ def log(*a):
 
 
 STEP_SOURCES = ("kvs_step_tile.hpp", "kvs_step.hip", "kvs_tiling.hpp")
+STEP2_SOURCES = ("kvs_step2.hip", "kvs_step_tile.hpp", "kvs_tiling.hpp")
 
 
-def step_source_sha():
-    """SHA-256 over the step kernel's sources (tile code, kernel and launch
-    shapes, tile order), in that order."""
+def step_source_sha(names=STEP_SOURCES):
+    """SHA-256 over a step kernel's sources (tile code, kernel and launch
+    shapes, tile order), in the order given."""
     import hashlib
     h = hashlib.sha256()
-    for name in STEP_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2607_28414_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def step2_traffic():
+    """Measured HBM bytes per two-step launch, or None when the counters are
+    not for this source."""
+    if STEP2_COUNTERS_KIB is None or step_source_sha(STEP2_SOURCES) != STEP2_SOURCE_SHA:
+        return None
+    fetch, write = STEP2_COUNTERS_KIB
+    return (fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024.0
 
 
 def step_traffic(variant):
@@ -990,6 +1027,9 @@ def main():
         else:
             variant, variant_ms = kvs.kvs_autotune_step(ctx, 20)
             log(f"bench: step-kernel variant {variant} ({', '.join(f'{m * 1e3:.1f}' for m in variant_ms)} us)")
+        kvs.kvs_set_step_blocking(ctx, args.step_blocking)
+        log(f"bench: {args.step_blocking} step(s) per launch (two-step kernel applies: "
+            f"{kvs.kvs_step_blocking_applies(ctx)})")
         torch.cuda.synchronize()
         nsteps = w.nsteps
         cells = w.interior_cells
@@ -1018,6 +1058,7 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         k_ms, k_launches = kvs.kvs_kernel_time(ctx)
+        (ms1, n1), (ms2, n2) = kvs.kvs_kernel_time_split(ctx)
         kvs.kvs_enable_kernel_timing(ctx, False)
         assert np.all(np.isfinite(tr)), "non-finite traces"
         # after the timed region: the same simulation with the force handed over
@@ -1034,17 +1075,89 @@ def main():
         pcie_ms = (time.perf_counter() - t1) * 1e3
         FS_host = kvs.kvs_get_projected_force(ctx, w.shape) if not args.no_cpu_baseline else None
         smax = kvs.kvs_sponge_sigma_max(ctx)
+        # reference: the one-step kernel alone on the same medium (200 launches
+        # without force, continuing from the state above)
+        kvs.kvs_set_envelope(ctx, [])
+        kvs.kvs_set_step_blocking(ctx, 1)
+        kvs.kvs_enable_kernel_timing(ctx, True)
+        kvs.kvs_step(ctx, 200)
+        one_ms, one_n = kvs.kvs_kernel_time(ctx)
+        kvs.kvs_enable_kernel_timing(ctx, False)
     finally:
         kvs.kvs_destroy(ctx)
 
     total_updates = args.steps * nsteps * cells
     value = total_updates / el / 1e9
-    # algorithmic bytes of the step kernel over the timed launches
+    # algorithmic bytes of the step launches over the timed launches (the
+    # one-step model: 60 B per cell-update, 72 B on push steps)
     bytes_total = args.steps * (nsteps * cells * 60 + n_push * cells * 12)
     achieved = bytes_total / (k_ms * 1e-3) / 1e9
-    traffic = step_traffic(variant)
     copy_gbs = measured_copy_gbs()  # after the timed region
     stream_gbs = kvs.kvs_measure_stream(cells, 10) if not args.no_extra_legs else None
+    one_us = one_ms / one_n * 1e3
+    one_gbs = cells * 60 / (one_us * 1e-6) / 1e9
+    one_step = {"kernel": "step_kernel (one step per launch, no force)", "us_per_launch": one_us,
+                "launches": one_n, "variant": variant, "achieved_GBs": one_gbs,
+                "frac_of_hbm_peak": one_gbs / HBM_PEAK_GBS, "traffic": step_traffic(variant),
+                "frac_of_stream": one_gbs / stream_gbs if stream_gbs else None,
+                "note": "reference run of the one-step kernel after the timed region, 60 B per cell-update"}
+    if n2 > 0:
+        # dominant kernel: two steps per launch, bound by vector-ALU issue
+        t2 = ms2 / n2  # ms per two-step launch
+        tflops = FLOP_PER_CELL_UPDATE * 2 * cells / (t2 * 1e-3) / 1e12
+        hbm_eq = 60 * 2 * cells / (t2 * 1e-3) / 1e9
+        traffic2 = step2_traffic()
+        roofline = {
+            "bound": "alu",
+            "achieved": tflops,
+            "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": tflops / FP32_PEAK_TFLOPS,
+            "traffic": traffic2,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_over_algorithmic": traffic2 / (cells * 60) if traffic2 else None,
+            "kernel": "step2_kernel (two FDTD steps per launch)",
+            "algorithmic_flop_per_cell_update": FLOP_PER_CELL_UPDATE,
+            "peak_note": "FP32 FMA peak without packed FP32 (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)",
+            "frac_of_packed_fp32_peak": tflops / FP32_PACKED_PEAK_TFLOPS,
+            "kernel_ms_avg": t2,
+            "launches": n2,
+            "steps_per_launch": 2,
+            "us_per_step": t2 / 2 * 1e3,
+            "hbm_model": {"bytes_per_cell_update": 60, "achieved_GBs": hbm_eq, "peak": HBM_PEAK_GBS,
+                          "frac": hbm_eq / HBM_PEAK_GBS,
+                          "frac_of_stream": hbm_eq / stream_gbs if stream_gbs else None,
+                          "note": "cell-updates per second x 60 B (the one-step algorithmic bytes): the "
+                                  "metric's % of the HBM roofline; the kernel itself moves 60 B per two "
+                                  "cell-updates"},
+            "one_step_launches": {"launches": n1, "ms_avg": ms1 / n1 if n1 else None,
+                                  "note": "push steps (with force) and an odd last step, one step each"},
+            "copy_gbs": copy_gbs,
+            "stream_gbs": stream_gbs,
+        }
+    else:
+        traffic = step_traffic(variant)
+        roofline = {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "traffic_over_algorithmic": traffic / (cells * 60) if traffic else None,
+            "kernel": "step_kernel (FDTD step)",
+            "algorithmic_bytes_per_cell_update": "60 (+12 on push steps)",
+            "kernel_ms_avg": k_ms / max(k_launches, 1),
+            "launches": k_launches,
+            "variant": variant,
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
+            "stream_gbs": stream_gbs,
+            "frac_of_stream": achieved / stream_gbs if stream_gbs else None,
+            "stream_note": "kvs_measure_stream: the step's 9 FP32 reads + 6 writes per cell (60 B) with no stencil, "
+                           "over the interior cell count",
+        }
     res = {
         "metric": METRIC,
         "value": value,
@@ -1066,27 +1179,9 @@ def main():
             "interior_cells": cells,
             "parallelism": "single GPU",
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "traffic_over_algorithmic": traffic / (cells * 60) if traffic else None,
-            "kernel": "step_kernel (FDTD step)",
-            "algorithmic_bytes_per_cell_update": "60 (+12 on push steps)",
-            "kernel_ms_avg": k_ms / max(k_launches, 1),
-            "launches": k_launches,
-            "variant": variant,
-            "copy_gbs": copy_gbs,
-            "frac_of_copy": achieved / copy_gbs,
-            "stream_gbs": stream_gbs,
-            "frac_of_stream": achieved / stream_gbs if stream_gbs else None,
-            "stream_note": "kvs_measure_stream: the step's 9 FP32 reads + 6 writes per cell (60 B) with no stencil, "
-                           "over the interior cell count",
-        },
+        "roofline": roofline,
+        "one_step_kernel": one_step,
+        "step_blocking": args.step_blocking,
         "fdtd_kernel_gcells": args.steps * nsteps * cells / (k_ms * 1e-3) / 1e9,
         "pcie_inclusive": {"value": nsteps * cells / (pcie_ms * 1e-3) / 1e9, "unit": "Gcell-updates/s",
                            "ms_per_step": pcie_ms, "host_force_bytes": int(F_host.nbytes),

@@ -367,9 +367,14 @@ kvs_status kvs_strain_get(const kvs_ctx* ctx, double* peak_strain, double* peak_
  * start and end in a pair of HIP events on the context's stream (events
  * attached to the dispatch, hipExtLaunchKernel: the kernel's duration, no
  * extra queue packets); kvs_kernel_time returns the summed duration [ms] and
- * the launch count since timing was switched on. */
+ * the number of steps those launches advanced (one per launch, two per
+ * two-step launch) since timing was switched on. */
 kvs_status kvs_enable_kernel_timing(kvs_ctx* ctx, int32_t on);
-kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* launches);
+kvs_status kvs_kernel_time(kvs_ctx* ctx, double* ms_total, int64_t* steps);
+/* The same totals by launch kind: ms[0], launches[0] for one-step launches,
+ * ms[1], launches[1] for two-step launches (host arrays of 2; either may be
+ * NULL). */
+kvs_status kvs_kernel_time_split(kvs_ctx* ctx, double* ms, int64_t* launches);
 /* Streaming reference for the roofline of the FDTD step: a kernel with the
  * step's memory pattern and no stencil (per cell 9 FP32 values read, 6
  * written: 60 B; 15 contiguous streams of n floats, 16-byte accesses) run
@@ -535,6 +540,21 @@ kvs_status kvs_set_step_variant(kvs_ctx* ctx, int32_t v);
  * z so that the blocks fill whole rounds of resident blocks), remap != 0
  * issues tiles XCD by XCD in contiguous ranges (y-adjacent tiles share L2). */
 kvs_status kvs_set_step_tuning(kvs_ctx* ctx, int32_t v, int32_t zchunk, int32_t remap);
+/* Steps per launch of kvs_step: 1 or 2 (the default), else KVS_EINVAL.  With
+ * 2, kvs_step advances each pair of consecutive steps whose envelope values
+ * g_n are both 0 in one launch (temporal blocking of the Sec. 3.1 update: the
+ * intermediate state is formed on chip, with its rows next to each tile's
+ * computed twice); the result is that of two one-step launches (the same
+ * FP32 operations in the same order).  Applies where kvs_step_blocking_applies
+ * says so: FP32 state, heterogeneous viscous medium, no absorbing layer, no
+ * peak planes, nx <= 256, and probe cells (if any) distinct and off the planes
+ * k = 0 and nz - 1; elsewhere, for a step with force and for the last step of
+ * an odd count, kvs_step launches one step as with 1.  Traces are recorded
+ * for every step either way.  Kernel timing (kvs_kernel_time) counts the
+ * steps the timed launches advanced. */
+kvs_status kvs_set_step_blocking(kvs_ctx* ctx, int32_t steps);
+/* 1 if two-step launches apply to the context as it is now, else 0. */
+int32_t kvs_step_blocking_applies(const kvs_ctx* ctx);
 /* Time every variant on this context's grid, precision and medium, each with
  * the automatic z split and with 16-, 32- and 64-plane z segments
  * (trial_steps >= 1 launches each, after one untimed launch), and keep the

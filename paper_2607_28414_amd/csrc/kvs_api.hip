@@ -84,6 +84,8 @@ void release(kvs_ctx* c) {
     dfree(c->mem, c->partials);
     dfree(c->mem, c->cgs);
     dfree(c->mem, c->probe_cells);
+    dfree(c->mem, c->probe_rowtab);
+    dfree(c->mem, c->probe_ptab);
     dfree(c->mem, c->traces);
     dfree(c->mem, c->peak);
     dfree(c->mem, c->arf_sum);
@@ -130,9 +132,12 @@ kvs_status flush_timing(kvs_ctx* c) {
     for (int64_t q = 0; q < c->ev_used; ++q) {
         float ms = 0.f;
         API_HIP(c, hipEventElapsedTime(&ms, c->ev_pool[2 * q], c->ev_pool[2 * q + 1]));
+        const int adv = c->ev_steps[(size_t)q];
         c->timed_ms += ms;
+        c->timed_launches += adv;
+        c->timed_ms_kind[adv - 1] += ms;
+        c->timed_n_kind[adv - 1] += 1;
     }
-    c->timed_launches += c->ev_used;
     c->ev_used = 0;
     return KVS_OK;
 }
@@ -148,6 +153,8 @@ kvs_status next_event_pair(kvs_ctx* c, hipEvent_t* a, hipEvent_t* b) {
         API_HIP(c, hipEventCreate(&e));
         c->ev_pool.push_back(e);
     }
+    if ((int64_t)c->ev_steps.size() < c->ev_used + 1) c->ev_steps.resize((size_t)c->ev_used + 1);
+    c->ev_steps[(size_t)c->ev_used] = 1;
     *a = c->ev_pool[2 * c->ev_used];
     *b = c->ev_pool[2 * c->ev_used + 1];
     c->ev_used += 1;
@@ -553,16 +560,62 @@ kvs_status kvs_set_probes(kvs_ctx* c, const int64_t* ijk, int64_t n, int32_t com
             return fail(c, KVS_EINVAL, "probe " + std::to_string(p) + " outside the grid");
         flat[(size_t)p] = i + g.nx * (j + g.ny * k);
     }
+    // row tables for the two-step kernel: each probed grid row (j, k) gets nx
+    // entries holding the probe index of each of its cells (or -1)
+    std::vector<int> rowtab, ptab;
+    bool rows_ok = n > 0 && n < (int64_t)1 << 30;
+    if (rows_ok) {
+        rowtab.assign((size_t)(g.ny * g.nz), -1);
+        for (int64_t p = 0; p < n && rows_ok; ++p) {
+            const int64_t i = ijk[3 * p], j = ijk[3 * p + 1], k = ijk[3 * p + 2];
+            if (k == 0 || k == g.nz - 1) {
+                rows_ok = false;  // never formed by the two-step kernel (Dirichlet planes)
+                break;
+            }
+            int& off = rowtab[(size_t)(j + g.ny * k)];
+            if (off < 0) {
+                off = (int)ptab.size();
+                ptab.resize(ptab.size() + (size_t)g.nx, -1);
+            }
+            int& slot = ptab[(size_t)off + (size_t)i];
+            if (slot >= 0) rows_ok = false;  // the same cell twice
+            slot = (int)p;
+        }
+    }
+    if (rows_ok) {
+        // one entry per 64-cell segment of each row: the row's offset where
+        // the segment holds a probe, else -1
+        const int64_t nseg = (g.nx + 63) / 64;
+        std::vector<int> segtab((size_t)(g.ny * g.nz * nseg), -1);
+        for (int64_t r = 0; r < g.ny * g.nz; ++r) {
+            const int off = rowtab[(size_t)r];
+            if (off < 0) continue;
+            for (int64_t i = 0; i < g.nx; ++i)
+                if (ptab[(size_t)off + (size_t)i] >= 0) segtab[(size_t)(r * nseg + i / 64)] = off;
+        }
+        rowtab.swap(segtab);
+    }
     API_HIP(c, hipStreamSynchronize(c->stream));
     dfree(c->mem, c->probe_cells);
+    dfree(c->mem, c->probe_rowtab);
+    dfree(c->mem, c->probe_ptab);
     dfree(c->mem, c->traces);
     c->trace_cap = 0;
     c->trace_steps = 0;
     c->nprobes = n;
     c->probe_comp = comp;
+    c->probe_rows_ok = n == 0 || rows_ok;
     if (n > 0) {
         API_HIP(c, c->mem.get(&c->probe_cells, sizeof(int64_t) * n));
         API_HIP(c, hipMemcpyAsync(c->probe_cells, flat.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, c->stream));
+        if (rows_ok) {
+            API_HIP(c, c->mem.get(&c->probe_rowtab, sizeof(int) * rowtab.size()));
+            API_HIP(c, c->mem.get(&c->probe_ptab, sizeof(int) * ptab.size()));
+            API_HIP(c, hipMemcpyAsync(c->probe_rowtab, rowtab.data(), sizeof(int) * rowtab.size(),
+                                      hipMemcpyHostToDevice, c->stream));
+            API_HIP(c, hipMemcpyAsync(c->probe_ptab, ptab.data(), sizeof(int) * ptab.size(), hipMemcpyHostToDevice,
+                                      c->stream));
+        }
         API_HIP(c, hipStreamSynchronize(c->stream));
     }
     return KVS_OK;
@@ -586,28 +639,36 @@ kvs_status kvs_step(kvs_ctx* c, int64_t nsteps) {
     }
     // The probe values of a step's result are recorded by extra blocks of the
     // next step's launch, which read that launch's input state: one launch
-    // per step, and one gather after the last step of the call.
+    // per step (or per pair of steps, where the two-step kernel applies: it
+    // records the intermediate state itself), and one gather after the last
+    // step of the call.
     const int64_t per_slot = c->nprobes * ncomp_of(c->probe_comp);
-    for (int64_t q = 0; q < nsteps; ++q) {
+    for (int64_t q = 0; q < nsteps;) {
         const int64_t n = c->step;
         const double gn = n < n_env ? c->env[(size_t)n] : 0.0;
+        const double gn1 = n + 1 < n_env ? c->env[(size_t)(n + 1)] : 0.0;
+        const int adv = c->step_block == 2 && q + 1 < nsteps && gn == 0.0 && gn1 == 0.0 && kvs_step2_supported(c) ? 2 : 1;
         if (c->nprobes > 0 && q > 0) c->probe_fused_out = c->traces + (c->trace_steps - 1) * per_slot;
+        if (c->nprobes > 0 && adv == 2) c->probe_mid_out = c->traces + c->trace_steps * per_slot;
         if (c->timing) {
             hipEvent_t ea = nullptr, eb = nullptr;
             s = next_event_pair(c, &ea, &eb);
             if (s != KVS_OK) return s;
+            c->ev_steps[(size_t)(c->ev_used - 1)] = adv;
             c->launch_ev[0] = ea;
             c->launch_ev[1] = eb;
         }
-        const hipError_t le = kvs_launch_step(c, gn);
+        const hipError_t le = adv == 2 ? kvs_launch_step2(c) : kvs_launch_step(c, gn);
         c->launch_ev[0] = c->launch_ev[1] = nullptr;
         c->probe_fused_out = nullptr;
+        c->probe_mid_out = nullptr;
         API_HIP(c, le);
         if (c->pml_cells > 0) API_HIP(c, kvs_launch_pml(c, gn));
         c->cur = 1 - c->cur;
-        if (c->nprobes > 0) c->trace_steps += 1;  // slot filled by the next launch or the gather below
+        if (c->nprobes > 0) c->trace_steps += adv;  // last slot filled by the next launch or the gather below
         if (c->npeak > 0) API_HIP(c, kvs_launch_peak_update(c, c->u[c->cur]));
-        c->step += 1;
+        c->step += adv;
+        q += adv;
     }
     if (c->nprobes > 0 && nsteps > 0) API_HIP(c, kvs_launch_probe_gather(c, c->u[c->cur], c->trace_steps - 1));
     return KVS_OK;
@@ -1011,6 +1072,10 @@ kvs_status kvs_enable_kernel_timing(kvs_ctx* c, int32_t on) {
     if (on && !c->timing) {
         c->timed_ms = 0.0;
         c->timed_launches = 0;
+        for (int q = 0; q < 2; ++q) {
+            c->timed_ms_kind[q] = 0.0;
+            c->timed_n_kind[q] = 0;
+        }
         c->ev_used = 0;
     }
     if (!on && c->timing) {
@@ -1027,6 +1092,17 @@ kvs_status kvs_kernel_time(kvs_ctx* c, double* ms_total, int64_t* launches) {
     if (s != KVS_OK) return s;
     if (ms_total) *ms_total = c->timed_ms;
     if (launches) *launches = c->timed_launches;
+    return KVS_OK;
+}
+
+kvs_status kvs_kernel_time_split(kvs_ctx* c, double* ms, int64_t* launches) {
+    if (!c) return KVS_EINVAL;
+    kvs_status s = flush_timing(c);
+    if (s != KVS_OK) return s;
+    for (int q = 0; q < 2; ++q) {
+        if (ms) ms[q] = c->timed_ms_kind[q];
+        if (launches) launches[q] = c->timed_n_kind[q];
+    }
     return KVS_OK;
 }
 
@@ -1048,6 +1124,15 @@ kvs_status kvs_set_step_tuning(kvs_ctx* c, int32_t v, int32_t zchunk, int32_t re
     c->step_remap = remap != 0;
     return KVS_OK;
 }
+
+kvs_status kvs_set_step_blocking(kvs_ctx* c, int32_t steps) {
+    if (!c) return KVS_EINVAL;
+    if (steps != 1 && steps != 2) return fail(c, KVS_EINVAL, "steps per launch must be 1 or 2");
+    c->step_block = steps;
+    return KVS_OK;
+}
+
+int32_t kvs_step_blocking_applies(const kvs_ctx* c) { return c && c->have_material && kvs_step2_supported(c) ? 1 : 0; }
 
 kvs_status kvs_autotune_step(kvs_ctx* c, int32_t trial_steps, int32_t* chosen, double* ms_per_launch,
                              int32_t cap) {

@@ -126,13 +126,29 @@ struct kvs_ctx {
     double* traces = nullptr;
     int64_t trace_cap = 0;    // steps of capacity
     int64_t trace_steps = 0;  // steps recorded
+    // two-step launches: the probe cells by grid row, for the threads that
+    // form the intermediate state (rowtab [nz][ny][ceil(nx / 64)]: the offset
+    // into ptab of row (j, k) where that 64-cell segment of it holds a probe,
+    // else -1; ptab: per probed row nx probe indices or -1); only when the
+    // probe cells are distinct and off the planes k = 0, nz - 1 (probe_rows_ok)
+    int* probe_rowtab = nullptr;
+    int* probe_ptab = nullptr;
+    bool probe_rows_ok = true;
+    // trace slot for the intermediate state of the two-step launch being
+    // issued (null: no probes)
+    double* probe_mid_out = nullptr;
 
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_steps;  // steps advanced by the launch of each event pair
     int64_t ev_used = 0;
     double timed_ms = 0.0;
-    int64_t timed_launches = 0;
+    int64_t timed_launches = 0;  // steps advanced by the timed launches
+    // the same split by kind: [0] one-step launches, [1] two-step launches
+    // (summed ms and launch counts)
+    double timed_ms_kind[2] = {0.0, 0.0};
+    int64_t timed_n_kind[2] = {0, 0};
 
     // learned preconditioner (borrowed; set by kvs_set_preconditioner)
     kvs_unet* net = nullptr;
@@ -143,6 +159,8 @@ struct kvs_ctx {
     int step_variant = 0;
     int step_zchunk = 0;
     int step_remap = 1;
+    // steps per launch where the two-step kernel applies (1 or 2)
+    int step_block = 2;
     // when set, the next step-kernel launch records its own start and end in
     // these events (the dispatch's timestamps, no extra queue packets)
     hipEvent_t launch_ev[2] = {nullptr, nullptr};
@@ -250,6 +268,10 @@ hipError_t kvs_launch_force_pattern(kvs_ctx* c, const kvs_force_pattern* p);
 // One FDTD step from (u[cur], w[cur]) into (u[1-cur], w[1-cur]) with source
 // amplitude gn (0: no force read).  Returns the launch error.
 hipError_t kvs_launch_step(kvs_ctx* c, double gn);
+// two steps in one launch (kvs_step2.hip), for two steps without force:
+// whether the precision, medium, layer, peak maps, probes and grid allow it
+bool kvs_step2_supported(const kvs_ctx* c);
+hipError_t kvs_launch_step2(kvs_ctx* c);
 hipError_t kvs_launch_step_variant(kvs_ctx* c, double gn, int variant);
 int kvs_step_variant_count();
 void kvs_step_variant_shape(int variant, int* by, int* vec, int* wx);

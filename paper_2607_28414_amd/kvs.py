@@ -192,6 +192,9 @@ SIGNATURES = {
     "kvs_set_step_variant": ([_P, C.c_int32], C.c_int),
     "kvs_set_step_tuning": ([_P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
+    "kvs_set_step_blocking": ([_P, C.c_int32], C.c_int),
+    "kvs_kernel_time_split": ([_P, _D, C.POINTER(C.c_int64)], C.c_int),
+    "kvs_step_blocking_applies": ([_P], C.c_int32),
     "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
     "kvs_measure_stream": ([C.c_int32, C.c_int64, C.c_int32, _D], C.c_int),
     "kvs_measure_stream_rw": ([C.c_int32, C.c_int64, C.c_int32, C.c_int32, C.c_int32, _D], C.c_int),
@@ -510,10 +513,19 @@ def kvs_enable_kernel_timing(ctx, on):
 
 
 def kvs_kernel_time(ctx):
+    """(summed kernel ms, steps the timed launches advanced)."""
     ms = C.c_double()
     n = C.c_int64()
     _check(lib().kvs_kernel_time(ctx, C.byref(ms), C.byref(n)), ctx)
     return ms.value, n.value
+
+
+def kvs_kernel_time_split(ctx):
+    """((ms, launches) of one-step launches, (ms, launches) of two-step launches)."""
+    ms = np.zeros(2)
+    n = (C.c_int64 * 2)()
+    _check(lib().kvs_kernel_time_split(ctx, _dptr(ms), n), ctx)
+    return (float(ms[0]), int(n[0])), (float(ms[1]), int(n[1]))
 
 
 def kvs_num_step_variants():
@@ -534,6 +546,14 @@ def kvs_autotune_step(ctx, trial_steps=20):
 
 def kvs_set_step_tuning(ctx, v, zchunk=0, remap=True):
     _check(lib().kvs_set_step_tuning(ctx, int(v), int(zchunk), int(bool(remap))), ctx)
+
+
+def kvs_set_step_blocking(ctx, steps):
+    _check(lib().kvs_set_step_blocking(ctx, int(steps)), ctx)
+
+
+def kvs_step_blocking_applies(ctx):
+    return bool(lib().kvs_step_blocking_applies(ctx))
 
 
 # ---- batches ----------------------------------------------------------------
