@@ -21,19 +21,20 @@ all instances), lateral-line traces read back.
 
 value = interior cell-updates of the timed steps / timed wall time
         (whole job, projection included), in Gcell-updates/s.
-roofline: the dominant FDTD kernel over its HIP-event-timed launches.  By
-          default that is the two-step kernel (two steps per launch, bound by
-          vector-ALU issue): bound "alu", algorithmic FP32 flop (147 per
-          cell-update, two updates per cell and launch) over its mean launch
-          duration against the 78.6 TFLOP/s FMA peak without packed FP32;
-          hbm_model: cell-updates per second x 60 B against 8 TB/s (the
-          metric's % of the HBM roofline); the one-step push launches beside
-          it.  With --step-blocking 1: the one-step kernel, algorithmic bytes
-          per interior cell-update (48 B of FP32 u, w read + written, 12 B of
-          G, eta, dt^2/rho, and 12 B of f_S on push steps), with stream_gbs /
-          frac_of_stream (a stream with the step's own 9 reads and 6 writes
-          per cell and no stencil, measured in the same run) and copy_gbs /
-          frac_of_copy (a plain device-to-device copy).
+roofline: the dominant FDTD kernel over its HIP-event-timed launches,
+          algorithmic bytes per interior cell-update (48 B of FP32 u, w read +
+          written, 12 B of G, eta, dt^2/rho, and 12 B of f_S on push steps) x
+          the cell-updates one launch processes, over its mean launch
+          duration, against 8 TB/s.  By default that kernel is the two-step
+          kernel (two cell-updates per cell and launch; it moves 60 B per two
+          updates and is limited by vector-ALU issue: limited_by, and alu =
+          its algorithmic FP32 flop rate, 147 flop per cell-update, against
+          the 78.6 TFLOP/s FMA peak without packed FP32); the one-step push
+          launches are listed beside it.  With --step-blocking 1 it is the
+          one-step kernel.  stream_gbs / frac_of_stream: a stream with the
+          one-step kernel's 9 reads and 6 writes per cell and no stencil,
+          measured in the same run (the ceiling of any one-step kernel);
+          copy_gbs / frac_of_copy: a plain device-to-device copy.
           traffic: HBM bytes per launch from the rocprofv3 counter runs of
           the same kernel source (null when the source differs).
 one_step_kernel: the one-step kernel alone after the timed region (200
@@ -1108,32 +1109,36 @@ def main():
         hbm_eq = 60 * 2 * cells / (t2 * 1e-3) / 1e9
         traffic2 = step2_traffic()
         roofline = {
-            "bound": "alu",
-            "achieved": tflops,
-            "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": tflops / FP32_PEAK_TFLOPS,
+            "bound": "hbm",
+            "achieved": hbm_eq,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": hbm_eq / HBM_PEAK_GBS,
             "traffic": traffic2,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "traffic_over_algorithmic": traffic2 / (cells * 60) if traffic2 else None,
+            "algorithmic_bytes_per_launch": 60 * 2 * cells,
+            "traffic_over_algorithmic": traffic2 / (60 * 2 * cells) if traffic2 else None,
             "kernel": "step2_kernel (two FDTD steps per launch)",
-            "algorithmic_flop_per_cell_update": FLOP_PER_CELL_UPDATE,
-            "peak_note": "FP32 FMA peak without packed FP32 (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)",
-            "frac_of_packed_fp32_peak": tflops / FP32_PACKED_PEAK_TFLOPS,
+            "algorithmic_bytes_per_cell_update": 60,
+            "units_per_launch": "2 x interior cells (cell-updates)",
+            "limited_by": "vector-ALU issue (78-82 % VALU busy in the counter runs); the kernel moves 60 B per "
+                          "two cell-updates, about 0.57x the one-step algorithmic bytes",
+            "alu": {"achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tflops / FP32_PEAK_TFLOPS, "flop_per_cell_update": FLOP_PER_CELL_UPDATE,
+                    "peak_note": "FP32 FMA peak without packed FP32 (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)",
+                    "frac_of_packed_fp32_peak": tflops / FP32_PACKED_PEAK_TFLOPS},
             "kernel_ms_avg": t2,
             "launches": n2,
             "steps_per_launch": 2,
             "us_per_step": t2 / 2 * 1e3,
-            "hbm_model": {"bytes_per_cell_update": 60, "achieved_GBs": hbm_eq, "peak": HBM_PEAK_GBS,
-                          "frac": hbm_eq / HBM_PEAK_GBS,
-                          "frac_of_stream": hbm_eq / stream_gbs if stream_gbs else None,
-                          "note": "cell-updates per second x 60 B (the one-step algorithmic bytes): the "
-                                  "metric's % of the HBM roofline; the kernel itself moves 60 B per two "
-                                  "cell-updates"},
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": hbm_eq / copy_gbs,
+            "stream_gbs": stream_gbs,
+            "frac_of_stream": hbm_eq / stream_gbs if stream_gbs else None,
+            "stream_note": "kvs_measure_stream: the one-step pattern, 9 FP32 reads + 6 writes per cell (60 B) with "
+                           "no stencil, over the interior cell count: the ceiling of any one-step kernel",
             "one_step_launches": {"launches": n1, "ms_avg": ms1 / n1 if n1 else None,
                                   "note": "push steps (with force) and an odd last step, one step each"},
-            "copy_gbs": copy_gbs,
-            "stream_gbs": stream_gbs,
         }
     else:
         traffic = step_traffic(variant)
