@@ -424,6 +424,17 @@ kvs_status kvs_batch_trace_count(const kvs_batch* b, int64_t* nsteps_recorded);
 /* Traces of instance i, [step][probe] doubles, into out (cap doubles). */
 kvs_status kvs_batch_read_traces(kvs_batch* b, int32_t i, double* out, int64_t cap, int64_t* n_written);
 
+/* Steps per launch of kvs_batch_step: 1 or 2 (the default), else KVS_EINVAL.
+ * With 2, pairs of consecutive steps in which no instance's envelope is
+ * non-zero are advanced by one launch of the two-step tile over all
+ * instances (the result is bitwise that of one-step launches); it applies to
+ * FP32 batches with a viscous instance, rows of at most 256 cells, and probe
+ * cells distinct and off each instance's planes k = 0, nz - 1
+ * (kvs_batch_step_blocking_applies).  Runs that take the persistent path are
+ * not affected. */
+kvs_status kvs_batch_set_step_blocking(kvs_batch* b, int32_t steps);
+/* 1 if two-step launches apply to the batch as it is now, else 0. */
+int32_t kvs_batch_step_blocking_applies(const kvs_batch* b);
 /* Persistent runs of small instances (on by default): when every instance's
  * whole state (u and w, 24 B per node in FP32, 48 B in FP64) fits in 150 KB,
  * a kvs_batch_step run is one launch with one workgroup per instance that

@@ -1212,6 +1212,9 @@ static void batch_release(kvs_batch* b) {
     b->graph = nullptr;
     dfree(b->mem, b->dev_params);
     dfree(b->mem, b->dev_work);
+    dfree(b->mem, b->dev_params2);
+    dfree(b->mem, b->dev_work2);
+    dfree(b->mem, b->dev_ptabs2);
     dfree(b->mem, b->dev_probes);
     dfree(b->mem, b->traces);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -1295,6 +1298,66 @@ kvs_status kvs_batch_share_projection(kvs_batch* b, int32_t src, int32_t dst) {
     return KVS_OK;
 }
 
+// Probe tables of the two-step launches, for every instance with probes: one
+// entry per 64-cell segment of each grid row (the row's offset into the probe
+// table where that segment holds a probe, else -1), and per probed row nx
+// instance-local probe indices.  Probe cells must be distinct and off the
+// planes k = 0, nz - 1 (else two-step launches are not used).
+static kvs_status batch_upload_probes2(kvs_batch* b) {
+    const size_t ni = b->inst.size();
+    dfree(b->mem, b->dev_ptabs2);
+    b->rowtab2_off.assign(ni, -1);
+    b->ptab2_off.assign(ni, -1);
+    b->probes2_ok = true;
+    std::vector<int> all;
+    for (size_t i = 0; i < ni && b->probes2_ok; ++i) {
+        const int64_t p0 = b->probe_first.empty() ? 0 : b->probe_first[i];
+        const int64_t p1 = b->probe_first.empty() ? 0 : b->probe_first[i + 1];
+        if (p1 == p0) continue;
+        const kvs_grid& g = b->inst[i]->grid;
+        const int64_t nseg = (g.nx + 63) / 64;
+        std::vector<int> row((size_t)(g.ny * g.nz), -1), ptab;
+        for (int64_t p = p0; p < p1 && b->probes2_ok; ++p) {
+            const int64_t cell = b->probe_cell[(size_t)p];
+            const int64_t x = cell % g.nx, y = (cell / g.nx) % g.ny, z = cell / (g.nx * g.ny);
+            if (z == 0 || z == g.nz - 1) {
+                b->probes2_ok = false;
+                break;
+            }
+            int& off = row[(size_t)(y + g.ny * z)];
+            if (off < 0) {
+                off = (int)ptab.size();
+                ptab.resize(ptab.size() + (size_t)g.nx, -1);
+            }
+            int& slot = ptab[(size_t)off + (size_t)x];
+            if (slot >= 0) b->probes2_ok = false;  // the same cell twice
+            slot = (int)(p - p0);
+        }
+        if (!b->probes2_ok) break;
+        std::vector<int> seg((size_t)(g.ny * g.nz * nseg), -1);
+        for (int64_t r = 0; r < g.ny * g.nz; ++r) {
+            const int off = row[(size_t)r];
+            if (off < 0) continue;
+            for (int64_t x = 0; x < g.nx; ++x)
+                if (ptab[(size_t)off + (size_t)x] >= 0) seg[(size_t)(r * nseg + x / 64)] = off;
+        }
+        b->rowtab2_off[i] = (int64_t)all.size();
+        all.insert(all.end(), seg.begin(), seg.end());
+        b->ptab2_off[i] = (int64_t)all.size();
+        all.insert(all.end(), ptab.begin(), ptab.end());
+    }
+    if (!b->probes2_ok || all.empty()) {
+        b->rowtab2_off.assign(ni, -1);
+        b->ptab2_off.assign(ni, -1);
+        return KVS_OK;
+    }
+    BATCH_HIP(b, b->mem.get(&b->dev_ptabs2, sizeof(int) * all.size()));
+    BATCH_HIP(b, hipMemcpyAsync(b->dev_ptabs2, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice,
+                                b->stream));
+    BATCH_HIP(b, hipStreamSynchronize(b->stream));
+    return KVS_OK;
+}
+
 static kvs_status batch_upload_probes(kvs_batch* b) {
     const size_t np = b->probe_inst.size();
     dfree(b->mem, b->dev_probes);
@@ -1303,6 +1366,8 @@ static kvs_status batch_upload_probes(kvs_batch* b) {
     b->trace_steps = 0;
     b->graph_valid = false;
     b->host_traces_valid = false;
+    kvs_status s2 = batch_upload_probes2(b);
+    if (s2 != KVS_OK) return s2;
     if (np == 0) return KVS_OK;
     // (instance, cell) pairs, then the first probe of every instance (n + 1
     // entries: the persistent path finds its instance's probes there)
@@ -1399,9 +1464,10 @@ kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
         b->graph_valid = false;
     }
     BATCH_HIP(b, kvs_batch_prepare(b));
-    BATCH_HIP(b, kvs_batch_run(b, nsteps));
+    int64_t flips = 0;
+    BATCH_HIP(b, kvs_batch_run(b, nsteps, &flips));
     for (kvs_ctx* c : b->inst) {
-        if (nsteps & 1) c->cur = 1 - c->cur;
+        if (flips & 1) c->cur = 1 - c->cur;
         c->step += nsteps;
     }
     b->step += nsteps;
@@ -1409,6 +1475,16 @@ kvs_status kvs_batch_step(kvs_batch* b, int64_t nsteps) {
     b->host_traces_valid = false;
     return KVS_OK;
 }
+
+kvs_status kvs_batch_set_step_blocking(kvs_batch* b, int32_t steps) {
+    if (!b) return KVS_EINVAL;
+    if (steps != 1 && steps != 2) return bfail(b, KVS_EINVAL, "steps per launch must be 1 or 2");
+    b->step_block = steps;
+    b->graph_valid = false;
+    return KVS_OK;
+}
+
+int32_t kvs_batch_step_blocking_applies(const kvs_batch* b) { return b && kvs_batch_two_step_supported(b) ? 1 : 0; }
 
 kvs_status kvs_batch_set_persistent(kvs_batch* b, int32_t on) {
     if (!b) return KVS_EINVAL;

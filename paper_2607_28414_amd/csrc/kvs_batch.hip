@@ -2,12 +2,13 @@
 // launch per step over every instance's tiles (captured once as a hipGraph
 // and replayed), or, when every instance's state fits one workgroup's LDS,
 // one persistent launch for the whole run.
+#include "kvs_step2_tile.hpp"
 #include "kvs_step_tile.hpp"
 
 namespace {
 
 // Batched homogeneous instances: one launch covers every instance's tiles
-// through a work list (instance, bx, by, bz).  `parity` (steps since the
+// through a work list (instance, bx, by, bz).  `parity` (launches since the
 // table was built, mod 2) selects which ping-pong buffers are current; the
 // absolute step n indexes each instance's envelope.
 template <typename T>
@@ -230,22 +231,172 @@ std::vector<uint8_t> batch_force_mask(const kvs_batch* b, int64_t nsteps) {
     return m;
 }
 
+// ---- two steps per launch ----------------------------------------------------
+//
+// Pairs of steps without force are advanced by one launch of the two-step tile
+// (kvs_step2_tile.hpp, homogeneous form) over a work list of (instance, row
+// pair, z segment), one launch per tile width (128, 192 or 256 threads per
+// row); the result is bitwise that of two one-step launches.  The
+// intermediate state's probe values are written by the kernel into their
+// trace slot; the gather after the launch records the second step's.
+
+struct BatchInst2 {
+    Step2Args a2[2];   // [parity], buffers as in BatchInst::a
+    long long probe0;  // the instance's first probe in the flat probe list
+};
+
+constexpr int kStep2Zchunk = 64;  // z planes per block of the two-step launches
+
+// Thread rows of the batched two-step tiles by tile width (64 WX threads per
+// row): close to 1024 threads per block, for four waves per SIMD at one block
+// per CU (the tiles' LDS allows one).
+#ifndef KVS_STEP2_ROWS2
+#define KVS_STEP2_ROWS2 8
+#endif
+#ifndef KVS_STEP2_ROWS3
+#define KVS_STEP2_ROWS3 5
+#endif
+template <int WX>
+constexpr int step2_rows() {
+    return WX == 2 ? KVS_STEP2_ROWS2 : WX == 3 ? KVS_STEP2_ROWS3 : 4;
+}
+
+template <int WX>
+__global__ __launch_bounds__(64 * WX * step2_rows<WX>()) void batch_step2_kernel(const BatchInst2* inst,
+                                                                                const int4* work, int nwork,
+                                                                                int parity, double* slot) {
+    const int t = tile_of(blockIdx.x, nwork);
+    const int4 wi = work[t];
+    const BatchInst2& bi = inst[wi.x];
+    Step2Args A = bi.a2[parity];
+    A.pmid = slot != nullptr && A.rowtab != nullptr ? slot + bi.probe0 : nullptr;
+    step2_tile<false, WX, step2_rows<WX>()>(A, wi.y, wi.z);
+}
+
+int step2_wx(int64_t nx) { return nx <= 128 ? 2 : nx <= 192 ? 3 : 4; }
+int step2_out_rows(int wx) { return (wx == 2 ? step2_rows<2>() : wx == 3 ? step2_rows<3>() : step2_rows<4>()) - 2; }
+
+hipError_t prepare2(kvs_batch* b) {
+    b->two_ok = kvs_batch_two_step_supported(b);
+    if (!b->two_ok) return hipSuccess;
+    const int n = (int)b->inst.size();
+    std::vector<BatchInst2> params((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        kvs_ctx* c = b->inst[(size_t)i];
+        const int64_t roff = i < (int)b->rowtab2_off.size() ? b->rowtab2_off[(size_t)i] : -1;
+        const int64_t poff = i < (int)b->ptab2_off.size() ? b->ptab2_off[(size_t)i] : -1;
+        for (int par = 0; par < 2; ++par) {
+            Step2Args& A = params[(size_t)i].a2[par];
+            A = Step2Args{};
+            A.a = instance_args<float>(c, par == 0 ? c->cur : 1 - c->cur, 4, 1, 1, kStep2Zchunk);
+            const int orow = step2_out_rows(step2_wx(A.a.nx));
+            A.a.gx = 1;
+            A.a.gy = (A.a.ny + orow - 1) / orow;
+            A.a.pcomp = b->comp;
+            A.rowtab = roff >= 0 ? b->dev_ptabs2 + roff : nullptr;
+            A.ptab = poff >= 0 ? b->dev_ptabs2 + poff : nullptr;
+        }
+        params[(size_t)i].probe0 = b->probe_first.empty() ? 0 : (long long)b->probe_first[(size_t)i];
+    }
+    const size_t bytes = sizeof(BatchInst2) * (size_t)n;
+    hipError_t e = hipSuccess;
+    if (!b->dev_params2 || b->params2_bytes < bytes) {
+        b->mem.put(b->dev_params2);
+        b->dev_params2 = nullptr;
+        e = b->mem.get(&b->dev_params2, bytes);
+        if (e != hipSuccess) return e;
+        b->params2_bytes = bytes;
+        b->graph_valid = false;
+    }
+    e = hipMemcpyAsync(b->dev_params2, params.data(), bytes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && !b->dev_work2) {
+        std::vector<int4> work;
+        b->groups2.clear();
+        for (int wx = 2; wx <= 4; ++wx) {
+            const int first = (int)work.size();
+            for (int i = 0; i < n; ++i) {
+                if (step2_wx(b->inst[(size_t)i]->grid.nx) != wx) continue;
+                const StepArgs<float>& a = params[(size_t)i].a2[0].a;
+                for (int bz = 0; bz < a.gz; ++bz)
+                    for (int by = 0; by < a.gy; ++by) work.push_back(make_int4(i, by, bz, 0));
+            }
+            if ((int)work.size() > first) b->groups2.push_back({wx, first, (int)work.size() - first});
+        }
+        e = b->mem.get(&b->dev_work2, sizeof(int4) * work.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->dev_work2, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice,
+                               b->stream);
+        b->nwork2 = (int)work.size();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return e;
+}
+
+void launch_batch_step2(kvs_batch* b, int parity, double* slot) {
+    const BatchInst2* inst = static_cast<const BatchInst2*>(b->dev_params2);
+    for (const kvs_batch::Group& g : b->groups2) {
+        const int4* w = static_cast<const int4*>(b->dev_work2) + g.off;
+        switch (g.shape) {
+            case 2:
+                hipLaunchKernelGGL(batch_step2_kernel<2>, dim3(g.count), dim3(128, step2_rows<2>()), 0, b->stream, inst, w,
+                                   g.count, parity, slot);
+                break;
+            case 3:
+                hipLaunchKernelGGL(batch_step2_kernel<3>, dim3(g.count), dim3(192, step2_rows<3>()), 0, b->stream, inst, w,
+                                   g.count, parity, slot);
+                break;
+            default:
+                hipLaunchKernelGGL(batch_step2_kernel<4>, dim3(g.count), dim3(256, step2_rows<4>()), 0, b->stream, inst, w,
+                                   g.count, parity, slot);
+                break;
+        }
+    }
+}
+
+// The launches of a run: per step 0 (one-step launch), 1 (one-step launch
+// reading f_S), 2 (first step of a two-step launch), 3 (its second step).
+std::vector<uint8_t> batch_plan(const kvs_batch* b, int64_t nsteps, int64_t* launches) {
+    std::vector<uint8_t> plan = batch_force_mask(b, nsteps);
+    const bool two = b->two_ok && b->step_block == 2;
+    int64_t nl = 0;
+    for (int64_t q = 0; q < nsteps; ++nl) {
+        if (two && q + 1 < nsteps && plan[(size_t)q] == 0 && plan[(size_t)(q + 1)] == 0) {
+            plan[(size_t)q] = 2;
+            plan[(size_t)(q + 1)] = 3;
+            q += 2;
+        } else {
+            q += 1;
+        }
+    }
+    *launches = nl;
+    return plan;
+}
+
 template <typename T>
-hipError_t capture_t(kvs_batch* b, int64_t nsteps, const std::vector<uint8_t>& force_mask) {
+hipError_t capture_t(kvs_batch* b, int64_t nsteps, const std::vector<uint8_t>& plan) {
     const int np = (int)b->probe_inst.size();
-    for (int64_t q = 0; q < nsteps; ++q) {
+    int64_t launch = 0;
+    for (int64_t q = 0; q < nsteps; ++launch) {
         const int64_t n = b->step + q;
-        const bool force = force_mask[(size_t)q] != 0;
-        const int parity = (int)(q & 1);
-        if (b->viscous)
-            force ? launch_batch_step<T, true, true>(b, n, parity) : launch_batch_step<T, true, false>(b, n, parity);
-        else
-            force ? launch_batch_step<T, false, true>(b, n, parity) : launch_batch_step<T, false, false>(b, n, parity);
+        const int parity = (int)(launch & 1);  // every launch swaps the buffers once
+        int adv = 1;
+        if (plan[(size_t)q] == 2) {
+            if constexpr (sizeof(T) == 4)
+                launch_batch_step2(b, parity, np > 0 ? b->traces + (b->trace_steps + q) * np : nullptr);
+            adv = 2;
+        } else {
+            const bool force = plan[(size_t)q] == 1;
+            if (b->viscous)
+                force ? launch_batch_step<T, true, true>(b, n, parity) : launch_batch_step<T, true, false>(b, n, parity);
+            else
+                force ? launch_batch_step<T, false, true>(b, n, parity) : launch_batch_step<T, false, false>(b, n, parity);
+        }
         if (np > 0)
             hipLaunchKernelGGL(batch_probe_kernel<T>, dim3((np + 255) / 256), dim3(256), 0, b->stream,
                                static_cast<const BatchInst<T>*>(b->dev_params),
                                static_cast<const long long*>(b->dev_probes), np, b->comp, parity,
-                               b->traces + (b->trace_steps + q) * np);
+                               b->traces + (b->trace_steps + q + adv - 1) * np);
+        q += adv;
     }
     return hipGetLastError();
 }
@@ -497,19 +648,34 @@ hipError_t kvs_batch_trial_launch(kvs_batch* b) {
     return hipGetLastError();
 }
 
-hipError_t kvs_batch_prepare(kvs_batch* b) {
-    return b->prec == KVS_FP32 ? prepare_t<float>(b) : prepare_t<double>(b);
+bool kvs_batch_two_step_supported(const kvs_batch* b) {
+    if (b->prec != KVS_FP32 || !b->probes2_ok || b->inst.empty()) return false;
+    bool visc = false;
+    for (const kvs_ctx* c : b->inst) {
+        if (!c->have_material || c->grid.nx > 256 || c->N >= ((int64_t)1 << 31) || c->npeak > 0 || c->pml_cells > 0)
+            return false;
+        visc = visc || c->viscous;
+    }
+    return visc;  // the two-step tile stages w: a batch with a viscous instance
 }
 
-hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps) {
+hipError_t kvs_batch_prepare(kvs_batch* b) {
+    hipError_t e = b->prec == KVS_FP32 ? prepare_t<float>(b) : prepare_t<double>(b);
+    if (e == hipSuccess) e = prepare2(b);
+    return e;
+}
+
+hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps, int64_t* flips) {
     int cpt = 0, thr = 0;
+    *flips = nsteps;
     if (b->small_ok && (b->prec == KVS_FP32 ? small_fits<float>(b, &cpt, &thr) : small_fits<double>(b, &cpt, &thr)))
         return b->prec == KVS_FP32 ? run_small_t<float>(b, nsteps, cpt, thr) : run_small_t<double>(b, nsteps, cpt, thr);
     // Replay the cached graph when it was captured for the same start step,
-    // step count, trace slot and per-step force switch (the parameter table
-    // and envelopes it reads were refreshed in place by kvs_batch_prepare);
-    // otherwise capture a new one.
-    std::vector<uint8_t> force_mask = batch_force_mask(b, nsteps);
+    // step count, trace slot and launch plan (which steps read f_S, which are
+    // paired into two-step launches; the parameter tables and envelopes it
+    // reads were refreshed in place by kvs_batch_prepare); otherwise capture a
+    // new one.
+    std::vector<uint8_t> force_mask = batch_plan(b, nsteps, flips);
     const bool hit = b->graph_valid && b->graph && b->graph_start == b->step && b->graph_steps == nsteps &&
                      b->graph_trace0 == b->trace_steps && b->graph_force == force_mask;
     hipError_t e = hipSuccess;

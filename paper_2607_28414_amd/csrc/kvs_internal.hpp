@@ -257,7 +257,23 @@ struct kvs_batch {
     hipGraphExec_t graph = nullptr;
     bool graph_valid = false;
     int64_t graph_start = -1, graph_steps = 0, graph_trace0 = -1;
-    std::vector<uint8_t> graph_force;
+    std::vector<uint8_t> graph_force;  // the per-step launch plan (see kvs_batch_run)
+
+    // two steps per launch: requested (1 or 2), and whether the batch allows
+    // it (set by kvs_batch_prepare: FP32, viscous, rows <= 256 cells, probe
+    // cells distinct and off the planes k = 0, nz - 1); the instances'
+    // two-step arguments [parity], the work list of (instance, row pair,
+    // z segment) grouped by tile width, and the probe row tables
+    int step_block = 2;
+    bool two_ok = false;
+    void* dev_params2 = nullptr;
+    size_t params2_bytes = 0;
+    void* dev_work2 = nullptr;
+    int nwork2 = 0;
+    std::vector<Group> groups2;  // shape = wavefronts per row (2, 3 or 4)
+    int* dev_ptabs2 = nullptr;   // row tables and probe tables of all instances
+    std::vector<int64_t> rowtab2_off, ptab2_off;  // per instance, into dev_ptabs2 (-1: none)
+    bool probes2_ok = true;      // the registered probes allow two-step launches
 };
 
 // ---- launchers (kvs_force.hip) ------------------------------------------
@@ -314,7 +330,12 @@ hipError_t kvs_launch_stable_dt(kvs_ctx* c, const double* dG, const double* drho
 // replay (or capture) the graph of nsteps steps starting at b->step
 hipError_t kvs_batch_prepare(kvs_batch* b);
 hipError_t kvs_batch_trial_launch(kvs_batch* b);
-hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps);
+// Runs nsteps steps; *flips = launches that advanced the state (each swaps
+// the current and next buffers once).
+hipError_t kvs_batch_run(kvs_batch* b, int64_t nsteps, int64_t* flips);
+// Whether the batch's instances allow two-step launches (precision, medium,
+// row width, probes); the step loop also needs steps without force.
+bool kvs_batch_two_step_supported(const kvs_batch* b);
 // True when kvs_batch_run takes the persistent path (every instance's state
 // fits one workgroup's LDS and the path is enabled).
 bool kvs_batch_small_path(const kvs_batch* b);

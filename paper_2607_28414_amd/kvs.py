@@ -194,6 +194,8 @@ SIGNATURES = {
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_set_step_blocking": ([_P, C.c_int32], C.c_int),
     "kvs_kernel_time_split": ([_P, _D, C.POINTER(C.c_int64)], C.c_int),
+    "kvs_batch_set_step_blocking": ([_P, C.c_int32], C.c_int),
+    "kvs_batch_step_blocking_applies": ([_P], C.c_int32),
     "kvs_step_blocking_applies": ([_P], C.c_int32),
     "kvs_kernel_time": ([_P, _D, _I64], C.c_int),
     "kvs_measure_stream": ([C.c_int32, C.c_int64, C.c_int32, _D], C.c_int),
@@ -578,6 +580,14 @@ def kvs_batch_create(grids, precision=KVS_FP32, sponge_cells=0, sponge_sigma_max
 
 def kvs_batch_set_persistent(b, on):
     _bcheck(lib().kvs_batch_set_persistent(b, int(bool(on))), b)
+
+
+def kvs_batch_set_step_blocking(b, steps):
+    _bcheck(lib().kvs_batch_set_step_blocking(b, int(steps)), b)
+
+
+def kvs_batch_step_blocking_applies(b):
+    return bool(lib().kvs_batch_step_blocking_applies(b))
 
 
 def kvs_batch_uses_persistent(b):

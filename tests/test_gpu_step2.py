@@ -54,7 +54,10 @@ def probe_set(grid, seed):
 def run(kvs, grid, mat, F, env, probes, comp, calls, blocking, zchunk=0, variant=None):
     ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, sponge_cells=4, sponge_sigma_max=-1.0)
     try:
-        kvs.kvs_set_material(ctx, *mat)
+        if np.isscalar(mat[0]):
+            kvs.kvs_set_material_uniform(ctx, *mat)
+        else:
+            kvs.kvs_set_material(ctx, *mat)
         kvs.kvs_set_dt(ctx, 0.5 * kvs.kvs_stable_dt(ctx))
         kvs.kvs_set_force(ctx, F)
         kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_JACOBI)
@@ -74,18 +77,20 @@ def run(kvs, grid, mat, F, env, probes, comp, calls, blocking, zchunk=0, variant
     return applies, tr, u, w, step
 
 
-@pytest.mark.parametrize("nx,ny,nz,zchunk,comp", [
-    (70, 41, 36, 0, 2),     # 128-wide tiles, odd row count
-    (70, 41, 36, 5, 3),     # seven z segments, the last ragged; all components
-    (200, 30, 40, 0, 0),    # 256-wide tiles
-    (256, 24, 19, 4, 1),    # full-width rows, ragged z segments
-    (5, 3, 3, 0, 2),        # one interior cell
+@pytest.mark.parametrize("nx,ny,nz,zchunk,comp,het", [
+    (70, 41, 36, 0, 2, True),     # 128-wide tiles, odd row count
+    (70, 41, 36, 5, 3, True),     # seven z segments, the last ragged; all components
+    (200, 30, 40, 0, 0, True),    # 256-wide tiles
+    (256, 24, 19, 4, 1, True),    # full-width rows, ragged z segments
+    (5, 3, 3, 0, 2, True),        # one interior cell
+    (96, 35, 30, 7, 2, False),    # homogeneous medium
+    (230, 17, 22, 0, 3, False),   # homogeneous, 256-wide tiles
 ])
-def test_two_step_launches_match_one_step_bitwise(kvs, nx, ny, nz, zchunk, comp):
+def test_two_step_launches_match_one_step_bitwise(kvs, nx, ny, nz, zchunk, comp, het):
     h = 0.25e-3
     grid = (nx, ny, nz, h, h, h)
-    say(f"case two-step bitwise {nx}x{ny}x{nz} zchunk {zchunk} comp {comp}")
-    mat = medium(grid, nx + ny + nz)
+    say(f"case two-step bitwise {nx}x{ny}x{nz} zchunk {zchunk} comp {comp} heterogeneous {het}")
+    mat = medium(grid, nx + ny + nz) if het else (4e3, 1050.0, 0.9)
     rng = np.random.default_rng(7)
     F = rng.standard_normal((3, nz, ny, nx))
     env = np.r_[np.ones(7), 0.0, 0.0, 1.0]  # force on steps 0..6 and 9
@@ -133,7 +138,8 @@ def test_where_two_step_launches_apply(kvs):
     assert applies()
     assert applies(probes=[[3, 4, 5], [4, 4, 5]])
     assert not applies(precision=kvs.KVS_FP64)
-    assert not applies(material=(3e3, 1000.0, 0.5))  # homogeneous
+    assert applies(material=(3e3, 1000.0, 0.5))  # homogeneous viscous
+    assert not applies(material=(3e3, 1000.0, 0.0))  # homogeneous elastic
     zero_eta = (mat[0], mat[1], np.zeros_like(mat[2]))
     assert not applies(material=zero_eta)  # elastic
     assert not applies(pml=4)
@@ -228,3 +234,79 @@ def test_two_step_fp32_traces_within_2e5_of_oracle(kvs):
     err = rel_l2(tr, tr_o)
     say(f"two-step fp32 trace rel L2 {err:.3e}")
     assert err <= 2e-5
+
+
+BATCH_CASES = [  # (nx, ny, nz), G, eta: 128-, 192- and 256-wide tiles, one elastic instance
+    ((70, 41, 36), 3e3, 0.5),
+    ((96, 30, 40), 8e3, 1.2),
+    ((130, 33, 29), 2e3, 0.0),
+    ((200, 26, 31), 5e3, 0.3),
+    ((64, 20, 18), 1e3, 0.8),
+]
+
+
+def run_batch(kvs, blocking, calls):
+    h = 0.25e-3
+    grids = [s + (h, h, h) for s, _, _ in BATCH_CASES]
+    b = kvs.kvs_batch_create(grids, precision=kvs.KVS_FP32, sponge_cells=4, sponge_sigma_max=800.0)
+    try:
+        kvs.kvs_batch_set_persistent(b, False)
+        probes = []
+        for i, (shape, G, eta) in enumerate(BATCH_CASES):
+            c = kvs.kvs_batch_instance(b, i)
+            kvs.kvs_set_material_uniform(c, G, 1000.0, eta)
+            kvs.kvs_set_dt(c, 0.4 * kvs.kvs_stable_dt(c))
+            rng = np.random.default_rng(20 + i)
+            kvs.kvs_set_projected_force(c, rng.standard_normal((3, shape[2], shape[1], shape[0])) * 1e-3)
+            kvs.kvs_set_envelope(c, np.r_[np.ones(5 + i), 0.0, 0.0, 1.0])  # push steps at odd and even offsets
+            p = probe_set(grids[i], 30 + i)
+            kvs.kvs_batch_set_probes(b, i, p)
+            probes.append(p)
+        kvs.kvs_batch_set_component(b, 2)
+        kvs.kvs_batch_set_step_blocking(b, blocking)
+        applies = kvs.kvs_batch_step_blocking_applies(b)
+        for n in calls:
+            kvs.kvs_batch_step(b, n)
+        traces = [kvs.kvs_batch_read_traces(b, i, len(probes[i])) for i in range(len(BATCH_CASES))]
+        states = [kvs.kvs_get_state(kvs.kvs_batch_instance(b, i), (s[2], s[1], s[0]))[:2]
+                  for i, (s, _, _) in enumerate(BATCH_CASES)]
+    finally:
+        kvs.kvs_batch_destroy(b)
+    return applies, traces, states
+
+
+def test_batch_two_step_launches_match_one_step_bitwise(kvs):
+    """A batch of homogeneous instances of five widths (one elastic) advanced
+    with two steps per launch: the traces and states of every instance are
+    bitwise those of one step per launch, over calls of odd step counts with
+    push steps mixed in, and a replayed graph gives the same again."""
+    say("case batch two-step bitwise")
+    calls = (1, 10, 6, 14)
+    _, ref_tr, ref_st = run_batch(kvs, 1, calls)
+    applies, tr, st = run_batch(kvs, 2, calls)
+    assert applies
+    for i in range(len(BATCH_CASES)):
+        assert ref_tr[i].shape == (sum(calls), len(probe_set(BATCH_CASES[i][0] + (1, 1, 1), 30 + i)))
+        assert np.array_equal(tr[i], ref_tr[i]), i
+        assert np.array_equal(st[i][0], ref_st[i][0]) and np.array_equal(st[i][1], ref_st[i][1]), i
+    assert max(np.max(np.abs(t)) for t in ref_tr) > 0.0
+
+
+def test_batch_two_step_applies_only_where_supported(kvs):
+    h = 0.25e-3
+    grids = [(40, 20, 12, h, h, h), (300, 10, 8, h, h, h)]
+    for wide, eta in ((False, 0.5), (False, 0.0), (True, 0.5)):
+        b = kvs.kvs_batch_create(grids if wide else grids[:1], precision=kvs.KVS_FP32)
+        try:
+            for i in range(2 if wide else 1):
+                c = kvs.kvs_batch_instance(b, i)
+                kvs.kvs_set_material_uniform(c, 3e3, 1000.0, eta)
+                kvs.kvs_set_dt(c, 0.4 * kvs.kvs_stable_dt(c))
+            assert kvs.kvs_batch_step_blocking_applies(b) == (eta > 0 and not wide)
+            if eta > 0 and not wide:
+                kvs.kvs_batch_set_probes(b, 0, [[3, 4, 0]])  # on the plane k = 0
+                assert not kvs.kvs_batch_step_blocking_applies(b)
+            with pytest.raises(kvs.KvsError):
+                kvs.kvs_batch_set_step_blocking(b, 3)
+        finally:
+            kvs.kvs_batch_destroy(b)
