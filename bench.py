@@ -85,8 +85,8 @@ STEP_COUNTERS_KIB = {  # variant -> (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatch
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 # The same counters for the two-step kernel (step2_kernel, one launch = two
 # steps without force), taken on STEP2_SOURCES with SHA-256 STEP2_SOURCE_SHA.
-STEP2_SOURCE_SHA = "5790dfd03989459253496200a6ba84abc02709fa4ce3a8c1c0333225a0eebe53"
-STEP2_COUNTERS_KIB = (355157.9, 390148.0)  # (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
+STEP2_SOURCE_SHA = "afa88b3dbaec40ae51905569016d154bdaa4c5af91a90cc636e50cb1dea255c5"
+STEP2_COUNTERS_KIB = (355196.0, 390148.0)  # (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
 # Algorithmic FP32 arithmetic of one heterogeneous viscous cell-update of the
 # summed-form leapfrog (Sec. 3.1), an FMA counted as two: six harmonic face
 # moduli 2 G G' / (G + G') / h^2 (5 each, 30); the sponge factors s,
@@ -116,7 +116,7 @@ def parse():
     ap.add_argument("--step-variant", type=int, default=-1,
                     help="pin the step-kernel tile shape (default: autotune); used by the counter runs")
     ap.add_argument("--step-blocking", type=int, default=2, choices=[1, 2],
-                    help="FDTD steps per step-kernel launch in the main leg (2: the two-step kernel)")
+                    help="FDTD steps per launch in the main and batched legs (2: the two-step kernels)")
     ap.add_argument("--train-rounds", type=int, default=4,
                     help="training rounds on the network's own flexible-PCG residuals")
     ap.add_argument("--train-grid", type=int, default=64, help="edge of the cubic unit training grids")
@@ -145,7 +145,7 @@ def log(*a):
 
 
 STEP_SOURCES = ("kvs_step_tile.hpp", "kvs_step.hip", "kvs_tiling.hpp")
-STEP2_SOURCES = ("kvs_step2.hip", "kvs_step_tile.hpp", "kvs_tiling.hpp")
+STEP2_SOURCES = ("kvs_step2.hip", "kvs_step2_tile.hpp", "kvs_step_tile.hpp", "kvs_tiling.hpp")
 
 
 def step_source_sha(names=STEP_SOURCES):
@@ -790,6 +790,8 @@ def run_batch(args, steps=None, warmup=None):
                 F_dev[e] = torch.from_numpy(gaussian_push(grids[i], 1e-3, 4e-3, 1e4)).to("cuda")
         kvs.kvs_batch_set_component(b, 2)
         bv, bz, bms = kvs.kvs_batch_autotune(b, 5)
+        kvs.kvs_batch_set_step_blocking(b, args.step_blocking)
+        two = args.step_blocking == 2 and kvs.kvs_batch_step_blocking_applies(b)
         log(f"bench: batch tile variant {bv}, z planes {bz} ({', '.join(f'{m:.2f}' for m in bms)} ms per step)")
         cells = [(e - 2) ** 3 for e, *_ in draws]
 
@@ -845,7 +847,11 @@ def run_batch(args, steps=None, warmup=None):
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "batch_step_kernel (one launch per step over all instances; graph time incl. probes)",
+                     "kernel": ("batch_step2_kernel (two steps per launch over all instances, one launch per "
+                                "tile width; push steps one per launch)" if two else
+                                "batch_step_kernel (one launch per step over all instances)")
+                               + "; graph time incl. probe gathers",
+                     "steps_per_launch": 2 if two else 1,
                      "algorithmic_bytes_per_cell_update": "48 (+12 on push steps)", "graph_ms": step_ms,
                      "variant": bv, "zchunk": bz, "stream_gbs": stream_gbs,
                      "frac_of_stream": achieved / stream_gbs,
