@@ -278,14 +278,17 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, c
         lds[buf][L.h_row][L.h_col] = hc;
         const int q2 = min(k + 2, ke) * sxy + L.col;
         const int qh = min(k + L.h_dz, ke) * sxy + L.h_off;
-        const double rn = r[q2], on = p_old[q2], hrn = r[qh], hon = p_old[qh];
+        // streamed accesses (non-temporal): the old direction, read once per
+        // iteration, and the new one, read by the next sweep from HBM anyway;
+        // r stays cached for the update sweep
+        const double rn = r[q2], on = __builtin_nontemporal_load(p_old + q2), hrn = r[qh], hon = p_old[qh];
         lds_barrier();
         const double c2 = 2.0 * pc;
         const double ap = -((lds[buf][ty + 1][tx + 2] + lds[buf][ty + 1][tx] - c2) * g.ihx2
                             + (lds[buf][ty + 2][tx + 1] + lds[buf][ty][tx + 1] - c2) * g.ihy2
                             + (pp + pm - c2) * g.ihz2);
         s1 += L.act ? pc * ap : 0.0;
-        p_new[k * sxy + L.scol] = L.act ? pc : 0.0;
+        __builtin_nontemporal_store(L.act ? pc : 0.0, p_new + k * sxy + L.scol);
         pm = pc;
         pc = pp;
         pp = pv(rn, on);
@@ -320,7 +323,9 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_upd_kernel(const CgGeom g, c
         const double pn = p[min(k + 2, ke) * sxy + L.col];
         const double hn = p[min(k + L.h_dz, ke) * sxy + L.h_off];
         const int q1 = min(k + 1, ke - 1) * sxy + L.col;
-        const double phn = phi[q1], rn = r[q1];
+        // streamed accesses (non-temporal): phi (read and written once per
+        // iteration) and the stores; r and p stay cached for the next sweep
+        const double phn = __builtin_nontemporal_load(phi + q1), rn = r[q1];
         lds_barrier();
         const double c2 = 2.0 * pc;
         const double ap = -((lds[buf][ty + 1][tx + 2] + lds[buf][ty + 1][tx] - c2) * g.ihx2
@@ -329,8 +334,8 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_upd_kernel(const CgGeom g, c
         const double phv = phc + alpha * pc;
         const double rv = rc - alpha * ap;
         const int q = k * sxy + L.scol;
-        phi[q] = L.act ? phv : 0.0;
-        r_out[q] = L.act ? rv : 0.0;
+        __builtin_nontemporal_store(L.act ? phv : 0.0, phi + q);
+        __builtin_nontemporal_store(L.act ? rv : 0.0, r_out + q);
         s1 += L.act ? rv * rv : 0.0;
         s2 += L.act ? rv * (rv * g.dinv) : 0.0;
         pm = pc;

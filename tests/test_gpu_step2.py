@@ -310,3 +310,54 @@ def test_batch_two_step_applies_only_where_supported(kvs):
                 kvs.kvs_batch_set_step_blocking(b, 3)
         finally:
             kvs.kvs_batch_destroy(b)
+
+
+def test_two_step_resume_from_saved_state_is_bitwise(kvs):
+    """Stop after an odd number of steps (the pairing of the steps changes),
+    save the state, restore it into a new context and go on: the state and the
+    traces of the continued run are bitwise those of an uninterrupted run."""
+    h = 0.25e-3
+    grid = (90, 33, 28, h, h, h)
+    say("case two-step resume")
+    mat = medium(grid, 9)
+    probes = probe_set(grid, 4)
+    shp = (grid[2], grid[1], grid[0])
+
+    def new_ctx():
+        ctx = kvs.kvs_create(grid, precision=kvs.KVS_FP32, sponge_cells=4, sponge_sigma_max=-1.0)
+        kvs.kvs_set_material(ctx, *mat)
+        kvs.kvs_set_dt(ctx, 0.5 * kvs.kvs_stable_dt(ctx))
+        kvs.kvs_set_probes(ctx, probes, 2)
+        return ctx
+
+    rng = np.random.default_rng(6)
+    u0 = rng.standard_normal((3,) + shp) * 1e-6
+    w0 = rng.standard_normal((3,) + shp) * 1e-8
+    ctx = new_ctx()
+    try:
+        kvs.kvs_set_state(ctx, u0, w0, 0)
+        kvs.kvs_step(ctx, 40)
+        ref_tr = kvs.kvs_read_traces(ctx, len(probes), 1)
+        ref_u, ref_w, ref_n = kvs.kvs_get_state(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    ctx = new_ctx()
+    try:
+        kvs.kvs_set_state(ctx, u0, w0, 0)
+        kvs.kvs_step(ctx, 13)
+        tr1 = kvs.kvs_read_traces(ctx, len(probes), 1)
+        u, w, n = kvs.kvs_get_state(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    ctx = new_ctx()
+    try:
+        assert kvs.kvs_step_blocking_applies(ctx)
+        kvs.kvs_set_state(ctx, u, w, n)
+        kvs.kvs_step(ctx, 27)
+        tr2 = kvs.kvs_read_traces(ctx, len(probes), 1)
+        got_u, got_w, got_n = kvs.kvs_get_state(ctx, shp)
+    finally:
+        kvs.kvs_destroy(ctx)
+    assert n == 13 and got_n == ref_n == 40
+    assert np.array_equal(np.concatenate([tr1, tr2]), ref_tr)
+    assert np.array_equal(got_u, ref_u) and np.array_equal(got_w, ref_w)
