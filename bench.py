@@ -85,8 +85,8 @@ STEP_COUNTERS_KIB = {  # variant -> (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatch
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 # The same counters for the two-step kernel (step2_kernel, one launch = two
 # steps without force), taken on STEP2_SOURCES with SHA-256 STEP2_SOURCE_SHA.
-STEP2_SOURCE_SHA = "afa88b3dbaec40ae51905569016d154bdaa4c5af91a90cc636e50cb1dea255c5"
-STEP2_COUNTERS_KIB = (355196.0, 390148.0)  # (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
+STEP2_SOURCE_SHA = "8a13c07d6ffc431d3d458ff01837be9fa8a7ec2b08a1f5cfc443e77c110124c7"
+STEP2_COUNTERS_KIB = (329607.6, 390148.0)  # (FETCH_SIZE, WRITE_SIZE), mean of 6 dispatches
 # Algorithmic FP32 arithmetic of one heterogeneous viscous cell-update of the
 # summed-form leapfrog (Sec. 3.1), an FMA counted as two: six harmonic face
 # moduli 2 G G' / (G + G') / h^2 (5 each, 30); the sponge factors s,
@@ -1127,8 +1127,8 @@ def main():
             "kernel": "step2_kernel (two FDTD steps per launch)",
             "algorithmic_bytes_per_cell_update": 60,
             "units_per_launch": "2 x interior cells (cell-updates)",
-            "limited_by": "vector-ALU issue (78-82 % VALU busy in the counter runs); the kernel moves 60 B per "
-                          "two cell-updates, about 0.57x the one-step algorithmic bytes",
+            "limited_by": "vector-ALU issue (79-83 % VALU busy in the counter runs); the kernel moves 60 B per "
+                          "two cell-updates, about 0.55x the one-step algorithmic bytes",
             "alu": {"achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": tflops / FP32_PEAK_TFLOPS, "flop_per_cell_update": FLOP_PER_CELL_UPDATE,
                     "peak_note": "FP32 FMA peak without packed FP32 (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)",

@@ -83,6 +83,10 @@ __device__ __forceinline__ void step2_tile(const Step2Args& A2, int by, int bz) 
     const bool inrow = i < nx && j >= 0 && j < ny;
     const bool act = i >= 1 && i <= nx - 2 && j >= 1 && j <= ny - 2;  // interior in x and y
     const bool own = ty >= 1 && ty <= R - 2;                           // output rows
+    // the output rows carry both steps: issued first, they reach the second
+    // step while the halo rows still form the first, instead of running it
+    // alone at the end of each plane (2 % per step at 256^3)
+    if (own) __builtin_amdgcn_s_setprio(1);
     const int sxy = nx * ny;
     const int col = inrow ? i + nx * j : 0;
     // halo rows of the input plane: thread row 0 loads row y0 - 2 (LDS row 0),
