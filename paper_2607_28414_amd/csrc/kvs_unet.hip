@@ -49,6 +49,17 @@ struct Dims {
     __host__ __device__ long long n() const { return (long long)nx * ny * nz; }
 };
 
+// The network input x = bf16(fp32(in_scale r)): the scaled FP64 residual is
+// rounded to FP32, then to BF16 (nearest even at each step).  The FP32 value
+// goes through an empty asm statement; without it the compiler merges the two
+// conversions into one direct conversion from FP64, which rounds once (and
+// takes a nine-instruction round-to-odd sequence more per value).
+__device__ __forceinline__ bf16 bf16_via_f32(double x) {
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return (bf16)f;
+}
+
 // 16 bytes of zeros: the source of taps outside the grid in the gathering conv
 __device__ __attribute__((aligned(16))) bf16 kZeroRow[8];
 
@@ -728,7 +739,7 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
         for (int h = 0; h < FP_IPT; ++h) {
             const int i = t + 256 * h;
             if (h + 1 < FP_IPT || i < FP_ITEMS)
-                sl[(i / FP_RX) * FP_RS + i % FP_RX] = m[h] ? (bf16)(float)(in_scale * v[h]) : (bf16)0.f;
+                sl[(i / FP_RX) * FP_RS + i % FP_RX] = m[h] ? bf16_via_f32(in_scale * v[h]) : (bf16)0.f;
         }
     };
     double va[FP_IPT], vb[FP_IPT];
@@ -817,7 +828,7 @@ __global__ void pool0_edge_kernel(const double* __restrict__ r, NetCtl ctl, Dims
                 for (int tap = 0; tap < 27; ++tap) {
                     const int gx = x + tap_dx(tap), gy = y + tap_dy(tap), gzz = z + tap_dz(tap);
                     if (gx < 0 || gx >= d.nx || gy < 0 || gy >= d.ny || gzz < 0 || gzz >= d.nz) continue;
-                    const float xv = (float)(bf16)(float)(in_scale * r[((size_t)gzz * d.ny + gy) * d.nx + gx]);
+                    const float xv = (float)bf16_via_f32(in_scale * r[((size_t)gzz * d.ny + gy) * d.nx + gx]);
                     sum = fmaf((float)W0[ch * 32 + tap], xv, sum);
                 }
             }
@@ -930,7 +941,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void z
             const int i = t + 256 * h;
             if (h < 3 || i < ZO_NX) {
                 const int ic = min(i, ZO_NX - 1);
-                xb[(ic / ZO_RX) * ZO_RS + ic % ZO_RX] = xm[h] ? (float)(bf16)(float)(in_scale * xv[h]) : 0.f;
+                xb[(ic / ZO_RX) * ZO_RS + ic % ZO_RX] = xm[h] ? (float)bf16_via_f32(in_scale * xv[h]) : 0.f;
                 if (part) {
                     const int row = ic / ZO_RX - 2, col = ic % ZO_RX - 2;
                     if (row >= 0 && row < ZO_TY && col >= 0 && col < ZO_TX) rring[p & 3][row][col] = xm[h] ? xv[h] : 0.0;
@@ -944,7 +955,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void z
             ro0 = r_old[st0 ? zq : 0];
             ro1 = r_old[st1 ? zq + d.nx : 0];
         }
-        if (t < ZO_GN) gs[buf][t] = 0.75f * ga + 0.25f * gb;  // output plane p - 2
+        // output plane p - 2; the interpolations are written as explicit FMAs
+        // (0.25 x is exact, so each weighted pair is rounded once) rather than
+        // left to the compiler's contraction, which may pick either product
+        if (t < ZO_GN) gs[buf][t] = fmaf(0.75f, ga, 0.25f * gb);
         if (p + 1 <= ze + 1) {
 #pragma unroll
             for (int h = 0; h < 4; ++h) xload(p + 1, h, xv[h], xm[h]);
@@ -993,10 +1007,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void z
         const int o = p - 2;
         if (o >= zs && o < ze) {
             const float* g = gs[buf];
-            const float up0 = 0.75f * (0.75f * g[gI0 + gIx] + 0.25f * g[gI0 + gJx]) +
-                              0.25f * (0.75f * g[gJ0 + gIx] + 0.25f * g[gJ0 + gJx]);
-            const float up1 = 0.75f * (0.75f * g[gI1 + gIx] + 0.25f * g[gI1 + gJx]) +
-                              0.25f * (0.75f * g[gJ1 + gIx] + 0.25f * g[gJ1 + gJx]);
+            const float up0 = fmaf(0.75f, fmaf(0.75f, g[gI0 + gIx], 0.25f * g[gI0 + gJx]),
+                                   0.25f * fmaf(0.75f, g[gJ0 + gIx], 0.25f * g[gJ0 + gJx]));
+            const float up1 = fmaf(0.75f, fmaf(0.75f, g[gI1 + gIx], 0.25f * g[gI1 + gJx]),
+                                   0.25f * fmaf(0.75f, g[gJ1 + gIx], 0.25f * g[gJ1 + gJx]));
             const bool inz = o >= 1 && o <= d.nz - 2;
             const size_t zo = (size_t)o * sxy + (size_t)yo * d.nx + xo;
             const double z0 = in0 && inz ? out_scale * (double)(a0[0] + up0) : 0.0;
@@ -1055,7 +1069,7 @@ __global__ void e0_keep_kernel(const double* __restrict__ r, NetCtl ctl, Dims d,
     for (int tap = 0; tap < 27; ++tap) {
         const int gx = x + tap_dx(tap), gy = y + tap_dy(tap), gzz = zz + tap_dz(tap);
         const bool in = gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gzz >= 0 && gzz < d.nz;
-        xt[tap] = in ? (float)(bf16)(float)(in_scale * r[((size_t)gzz * d.ny + gy) * d.nx + gx]) : 0.f;
+        xt[tap] = in ? (float)bf16_via_f32(in_scale * r[((size_t)gzz * d.ny + gy) * d.nx + gx]) : 0.f;
     }
     for (int c0 = 0; c0 < 16; c0 += 8) {
         bf16x8 o;
@@ -1254,7 +1268,7 @@ __global__ __launch_bounds__(256) void dw_partial(const bf16* __restrict__ A, co
                 if (x >= 0 && x < d.nx && y >= 0 && y < d.ny && z >= 0 && z < d.nz) {
                     const long long p = x + (long long)d.nx * (y + (long long)d.ny * z);
                     if constexpr (FIRST) {
-                        val = (float)(bf16)(float)(in_scale * r[p]);
+                        val = (float)bf16_via_f32(in_scale * r[p]);
                     } else {
                         val = (float)A[p * CI + c];
                     }

@@ -130,6 +130,71 @@ def test_output_stencil_matches_oracle(kvs, dims):
     assert np.max(np.abs(z - zo)) <= 1e-5 * scale, np.max(np.abs(z - zo)) / scale
 
 
+def tie_inputs(rng, shape):
+    """Inputs on which the two readings of x = bf16(fp32(r)) differ: for even
+    BF16 values b (last mantissa bit 0), x lies above the midpoint between b
+    and its upper neighbour by a relative 2^-30, less than half an FP32 ulp.
+    FP32 rounds x to the midpoint, which BF16 rounds to the even b; a single
+    direct rounding from FP64 would give the upper neighbour instead.
+    Returns (b, x, upper neighbour)."""
+    f = rng.standard_normal(shape).astype(np.float32)
+    bits = f.view(np.uint32) & np.uint32(0xFFFE0000)
+    b = bits.view(np.float32).astype(np.float64)
+    mid = (bits | np.uint32(0x8000)).view(np.float32).astype(np.float64)
+    up = (bits + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    return b, mid * (1.0 + 2.0 ** -30), up
+
+
+def test_input_rounding_at_ties(kvs):
+    """The network input is rounded FP64 -> FP32 -> BF16, nearest even at each
+    step, as the oracle defines it (not FP64 -> BF16 in one rounding).  Every
+    interior input sits at a double-rounding tie (tie_inputs).  With only the
+    first and output layers non-zero the output is the composed stencil of x
+    alone, held to 1e-5 of max|z|; the full network (encoder input included)
+    is held to the forward bar 2e-3, against 5.8e-3 had every input been
+    rounded up."""
+    import torch
+    rng = np.random.default_rng(5)
+    nz, ny, nx = 22, 18, 26
+    b, x, up = tie_inputs(rng, (nz - 2, ny - 2, nx - 2))
+    assert np.array_equal(unet.bf16_round(np.float32(x)), b)
+    r = np.zeros((nz, ny, nx))
+    r[1:-1, 1:-1, 1:-1] = x
+    shapes = unet.layer_shapes(16, 32, 64, 4)
+    w_full = np.concatenate([rng.standard_normal(unet.layer_size(ci, co, dl)) / np.sqrt(unet.layer_taps(dl) * ci)
+                             for ci, co, dl in shapes]).astype(np.float32)
+    offs = np.cumsum([0] + [unet.layer_size(ci, co, dl) for ci, co, dl in shapes])
+    w_out = np.zeros_like(w_full)  # first and output layers only
+    for li in (0, len(shapes) - 1):
+        w_out[offs[li]:offs[li + 1]] = w_full[offs[li]:offs[li + 1]]
+    rd = torch.from_numpy(r).cuda()
+    for name, w, bar in (("output stencil", w_out, None), ("full network", w_full, 2e-3)):
+        say(f"case input ties {name}")
+        net = kvs.kvs_unet_create((16, 32, 64), 4)
+        try:
+            kvs.kvs_unet_set_weights(net, w)
+            zd = torch.full_like(rd, np.nan)
+            kvs.kvs_unet_forward(net, rd.data_ptr(), 1.0, 3.0, zd.data_ptr(), (nx, ny, nz),
+                                 torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            z = zd.cpu().numpy()
+        finally:
+            kvs.kvs_unet_destroy(net)
+        zo = unet.forward(r, 1.0, 3.0, w.astype(np.float64), nbott=4)
+        assert np.isfinite(z).all()
+        if bar is None:
+            scale = np.abs(zo).max()
+            assert np.max(np.abs(z - zo)) <= 1e-5 * scale, np.max(np.abs(z - zo)) / scale
+        else:
+            ru = np.zeros_like(r)
+            ru[1:-1, 1:-1, 1:-1] = up
+            zu = unet.forward(ru, 1.0, 3.0, w.astype(np.float64), nbott=4)
+            assert np.linalg.norm(zu - zo) / np.linalg.norm(zo) > 2 * bar
+            err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+            say(f"full network at ties: rel L2 {err:.2e}")
+            assert err < bar
+
+
 def random_weights(rng, nbott=4, scale=1.0):
     shapes = unet.layer_shapes(16, 32, 64, nbott)
     return np.concatenate([scale * rng.standard_normal(unet.layer_size(ci, co, dl)) / np.sqrt(unet.layer_taps(dl) * ci)
