@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -574,6 +575,10 @@ kvs_status kvs_set_probes(kvs_ctx* c, const int64_t* ijk, int64_t n, int32_t com
             }
             int& off = rowtab[(size_t)(j + g.ny * k)];
             if (off < 0) {
+                if (ptab.size() + (size_t)g.nx > (size_t)INT_MAX) {
+                    rows_ok = false;  // offsets are 32-bit on the device
+                    break;
+                }
                 off = (int)ptab.size();
                 ptab.resize(ptab.size() + (size_t)g.nx, -1);
             }
@@ -1326,6 +1331,10 @@ static kvs_status batch_upload_probes2(kvs_batch* b) {
             }
             int& off = row[(size_t)(y + g.ny * z)];
             if (off < 0) {
+                if (ptab.size() + (size_t)g.nx > (size_t)INT_MAX) {
+                    b->probes2_ok = false;  // offsets are 32-bit on the device
+                    break;
+                }
                 off = (int)ptab.size();
                 ptab.resize(ptab.size() + (size_t)g.nx, -1);
             }
