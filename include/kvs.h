@@ -215,6 +215,14 @@ kvs_status kvs_set_envelope(kvs_ctx* ctx, const double* g, int64_t n_env);
  * KVS_EBREAKDOWN); f_S is produced in every case but EBREAKDOWN.  `report`
  * may be NULL. */
 kvs_status kvs_project(kvs_ctx* ctx, const kvs_solve_opts* opts, kvs_solve_report* report);
+/* Storage of the search direction p of the projection's CG (Sec. 3.2.3): KVS_FP64 or KVS_FP32
+ * (other values: KVS_EINVAL); default: the context's state precision.  The residual r and phi
+ * stay FP64 and are both updated with the stored direction, so r stays the residual of phi to
+ * FP64 rounding and the stop rule, the inner products and the norms are as before; only the
+ * direction is rounded to FP32, which the iteration absorbs like any other choice of
+ * direction.  The two CG sweeps then move 52 instead of 64 B per cell and iteration.  Applies
+ * from the next kvs_project. */
+kvs_status kvs_set_direction_precision(kvs_ctx* ctx, int32_t prec);
 /* Network used by kvs_project with precond = KVS_PC_UNET (flexible PCG:
  * z = U(r) with the network's input scaled to unit RMS of r and its output
  * by h^2 rms(r); beta = z_{k+1}.(r_{k+1} - r_k) / (z_k.r_k); when z.r <= 0

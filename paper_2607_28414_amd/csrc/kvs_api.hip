@@ -220,6 +220,7 @@ kvs_status kvs_create(const kvs_grid* grid, const kvs_opts* opts, kvs_ctx** out)
     c->grid = g;
     c->N = g.nx * g.ny * g.nz;
     c->prec = o.precision;
+    c->dir_prec = o.precision;
     c->device = o.device;
     c->sponge_cells = o.sponge_cells;
     c->sigma_user = o.sponge_sigma_max;
@@ -1134,6 +1135,14 @@ kvs_status kvs_set_step_blocking(kvs_ctx* c, int32_t steps) {
     if (!c) return KVS_EINVAL;
     if (steps != 1 && steps != 2) return fail(c, KVS_EINVAL, "steps per launch must be 1 or 2");
     c->step_block = steps;
+    return KVS_OK;
+}
+
+kvs_status kvs_set_direction_precision(kvs_ctx* c, int32_t prec) {
+    if (!c) return KVS_EINVAL;
+    if (prec != KVS_FP64 && prec != KVS_FP32) return fail(c, KVS_EINVAL, "direction precision must be FP64 or FP32");
+    if (prec != c->dir_prec) c->p_dirty = true;
+    c->dir_prec = prec;
     return KVS_OK;
 }
 

@@ -251,9 +251,9 @@ __device__ __forceinline__ void sweep_partials(double v0, double v1, double* par
 // sweep 1: p' = z + beta p, A p' = -lap p', partial p'.Ap'.  z = zs * src
 // with src = r (CG: zs = 1, Jacobi: zs = 1/diag) or, in flexible PCG, the
 // network output zf (zs = 1) unless this iteration fell back to Jacobi.
-template <int WX, int SBY>
+template <int WX, int SBY, typename PT>
 __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const double* r_in,
-                                                               const double* zf, const double* p_old, double* p_new,
+                                                               const double* zf, const PT* p_old, PT* p_new,
                                                                const CgState* st, double* partials, int npart) {
     if (st->done) return;
     __shared__ double lds[2][SBY + 3][64 * WX + 4];
@@ -265,7 +265,9 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, c
     const double* r = net_z ? zf : r_in;
     const double zs = (st->jacobi || (st->flexible && st->zjacobi)) ? g.dinv : 1.0;
     const bool first = beta == 0.0;
-    auto pv = [&](double rv, double po) { return first ? rv * zs : rv * zs + beta * po; };
+    // the new direction as stored (PT = float: rounded once); the stencil,
+    // p.Ap and the update sweep all use this stored value
+    auto pv = [&](double rv, double po) { return (double)(PT)(first ? rv * zs : rv * zs + beta * po); };
     const int kb = L.kb, ke = L.ke;
     double pm = pv(r[(kb - 1) * sxy + L.col], p_old[(kb - 1) * sxy + L.col]);
     double pc = pv(r[kb * sxy + L.col], p_old[kb * sxy + L.col]);
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, c
                             + (lds[buf][ty + 2][tx + 1] + lds[buf][ty][tx + 1] - c2) * g.ihy2
                             + (pp + pm - c2) * g.ihz2);
         s1 += L.act ? pc * ap : 0.0;
-        __builtin_nontemporal_store(L.act ? pc : 0.0, p_new + k * sxy + L.scol);
+        __builtin_nontemporal_store(L.act ? (PT)pc : (PT)0, p_new + k * sxy + L.scol);
         pm = pc;
         pc = pp;
         pp = pv(rn, on);
@@ -299,9 +301,9 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, c
 
 // sweep 2: A p recomputed, phi += alpha p, r_out = r - alpha A p (r_out may
 // be r itself), partials r.r, r.z
-template <int WX, int SBY>
+template <int WX, int SBY, typename PT>
 __global__ __launch_bounds__(64 * WX * SBY) void cg_upd_kernel(const CgGeom g, const SweepGeom sg, double* phi,
-                                                               const double* r, double* r_out, const double* p,
+                                                               const double* r, double* r_out, const PT* p,
                                                                const CgState* st, double* partials, int npart) {
     if (st->done) return;
     __shared__ double lds[2][SBY + 3][64 * WX + 4];
@@ -598,6 +600,7 @@ struct CgBuffers {
     kvs_unet* net;
     bool warm;
     bool use_events;  // time with HIP events (else with the host clock)
+    bool dir_fp32;    // p[] hold FP32 directions (the first half of each buffer)
 };
 
 __global__ void fill_zero_kernel(double* a, long long n) {
@@ -652,36 +655,55 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
     sg.gx = (g.nx + 64 * shp.wx - 1) / (64 * shp.wx);
     sg.gy = (g.ny + shp.by - 1) / shp.by;
     {
-        static const int cap1 = kvs_tiling::resident_blocks(cg_dir_kernel<1, 8>, 512);
-        static const int cap2 = kvs_tiling::resident_blocks(cg_dir_kernel<2, 8>, 1024);
-        static const int cap4 = kvs_tiling::resident_blocks(cg_dir_kernel<4, 4>, 1024);
+        static const int cap1 = kvs_tiling::resident_blocks(cg_dir_kernel<1, 8, double>, 512);
+        static const int cap2 = kvs_tiling::resident_blocks(cg_dir_kernel<2, 8, double>, 1024);
+        static const int cap4 = kvs_tiling::resident_blocks(cg_dir_kernel<4, 4, double>, 1024);
         const int cap = shp.wx == 4 ? cap4 : (shp.wx == 2 ? cap2 : cap1);
         sg.kchunk = kvs_tiling::choose_kchunk(sg.gx * sg.gy, g.nz - 2, cap);
         sg.gz = (g.nz - 2 + sg.kchunk - 1) / sg.kchunk;
     }
     const int nbs = sg.gx * sg.gy * sg.gz;
     const dim3 sblk(64 * shp.wx, shp.by);
-    auto launch_dir = [&](const double* r_in, const double* zf, const double* p_old, double* p_new) {
+    // the direction buffers hold PT values (B.dir_fp32: float)
+    auto launch_dir_t = [&](auto tag, const double* r_in, const double* zf, const double* p_old_buf,
+                            double* p_new_buf) {
+        using PT = decltype(tag);
+        const PT* p_old = reinterpret_cast<const PT*>(p_old_buf);
+        PT* p_new = reinterpret_cast<PT*>(p_new_buf);
         if (shp.wx == 4)
-            hipLaunchKernelGGL((cg_dir_kernel<4, 4>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
+            hipLaunchKernelGGL((cg_dir_kernel<4, 4, PT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
                                B.cgs, part, npart);
         else if (shp.wx == 2)
-            hipLaunchKernelGGL((cg_dir_kernel<2, 8>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
+            hipLaunchKernelGGL((cg_dir_kernel<2, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
                                B.cgs, part, npart);
         else
-            hipLaunchKernelGGL((cg_dir_kernel<1, 8>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
+            hipLaunchKernelGGL((cg_dir_kernel<1, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
                                B.cgs, part, npart);
     };
-    auto launch_upd = [&](const double* r_in, double* r_out, const double* pv) {
+    auto launch_upd_t = [&](auto tag, const double* r_in, double* r_out, const double* p_buf) {
+        using PT = decltype(tag);
+        const PT* pv = reinterpret_cast<const PT*>(p_buf);
         if (shp.wx == 4)
-            hipLaunchKernelGGL((cg_upd_kernel<4, 4>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
+            hipLaunchKernelGGL((cg_upd_kernel<4, 4, PT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
                                B.cgs, part, npart);
         else if (shp.wx == 2)
-            hipLaunchKernelGGL((cg_upd_kernel<2, 8>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
+            hipLaunchKernelGGL((cg_upd_kernel<2, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
                                B.cgs, part, npart);
         else
-            hipLaunchKernelGGL((cg_upd_kernel<1, 8>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
+            hipLaunchKernelGGL((cg_upd_kernel<1, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
                                B.cgs, part, npart);
+    };
+    auto launch_dir = [&](const double* r_in, const double* zf, const double* p_old, double* p_new) {
+        if (B.dir_fp32)
+            launch_dir_t(float{}, r_in, zf, p_old, p_new);
+        else
+            launch_dir_t(double{}, r_in, zf, p_old, p_new);
+    };
+    auto launch_upd = [&](const double* r_in, double* r_out, const double* pv) {
+        if (B.dir_fp32)
+            launch_upd_t(float{}, r_in, r_out, pv);
+        else
+            launch_upd_t(double{}, r_in, r_out, pv);
     };
     int pi = 0;  // p[pi] holds the current search direction
     const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
@@ -849,6 +871,17 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     B.net = c->net;
     B.warm = o->warm_start && c->have_phi;
     B.use_events = true;
+    B.dir_fp32 = c->dir_prec == KVS_FP32;
+    if (c->p_dirty) {
+        for (double* v : {c->p[0], c->p[1]}) {
+            const hipError_t e = fill_zero(v, (long long)c->N, c->stream);
+            if (e != hipSuccess) {
+                c->err = std::string("fill_zero_kernel: ") + hipGetErrorString(e);
+                return KVS_EDEVICE;
+            }
+        }
+        c->p_dirty = false;
+    }
     CgErr err;
     const kvs_status st = cg_project(B, o, rep, err);
     if (st == KVS_EDEVICE && err.hip) {  // a HIP failure: the solve did not finish

@@ -161,6 +161,12 @@ struct kvs_ctx {
     int step_remap = 1;
     // steps per launch where the two-step kernel applies (1 or 2)
     int step_block = 2;
+    // storage of the projection's CG search direction (KVS_FP64 or KVS_FP32;
+    // set to the state precision at creation); p_dirty: both direction
+    // buffers are cleared before the next solve (after a change, the other
+    // width's view would find the last solve's values on its outer planes)
+    int dir_prec = 0;
+    bool p_dirty = false;
     // when set, the next step-kernel launch records its own start and end in
     // these events (the dispatch's timestamps, no extra queue packets)
     hipEvent_t launch_ev[2] = {nullptr, nullptr};
