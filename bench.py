@@ -1184,7 +1184,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"heterogeneous inclusions {n}^3, dx 0.25 mm, 12 spheres, Gaussian push 100 us, "
-                        f"dt 0.4 x stable limit, {nsteps} FDTD steps, FP32 state + Jacobi-PCG projection to 1e-8 (FP64 residual, potential and inner products, FP32 search direction)",
+                        f"dt 0.4 x stable limit, {nsteps} FDTD steps, FP32 state + Jacobi-PCG projection to 1e-8 (FP64 potential, inner products and true residual; FP32 search direction and recursive residual with reliable updates)",
             "grid": [n, n, n],
             "fdtd_steps": nsteps,
             "interior_cells": cells,

@@ -221,6 +221,7 @@ kvs_status kvs_create(const kvs_grid* grid, const kvs_opts* opts, kvs_ctx** out)
     c->N = g.nx * g.ny * g.nz;
     c->prec = o.precision;
     c->dir_prec = o.precision;
+    c->res_prec = o.precision;
     c->device = o.device;
     c->sponge_cells = o.sponge_cells;
     c->sigma_user = o.sponge_sigma_max;
@@ -1143,6 +1144,13 @@ kvs_status kvs_set_direction_precision(kvs_ctx* c, int32_t prec) {
     if (prec != KVS_FP64 && prec != KVS_FP32) return fail(c, KVS_EINVAL, "direction precision must be FP64 or FP32");
     if (prec != c->dir_prec) c->p_dirty = true;
     c->dir_prec = prec;
+    return KVS_OK;
+}
+
+kvs_status kvs_set_residual_precision(kvs_ctx* c, int32_t prec) {
+    if (!c) return KVS_EINVAL;
+    if (prec != KVS_FP64 && prec != KVS_FP32) return fail(c, KVS_EINVAL, "residual precision must be FP64 or FP32");
+    c->res_prec = prec;
     return KVS_OK;
 }
 

@@ -52,7 +52,7 @@ struct CgGeom {
     double dinv;              // 1/diag(A)
 };
 
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3, FIN_FZ0 = 4, FIN_FBETA = 5, FIN_RESTART = 6 };
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_TRUE = 3, FIN_FZ0 = 4, FIN_FBETA = 5, FIN_RESTART = 6, FIN_REPLACE = 7 };
 
 using kvs_tiling::tile_of;
 
@@ -127,8 +127,11 @@ __device__ __forceinline__ double negative_lap_at(const CgGeom& g, const double*
 }
 
 // r0 = -b - A phi0 (warm) or -b; partials of r.r, r.z, b.b
+// r = -b (- A phi when warm) in FP64, stored as RT (float: the FP32
+// residual of the plain CG, whose sums are of the stored values)
+template <typename RT>
 __global__ __launch_bounds__(64 * CBY) void cg_init_kernel(const CgGeom g, const double* F, const double* phi,
-                                                           double* r, int warm, double* partials, int npart) {
+                                                           RT* r, int warm, double* partials, int npart) {
     const Tile t = tile_coords(g);
     const int sxy = g.nx * g.ny;
     double s1 = 0, s2 = 0, s3 = 0;
@@ -138,7 +141,8 @@ __global__ __launch_bounds__(64 * CBY) void cg_init_kernel(const CgGeom g, const
             const double b = div_at(g, F, idx);
             double rv = -b;
             if (warm) rv -= negative_lap_at(g, phi, idx);
-            r[idx] = rv;
+            rv = (double)(RT)rv;
+            r[idx] = (RT)rv;
             s1 += rv * rv;
             s2 += rv * (rv * g.dinv);
             s3 += b * b;
@@ -251,8 +255,8 @@ __device__ __forceinline__ void sweep_partials(double v0, double v1, double* par
 // sweep 1: p' = z + beta p, A p' = -lap p', partial p'.Ap'.  z = zs * src
 // with src = r (CG: zs = 1, Jacobi: zs = 1/diag) or, in flexible PCG, the
 // network output zf (zs = 1) unless this iteration fell back to Jacobi.
-template <int WX, int SBY, typename PT>
-__global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const double* r_in,
+template <int WX, int SBY, typename PT, typename RT>
+__global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const RT* r_in,
                                                                const double* zf, const PT* p_old, PT* p_new,
                                                                const CgState* st, double* partials, int npart) {
     if (st->done) return;
@@ -262,7 +266,9 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, c
     const int sxy = g.nx * g.ny;
     const double beta = st->beta;
     const bool net_z = st->flexible && !st->zjacobi;
-    const double* r = net_z ? zf : r_in;
+    // flexible PCG keeps r in FP64 (RT = double), so zf and r_in then have
+    // the same type; an FP32 residual is only launched for the plain CG
+    const RT* r = net_z ? reinterpret_cast<const RT*>(zf) : r_in;
     const double zs = (st->jacobi || (st->flexible && st->zjacobi)) ? g.dinv : 1.0;
     const bool first = beta == 0.0;
     // the new direction as stored (PT = float: rounded once); the stencil,
@@ -301,9 +307,9 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, c
 
 // sweep 2: A p recomputed, phi += alpha p, r_out = r - alpha A p (r_out may
 // be r itself), partials r.r, r.z
-template <int WX, int SBY, typename PT>
+template <int WX, int SBY, typename PT, typename RT>
 __global__ __launch_bounds__(64 * WX * SBY) void cg_upd_kernel(const CgGeom g, const SweepGeom sg, double* phi,
-                                                               const double* r, double* r_out, const PT* p,
+                                                               const RT* r, RT* r_out, const PT* p,
                                                                const CgState* st, double* partials, int npart) {
     if (st->done) return;
     __shared__ double lds[2][SBY + 3][64 * WX + 4];
@@ -334,10 +340,10 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_upd_kernel(const CgGeom g, c
                             + (lds[buf][ty + 2][tx + 1] + lds[buf][ty][tx + 1] - c2) * g.ihy2
                             + (pp + pm - c2) * g.ihz2);
         const double phv = phc + alpha * pc;
-        const double rv = rc - alpha * ap;
+        const double rv = (double)(RT)(rc - alpha * ap);  // as stored
         const int q = k * sxy + L.scol;
         __builtin_nontemporal_store(L.act ? phv : 0.0, phi + q);
-        __builtin_nontemporal_store(L.act ? rv : 0.0, r_out + q);
+        __builtin_nontemporal_store(L.act ? (RT)rv : (RT)0, r_out + q);
         s1 += L.act ? rv * rv : 0.0;
         s2 += L.act ? rv * (rv * g.dinv) : 0.0;
         pm = pc;
@@ -519,6 +525,20 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
             st->done = 1;
         }
         set_net_scales(s1);
+    } else if (mode == FIN_REPLACE) {
+        // reliable update of the FP32 residual: the recursive r was replaced
+        // by the true residual -b - A phi; the direction is kept and beta,
+        // formed from the recursive z.r, is rescaled to the new one
+        const double rz_new = st->jacobi ? s2 : s1;
+        if (!isfinite(s1) || !isfinite(rz_new) || !(st->rz > 0.0)) {
+            st->status = KVS_EBREAKDOWN;
+            st->done = 1;
+            return;
+        }
+        st->beta *= rz_new / st->rz;
+        st->rz = rz_new;
+        st->rr = s1;
+        if (st->fixed_iters <= 0 && sqrt(st->rr / st->bb) < sqrt(st->tol2)) st->done = 1;
     } else {  // FIN_TRUE
         st->relres_true2 = s3 > 0.0 ? s1 / s3 : 0.0;
     }
@@ -601,6 +621,7 @@ struct CgBuffers {
     bool warm;
     bool use_events;  // time with HIP events (else with the host clock)
     bool dir_fp32;    // p[] hold FP32 directions (the first half of each buffer)
+    bool res_fp32;    // r holds an FP32 residual (plain CG / Jacobi-PCG only)
 };
 
 __global__ void fill_zero_kernel(double* a, long long n) {
@@ -646,7 +667,17 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
     const bool warm = B.warm;
     if (!warm) CG_HIP(fill_zero(B.phi, g.N, stream));
 
-    hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, stream, g, B.F, B.phi, B.r, warm ? 1 : 0, part, npart);
+    // the residual buffers hold FP32 values for the plain CG with B.res_fp32
+    const bool res32 = B.res_fp32 && !flexible;
+    auto launch_init = [&](double* rbuf, int warm_flag) {
+        if (res32)
+            hipLaunchKernelGGL(cg_init_kernel<float>, dim3(nb), blk, 0, stream, g, B.F, B.phi,
+                               reinterpret_cast<float*>(rbuf), warm_flag, part, npart);
+        else
+            hipLaunchKernelGGL(cg_init_kernel<double>, dim3(nb), blk, 0, stream, g, B.F, B.phi, rbuf, warm_flag, part,
+                               npart);
+    };
+    launch_init(B.r, warm ? 1 : 0);
     hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nb, npart, 3, (int)FIN_INIT, B.cgs);
     CG_HIP(hipGetLastError());
 
@@ -655,55 +686,69 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
     sg.gx = (g.nx + 64 * shp.wx - 1) / (64 * shp.wx);
     sg.gy = (g.ny + shp.by - 1) / shp.by;
     {
-        static const int cap1 = kvs_tiling::resident_blocks(cg_dir_kernel<1, 8, double>, 512);
-        static const int cap2 = kvs_tiling::resident_blocks(cg_dir_kernel<2, 8, double>, 1024);
-        static const int cap4 = kvs_tiling::resident_blocks(cg_dir_kernel<4, 4, double>, 1024);
+        static const int cap1 = kvs_tiling::resident_blocks(cg_dir_kernel<1, 8, double, double>, 512);
+        static const int cap2 = kvs_tiling::resident_blocks(cg_dir_kernel<2, 8, double, double>, 1024);
+        static const int cap4 = kvs_tiling::resident_blocks(cg_dir_kernel<4, 4, double, double>, 1024);
         const int cap = shp.wx == 4 ? cap4 : (shp.wx == 2 ? cap2 : cap1);
         sg.kchunk = kvs_tiling::choose_kchunk(sg.gx * sg.gy, g.nz - 2, cap);
         sg.gz = (g.nz - 2 + sg.kchunk - 1) / sg.kchunk;
     }
     const int nbs = sg.gx * sg.gy * sg.gz;
     const dim3 sblk(64 * shp.wx, shp.by);
-    // the direction buffers hold PT values (B.dir_fp32: float)
-    auto launch_dir_t = [&](auto tag, const double* r_in, const double* zf, const double* p_old_buf,
+    // the direction buffers hold PT values (B.dir_fp32: float), the residual
+    // buffers RT values (res32: float)
+    auto launch_dir_t = [&](auto ptag, auto rtag, const double* r_buf, const double* zf, const double* p_old_buf,
                             double* p_new_buf) {
-        using PT = decltype(tag);
+        using PT = decltype(ptag);
+        using RT = decltype(rtag);
+        const RT* r_in = reinterpret_cast<const RT*>(r_buf);
         const PT* p_old = reinterpret_cast<const PT*>(p_old_buf);
         PT* p_new = reinterpret_cast<PT*>(p_new_buf);
         if (shp.wx == 4)
-            hipLaunchKernelGGL((cg_dir_kernel<4, 4, PT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
-                               B.cgs, part, npart);
+            hipLaunchKernelGGL((cg_dir_kernel<4, 4, PT, RT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old,
+                               p_new, B.cgs, part, npart);
         else if (shp.wx == 2)
-            hipLaunchKernelGGL((cg_dir_kernel<2, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
-                               B.cgs, part, npart);
+            hipLaunchKernelGGL((cg_dir_kernel<2, 8, PT, RT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old,
+                               p_new, B.cgs, part, npart);
         else
-            hipLaunchKernelGGL((cg_dir_kernel<1, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old, p_new,
-                               B.cgs, part, npart);
+            hipLaunchKernelGGL((cg_dir_kernel<1, 8, PT, RT>), dim3(nbs), sblk, 0, stream, g, sg, r_in, zf, p_old,
+                               p_new, B.cgs, part, npart);
     };
-    auto launch_upd_t = [&](auto tag, const double* r_in, double* r_out, const double* p_buf) {
-        using PT = decltype(tag);
+    auto launch_upd_t = [&](auto ptag, auto rtag, const double* r_buf, double* r_out_buf, const double* p_buf) {
+        using PT = decltype(ptag);
+        using RT = decltype(rtag);
+        const RT* r_in = reinterpret_cast<const RT*>(r_buf);
+        RT* r_out = reinterpret_cast<RT*>(r_out_buf);
         const PT* pv = reinterpret_cast<const PT*>(p_buf);
         if (shp.wx == 4)
-            hipLaunchKernelGGL((cg_upd_kernel<4, 4, PT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
-                               B.cgs, part, npart);
+            hipLaunchKernelGGL((cg_upd_kernel<4, 4, PT, RT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out,
+                               pv, B.cgs, part, npart);
         else if (shp.wx == 2)
-            hipLaunchKernelGGL((cg_upd_kernel<2, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
-                               B.cgs, part, npart);
+            hipLaunchKernelGGL((cg_upd_kernel<2, 8, PT, RT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out,
+                               pv, B.cgs, part, npart);
         else
-            hipLaunchKernelGGL((cg_upd_kernel<1, 8, PT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out, pv,
-                               B.cgs, part, npart);
+            hipLaunchKernelGGL((cg_upd_kernel<1, 8, PT, RT>), dim3(nbs), sblk, 0, stream, g, sg, B.phi, r_in, r_out,
+                               pv, B.cgs, part, npart);
     };
     auto launch_dir = [&](const double* r_in, const double* zf, const double* p_old, double* p_new) {
-        if (B.dir_fp32)
-            launch_dir_t(float{}, r_in, zf, p_old, p_new);
+        if (B.dir_fp32 && res32)
+            launch_dir_t(float{}, float{}, r_in, zf, p_old, p_new);
+        else if (B.dir_fp32)
+            launch_dir_t(float{}, double{}, r_in, zf, p_old, p_new);
+        else if (res32)
+            launch_dir_t(double{}, float{}, r_in, zf, p_old, p_new);
         else
-            launch_dir_t(double{}, r_in, zf, p_old, p_new);
+            launch_dir_t(double{}, double{}, r_in, zf, p_old, p_new);
     };
     auto launch_upd = [&](const double* r_in, double* r_out, const double* pv) {
-        if (B.dir_fp32)
-            launch_upd_t(float{}, r_in, r_out, pv);
+        if (B.dir_fp32 && res32)
+            launch_upd_t(float{}, float{}, r_in, r_out, pv);
+        else if (B.dir_fp32)
+            launch_upd_t(float{}, double{}, r_in, r_out, pv);
+        else if (res32)
+            launch_upd_t(double{}, float{}, r_in, r_out, pv);
         else
-            launch_upd_t(double{}, r_in, r_out, pv);
+            launch_upd_t(double{}, double{}, r_in, r_out, pv);
     };
     int pi = 0;  // p[pi] holds the current search direction
     const long long cap = (o->fixed_iters > 0 ? o->fixed_iters : o->max_iter) + 1;
@@ -725,9 +770,16 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
     }
     // Iterate until the device sets the stop flag (tolerance on the recursive
     // residual, max_iter, fixed_iters or a breakdown).
+    // Reliable updates of an FP32 residual: its rounding at every update
+    // makes the recursive r drift from -b - A phi by about 6e-8 of the
+    // largest |r| since it was last exact, so whenever r.r has fallen by
+    // kReplace since then (checked where the host reads the state), r is
+    // recomputed from phi in FP64 and beta rescaled to it (FIN_REPLACE).
+    constexpr double kReplace = 1e-4;  // r.r ratio: |r| down by 100
     auto iterate = [&]() -> kvs_status {
         int chunk = flexible ? 2 : 4;
         long long launched = 0;
+        double rr_ref = -1.0;  // r.r when r was last exact (first read of this call)
         while (true) {
             for (int m = 0; m < chunk; ++m) {
                 launch_dir(rb[ri], z, B.p[pi], B.p[1 - pi]);
@@ -754,6 +806,17 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
             CG_HIP(hipStreamSynchronize(stream));
             if (B.cgs_host->done) break;
             if (launched > cap) return cg_fail(err, KVS_EDEVICE, "CG: iteration cap passed without a stop flag");
+            if (res32) {
+                if (rr_ref < 0.0) {
+                    rr_ref = B.cgs_host->rr;
+                } else if (B.cgs_host->rr < kReplace * rr_ref) {
+                    launch_init(rb[ri], 1);
+                    hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nb, npart, 3,
+                                       (int)FIN_REPLACE, B.cgs);
+                    CG_HIP(hipGetLastError());
+                    rr_ref = B.cgs_host->rr;
+                }
+            }
             chunk = std::min(chunk * 2, flexible ? 8 : 64);
         }
         return KVS_OK;
@@ -773,7 +836,7 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
     // changes between iterations; on request for CG / Jacobi-PCG): when the
     // recursive residual met tol but ||-b - A phi|| / ||b|| did not, restart
     // from the true residual and continue, counting iterations on.
-    const bool confirm = (flexible || o->confirm_true) && o->fixed_iters <= 0;
+    const bool confirm = (flexible || res32 || o->confirm_true) && o->fixed_iters <= 0;
     for (int restarts = 0;; ++restarts) {
         hipLaunchKernelGGL(cg_true_residual_kernel, dim3(nb), blk, 0, stream, g, B.F, B.phi, part, npart);
         hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nb, npart, 3, (int)FIN_TRUE,
@@ -786,7 +849,7 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
         if (h.status != KVS_OK || h.bb == 0.0 || !(h.relres_true2 >= h.tol2) || h.iters >= h.max_iter ||
             restarts >= 8)
             break;
-        hipLaunchKernelGGL(cg_init_kernel, dim3(nb), blk, 0, stream, g, B.F, B.phi, rb[ri], 1, part, npart);
+        launch_init(rb[ri], 1);
         hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nb, npart, 3, (int)FIN_RESTART,
                            B.cgs);
         if (flexible) {
@@ -872,6 +935,18 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     B.warm = o->warm_start && c->have_phi;
     B.use_events = true;
     B.dir_fp32 = c->dir_prec == KVS_FP32;
+    B.res_fp32 = c->res_prec == KVS_FP32;
+    // the residual buffer's outer layer is read as zeros by the sweeps: clear
+    // it when this solve views it at the other width than the last one
+    const bool r32 = B.res_fp32 && o->precond != KVS_PC_UNET;
+    if (r32 != c->r_view32) {
+        const hipError_t e = fill_zero(c->r, (long long)c->N, c->stream);
+        if (e != hipSuccess) {
+            c->err = std::string("fill_zero_kernel: ") + hipGetErrorString(e);
+            return KVS_EDEVICE;
+        }
+        c->r_view32 = r32;
+    }
     if (c->p_dirty) {
         for (double* v : {c->p[0], c->p[1]}) {
             const hipError_t e = fill_zero(v, (long long)c->N, c->stream);

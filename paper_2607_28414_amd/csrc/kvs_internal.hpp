@@ -167,6 +167,10 @@ struct kvs_ctx {
     // width's view would find the last solve's values on its outer planes)
     int dir_prec = 0;
     bool p_dirty = false;
+    // storage of the residual of the plain CG / Jacobi-PCG (the flexible PCG
+    // keeps it in FP64); r_view32: the last solve viewed r as FP32
+    int res_prec = 0;
+    bool r_view32 = false;
     // when set, the next step-kernel launch records its own start and end in
     // these events (the dispatch's timestamps, no extra queue packets)
     hipEvent_t launch_ev[2] = {nullptr, nullptr};

@@ -194,6 +194,7 @@ SIGNATURES = {
     "kvs_autotune_step": ([_P, C.c_int32, C.POINTER(C.c_int32), _D, C.c_int32], C.c_int),
     "kvs_set_step_blocking": ([_P, C.c_int32], C.c_int),
     "kvs_set_direction_precision": ([_P, C.c_int32], C.c_int),
+    "kvs_set_residual_precision": ([_P, C.c_int32], C.c_int),
     "kvs_kernel_time_split": ([_P, _D, C.POINTER(C.c_int64)], C.c_int),
     "kvs_batch_set_step_blocking": ([_P, C.c_int32], C.c_int),
     "kvs_batch_step_blocking_applies": ([_P], C.c_int32),
@@ -558,6 +559,11 @@ def kvs_set_step_blocking(ctx, steps):
 def kvs_set_direction_precision(ctx, precision):
     """Storage of the projection's CG search direction (KVS_FP64 or KVS_FP32)."""
     _check(lib().kvs_set_direction_precision(ctx, int(precision)), ctx)
+
+
+def kvs_set_residual_precision(ctx, precision):
+    """Storage of the plain CG's residual (KVS_FP64 or KVS_FP32, reliable updates)."""
+    _check(lib().kvs_set_residual_precision(ctx, int(precision)), ctx)
 
 
 def kvs_step_blocking_applies(ctx):

@@ -154,11 +154,14 @@ def test_cfg2_full_size_traces_within_2e5(kvs, cfg2_oracle):
         kvs.kvs_set_probes(ctx, w.probes, w.comp)
         variant, _ = kvs.kvs_autotune_step(ctx, 10)
         kvs.kvs_set_force(ctx, w.F)
-        # the oracle's algorithm (FP64 directions) first, then the benchmark's
-        # (the FP32 context's default, FP32 directions), whose f_S is stepped
+        # the oracle's algorithm (FP64 direction and residual) first, then the
+        # benchmark's (the FP32 context's default, FP32 storage of both),
+        # whose f_S is stepped
         kvs.kvs_set_direction_precision(ctx, kvs.KVS_FP64)
+        kvs.kvs_set_residual_precision(ctx, kvs.KVS_FP64)
         rep64 = kvs.kvs_project(ctx, tol=w.tol, max_iter=20000, precond=kvs.KVS_PC_JACOBI)
         kvs.kvs_set_direction_precision(ctx, kvs.KVS_FP32)
+        kvs.kvs_set_residual_precision(ctx, kvs.KVS_FP32)
         rep = kvs.kvs_project(ctx, tol=w.tol, max_iter=20000, precond=kvs.KVS_PC_JACOBI)
         kvs.kvs_step(ctx, nsteps)
         tr = kvs.kvs_read_traces(ctx, len(w.probes), 1)
@@ -169,11 +172,11 @@ def test_cfg2_full_size_traces_within_2e5(kvs, cfg2_oracle):
     _, _, tr_o = oracle.run(w.grid, w.G, w.rho, w.eta, dt, nsteps, FS=FS_o, env=env, probes=w.probes, comp=w.comp,
                             sponge_cells=w.sponge_cells, sigma_max=smax_o)
     err = rel_l2(tr, tr_o)
-    say(f"cfg2 traces: oracle projection {rep_o['iters']} iterations, GPU with FP64 directions "
-        f"{rep64['iters']}; trace rel L2 {err:.3e}")
+    say(f"cfg2 traces: oracle projection {rep_o['iters']} iterations, GPU with FP64 storage "
+        f"{rep64['iters']}, with FP32 storage {rep['iters']}; trace rel L2 {err:.3e}")
     assert rep64["iters"] == rep_o["iters"]
-    # FP32 directions: the same stop rule on an exact FP64 residual, 1 % more
-    # iterations measured (904 against 894)
+    # FP32 storage: the tolerance on the true residual, 1 % more iterations
+    # measured (904 against 894)
     assert rep["relres_true"] < w.tol and abs(rep["iters"] - rep_o["iters"]) <= 0.03 * rep_o["iters"]
     assert err <= 2e-5
 
@@ -185,9 +188,9 @@ def test_cfg2_full_length_traces_against_stored_oracle_run(kvs):
     u_z traces of 32 of the probes against the oracle's own end-to-end FP64
     run (tests/golden/make_cfg2.py), relative L2 within 2e-5 over the whole
     run and within each 1000-step window; the stable dt, sponge strength and
-    push length equal the oracle's, the projection (FP32 directions, the
-    benchmark's) meets the tolerance on the true residual within 3 % of the
-    oracle's iteration count."""
+    push length equal the oracle's, the projection (FP32 direction and
+    residual, the benchmark's) meets the tolerance on the true residual within
+    3 % of the oracle's iteration count."""
     import os
 
     import torch

@@ -220,9 +220,11 @@ def test_qiba_phantoms_recover_shear_speed(kvs):
             dts.append(dt)
         ctx0 = kvs.kvs_batch_instance(b, 0)
         kvs.kvs_set_force(ctx0, w["F"])
-        # the oracle's algorithm: FP64 search directions (FP32 ones, the FP32
-        # context's default, need about 1 % more iterations to the tolerance)
+        # the oracle's algorithm: FP64 search direction and residual (FP32
+        # storage, the FP32 context's default, needs about 1 % more
+        # iterations to the tolerance)
         kvs.kvs_set_direction_precision(ctx0, kvs.KVS_FP64)
+        kvs.kvs_set_residual_precision(ctx0, kvs.KVS_FP64)
         rep = kvs.kvs_project(ctx0, tol=1e-8, max_iter=20000, fixed_iters=load_qiba.projection_iters)
         for i in range(1, n):
             kvs.kvs_batch_share_projection(b, 0, i)
