@@ -257,7 +257,7 @@ __device__ __forceinline__ void sweep_partials(double v0, double v1, double* par
 // network output zf (zs = 1) unless this iteration fell back to Jacobi.
 template <int WX, int SBY, typename PT, typename RT>
 __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, const SweepGeom sg, const RT* r_in,
-                                                               const double* zf, const PT* p_old, PT* p_new,
+                                                               const RT* zf, const PT* p_old, PT* p_new,
                                                                const CgState* st, double* partials, int npart) {
     if (st->done) return;
     __shared__ double lds[2][SBY + 3][64 * WX + 4];
@@ -266,10 +266,11 @@ __global__ __launch_bounds__(64 * WX * SBY) void cg_dir_kernel(const CgGeom g, c
     const int sxy = g.nx * g.ny;
     const double beta = st->beta;
     const bool net_z = st->flexible && !st->zjacobi;
-    // flexible PCG keeps r in FP64 (RT = double), so zf and r_in then have
-    // the same type; an FP32 residual is only launched for the plain CG
-    const RT* r = net_z ? reinterpret_cast<const RT*>(zf) : r_in;
-    const double zs = (st->jacobi || (st->flexible && st->zjacobi)) ? g.dinv : 1.0;
+    // the network's z is stored like r: z itself in FP64, or (RT = float) the
+    // FP32 sum before the output scale st->net_out it was formed with
+    const RT* r = net_z ? zf : r_in;
+    const double zs = net_z ? (sizeof(RT) == 4 ? st->net_out : 1.0)
+                            : ((st->jacobi || (st->flexible && st->zjacobi)) ? g.dinv : 1.0);
     const bool first = beta == 0.0;
     // the new direction as stored (PT = float: rounded once); the stencil,
     // p.Ap and the update sweep all use this stored value
@@ -527,8 +528,22 @@ __global__ __launch_bounds__(256) void cg_finalize_kernel(const double* partials
         set_net_scales(s1);
     } else if (mode == FIN_REPLACE) {
         // reliable update of the FP32 residual: the recursive r was replaced
-        // by the true residual -b - A phi; the direction is kept and beta,
-        // formed from the recursive z.r, is rescaled to the new one
+        // by the true residual -b - A phi; the direction is kept.  Flexible
+        // PCG: z, its scalars and the network scales stay those of the
+        // recursive r (a perturbation at the size of the drift, which the
+        // flexible beta absorbs like any change of the preconditioner); only
+        // r.r and the stop test are refreshed.
+        if (st->flexible) {
+            if (!isfinite(s1)) {
+                st->status = KVS_EBREAKDOWN;
+                st->done = 1;
+                return;
+            }
+            st->rr = s1;
+            if (st->fixed_iters <= 0 && sqrt(st->rr / st->bb) < sqrt(st->tol2)) st->done = 1;
+            return;
+        }
+        // plain CG: beta, formed from the recursive z.r, is rescaled to the new one
         const double rz_new = st->jacobi ? s2 : s1;
         if (!isfinite(s1) || !isfinite(rz_new) || !(st->rz > 0.0)) {
             st->status = KVS_EBREAKDOWN;
@@ -667,8 +682,18 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
     const bool warm = B.warm;
     if (!warm) CG_HIP(fill_zero(B.phi, g.N, stream));
 
-    // the residual buffers hold FP32 values for the plain CG with B.res_fp32
-    const bool res32 = B.res_fp32 && !flexible;
+    // the residual buffers (and, in flexible PCG, z) hold FP32 values with
+    // B.res_fp32
+    const bool res32 = B.res_fp32;
+    // z = U(r) from the network, stored as r is (FP32: the sum before the
+    // output scale), with the partial sums for the flexible PCG's scalars
+    auto precondition = [&](const double* r_buf, const UnetDots* dots, int* nbo) {
+        if (res32)
+            return kvs_unet_precondition32(B.net, reinterpret_cast<const float*>(r_buf), reinterpret_cast<float*>(B.Ap),
+                                           B.grid, &B.cgs->net_in, &B.cgs->net_out, &B.cgs->done, stream, dots, nbo);
+        return kvs_unet_precondition(B.net, r_buf, B.Ap, B.grid, &B.cgs->net_in, &B.cgs->net_out, &B.cgs->done, stream,
+                                     dots, nbo);
+    };
     auto launch_init = [&](double* rbuf, int warm_flag) {
         if (res32)
             hipLaunchKernelGGL(cg_init_kernel<float>, dim3(nb), blk, 0, stream, g, B.F, B.phi,
@@ -697,11 +722,12 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
     const dim3 sblk(64 * shp.wx, shp.by);
     // the direction buffers hold PT values (B.dir_fp32: float), the residual
     // buffers RT values (res32: float)
-    auto launch_dir_t = [&](auto ptag, auto rtag, const double* r_buf, const double* zf, const double* p_old_buf,
+    auto launch_dir_t = [&](auto ptag, auto rtag, const double* r_buf, const double* zf_buf, const double* p_old_buf,
                             double* p_new_buf) {
         using PT = decltype(ptag);
         using RT = decltype(rtag);
         const RT* r_in = reinterpret_cast<const RT*>(r_buf);
+        const RT* zf = reinterpret_cast<const RT*>(zf_buf);
         const PT* p_old = reinterpret_cast<const PT*>(p_old_buf);
         PT* p_new = reinterpret_cast<PT*>(p_new_buf);
         if (shp.wx == 4)
@@ -762,8 +788,7 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
         // z = U(r) and the partial sums of z.r from the network's output kernel
         const UnetDots dots{nullptr, part, npart};
         int nbo = 0;
-        CG_HIP(kvs_unet_precondition(B.net, rb[0], z, B.grid, &B.cgs->net_in, &B.cgs->net_out, stop, stream, &dots,
-                                     &nbo));
+        CG_HIP(precondition(rb[0], &dots, &nbo));
         hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbo, npart, 3, (int)FIN_FZ0,
                            B.cgs);
         CG_HIP(hipGetLastError());
@@ -792,8 +817,7 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
                     // z = U(r_new) with the partial sums of z.r_new, z.r_old, r_new.r_old
                     const UnetDots dots{rb[ri], part, npart};
                     int nbo = 0;
-                    CG_HIP(kvs_unet_precondition(B.net, rb[1 - ri], z, B.grid, &B.cgs->net_in, &B.cgs->net_out, stop,
-                                                 stream, &dots, &nbo));
+                    CG_HIP(precondition(rb[1 - ri], &dots, &nbo));
                     hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbo, npart, 3,
                                        (int)FIN_FBETA, B.cgs);
                     ri = 1 - ri;
@@ -855,8 +879,7 @@ kvs_status cg_project(const CgBuffers& B, const kvs_solve_opts* o, kvs_solve_rep
         if (flexible) {
             const UnetDots dots{nullptr, part, npart};
             int nbo = 0;
-            CG_HIP(kvs_unet_precondition(B.net, rb[ri], z, B.grid, &B.cgs->net_in, &B.cgs->net_out, stop, stream,
-                                         &dots, &nbo));
+            CG_HIP(precondition(rb[ri], &dots, &nbo));
             hipLaunchKernelGGL(cg_finalize_kernel, dim3(1), dim3(256), 0, stream, part, nbo, npart, 3, (int)FIN_FZ0,
                                B.cgs);
         }
@@ -914,6 +937,13 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
             c->err = std::string("device allocation (second residual): ") + hipGetErrorString(e);
             return KVS_ENOMEM;
         }
+        // its outer layer is read as zeros (by the sweeps and the network)
+        // and never written: clear what the allocator handed over
+        const hipError_t ez = fill_zero(c->r2, (long long)c->N, c->stream);
+        if (ez != hipSuccess) {
+            c->err = std::string("fill_zero_kernel: ") + hipGetErrorString(ez);
+            return KVS_EDEVICE;
+        }
     }
     CgBuffers B{};
     B.grid = c->grid;
@@ -936,16 +966,18 @@ kvs_status kvs_run_projection(kvs_ctx* c, const kvs_solve_opts* o, kvs_solve_rep
     B.use_events = true;
     B.dir_fp32 = c->dir_prec == KVS_FP32;
     B.res_fp32 = c->res_prec == KVS_FP32;
-    // the residual buffer's outer layer is read as zeros by the sweeps: clear
-    // it when this solve views it at the other width than the last one
-    const bool r32 = B.res_fp32 && o->precond != KVS_PC_UNET;
-    if (r32 != c->r_view32) {
-        const hipError_t e = fill_zero(c->r, (long long)c->N, c->stream);
-        if (e != hipSuccess) {
-            c->err = std::string("fill_zero_kernel: ") + hipGetErrorString(e);
-            return KVS_EDEVICE;
+    // the residual buffers' outer layer is read as zeros by the sweeps: clear
+    // them when this solve views them at the other width than the last one
+    if (B.res_fp32 != c->r_view32) {
+        for (double* v : {c->r, c->r2}) {
+            if (!v) continue;
+            const hipError_t e = fill_zero(v, (long long)c->N, c->stream);
+            if (e != hipSuccess) {
+                c->err = std::string("fill_zero_kernel: ") + hipGetErrorString(e);
+                return KVS_EDEVICE;
+            }
         }
-        c->r_view32 = r32;
+        c->r_view32 = B.res_fp32;
     }
     if (c->p_dirty) {
         for (double* v : {c->p[0], c->p[1]}) {

@@ -356,7 +356,7 @@ bool kvs_batch_small_path(const kvs_batch* b);
 // FP64): partial sums z.r, z.r_old and r.r_old per block at part[block],
 // part[npart + block], part[2 npart + block].  r_old = null: z.r only.
 struct UnetDots {
-    const double* r_old;
+    const void* r_old;  // the previous residual, stored as the r it comes with
     double* part;
     int npart;
 };
@@ -366,6 +366,11 @@ struct UnetDots {
 hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const kvs_grid& g, const double* in_scale,
                                  const double* out_scale, const int* stop, hipStream_t s, const UnetDots* dots = nullptr,
                                  int* nblocks = nullptr);
+// The same with FP32 storage: r (and dots->r_old) FP32, and z_sum the FP32
+// network output before the output scale (z = out_scale * z_sum).
+hipError_t kvs_unet_precondition32(kvs_unet* u, const float* r, float* z_sum, const kvs_grid& g,
+                                   const double* in_scale, const double* out_scale, const int* stop, hipStream_t s,
+                                   const UnetDots* dots = nullptr, int* nblocks = nullptr);
 // Blocks of the network's output kernel on a grid (the partial sums above).
 int64_t kvs_unet_out_blocks(const kvs_grid& g);
 

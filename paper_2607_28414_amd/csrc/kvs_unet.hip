@@ -698,7 +698,8 @@ constexpr int FP_RX = 2 * FP_CX + 2, FP_RY = 2 * FP_CY + 2, FP_RS = FP_RX + 2, F
 constexpr int FP_ITEMS = FP_RX * FP_RY;            // staged values per fine plane
 constexpr int FP_IPT = (FP_ITEMS + 255) / 256;     // per thread
 
-__global__ __launch_bounds__(256) void first_pool_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
+template <typename RT>  // the residual as stored: FP64, or FP32 (the flexible PCG's FP32 storage)
+__global__ __launch_bounds__(256) void first_pool_kernel(const RT* __restrict__ r, NetCtl ctl, Dims d, int ntx,
                                                          int nty, int zchunk, const bf16* __restrict__ Wp,
                                                          bf16* __restrict__ p0) {
     __shared__ __attribute__((aligned(16))) bf16 xs[FP_SLOTS * FP_RN];
@@ -796,7 +797,8 @@ __global__ __launch_bounds__(256) void first_pool_kernel(const double* __restric
 // children of e0 = conv(x; W0) (unrounded, FP32), rounded once.  One thread
 // per such voxel and channel; the faces are enumerated x, then y, then z
 // (voxels on two faces are written twice with the same value).
-__global__ void pool0_edge_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, const bf16* __restrict__ W0,
+template <typename RT>
+__global__ void pool0_edge_kernel(const RT* __restrict__ r, NetCtl ctl, Dims d, const bf16* __restrict__ W0,
                                   bf16* __restrict__ p0) {
     if (ctl.stop && *ctl.stop) return;
     const Dims c = coarse(d);
@@ -863,10 +865,15 @@ constexpr int ZO_RX = ZO_TX + 4, ZO_RY = ZO_TY + 4, ZO_RS = 72, ZO_PLANE = ZO_RY
 constexpr int ZO_NX = ZO_RX * ZO_RY;  // staged x values per plane (816)
 constexpr int ZO_GX = ZO_TX / 2 + 2, ZO_GY = ZO_TY / 2 + 2, ZO_GN = ZO_GX * ZO_GY;  // coarse tile 34 x 6
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void zout_kernel(const double* __restrict__ r, NetCtl ctl, Dims d, int ntx,
+// RT: the residual as stored (r and r_old); ZF32: z is stored as the FP32
+// sum before the output scale (the flexible PCG's FP32 storage, which applies
+// the scale where it reads z), else as out_scale times it in FP64.
+template <typename RT, bool ZF32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void zout_kernel(const RT* __restrict__ r, NetCtl ctl, Dims d, int ntx,
                                                    int nty, int zchunk, const float* __restrict__ Wc,
-                                                   const float* __restrict__ gz, double* __restrict__ z,
-                                                   const double* __restrict__ r_old, double* __restrict__ part,
+                                                   const float* __restrict__ gz,
+                                                   std::conditional_t<ZF32, float, double>* __restrict__ z,
+                                                   const RT* __restrict__ r_old, double* __restrict__ part,
                                                    int npart) {
     __shared__ float xs[2][ZO_PLANE];
     __shared__ float gs[2][ZO_GN];
@@ -1013,10 +1020,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void z
                                    0.25f * fmaf(0.75f, g[gJ1 + gIx], 0.25f * g[gJ1 + gJx]));
             const bool inz = o >= 1 && o <= d.nz - 2;
             const size_t zo = (size_t)o * sxy + (size_t)yo * d.nx + xo;
-            const double z0 = in0 && inz ? out_scale * (double)(a0[0] + up0) : 0.0;
-            const double z1 = in1 && inz ? out_scale * (double)(a1[0] + up1) : 0.0;
-            if (st0) z[zo] = z0;
-            if (st1) z[zo + d.nx] = z1;
+            const float zu0 = in0 && inz ? a0[0] + up0 : 0.f, zu1 = in1 && inz ? a1[0] + up1 : 0.f;
+            const double z0 = out_scale * (double)zu0;
+            const double z1 = out_scale * (double)zu1;
+            if constexpr (ZF32) {
+                if (st0) z[zo] = zu0;
+                if (st1) z[zo + d.nx] = zu1;
+            } else {
+                if (st0) z[zo] = z0;
+                if (st1) z[zo + d.nx] = z1;
+            }
             if (part) {
                 // residuals at this lane's two outputs (outputs past the grid
                 // have z = 0 and are left out of r.r_old)
@@ -1211,7 +1224,7 @@ OutLaunch first_pool_launch(Dims d) {
     OutLaunch L;
     L.ntx = (c.nx + FP_CX - 1) / FP_CX;
     L.nty = (c.ny + FP_CY - 1) / FP_CY;
-    static const int cap = kvs_tiling::resident_blocks(first_pool_kernel, 256);
+    static const int cap = kvs_tiling::resident_blocks(first_pool_kernel<double>, 256);
     L.zchunk = kvs_tiling::choose_kchunk(L.ntx * L.nty, c.nz, cap);
     L.nblocks = L.ntx * L.nty * ((c.nz + L.zchunk - 1) / L.zchunk);
     return L;
@@ -1221,7 +1234,7 @@ OutLaunch out_launch(Dims d) {
     OutLaunch L;
     L.ntx = (d.nx + ZO_TX - 1) / ZO_TX;
     L.nty = (d.ny + ZO_TY - 1) / ZO_TY;
-    static const int cap = kvs_tiling::resident_blocks(zout_kernel, 256);
+    static const int cap = kvs_tiling::resident_blocks(zout_kernel<double, false>, 256);
     L.zchunk = kvs_tiling::choose_kchunk(L.ntx * L.nty, d.nz, cap);
     L.nblocks = L.ntx * L.nty * ((d.nz + L.zchunk - 1) / L.zchunk);
     return L;
@@ -1701,8 +1714,10 @@ void build_layers(kvs_unet* u) {
 // Network application: z = out_scale * U(in_scale * r) (scales from ctl);
 // keep: also store g1 (1/2 resolution) and e0 (full resolution) for a
 // backward pass.
-hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, double* z, Dims d, hipStream_t s,
-                          bool keep = false, const UnetDots* dots = nullptr, int* nblocks = nullptr) {
+// RT, ZF32: the storage of r and z (zout_kernel); keep needs FP64 r.
+template <typename RT = double, bool ZF32 = false>
+hipError_t kvs_unet_apply(kvs_unet* u, const RT* r, const NetCtl& ctl, std::conditional_t<ZF32, float, double>* z, Dims d,
+                          hipStream_t s, bool keep = false, const UnetDots* dots = nullptr, int* nblocks = nullptr) {
     if (d.n() >= (1LL << 31)) return hipErrorInvalidValue;  // 32-bit voxel indices in the kernels
     hipError_t e = unet_ensure_acts(u, d);
     if (e == hipSuccess && keep) e = unet_ensure_e0(u, d);
@@ -1714,14 +1729,14 @@ hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, doubl
     const int ld1 = nl - 3;
     const int* stop = ctl.stop;
     const OutLaunch fl = first_pool_launch(d);
-    hipLaunchKernelGGL(first_pool_kernel, dim3(fl.nblocks), dim3(256), 0, s, r, ctl, d, fl.ntx, fl.nty, fl.zchunk,
+    hipLaunchKernelGGL(first_pool_kernel<RT>, dim3(fl.nblocks), dim3(256), 0, s, r, ctl, d, fl.ntx, fl.nty, fl.zchunk,
                        u->w_pool, u->p0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((d.nx | d.ny | d.nz) & 1) {
         const Dims c = coarse(d);
         const long long faces = ((d.nx & 1) ? (long long)c.ny * c.nz : 0) + ((d.ny & 1) ? (long long)c.nx * c.nz : 0) +
                                 ((d.nz & 1) ? (long long)c.nx * c.ny : 0);
-        hipLaunchKernelGGL(pool0_edge_kernel, dim3(nblocks256(faces * 16)), dim3(256), 0, s, r, ctl, d,
+        hipLaunchKernelGGL(pool0_edge_kernel<RT>, dim3(nblocks256(faces * 16)), dim3(256), 0, s, r, ctl, d,
                            u->w + u->w_off[0], u->p0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -1742,14 +1757,19 @@ hipError_t kvs_unet_apply(kvs_unet* u, const double* r, const NetCtl& ctl, doubl
         return e;
     const OutLaunch ol = out_launch(d);
     if (dots && ol.nblocks > dots->npart) return hipErrorInvalidValue;  // partials sized at context creation
-    hipLaunchKernelGGL(zout_kernel, dim3(ol.nblocks), dim3(256), 0, s, r, ctl, d, ol.ntx, ol.nty, ol.zchunk, u->w_comp,
-                       u->gz, z, dots ? dots->r_old : nullptr, dots ? dots->part : nullptr, dots ? dots->npart : 0);
+    hipLaunchKernelGGL((zout_kernel<RT, ZF32>), dim3(ol.nblocks), dim3(256), 0, s, r, ctl, d, ol.ntx, ol.nty, ol.zchunk,
+                       u->w_comp, u->gz, z, dots ? static_cast<const RT*>(dots->r_old) : nullptr,
+                       dots ? dots->part : nullptr, dots ? dots->npart : 0);
     if (nblocks) *nblocks = ol.nblocks;
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (keep) {
-        hipLaunchKernelGGL(e0_keep_kernel, dim3(nblocks256(d.n())), dim3(256), 0, s, r, ctl, d, u->w + u->w_off[0],
-                           u->e0k);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    if constexpr (std::is_same_v<RT, double>) {
+        if (keep) {
+            hipLaunchKernelGGL(e0_keep_kernel, dim3(nblocks256(d.n())), dim3(256), 0, s, r, ctl, d,
+                               u->w + u->w_off[0], u->e0k);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    } else if (keep) {
+        return hipErrorInvalidValue;
     }
     u->kept = keep;
     return hipSuccess;
@@ -1760,6 +1780,14 @@ hipError_t kvs_unet_precondition(kvs_unet* u, const double* r, double* z, const 
                                  int* nblocks) {
     NetCtl ctl{in_scale, out_scale, stop, 1.0, 1.0};
     return kvs_unet_apply(u, r, ctl, z, Dims{(int)g.nx, (int)g.ny, (int)g.nz}, s, false, dots, nblocks);
+}
+
+hipError_t kvs_unet_precondition32(kvs_unet* u, const float* r, float* z_sum, const kvs_grid& g,
+                                   const double* in_scale, const double* out_scale, const int* stop, hipStream_t s,
+                                   const UnetDots* dots, int* nblocks) {
+    NetCtl ctl{in_scale, out_scale, stop, 1.0, 1.0};
+    return kvs_unet_apply<float, true>(u, r, ctl, z_sum, Dims{(int)g.nx, (int)g.ny, (int)g.nz}, s, false, dots,
+                                       nblocks);
 }
 
 int64_t kvs_unet_out_blocks(const kvs_grid& g) {
