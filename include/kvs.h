@@ -223,14 +223,15 @@ kvs_status kvs_project(kvs_ctx* ctx, const kvs_solve_opts* opts, kvs_solve_repor
  * direction.  The two CG sweeps then move 52 instead of 64 B per cell and iteration.  Applies
  * from the next kvs_project. */
 kvs_status kvs_set_direction_precision(kvs_ctx* ctx, int32_t prec);
-/* Storage of the residual r of the plain CG and Jacobi-PCG (Sec. 3.2.3): KVS_FP64 or KVS_FP32
- * (other values: KVS_EINVAL); default: the context's state precision.  With FP32 the update's
- * rounding makes the recursive r drift from the true residual -b - A phi (phi stays FP64), so
- * whenever r.r has fallen 10^4-fold since r was last exact (checked where the host reads the
- * solver state), r is recomputed from phi in FP64 and the iteration continues with its
- * direction ("reliable update"); once the recursive residual meets tol, the true one is
- * confirmed as with confirm_true.  Inner products and norms are FP64.  With an FP32 direction
- * the sweeps then move 40 B per cell and iteration.  The flexible PCG keeps r in FP64.
+/* Storage of the residual r of the projection's CG (Sec. 3.2.3): KVS_FP64 or KVS_FP32 (other
+ * values: KVS_EINVAL); default: the context's state precision.  With FP32 the update's rounding
+ * makes the recursive r drift from the true residual -b - A phi (phi stays FP64), so whenever
+ * r.r has fallen 10^4-fold since r was last exact (checked where the host reads the solver
+ * state), r is recomputed from phi in FP64 and the iteration continues with its direction
+ * ("reliable update"); once the recursive residual meets tol, the true one is confirmed as with
+ * confirm_true.  Inner products and norms are FP64.  In flexible PCG the network then reads the
+ * FP32 r and its output z is stored as the FP32 sum before the output scale (the value is the
+ * same).  With an FP32 direction the plain CG's sweeps move 40 B per cell and iteration.
  * Applies from the next kvs_project. */
 kvs_status kvs_set_residual_precision(kvs_ctx* ctx, int32_t prec);
 /* Network used by kvs_project with precond = KVS_PC_UNET (flexible PCG:

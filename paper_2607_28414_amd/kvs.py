@@ -562,7 +562,7 @@ def kvs_set_direction_precision(ctx, precision):
 
 
 def kvs_set_residual_precision(ctx, precision):
-    """Storage of the plain CG's residual (KVS_FP64 or KVS_FP32, reliable updates)."""
+    """Storage of the projection CG's residual (KVS_FP64 or KVS_FP32, reliable updates)."""
     _check(lib().kvs_set_residual_precision(ctx, int(precision)), ctx)
 
 
