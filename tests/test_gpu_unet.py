@@ -285,14 +285,17 @@ def test_make_sample_and_training_loss(kvs):
         kvs.kvs_destroy(ctx)
 
 
-def test_untrained_network_falls_back_to_jacobi(kvs):
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_untrained_network_falls_back_to_jacobi(kvs, precision):
     """All-zero weights give z = 0, so every flexible-PCG iteration takes the
-    Jacobi fallback: the solve converges like Jacobi-PCG."""
-    say("case fpcg fallback")
+    Jacobi fallback: the solve converges like Jacobi-PCG, on an FP64 context
+    and on an FP32 one (FP32 storage of residual, direction and z, reliable
+    updates in both solves)."""
+    say(f"case fpcg fallback precision {precision}")
     from workloads import cfg1_homogeneous_fp64
     w = cfg1_homogeneous_fp64()
     net = kvs.kvs_unet_create((16, 32, 64), 4)
-    ctx = kvs.kvs_create(w.grid)
+    ctx = kvs.kvs_create(w.grid, precision=precision)
     try:
         kvs.kvs_set_force(ctx, w.F)
         rj = kvs.kvs_project(ctx, tol=1e-8, precond=kvs.KVS_PC_JACOBI)
