@@ -636,7 +636,7 @@ struct CgBuffers {
     bool warm;
     bool use_events;  // time with HIP events (else with the host clock)
     bool dir_fp32;    // p[] hold FP32 directions (the first half of each buffer)
-    bool res_fp32;    // r holds an FP32 residual (plain CG / Jacobi-PCG only)
+    bool res_fp32;    // r (and r2, and the network's z) hold FP32 values
 };
 
 __global__ void fill_zero_kernel(double* a, long long n) {

@@ -167,8 +167,8 @@ struct kvs_ctx {
     // width's view would find the last solve's values on its outer planes)
     int dir_prec = 0;
     bool p_dirty = false;
-    // storage of the residual of the plain CG / Jacobi-PCG (the flexible PCG
-    // keeps it in FP64); r_view32: the last solve viewed r as FP32
+    // storage of the projection's residual (with the flexible PCG, also of the
+    // network's output z); r_view32: the last solve viewed r and r2 as FP32
     int res_prec = 0;
     bool r_view32 = false;
     // when set, the next step-kernel launch records its own start and end in
