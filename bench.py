@@ -94,6 +94,9 @@ STEP2_COUNTERS_KIB = (329607.6, 390148.0)  # (FETCH_SIZE, WRITE_SIZE), mean of 6
 # the flux divergence of G grad u (6 differences, 6 products, 5 sums: 17), the
 # Laplacian of w (4 per axis and 2 sums: 14), acc += (eta / dt) lap w (2),
 # w' = a1 w + a2 acc (3) and u' = u + w' (1): 37 x 3 = 111.  Total 147.
+# storage of the projection's CG on the FP32 contexts of every leg (the library's default there)
+CG_STORAGE = ("FP32 search direction and residual (residual recomputed from phi whenever r.r has fallen 1e4-fold), "
+              "FP64 potential, inner products and norms; flexible PCG: also z in FP32")
 FLOP_PER_CELL_UPDATE = 147
 # FP32 vector peak of the MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2
 # (FMA) = 78.6 TFLOP/s without packed FP32 instructions (which this build does
@@ -280,6 +283,7 @@ def learned_projection(args, net):
         "jacobi_relres_true": res["jacobi"]["relres_true"], "fpcg_relres_true": res["fpcg"]["relres_true"],
         "stop_rule": "FP64 true residual ||-b - A phi|| / ||b|| < 1e-8 for both methods (restart from the true "
                      "residual when the recursive one met the tolerance first)",
+        "cg_storage": CG_STORAGE,
         "warm_start": {"jacobi_ms": float(np.mean(res["jacobi_warm"]["ms"])) if res["jacobi_warm"]["ms"] else None,
                        "fpcg_ms": float(np.mean(res["fpcg_warm"]["ms"])) if res["fpcg_warm"]["ms"] else None,
                        "jacobi_iters": res["jacobi_warm"]["iters"], "fpcg_iters": res["fpcg_warm"]["iters"],
@@ -564,7 +568,8 @@ def shell_workload(args, net):
                     f"maps on 3 planes",
         "projection": {"tol": 1e-8, "jacobi_iters": rj["iters"], "jacobi_ms": rj["ms"], "fpcg_iters": rf["iters"],
                        "fpcg_ms": rf["ms"], "speedup": rj["ms"] / rf["ms"], "fpcg_fallbacks": fb,
-                       "jacobi_relres_true": rj["relres_true"], "fpcg_relres_true": rf["relres_true"]},
+                       "jacobi_relres_true": rj["relres_true"], "fpcg_relres_true": rf["relres_true"],
+                       "cg_storage": CG_STORAGE},
         "fdtd_kernel_ms_avg": per, "fdtd_kernel_gcells": cells * args.shell_steps / (k_ms * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -1199,7 +1204,7 @@ def main():
                            "note": "one simulation with the force copied from pageable host memory (FP64) "
                                    "instead of device memory; traces to the host as in the timed steps"},
         "projection": {"precond": "jacobi", "tol": w.tol, "iters": rep["iters"],
-                       "relres_true": rep["relres_true"], "ms": float(np.mean(proj_ms))},
+                       "relres_true": rep["relres_true"], "ms": float(np.mean(proj_ms)), "cg_storage": CG_STORAGE},
     }
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle sample ({args.cpu_sample_steps} steps, then 4 on one thread)")
